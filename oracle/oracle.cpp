@@ -1,0 +1,874 @@
+// Plain, slow CPU reference of the tile-based differentiable Gaussian splatting
+// rasterizer used by GSFusion's online optimisation (Sec. III-B-3, Eq. 3-5, 11-12).
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+// calls this file; only the test-suite, the smoke check and the benchmark's
+// CPU-baseline leg use it.  It shares no code with the HIP path.
+//
+// Two stages:
+//  * a discrete stage (cull, splat centre, screen rectangle, tile keys) written
+//    as a fixed sequence of IEEE binary32 operations, so that tile keys, sort
+//    order and tile ranges are reproducible bit for bit by any other
+//    implementation that performs the same sequence (no fused multiply-add,
+//    correctly rounded divide and square root);
+//  * a value stage in binary64: projected covariance (Eq. 5), conic, SH colour,
+//    per-pixel front-to-back compositing (Eq. 11 with clamp/skip/stop rules)
+//    and the exact reverse-mode gradients of all of it.
+//
+// Build: g++ -O2 -std=c++17 -ffp-contract=off -fno-fast-math -shared -fPIC
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <numeric>
+#include <thread>
+#include <vector>
+
+extern "C" {
+
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float R[9];   // world->camera rotation, row-major
+  float t[3];   // world->camera translation: x_c = R x_w + t
+  float znear;
+} or_camera;
+
+typedef struct {
+  int32_t tile;        // tile edge in pixels
+  float extent_k;      // screen rectangle half-width in standard deviations
+  float lowpass;       // added to the diagonal of the projected covariance (px^2)
+  float alpha_min;     // a splat value below this is skipped
+  float alpha_max;     // opacity clamp
+  float T_min;         // stop once transmittance falls below this
+  float bg[3];         // background colour
+  int32_t mu_fp32;     // 1: value stage uses the binary32 splat centre of the discrete stage
+  int32_t threads;     // worker threads for the pixel loop (>=1)
+  float amb_rel;       // relative margin that flags a per-pixel decision as ambiguous
+} or_settings;
+
+}  // extern "C"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ------------------------------------------------------------------------------------
+// Real spherical harmonics from their definition (orthonormal, Condon-Shortley phase):
+//   Y_l^0  = N_l^0 P_l^0(cos t)
+//   Y_l^m  = sqrt2 N_l^m cos(m phi) P_l^m(cos t)      m > 0
+//   Y_l^-m = sqrt2 N_l^m sin(m phi) P_l^m(cos t)      m > 0
+//   N_l^m  = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!),  P_l^m(x) = (-1)^m (1-x^2)^(m/2) d^m/dx^m P_l(x)
+// With (x,y,z) a unit vector, (1-z^2)^(m/2) e^{i m phi} = (x+iy)^m, which gives a
+// polynomial extension whose gradient, projected onto the sphere's tangent plane,
+// is the surface gradient.  Coefficient index k = l*l + l + m.
+// ------------------------------------------------------------------------------------
+struct SHBasis {
+  int deg = -1;
+  // pd[l][m] = coefficients (ascending powers) of the m-th derivative of P_l
+  std::vector<std::vector<std::vector<double>>> pd;
+  std::vector<std::vector<double>> norm;  // N_l^m
+
+  explicit SHBasis(int degree) : deg(degree) {
+    std::vector<std::vector<double>> P(degree + 2);
+    P[0] = {1.0};
+    if (degree + 1 >= 1) P[1] = {0.0, 1.0};
+    for (int n = 1; n + 1 <= degree + 1; ++n) {  // (n+1)P_{n+1} = (2n+1) x P_n - n P_{n-1}
+      std::vector<double> r(n + 2, 0.0);
+      for (int i = 0; i <= n; ++i) r[i + 1] += (2.0 * n + 1.0) * P[n][i];
+      for (int i = 0; i <= n - 1; ++i) r[i] -= n * P[n - 1][i];
+      for (double& v : r) v /= (n + 1.0);
+      P[n + 1] = r;
+    }
+    pd.resize(degree + 1);
+    norm.resize(degree + 1);
+    for (int l = 0; l <= degree; ++l) {
+      pd[l].resize(l + 2);
+      pd[l][0] = P[l];
+      for (int m = 1; m <= l + 1; ++m) {
+        const auto& prev = pd[l][m - 1];
+        std::vector<double> d(prev.size() > 1 ? prev.size() - 1 : 1, 0.0);
+        for (size_t i = 1; i < prev.size(); ++i) d[i - 1] = prev[i] * double(i);
+        pd[l][m] = d;
+      }
+      norm[l].resize(l + 1);
+      for (int m = 0; m <= l; ++m) {
+        double ratio = 1.0;  // (l-m)!/(l+m)!
+        for (int i = l - m + 1; i <= l + m; ++i) ratio /= double(i);
+        norm[l][m] = std::sqrt((2.0 * l + 1.0) / (4.0 * kPi) * ratio);
+      }
+    }
+  }
+
+  static double poly(const std::vector<double>& c, double x) {
+    double r = 0.0;
+    for (size_t i = c.size(); i-- > 0;) r = r * x + c[i];
+    return r;
+  }
+
+  // Y[k] and the gradient of the polynomial extension dY[k][3] at unit v.
+  void eval(const double v[3], double* Y, double (*dY)[3]) const {
+    const double x = v[0], y = v[1], z = v[2];
+    // powers of w = x + i y: w^m = re[m] + i im[m]
+    double re[8], im[8];
+    re[0] = 1.0;
+    im[0] = 0.0;
+    for (int m = 1; m <= deg; ++m) {
+      re[m] = re[m - 1] * x - im[m - 1] * y;
+      im[m] = re[m - 1] * y + im[m - 1] * x;
+    }
+    const double s2 = std::sqrt(2.0);
+    for (int l = 0; l <= deg; ++l) {
+      for (int m = -l; m <= l; ++m) {
+        const int am = m < 0 ? -m : m;
+        const int k = l * l + l + m;
+        const double f = poly(pd[l][am], z);
+        const double fz = poly(pd[l][am + 1], z);
+        const double sign = (am % 2) ? -1.0 : 1.0;
+        double c = norm[l][am] * sign * (am ? s2 : 1.0);
+        double ang, dax, day;
+        if (m > 0) {
+          ang = re[am];
+          dax = am * re[am - 1];
+          day = -am * im[am - 1];
+        } else if (m < 0) {
+          ang = im[am];
+          dax = am * im[am - 1];
+          day = am * re[am - 1];
+        } else {
+          ang = 1.0;
+          dax = 0.0;
+          day = 0.0;
+        }
+        Y[k] = c * f * ang;
+        if (dY) {
+          dY[k][0] = c * f * dax;
+          dY[k][1] = c * f * day;
+          dY[k][2] = c * fz * ang;
+        }
+      }
+    }
+  }
+};
+
+// ------------------------------------------------------------------------------------
+// Discrete stage, binary32.  The operation order below is the contract shared (as
+// text, not code) with the GPU path; every line is one correctly rounded operation.
+// ------------------------------------------------------------------------------------
+struct Disc {
+  bool vis = false;
+  float mux = 0.f, muy = 0.f, z = 0.f;
+  float ca = 0.f, cb = 0.f, cc = 0.f;  // projected covariance incl. low-pass
+  int x0 = 0, x1 = -1, y0 = 0, y1 = -1;  // inclusive pixel rectangle
+};
+
+Disc discrete_stage(const float p[3], const float s[3], const float q[4], const or_camera& cam,
+                    float k, float lowpass) {
+  Disc d;
+  const float* W = cam.R;
+  // camera-space mean, each row summed left to right
+  float tx = W[0] * p[0];
+  tx = tx + W[1] * p[1];
+  tx = tx + W[2] * p[2];
+  tx = tx + cam.t[0];
+  float ty = W[3] * p[0];
+  ty = ty + W[4] * p[1];
+  ty = ty + W[5] * p[2];
+  ty = ty + cam.t[1];
+  float tz = W[6] * p[0];
+  tz = tz + W[7] * p[1];
+  tz = tz + W[8] * p[2];
+  tz = tz + cam.t[2];
+  if (!(tz > cam.znear)) return d;
+  // normalised quaternion
+  float nq = q[0] * q[0];
+  nq = nq + q[1] * q[1];
+  nq = nq + q[2] * q[2];
+  nq = nq + q[3] * q[3];
+  nq = std::sqrt(nq);
+  if (!(nq > 0.f)) return d;
+  const float w = q[0] / nq, x = q[1] / nq, y = q[2] / nq, z = q[3] / nq;
+  // rotation matrix of the unit quaternion
+  float r[9];
+  r[0] = 1.f - 2.f * (y * y + z * z);
+  r[1] = 2.f * (x * y - w * z);
+  r[2] = 2.f * (x * z + w * y);
+  r[3] = 2.f * (x * y + w * z);
+  r[4] = 1.f - 2.f * (x * x + z * z);
+  r[5] = 2.f * (y * z - w * x);
+  r[6] = 2.f * (x * z - w * y);
+  r[7] = 2.f * (y * z + w * x);
+  r[8] = 1.f - 2.f * (x * x + y * y);
+  // M = R diag(s)
+  float m[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) m[i * 3 + j] = r[i * 3 + j] * s[j];
+  // Jacobian of the perspective projection
+  const float tz2 = tz * tz;
+  const float j00 = cam.fx / tz;
+  const float j11 = cam.fy / tz;
+  const float j02 = -(cam.fx * tx) / tz2;
+  const float j12 = -(cam.fy * ty) / tz2;
+  // T = J W (2x3)
+  float T[6];
+  for (int c = 0; c < 3; ++c) {
+    T[c] = j00 * W[c] + j02 * W[6 + c];
+    T[3 + c] = j11 * W[3 + c] + j12 * W[6 + c];
+  }
+  // U = T M (2x3)
+  float U[6];
+  for (int i = 0; i < 2; ++i)
+    for (int c = 0; c < 3; ++c) {
+      float acc = T[i * 3 + 0] * m[0 * 3 + c];
+      acc = acc + T[i * 3 + 1] * m[1 * 3 + c];
+      acc = acc + T[i * 3 + 2] * m[2 * 3 + c];
+      U[i * 3 + c] = acc;
+    }
+  // projected covariance U U^T + lowpass I
+  float a = U[0] * U[0];
+  a = a + U[1] * U[1];
+  a = a + U[2] * U[2];
+  a = a + lowpass;
+  float b = U[0] * U[3];
+  b = b + U[1] * U[4];
+  b = b + U[2] * U[5];
+  float c = U[3] * U[3];
+  c = c + U[4] * U[4];
+  c = c + U[5] * U[5];
+  c = c + lowpass;
+  const float det = a * c - b * b;
+  if (!(det > 0.f)) return d;
+  const float mux = cam.fx * (tx / tz) + cam.cx;
+  const float muy = cam.fy * (ty / tz) + cam.cy;
+  const float rx = k * std::sqrt(a);
+  const float ry = k * std::sqrt(c);
+  float fx0 = std::ceil(mux - rx), fx1 = std::floor(mux + rx);
+  float fy0 = std::ceil(muy - ry), fy1 = std::floor(muy + ry);
+  const float wmax = float(cam.width - 1), hmax = float(cam.height - 1);
+  fx0 = (fx0 < 0.f) ? 0.f : fx0;
+  fy0 = (fy0 < 0.f) ? 0.f : fy0;
+  fx1 = (fx1 > wmax) ? wmax : fx1;
+  fy1 = (fy1 > hmax) ? hmax : fy1;
+  if (!(fx0 <= fx1 && fy0 <= fy1)) return d;
+  d.vis = true;
+  d.mux = mux;
+  d.muy = muy;
+  d.z = tz;
+  d.ca = a;
+  d.cb = b;
+  d.cc = c;
+  d.x0 = int(fx0);
+  d.x1 = int(fx1);
+  d.y0 = int(fy0);
+  d.y1 = int(fy1);
+  return d;
+}
+
+uint32_t f32_bits(float v) {
+  uint32_t u;
+  std::memcpy(&u, &v, 4);
+  return u;
+}
+
+// binary64 per-(view, Gaussian) quantities of the value stage
+struct Rec {
+  double mux, muy, z;
+  double A, B, C;       // conic = inverse projected covariance
+  double opacity;
+  double color[3];
+};
+
+struct Mat3 {
+  double m[9];
+};
+
+void quat_rot(const double qn[4], double R[9]) {
+  const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+  R[0] = 1 - 2 * (y * y + z * z);
+  R[1] = 2 * (x * y - w * z);
+  R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z);
+  R[4] = 1 - 2 * (x * x + z * z);
+  R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y);
+  R[7] = 2 * (y * z + w * x);
+  R[8] = 1 - 2 * (x * x + y * y);
+}
+
+// Partial derivatives of R(q) (unit q) with respect to w, x, y, z.
+void quat_rot_grad(const double qn[4], double dR[4][9]) {
+  const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+  const double gw[9] = {0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0};
+  const double gx[9] = {0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x};
+  const double gy[9] = {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y};
+  const double gz[9] = {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0};
+  std::memcpy(dR[0], gw, sizeof gw);
+  std::memcpy(dR[1], gx, sizeof gx);
+  std::memcpy(dR[2], gy, sizeof gy);
+  std::memcpy(dR[3], gz, sizeof gz);
+}
+
+// Everything of the value stage that depends only on (view, Gaussian), binary64.
+struct Geo {
+  double p[3], s[3], qn[4], qnorm;
+  double R[9], M[9], Sig[9];      // rotation, R diag(s), Sigma = M M^T (Eq. 2)
+  double W[9], t[3];              // camera rotation, camera-space mean
+  double J[6], T[6];              // Jacobian (2x3) and T = J W
+  double S2[3];                   // projected covariance (a, b, c) incl. low-pass (Eq. 5)
+  double det, A, B, C;            // conic
+  double mux, muy;
+  double dir[3], dnorm, v[3];     // view direction for SH
+};
+
+struct Ctx {
+  // inputs
+  int64_t n = 0;
+  int deg = 0, K = 1;
+  std::vector<double> means, scales, quats, opac, sh;
+  std::vector<or_camera> cams;
+  or_settings set{};
+  // discrete stage
+  std::vector<Disc> disc;           // [V*N]
+  std::vector<int64_t> tile_off;    // [V+1]
+  std::vector<int> tiles_x, tiles_y;
+  std::vector<uint64_t> keys;
+  std::vector<uint32_t> vals;
+  std::vector<uint32_t> ranges;     // [tiles*2]
+  // value stage
+  std::vector<Rec> rec;             // [V*N]
+  std::vector<int64_t> pix_off;     // [V+1]
+};
+
+void make_geo(const Ctx& c, int v, int64_t g, Geo& o) {
+  const or_camera& cam = c.cams[v];
+  for (int i = 0; i < 3; ++i) {
+    o.p[i] = c.means[g * 3 + i];
+    o.s[i] = c.scales[g * 3 + i];
+  }
+  double q[4];
+  for (int i = 0; i < 4; ++i) q[i] = c.quats[g * 4 + i];
+  o.qnorm = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int i = 0; i < 4; ++i) o.qn[i] = q[i] / o.qnorm;
+  quat_rot(o.qn, o.R);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) o.M[i * 3 + j] = o.R[i * 3 + j] * o.s[j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0;
+      for (int k = 0; k < 3; ++k) acc += o.M[i * 3 + k] * o.M[j * 3 + k];
+      o.Sig[i * 3 + j] = acc;
+    }
+  for (int i = 0; i < 9; ++i) o.W[i] = cam.R[i];
+  for (int i = 0; i < 3; ++i)
+    o.t[i] = o.W[i * 3 + 0] * o.p[0] + o.W[i * 3 + 1] * o.p[1] + o.W[i * 3 + 2] * o.p[2] + double(cam.t[i]);
+  const double fx = cam.fx, fy = cam.fy, tx = o.t[0], ty = o.t[1], tz = o.t[2];
+  o.J[0] = fx / tz;
+  o.J[1] = 0;
+  o.J[2] = -fx * tx / (tz * tz);
+  o.J[3] = 0;
+  o.J[4] = fy / tz;
+  o.J[5] = -fy * ty / (tz * tz);
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0;
+      for (int k = 0; k < 3; ++k) acc += o.J[i * 3 + k] * o.W[k * 3 + j];
+      o.T[i * 3 + j] = acc;
+    }
+  // Sigma_hat = T Sigma T^T + lowpass I
+  double TS[6];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0;
+      for (int k = 0; k < 3; ++k) acc += o.T[i * 3 + k] * o.Sig[k * 3 + j];
+      TS[i * 3 + j] = acc;
+    }
+  double S[4];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      double acc = 0;
+      for (int k = 0; k < 3; ++k) acc += TS[i * 3 + k] * o.T[j * 3 + k];
+      S[i * 2 + j] = acc;
+    }
+  const double lp = c.set.lowpass;
+  o.S2[0] = S[0] + lp;
+  o.S2[1] = S[1];
+  o.S2[2] = S[3] + lp;
+  o.det = o.S2[0] * o.S2[2] - o.S2[1] * o.S2[1];
+  o.A = o.S2[2] / o.det;
+  o.B = -o.S2[1] / o.det;
+  o.C = o.S2[0] / o.det;
+  o.mux = fx * tx / tz + double(cam.cx);
+  o.muy = fy * ty / tz + double(cam.cy);
+  // camera centre C = -W^T t_cam
+  double cc[3];
+  for (int i = 0; i < 3; ++i)
+    cc[i] = -(o.W[0 * 3 + i] * double(cam.t[0]) + o.W[1 * 3 + i] * double(cam.t[1]) +
+              o.W[2 * 3 + i] * double(cam.t[2]));
+  for (int i = 0; i < 3; ++i) o.dir[i] = o.p[i] - cc[i];
+  o.dnorm = std::sqrt(o.dir[0] * o.dir[0] + o.dir[1] * o.dir[1] + o.dir[2] * o.dir[2]);
+  for (int i = 0; i < 3; ++i) o.v[i] = o.dir[i] / o.dnorm;
+}
+
+void build(Ctx& c) {
+  const int V = int(c.cams.size());
+  const int64_t N = c.n;
+  c.disc.assign(size_t(V) * N, Disc{});
+  c.tile_off.assign(V + 1, 0);
+  c.tiles_x.resize(V);
+  c.tiles_y.resize(V);
+  c.pix_off.assign(V + 1, 0);
+  const int ts = c.set.tile;
+  for (int v = 0; v < V; ++v) {
+    c.tiles_x[v] = (c.cams[v].width + ts - 1) / ts;
+    c.tiles_y[v] = (c.cams[v].height + ts - 1) / ts;
+    c.tile_off[v + 1] = c.tile_off[v] + int64_t(c.tiles_x[v]) * c.tiles_y[v];
+    c.pix_off[v + 1] = c.pix_off[v] + int64_t(c.cams[v].width) * c.cams[v].height;
+  }
+  // discrete stage, keys in duplication order (view, Gaussian, tile row, tile column)
+  std::vector<uint64_t> keys;
+  std::vector<uint32_t> vals;
+  for (int v = 0; v < V; ++v)
+    for (int64_t g = 0; g < N; ++g) {
+      float p[3], s[3], q[4];
+      for (int i = 0; i < 3; ++i) {
+        p[i] = float(c.means[g * 3 + i]);
+        s[i] = float(c.scales[g * 3 + i]);
+      }
+      for (int i = 0; i < 4; ++i) q[i] = float(c.quats[g * 4 + i]);
+      Disc d = discrete_stage(p, s, q, c.cams[v], c.set.extent_k, c.set.lowpass);
+      c.disc[size_t(v) * N + g] = d;
+      if (!d.vis) continue;
+      const int tx0 = d.x0 / ts, tx1 = d.x1 / ts, ty0 = d.y0 / ts, ty1 = d.y1 / ts;
+      for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) {
+          const uint64_t tile = uint64_t(c.tile_off[v] + int64_t(ty) * c.tiles_x[v] + tx);
+          keys.push_back((tile << 32) | f32_bits(d.z));
+          vals.push_back(uint32_t(int64_t(v) * N + g));
+        }
+    }
+  // stable ascending sort by key
+  std::vector<size_t> order(keys.size());
+  std::iota(order.begin(), order.end(), size_t(0));
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return keys[a] < keys[b]; });
+  c.keys.resize(keys.size());
+  c.vals.resize(keys.size());
+  for (size_t i = 0; i < order.size(); ++i) {
+    c.keys[i] = keys[order[i]];
+    c.vals[i] = vals[order[i]];
+  }
+  // tile ranges [start, end); empty tiles [0, 0)
+  c.ranges.assign(size_t(c.tile_off[V]) * 2, 0u);
+  for (size_t i = 0; i < c.keys.size(); ++i) {
+    const uint64_t tile = c.keys[i] >> 32;
+    if (i == 0 || (c.keys[i - 1] >> 32) != tile) c.ranges[tile * 2] = uint32_t(i);
+    if (i + 1 == c.keys.size() || (c.keys[i + 1] >> 32) != tile) c.ranges[tile * 2 + 1] = uint32_t(i + 1);
+  }
+  // value stage per visible (view, Gaussian)
+  SHBasis sh(c.deg);
+  c.rec.assign(size_t(V) * N, Rec{});
+  std::vector<double> Y(c.K);
+  for (int v = 0; v < V; ++v)
+    for (int64_t g = 0; g < N; ++g) {
+      const Disc& d = c.disc[size_t(v) * N + g];
+      if (!d.vis) continue;
+      Geo o;
+      make_geo(c, v, g, o);
+      Rec& r = c.rec[size_t(v) * N + g];
+      if (c.set.mu_fp32) {
+        r.mux = d.mux;
+        r.muy = d.muy;
+      } else {
+        r.mux = o.mux;
+        r.muy = o.muy;
+      }
+      r.z = o.t[2];
+      r.A = o.A;
+      r.B = o.B;
+      r.C = o.C;
+      r.opacity = c.opac[g];
+      sh.eval(o.v, Y.data(), nullptr);
+      for (int ch = 0; ch < 3; ++ch) {
+        double acc = 0.5;
+        for (int k = 0; k < c.K; ++k) acc += c.sh[(g * c.K + k) * 3 + ch] * Y[k];
+        r.color[ch] = acc > 0.0 ? acc : 0.0;
+      }
+    }
+}
+
+struct Hit {
+  uint32_t rec;
+  double G, a, alpha, T, dx, dy;
+};
+
+// Front-to-back compositing of one pixel over its tile's sorted list.
+// Returns the processed contributors (skipped entries omitted).
+void composite(const Ctx& c, int64_t tile, double px, double py, double out[5], int32_t& ncontrib,
+               int32_t& nused, bool& ambiguous, std::vector<Hit>* hits) {
+  const uint32_t s = c.ranges[tile * 2], e = c.ranges[tile * 2 + 1];
+  const double amin = c.set.alpha_min, amax = c.set.alpha_max, Tmin = c.set.T_min;
+  const double rel = c.set.amb_rel;
+  double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
+  int32_t n = 0;
+  nused = 0;
+  ambiguous = false;
+  for (uint32_t i = s; i < e; ++i) {
+    const uint32_t ri = c.vals[i];
+    const Rec& r = c.rec[ri];
+    const double dx = px - r.mux, dy = py - r.muy;
+    const double power = -0.5 * (r.A * dx * dx + 2.0 * r.B * dx * dy + r.C * dy * dy);
+    const double G = std::exp(power);
+    const double a = r.opacity * G;
+    if (std::fabs(a - amin) <= rel * amin) ambiguous = true;
+    if (a < amin) continue;
+    const double alpha = a < amax ? a : amax;
+    if (hits) hits->push_back(Hit{ri, G, a, alpha, T, dx, dy});
+    for (int ch = 0; ch < 3; ++ch) C[ch] += r.color[ch] * alpha * T;
+    D += r.z * alpha * T;
+    T = T * (1.0 - alpha);
+    n = int32_t(i - s + 1);
+    ++nused;
+    if (std::fabs(T - Tmin) <= rel * Tmin) ambiguous = true;
+    if (T < Tmin) break;
+  }
+  for (int ch = 0; ch < 3; ++ch) out[ch] = C[ch] + T * double(c.set.bg[ch]);
+  out[3] = D;
+  out[4] = T;
+  ncontrib = n;
+}
+
+template <class F>
+void parallel_tiles(const Ctx& c, F&& f) {
+  const int64_t tiles = c.tile_off.back();
+  int th = c.set.threads < 1 ? 1 : c.set.threads;
+  if (th == 1 || tiles < 2) {
+    f(0, int64_t(0), tiles);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int w = 0; w < th; ++w) {
+    const int64_t a = tiles * w / th, b = tiles * (w + 1) / th;
+    pool.emplace_back([&, w, a, b] { f(w, a, b); });
+  }
+  for (auto& t : pool) t.join();
+}
+
+int view_of_tile(const Ctx& c, int64_t tile) {
+  int v = 0;
+  while (c.tile_off[v + 1] <= tile) ++v;
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Build the oracle for V cameras.  Parameters are binary64 arrays (promote binary32
+// inputs exactly); the discrete stage rounds them to binary32.
+void* or_create(const double* means, const double* scales, const double* quats, const double* opac,
+                const double* sh, int64_t n, int32_t sh_degree, const or_camera* cams, int32_t V,
+                const or_settings* set) {
+  Ctx* c = new Ctx;
+  c->n = n;
+  c->deg = sh_degree;
+  c->K = (sh_degree + 1) * (sh_degree + 1);
+  c->means.assign(means, means + n * 3);
+  c->scales.assign(scales, scales + n * 3);
+  c->quats.assign(quats, quats + n * 4);
+  c->opac.assign(opac, opac + n);
+  c->sh.assign(sh, sh + n * c->K * 3);
+  c->cams.assign(cams, cams + V);
+  c->set = *set;
+  build(*c);
+  return c;
+}
+
+void or_destroy(void* h) { delete static_cast<Ctx*>(h); }
+
+int64_t or_num_keys(void* h) { return int64_t(static_cast<Ctx*>(h)->keys.size()); }
+int64_t or_num_tiles(void* h) { return static_cast<Ctx*>(h)->tile_off.back(); }
+
+void or_get_keys(void* h, uint64_t* keys, uint32_t* vals, uint32_t* ranges) {
+  const Ctx& c = *static_cast<Ctx*>(h);
+  if (keys) std::copy(c.keys.begin(), c.keys.end(), keys);
+  if (vals) std::copy(c.vals.begin(), c.vals.end(), vals);
+  if (ranges) std::copy(c.ranges.begin(), c.ranges.end(), ranges);
+}
+
+// Per (view, Gaussian): visible flag, binary32 centre/depth/projected covariance and the
+// inclusive pixel rectangle of the discrete stage; binary64 conic and colour.
+void or_get_records(void* h, uint8_t* vis, float* mu, float* z, float* cov, int32_t* rect, double* conic,
+                    double* color) {
+  const Ctx& c = *static_cast<Ctx*>(h);
+  for (size_t i = 0; i < c.disc.size(); ++i) {
+    const Disc& d = c.disc[i];
+    if (vis) vis[i] = d.vis;
+    if (mu) {
+      mu[i * 2] = d.mux;
+      mu[i * 2 + 1] = d.muy;
+    }
+    if (z) z[i] = d.z;
+    if (cov) {
+      cov[i * 3] = d.ca;
+      cov[i * 3 + 1] = d.cb;
+      cov[i * 3 + 2] = d.cc;
+    }
+    if (rect) {
+      rect[i * 4] = d.x0;
+      rect[i * 4 + 1] = d.x1;
+      rect[i * 4 + 2] = d.y0;
+      rect[i * 4 + 3] = d.y1;
+    }
+    const Rec& r = c.rec[i];
+    if (conic) {
+      conic[i * 3] = r.A;
+      conic[i * 3 + 1] = r.B;
+      conic[i * 3 + 2] = r.C;
+    }
+    if (color)
+      for (int ch = 0; ch < 3; ++ch) color[i * 3 + ch] = r.color[ch];
+  }
+}
+
+// Forward render of every view.  Image outputs are concatenated over views:
+// color [3,H,W] per view, the others [H,W] per view.  n_contrib is one past the
+// list position of the last contributor; n_used counts the contributors.
+void or_forward(void* h, double* color, double* depth, double* alpha, double* T_final, int32_t* n_contrib,
+                int32_t* n_used, uint8_t* ambiguous) {
+  const Ctx& c = *static_cast<Ctx*>(h);
+  const int ts = c.set.tile;
+  parallel_tiles(c, [&](int, int64_t t0, int64_t t1) {
+    for (int64_t tile = t0; tile < t1; ++tile) {
+      const int v = view_of_tile(c, tile);
+      const int64_t lt = tile - c.tile_off[v];
+      const int W = c.cams[v].width, H = c.cams[v].height;
+      const int tx = int(lt % c.tiles_x[v]), ty = int(lt / c.tiles_x[v]);
+      const int64_t P = int64_t(W) * H;
+      for (int y = ty * ts; y < std::min(H, (ty + 1) * ts); ++y)
+        for (int x = tx * ts; x < std::min(W, (tx + 1) * ts); ++x) {
+          double out[5];
+          int32_t n, nu;
+          bool amb;
+          composite(c, tile, x, y, out, n, nu, amb, nullptr);
+          const int64_t pix = int64_t(y) * W + x;
+          const int64_t base = c.pix_off[v];
+          if (color)
+            for (int ch = 0; ch < 3; ++ch) color[base * 3 + ch * P + pix] = out[ch];
+          if (depth) depth[base + pix] = out[3];
+          if (alpha) alpha[base + pix] = 1.0 - out[4];
+          if (T_final) T_final[base + pix] = out[4];
+          if (n_contrib) n_contrib[base + pix] = n;
+          if (n_used) n_used[base + pix] = nu;
+          if (ambiguous) ambiguous[base + pix] = amb;
+        }
+    }
+  });
+}
+
+// Reverse pass.  g_color/g_depth/g_alpha are dL/d(output) with the layouts of
+// or_forward (NULL = zero).  Writes dL/d(parameters) in the parameter layouts, and per
+// Gaussian a flag that is set when a contributing event sat within the ambiguity
+// margin of a discrete rule (skip, stop or clamp edge), so its gradient is not unique.
+void or_backward(void* h, const double* g_color, const double* g_depth, const double* g_alpha,
+                 double* d_means, double* d_scales, double* d_quats, double* d_opac, double* d_sh,
+                 uint8_t* flagged) {
+  const Ctx& c = *static_cast<Ctx*>(h);
+  const int V = int(c.cams.size());
+  const int64_t N = c.n;
+  const int ts = c.set.tile;
+  const int nth = c.set.threads < 1 ? 1 : c.set.threads;
+  // per-thread accumulators of the 2D gradients: dmu(2), dconic(3), dopacity, dcolor(3), ddepth
+  std::vector<std::vector<double>> acc(nth, std::vector<double>(size_t(V) * N * 10, 0.0));
+  std::vector<std::vector<uint8_t>> flag(nth, std::vector<uint8_t>(size_t(V) * N, 0));
+  const double amax = c.set.alpha_max, rel = c.set.amb_rel;
+  parallel_tiles(c, [&](int w, int64_t t0, int64_t t1) {
+    std::vector<Hit> hits;
+    std::vector<double>& G2 = acc[w];
+    std::vector<uint8_t>& F = flag[w];
+    for (int64_t tile = t0; tile < t1; ++tile) {
+      const int v = view_of_tile(c, tile);
+      const int64_t lt = tile - c.tile_off[v];
+      const int W = c.cams[v].width, H = c.cams[v].height;
+      const int tx = int(lt % c.tiles_x[v]), ty = int(lt / c.tiles_x[v]);
+      const int64_t P = int64_t(W) * H, base = c.pix_off[v];
+      for (int y = ty * ts; y < std::min(H, (ty + 1) * ts); ++y)
+        for (int x = tx * ts; x < std::min(W, (tx + 1) * ts); ++x) {
+          const int64_t pix = int64_t(y) * W + x;
+          double gC[3], gD, gA;
+          for (int ch = 0; ch < 3; ++ch) gC[ch] = g_color ? g_color[base * 3 + ch * P + pix] : 0.0;
+          gD = g_depth ? g_depth[base + pix] : 0.0;
+          gA = g_alpha ? g_alpha[base + pix] : 0.0;
+          hits.clear();
+          double out[5];
+          int32_t n, nu;
+          bool amb;
+          composite(c, tile, x, y, out, n, nu, amb, &hits);
+          const double Tfin = out[4];
+          double BC[3] = {c.set.bg[0], c.set.bg[1], c.set.bg[2]}, BD = 0.0;
+          for (size_t i = hits.size(); i-- > 0;) {
+            const Hit& hh = hits[i];
+            const Rec& r = c.rec[hh.rec];
+            double* g = &G2[size_t(hh.rec) * 10];
+            if (amb || std::fabs(hh.a - amax) <= rel * amax) F[hh.rec] = 1;
+            double dal = 0.0;
+            for (int ch = 0; ch < 3; ++ch) dal += gC[ch] * (r.color[ch] - BC[ch]);
+            dal += gD * (r.z - BD);
+            dal *= hh.T;
+            dal += gA * Tfin / (1.0 - hh.alpha);
+            for (int ch = 0; ch < 3; ++ch) g[6 + ch] += gC[ch] * hh.alpha * hh.T;
+            g[9] += gD * hh.alpha * hh.T;
+            for (int ch = 0; ch < 3; ++ch) BC[ch] = hh.alpha * r.color[ch] + (1.0 - hh.alpha) * BC[ch];
+            BD = hh.alpha * r.z + (1.0 - hh.alpha) * BD;
+            const double da = hh.a <= amax ? dal : 0.0;
+            g[5] += da * hh.G;
+            const double dpow = da * hh.a;
+            g[0] += dpow * (r.A * hh.dx + r.B * hh.dy);
+            g[1] += dpow * (r.B * hh.dx + r.C * hh.dy);
+            g[2] += -0.5 * dpow * hh.dx * hh.dx;
+            g[3] += -dpow * hh.dx * hh.dy;
+            g[4] += -0.5 * dpow * hh.dy * hh.dy;
+          }
+        }
+    }
+  });
+  for (int w = 1; w < nth; ++w) {
+    for (size_t i = 0; i < acc[0].size(); ++i) acc[0][i] += acc[w][i];
+    for (size_t i = 0; i < flag[0].size(); ++i) flag[0][i] |= flag[w][i];
+  }
+  const std::vector<double>& G2 = acc[0];
+  // chain rule per Gaussian, summed over views in view order
+  SHBasis sh(c.deg);
+  std::vector<double> Y(c.K);
+  std::vector<double> dYbuf(size_t(c.K) * 3);
+  double (*dY)[3] = reinterpret_cast<double (*)[3]>(dYbuf.data());
+  for (int64_t g = 0; g < N; ++g) {
+    double dp[3] = {0, 0, 0}, ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dop = 0.0;
+    std::vector<double> dk(size_t(c.K) * 3, 0.0);
+    uint8_t fl = 0;
+    for (int v = 0; v < V; ++v) {
+      const size_t ri = size_t(v) * N + g;
+      if (!c.disc[ri].vis) continue;
+      fl |= flag[0][ri];
+      const double* G = &G2[ri * 10];
+      const or_camera& cam = c.cams[v];
+      Geo o;
+      make_geo(c, v, g, o);
+      // opacity
+      dop += G[5];
+      // colour through SH, with the clamp at zero masking the gradient
+      sh.eval(o.v, Y.data(), dY);
+      double dv[3] = {0, 0, 0};
+      for (int ch = 0; ch < 3; ++ch) {
+        double raw = 0.5;
+        for (int k = 0; k < c.K; ++k) raw += c.sh[(g * c.K + k) * 3 + ch] * Y[k];
+        if (!(raw > 0.0)) continue;
+        const double gc = G[6 + ch];
+        for (int k = 0; k < c.K; ++k) {
+          dk[k * 3 + ch] += Y[k] * gc;
+          const double kc = c.sh[(g * c.K + k) * 3 + ch] * gc;
+          for (int i = 0; i < 3; ++i) dv[i] += kc * dY[k][i];
+        }
+      }
+      const double vdot = dv[0] * o.v[0] + dv[1] * o.v[1] + dv[2] * o.v[2];
+      for (int i = 0; i < 3; ++i) dp[i] += (dv[i] - o.v[i] * vdot) / o.dnorm;
+      // conic -> projected covariance: dS = -Q G_Q Q
+      const double Q[4] = {o.A, o.B, o.B, o.C};
+      const double GQ[4] = {G[2], 0.5 * G[3], 0.5 * G[3], G[4]};
+      double QG[4], dS[4];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) QG[i * 2 + j] = Q[i * 2 + 0] * GQ[0 * 2 + j] + Q[i * 2 + 1] * GQ[1 * 2 + j];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) dS[i * 2 + j] = -(QG[i * 2 + 0] * Q[0 * 2 + j] + QG[i * 2 + 1] * Q[1 * 2 + j]);
+      // Sigma_hat = T Sigma T^T: dSigma = T^T dS T, dT = 2 dS T Sigma
+      double dSig[9], dT[6];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double a = 0;
+          for (int k = 0; k < 2; ++k)
+            for (int l = 0; l < 2; ++l) a += o.T[k * 3 + i] * dS[k * 2 + l] * o.T[l * 3 + j];
+          dSig[i * 3 + j] = a;
+        }
+      double TSig[6];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double a = 0;
+          for (int k = 0; k < 3; ++k) a += o.T[i * 3 + k] * o.Sig[k * 3 + j];
+          TSig[i * 3 + j] = a;
+        }
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j) dT[i * 3 + j] = 2.0 * (dS[i * 2 + 0] * TSig[0 * 3 + j] + dS[i * 2 + 1] * TSig[1 * 3 + j]);
+      // T = J W: dJ = dT W^T
+      double dJ[6];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double a = 0;
+          for (int k = 0; k < 3; ++k) a += dT[i * 3 + k] * o.W[j * 3 + k];
+          dJ[i * 3 + j] = a;
+        }
+      const double fx = cam.fx, fy = cam.fy, tx = o.t[0], ty = o.t[1], tz = o.t[2];
+      double dt[3] = {0, 0, 0};
+      dt[0] += dJ[2] * (-fx / (tz * tz));
+      dt[1] += dJ[5] * (-fy / (tz * tz));
+      dt[2] += dJ[0] * (-fx / (tz * tz)) + dJ[2] * (2.0 * fx * tx / (tz * tz * tz)) + dJ[4] * (-fy / (tz * tz)) +
+               dJ[5] * (2.0 * fy * ty / (tz * tz * tz));
+      // splat centre (Eq. 4) and depth
+      dt[0] += G[0] * fx / tz;
+      dt[2] += -G[0] * fx * tx / (tz * tz);
+      dt[1] += G[1] * fy / tz;
+      dt[2] += -G[1] * fy * ty / (tz * tz);
+      dt[2] += G[9];
+      for (int i = 0; i < 3; ++i) dp[i] += o.W[0 * 3 + i] * dt[0] + o.W[1 * 3 + i] * dt[1] + o.W[2 * 3 + i] * dt[2];
+      // Sigma = M M^T: dM = 2 dSigma M; M = R diag(s)
+      double dM[9];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double a = 0;
+          for (int k = 0; k < 3; ++k) a += dSig[i * 3 + k] * o.M[k * 3 + j];
+          dM[i * 3 + j] = 2.0 * a;
+        }
+      double dR[9];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          ds[j] += dM[i * 3 + j] * o.R[i * 3 + j];
+          dR[i * 3 + j] = dM[i * 3 + j] * o.s[j];
+        }
+      double gR[4][9];
+      quat_rot_grad(o.qn, gR);
+      double dqn[4];
+      for (int a = 0; a < 4; ++a) {
+        double s = 0;
+        for (int i = 0; i < 9; ++i) s += gR[a][i] * dR[i];
+        dqn[a] = s;
+      }
+      const double qd = dqn[0] * o.qn[0] + dqn[1] * o.qn[1] + dqn[2] * o.qn[2] + dqn[3] * o.qn[3];
+      for (int a = 0; a < 4; ++a) dq[a] += (dqn[a] - o.qn[a] * qd) / o.qnorm;
+    }
+    for (int i = 0; i < 3; ++i) {
+      if (d_means) d_means[g * 3 + i] = dp[i];
+      if (d_scales) d_scales[g * 3 + i] = ds[i];
+    }
+    if (d_quats)
+      for (int i = 0; i < 4; ++i) d_quats[g * 4 + i] = dq[i];
+    if (d_opac) d_opac[g] = dop;
+    if (d_sh)
+      for (int i = 0; i < c.K * 3; ++i) d_sh[g * c.K * 3 + i] = dk[i];
+    if (flagged) flagged[g] = fl;
+  }
+}
+
+// Real SH basis values and polynomial-extension gradients at unit directions.
+void or_sh_eval(int32_t degree, const double* dirs, int64_t n, double* Y, double* dY) {
+  SHBasis sh(degree);
+  const int K = (degree + 1) * (degree + 1);
+  std::vector<double> gbuf(size_t(K) * 3);
+  double (*g)[3] = reinterpret_cast<double (*)[3]>(gbuf.data());
+  for (int64_t i = 0; i < n; ++i) {
+    sh.eval(dirs + i * 3, Y + i * K, dY ? g : nullptr);
+    if (dY)
+      for (int k = 0; k < K; ++k)
+        for (int j = 0; j < 3; ++j) dY[(i * K + k) * 3 + j] = g[k][j];
+  }
+}
+
+int32_t or_version(void) { return 1; }
+
+}  // extern "C"

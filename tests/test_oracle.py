@@ -1,0 +1,479 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+None of these compare the oracle with itself: each checks a closed form, an
+invariant, an independent library routine (SciPy's spherical harmonics), an
+independent NumPy implementation of the per-pixel definition, or finite
+differences.  Equation numbers refer to GSFusion (arXiv 2408.12677).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from oracle import brute
+
+I3 = np.eye(3, dtype=np.float32)
+Z3 = np.zeros(3, np.float32)
+
+
+def cam(W, H, f, cx=None, cy=None, R=I3, t=Z3):
+    return scenes.Camera(W, H, float(f), float(f), float(W / 2 if cx is None else cx),
+                         float(H / 2 if cy is None else cy), np.asarray(R, np.float32), np.asarray(t, np.float32))
+
+
+def gaussians(means, scales, quats=None, opac=None, rgb=None, sh=None, deg=0):
+    n = len(means)
+    means = np.asarray(means, np.float32).reshape(n, 3)
+    scales = np.asarray(scales, np.float32).reshape(n, 3)
+    quats = np.tile([1, 0, 0, 0], (n, 1)).astype(np.float32) if quats is None else np.asarray(quats, np.float32)
+    opac = np.full(n, 0.5, np.float32) if opac is None else np.asarray(opac, np.float32)
+    if sh is None:
+        rgb = np.full((n, 3), 0.5) if rgb is None else np.asarray(rgb, np.float64)
+        sh = scenes.dc_from_rgb(rgb).reshape(n, 1, 3).astype(np.float32)
+    return [means, scales, quats, opac, np.asarray(sh, np.float32)]
+
+
+def rot_z(theta):
+    return [math.cos(theta / 2), 0.0, 0.0, math.sin(theta / 2)]
+
+
+# ---------------------------------------------------------------------------------------
+# spherical harmonics (colour model, Sec. III-A-2)
+# ---------------------------------------------------------------------------------------
+
+def test_sh_matches_scipy_definition():
+    rng = np.random.default_rng(1)
+    d = rng.standard_normal((200, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    np.testing.assert_allclose(oracle.sh_eval(3, d), brute.real_sh(3, d), atol=1e-13)
+
+
+def test_sh_orthonormal_by_quadrature():
+    # product Gauss-Legendre (in cos theta) x uniform phi is exact for degree <= 6 products
+    xg, wg = np.polynomial.legendre.leggauss(8)
+    nphi = 16
+    phi = 2 * np.pi * np.arange(nphi) / nphi
+    ct, ph = np.meshgrid(xg, phi, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    dirs = np.stack([st * np.cos(ph), st * np.sin(ph), ct], -1).reshape(-1, 3)
+    w = (wg[:, None] * np.full(nphi, 2 * np.pi / nphi)[None, :]).reshape(-1)
+    Y = oracle.sh_eval(3, dirs)
+    G = (Y * w[:, None]).T @ Y
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_addition_theorem_and_constant():
+    rng = np.random.default_rng(2)
+    d = rng.standard_normal((100, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y = oracle.sh_eval(3, d)
+    np.testing.assert_allclose(Y[:, 0], 1 / (2 * math.sqrt(math.pi)), rtol=1e-15)
+    for l in range(4):
+        s = (Y[:, l * l:(l + 1) ** 2] ** 2).sum(1)
+        np.testing.assert_allclose(s, (2 * l + 1) / (4 * math.pi), rtol=1e-12)
+    # Condon-Shortley phase: Y_1^1 = -sqrt(3/4pi) x, Y_1^-1 = -sqrt(3/4pi) y, Y_1^0 = +sqrt(3/4pi) z
+    c1 = math.sqrt(3 / (4 * math.pi))
+    np.testing.assert_allclose(Y[:, 1:4], np.stack([-c1 * d[:, 1], c1 * d[:, 2], -c1 * d[:, 0]], 1), atol=1e-14)
+
+
+def test_sh_gradient_is_surface_gradient():
+    rng = np.random.default_rng(3)
+    d = rng.standard_normal((20, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    _, dY = oracle.sh_eval(3, d, grad=True)
+    h = 1e-6
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = h
+        dp, dm = d + e, d - e
+        fd = (oracle.sh_eval(3, dp / np.linalg.norm(dp, axis=1, keepdims=True)) -
+              oracle.sh_eval(3, dm / np.linalg.norm(dm, axis=1, keepdims=True))) / (2 * h)
+        # chain rule of normalisation: (I - v v^T) grad
+        proj = dY[:, :, j] - d[:, None, j] * np.einsum("nki,ni->nk", dY, d)
+        np.testing.assert_allclose(fd, proj, atol=1e-7)
+
+
+# ---------------------------------------------------------------------------------------
+# projection (Eq. 2, 4, 5)
+# ---------------------------------------------------------------------------------------
+
+def test_projection_on_axis_closed_form():
+    f, z = 100.0, 2.0
+    sx, sy, sz = 0.05, 0.07, 0.01
+    c = cam(64, 48, f)
+    p = gaussians([[0, 0, z]], [[sx, sy, sz]])
+    o = oracle.Oracle(p, 0, [c], oracle.Settings(mu_fp32=False))
+    r = o.records()
+    assert r["visible"][0]
+    np.testing.assert_array_equal(r["mu"][0], [32.0, 24.0])
+    f32 = lambda v: float(np.float32(v))     # binary32 inputs promoted exactly
+    cov = np.array([[(f * f32(sx) / z) ** 2 + f32(0.3), 0],
+                    [0, (f * f32(sy) / z) ** 2 + f32(0.3)]])
+    np.testing.assert_allclose(r["conic"][0], [1 / cov[0, 0], 0.0, 1 / cov[1, 1]], rtol=1e-12, atol=1e-15)
+
+
+def test_projection_isotropic_ignores_rotation():
+    c = cam(48, 40, 80.0)
+    base = gaussians([[0.1, -0.05, 2.0]], [[0.04, 0.04, 0.04]], quats=[[1, 0, 0, 0]], opac=[0.8], rgb=[[0.2, 0.6, 0.9]])
+    rot = [a.copy() for a in base]
+    rot[2] = np.array([[0.3, -0.5, 0.7, 0.2]], np.float32)
+    s = oracle.Settings(mu_fp32=False)
+    a = oracle.Oracle(base, 0, [c], s).forward()[0]
+    b = oracle.Oracle(rot, 0, [c], s).forward()[0]
+    np.testing.assert_allclose(a["color"], b["color"], atol=1e-13)
+    g = oracle.Oracle(rot, 0, [c], s).backward([np.ones((3, 40, 48))], [np.ones((40, 48))], None)
+    assert np.abs(g["quats"]).max() < 1e-9 * max(1.0, np.abs(g["means"]).max())
+    assert np.abs(g["means"]).max() > 1e-3
+
+
+# ---------------------------------------------------------------------------------------
+# compositing closed forms (Eq. 3, 11)
+# ---------------------------------------------------------------------------------------
+
+def _splat(W, H, f, z, s, theta, o):
+    """Closed-form alpha of an on-axis Gaussian rotated by theta about the optical axis."""
+    q32 = np.asarray(rot_z(theta), np.float32).astype(np.float64)
+    theta = 2.0 * math.atan2(q32[3], q32[0])          # angle of the binary32 quaternion
+    Rz = np.array([[math.cos(theta), -math.sin(theta)], [math.sin(theta), math.cos(theta)]])
+    s32 = np.float32(s)
+    cov = (f / z) ** 2 * Rz @ np.diag([float(s32[0]) ** 2, float(s32[1]) ** 2]) @ Rz.T + float(np.float32(0.3)) * np.eye(2)
+    Q = np.linalg.inv(cov)
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    dx, dy = xs - W / 2, ys - H / 2
+    q = Q[0, 0] * dx * dx + 2 * Q[0, 1] * dx * dy + Q[1, 1] * dy * dy
+    a = float(np.float32(o)) * np.exp(-0.5 * q)
+    alpha = np.where(a < float(np.float32(1 / 255)), 0.0, np.minimum(a, float(np.float32(0.99))))
+    return alpha, cov, np.exp(-0.5 * q)
+
+
+def test_single_gaussian_closed_form():
+    W, H, f, z = 64, 48, 100.0, 2.0
+    s, th, o, rgb, bg = [0.05, 0.08, 0.01], 0.6, 0.7, [0.9, 0.3, 0.1], (0.2, 0.4, 0.6)
+    p = gaussians([[0, 0, z]], [s], quats=[rot_z(th)], opac=[o], rgb=[rgb])
+    out = oracle.Oracle(p, 0, [cam(W, H, f)], oracle.Settings(mu_fp32=False, bg=bg)).forward()[0]
+    alpha, _, _ = _splat(W, H, f, z, s, th, o)
+    c = np.float32(scenes.dc_from_rgb(rgb)).astype(np.float64) / (2 * math.sqrt(math.pi)) + 0.5
+    np.testing.assert_allclose(out["alpha"], alpha, atol=1e-12)
+    np.testing.assert_allclose(out["depth"], float(np.float32(z)) * alpha, atol=1e-12)
+    exp_c = c[:, None, None] * alpha + np.asarray(bg, np.float64)[:, None, None] * (1 - alpha)
+    np.testing.assert_allclose(out["color"], exp_c, atol=1e-12)
+
+
+def test_opacity_clamp_and_skip_rule():
+    W, H, f, z = 32, 32, 100.0, 2.0
+    # o = 0.999 -> centre clamps to 0.99; faint tail below 1/255 is dropped entirely
+    p = gaussians([[0, 0, z]], [[0.03, 0.03, 0.03]], opac=[0.999])
+    out = oracle.Oracle(p, 0, [cam(W, H, f)], oracle.Settings(mu_fp32=False)).forward()[0]
+    assert out["alpha"].max() == pytest.approx(float(np.float32(0.99)), abs=1e-15)
+    nz = out["alpha"][out["alpha"] > 0]
+    assert nz.min() >= float(np.float32(1 / 255))
+
+
+def test_two_gaussians_closed_form():
+    W, H, f = 48, 40, 90.0
+    z1, z2 = 1.5, 3.0
+    s1, s2 = [0.04, 0.06, 0.01], [0.09, 0.05, 0.02]
+    o1, o2 = 0.6, 0.8
+    c1, c2 = [0.1, 0.7, 0.3], [0.8, 0.2, 0.5]
+    # list them back to front to check the depth sort
+    p = gaussians([[0, 0, z2], [0, 0, z1]], [s2, s1], quats=[rot_z(1.0), rot_z(0.3)], opac=[o2, o1], rgb=[c2, c1])
+    out = oracle.Oracle(p, 0, [cam(W, H, f)], oracle.Settings(mu_fp32=False, T_min=0.0)).forward()[0]
+    a1, _, _ = _splat(W, H, f, float(np.float32(z1)), s1, 0.3, o1)
+    a2, _, _ = _splat(W, H, f, float(np.float32(z2)), s2, 1.0, o2)
+    col = lambda c: (np.float32(scenes.dc_from_rgb(c)).astype(np.float64) / (2 * math.sqrt(math.pi)) + 0.5)[:, None, None]
+    C = col(c1) * a1 + col(c2) * a2 * (1 - a1)
+    D = float(np.float32(z1)) * a1 + float(np.float32(z2)) * a2 * (1 - a1)
+    np.testing.assert_allclose(out["color"], C, atol=1e-6)   # splats use the binary32 quaternion
+    np.testing.assert_allclose(out["depth"], D, atol=1e-6)
+    np.testing.assert_allclose(out["T_final"], (1 - a1) * (1 - a2), atol=1e-6)
+
+
+def test_riemann_mass_pins_conic_scale_and_skip_rule():
+    # sum_u alpha(u) -> 2 pi sqrt(det Sigma_hat) (o - 1/255) for a wide unclamped splat
+    W, H, f, z, o = 96, 96, 100.0, 2.0, 0.6
+    s, th = [0.05, 0.08, 0.01], 0.4
+    p = gaussians([[0, 0, z]], [s], quats=[rot_z(th)], opac=[o])
+    out = oracle.Oracle(p, 0, [cam(W, H, f)], oracle.Settings(mu_fp32=False)).forward()[0]
+    _, cov, _ = _splat(W, H, f, z, s, th, o)
+    mass = 2 * math.pi * math.sqrt(np.linalg.det(cov)) * (float(np.float32(o)) - float(np.float32(1 / 255)))
+    assert out["alpha"].sum() == pytest.approx(mass, rel=1e-3)
+
+
+def test_single_gaussian_opacity_gradient_closed_form():
+    # d alpha / d o = G(u) where the splat is neither skipped nor clamped
+    W, H, f, z = 40, 40, 100.0, 2.0
+    s, th, o = [0.04, 0.06, 0.02], 0.2, 0.5
+    p = gaussians([[0, 0, z]], [s], quats=[rot_z(th)], opac=[o])
+    orc = oracle.Oracle(p, 0, [cam(W, H, f)], oracle.Settings(mu_fp32=False))
+    alpha, _, G = _splat(W, H, f, z, s, th, o)
+    gA = np.zeros((H, W))
+    gA[20, 20] = 1.0
+    gA[23, 18] = 1.0
+    g = orc.backward(None, None, [gA])
+    assert g["opacities"][0] == pytest.approx(G[20, 20] + G[23, 18], rel=1e-10)
+
+
+# ---------------------------------------------------------------------------------------
+# invariants
+# ---------------------------------------------------------------------------------------
+
+def test_transmittance_non_increasing_along_list():
+    w = scenes.make_cfg1(n=300)
+    g = w.gaussians
+    c = cam(64, 48, 55.0)
+    s = oracle.Settings(mu_fp32=False)
+    z = np.asarray(g.means[:, 2])
+    order = np.argsort(z, kind="stable")
+    prev = np.ones((48, 64))
+    for k in (10, 40, 80, 160, 300):
+        sub = g.subset(np.sort(order[:k]))
+        out = oracle.Oracle(sub.arrays(), 0, [c], s).forward()[0]
+        assert np.all(out["T_final"] <= prev + 1e-15)
+        prev = out["T_final"]
+    out = oracle.Oracle(g.arrays(), 0, [c], s).forward()[0]
+    assert np.all(out["alpha"] >= 0) and np.all(out["alpha"] < 1)
+    cmax = (0.5 + g.sh[:, 0, :].astype(np.float64) / (2 * math.sqrt(math.pi))).max(0)   # per-channel max splat colour
+    assert np.all(out["color"] <= cmax[:, None, None] * out["alpha"] + 1e-12)
+
+
+def test_permutation_invariance():
+    w = scenes.make_cfg1(n=200)
+    g = w.gaussians
+    c = cam(64, 48, 55.0)
+    s = oracle.Settings()
+    perm = np.random.default_rng(5).permutation(g.n)
+    a = oracle.Oracle(g.arrays(), 0, [c], s)
+    b = oracle.Oracle(g.subset(perm).arrays(), 0, [c], s)
+    fa, fb = a.forward()[0], b.forward()[0]
+    np.testing.assert_array_equal(fa["color"], fb["color"])
+    gC = [np.random.default_rng(6).standard_normal((3, 48, 64))]
+    ga, gb = a.backward(gC), b.backward(gC)
+    np.testing.assert_array_equal(ga["means"][perm], gb["means"])
+    np.testing.assert_array_equal(ga["sh"][perm], gb["sh"])
+
+
+def test_shift_principal_point_by_one_tile():
+    w = scenes.make_cfg1(n=300)
+    g = w.gaussians
+    s = oracle.Settings(mu_fp32=False)
+    a = oracle.Oracle(g.arrays(), 0, [cam(96, 64, 60.0, cx=40.0, cy=32.0)], s).forward()[0]
+    b = oracle.Oracle(g.arrays(), 0, [cam(96, 64, 60.0, cx=56.0, cy=32.0)], s).forward()[0]
+    np.testing.assert_allclose(b["color"][:, :, 16:], a["color"][:, :, :80], atol=1e-12)
+
+
+# ---------------------------------------------------------------------------------------
+# brute force (no tiles) and literal Eq. 11
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("deg", [0, 3])
+def test_tiles_equal_brute_force(deg):
+    rng = np.random.default_rng(10 + deg)
+    n = 150
+    means = np.stack([rng.uniform(-1, 1, n), rng.uniform(-0.8, 0.8, n), rng.uniform(1, 4, n)], 1)
+    g = scenes.random_gaussians(rng, means * 0.5, deg)
+    g.scales *= 3
+    c = cam(40, 32, 30.0, cx=19.5, cy=16.25)
+    out = oracle.Oracle(g.arrays(), deg, [c], oracle.Settings(mu_fp32=False, tile=8)).forward()[0]
+    b = brute.render(g.arrays(), deg, c)
+    for k in ("color", "depth", "alpha", "T_final"):
+        np.testing.assert_allclose(out[k], b[k], atol=1e-12, err_msg=k)
+    assert out["n_used"].sum() > 200
+
+
+def test_literal_eq11_without_rules():
+    rng = np.random.default_rng(12)
+    n = 30
+    means = np.stack([rng.uniform(-0.5, 0.5, n), rng.uniform(-0.4, 0.4, n), rng.uniform(1, 3, n)], 1)
+    g = scenes.random_gaussians(rng, means, 0)
+    g.scales *= 4
+    c = cam(24, 20, 25.0)
+    s = oracle.Settings(mu_fp32=False, extent_k=1e4, alpha_min=0.0, alpha_max=1.0, T_min=0.0, tile=8)
+    out = oracle.Oracle(g.arrays(), 0, [c], s).forward()[0]
+    # Eq. 11 word for word, Gaussians sorted by depth
+    pr = brute.project(g.arrays(), 0, c)
+    order = np.argsort(pr["z"], kind="stable")
+    ys, xs = np.mgrid[0:20, 0:24].astype(np.float64)
+    I = np.zeros((3, 20, 24))
+    for i, gi in enumerate(order):
+        def Ghat(j):
+            Q = pr["conic"][j]
+            dx, dy = xs - pr["mu"][j, 0], ys - pr["mu"][j, 1]
+            return np.exp(-0.5 * (Q[0, 0] * dx * dx + 2 * Q[0, 1] * dx * dy + Q[1, 1] * dy * dy))
+        prod = np.ones((20, 24))
+        for gj in order[:i]:
+            prod *= 1 - pr["opacity"][gj] * Ghat(gj)
+        I += pr["color"][gi][:, None, None] * pr["opacity"][gi] * Ghat(gi) * prod
+    np.testing.assert_allclose(out["color"], I, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------------------
+# discrete stage: an independent float32 transcription of the documented op sequence
+# ---------------------------------------------------------------------------------------
+
+def discrete_stage_f32(p, s, q, c, k=3.33, lowpass=0.3, full=False):
+    f = np.float32
+    p, s, q = (np.asarray(a, np.float32) for a in (p, s, q))
+    W = np.asarray(c.R, np.float32).reshape(9)
+    t = np.asarray(c.t, np.float32)
+    tx = ((W[0] * p[:, 0] + W[1] * p[:, 1]) + W[2] * p[:, 2]) + t[0]
+    ty = ((W[3] * p[:, 0] + W[4] * p[:, 1]) + W[5] * p[:, 2]) + t[1]
+    tz = ((W[6] * p[:, 0] + W[7] * p[:, 1]) + W[8] * p[:, 2]) + t[2]
+    nq = np.sqrt(((q[:, 0] * q[:, 0] + q[:, 1] * q[:, 1]) + q[:, 2] * q[:, 2]) + q[:, 3] * q[:, 3])
+    w, x, y, z = (q[:, i] / nq for i in range(4))
+    one, two = f(1), f(2)
+    r = [one - two * (y * y + z * z), two * (x * y - w * z), two * (x * z + w * y),
+         two * (x * y + w * z), one - two * (x * x + z * z), two * (y * z - w * x),
+         two * (x * z - w * y), two * (y * z + w * x), one - two * (x * x + y * y)]
+    m = [r[i * 3 + j] * s[:, j] for i in range(3) for j in range(3)]
+    fx, fy = f(c.fx), f(c.fy)
+    tz2 = tz * tz
+    j00, j11 = fx / tz, fy / tz
+    j02, j12 = -(fx * tx) / tz2, -(fy * ty) / tz2
+    T = [j00 * W[cc] + j02 * W[6 + cc] for cc in range(3)] + [j11 * W[3 + cc] + j12 * W[6 + cc] for cc in range(3)]
+    U = [((T[i * 3] * m[cc] + T[i * 3 + 1] * m[3 + cc]) + T[i * 3 + 2] * m[6 + cc]) for i in range(2) for cc in range(3)]
+    lp = f(lowpass)
+    a = ((U[0] * U[0] + U[1] * U[1]) + U[2] * U[2]) + lp
+    b = (U[0] * U[3] + U[1] * U[4]) + U[2] * U[5]
+    cc_ = ((U[3] * U[3] + U[4] * U[4]) + U[5] * U[5]) + lp
+    det = a * cc_ - b * b
+    mux = fx * (tx / tz) + f(c.cx)
+    muy = fy * (ty / tz) + f(c.cy)
+    kk = f(k)
+    rx, ry = kk * np.sqrt(a), kk * np.sqrt(cc_)
+    x0, x1 = np.ceil(mux - rx), np.floor(mux + rx)
+    y0, y1 = np.ceil(muy - ry), np.floor(muy + ry)
+    x0 = np.where(x0 < 0, f(0), x0)
+    y0 = np.where(y0 < 0, f(0), y0)
+    x1 = np.where(x1 > f(c.width - 1), f(c.width - 1), x1)
+    y1 = np.where(y1 > f(c.height - 1), f(c.height - 1), y1)
+    vis = (tz > f(c.znear)) & (nq > 0) & (det > 0) & (x0 <= x1) & (y0 <= y1)
+    if full:
+        return vis, tz, np.stack([mux, muy], 1), np.stack([x0, x1, y0, y1], 1), a
+    return vis, tz, np.stack([mux, muy], 1), np.stack([x0, x1, y0, y1], 1)
+
+
+@pytest.mark.parametrize("posed", [False, True])
+def test_discrete_stage_matches_float32_transcription(posed):
+    w = scenes.make_cfg1(n=20000)
+    g = w.gaussians
+    c = w.cameras[0]
+    if posed:   # a general rotation and translation so every product and sum matters
+        R, t = scenes.look_at([0.3, -0.2, -0.5], [0.1, 0.05, 3.0], up=(0.1, -1, 0))
+        c = scenes.Camera(c.width, c.height, c.fx, c.fy, 63.7, 47.9, R, t)
+    with np.errstate(all="ignore"):
+        vis, tz, mu, rect = discrete_stage_f32(g.means, g.scales, g.quats, c)
+    r = oracle.Oracle(g.arrays(), 0, [c]).records()
+    assert vis.sum() > 1000
+    np.testing.assert_array_equal(r["visible"], vis)
+    np.testing.assert_array_equal(r["z"][vis].view(np.uint32), tz[vis].view(np.uint32))
+    np.testing.assert_array_equal(r["mu"][vis].view(np.uint32), mu[vis].view(np.uint32))
+    np.testing.assert_array_equal(r["cov"][vis][:, 0].view(np.uint32), _cov_a(g, c)[vis].view(np.uint32))
+    np.testing.assert_array_equal(r["rect"][vis], rect[vis].astype(np.int32))
+
+
+def _cov_a(g, c):
+    """First entry of the binary32 projected covariance, recomputed via the transcription."""
+    with np.errstate(all="ignore"):
+        return discrete_stage_f32(g.means, g.scales, g.quats, c, full=True)[4]
+
+
+def test_keys_sorted_unique_and_ranges_partition():
+    w = scenes.make_cfg1()
+    g = w.gaussians
+    c = w.cameras[0]
+    o = oracle.Oracle(g.arrays(), 0, [c, c.crop(10, 8, 100, 70)], oracle.Settings(tile=16))
+    keys, vals, ranges = o.keys()
+    assert np.all(keys[1:] >= keys[:-1])
+    r = o.records()
+    tiles = keys >> np.uint64(32)
+    pairs = set(zip(tiles.tolist(), vals.tolist()))
+    assert len(pairs) == len(keys)                       # each (tile, Gaussian) once
+    rect = r["rect"][r["visible"]]
+    area = ((rect[:, 1] // 16 - rect[:, 0] // 16 + 1) * (rect[:, 3] // 16 - rect[:, 2] // 16 + 1)).sum()
+    assert area == len(keys)                             # M = sum of tile-rect areas
+    nz = ranges[ranges[:, 1] > ranges[:, 0]]
+    assert nz[0, 0] == 0 and nz[-1, 1] == len(keys)
+    assert np.all(nz[1:, 0] == nz[:-1, 1])               # ranges partition [0, M)
+    for t in np.unique(tiles)[:20]:
+        s, e = ranges[t]
+        assert np.all(tiles[s:e] == t)
+        z = (keys[s:e] & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+        v = vals[s:e]
+        assert np.all((z[1:] > z[:-1]) | ((z[1:] == z[:-1]) & (v[1:] > v[:-1])))   # ties by index
+
+
+# ---------------------------------------------------------------------------------------
+# gradients: central finite differences in FP64
+# ---------------------------------------------------------------------------------------
+
+def _fd_scene(deg, seed):
+    rng = np.random.default_rng(seed)
+    n = 24
+    means = np.stack([rng.uniform(-0.5, 0.5, n), rng.uniform(-0.4, 0.4, n), rng.uniform(1.5, 3.0, n)], 1)
+    g = scenes.random_gaussians(rng, means, deg)
+    g.scales *= 3
+    g.opacities[:] = np.float32(0.3 + 0.6 * rng.random(n))
+    c = scenes.Camera(40, 32, 35.0, 35.0, 20.0, 16.0, *scenes.look_at([0.05, -0.02, -0.1], [0.0, 0.0, 2.0], up=(0, -1, 0)))
+    return g, c
+
+
+@pytest.mark.parametrize("deg,seed", [(0, 20), (3, 21)])
+def test_backward_matches_central_differences(deg, seed):
+    g, c = _fd_scene(deg, seed)
+    s = oracle.Settings(mu_fp32=False, tile=8, bg=(0.1, 0.2, 0.3))
+    rng = np.random.default_rng(seed + 100)
+    H, W = c.height, c.width
+    wC, wD, wA = rng.standard_normal((3, H, W)), rng.standard_normal((H, W)), rng.standard_normal((H, W))
+    base = [np.asarray(a, np.float64).copy() for a in g.arrays()]
+    orc = oracle.Oracle(base, deg, [c], s)
+    ref_keys = orc.keys()
+    ref_out = orc.forward()[0]
+    an = orc.backward([wC], [wD], [wA])
+
+    def f(params):
+        o = oracle.Oracle(params, deg, [c], s)
+        out = o.forward()[0]
+        val = (wC * out["color"]).sum() + (wD * out["depth"]).sum() + (wA * out["alpha"]).sum()
+        k = o.keys()
+        same = (np.array_equal(k[0] >> np.uint64(32), ref_keys[0] >> np.uint64(32)) and np.array_equal(k[1], ref_keys[1])
+                and np.array_equal(out["n_contrib"], ref_out["n_contrib"]) and np.array_equal(out["n_used"], ref_out["n_used"]))
+        return val, same
+
+    names = ["means", "scales", "quats", "opacities", "sh"]
+    h = 1e-6
+    checked = 0
+    for trial in range(100):
+        gi = trial % 5
+        arr = base[gi]
+        idx = tuple(rng.integers(0, d) for d in arr.shape)
+        plus = [a.copy() for a in base]
+        minus = [a.copy() for a in base]
+        plus[gi][idx] += h
+        minus[gi][idx] -= h
+        fp, sp = f(plus)
+        fm, sm = f(minus)
+        if not (sp and sm):
+            continue
+        fd = (fp - fm) / (2 * h)
+        a = an[names[gi]][idx]
+        scale = max(abs(a), 1e-2 * np.abs(an[names[gi]]).max(), 1e-6)
+        assert abs(fd - a) <= 1e-4 * scale, (names[gi], idx, fd, a)
+        checked += 1
+    assert checked >= 80
+
+
+def test_loss_l1_gradient():
+    rng = np.random.default_rng(30)
+    C, D = rng.random((3, 8, 9)), rng.random((8, 9)) * 3
+    tc, td = rng.random((3, 8, 9)), rng.random((8, 9)) * 3
+    td[0, :4] = 0.0
+    L, gC, gD = oracle.l1_loss(C, D, tc, td, 0.1)
+    h = 1e-7
+    for idx in [(0, 1, 2), (2, 7, 8)]:
+        Cp = C.copy()
+        Cp[idx] += h
+        assert (oracle.l1_loss(Cp, D, tc, td)[0] - L) / h == pytest.approx(gC[idx], rel=1e-5)
+    assert np.all(gD[0, :4] == 0)
+    assert L == pytest.approx(np.abs(C - tc).mean() + 0.1 * np.abs(D - td)[td > 0].sum() / D.size)
