@@ -1,0 +1,212 @@
+/*
+ * gsr.h -- C ABI of an MI355X (gfx950) differentiable tile-based Gaussian-splatting
+ * rasterizer: the step GSFusion's online optimisation runs forward and backward over
+ * the Gaussian map at every iteration (Sec. III-B-3 of arXiv 2408.12677).
+ *
+ * The library renders a set of 3D Gaussians (Eq. 1-2: mean p_g, covariance
+ * Sigma = R S S^T R^T, opacity, spherical-harmonic colour) through one or more pinhole
+ * cameras: it projects each Gaussian to a 2D splat (Eq. 3-5), sorts the splats by
+ * depth inside every screen tile, alpha-blends them front to back (Eq. 11) into
+ * colour, depth and alpha images, evaluates the L1 loss of Eq. 12 (plus an optional
+ * weighted L1 depth term), and propagates the loss gradient back to every Gaussian
+ * parameter ("all the gradients for parameters are explicitly derived").
+ *
+ * Conventions
+ *  - Every buffer pointer handed to the library is DEVICE memory on the context's
+ *    GPU unless the comment says "host".  All arrays are float32, C-contiguous.
+ *  - Gaussians (structure of arrays, N entries):
+ *      means [N,3]      world-space centres
+ *      scales [N,3]     per-axis standard deviations (S = diag(scales)), > 0
+ *      quats [N,4]      rotation as (w,x,y,z); normalised inside, need not be unit
+ *      opacities [N]    activated opacity in [0,1]
+ *      sh [N,K,3]       real SH coefficients per colour channel, K=(deg+1)^2, index
+ *                       k = l*l+l+m; colour = max(0, 0.5 + sum_k sh_k Y_k(d)) with d the
+ *                       unit direction from the camera centre to the mean and Y the
+ *                       orthonormal real harmonics with Condon-Shortley phase.
+ *  - Cameras (host structs): OpenCV pinhole, world->camera x_c = R x_w + t, pixel
+ *    (i,j) is sampled at its integer coordinates; Gaussians with camera depth
+ *    <= znear are culled.
+ *  - Images: colour [3,H,W] (planar), depth [H,W] (sum of z*alpha*T, background 0),
+ *    alpha [H,W] (1 - final transmittance).
+ *  - Keys: (global tile id << 32) | bits(float32 depth), sorted ascending and stably;
+ *    a global tile id is the view's tile offset plus ty*tiles_x+tx.
+ *  - Streams: all device work is enqueued on the context's HIP stream.  Only
+ *    gsr_forward (one 8-byte read-back of the duplicated-key count) and
+ *    gsr_debug_export synchronise with the host.  A context is not thread-safe.
+ *  - Errors: every call returns a gsr_status; arguments are validated before any
+ *    device work; a failing call leaves outputs unspecified but the context usable.
+ *    gsr_last_error() gives a message.  NaN/Inf inputs are not rejected.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSR_ABI_VERSION 1
+#define GSR_MAX_VIEWS 16
+
+typedef enum {
+  GSR_OK = 0,
+  GSR_EINVAL = 1,    /* invalid argument (NULL pointer, size out of range, bad enum) */
+  GSR_ENOMEM = 2,    /* device allocation failed */
+  GSR_EDEVICE = 3,   /* HIP runtime error or no usable device */
+  GSR_ECAPACITY = 4, /* a captured graph's key capacity was exceeded; re-create it */
+  GSR_EINTERNAL = 5
+} gsr_status;
+
+typedef struct gsr_ctx gsr_ctx;     /* per-stream context (owns scratch memory) */
+typedef struct gsr_saved gsr_saved; /* forward state needed by the backward pass */
+typedef struct gsr_graph gsr_graph; /* a captured forward+loss+backward step */
+
+typedef struct {
+  int64_t n;          /* number of Gaussians, >= 0 */
+  int32_t sh_degree;  /* 0..3 */
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opacities;
+  const float* sh;
+} gsr_gaussians;
+
+typedef struct {
+  int32_t width, height; /* 1..8192 */
+  float fx, fy, cx, cy;  /* intrinsics in pixels */
+  float R[9];            /* world->camera rotation, row-major (host) */
+  float t[3];            /* world->camera translation (host) */
+  float znear;           /* > 0 */
+} gsr_camera;
+
+/* Rendering rules.  gsr_settings_default() gives tile 16, batch 256, extent 3.33
+ * standard deviations (>= sqrt(2 ln 255), so no splat value >= alpha_min is ever
+ * outside its tile rectangle), low-pass 0.3 px^2 on the projected covariance,
+ * alpha_min 1/255 (strictly smaller values are skipped), alpha_max 0.99 (clamp),
+ * T_min 1e-4 (stop after the Gaussian that takes transmittance below it), guard 0.15
+ * (only Gaussians "lying in the current view frustum" are rendered: the projected
+ * centre must fall inside the image widened by guard x its width/height on each
+ * side, and the depth must exceed znear), black background. */
+typedef struct {
+  int32_t tile;      /* 8, 16 or 32 */
+  int32_t batch;     /* Gaussians staged in LDS per round: 128 or 256 */
+  float extent_k;
+  float lowpass;
+  float alpha_min;
+  float alpha_max;
+  float T_min;
+  float guard;       /* >= 0 */
+  float bg[3];
+  uint32_t flags;    /* reserved, must be 0 */
+} gsr_settings;
+
+typedef struct {
+  float* color; /* [3,H,W] */
+  float* depth; /* [H,W] or NULL */
+  float* alpha; /* [H,W] or NULL */
+} gsr_view_out;
+
+/* dL/d(outputs) of one view; NULL means zero. */
+typedef struct {
+  const float* color; /* [3,H,W] */
+  const float* depth; /* [H,W] */
+  const float* alpha; /* [H,W] */
+} gsr_view_grad;
+
+/* L1 targets of one view (Eq. 12 and the depth term). */
+typedef struct {
+  const float* color; /* [3,H,W] */
+  const float* depth; /* [H,W]; pixels with target depth <= 0 are left out of the depth term */
+} gsr_target;
+
+/* Output gradients in the parameter layouts; any pointer may be NULL to skip it. */
+typedef struct {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opacities;
+  float* sh;
+} gsr_gaussian_grads;
+
+/* Sizes of a forward pass (host values). */
+typedef struct {
+  int64_t num_keys;      /* M: duplicated (tile, Gaussian) pairs */
+  int64_t num_tiles;     /* tiles over all views */
+  int64_t num_pixels;    /* pixels over all views */
+  int64_t num_records;   /* V*N */
+  int32_t views;
+  int32_t sort_passes;   /* 8-bit radix passes run */
+} gsr_info;
+
+/* Host copies of the intermediate state, for tests.  Each pointer may be NULL;
+ * sizes follow gsr_info. */
+typedef struct {
+  uint64_t* keys;     /* [M] sorted keys */
+  uint32_t* values;   /* [M] record index v*N+g of each sorted key */
+  uint32_t* ranges;   /* [num_tiles,2] [start,end) per tile, [0,0) when empty */
+  float* T_final;     /* [num_pixels] final transmittance, views concatenated */
+  uint32_t* n_contrib;/* [num_pixels] one past the list position of the last contributor */
+  uint32_t* tiles_touched; /* [V*N] tile-rectangle area, 0 when culled */
+  float* mu;          /* [V*N,2] splat centres (binary32, exact op sequence) */
+  float* depth;       /* [V*N] camera depth (binary32) */
+  float* conic;       /* [V*N,3] inverse projected covariance (A, B, C) */
+  float* color;       /* [V*N,3] SH colour */
+  int32_t* rect;      /* [V*N,4] tile rectangle (tx0, tx1, ty0, ty1), inclusive */
+} gsr_debug;
+
+/* Library version of this header. */
+int32_t gsr_abi_version(void);
+
+/* Fill *s with the default rules above.  EINVAL if s is NULL. */
+gsr_status gsr_settings_default(gsr_settings* s);
+
+/* Create a context on HIP device `device` enqueuing on `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  Scratch memory comes from the device's stream-ordered
+ * memory pool.  EDEVICE when the device cannot be used. */
+gsr_status gsr_ctx_create(int32_t device, void* hip_stream, gsr_ctx** out);
+gsr_status gsr_ctx_destroy(gsr_ctx* ctx);
+gsr_status gsr_ctx_set_stream(gsr_ctx* ctx, void* hip_stream);
+
+/* Forward render (Eq. 2-5 and 11) of V views of one Gaussian map.
+ * cams[V] are host structs, outs[V] device images.  With saved != NULL the state
+ * the backward needs (splat records, sorted list, tile ranges, final transmittance,
+ * contributor counts) is kept in *saved; the caller must then keep g's arrays
+ * alive and unchanged until gsr_saved_free.  1 <= V <= GSR_MAX_VIEWS.
+ * Synchronises once to read the duplicated-key count back. */
+gsr_status gsr_forward(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
+                       const gsr_settings* s, const gsr_view_out* outs, gsr_saved** saved);
+
+/* L1 loss (Eq. 12, mean over 3*P colour values) plus depth_weight times the mean
+ * absolute depth error over pixels with a valid target depth, summed over views.
+ * Reads the rendered images outs[V] and targets[V]; writes dL/dcolour and
+ * dL/ddepth into grads_out[V] (device buffers of the image shapes; sign(0) = 0).
+ * *loss_dev (device float) receives the loss. */
+gsr_status gsr_loss_l1(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_out* outs,
+                       const gsr_target* targets, float depth_weight, float* const* grad_color_out,
+                       float* const* grad_depth_out, float* loss_dev);
+
+#define GSR_ACCUMULATE 1u /* add into the gradient buffers instead of overwriting */
+
+/* Backward pass: given dL/d(outputs) per view, write dL/d(parameters) of the
+ * Gaussians saved by gsr_forward, summed over views.  Transmittance is recovered
+ * per pixel from the saved final value; no per-(pixel, Gaussian) state is stored.
+ * Floating-point atomics make the summation order (not the value) nondeterministic. */
+gsr_status gsr_backward(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_grad* grads,
+                        const gsr_gaussian_grads* out, uint32_t flags);
+
+gsr_status gsr_saved_info(const gsr_saved* saved, gsr_info* info);
+gsr_status gsr_saved_free(gsr_saved* saved);
+
+/* Copy intermediate state to host memory (synchronises the stream). */
+gsr_status gsr_debug_export(gsr_ctx* ctx, const gsr_saved* saved, const gsr_debug* out);
+
+/* Message of the last failing call on ctx ("" if none); ctx may be NULL for
+ * failures that had no context. */
+const char* gsr_last_error(const gsr_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSR_H */

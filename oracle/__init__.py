@@ -54,8 +54,8 @@ class _Cam(ctypes.Structure):
 class _Set(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("extent_k", ctypes.c_float), ("lowpass", ctypes.c_float),
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("T_min", ctypes.c_float),
-                ("bg", ctypes.c_float * 3), ("mu_fp32", ctypes.c_int32), ("threads", ctypes.c_int32),
-                ("amb_rel", ctypes.c_float)]
+                ("guard", ctypes.c_float), ("bg", ctypes.c_float * 3), ("mu_fp32", ctypes.c_int32),
+                ("threads", ctypes.c_int32), ("amb_rel_a", ctypes.c_float), ("amb_rel_T", ctypes.c_float)]
 
 
 _lib = None
@@ -88,21 +88,26 @@ def _ptr(a):
 
 @dataclass
 class Settings:
-    """Rendering rules (paper readings: clamp 0.99, skip < 1/255, stop at T < 1e-4)."""
+    """Rendering rules (paper readings: clamp 0.99, skip < 1/255, stop at T < 1e-4; only
+    Gaussians whose centre lies in the view frustum, widened by ``guard`` x the image
+    size on each side, are rendered)."""
     tile: int = 16
     extent_k: float = 3.33
     lowpass: float = 0.3
     alpha_min: float = 1.0 / 255.0
     alpha_max: float = 0.99
     T_min: float = 1e-4
+    guard: float = 0.15
     bg: tuple = (0.0, 0.0, 0.0)
     mu_fp32: bool = True
     threads: int = 1
-    amb_rel: float = 1e-4
+    amb_rel_a: float = 1e-5     # binary32 a = o exp(-q/2) is good to ~5e-6 relative
+    amb_rel_T: float = 1e-4     # binary32 T accumulates ~100 rounded products
 
     def _c(self):
-        return _Set(self.tile, self.extent_k, self.lowpass, self.alpha_min, self.alpha_max, self.T_min,
-                    (ctypes.c_float * 3)(*self.bg), int(self.mu_fp32), int(self.threads), self.amb_rel)
+        return _Set(self.tile, self.extent_k, self.lowpass, self.alpha_min, self.alpha_max, self.T_min, self.guard,
+                    (ctypes.c_float * 3)(*self.bg), int(self.mu_fp32), int(self.threads), self.amb_rel_a,
+                    self.amb_rel_T)
 
 
 def _cams(cameras):

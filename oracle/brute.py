@@ -61,8 +61,12 @@ def quat_to_rot(q):
     return R
 
 
-def project(params, sh_degree, cam, lowpass=0.3):
-    """FP64 splat parameters of every Gaussian: dict(mu, conic, z, color, opacity, front)."""
+def project(params, sh_degree, cam, lowpass=0.3, guard=0.15):
+    """FP64 splat parameters of every Gaussian: dict(mu, conic, z, color, opacity, front).
+
+    ``front`` marks the Gaussians in the view frustum: binary32 depth above znear and
+    binary32 projected centre inside the image widened by guard x (W, H) per side.
+    """
     means, scales, quats, opac, sh = (np.asarray(a, np.float64) for a in params)
     W = np.asarray(cam.R, np.float32).astype(np.float64)
     tc = np.asarray(cam.t, np.float32).astype(np.float64)
@@ -86,19 +90,31 @@ def project(params, sh_degree, cam, lowpass=0.3):
     dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
     Y = real_sh(sh_degree, dirs)
     color = np.maximum(0.0, 0.5 + np.einsum("nk,nkc->nc", Y, sh))
-    # binary32 depth, same operation order as the discrete stage, for the ordering
+    # binary32 camera coordinates and centre, same operation order as the discrete stage,
+    # for the ordering and the frustum decision
     p32 = np.asarray(params[0], np.float32)
     W32 = np.asarray(cam.R, np.float32)
-    z32 = (W32[2, 0] * p32[:, 0] + W32[2, 1] * p32[:, 1]).astype(np.float32)
-    z32 = (z32 + W32[2, 2] * p32[:, 2]).astype(np.float32)
-    z32 = (z32 + np.float32(cam.t[2])).astype(np.float32)
-    front = z32 > np.float32(cam.znear)
+    t32 = np.asarray(cam.t, np.float32)
+    c32 = []
+    for r in range(3):
+        v = (W32[r, 0] * p32[:, 0] + W32[r, 1] * p32[:, 1]).astype(np.float32)
+        v = (v + W32[r, 2] * p32[:, 2]).astype(np.float32)
+        c32.append((v + t32[r]).astype(np.float32))
+    x32, y32, z32 = c32
+    f = np.float32
+    with np.errstate(all="ignore"):
+        mux = f(cam.fx) * (x32 / z32) + f(cam.cx)
+        muy = f(cam.fy) * (y32 / z32) + f(cam.cy)
+    gx, gy = f(guard) * f(cam.width), f(guard) * f(cam.height)
+    inside = (mux >= -gx) & (mux <= f(cam.width) + gx) & (muy >= -gy) & (muy <= f(cam.height) + gy)
+    front = (z32 > np.float32(cam.znear)) & inside
     return dict(mu=mu, conic=conic, z=tz, z32=z32, color=color, opacity=opac, front=front)
 
 
-def render(params, sh_degree, cam, alpha_min=1 / 255, alpha_max=0.99, T_min=1e-4, bg=(0, 0, 0), lowpass=0.3):
-    """Per-pixel front-to-back compositing over all Gaussians (no tiles)."""
-    pr = project(params, sh_degree, cam, lowpass)
+def render(params, sh_degree, cam, alpha_min=1 / 255, alpha_max=0.99, T_min=1e-4, bg=(0, 0, 0), lowpass=0.3,
+           guard=0.15):
+    """Per-pixel front-to-back compositing over all Gaussians in the frustum (no tiles)."""
+    pr = project(params, sh_degree, cam, lowpass, guard)
     idx = np.nonzero(pr["front"])[0]
     zb = pr["z32"][idx].view(np.uint32)
     order = idx[np.lexsort((idx, zb))]

@@ -41,10 +41,12 @@ typedef struct {
   float alpha_min;     // a splat value below this is skipped
   float alpha_max;     // opacity clamp
   float T_min;         // stop once transmittance falls below this
+  float guard;         // frustum guard band, as a fraction of the image size per side
   float bg[3];         // background colour
   int32_t mu_fp32;     // 1: value stage uses the binary32 splat centre of the discrete stage
   int32_t threads;     // worker threads for the pixel loop (>=1)
-  float amb_rel;       // relative margin that flags a per-pixel decision as ambiguous
+  float amb_rel_a;     // relative margin around alpha_min that flags a skip decision as ambiguous
+  float amb_rel_T;     // relative margin around T_min that flags a stop decision as ambiguous
 } or_settings;
 
 }  // extern "C"
@@ -163,7 +165,7 @@ struct Disc {
 };
 
 Disc discrete_stage(const float p[3], const float s[3], const float q[4], const or_camera& cam,
-                    float k, float lowpass) {
+                    float k, float lowpass, float guard) {
   Disc d;
   const float* W = cam.R;
   // camera-space mean, each row summed left to right
@@ -240,6 +242,9 @@ Disc discrete_stage(const float p[3], const float s[3], const float q[4], const 
   if (!(det > 0.f)) return d;
   const float mux = cam.fx * (tx / tz) + cam.cx;
   const float muy = cam.fy * (ty / tz) + cam.cy;
+  // view frustum: the centre must project inside the image widened by the guard band
+  const float gx = guard * float(cam.width), gy = guard * float(cam.height);
+  if (!(mux >= -gx && mux <= float(cam.width) + gx && muy >= -gy && muy <= float(cam.height) + gy)) return d;
   const float rx = k * std::sqrt(a);
   const float ry = k * std::sqrt(c);
   float fx0 = std::ceil(mux - rx), fx1 = std::floor(mux + rx);
@@ -435,7 +440,7 @@ void build(Ctx& c) {
         s[i] = float(c.scales[g * 3 + i]);
       }
       for (int i = 0; i < 4; ++i) q[i] = float(c.quats[g * 4 + i]);
-      Disc d = discrete_stage(p, s, q, c.cams[v], c.set.extent_k, c.set.lowpass);
+      Disc d = discrete_stage(p, s, q, c.cams[v], c.set.extent_k, c.set.lowpass, c.set.guard);
       c.disc[size_t(v) * N + g] = d;
       if (!d.vis) continue;
       const int tx0 = d.x0 / ts, tx1 = d.x1 / ts, ty0 = d.y0 / ts, ty1 = d.y1 / ts;
@@ -506,7 +511,7 @@ void composite(const Ctx& c, int64_t tile, double px, double py, double out[5], 
                int32_t& nused, bool& ambiguous, std::vector<Hit>* hits) {
   const uint32_t s = c.ranges[tile * 2], e = c.ranges[tile * 2 + 1];
   const double amin = c.set.alpha_min, amax = c.set.alpha_max, Tmin = c.set.T_min;
-  const double rel = c.set.amb_rel;
+  const double rel_a = c.set.amb_rel_a, rel_T = c.set.amb_rel_T;
   double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
   int32_t n = 0;
   nused = 0;
@@ -518,7 +523,7 @@ void composite(const Ctx& c, int64_t tile, double px, double py, double out[5], 
     const double power = -0.5 * (r.A * dx * dx + 2.0 * r.B * dx * dy + r.C * dy * dy);
     const double G = std::exp(power);
     const double a = r.opacity * G;
-    if (std::fabs(a - amin) <= rel * amin) ambiguous = true;
+    if (std::fabs(a - amin) <= rel_a * amin) ambiguous = true;
     if (a < amin) continue;
     const double alpha = a < amax ? a : amax;
     if (hits) hits->push_back(Hit{ri, G, a, alpha, T, dx, dy});
@@ -527,7 +532,7 @@ void composite(const Ctx& c, int64_t tile, double px, double py, double out[5], 
     T = T * (1.0 - alpha);
     n = int32_t(i - s + 1);
     ++nused;
-    if (std::fabs(T - Tmin) <= rel * Tmin) ambiguous = true;
+    if (std::fabs(T - Tmin) <= rel_T * Tmin) ambiguous = true;
     if (T < Tmin) break;
   }
   for (int ch = 0; ch < 3; ++ch) out[ch] = C[ch] + T * double(c.set.bg[ch]);
@@ -679,7 +684,7 @@ void or_backward(void* h, const double* g_color, const double* g_depth, const do
   // per-thread accumulators of the 2D gradients: dmu(2), dconic(3), dopacity, dcolor(3), ddepth
   std::vector<std::vector<double>> acc(nth, std::vector<double>(size_t(V) * N * 10, 0.0));
   std::vector<std::vector<uint8_t>> flag(nth, std::vector<uint8_t>(size_t(V) * N, 0));
-  const double amax = c.set.alpha_max, rel = c.set.amb_rel;
+  const double amax = c.set.alpha_max, rel = c.set.amb_rel_a;
   parallel_tiles(c, [&](int w, int64_t t0, int64_t t1) {
     std::vector<Hit> hits;
     std::vector<double>& G2 = acc[w];

@@ -1,0 +1,99 @@
+// Internal declarations shared by the host orchestration and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "gsr.h"
+
+namespace gsr {
+
+constexpr int kProjThreads = 256;  // Gaussians per block in the per-Gaussian kernels
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;  // keys per radix-sort block
+constexpr int kGrad2D = 12;  // floats per (view, Gaussian) 2D-gradient record (10 used)
+
+// One camera plus where its tiles and pixels live in the concatenated spaces.
+struct ViewDev {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy, znear;
+  float cam_pos[3];  // camera centre in world coordinates
+  int32_t W, H, tiles_x, tiles_y;
+  int32_t tile_off;  // first global tile id of this view
+  int32_t pad;
+  int64_t pix_off;   // first pixel of this view in the per-pixel state arrays
+  float* color;      // forward outputs
+  float* depth;
+  float* alpha;
+  const float* g_color;  // backward inputs (dL/d outputs)
+  const float* g_depth;
+  const float* g_alpha;
+  const float* t_color;  // loss targets
+  const float* t_depth;
+  float* lg_color;       // loss gradient outputs
+  float* lg_depth;
+};
+
+struct ViewTable {
+  ViewDev v[GSR_MAX_VIEWS];
+  int32_t nviews;
+  int32_t total_tiles;
+};
+
+struct Rules {
+  float k, lowpass, amin, amax, Tmin, guard;
+  float bg[3];
+};
+
+struct GaussDev {
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opac;
+  const float* sh;
+  int64_t n;
+};
+
+// Per-(view, Gaussian) splat records written by the projection kernel.
+struct Records {
+  float4* r0;       // (mu_x, mu_y, conic A, conic B)
+  float4* r1;       // (conic C, opacity, depth, unused)
+  float4* rgb;      // (r, g, b, unused)
+  uint2* rect;      // (tx0 | tx1 << 16, ty0 | ty1 << 16)
+  uint32_t* counts; // tiles touched, 0 when culled
+};
+
+struct GradOut {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opac;
+  float* sh;
+  int accumulate;
+};
+
+// ---- launchers (gsr_kernels.hip) --------------------------------------------------
+hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru, int tile,
+                          const Records& rec, uint32_t* blocksums, int nblk, hipStream_t s);
+hipError_t launch_scan_blocksums(uint32_t* blocksums, int count, unsigned long long* total, hipStream_t s);
+hipError_t launch_duplicate(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* blocksums,
+                            int nblk, uint64_t* keys, uint32_t* vals, uint64_t capacity, uint32_t* overflow,
+                            hipStream_t s);
+hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                             uint32_t* hist, uint32_t* digit_tot, int64_t M, int key_bits, bool* result_in_alt,
+                             int* passes, hipStream_t s);
+hipError_t launch_ranges(const uint64_t* keys, int64_t M, uint2* ranges, int total_tiles, hipStream_t s);
+hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
+                            const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
+                            hipStream_t s);
+hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* loss, hipStream_t s);
+hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
+                            const uint2* ranges, const uint32_t* vals, const float* T_final,
+                            const uint32_t* n_contrib, float* grad2d, hipStream_t s);
+hipError_t launch_project_bwd(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru,
+                              const Records& rec, const float* grad2d, const GradOut& out, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
+
+}  // namespace gsr

@@ -1,0 +1,1088 @@
+// gfx950 kernels of the differentiable tile-based Gaussian-splatting rasterizer.
+//
+//   K1 k_project        per Gaussian, loop over views: Eq. 2, 4, 5 (+ low-pass), conic of
+//                       the 2D splat (Eq. 3), SH colour, frustum cull, tile rectangle, tile count,
+//                       block sums of the counts
+//   K2 k_scan_blocksums exclusive scan of the block sums (one block)
+//   K3 k_duplicate      (tile id << 32 | depth bits, record id) pairs in duplication order
+//   K4 k_radix_*        stable LSD radix sort, 8-bit digits (histogram / row scan / scatter)
+//   K5 k_ranges         [start, end) of every tile in the sorted list
+//   K6 k_blend_fwd      per tile: front-to-back compositing, Eq. 11 with clamp/skip/stop
+//   K7 k_loss_l1        Eq. 12 (mean L1 colour) + weighted mean L1 depth, its gradient
+//   K8 k_blend_bwd      per tile, back to front: transmittance recovered by division,
+//                       per-(pixel, splat) partials reduced across the wavefront with DPP
+//                       and added with one set of float atomics per (wavefront, splat)
+//   K9 k_project_bwd    per Gaussian, loop over views: chain rule to means, scales,
+//                       rotations, opacities and SH coefficients
+//
+// Nothing here is a dense contraction, so no MFMA: the per-Gaussian kernels are HBM
+// bound, the blend kernels VALU/transcendental bound.
+#include "gsr_internal.h"
+
+namespace gsr {
+namespace {
+
+// ------------------------------------------------------------------------------------
+// wavefront / block helpers (wave64)
+// ------------------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK,
+                                                               0xF, false));
+}
+
+// Sum over the 64 lanes; the total lands in lane 63.  Needs every lane active.
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+  v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_move<0x140, 0xF>(v);  // row_mirror: every lane holds its 16-lane row sum
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint32_t tot = 0;
+  for (int i = 0; i < nw; ++i) tot += red[i];
+  __syncthreads();
+  return tot;
+}
+
+__device__ __forceinline__ uint32_t block_exclusive_scan_u32(uint32_t v, uint32_t* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t incl = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(incl, off);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) red[w] = incl;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int i = 0; i < w; ++i) pre += red[i];
+  return pre + incl - v;
+}
+
+// ------------------------------------------------------------------------------------
+// Discrete stage.  A fixed sequence of correctly rounded binary32 operations (no fused
+// multiply-add: the pragma turns contraction off, divide and square root are built
+// correctly rounded) so that culling, splat centre, depth bits and tile rectangle are
+// reproducible bit for bit.
+// ------------------------------------------------------------------------------------
+struct Proj {
+  float tx, ty, tz;
+  float qw, qx, qy, qz, nq;
+  float r[9];  // rotation of the normalised quaternion
+  float m[9];  // R diag(s)
+  float T[6];  // J W
+  float U[6];  // T M
+  float a, b, c;  // projected covariance + low-pass
+  float mux, muy;
+  int x0, x1, y0, y1;  // inclusive pixel rectangle
+  bool vis;
+};
+
+__device__ __forceinline__ void discrete_stage(const float p[3], const float s[3], const float q[4],
+                                               const ViewDev& cam, float k, float lowpass, float guard,
+                                               Proj& o) {
+#pragma clang fp contract(off)
+  const float* W = cam.R;
+  o.vis = false;
+  float tx = W[0] * p[0];
+  tx = tx + W[1] * p[1];
+  tx = tx + W[2] * p[2];
+  tx = tx + cam.t[0];
+  float ty = W[3] * p[0];
+  ty = ty + W[4] * p[1];
+  ty = ty + W[5] * p[2];
+  ty = ty + cam.t[1];
+  float tz = W[6] * p[0];
+  tz = tz + W[7] * p[1];
+  tz = tz + W[8] * p[2];
+  tz = tz + cam.t[2];
+  o.tx = tx;
+  o.ty = ty;
+  o.tz = tz;
+  if (!(tz > cam.znear)) return;
+  float nq = q[0] * q[0];
+  nq = nq + q[1] * q[1];
+  nq = nq + q[2] * q[2];
+  nq = nq + q[3] * q[3];
+  nq = __builtin_sqrtf(nq);
+  o.nq = nq;
+  if (!(nq > 0.f)) return;
+  const float w = q[0] / nq, x = q[1] / nq, y = q[2] / nq, z = q[3] / nq;
+  o.qw = w;
+  o.qx = x;
+  o.qy = y;
+  o.qz = z;
+  float* r = o.r;
+  r[0] = 1.f - 2.f * (y * y + z * z);
+  r[1] = 2.f * (x * y - w * z);
+  r[2] = 2.f * (x * z + w * y);
+  r[3] = 2.f * (x * y + w * z);
+  r[4] = 1.f - 2.f * (x * x + z * z);
+  r[5] = 2.f * (y * z - w * x);
+  r[6] = 2.f * (x * z - w * y);
+  r[7] = 2.f * (y * z + w * x);
+  r[8] = 1.f - 2.f * (x * x + y * y);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) o.m[i * 3 + j] = r[i * 3 + j] * s[j];
+  const float tz2 = tz * tz;
+  const float j00 = cam.fx / tz;
+  const float j11 = cam.fy / tz;
+  const float j02 = -(cam.fx * tx) / tz2;
+  const float j12 = -(cam.fy * ty) / tz2;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    o.T[c] = j00 * W[c] + j02 * W[6 + c];
+    o.T[3 + c] = j11 * W[3 + c] + j12 * W[6 + c];
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float acc = o.T[i * 3 + 0] * o.m[0 * 3 + c];
+      acc = acc + o.T[i * 3 + 1] * o.m[1 * 3 + c];
+      acc = acc + o.T[i * 3 + 2] * o.m[2 * 3 + c];
+      o.U[i * 3 + c] = acc;
+    }
+  const float* U = o.U;
+  float a = U[0] * U[0];
+  a = a + U[1] * U[1];
+  a = a + U[2] * U[2];
+  a = a + lowpass;
+  float b = U[0] * U[3];
+  b = b + U[1] * U[4];
+  b = b + U[2] * U[5];
+  float c = U[3] * U[3];
+  c = c + U[4] * U[4];
+  c = c + U[5] * U[5];
+  c = c + lowpass;
+  o.a = a;
+  o.b = b;
+  o.c = c;
+  const float det = a * c - b * b;
+  if (!(det > 0.f)) return;
+  const float mux = cam.fx * (tx / tz) + cam.cx;
+  const float muy = cam.fy * (ty / tz) + cam.cy;
+  o.mux = mux;
+  o.muy = muy;
+  // view frustum: the centre must project inside the image widened by the guard band
+  const float gx = guard * float(cam.W), gy = guard * float(cam.H);
+  if (!(mux >= -gx && mux <= float(cam.W) + gx && muy >= -gy && muy <= float(cam.H) + gy)) return;
+  const float rx = k * __builtin_sqrtf(a);
+  const float ry = k * __builtin_sqrtf(c);
+  float fx0 = __builtin_ceilf(mux - rx), fx1 = __builtin_floorf(mux + rx);
+  float fy0 = __builtin_ceilf(muy - ry), fy1 = __builtin_floorf(muy + ry);
+  const float wmax = float(cam.W - 1), hmax = float(cam.H - 1);
+  fx0 = (fx0 < 0.f) ? 0.f : fx0;
+  fy0 = (fy0 < 0.f) ? 0.f : fy0;
+  fx1 = (fx1 > wmax) ? wmax : fx1;
+  fy1 = (fy1 > hmax) ? hmax : fy1;
+  if (!(fx0 <= fx1 && fy0 <= fy1)) return;
+  o.x0 = int(fx0);
+  o.x1 = int(fx1);
+  o.y0 = int(fy0);
+  o.y1 = int(fy1);
+  o.vis = true;
+}
+
+// Conic (inverse projected covariance); shared by the forward and backward kernels so
+// both see identical bits.
+__device__ __forceinline__ void conic_of(float a, float b, float c, float& A, float& B, float& C) {
+#pragma clang fp contract(off)
+  const float det = a * c - b * b;
+  const float inv = 1.f / det;
+  A = c * inv;
+  B = -b * inv;
+  C = a * inv;
+}
+
+// Splat value a = o * exp(-q/2), q = A dx^2 + 2 B dx dy + C dy^2, as one fixed instruction
+// sequence: the forward skip decision and its recomputation in the backward agree bitwise.
+__device__ __forceinline__ float splat_alpha(float dx, float dy, float A, float B, float C, float o, float& G) {
+#pragma clang fp contract(off)
+  const float q = __builtin_fmaf(A * dx, dx, __builtin_fmaf(C * dy, dy, 2.f * (B * dx) * dy));
+  G = __expf(-0.5f * q);
+  return o * G;
+}
+
+// ------------------------------------------------------------------------------------
+// Real spherical harmonics, orthonormal with Condon-Shortley phase, as Cartesian
+// polynomials of the unit direction (x, y, z).  Constants are N_l^m (and sqrt 2 for
+// m != 0) times the Legendre factors:
+//   l=0: 1/(2 sqrt(pi))
+//   l=1: sqrt(3/(4 pi))                          -> -y, z, -x
+//   l=2: sqrt(15/(4 pi)) xy, -..yz, sqrt(5/(16 pi))(3z^2-1), -..xz, sqrt(15/(16 pi))(x^2-y^2)
+//   l=3: sqrt(35/(32 pi)), sqrt(105/(4 pi)), sqrt(21/(32 pi)), sqrt(7/(16 pi)), sqrt(105/(16 pi))
+// Gradients are those of these polynomials; the chain rule through the normalisation
+// of the direction removes their radial part.
+// ------------------------------------------------------------------------------------
+constexpr float kY00 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
+constexpr float kY1 = 0.4886025119029199f;     // sqrt(3/(4 pi))
+constexpr float kY2a = 1.0925484305920792f;    // sqrt(15/(4 pi))
+constexpr float kY2b = 0.31539156525252005f;   // sqrt(5/(16 pi))
+constexpr float kY2c = 0.5462742152960396f;    // sqrt(15/(16 pi))
+constexpr float kY3a = 0.5900435899266435f;    // sqrt(35/(32 pi))
+constexpr float kY3b = 2.890611442640554f;     // sqrt(105/(4 pi))
+constexpr float kY3c = 0.4570457994644658f;    // sqrt(21/(32 pi))
+constexpr float kY3d = 0.3731763325901154f;    // sqrt(7/(16 pi))
+constexpr float kY3e = 1.445305721320277f;     // sqrt(105/(16 pi))
+
+template <int DEG>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y) {
+  Y[0] = kY00;
+  if (DEG >= 1) {
+    Y[1] = -kY1 * y;
+    Y[2] = kY1 * z;
+    Y[3] = -kY1 * x;
+  }
+  if (DEG >= 2) {
+    Y[4] = kY2a * x * y;
+    Y[5] = -kY2a * y * z;
+    Y[6] = kY2b * (3.f * z * z - 1.f);
+    Y[7] = -kY2a * x * z;
+    Y[8] = kY2c * (x * x - y * y);
+  }
+  if (DEG >= 3) {
+    Y[9] = -kY3a * y * (3.f * x * x - y * y);
+    Y[10] = kY3b * x * y * z;
+    Y[11] = -kY3c * y * (5.f * z * z - 1.f);
+    Y[12] = kY3d * z * (5.f * z * z - 3.f);
+    Y[13] = -kY3c * x * (5.f * z * z - 1.f);
+    Y[14] = kY3e * z * (x * x - y * y);
+    Y[15] = -kY3a * x * (x * x - 3.f * y * y);
+  }
+}
+
+// d/d(x,y,z) of the basis polynomials, contracted with weights w[k]: out = sum_k w_k grad Y_k.
+template <int DEG>
+__device__ __forceinline__ void sh_grad_dot(float x, float y, float z, const float* w, float out[3]) {
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+  if (DEG >= 1) {
+    gy += -kY1 * w[1];
+    gz += kY1 * w[2];
+    gx += -kY1 * w[3];
+  }
+  if (DEG >= 2) {
+    gx += kY2a * y * w[4];
+    gy += kY2a * x * w[4];
+    gy += -kY2a * z * w[5];
+    gz += -kY2a * y * w[5];
+    gz += 6.f * kY2b * z * w[6];
+    gx += -kY2a * z * w[7];
+    gz += -kY2a * x * w[7];
+    gx += 2.f * kY2c * x * w[8];
+    gy += -2.f * kY2c * y * w[8];
+  }
+  if (DEG >= 3) {
+    gx += -6.f * kY3a * x * y * w[9];
+    gy += -kY3a * (3.f * x * x - 3.f * y * y) * w[9];
+    gx += kY3b * y * z * w[10];
+    gy += kY3b * x * z * w[10];
+    gz += kY3b * x * y * w[10];
+    gy += -kY3c * (5.f * z * z - 1.f) * w[11];
+    gz += -10.f * kY3c * y * z * w[11];
+    gz += kY3d * (15.f * z * z - 3.f) * w[12];
+    gx += -kY3c * (5.f * z * z - 1.f) * w[13];
+    gz += -10.f * kY3c * x * z * w[13];
+    gx += 2.f * kY3e * x * z * w[14];
+    gy += -2.f * kY3e * y * z * w[14];
+    gz += kY3e * (x * x - y * y) * w[14];
+    gx += -kY3a * (3.f * x * x - 3.f * y * y) * w[15];
+    gy += 6.f * kY3a * x * y * w[15];
+  }
+  out[0] = gx;
+  out[1] = gy;
+  out[2] = gz;
+}
+
+// ------------------------------------------------------------------------------------
+// K1: projection
+// ------------------------------------------------------------------------------------
+template <int DEG>
+__global__ __launch_bounds__(kProjThreads) void k_project(GaussDev g, ViewTable vt, Rules ru, int tile,
+                                                          Records rec, uint32_t* blocksums, int nblk) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  __shared__ uint32_t red[kProjThreads / 64];
+  const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
+  const bool valid = gi < g.n;
+  float p[3] = {0.f, 0.f, 0.f}, s[3] = {1.f, 1.f, 1.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, op = 0.f;
+  float sh[K * 3];
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      p[i] = g.means[gi * 3 + i];
+      s[i] = g.scales[gi * 3 + i];
+    }
+    const float4 q4 = reinterpret_cast<const float4*>(g.quats)[gi];
+    q[0] = q4.x;
+    q[1] = q4.y;
+    q[2] = q4.z;
+    q[3] = q4.w;
+    op = g.opac[gi];
+    const float* src = g.sh + gi * (K * 3);
+#pragma unroll
+    for (int i = 0; i < K * 3; ++i) sh[i] = src[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < K * 3; ++i) sh[i] = 0.f;
+  }
+  for (int v = 0; v < vt.nviews; ++v) {
+    const ViewDev& cam = vt.v[v];
+    uint32_t cnt = 0;
+    if (valid) {
+      Proj pr;
+      discrete_stage(p, s, q, cam, ru.k, ru.lowpass, ru.guard, pr);
+      const int64_t rid = int64_t(v) * g.n + gi;
+      if (pr.vis) {
+        const int tx0 = pr.x0 / tile, tx1 = pr.x1 / tile, ty0 = pr.y0 / tile, ty1 = pr.y1 / tile;
+        cnt = uint32_t((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+        float A, B, C;
+        conic_of(pr.a, pr.b, pr.c, A, B, C);
+        float d0 = p[0] - cam.cam_pos[0], d1 = p[1] - cam.cam_pos[1], d2 = p[2] - cam.cam_pos[2];
+        const float inv = 1.f / __builtin_sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+        float Y[K];
+        sh_basis<DEG>(d0 * inv, d1 * inv, d2 * inv, Y);
+        float col[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          float acc = 0.5f;
+#pragma unroll
+          for (int kk = 0; kk < K; ++kk) acc += sh[kk * 3 + ch] * Y[kk];
+          col[ch] = acc > 0.f ? acc : 0.f;
+        }
+        rec.r0[rid] = make_float4(pr.mux, pr.muy, A, B);
+        rec.r1[rid] = make_float4(C, op, pr.tz, 0.f);
+        rec.rgb[rid] = make_float4(col[0], col[1], col[2], 0.f);
+        rec.rect[rid] = make_uint2(uint32_t(tx0) | (uint32_t(tx1) << 16), uint32_t(ty0) | (uint32_t(ty1) << 16));
+      }
+      rec.counts[rid] = cnt;
+    }
+    const uint32_t bs = block_sum_u32(cnt, red);
+    if (threadIdx.x == 0) blocksums[int64_t(v) * nblk + blockIdx.x] = bs;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// K2: exclusive scan of the per-block tile counts (one block of 1024 threads)
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_scan_blocksums(uint32_t* a, int count, unsigned long long* total) {
+  __shared__ unsigned long long part[1024];
+  const int t = threadIdx.x;
+  const int per = (count + 1023) / 1024;
+  const int beg = min(count, t * per), end = min(count, beg + per);
+  unsigned long long sum = 0;
+  for (int i = beg; i < end; ++i) sum += a[i];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const unsigned long long add = t >= off ? part[t - off] : 0ull;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  unsigned long long run = t ? part[t - 1] : 0ull;
+  for (int i = beg; i < end; ++i) {
+    const uint32_t x = a[i];
+    a[i] = uint32_t(run);
+    run += x;
+  }
+  if (t == 1023) *total = part[1023];
+}
+
+// ------------------------------------------------------------------------------------
+// K3: duplication into (tile | depth) keys, in (view, Gaussian, tile row, column) order
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kProjThreads) void k_duplicate(ViewTable vt, int64_t n, Records rec,
+                                                            const uint32_t* blocksums, int nblk, uint64_t* keys,
+                                                            uint32_t* vals, uint64_t cap, uint32_t* overflow) {
+  __shared__ uint32_t red[kProjThreads / 64];
+  const int v = blockIdx.y;
+  const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
+  const int64_t rid = int64_t(v) * n + gi;
+  const uint32_t cnt = gi < n ? rec.counts[rid] : 0u;
+  const uint32_t excl = block_exclusive_scan_u32(cnt, red);
+  if (cnt == 0) return;
+  const uint64_t off = uint64_t(blocksums[int64_t(v) * nblk + blockIdx.x]) + excl;
+  if (off + cnt > cap) {
+    atomicOr(overflow, 1u);
+    return;
+  }
+  const uint2 rc = rec.rect[rid];
+  const uint64_t zb = __float_as_uint(rec.r1[rid].z);
+  const int tx0 = rc.x & 0xFFFF, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
+  const ViewDev& cam = vt.v[v];
+  uint64_t o = off;
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      const uint64_t tid = uint64_t(cam.tile_off + ty * cam.tiles_x + tx);
+      keys[o] = (tid << 32) | zb;
+      vals[o] = uint32_t(rid);
+      ++o;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// K4: stable LSD radix sort of (key, value), 8-bit digits.  Per pass:
+//   hist:    per-block digit histograms, stored digit-major [256][nblk]
+//   rowscan: one block per digit scans its row -> start of each block in that digit,
+//            and the digit total
+//   scatter: each block ranks its keys stably (wavefront multisplit by ballots, then
+//            across the four wavefronts through LDS) and writes them to their slots
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* keys, int64_t M, int shift,
+                                                             uint32_t* hist, int nblk) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * kSortTile;
+#pragma unroll 4
+  for (int i = 0; i < kSortItems; ++i) {
+    const int64_t idx = base + i * kSortThreads + threadIdx.x;
+    if (idx < M) atomicAdd(&h[uint32_t(keys[idx] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* hist, int nblk, uint32_t* digit_tot) {
+  __shared__ uint32_t red[kSortThreads / 64];
+  __shared__ uint32_t carry;
+  uint32_t* row = hist + int64_t(blockIdx.x) * nblk;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int start = 0; start < nblk; start += kSortThreads) {
+    const int i = start + threadIdx.x;
+    const uint32_t v = i < nblk ? row[i] : 0u;
+    const uint32_t ex = block_exclusive_scan_u32(v, red);
+    const uint32_t c = carry;
+    if (i < nblk) row[i] = c + ex;
+    __syncthreads();
+    if (threadIdx.x == kSortThreads - 1) carry = c + ex + v;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* kin, const uint32_t* vin,
+                                                                uint64_t* kout, uint32_t* vout, int64_t M,
+                                                                int shift, const uint32_t* hist,
+                                                                const uint32_t* digit_tot, int nblk) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[kSortThreads / 64][256];
+  __shared__ uint32_t red[kSortThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const uint32_t ex = block_exclusive_scan_u32(digit_tot[t], red);
+  base[t] = ex + hist[int64_t(t) * nblk + blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kSortThreads / 64; ++i) wcnt[i][t] = 0;
+  __syncthreads();
+  const int64_t b0 = int64_t(blockIdx.x) * kSortTile;
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t idx = b0 + r * kSortThreads + t;
+    const bool valid = idx < M;
+    uint64_t key = 0;
+    uint32_t val = 0, d = 0;
+    if (valid) {
+      key = kin[idx];
+      val = vin[idx];
+      d = uint32_t(key >> shift) & 255u;
+    }
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const uint64_t m = __ballot(on);
+      peers &= on ? m : ~m;
+    }
+    const uint32_t rank = __popcll(peers & lt_mask);
+    if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+    __syncthreads();
+    uint32_t run = 0;
+#pragma unroll
+    for (int i = 0; i < kSortThreads / 64; ++i) {
+      const uint32_t c = wcnt[i][t];
+      wcnt[i][t] = run;
+      run += c;
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t dst = base[d] + wcnt[w][d] + rank;
+      kout[dst] = key;
+      vout[dst] = val;
+    }
+    __syncthreads();
+    base[t] += run;
+#pragma unroll
+    for (int i = 0; i < kSortThreads / 64; ++i) wcnt[i][t] = 0;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// K5: tile ranges
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ranges(const uint64_t* keys, int64_t M, uint2* ranges) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= M) return;
+  const uint32_t tile = uint32_t(keys[i] >> 32);
+  if (i == 0) {
+    ranges[tile].x = 0;
+  } else {
+    const uint32_t prev = uint32_t(keys[i - 1] >> 32);
+    if (prev != tile) {
+      ranges[prev].y = uint32_t(i);
+      ranges[tile].x = uint32_t(i);
+    }
+  }
+  if (i == M - 1) ranges[tile].y = uint32_t(M);
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < count) p[i] = value;
+}
+
+__device__ __forceinline__ int view_of_tile(const ViewTable& vt, int tile) {
+  int v = 0;
+  for (int i = 1; i < vt.nviews; ++i)
+    if (tile >= vt.v[i].tile_off) v = i;
+  return v;
+}
+
+// ------------------------------------------------------------------------------------
+// K6: forward compositing.  One block per tile, one thread per pixel; the tile's sorted
+// list is staged through LDS BATCH records at a time; the block leaves once every
+// pixel has reached T < T_min.
+// ------------------------------------------------------------------------------------
+template <int TS, int BATCH>
+__global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Records rec, const uint2* ranges,
+                                                     const uint32_t* vals, float* T_final, uint32_t* n_contrib) {
+  constexpr int NT = TS * TS;
+  __shared__ float4 s_r0[BATCH];
+  __shared__ float4 s_r1[BATCH];
+  __shared__ float4 s_rgb[BATCH];
+  const int tile = blockIdx.x;
+  const ViewDev& cam = vt.v[view_of_tile(vt, tile)];
+  const int lt = tile - cam.tile_off;
+  const int ty = lt / cam.tiles_x, tx = lt - ty * cam.tiles_x;
+  const int px = tx * TS + int(threadIdx.x % TS), py = ty * TS + int(threadIdx.x / TS);
+  const bool inside = px < cam.W && py < cam.H;
+  const uint2 rg = ranges[tile];
+  const int n = int(rg.y - rg.x);
+  const float fpx = float(px), fpy = float(py);
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
+  uint32_t last = 0;
+  bool done = !inside;
+  for (int b0 = 0; b0 < n; b0 += BATCH) {
+    if (__syncthreads_count(!done) == 0) break;
+    for (int j = threadIdx.x; j < BATCH && b0 + j < n; j += NT) {
+      const uint32_t id = vals[rg.x + b0 + j];
+      s_r0[j] = rec.r0[id];
+      s_r1[j] = rec.r1[id];
+      s_rgb[j] = rec.rgb[id];
+    }
+    __syncthreads();
+    if (!done) {
+      const int cnt = min(BATCH, n - b0);
+      for (int j = 0; j < cnt; ++j) {
+        const float4 r0 = s_r0[j];
+        const float4 r1 = s_r1[j];
+        float G;
+        const float a = splat_alpha(fpx - r0.x, fpy - r0.y, r0.z, r0.w, r1.x, r1.y, G);
+        if (a < ru.amin) continue;
+        const float al = a < ru.amax ? a : ru.amax;
+        const float wgt = al * T;
+        const float4 c = s_rgb[j];
+        C0 += c.x * wgt;
+        C1 += c.y * wgt;
+        C2 += c.z * wgt;
+        D += r1.z * wgt;
+        T = T * (1.f - al);
+        last = uint32_t(b0 + j + 1);
+        if (T < ru.Tmin) {
+          done = true;
+          break;
+        }
+      }
+    }
+  }
+  if (inside) {
+    const int64_t P = int64_t(cam.W) * cam.H;
+    const int64_t pix = int64_t(py) * cam.W + px;
+    cam.color[pix] = C0 + T * ru.bg[0];
+    cam.color[P + pix] = C1 + T * ru.bg[1];
+    cam.color[2 * P + pix] = C2 + T * ru.bg[2];
+    if (cam.depth) cam.depth[pix] = D;
+    if (cam.alpha) cam.alpha[pix] = 1.f - T;
+    T_final[cam.pix_off + pix] = T;
+    n_contrib[cam.pix_off + pix] = last;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// K7: L1 loss and its gradient with respect to the rendered colour and depth
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_loss_l1(ViewTable vt, float depth_w, float* loss) {
+  __shared__ float red[4];
+  const ViewDev& cam = vt.v[blockIdx.y];
+  const int64_t P = int64_t(cam.W) * cam.H;
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  float part = 0.f;
+  if (i < P) {
+    const float inv3p = 1.f / float(3 * P), invp = 1.f / float(P);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const float d = cam.color[ch * P + i] - cam.t_color[ch * P + i];
+      part += fabsf(d) * inv3p;
+      cam.lg_color[ch * P + i] = (d > 0.f ? inv3p : (d < 0.f ? -inv3p : 0.f));
+    }
+    float gd = 0.f;
+    if (cam.t_depth) {
+      const float td = cam.t_depth[i];
+      if (td > 0.f) {
+        const float d = cam.depth[i] - td;
+        part += depth_w * fabsf(d) * invp;
+        gd = d > 0.f ? depth_w * invp : (d < 0.f ? -depth_w * invp : 0.f);
+      }
+    }
+    if (cam.lg_depth) cam.lg_depth[i] = gd;
+  }
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(loss, red[0] + red[1] + red[2] + red[3]);
+}
+
+__global__ void k_zero_f32(float* p) { *p = 0.f; }
+
+// ------------------------------------------------------------------------------------
+// K8: backward compositing.  Back to front over each pixel's contributors; the
+// transmittance before contributor i is T_{i+1} / (1 - alpha_i), starting from the saved
+// final value; the colour/depth behind i is carried as a running blend.
+// ------------------------------------------------------------------------------------
+template <int TS, int BATCH>
+__global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Records rec, const uint2* ranges,
+                                                     const uint32_t* vals, const float* T_final,
+                                                     const uint32_t* n_contrib, float* grad2d) {
+  constexpr int NT = TS * TS;
+  __shared__ float4 s_r0[BATCH];
+  __shared__ float4 s_r1[BATCH];
+  __shared__ float4 s_rgb[BATCH];
+  __shared__ uint32_t s_id[BATCH];
+  __shared__ uint32_t s_max;
+  const int tile = blockIdx.x;
+  const ViewDev& cam = vt.v[view_of_tile(vt, tile)];
+  const int lt = tile - cam.tile_off;
+  const int ty = lt / cam.tiles_x, tx = lt - ty * cam.tiles_x;
+  const int px = tx * TS + int(threadIdx.x % TS), py = ty * TS + int(threadIdx.x / TS);
+  const bool inside = px < cam.W && py < cam.H;
+  const uint2 rg = ranges[tile];
+  const int lane = threadIdx.x & 63;
+  const int64_t P = int64_t(cam.W) * cam.H;
+  const int64_t pix = int64_t(py) * cam.W + px;
+  float T = 1.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gA = 0.f;
+  uint32_t last = 0;
+  if (inside) {
+    T = T_final[cam.pix_off + pix];
+    last = n_contrib[cam.pix_off + pix];
+    if (cam.g_color) {
+      gC0 = cam.g_color[pix];
+      gC1 = cam.g_color[P + pix];
+      gC2 = cam.g_color[2 * P + pix];
+    }
+    if (cam.g_depth) gD = cam.g_depth[pix];
+    if (cam.g_alpha) gA = cam.g_alpha[pix];
+  }
+  if (threadIdx.x == 0) s_max = 0;
+  __syncthreads();
+  if (last) atomicMax(&s_max, last);
+  __syncthreads();
+  const int nmax = int(s_max);
+  const float Tfin = T;
+  const float fpx = float(px), fpy = float(py);
+  float BC0 = ru.bg[0], BC1 = ru.bg[1], BC2 = ru.bg[2], BD = 0.f;
+  for (int bend = nmax; bend > 0; bend -= BATCH) {
+    const int bstart = bend > BATCH ? bend - BATCH : 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < bend - bstart; j += NT) {
+      const uint32_t id = vals[rg.x + bstart + j];
+      s_id[j] = id;
+      s_r0[j] = rec.r0[id];
+      s_r1[j] = rec.r1[id];
+      s_rgb[j] = rec.rgb[id];
+    }
+    __syncthreads();
+    for (int j = bend - bstart - 1; j >= 0; --j) {
+      const int pos = bstart + j;
+      float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, g4 = 0.f, g5 = 0.f, g6 = 0.f, g7 = 0.f, g8 = 0.f, g9 = 0.f;
+      bool act = false;
+      if (pos < int(last)) {
+        const float4 r0 = s_r0[j];
+        const float4 r1 = s_r1[j];
+        const float dx = fpx - r0.x, dy = fpy - r0.y;
+        float G;
+        const float a = splat_alpha(dx, dy, r0.z, r0.w, r1.x, r1.y, G);
+        if (!(a < ru.amin)) {
+          act = true;
+          const float4 c = s_rgb[j];
+          const float al = a < ru.amax ? a : ru.amax;
+          const float om = 1.f - al;
+          T = T / om;
+          const float wgt = al * T;
+          g6 = gC0 * wgt;
+          g7 = gC1 * wgt;
+          g8 = gC2 * wgt;
+          g9 = gD * wgt;
+          const float dal =
+              T * (gC0 * (c.x - BC0) + gC1 * (c.y - BC1) + gC2 * (c.z - BC2) + gD * (r1.z - BD)) + gA * Tfin / om;
+          BC0 = al * c.x + om * BC0;
+          BC1 = al * c.y + om * BC1;
+          BC2 = al * c.z + om * BC2;
+          BD = al * r1.z + om * BD;
+          const float da = a <= ru.amax ? dal : 0.f;
+          g5 = da * G;
+          const float dpw = da * a;
+          g0 = dpw * (r0.z * dx + r0.w * dy);
+          g1 = dpw * (r0.w * dx + r1.x * dy);
+          g2 = -0.5f * dpw * dx * dx;
+          g3 = -dpw * dx * dy;
+          g4 = -0.5f * dpw * dy * dy;
+        }
+      }
+      if (__ballot(act) != 0ull) {
+        g0 = wave_sum_to_lane63(g0);
+        g1 = wave_sum_to_lane63(g1);
+        g2 = wave_sum_to_lane63(g2);
+        g3 = wave_sum_to_lane63(g3);
+        g4 = wave_sum_to_lane63(g4);
+        g5 = wave_sum_to_lane63(g5);
+        g6 = wave_sum_to_lane63(g6);
+        g7 = wave_sum_to_lane63(g7);
+        g8 = wave_sum_to_lane63(g8);
+        g9 = wave_sum_to_lane63(g9);
+        if (lane == 63) {
+          float* dst = grad2d + int64_t(s_id[j]) * kGrad2D;
+          unsafeAtomicAdd(dst + 0, g0);
+          unsafeAtomicAdd(dst + 1, g1);
+          unsafeAtomicAdd(dst + 2, g2);
+          unsafeAtomicAdd(dst + 3, g3);
+          unsafeAtomicAdd(dst + 4, g4);
+          unsafeAtomicAdd(dst + 5, g5);
+          unsafeAtomicAdd(dst + 6, g6);
+          unsafeAtomicAdd(dst + 7, g7);
+          unsafeAtomicAdd(dst + 8, g8);
+          unsafeAtomicAdd(dst + 9, g9);
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// K9: chain rule per Gaussian, summed over views in view order
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ void store_grad(float* p, float v, int acc) {
+  if (acc)
+    *p += v;
+  else
+    *p = v;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(kProjThreads) void k_project_bwd(GaussDev g, ViewTable vt, Rules ru, Records rec,
+                                                              const float* grad2d, GradOut out) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
+  if (gi >= g.n) return;
+  float p[3], s[3], q[4], sh[K * 3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    p[i] = g.means[gi * 3 + i];
+    s[i] = g.scales[gi * 3 + i];
+  }
+  const float4 q4 = reinterpret_cast<const float4*>(g.quats)[gi];
+  q[0] = q4.x;
+  q[1] = q4.y;
+  q[2] = q4.z;
+  q[3] = q4.w;
+  const float* src = g.sh + gi * (K * 3);
+#pragma unroll
+  for (int i = 0; i < K * 3; ++i) sh[i] = src[i];
+  float dp[3] = {0.f, 0.f, 0.f}, ds[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f}, dop = 0.f;
+  float dsh[K * 3];
+#pragma unroll
+  for (int i = 0; i < K * 3; ++i) dsh[i] = 0.f;
+  for (int v = 0; v < vt.nviews; ++v) {
+    const int64_t rid = int64_t(v) * g.n + gi;
+    if (rec.counts[rid] == 0) continue;
+    const ViewDev& cam = vt.v[v];
+    const float4* G4 = reinterpret_cast<const float4*>(grad2d + rid * kGrad2D);
+    const float4 ga = G4[0], gb = G4[1], gc = G4[2];
+    const float dmux = ga.x, dmuy = ga.y, dA = ga.z, dB = ga.w, dC = gb.x, dO = gb.y;
+    const float dcol[3] = {gb.z, gb.w, gc.x};
+    const float dz = gc.y;
+    Proj pr;
+    discrete_stage(p, s, q, cam, ru.k, ru.lowpass, ru.guard, pr);
+    float A, B, C;
+    conic_of(pr.a, pr.b, pr.c, A, B, C);
+    dop += dO;
+    // colour: c = max(0, 0.5 + sum_k sh_k Y_k(d)), d = (p - centre)/|p - centre|
+    const float d0 = p[0] - cam.cam_pos[0], d1 = p[1] - cam.cam_pos[1], d2 = p[2] - cam.cam_pos[2];
+    const float len = __builtin_sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+    const float il = 1.f / len;
+    const float vx = d0 * il, vy = d1 * il, vz = d2 * il;
+    float Y[K];
+    sh_basis<DEG>(vx, vy, vz, Y);
+    float dcm[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      float raw = 0.5f;
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk) raw += sh[kk * 3 + ch] * Y[kk];
+      dcm[ch] = raw > 0.f ? dcol[ch] : 0.f;
+    }
+    float wk[K];
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+      dsh[kk * 3 + 0] += Y[kk] * dcm[0];
+      dsh[kk * 3 + 1] += Y[kk] * dcm[1];
+      dsh[kk * 3 + 2] += Y[kk] * dcm[2];
+      wk[kk] = sh[kk * 3 + 0] * dcm[0] + sh[kk * 3 + 1] * dcm[1] + sh[kk * 3 + 2] * dcm[2];
+    }
+    if (DEG > 0) {
+      float dv[3];
+      sh_grad_dot<DEG>(vx, vy, vz, wk, dv);
+      const float vd = dv[0] * vx + dv[1] * vy + dv[2] * vz;
+      dp[0] += (dv[0] - vx * vd) * il;
+      dp[1] += (dv[1] - vy * vd) * il;
+      dp[2] += (dv[2] - vz * vd) * il;
+    }
+    // conic -> projected covariance: dS = -Q G_Q Q with G_Q = [[dA, dB/2], [dB/2, dC]]
+    const float hB = 0.5f * dB;
+    const float QG00 = A * dA + B * hB, QG01 = A * hB + B * dC;
+    const float QG10 = B * dA + C * hB, QG11 = B * hB + C * dC;
+    const float S00 = -(QG00 * A + QG01 * B);
+    const float S01 = -(QG00 * B + QG01 * C);
+    const float S11 = -(QG10 * B + QG11 * C);
+    // Sigma_hat = U U^T + lowpass I with U = T M: dU = 2 dS U
+    float dU[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      dU[k] = 2.f * (S00 * pr.U[k] + S01 * pr.U[3 + k]);
+      dU[3 + k] = 2.f * (S01 * pr.U[k] + S11 * pr.U[3 + k]);
+    }
+    // dT = dU M^T, dM = T^T dU
+    float dT[6], dM[9];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        dT[i * 3 + j] = dU[i * 3 + 0] * pr.m[j * 3 + 0] + dU[i * 3 + 1] * pr.m[j * 3 + 1] + dU[i * 3 + 2] * pr.m[j * 3 + 2];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) dM[j * 3 + k] = pr.T[j] * dU[k] + pr.T[3 + j] * dU[3 + k];
+    // T = J W: dJ = dT W^T (only the four non-constant entries of J matter)
+    const float* W = cam.R;
+    const float dJ00 = dT[0] * W[0] + dT[1] * W[1] + dT[2] * W[2];
+    const float dJ02 = dT[0] * W[6] + dT[1] * W[7] + dT[2] * W[8];
+    const float dJ11 = dT[3] * W[3] + dT[4] * W[4] + dT[5] * W[5];
+    const float dJ12 = dT[3] * W[6] + dT[4] * W[7] + dT[5] * W[8];
+    const float tx = pr.tx, ty = pr.ty, tz = pr.tz;
+    const float iz = 1.f / tz, iz2 = iz * iz, iz3 = iz2 * iz;
+    const float fx = cam.fx, fy = cam.fy;
+    const float dtx = -fx * iz2 * dJ02 + fx * iz * dmux;
+    const float dty = -fy * iz2 * dJ12 + fy * iz * dmuy;
+    const float dtz = -fx * iz2 * dJ00 + 2.f * fx * tx * iz3 * dJ02 - fy * iz2 * dJ11 + 2.f * fy * ty * iz3 * dJ12 -
+                      fx * tx * iz2 * dmux - fy * ty * iz2 * dmuy + dz;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dp[j] += W[j] * dtx + W[3 + j] * dty + W[6 + j] * dtz;
+    // M = R diag(s)
+    float dR[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        ds[j] += dM[i * 3 + j] * pr.r[i * 3 + j];
+        dR[i * 3 + j] = dM[i * 3 + j] * s[j];
+      }
+    // R(q^) partials contracted with dR
+    const float w = pr.qw, x = pr.qx, y = pr.qy, z = pr.qz;
+    const float dqw = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    const float dqx = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                             2.f * x * dR[8]);
+    const float dqy = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                             2.f * y * dR[8]);
+    const float dqz = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] + y * dR[5] +
+                             x * dR[6] + y * dR[7]);
+    const float qd = dqw * w + dqx * x + dqy * y + dqz * z;
+    const float inq = 1.f / pr.nq;
+    dq[0] += (dqw - w * qd) * inq;
+    dq[1] += (dqx - x * qd) * inq;
+    dq[2] += (dqy - y * qd) * inq;
+    dq[3] += (dqz - z * qd) * inq;
+  }
+  const int acc = out.accumulate;
+  if (out.means)
+    for (int i = 0; i < 3; ++i) store_grad(out.means + gi * 3 + i, dp[i], acc);
+  if (out.scales)
+    for (int i = 0; i < 3; ++i) store_grad(out.scales + gi * 3 + i, ds[i], acc);
+  if (out.quats)
+    for (int i = 0; i < 4; ++i) store_grad(out.quats + gi * 4 + i, dq[i], acc);
+  if (out.opac) store_grad(out.opac + gi, dop, acc);
+  if (out.sh)
+#pragma unroll
+    for (int i = 0; i < K * 3; ++i) store_grad(out.sh + gi * (K * 3) + i, dsh[i], acc);
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return unsigned((n + per - 1) / per); }
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------
+hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru, int tile,
+                          const Records& rec, uint32_t* blocksums, int nblk, hipStream_t s) {
+  if (nblk == 0) return hipSuccess;
+  dim3 grid(nblk), block(kProjThreads);
+  switch (deg) {
+    case 0: k_project<0><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk); break;
+    case 1: k_project<1><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk); break;
+    case 2: k_project<2><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk); break;
+    default: k_project<3><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_blocksums(uint32_t* blocksums, int count, unsigned long long* total, hipStream_t s) {
+  k_scan_blocksums<<<1, 1024, 0, s>>>(blocksums, count, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_duplicate(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* blocksums,
+                            int nblk, uint64_t* keys, uint32_t* vals, uint64_t capacity, uint32_t* overflow,
+                            hipStream_t s) {
+  if (nblk == 0) return hipSuccess;
+  k_duplicate<<<dim3(nblk, vt.nviews), kProjThreads, 0, s>>>(vt, n, rec, blocksums, nblk, keys, vals, capacity,
+                                                             overflow);
+  return hipGetLastError();
+}
+
+hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                             uint32_t* hist, uint32_t* digit_tot, int64_t M, int key_bits, bool* result_in_alt,
+                             int* passes, hipStream_t s) {
+  const int np = (key_bits + 7) / 8;
+  *passes = np;
+  *result_in_alt = false;
+  if (M <= 1) {
+    *passes = 0;
+    return hipSuccess;
+  }
+  const int nblk = int((M + kSortTile - 1) / kSortTile);
+  uint64_t* kin = keys;
+  uint32_t* vin = vals;
+  uint64_t* kout = keys_alt;
+  uint32_t* vout = vals_alt;
+  for (int p = 0; p < np; ++p) {
+    const int shift = 8 * p;
+    k_radix_hist<<<nblk, kSortThreads, 0, s>>>(kin, M, shift, hist, nblk);
+    k_radix_rowscan<<<256, kSortThreads, 0, s>>>(hist, nblk, digit_tot);
+    k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(kin, vin, kout, vout, M, shift, hist, digit_tot, nblk);
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+  *result_in_alt = (np % 2) == 1;
+  return hipGetLastError();
+}
+
+hipError_t launch_ranges(const uint64_t* keys, int64_t M, uint2* ranges, int total_tiles, hipStream_t s) {
+  if (total_tiles > 0)
+    k_fill_u32<<<blocks_for(int64_t(total_tiles) * 2, 256), 256, 0, s>>>(reinterpret_cast<uint32_t*>(ranges), 0u,
+                                                                          int64_t(total_tiles) * 2);
+  if (M > 0) k_ranges<<<blocks_for(M, 256), 256, 0, s>>>(keys, M, ranges);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {
+  if (count > 0) k_fill_u32<<<blocks_for(count, 256), 256, 0, s>>>(p, value, count);
+  return hipGetLastError();
+}
+
+template <int TS, int BATCH>
+static void blend_fwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
+                        const uint32_t* vals, float* T_final, uint32_t* n_contrib, hipStream_t s) {
+  k_blend_fwd<TS, BATCH><<<vt.total_tiles, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib);
+}
+
+hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
+                            const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
+                            hipStream_t s) {
+  if (vt.total_tiles == 0) return hipSuccess;
+  const bool b256 = batch == 256;
+  switch (tile) {
+    case 8: b256 ? blend_fwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, s)
+                 : blend_fwd_t<8, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, s); break;
+    case 32: b256 ? blend_fwd_t<32, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, s)
+                  : blend_fwd_t<32, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, s); break;
+    default: b256 ? blend_fwd_t<16, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, s)
+                  : blend_fwd_t<16, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, s); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* loss, hipStream_t s) {
+  k_zero_f32<<<1, 1, 0, s>>>(loss);
+  int64_t maxp = 0;
+  for (int v = 0; v < vt.nviews; ++v) maxp = std::max<int64_t>(maxp, int64_t(vt.v[v].W) * vt.v[v].H);
+  if (maxp > 0) k_loss_l1<<<dim3(blocks_for(maxp, 256), vt.nviews), 256, 0, s>>>(vt, depth_w, loss);
+  return hipGetLastError();
+}
+
+template <int TS, int BATCH>
+static void blend_bwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
+                        const uint32_t* vals, const float* T_final, const uint32_t* n_contrib, float* grad2d,
+                        hipStream_t s) {
+  k_blend_bwd<TS, BATCH><<<vt.total_tiles, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d);
+}
+
+hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
+                            const uint2* ranges, const uint32_t* vals, const float* T_final,
+                            const uint32_t* n_contrib, float* grad2d, hipStream_t s) {
+  if (vt.total_tiles == 0) return hipSuccess;
+  const bool b256 = batch == 256;
+  switch (tile) {
+    case 8: b256 ? blend_bwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, s)
+                 : blend_bwd_t<8, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, s); break;
+    case 32: b256 ? blend_bwd_t<32, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, s)
+                  : blend_bwd_t<32, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, s); break;
+    default: b256 ? blend_bwd_t<16, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, s)
+                  : blend_bwd_t<16, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, s); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru,
+                              const Records& rec, const float* grad2d, const GradOut& out, hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  dim3 grid(blocks_for(g.n, kProjThreads)), block(kProjThreads);
+  switch (deg) {
+    case 0: k_project_bwd<0><<<grid, block, 0, s>>>(g, vt, ru, rec, grad2d, out); break;
+    case 1: k_project_bwd<1><<<grid, block, 0, s>>>(g, vt, ru, rec, grad2d, out); break;
+    case 2: k_project_bwd<2><<<grid, block, 0, s>>>(g, vt, ru, rec, grad2d, out); break;
+    default: k_project_bwd<3><<<grid, block, 0, s>>>(g, vt, ru, rec, grad2d, out); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gsr

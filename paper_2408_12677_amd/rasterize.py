@@ -1,0 +1,282 @@
+"""PyTorch-facing API of libgsr: device memory and streams come from torch, every
+computation runs in the HIP library (argument marshalling only here).
+
+    images, saved = forward(means, scales, quats, opacities, sh, cameras)
+    loss, gC, gD  = loss_l1(saved, images, targets, depth_weight=0.1)
+    grads         = backward(saved, gC, gD)
+
+``GSRasterize`` wraps forward/backward as a ``torch.autograd.Function``; the backward
+recomputes per-pixel transmittance from the saved final value instead of storing
+per-(pixel, Gaussian) state.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+
+@dataclass
+class Settings:
+    """Rendering rules; defaults: 16 px tiles, 256-record LDS batches, extent 3.33 sigma,
+    low-pass 0.3 px^2, skip a < 1/255, clamp alpha at 0.99, stop at T < 1e-4, frustum
+    guard band 0.15 x the image size per side, black bg."""
+    tile: int = 16
+    batch: int = 256
+    extent_k: float = 3.33
+    lowpass: float = 0.3
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    guard: float = 0.15
+    bg: tuple = (0.0, 0.0, 0.0)
+
+    def c(self) -> N.Settings:
+        return N.Settings(self.tile, self.batch, self.extent_k, self.lowpass, self.alpha_min, self.alpha_max,
+                          self.T_min, self.guard, (ctypes.c_float * 3)(*self.bg), 0)
+
+
+@dataclass
+class Camera:
+    """OpenCV pinhole camera; R (3x3) and t (3,) map world to camera: x_c = R x_w + t."""
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    R: np.ndarray = field(default_factory=lambda: np.eye(3, dtype=np.float32))
+    t: np.ndarray = field(default_factory=lambda: np.zeros(3, np.float32))
+    znear: float = 0.01
+
+
+def _cams(cameras):
+    if not 1 <= len(cameras) <= N.MAX_VIEWS:
+        raise ValueError(f"need 1..{N.MAX_VIEWS} cameras")
+    arr = (N.Camera * len(cameras))()
+    for i, c in enumerate(cameras):
+        a = arr[i]
+        a.width, a.height = int(c.width), int(c.height)
+        a.fx, a.fy, a.cx, a.cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+        a.R[:] = [float(v) for v in np.asarray(c.R, np.float32).reshape(9)]
+        a.t[:] = [float(v) for v in np.asarray(c.t, np.float32).reshape(3)]
+        a.znear = float(getattr(c, "znear", 0.01))
+    return arr
+
+
+class Context:
+    """A gsr_ctx bound to one device and one HIP stream."""
+
+    def __init__(self, device: int, stream: int):
+        lib = N.load()
+        self.lib = lib
+        self.device = device
+        self.stream = stream
+        h = ctypes.c_void_p()
+        N.check(lib.gsr_ctx_create(device, ctypes.c_void_p(stream), ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and h.value:
+            self.lib.gsr_ctx_destroy(h)
+            self.h = None
+
+
+_contexts: dict = {}
+
+
+def context(device: torch.device | int | None = None) -> Context:
+    """The cached context of ``device`` bound to torch's current stream there."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    stream = torch.cuda.current_stream(idx).cuda_stream
+    key = (idx, stream)
+    ctx = _contexts.get(key)
+    if ctx is None:
+        ctx = _contexts[key] = Context(idx, stream)
+    return ctx
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, name, shape, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float32 or t.device != device or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 tensor on {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Saved:
+    """Owner of a gsr_saved handle plus references that keep its inputs alive."""
+
+    def __init__(self, ctx: Context, handle, keep, cameras, n, sh_degree):
+        self.ctx = ctx
+        self.h = handle
+        self.keep = keep
+        self.cameras = list(cameras)
+        self.n = n
+        self.sh_degree = sh_degree
+
+    def info(self) -> dict:
+        inf = N.Info()
+        N.check(self.ctx.lib.gsr_saved_info(self.h, ctypes.byref(inf)), self.ctx.h)
+        return {k: getattr(inf, k) for k, _ in N.Info._fields_}
+
+    def debug_export(self) -> dict:
+        inf = self.info()
+        M, T, P, R = inf["num_keys"], inf["num_tiles"], inf["num_pixels"], inf["num_records"]
+        out = dict(keys=np.zeros(M, np.uint64), values=np.zeros(M, np.uint32), ranges=np.zeros((T, 2), np.uint32),
+                   T_final=np.zeros(P, np.float32), n_contrib=np.zeros(P, np.uint32),
+                   tiles_touched=np.zeros(R, np.uint32), mu=np.zeros((R, 2), np.float32),
+                   depth=np.zeros(R, np.float32), conic=np.zeros((R, 3), np.float32),
+                   color=np.zeros((R, 3), np.float32), rect=np.zeros((R, 4), np.int32))
+        d = N.Debug(*(ctypes.c_void_p(out[k].ctypes.data) for k, _ in N.Debug._fields_))
+        N.check(self.ctx.lib.gsr_debug_export(self.ctx.h, self.h, ctypes.byref(d)), self.ctx.h)
+        return out
+
+    def free(self):
+        if self.h is not None and self.h.value:
+            self.ctx.lib.gsr_saved_free(self.h)
+        self.h = None
+        self.keep = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _sh_degree(sh):
+    K = sh.shape[1]
+    deg = int(round(math.sqrt(K))) - 1
+    if (deg + 1) ** 2 != K or not 0 <= deg <= 3:
+        raise ValueError("sh must have shape [N, (deg+1)^2, 3] with deg in 0..3")
+    return deg
+
+
+def forward(means, scales, quats, opacities, sh, cameras, settings: Settings | None = None, save: bool = True):
+    """Render every camera.  Returns ([(color[3,H,W], depth[H,W], alpha[H,W]) per view], Saved|None)."""
+    settings = settings or Settings()
+    dev = means.device
+    n = means.shape[0]
+    deg = _sh_degree(sh)
+    _need(means, "means", (n, 3), dev)
+    _need(scales, "scales", (n, 3), dev)
+    _need(quats, "quats", (n, 4), dev)
+    _need(opacities, "opacities", (n,), dev)
+    _need(sh, "sh", (n, (deg + 1) ** 2, 3), dev)
+    if n and quats.data_ptr() % 16:
+        raise ValueError("quats must be 16-byte aligned")
+    ctx = context(dev)
+    cams = _cams(cameras)
+    images = []
+    outs = (N.ViewOut * len(cameras))()
+    for i, c in enumerate(cameras):
+        H, W = int(c.height), int(c.width)
+        col = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+        dep = torch.empty((H, W), dtype=torch.float32, device=dev)
+        alp = torch.empty((H, W), dtype=torch.float32, device=dev)
+        images.append((col, dep, alp))
+        outs[i] = N.ViewOut(col.data_ptr(), dep.data_ptr(), alp.data_ptr())
+    g = N.Gaussians(n, deg, means.data_ptr(), scales.data_ptr(), quats.data_ptr(), opacities.data_ptr(),
+                    sh.data_ptr())
+    s = settings.c()
+    h = ctypes.c_void_p()
+    N.check(ctx.lib.gsr_forward(ctx.h, ctypes.byref(g), cams, len(cameras), ctypes.byref(s), outs,
+                                ctypes.byref(h) if save else None), ctx.h)
+    saved = Saved(ctx, h, (means, scales, quats, opacities, sh), cameras, n, deg) if save else None
+    return images, saved
+
+
+def loss_l1(saved: Saved, images, targets, depth_weight: float = 0.1):
+    """Eq. 12 as a mean L1 colour error plus depth_weight x mean L1 depth error over valid target
+    depths, summed over views.  Returns (loss[()], [dL/dcolor], [dL/ddepth])."""
+    ctx = saved.ctx
+    V = len(saved.cameras)
+    dev = images[0][0].device
+    outs = (N.ViewOut * V)()
+    tg = (N.Target * V)()
+    gcs, gds = [], []
+    gcp = (ctypes.c_void_p * V)()
+    gdp = (ctypes.c_void_p * V)()
+    for i, ((col, dep, alp), (tc, td)) in enumerate(zip(images, targets)):
+        _need(tc, "target color", col.shape, dev)
+        if td is not None:
+            _need(td, "target depth", dep.shape, dev)
+        outs[i] = N.ViewOut(col.data_ptr(), dep.data_ptr(), alp.data_ptr())
+        tg[i] = N.Target(tc.data_ptr(), None if td is None else td.data_ptr())
+        gc = torch.empty_like(col)
+        gd = torch.empty_like(dep)
+        gcs.append(gc)
+        gds.append(gd)
+        gcp[i] = gc.data_ptr()
+        gdp[i] = gd.data_ptr()
+    loss = torch.empty((), dtype=torch.float32, device=dev)
+    N.check(ctx.lib.gsr_loss_l1(ctx.h, saved.h, outs, tg, float(depth_weight), gcp, gdp,
+                                ctypes.c_void_p(loss.data_ptr())), ctx.h)
+    return loss, gcs, gds
+
+
+def backward(saved: Saved, g_color, g_depth=None, g_alpha=None, grads=None, accumulate: bool = False):
+    """dL/d(means, scales, quats, opacities, sh) for dL/d(outputs) given per view (None = 0)."""
+    ctx = saved.ctx
+    means, scales, quats, opacities, sh = saved.keep
+    V = len(saved.cameras)
+    gv = (N.ViewGrad * V)()
+    keep = []
+    for i in range(V):
+        def p(lst):
+            if lst is None or lst[i] is None:
+                return None
+            t = lst[i].contiguous().float()
+            keep.append(t)
+            return t.data_ptr()
+        gv[i] = N.ViewGrad(p(g_color), p(g_depth), p(g_alpha))
+    if grads is None:
+        grads = dict(means=torch.empty_like(means), scales=torch.empty_like(scales), quats=torch.empty_like(quats),
+                     opacities=torch.empty_like(opacities), sh=torch.empty_like(sh))
+        accumulate = False
+    go = N.GaussianGrads(*(None if grads.get(k) is None else grads[k].data_ptr()
+                           for k in ("means", "scales", "quats", "opacities", "sh")))
+    N.check(ctx.lib.gsr_backward(ctx.h, saved.h, gv, ctypes.byref(go), N.ACCUMULATE if accumulate else 0), ctx.h)
+    return grads
+
+
+class GSRasterize(torch.autograd.Function):
+    """Differentiable render of V views; outputs (color_0, depth_0, alpha_0, color_1, ...)."""
+
+    @staticmethod
+    def forward(ctx, means, scales, quats, opacities, sh, cameras, settings):
+        images, saved = forward(means, scales, quats, opacities, sh, cameras, settings, save=True)
+        ctx.saved_handle = saved
+        ctx.views = len(cameras)
+        return tuple(t for img in images for t in img)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        saved = ctx.saved_handle
+        V = ctx.views
+        gc = [grads[3 * i] for i in range(V)]
+        gd = [grads[3 * i + 1] for i in range(V)]
+        ga = [grads[3 * i + 2] for i in range(V)]
+        out = backward(saved, gc, gd, ga)
+        saved.free()
+        ctx.saved_handle = None
+        return out["means"], out["scales"], out["quats"], out["opacities"], out["sh"], None, None
+
+
+def render(means, scales, quats, opacities, sh, cameras, settings: Settings | None = None):
+    """Autograd-enabled render; returns [(color, depth, alpha)] per camera."""
+    flat = GSRasterize.apply(means, scales, quats, opacities, sh, list(cameras), settings or Settings())
+    return [tuple(flat[3 * i:3 * i + 3]) for i in range(len(cameras))]

@@ -362,35 +362,62 @@ def seed_from_view(cam: Camera, depth: np.ndarray, **qt):
     return pw, scale
 
 
+def _seed_view(args):
+    room, cam, qt = args
+    depth, _ = room.raycast(cam, with_color=False)
+    return seed_from_view(cam, depth, **qt)
+
+
+def _seed_views(room, cams, qt, workers):
+    """Ray-cast and quadtree-seed a batch of views (NumPy releases the GIL in the heavy parts)."""
+    jobs = [(room, c, qt) for c in cams]
+    if workers <= 1 or len(cams) == 1:
+        return [_seed_view(j) for j in jobs]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(_seed_view, jobs))
+
+
+def _workers():
+    import os
+    return max(1, min(8, (os.cpu_count() or 1)))
+
+
 def grow_room_map(room: Room, rng, n_target, width=640, height=480, voxel=0.01,
-                  max_views=100000, sh_degree=3, opacity=0.9):
+                  max_views=100000, sh_degree=3, opacity=0.9, batch=16, qt=None):
     """Seed Gaussians from successive random in-room views until ``n_target``.
 
-    A new Gaussian is dropped when its 1 cm voxel already holds one (a stand-in
-    for the voxel-weight neighbourhood check, which needs the TSDF map).
+    Cameras are drawn in batches of ``batch`` (the whole batch is drawn even when
+    the target is reached part-way, so results do not depend on the worker count).
+    A new Gaussian is dropped when its ``voxel`` cell already holds one (a stand-in
+    for the voxel-weight neighbourhood check, which needs the TSDF map); None keeps all.
     Rotation identity, isotropic scale, fixed opacity; SH ~ N(0, 0.1).
     Returns the map and the seeding cameras in order.
     """
+    qt = qt or {}
     pts, scl, cams = [], [], []
     seen = set()
     total = 0
-    for _ in range(max_views):
-        cam = room.random_camera(rng, width, height)
-        depth, _ = room.raycast(cam, with_color=False)
-        p, s = seed_from_view(cam, depth)
-        keys = np.floor(p / voxel).astype(np.int64)
-        kk = (keys[:, 0] * 1_000_003 + keys[:, 1]) * 1_000_033 + keys[:, 2]
-        keep = np.zeros(len(kk), bool)
-        for i, k in enumerate(kk.tolist()):
-            if k not in seen:
-                seen.add(k)
-                keep[i] = True
-        cams.append(cam)
-        pts.append(p[keep])
-        scl.append(s[keep])
-        total += int(keep.sum())
-        if total >= n_target:
-            break
+    workers = _workers()
+    while total < n_target and len(cams) < max_views:
+        batch_cams = [room.random_camera(rng, width, height) for _ in range(batch)]
+        for cam, (p, s) in zip(batch_cams, _seed_views(room, batch_cams, qt, workers)):
+            if total >= n_target:
+                break
+            if voxel is None:
+                keep = np.ones(len(p), bool)
+            else:
+                keys = np.floor(p / voxel).astype(np.int64)
+                kk = (keys[:, 0] * 1_000_003 + keys[:, 1]) * 1_000_033 + keys[:, 2]
+                keep = np.zeros(len(kk), bool)
+                for i, k in enumerate(kk.tolist()):
+                    if k not in seen:
+                        seen.add(k)
+                        keep[i] = True
+            cams.append(cam)
+            pts.append(p[keep])
+            scl.append(s[keep])
+            total += int(keep.sum())
     means = np.concatenate(pts, 0)[:n_target]
     scales = np.concatenate(scl, 0)[:n_target]
     n = means.shape[0]
@@ -497,29 +524,15 @@ def make_cfg4(seed=4, n=500_000):
 def make_cfg5(seed=5, n=3_000_000, n_maps=64, batch=16):
     """3M Gaussians from 64 quadtree-seeded 1752x1168 depth maps, 16-view batch.
 
-    The depth-variance quadtree alone yields far fewer than 3M leaves on 64
-    maps, so seeding cells are split down to 4x4 wherever the depth varies at
-    all (threshold 1e-6 m^2) and the maps are repeated with fresh poses until
-    the 3M target is met.
+    The depth-variance quadtree at 0.01 m^2 yields far fewer than 3M leaves on
+    64 maps, so seeding cells are split down to 4x4 wherever the depth varies at
+    all (threshold 1e-6 m^2), every leaf is kept, and views are added with fresh
+    poses until the 3M target is met.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     room = Room(rng, (10.0, 8.0, 3.0), 200)
-    pts, scl = [], []
-    total, views = 0, 0
-    while total < n:
-        cam = room.random_camera(rng, 1752, 1168)
-        depth, _ = room.raycast(cam, with_color=False)
-        p, s = seed_from_view(cam, depth, var_thresh=1e-6)
-        pts.append(p)
-        scl.append(s)
-        total += p.shape[0]
-        views += 1
-    means = np.concatenate(pts, 0)[:n]
-    scales = np.concatenate(scl, 0)[:n]
-    m = means.shape[0]
-    g = Gaussians(means.astype(np.float32), np.repeat(scales[:, None], 3, 1).astype(np.float32),
-                  np.tile(np.array([1, 0, 0, 0], np.float32), (m, 1)), np.full(m, 0.9, np.float32),
-                  (rng.standard_normal((m, 16, 3)) * 0.1).astype(np.float32), 3)
+    g, seeds = grow_room_map(room, rng, n, width=1752, height=1168, voxel=None, qt=dict(var_thresh=1e-6))
+    views = len(seeds)
     cams = [room.random_camera(rng, 1752, 1168) for _ in range(batch)]
     targets = [room.raycast(c, perturbed=True)[::-1] for c in cams]
     return Workload("cfg5", g, cams, targets,

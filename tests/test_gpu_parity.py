@@ -1,0 +1,287 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances and the ambiguity rule are stated in parity_util.  Every input is a
+seeded synthetic workload from ``scenes``.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from parity_util import (check_grads, check_images, check_keys, check_records, oracle_for, settings,  # noqa: E402
+                         to_dev)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_12677_amd import rasterize
+    return rasterize
+
+
+def run_fwd(R, g, cams, s, save=True):
+    params = to_dev(g)
+    images, saved = R.forward(*params, cams, s, save=save)
+    torch.cuda.synchronize()
+    return params, images, saved
+
+
+def fwd_bwd_parity(R, g, cams, s, targets=None, threads=8, check_key=True):
+    params, images, saved = run_fwd(R, g, cams, s)
+    dbg = saved.debug_export()
+    orc = oracle_for(g, cams, s, threads=threads)
+    if check_key:
+        check_keys(dbg, orc)
+        check_records(dbg, orc, s.tile)
+    outs = orc.forward()
+    rep = check_images(images, outs, dbg, cams)
+    # output gradients: the library's L1 loss (when targets are given) or seeded random
+    if targets is not None:
+        tg = [(torch.from_numpy(tc).cuda(), torch.from_numpy(td).cuda()) for tc, td in targets]
+        loss, gc, gd = R.loss_l1(saved, images, tg, 0.1)
+        ga = [None] * len(cams)
+    else:
+        rng = np.random.default_rng(7)
+        gc = [torch.from_numpy(rng.standard_normal((3, c.height, c.width)).astype(np.float32)).cuda() for c in cams]
+        gd = [torch.from_numpy(rng.standard_normal((c.height, c.width)).astype(np.float32)).cuda() for c in cams]
+        ga = [torch.from_numpy(rng.standard_normal((c.height, c.width)).astype(np.float32)).cuda() for c in cams]
+    grads = R.backward(saved, gc, gd, ga)
+    torch.cuda.synchronize()
+    np_ = lambda lst: None if lst[0] is None else [t.cpu().numpy().astype(np.float64) for t in lst]
+    ref = orc.backward(np_(gc), np_(gd), np_(ga))
+    grep = check_grads(grads, ref)
+    saved.free()
+    return rep, grep
+
+
+# ---------------------------------------------------------------------------------------
+# forward: keys, order, ranges bit-exact; images within 1e-4
+# ---------------------------------------------------------------------------------------
+
+def test_cfg1_forward_parity(R):
+    w = scenes.make_cfg1()
+    s = settings()
+    say("cfg1 forward", w.gaussians.n)
+    params, images, saved = run_fwd(R, w.gaussians, w.cameras, s)
+    dbg = saved.debug_export()
+    orc = oracle_for(w.gaussians, w.cameras, s)
+    check_keys(dbg, orc)
+    check_records(dbg, orc, s.tile)
+    rep = check_images(images, orc.forward(), dbg, w.cameras)
+    assert dbg["keys"].size > 1000
+    say("cfg1", rep, saved.info())
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_keys_bitexact_every_tile_size(R, tile):
+    w = scenes.make_cfg1()
+    s = settings(tile=tile)
+    say("keys tile", tile)
+    _, _, saved = run_fwd(R, w.gaussians, w.cameras, s)
+    dbg = saved.debug_export()
+    check_keys(dbg, oracle_for(w.gaussians, w.cameras, s))
+
+
+def test_forward_bitwise_invariant_across_autotune_points(R):
+    w = scenes.make_cfg1()
+    cams = w.cameras + [w.cameras[0].crop(5, 3, 77, 61)]
+    say("autotune invariance")
+    ref = None
+    for tile in (8, 16, 32):
+        for batch in (128, 256):
+            _, images, _ = run_fwd(R, w.gaussians, cams, settings(tile=tile, batch=batch), save=False)
+            cur = [t.cpu().numpy() for img in images for t in img]
+            if ref is None:
+                ref = cur
+            else:
+                for a, b in zip(ref, cur):
+                    np.testing.assert_array_equal(a, b)
+
+
+def test_forward_is_deterministic(R):
+    w = scenes.make_cfg1()
+    s = settings()
+    _, a, _ = run_fwd(R, w.gaussians, w.cameras, s, save=False)
+    _, b, _ = run_fwd(R, w.gaussians, w.cameras, s, save=False)
+    for x, y in zip(a[0], b[0]):
+        assert torch.equal(x, y)
+
+
+# ---------------------------------------------------------------------------------------
+# forward + backward
+# ---------------------------------------------------------------------------------------
+
+def test_cfg1_fwd_bwd_random_output_grads(R):
+    w = scenes.make_cfg1()
+    say("cfg1 fwd+bwd")
+    rep, grep = fwd_bwd_parity(R, w.gaussians, w.cameras, settings(bg=(0.1, 0.3, 0.2)))
+    say("cfg1 bwd", rep, grep)
+
+
+def test_multiview_uneven_ragged(R):
+    w = scenes.make_cfg1()
+    c = w.cameras[0]
+    R1, t1 = scenes.look_at([0.2, 0.1, -0.3], [0.0, 0.0, 3.0], up=(0, -1, 0))
+    cams = [c, scenes.Camera(100, 75, 90.0, 90.0, 50.3, 37.6, R1, t1), c.crop(13, 7, 37, 29)]
+    say("multiview ragged")
+    rep, grep = fwd_bwd_parity(R, w.gaussians, cams, settings())
+    say(rep, grep)
+
+
+@pytest.mark.parametrize("tile,batch", [(8, 128), (32, 256)])
+def test_multiview_other_launch_shapes(R, tile, batch):
+    w = scenes.make_cfg1()
+    c = w.cameras[0]
+    cams = [c, c.crop(20, 10, 50, 40)]
+    fwd_bwd_parity(R, w.gaussians, cams, settings(tile=tile, batch=batch))
+
+
+def test_cfg2_fwd_bwd_with_l1_loss(R):
+    w = scenes.make_cfg2()
+    say("cfg2", w.gaussians.n)
+    rep, grep = fwd_bwd_parity(R, w.gaussians, w.cameras, settings(), targets=w.targets)
+    say("cfg2", rep, grep)
+
+
+def test_cfg3_crop_fwd_bwd(R):
+    w = scenes.make_cfg3()
+    rng = np.random.default_rng(33)
+    cam = w.cameras[0]
+    x0, y0 = int(rng.integers(0, cam.width - 64)), int(rng.integers(0, cam.height - 64))
+    crop = cam.crop(x0, y0, 64, 64)
+    rec = oracle.Oracle(w.gaussians.arrays(), 3, [crop], oracle.Settings(threads=8)).records()
+    idx = np.nonzero(rec["visible"])[0]
+    pick = np.sort(rng.choice(idx, size=min(2000, idx.size), replace=False))
+    g = w.gaussians.subset(pick)
+    say("cfg3 crop", x0, y0, g.n)
+    rep, grep = fwd_bwd_parity(R, g, [crop], settings())
+    say("cfg3", rep, grep)
+
+
+def test_loss_kernel_matches_oracle(R):
+    w = scenes.make_cfg1()
+    s = settings()
+    params, images, saved = run_fwd(R, w.gaussians, w.cameras, s)
+    rng = np.random.default_rng(4)
+    tc = rng.random((3, 96, 128)).astype(np.float32)
+    td = (rng.random((96, 128)) * 5).astype(np.float32)
+    td[:10] = 0.0
+    loss, gc, gd = R.loss_l1(saved, images, [(torch.from_numpy(tc).cuda(), torch.from_numpy(td).cuda())], 0.1)
+    col, dep, _ = images[0]
+    L, gC, gD = oracle.l1_loss(col.cpu().numpy(), dep.cpu().numpy(), tc, td, 0.1)
+    assert float(loss) == pytest.approx(L, rel=1e-5)
+    np.testing.assert_allclose(gc[0].cpu().numpy(), gC, rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(gd[0].cpu().numpy(), gD, rtol=1e-6, atol=1e-12)
+
+
+def test_autograd_function_matches_direct_backward(R):
+    w = scenes.make_cfg1()
+    s = settings()
+    params = [p.clone().requires_grad_(True) for p in to_dev(w.gaussians)]
+    out = R.render(*params, w.cameras, s)
+    col, dep, alp = out[0]
+    loss = col.square().mean() + 0.3 * dep.mean() + 0.2 * alp.sum()
+    loss.backward()
+    P = col.shape[1] * col.shape[2]
+    gc = [2 * col.detach() / (3 * P)]
+    gd = [torch.full_like(dep, 0.3 / P)]
+    ga = [torch.full_like(alp, 0.2)]
+    _, _, saved = run_fwd(R, w.gaussians, w.cameras, s)
+    direct = R.backward(saved, gc, gd, ga)
+    for name, p in zip(("means", "scales", "quats", "opacities", "sh"), params):
+        a, b = p.grad.cpu().numpy(), direct[name].cpu().numpy()
+        assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(b) + 1e-12, name
+
+
+def test_backward_accumulate_flag(R):
+    w = scenes.make_cfg1()
+    _, images, saved = run_fwd(R, w.gaussians, w.cameras, settings())
+    gc = [torch.ones_like(images[0][0])]
+    a = R.backward(saved, gc)
+    b = {k: v.clone() for k, v in a.items()}
+    R.backward(saved, gc, grads=b, accumulate=True)
+    for k in a:
+        np.testing.assert_allclose(b[k].cpu().numpy(), 2 * a[k].cpu().numpy(), rtol=1e-4, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------------------
+
+def _one(R, g, cams, s):
+    params, images, saved = run_fwd(R, g, cams, s)
+    return params, images, saved
+
+
+def test_empty_map(R):
+    g = scenes.random_gaussians(np.random.default_rng(0), np.zeros((0, 3)), 0)
+    cam = scenes.Camera(40, 30, 30.0, 30.0, 20.0, 15.0, np.eye(3, dtype=np.float32), np.zeros(3, np.float32))
+    s = settings(bg=(0.25, 0.5, 0.75))
+    _, images, saved = _one(R, g, [cam], s)
+    col, dep, alp = (t.cpu().numpy() for t in images[0])
+    assert np.all(col[0] == 0.25) and np.all(col[2] == 0.75) and np.all(dep == 0) and np.all(alp == 0)
+    assert saved.info()["num_keys"] == 0
+    grads = R.backward(saved, [torch.ones(3, 30, 40, device="cuda")])
+    assert grads["means"].numel() == 0
+
+
+def test_everything_culled(R):
+    rng = np.random.default_rng(1)
+    g = scenes.random_gaussians(rng, np.stack([rng.uniform(-1, 1, 50), rng.uniform(-1, 1, 50), -rng.uniform(1, 3, 50)], 1), 3)
+    cam = scenes.Camera(33, 17, 30.0, 30.0, 16.0, 8.0, np.eye(3, dtype=np.float32), np.zeros(3, np.float32))
+    _, images, saved = _one(R, g, [cam], settings())
+    assert saved.info()["num_keys"] == 0
+    assert float(images[0][2].abs().max()) == 0.0
+    grads = R.backward(saved, [torch.ones(3, 17, 33, device="cuda")], [torch.ones(17, 33, device="cuda")])
+    for k, v in grads.items():
+        assert float(v.abs().max()) == 0.0, k
+
+
+def test_single_pixel_and_huge_splat(R):
+    # one Gaussian much larger than the image plus a tiny camera, with opacity above the clamp
+    means = np.array([[0.0, 0.0, 2.0], [0.01, 0.0, 3.0]])
+    g = scenes.random_gaussians(np.random.default_rng(2), means, 1)
+    g.scales[:] = np.array([[2.0, 1.5, 1.0], [0.01, 0.01, 0.01]], np.float32)
+    g.opacities[:] = np.array([0.999, 0.5], np.float32)
+    for W, H in ((1, 1), (17, 9), (64, 48)):
+        cam = scenes.Camera(W, H, 40.0, 40.0, W / 2, H / 2, np.eye(3, dtype=np.float32), np.zeros(3, np.float32))
+        fwd_bwd_parity(R, g, [cam], settings())
+
+
+def test_invalid_arguments_raise(R):
+    w = scenes.make_cfg1()
+    params = to_dev(w.gaussians)
+    with pytest.raises(ValueError):
+        R.forward(params[0].double(), *params[1:], w.cameras)
+    from paper_2408_12677_amd._native import GsrError
+    with pytest.raises(GsrError):
+        R.forward(*params, w.cameras, settings(tile=12))
+    bad = scenes.Camera(0, 10, 1.0, 1.0, 0.0, 0.0, np.eye(3, dtype=np.float32), np.zeros(3, np.float32))
+    with pytest.raises(GsrError):
+        R.forward(*params, [bad])
+
+
+# ---------------------------------------------------------------------------------------
+# full size: the headline 640x480 view of the 500k-Gaussian map, in the bench launch shape
+# ---------------------------------------------------------------------------------------
+
+def test_headline_view_full_size(R):
+    w = scenes.make_cfg4()
+    v = scenes.HEADLINE_VIEW
+    cam = w.cameras[v]
+    say("headline", w.gaussians.n, cam.width, cam.height)
+    rep, grep = fwd_bwd_parity(R, w.gaussians, [cam], settings(), targets=[w.targets[v]], threads=8)
+    say("headline", rep, grep)

@@ -128,6 +128,18 @@ def test_projection_isotropic_ignores_rotation():
     assert np.abs(g["means"]).max() > 1e-3
 
 
+def test_view_frustum_cull_with_guard_band():
+    # only Gaussians lying in the view frustum are rendered (Sec. III-B-3): the centre must
+    # project inside the image widened by guard x (W, H) per side, in front of znear
+    W, H, f, z = 64, 48, 50.0, 2.0
+    xs = [(W * 1.10 - W / 2) / f * z, (W * 1.20 - W / 2) / f * z, 0.0, 0.0]
+    p = gaussians([[xs[0], 0, z], [xs[1], 0, z], [0, 0, 0.005], [0, 0, -1.0]], [[0.3, 0.3, 0.3]] * 4)
+    r = oracle.Oracle(p, 0, [cam(W, H, f)], oracle.Settings(guard=0.15)).records()
+    assert r["visible"].tolist() == [True, False, False, False]
+    r = oracle.Oracle(p, 0, [cam(W, H, f)], oracle.Settings(guard=0.25)).records()
+    assert r["visible"].tolist() == [True, True, False, False]
+
+
 # ---------------------------------------------------------------------------------------
 # compositing closed forms (Eq. 3, 11)
 # ---------------------------------------------------------------------------------------
@@ -312,7 +324,7 @@ def test_literal_eq11_without_rules():
 # discrete stage: an independent float32 transcription of the documented op sequence
 # ---------------------------------------------------------------------------------------
 
-def discrete_stage_f32(p, s, q, c, k=3.33, lowpass=0.3, full=False):
+def discrete_stage_f32(p, s, q, c, k=3.33, lowpass=0.3, full=False, guard=0.15):
     f = np.float32
     p, s, q = (np.asarray(a, np.float32) for a in (p, s, q))
     W = np.asarray(c.R, np.float32).reshape(9)
@@ -340,6 +352,8 @@ def discrete_stage_f32(p, s, q, c, k=3.33, lowpass=0.3, full=False):
     det = a * cc_ - b * b
     mux = fx * (tx / tz) + f(c.cx)
     muy = fy * (ty / tz) + f(c.cy)
+    gx, gy = f(guard) * f(c.width), f(guard) * f(c.height)
+    infrustum = (mux >= -gx) & (mux <= f(c.width) + gx) & (muy >= -gy) & (muy <= f(c.height) + gy)
     kk = f(k)
     rx, ry = kk * np.sqrt(a), kk * np.sqrt(cc_)
     x0, x1 = np.ceil(mux - rx), np.floor(mux + rx)
@@ -348,7 +362,7 @@ def discrete_stage_f32(p, s, q, c, k=3.33, lowpass=0.3, full=False):
     y0 = np.where(y0 < 0, f(0), y0)
     x1 = np.where(x1 > f(c.width - 1), f(c.width - 1), x1)
     y1 = np.where(y1 > f(c.height - 1), f(c.height - 1), y1)
-    vis = (tz > f(c.znear)) & (nq > 0) & (det > 0) & (x0 <= x1) & (y0 <= y1)
+    vis = (tz > f(c.znear)) & (nq > 0) & (det > 0) & infrustum & (x0 <= x1) & (y0 <= y1)
     if full:
         return vis, tz, np.stack([mux, muy], 1), np.stack([x0, x1, y0, y1], 1), a
     return vis, tz, np.stack([mux, muy], 1), np.stack([x0, x1, y0, y1], 1)
