@@ -140,6 +140,15 @@ typedef struct {
   int32_t sort_passes;   /* 8-bit radix passes run */
 } gsr_info;
 
+/* Per-kernel device time accumulated by the optional event timer (see
+ * gsr_ctx_set_timing); entry i belongs to the kernel gsr_kernel_name(i). */
+#define GSR_MAX_KERNELS 16
+typedef struct {
+  double ms[GSR_MAX_KERNELS];         /* summed launch durations, milliseconds */
+  int64_t launches[GSR_MAX_KERNELS];  /* launches timed */
+  int32_t count;                      /* kernels in use */
+} gsr_timing;
+
 /* Host copies of the intermediate state, for tests.  Each pointer may be NULL;
  * sizes follow gsr_info. */
 typedef struct {
@@ -168,6 +177,17 @@ gsr_status gsr_settings_default(gsr_settings* s);
 gsr_status gsr_ctx_create(int32_t device, void* hip_stream, gsr_ctx** out);
 gsr_status gsr_ctx_destroy(gsr_ctx* ctx);
 gsr_status gsr_ctx_set_stream(gsr_ctx* ctx, void* hip_stream);
+
+/* Turn the per-kernel HIP-event timer on or off.  When on, every kernel launch is
+ * bracketed by two events on the context's stream (a few microseconds of overhead). */
+gsr_status gsr_ctx_set_timing(gsr_ctx* ctx, int32_t enable);
+
+/* Synchronise the stream and report the time accumulated per kernel since the last
+ * reset; reset != 0 starts a new accumulation. */
+gsr_status gsr_ctx_get_timing(gsr_ctx* ctx, gsr_timing* out, int32_t reset);
+
+/* Name of timer entry `id` ("" when out of range). */
+const char* gsr_kernel_name(int32_t id);
 
 /* Forward render (Eq. 2-5 and 11) of V views of one Gaussian map.
  * cams[V] are host structs, outs[V] device images.  With saved != NULL the state

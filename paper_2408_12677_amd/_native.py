@@ -60,6 +60,10 @@ class Info(ctypes.Structure):
                 ("num_records", ctypes.c_int64), ("views", ctypes.c_int32), ("sort_passes", ctypes.c_int32)]
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 16), ("launches", ctypes.c_int64 * 16), ("count", ctypes.c_int32)]
+
+
 class Debug(ctypes.Structure):
     _fields_ = [("keys", P), ("values", P), ("ranges", P), ("T_final", P), ("n_contrib", P),
                 ("tiles_touched", P), ("mu", P), ("depth", P), ("conic", P), ("color", P), ("rect", P)]
@@ -72,6 +76,9 @@ SIGNATURES = {
     "gsr_ctx_create": (ctypes.c_int, [ctypes.c_int32, P, P]),
     "gsr_ctx_destroy": (ctypes.c_int, [P]),
     "gsr_ctx_set_stream": (ctypes.c_int, [P, P]),
+    "gsr_ctx_set_timing": (ctypes.c_int, [P, ctypes.c_int32]),
+    "gsr_ctx_get_timing": (ctypes.c_int, [P, P, ctypes.c_int32]),
+    "gsr_kernel_name": (ctypes.c_char_p, [ctypes.c_int32]),
     "gsr_forward": (ctypes.c_int, [P, P, P, ctypes.c_int32, P, P, P]),
     "gsr_loss_l1": (ctypes.c_int, [P, P, P, P, ctypes.c_float, P, P, P]),
     "gsr_backward": (ctypes.c_int, [P, P, P, P, ctypes.c_uint32]),

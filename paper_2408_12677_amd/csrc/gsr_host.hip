@@ -19,7 +19,24 @@ struct gsr_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   unsigned long long* h_total = nullptr;  // pinned read-back slot
+  Timer timer;
 };
+
+namespace {
+const char* const kKernelNames[K_COUNT] = {"project",       "scan_blocksums", "duplicate", "radix_hist",
+                                           "radix_rowscan", "radix_scatter",  "ranges",    "fill",
+                                           "blend_fwd",     "loss_l1",        "blend_bwd", "project_bwd"};
+
+// Wraps one launch (or launch sequence) in the context's optional event timer.
+template <class F>
+hipError_t timed(gsr_ctx* ctx, int k, F&& f) {
+  ctx->timer.stream = ctx->stream;
+  ctx->timer.begin(k);
+  hipError_t e = f();
+  ctx->timer.end(k);
+  return e;
+}
+}  // namespace
 
 struct gsr_saved {
   gsr_ctx* ctx = nullptr;
@@ -188,10 +205,34 @@ gsr_status gsr_ctx_create(int32_t device, void* hip_stream, gsr_ctx** out) {
 gsr_status gsr_ctx_destroy(gsr_ctx* ctx) {
   if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
   (void)hipStreamSynchronize(ctx->stream);
+  ctx->timer.destroy();
   if (ctx->h_total) (void)hipHostFree(ctx->h_total);
   delete ctx;
   return GSR_OK;
 }
+
+gsr_status gsr_ctx_set_timing(gsr_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
+  ctx->timer.on = enable != 0;
+  ctx->timer.stream = ctx->stream;
+  return GSR_OK;
+}
+
+gsr_status gsr_ctx_get_timing(gsr_ctx* ctx, gsr_timing* out, int32_t reset) {
+  if (!ctx || !out) return fail(ctx, GSR_EINVAL, "NULL argument to gsr_ctx_get_timing");
+  GSR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->timer.collect();
+  std::memset(out, 0, sizeof(*out));
+  out->count = K_COUNT;
+  for (int i = 0; i < K_COUNT; ++i) {
+    out->ms[i] = ctx->timer.ms[i];
+    out->launches[i] = ctx->timer.launches[i];
+  }
+  if (reset) ctx->timer.reset();
+  return GSR_OK;
+}
+
+const char* gsr_kernel_name(int32_t id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : ""; }
 
 gsr_status gsr_ctx_set_stream(gsr_ctx* ctx, void* hip_stream) {
   if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
@@ -288,8 +329,10 @@ gsr_status gsr_forward(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* c
 
   int64_t M = 0;
   if (g->n > 0) {
-    TRYH(launch_project(sv->deg, sv->g, vt, sv->ru, s->tile, sv->rec, sv->blocksums, sv->nblk, st_));
-    TRYH(launch_scan_blocksums(sv->blocksums, V * sv->nblk, sv->d_total, st_));
+    TRYH(timed(ctx, K_PROJECT, [&] {
+      return launch_project(sv->deg, sv->g, vt, sv->ru, s->tile, sv->rec, sv->blocksums, sv->nblk, st_);
+    }));
+    TRYH(timed(ctx, K_SCAN, [&] { return launch_scan_blocksums(sv->blocksums, V * sv->nblk, sv->d_total, st_); }));
     TRYH(hipMemcpyAsync(ctx->h_total, sv->d_total, sizeof(unsigned long long), hipMemcpyDeviceToHost, st_));
     TRYH(hipStreamSynchronize(st_));
     M = int64_t(*ctx->h_total);
@@ -323,12 +366,17 @@ gsr_status gsr_forward(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* c
     hist = static_cast<uint32_t*>(th);
     dtot = static_cast<uint32_t*>(td);
     ovf = static_cast<uint32_t*>(to);
-    hipError_t e = launch_fill_u32(ovf, 0u, 1, st_);
+    hipError_t e = timed(ctx, K_FILL, [&] { return launch_fill_u32(ovf, 0u, 1, st_); });
     if (e == hipSuccess)
-      e = launch_duplicate(vt, g->n, sv->rec, sv->blocksums, sv->nblk, k0, v0, uint64_t(M), ovf, st_);
+      e = timed(ctx, K_DUPLICATE, [&] {
+        return launch_duplicate(vt, g->n, sv->rec, sv->blocksums, sv->nblk, k0, v0, uint64_t(M), ovf, st_);
+      });
     bool in_alt = false;
     const int key_bits = 32 + bits_for(uint64_t(tiles > 0 ? tiles - 1 : 0));
-    if (e == hipSuccess) e = launch_radix_sort(k0, v0, k1, v1, hist, dtot, M, key_bits, &in_alt, &sv->sort_passes, st_);
+    ctx->timer.stream = st_;
+    if (e == hipSuccess)
+      e = launch_radix_sort(k0, v0, k1, v1, hist, dtot, M, key_bits, &in_alt, &sv->sort_passes, st_,
+                            ctx->timer.on ? &ctx->timer : nullptr);
     if (e != hipSuccess) {
       free_tmp();
       release(sv);
@@ -346,9 +394,11 @@ gsr_status gsr_forward(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* c
     sv->vals = v0;
     free_tmp();
   }
-  TRYH(launch_ranges(sv->keys, M, sv->ranges, vt.total_tiles, st_));
-  TRYH(launch_blend_fwd(s->tile, s->batch, vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final, sv->n_contrib,
-                        st_));
+  TRYH(timed(ctx, K_RANGES, [&] { return launch_ranges(sv->keys, M, sv->ranges, vt.total_tiles, st_); }));
+  TRYH(timed(ctx, K_BLEND_FWD, [&] {
+    return launch_blend_fwd(s->tile, s->batch, vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final,
+                            sv->n_contrib, st_);
+  }));
 #undef TRY
 #undef TRYH
   if (saved)
@@ -378,7 +428,7 @@ gsr_status gsr_loss_l1(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_out*
     vt.v[v].lg_color = grad_color_out[v];
     vt.v[v].lg_depth = grad_depth_out ? grad_depth_out[v] : nullptr;
   }
-  GSR_HIP(ctx, launch_loss_l1(vt, depth_weight, loss_dev, ctx->stream));
+  GSR_HIP(ctx, timed(ctx, K_LOSS, [&] { return launch_loss_l1(vt, depth_weight, loss_dev, ctx->stream); }));
   return GSR_OK;
 }
 
@@ -399,12 +449,17 @@ gsr_status gsr_backward(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_gra
   if (st != GSR_OK) return st;
   float* grad2d = static_cast<float*>(g2);
   hipStream_t s = ctx->stream;
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, VN * kGrad2D, s);
+  hipError_t e =
+      timed(ctx, K_FILL, [&] { return launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, VN * kGrad2D, s); });
   if (e == hipSuccess)
-    e = launch_blend_bwd(saved->s.tile, saved->s.batch, vt, saved->ru, saved->rec, saved->ranges, saved->vals,
-                         saved->T_final, saved->n_contrib, grad2d, s);
+    e = timed(ctx, K_BLEND_BWD, [&] {
+      return launch_blend_bwd(saved->s.tile, saved->s.batch, vt, saved->ru, saved->rec, saved->ranges,
+                              saved->vals, saved->T_final, saved->n_contrib, grad2d, s);
+    });
   GradOut go{out->means, out->scales, out->quats, out->opacities, out->sh, int(flags & GSR_ACCUMULATE)};
-  if (e == hipSuccess) e = launch_project_bwd(saved->deg, saved->g, vt, saved->ru, saved->rec, grad2d, go, s);
+  if (e == hipSuccess)
+    e = timed(ctx, K_PROJECT_BWD,
+              [&] { return launch_project_bwd(saved->deg, saved->g, vt, saved->ru, saved->rec, grad2d, go, s); });
   if (g2) (void)hipFreeAsync(g2, s);
   if (e != hipSuccess) return fail(ctx, GSR_EDEVICE, std::string("backward launch failed: ") + hipGetErrorString(e));
   return GSR_OK;

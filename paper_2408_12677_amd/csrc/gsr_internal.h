@@ -3,10 +3,91 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "gsr.h"
 
 namespace gsr {
+
+// Kernel ids of the optional per-launch event timer (order matches gsr_kernel_name).
+enum KernelId {
+  K_PROJECT = 0,
+  K_SCAN,
+  K_DUPLICATE,
+  K_RADIX_HIST,
+  K_RADIX_ROWSCAN,
+  K_RADIX_SCATTER,
+  K_RANGES,
+  K_FILL,
+  K_BLEND_FWD,
+  K_LOSS,
+  K_BLEND_BWD,
+  K_PROJECT_BWD,
+  K_COUNT
+};
+
+// Records a HIP event pair around each launch when enabled; durations are collected
+// (after a synchronisation) by Timer::collect.
+struct Timer {
+  bool on = false;
+  hipStream_t stream = nullptr;
+  struct Rec {
+    int k;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> free_events;
+  std::vector<Rec> pending;
+  hipEvent_t open[K_COUNT] = {};
+  double ms[K_COUNT] = {};
+  long long launches[K_COUNT] = {};
+
+  hipEvent_t take() {
+    hipEvent_t e = nullptr;
+    if (!free_events.empty()) {
+      e = free_events.back();
+      free_events.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  void begin(int k) {
+    if (!on) return;
+    open[k] = take();
+    if (open[k]) (void)hipEventRecord(open[k], stream);
+  }
+  void end(int k) {
+    if (!on || !open[k]) return;
+    hipEvent_t b = take();
+    if (!b) return;
+    (void)hipEventRecord(b, stream);
+    pending.push_back(Rec{k, open[k], b});
+    open[k] = nullptr;
+  }
+  void collect() {
+    for (const Rec& r : pending) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        ms[r.k] += t;
+        launches[r.k] += 1;
+      }
+      free_events.push_back(r.a);
+      free_events.push_back(r.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    for (int i = 0; i < K_COUNT; ++i) {
+      ms[i] = 0.0;
+      launches[i] = 0;
+    }
+  }
+  void destroy() {
+    collect();
+    for (hipEvent_t e : free_events) (void)hipEventDestroy(e);
+    free_events.clear();
+  }
+};
 
 constexpr int kProjThreads = 256;  // Gaussians per block in the per-Gaussian kernels
 constexpr int kSortThreads = 256;
@@ -83,7 +164,7 @@ hipError_t launch_duplicate(const ViewTable& vt, int64_t n, const Records& rec, 
                             hipStream_t s);
 hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
                              uint32_t* hist, uint32_t* digit_tot, int64_t M, int key_bits, bool* result_in_alt,
-                             int* passes, hipStream_t s);
+                             int* passes, hipStream_t s, Timer* tm);
 hipError_t launch_ranges(const uint64_t* keys, int64_t M, uint2* ranges, int total_tiles, hipStream_t s);
 hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,

@@ -981,7 +981,7 @@ hipError_t launch_duplicate(const ViewTable& vt, int64_t n, const Records& rec, 
 
 hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
                              uint32_t* hist, uint32_t* digit_tot, int64_t M, int key_bits, bool* result_in_alt,
-                             int* passes, hipStream_t s) {
+                             int* passes, hipStream_t s, Timer* tm) {
   const int np = (key_bits + 7) / 8;
   *passes = np;
   *result_in_alt = false;
@@ -996,9 +996,15 @@ hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
   uint32_t* vout = vals_alt;
   for (int p = 0; p < np; ++p) {
     const int shift = 8 * p;
+    if (tm) tm->begin(K_RADIX_HIST);
     k_radix_hist<<<nblk, kSortThreads, 0, s>>>(kin, M, shift, hist, nblk);
+    if (tm) tm->end(K_RADIX_HIST);
+    if (tm) tm->begin(K_RADIX_ROWSCAN);
     k_radix_rowscan<<<256, kSortThreads, 0, s>>>(hist, nblk, digit_tot);
+    if (tm) tm->end(K_RADIX_ROWSCAN);
+    if (tm) tm->begin(K_RADIX_SCATTER);
     k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(kin, vin, kout, vout, M, shift, hist, digit_tot, nblk);
+    if (tm) tm->end(K_RADIX_SCATTER);
     std::swap(kin, kout);
     std::swap(vin, vout);
   }

@@ -81,6 +81,15 @@ class Context:
         N.check(lib.gsr_ctx_create(device, ctypes.c_void_p(stream), ctypes.byref(h)))
         self.h = h
 
+    def set_timing(self, on: bool):
+        N.check(self.lib.gsr_ctx_set_timing(self.h, int(bool(on))), self.h)
+
+    def timing(self, reset: bool = True) -> dict:
+        """{kernel name: (total ms, launches)} accumulated since the last reset (synchronises)."""
+        t = N.Timing()
+        N.check(self.lib.gsr_ctx_get_timing(self.h, ctypes.byref(t), int(reset)), self.h)
+        return {self.lib.gsr_kernel_name(i).decode(): (t.ms[i], t.launches[i]) for i in range(t.count)}
+
     def __del__(self):
         h = getattr(self, "h", None)
         if h and h.value:
