@@ -669,16 +669,29 @@ __global__ void k_zero_f32(float* p) { *p = 0.f; }
 // K8: backward compositing.  Back to front over each pixel's contributors; the
 // transmittance before contributor i is T_{i+1} / (1 - alpha_i), starting from the saved
 // final value; the colour/depth behind i is carried as a running blend.
+//
+// Each wavefront walks the staged batch only down from its own longest contributor list.
+// The ten per-(pixel, splat) partials are summed across the wavefront with DPP; with more
+// than one wavefront per tile the wavefront sums meet in LDS and the block adds each
+// splat's total to the 2D-gradient buffer once per batch, with the atomics spread over
+// all lanes.
 // ------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, uint32_t(__shfl_xor(v, off)));
+  return v;
+}
+
 template <int TS, int BATCH>
 __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Records rec, const uint2* ranges,
                                                      const uint32_t* vals, const float* T_final,
                                                      const uint32_t* n_contrib, float* grad2d) {
   constexpr int NT = TS * TS;
+  constexpr bool kBlockSum = NT > 64;
   __shared__ float4 s_r0[BATCH];
   __shared__ float4 s_r1[BATCH];
   __shared__ float4 s_rgb[BATCH];
   __shared__ uint32_t s_id[BATCH];
+  __shared__ float s_g[kBlockSum ? 10 : 1][kBlockSum ? BATCH : 1];
   __shared__ uint32_t s_max;
   const int tile = blockIdx.x;
   const ViewDev& cam = vt.v[view_of_tile(vt, tile)];
@@ -703,9 +716,12 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
     if (cam.g_depth) gD = cam.g_depth[pix];
     if (cam.g_alpha) gA = cam.g_alpha[pix];
   }
+  const int wmax = int(wave_max_u32(last));
   if (threadIdx.x == 0) s_max = 0;
+  if (kBlockSum)
+    for (int i = threadIdx.x; i < 10 * BATCH; i += NT) (&s_g[0][0])[i] = 0.f;
   __syncthreads();
-  if (last) atomicMax(&s_max, last);
+  if (lane == 0 && wmax) atomicMax(&s_max, uint32_t(wmax));
   __syncthreads();
   const int nmax = int(s_max);
   const float Tfin = T;
@@ -713,8 +729,9 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
   float BC0 = ru.bg[0], BC1 = ru.bg[1], BC2 = ru.bg[2], BD = 0.f;
   for (int bend = nmax; bend > 0; bend -= BATCH) {
     const int bstart = bend > BATCH ? bend - BATCH : 0;
+    const int cnt = bend - bstart;
     __syncthreads();
-    for (int j = threadIdx.x; j < bend - bstart; j += NT) {
+    for (int j = threadIdx.x; j < cnt; j += NT) {
       const uint32_t id = vals[rg.x + bstart + j];
       s_id[j] = id;
       s_r0[j] = rec.r0[id];
@@ -722,7 +739,8 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
       s_rgb[j] = rec.rgb[id];
     }
     __syncthreads();
-    for (int j = bend - bstart - 1; j >= 0; --j) {
+    const int jtop = min(cnt, wmax - bstart) - 1;  // wavefront-uniform
+    for (int j = jtop; j >= 0; --j) {
       const int pos = bstart + j;
       float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, g4 = 0.f, g5 = 0.f, g6 = 0.f, g7 = 0.f, g8 = 0.f, g9 = 0.f;
       bool act = false;
@@ -737,14 +755,15 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
           const float4 c = s_rgb[j];
           const float al = a < ru.amax ? a : ru.amax;
           const float om = 1.f - al;
-          T = T / om;
+          const float iom = __builtin_amdgcn_rcpf(om);
+          T = T * iom;
           const float wgt = al * T;
           g6 = gC0 * wgt;
           g7 = gC1 * wgt;
           g8 = gC2 * wgt;
           g9 = gD * wgt;
           const float dal =
-              T * (gC0 * (c.x - BC0) + gC1 * (c.y - BC1) + gC2 * (c.z - BC2) + gD * (r1.z - BD)) + gA * Tfin / om;
+              T * (gC0 * (c.x - BC0) + gC1 * (c.y - BC1) + gC2 * (c.z - BC2) + gD * (r1.z - BD)) + gA * Tfin * iom;
           BC0 = al * c.x + om * BC0;
           BC1 = al * c.y + om * BC1;
           BC2 = al * c.z + om * BC2;
@@ -771,17 +790,41 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
         g8 = wave_sum_to_lane63(g8);
         g9 = wave_sum_to_lane63(g9);
         if (lane == 63) {
-          float* dst = grad2d + int64_t(s_id[j]) * kGrad2D;
-          unsafeAtomicAdd(dst + 0, g0);
-          unsafeAtomicAdd(dst + 1, g1);
-          unsafeAtomicAdd(dst + 2, g2);
-          unsafeAtomicAdd(dst + 3, g3);
-          unsafeAtomicAdd(dst + 4, g4);
-          unsafeAtomicAdd(dst + 5, g5);
-          unsafeAtomicAdd(dst + 6, g6);
-          unsafeAtomicAdd(dst + 7, g7);
-          unsafeAtomicAdd(dst + 8, g8);
-          unsafeAtomicAdd(dst + 9, g9);
+          if (kBlockSum) {
+            atomicAdd(&s_g[0][j], g0);
+            atomicAdd(&s_g[1][j], g1);
+            atomicAdd(&s_g[2][j], g2);
+            atomicAdd(&s_g[3][j], g3);
+            atomicAdd(&s_g[4][j], g4);
+            atomicAdd(&s_g[5][j], g5);
+            atomicAdd(&s_g[6][j], g6);
+            atomicAdd(&s_g[7][j], g7);
+            atomicAdd(&s_g[8][j], g8);
+            atomicAdd(&s_g[9][j], g9);
+          } else {
+            float* dst = grad2d + int64_t(s_id[j]) * kGrad2D;
+            unsafeAtomicAdd(dst + 0, g0);
+            unsafeAtomicAdd(dst + 1, g1);
+            unsafeAtomicAdd(dst + 2, g2);
+            unsafeAtomicAdd(dst + 3, g3);
+            unsafeAtomicAdd(dst + 4, g4);
+            unsafeAtomicAdd(dst + 5, g5);
+            unsafeAtomicAdd(dst + 6, g6);
+            unsafeAtomicAdd(dst + 7, g7);
+            unsafeAtomicAdd(dst + 8, g8);
+            unsafeAtomicAdd(dst + 9, g9);
+          }
+        }
+      }
+    }
+    if (kBlockSum) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < 10 * cnt; i += NT) {
+        const int k = i / cnt, j = i - k * cnt;
+        const float v = s_g[k][j];
+        if (v != 0.f) {
+          unsafeAtomicAdd(grad2d + int64_t(s_id[j]) * kGrad2D + k, v);
+          s_g[k][j] = 0.f;
         }
       }
     }
