@@ -18,14 +18,14 @@ struct gsr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
-  unsigned long long* h_total = nullptr;  // pinned read-back slot
+  unsigned long long* h_total = nullptr;  // pinned read-back slots: pair count M, visible records
   Timer timer;
 };
 
 namespace {
-const char* const kKernelNames[K_COUNT] = {"project",       "scan_blocksums", "duplicate", "radix_hist",
-                                           "radix_rowscan", "radix_scatter",  "ranges",    "fill",
-                                           "blend_fwd",     "loss_l1",        "blend_bwd", "project_bwd"};
+const char* const kKernelNames[K_COUNT] = {
+    "project", "scan",   "compact", "sorted_counts", "duplicate", "radix_hist", "radix_rowscan", "radix_scatter",
+    "ranges",  "fill",   "blend_fwd", "loss_l1",     "blend_bwd", "project_bwd"};
 
 // Wraps one launch (or launch sequence) in the context's optional event timer.
 template <class F>
@@ -49,11 +49,12 @@ struct gsr_saved {
   ViewTable vt{};
   Records rec{};
   int nblk = 0;
-  uint32_t* blocksums = nullptr;
-  unsigned long long* d_total = nullptr;
+  uint2* blocksums = nullptr;
+  unsigned long long* d_total = nullptr;  // [0] pairs M, [1] visible records, [2] pairs written
   int64_t M = 0;
-  uint64_t* keys = nullptr;
-  uint32_t* vals = nullptr;
+  int64_t n_vis = 0;
+  uint32_t* tiles = nullptr;  // sorted tile id of every pair
+  uint32_t* vals = nullptr;   // sorted record id of every pair
   uint2* ranges = nullptr;
   float* T_final = nullptr;
   uint32_t* n_contrib = nullptr;
@@ -186,7 +187,7 @@ gsr_status gsr_ctx_create(int32_t device, void* hip_stream, gsr_ctx** out) {
   gsr_ctx* c = new gsr_ctx;
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_total), sizeof(unsigned long long), hipHostMallocDefault) !=
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_total), 2 * sizeof(unsigned long long), hipHostMallocDefault) !=
       hipSuccess) {
     delete c;
     return fail(nullptr, GSR_ENOMEM, "pinned host allocation failed");
@@ -322,79 +323,103 @@ gsr_status gsr_forward(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* c
   TRY(saved_alloc(sv, &sv->rec.rect, VN));
   TRY(saved_alloc(sv, &sv->rec.counts, VN));
   TRY(saved_alloc(sv, &sv->blocksums, size_t(V) * sv->nblk + 1));
-  TRY(saved_alloc(sv, &sv->d_total, 1));
+  TRY(saved_alloc(sv, &sv->d_total, 4));
   TRY(saved_alloc(sv, &sv->ranges, size_t(tiles)));
   TRY(saved_alloc(sv, &sv->T_final, size_t(pix)));
   TRY(saved_alloc(sv, &sv->n_contrib, size_t(pix)));
 
-  int64_t M = 0;
+  int64_t M = 0, NV = 0;
   if (g->n > 0) {
     TRYH(timed(ctx, K_PROJECT, [&] {
       return launch_project(sv->deg, sv->g, vt, sv->ru, s->tile, sv->rec, sv->blocksums, sv->nblk, st_);
     }));
-    TRYH(timed(ctx, K_SCAN, [&] { return launch_scan_blocksums(sv->blocksums, V * sv->nblk, sv->d_total, st_); }));
-    TRYH(hipMemcpyAsync(ctx->h_total, sv->d_total, sizeof(unsigned long long), hipMemcpyDeviceToHost, st_));
+    TRYH(timed(ctx, K_SCAN, [&] { return launch_scan_pairs(sv->blocksums, V * sv->nblk, sv->d_total, st_); }));
+    TRYH(hipMemcpyAsync(ctx->h_total, sv->d_total, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st_));
     TRYH(hipStreamSynchronize(st_));
-    M = int64_t(*ctx->h_total);
+    M = int64_t(ctx->h_total[0]);
+    NV = int64_t(ctx->h_total[1]);
     if (M >= (int64_t(1) << 32)) {
       release(sv);
       return fail(ctx, GSR_ECAPACITY, "more than 2^32 duplicated keys");
     }
   }
   sv->M = M;
+  sv->n_vis = NV;
   if (M > 0) {
-    uint64_t *k0 = nullptr, *k1 = nullptr;
-    uint32_t *v0 = nullptr, *v1 = nullptr, *hist = nullptr, *dtot = nullptr, *ovf = nullptr;
-    TRY(saved_alloc(sv, &k0, size_t(M)));
-    TRY(saved_alloc(sv, &v0, size_t(M)));
-    void *tk = nullptr, *tv = nullptr, *th = nullptr, *td = nullptr, *to = nullptr;
-    const int sort_blocks = int((M + kSortTile - 1) / kSortTile);
-    auto free_tmp = [&]() {
-      for (void* p : {tk, tv, th, td, to})
-        if (p) (void)hipFreeAsync(p, st_);
+    // Stable LSD sort of the (tile << 32 | depth) keys: the depth digits on the NV records,
+    // then duplication in depth order, then the tile digits on the M pairs.
+    uint32_t *tk = nullptr, *tv = nullptr;
+    TRY(saved_alloc(sv, &tk, size_t(M)));
+    TRY(saved_alloc(sv, &tv, size_t(M)));
+    const int tile_bits = bits_for(uint64_t(tiles > 0 ? tiles - 1 : 0));
+    const int64_t sort_cap = std::max(NV, M);
+    const int nb_sort = int((sort_cap + kSortTile - 1) / kSortTile);
+    const int nb_vis = int((NV + kProjThreads - 1) / kProjThreads);
+    std::vector<void*> tmp;
+    auto tmp_alloc = [&](void** p, size_t bytes) -> gsr_status {
+      gsr_status r = dev_alloc(ctx, p, bytes);
+      if (r == GSR_OK && *p) tmp.push_back(*p);
+      return r;
     };
+    auto free_tmp = [&]() {
+      for (void* p : tmp) (void)hipFreeAsync(p, st_);
+      tmp.clear();
+    };
+    void *dk = nullptr, *dv = nullptr, *dk2 = nullptr, *dv2 = nullptr, *tk2 = nullptr, *tv2 = nullptr;
+    void *hist = nullptr, *dtot = nullptr, *bs2 = nullptr, *ovf = nullptr;
     gsr_status a = GSR_OK;
-    if ((a = dev_alloc(ctx, &tk, size_t(M) * 8)) != GSR_OK || (a = dev_alloc(ctx, &tv, size_t(M) * 4)) != GSR_OK ||
-        (a = dev_alloc(ctx, &th, size_t(sort_blocks) * 256 * 4)) != GSR_OK ||
-        (a = dev_alloc(ctx, &td, 256 * 4)) != GSR_OK || (a = dev_alloc(ctx, &to, 4)) != GSR_OK) {
+    if ((a = tmp_alloc(&dk, size_t(NV) * 4)) != GSR_OK || (a = tmp_alloc(&dv, size_t(NV) * 4)) != GSR_OK ||
+        (a = tmp_alloc(&dk2, size_t(NV) * 4)) != GSR_OK || (a = tmp_alloc(&dv2, size_t(NV) * 4)) != GSR_OK ||
+        (a = tmp_alloc(&tk2, size_t(M) * 4)) != GSR_OK || (a = tmp_alloc(&tv2, size_t(M) * 4)) != GSR_OK ||
+        (a = tmp_alloc(&hist, size_t(nb_sort) * 256 * 4)) != GSR_OK ||
+        (a = tmp_alloc(&dtot, 256 * 4)) != GSR_OK || (a = tmp_alloc(&bs2, size_t(nb_vis + 1) * 4)) != GSR_OK ||
+        (a = tmp_alloc(&ovf, 4)) != GSR_OK) {
       free_tmp();
       release(sv);
       return a;
     }
-    k1 = static_cast<uint64_t*>(tk);
-    v1 = static_cast<uint32_t*>(tv);
-    hist = static_cast<uint32_t*>(th);
-    dtot = static_cast<uint32_t*>(td);
-    ovf = static_cast<uint32_t*>(to);
-    hipError_t e = timed(ctx, K_FILL, [&] { return launch_fill_u32(ovf, 0u, 1, st_); });
-    if (e == hipSuccess)
-      e = timed(ctx, K_DUPLICATE, [&] {
-        return launch_duplicate(vt, g->n, sv->rec, sv->blocksums, sv->nblk, k0, v0, uint64_t(M), ovf, st_);
-      });
-    bool in_alt = false;
-    const int key_bits = 32 + bits_for(uint64_t(tiles > 0 ? tiles - 1 : 0));
+    Timer* tm = ctx->timer.on ? &ctx->timer : nullptr;
     ctx->timer.stream = st_;
+    bool alt1 = false, alt2 = false;
+    int p1 = 0, p2 = 0;
+    hipError_t e = timed(ctx, K_FILL, [&] { return launch_fill_u32(static_cast<uint32_t*>(ovf), 0u, 1, st_); });
     if (e == hipSuccess)
-      e = launch_radix_sort(k0, v0, k1, v1, hist, dtot, M, key_bits, &in_alt, &sv->sort_passes, st_,
-                            ctx->timer.on ? &ctx->timer : nullptr);
+      e = timed(ctx, K_COMPACT, [&] {
+        return launch_compact(g->n, V, sv->rec, sv->blocksums, sv->nblk, static_cast<uint32_t*>(dk),
+                              static_cast<uint32_t*>(dv), st_);
+      });
+    if (e == hipSuccess)
+      e = launch_radix_sort(static_cast<uint32_t*>(dk), static_cast<uint32_t*>(dv), static_cast<uint32_t*>(dk2),
+                            static_cast<uint32_t*>(dv2), static_cast<uint32_t*>(hist), static_cast<uint32_t*>(dtot),
+                            sv->d_total + 1, NV, 32, &alt1, &p1, st_, tm);
+    const uint32_t* dsorted = static_cast<const uint32_t*>(alt1 ? dv2 : dv);
+    if (e == hipSuccess)
+      e = launch_duplicate(vt, g->n, sv->rec, dsorted, sv->d_total + 1, NV, static_cast<uint32_t*>(bs2),
+                           sv->d_total + 2, tk, tv, M, static_cast<uint32_t*>(ovf), st_, tm);
+    if (e == hipSuccess)
+      e = launch_radix_sort(tk, tv, static_cast<uint32_t*>(tk2), static_cast<uint32_t*>(tv2),
+                            static_cast<uint32_t*>(hist), static_cast<uint32_t*>(dtot), sv->d_total, M, tile_bits,
+                            &alt2, &p2, st_, tm);
     if (e != hipSuccess) {
       free_tmp();
       release(sv);
-      return fail(ctx, GSR_EDEVICE, std::string("key duplication/sort launch failed: ") + hipGetErrorString(e));
+      return fail(ctx, GSR_EDEVICE, std::string("sort launch failed: ") + hipGetErrorString(e));
     }
-    if (in_alt) {  // keep the sorted copy, return the other to the pool
-      std::replace(sv->blocks.begin(), sv->blocks.end(), static_cast<void*>(k0), tk);
-      std::replace(sv->blocks.begin(), sv->blocks.end(), static_cast<void*>(v0), tv);
-      tk = k0;
-      tv = v0;
-      std::swap(k0, k1);
-      std::swap(v0, v1);
+    if (alt2) {  // the sorted pairs ended in the second buffers: keep those, recycle the first
+      std::replace(sv->blocks.begin(), sv->blocks.end(), static_cast<void*>(tk), tk2);
+      std::replace(sv->blocks.begin(), sv->blocks.end(), static_cast<void*>(tv), tv2);
+      std::replace(tmp.begin(), tmp.end(), tk2, static_cast<void*>(tk));
+      std::replace(tmp.begin(), tmp.end(), tv2, static_cast<void*>(tv));
+      tk = static_cast<uint32_t*>(tk2);
+      tv = static_cast<uint32_t*>(tv2);
     }
-    sv->keys = k0;
-    sv->vals = v0;
+    sv->tiles = tk;
+    sv->vals = tv;
+    sv->sort_passes = p1 + p2;
     free_tmp();
   }
-  TRYH(timed(ctx, K_RANGES, [&] { return launch_ranges(sv->keys, M, sv->ranges, vt.total_tiles, st_); }));
+  TRYH(timed(ctx, K_RANGES,
+             [&] { return launch_ranges(sv->tiles, sv->d_total, M, sv->ranges, vt.total_tiles, st_); }));
   TRYH(timed(ctx, K_BLEND_FWD, [&] {
     return launch_blend_fwd(s->tile, s->batch, vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final,
                             sv->n_contrib, st_);
@@ -492,7 +517,18 @@ gsr_status gsr_debug_export(gsr_ctx* ctx, const gsr_saved* sv, const gsr_debug* 
     if (!dst || !src || bytes == 0) return hipSuccess;
     return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
   };
-  GSR_HIP(ctx, cp(out->keys, sv->keys, size_t(sv->M) * 8));
+  if (out->keys && sv->M > 0) {  // key = tile << 32 | depth bits of the pair's record
+    std::vector<uint32_t> t(sv->M), v(sv->M);
+    std::vector<float4> r1(VN);
+    GSR_HIP(ctx, cp(t.data(), sv->tiles, size_t(sv->M) * 4));
+    GSR_HIP(ctx, cp(v.data(), sv->vals, size_t(sv->M) * 4));
+    GSR_HIP(ctx, cp(r1.data(), sv->rec.r1, size_t(VN) * sizeof(float4)));
+    for (int64_t i = 0; i < sv->M; ++i) {
+      uint32_t zb;
+      std::memcpy(&zb, &r1[v[i]].z, 4);
+      out->keys[i] = (uint64_t(t[i]) << 32) | zb;
+    }
+  }
   GSR_HIP(ctx, cp(out->values, sv->vals, size_t(sv->M) * 4));
   GSR_HIP(ctx, cp(out->ranges, sv->ranges, size_t(sv->vt.total_tiles) * 8));
   GSR_HIP(ctx, cp(out->T_final, sv->T_final, size_t(sv->total_pix) * 4));

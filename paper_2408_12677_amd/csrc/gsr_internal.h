@@ -13,6 +13,8 @@ namespace gsr {
 enum KernelId {
   K_PROJECT = 0,
   K_SCAN,
+  K_COMPACT,
+  K_DUP_COUNT,
   K_DUPLICATE,
   K_RADIX_HIST,
   K_RADIX_ROWSCAN,
@@ -156,16 +158,22 @@ struct GradOut {
 };
 
 // ---- launchers (gsr_kernels.hip) --------------------------------------------------
+// Device-side counts (unsigned long long) are clamped by each kernel to the capacity its
+// grid and buffers were sized for.
 hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru, int tile,
-                          const Records& rec, uint32_t* blocksums, int nblk, hipStream_t s);
-hipError_t launch_scan_blocksums(uint32_t* blocksums, int count, unsigned long long* total, hipStream_t s);
-hipError_t launch_duplicate(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* blocksums,
-                            int nblk, uint64_t* keys, uint32_t* vals, uint64_t capacity, uint32_t* overflow,
-                            hipStream_t s);
-hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-                             uint32_t* hist, uint32_t* digit_tot, int64_t M, int key_bits, bool* result_in_alt,
-                             int* passes, hipStream_t s, Timer* tm);
-hipError_t launch_ranges(const uint64_t* keys, int64_t M, uint2* ranges, int total_tiles, hipStream_t s);
+                          const Records& rec, uint2* blocksums, int nblk, hipStream_t s);
+hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* totals, hipStream_t s);
+hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
+                          uint32_t* dkeys, uint32_t* dvals, hipStream_t s);
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                             uint32_t* hist, uint32_t* digit_tot, const unsigned long long* count, int64_t cap,
+                             int key_bits, bool* result_in_alt, int* passes, hipStream_t s, Timer* tm);
+hipError_t launch_duplicate(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* dvals,
+                            const unsigned long long* nvis, int64_t cap_vis, uint32_t* blocksums,
+                            unsigned long long* total, uint32_t* tkeys, uint32_t* tvals, int64_t cap_M,
+                            uint32_t* overflow, hipStream_t s, Timer* tm);
+hipError_t launch_ranges(const uint32_t* tkeys, const unsigned long long* count, int64_t cap, uint2* ranges,
+                         int total_tiles, hipStream_t s);
 hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
                             hipStream_t s);

@@ -2,10 +2,15 @@
 //
 //   K1 k_project        per Gaussian, loop over views: Eq. 2, 4, 5 (+ low-pass), conic of
 //                       the 2D splat (Eq. 3), SH colour, frustum cull, tile rectangle, tile count,
-//                       block sums of the counts
-//   K2 k_scan_blocksums exclusive scan of the block sums (one block)
-//   K3 k_duplicate      (tile id << 32 | depth bits, record id) pairs in duplication order
-//   K4 k_radix_*        stable LSD radix sort, 8-bit digits (histogram / row scan / scatter)
+//                       block sums of the tile counts and of the visible records
+//   K2 k_scan_pairs     exclusive scans of those block sums (one block)
+//   K3/K4               the stable sort of the (tile id << 32 | depth bits) keys, in LSD order:
+//                       k_compact + k_radix_* sort the visible records by their depth bits
+//                       (the four low digits) before duplication, which commutes with a
+//                       stable depth sort; k_sorted_counts + k_duplicate then write
+//                       (tile id, record) pairs in depth order, and k_radix_* passes over the
+//                       tile digits finish the sort (8-bit digits: histogram / row scan /
+//                       ballot-multisplit scatter)
 //   K5 k_ranges         [start, end) of every tile in the sorted list
 //   K6 k_blend_fwd      per tile: front-to-back compositing, Eq. 11 with clamp/skip/stop
 //   K7 k_loss_l1        Eq. 12 (mean L1 colour) + weighted mean L1 depth, its gradient
@@ -305,11 +310,11 @@ __device__ __forceinline__ void sh_grad_dot(float x, float y, float z, const flo
 }
 
 // ------------------------------------------------------------------------------------
-// K1: projection
+// K1: projection.  Per view, the block also sums its tile counts and visible records.
 // ------------------------------------------------------------------------------------
 template <int DEG>
 __global__ __launch_bounds__(kProjThreads) void k_project(GaussDev g, ViewTable vt, Rules ru, int tile,
-                                                          Records rec, uint32_t* blocksums, int nblk) {
+                                                          Records rec, uint2* blocksums, int nblk) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ uint32_t red[kProjThreads / 64];
   const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
@@ -367,21 +372,19 @@ __global__ __launch_bounds__(kProjThreads) void k_project(GaussDev g, ViewTable 
       rec.counts[rid] = cnt;
     }
     const uint32_t bs = block_sum_u32(cnt, red);
-    if (threadIdx.x == 0) blocksums[int64_t(v) * nblk + blockIdx.x] = bs;
+    const uint32_t bv = block_sum_u32(cnt ? 1u : 0u, red);
+    if (threadIdx.x == 0) blocksums[int64_t(v) * nblk + blockIdx.x] = make_uint2(bs, bv);
   }
 }
 
 // ------------------------------------------------------------------------------------
-// K2: exclusive scan of the per-block tile counts (one block of 1024 threads)
+// K2: exclusive scans of per-block sums (one block of 1024 threads).  Totals are written
+// as 64-bit values; consumers clamp them to their buffer capacity.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_scan_blocksums(uint32_t* a, int count, unsigned long long* total) {
-  __shared__ unsigned long long part[1024];
+__device__ __forceinline__ unsigned long long block_inclusive_scan_u64_1024(unsigned long long v,
+                                                                           unsigned long long* part) {
   const int t = threadIdx.x;
-  const int per = (count + 1023) / 1024;
-  const int beg = min(count, t * per), end = min(count, beg + per);
-  unsigned long long sum = 0;
-  for (int i = beg; i < end; ++i) sum += a[i];
-  part[t] = sum;
+  part[t] = v;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
     const unsigned long long add = t >= off ? part[t - off] : 0ull;
@@ -389,65 +392,95 @@ __global__ __launch_bounds__(1024) void k_scan_blocksums(uint32_t* a, int count,
     part[t] += add;
     __syncthreads();
   }
-  unsigned long long run = t ? part[t - 1] : 0ull;
+  return part[t];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_pairs(uint2* a, int count, unsigned long long* totals) {
+  __shared__ unsigned long long part[1024];
+  const int t = threadIdx.x;
+  const int per = (count + 1023) / 1024;
+  const int beg = min(count, t * per), end = min(count, beg + per);
+  unsigned long long sx = 0, sy = 0;
+  for (int i = beg; i < end; ++i) {
+    const uint2 x = a[i];
+    sx += x.x;
+    sy += x.y;
+  }
+  const unsigned long long ix = block_inclusive_scan_u64_1024(sx, part);
+  __syncthreads();
+  const unsigned long long iy = block_inclusive_scan_u64_1024(sy, part);
+  unsigned long long rx = ix - sx, ry = iy - sy;
+  for (int i = beg; i < end; ++i) {
+    const uint2 x = a[i];
+    a[i] = make_uint2(uint32_t(rx), uint32_t(ry));
+    rx += x.x;
+    ry += x.y;
+  }
+  if (t == 1023) {
+    totals[0] = ix;
+    totals[1] = iy;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* a, int count, unsigned long long* total) {
+  __shared__ unsigned long long part[1024];
+  const int t = threadIdx.x;
+  const int per = (count + 1023) / 1024;
+  const int beg = min(count, t * per), end = min(count, beg + per);
+  unsigned long long sum = 0;
+  for (int i = beg; i < end; ++i) sum += a[i];
+  const unsigned long long incl = block_inclusive_scan_u64_1024(sum, part);
+  unsigned long long run = incl - sum;
   for (int i = beg; i < end; ++i) {
     const uint32_t x = a[i];
     a[i] = uint32_t(run);
     run += x;
   }
-  if (t == 1023) *total = part[1023];
+  if (t == 1023) *total = incl;
+}
+
+__device__ __forceinline__ uint32_t clamp_count(const unsigned long long* count, int64_t cap) {
+  const unsigned long long c = *count;
+  return uint32_t(c < (unsigned long long)cap ? c : (unsigned long long)cap);
 }
 
 // ------------------------------------------------------------------------------------
-// K3: duplication into (tile | depth) keys, in (view, Gaussian, tile row, column) order
+// K3a: compaction of the visible records into (depth bits, record id) pairs, record order
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kProjThreads) void k_duplicate(ViewTable vt, int64_t n, Records rec,
-                                                            const uint32_t* blocksums, int nblk, uint64_t* keys,
-                                                            uint32_t* vals, uint64_t cap, uint32_t* overflow) {
+__global__ __launch_bounds__(kProjThreads) void k_compact(int64_t n, Records rec, const uint2* blocksums, int nblk,
+                                                          uint32_t* dkeys, uint32_t* dvals) {
   __shared__ uint32_t red[kProjThreads / 64];
   const int v = blockIdx.y;
   const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
   const int64_t rid = int64_t(v) * n + gi;
-  const uint32_t cnt = gi < n ? rec.counts[rid] : 0u;
-  const uint32_t excl = block_exclusive_scan_u32(cnt, red);
-  if (cnt == 0) return;
-  const uint64_t off = uint64_t(blocksums[int64_t(v) * nblk + blockIdx.x]) + excl;
-  if (off + cnt > cap) {
-    atomicOr(overflow, 1u);
-    return;
-  }
-  const uint2 rc = rec.rect[rid];
-  const uint64_t zb = __float_as_uint(rec.r1[rid].z);
-  const int tx0 = rc.x & 0xFFFF, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
-  const ViewDev& cam = vt.v[v];
-  uint64_t o = off;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      const uint64_t tid = uint64_t(cam.tile_off + ty * cam.tiles_x + tx);
-      keys[o] = (tid << 32) | zb;
-      vals[o] = uint32_t(rid);
-      ++o;
-    }
+  const uint32_t vis = (gi < n && rec.counts[rid] != 0u) ? 1u : 0u;
+  const uint32_t excl = block_exclusive_scan_u32(vis, red);
+  if (!vis) return;
+  const uint32_t off = blocksums[int64_t(v) * nblk + blockIdx.x].y + excl;
+  dkeys[off] = __float_as_uint(rec.r1[rid].z);
+  dvals[off] = uint32_t(rid);
 }
 
 // ------------------------------------------------------------------------------------
-// K4: stable LSD radix sort of (key, value), 8-bit digits.  Per pass:
+// K4: stable LSD radix sort of (u32 key, u32 value), 8-bit digits, count read from the
+// device (clamped to the capacity the grid was sized for).  Per pass:
 //   hist:    per-block digit histograms, stored digit-major [256][nblk]
 //   rowscan: one block per digit scans its row -> start of each block in that digit,
 //            and the digit total
 //   scatter: each block ranks its keys stably (wavefront multisplit by ballots, then
 //            across the four wavefronts through LDS) and writes them to their slots
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* keys, int64_t M, int shift,
-                                                             uint32_t* hist, int nblk) {
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* keys, const unsigned long long* count,
+                                                             int64_t cap, int shift, uint32_t* hist, int nblk) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
+  const int64_t M = clamp_count(count, cap);
   const int64_t base = int64_t(blockIdx.x) * kSortTile;
 #pragma unroll 4
   for (int i = 0; i < kSortItems; ++i) {
     const int64_t idx = base + i * kSortThreads + threadIdx.x;
-    if (idx < M) atomicAdd(&h[uint32_t(keys[idx] >> shift) & 255u], 1u);
+    if (idx < M) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
   }
   __syncthreads();
   hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
@@ -472,14 +505,16 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* hist, 
   if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* kin, const uint32_t* vin,
-                                                                uint64_t* kout, uint32_t* vout, int64_t M,
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* kin, const uint32_t* vin,
+                                                                uint32_t* kout, uint32_t* vout,
+                                                                const unsigned long long* count, int64_t cap,
                                                                 int shift, const uint32_t* hist,
                                                                 const uint32_t* digit_tot, int nblk) {
   __shared__ uint32_t base[256];
   __shared__ uint32_t wcnt[kSortThreads / 64][256];
   __shared__ uint32_t red[kSortThreads / 64];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t M = clamp_count(count, cap);
   const uint32_t ex = block_exclusive_scan_u32(digit_tot[t], red);
   base[t] = ex + hist[int64_t(t) * nblk + blockIdx.x];
 #pragma unroll
@@ -490,12 +525,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t idx = b0 + r * kSortThreads + t;
     const bool valid = idx < M;
-    uint64_t key = 0;
-    uint32_t val = 0, d = 0;
+    uint32_t key = 0, val = 0, d = 0;
     if (valid) {
       key = kin[idx];
       val = vin[idx];
-      d = uint32_t(key >> shift) & 255u;
+      d = (key >> shift) & 255u;
     }
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -529,16 +563,89 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
 }
 
 // ------------------------------------------------------------------------------------
+// K3b: duplication of the depth-sorted records into (tile id, record id) pairs.
+//   k_sorted_counts: block sums of the tile counts in depth order
+//   k_duplicate:     each wavefront spreads its 64 records' tile runs over its lanes
+//                    (lane l writes pairs l, l+64, ...), so stores are contiguous and
+//                    records with many tiles do not serialise one lane
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kProjThreads) void k_sorted_counts(const uint32_t* dvals, const uint32_t* counts,
+                                                                const unsigned long long* nvis, int64_t cap,
+                                                                uint32_t* blocksums) {
+  __shared__ uint32_t red[kProjThreads / 64];
+  const int64_t r = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
+  const uint32_t c = r < int64_t(clamp_count(nvis, cap)) ? counts[dvals[r]] : 0u;
+  const uint32_t bs = block_sum_u32(c, red);
+  if (threadIdx.x == 0) blocksums[blockIdx.x] = bs;
+}
+
+__global__ __launch_bounds__(kProjThreads) void k_duplicate(ViewTable vt, int64_t n, Records rec,
+                                                            const uint32_t* dvals, const unsigned long long* nvis,
+                                                            int64_t cap_vis, const uint32_t* blocksums,
+                                                            uint32_t* tkeys, uint32_t* tvals, int64_t cap_M,
+                                                            uint32_t* overflow) {
+  constexpr int NW = kProjThreads / 64;
+  __shared__ uint32_t red[NW];
+  __shared__ uint32_t s_off[NW][64];
+  __shared__ uint32_t s_rid[NW][64];
+  __shared__ uint2 s_rect[NW][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t r = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
+  uint32_t rid = 0, cnt = 0;
+  uint2 rc = make_uint2(0u, 0u);
+  if (r < int64_t(clamp_count(nvis, cap_vis))) {
+    rid = dvals[r];
+    cnt = rec.counts[rid];
+    rc = rec.rect[rid];
+  }
+  const uint32_t excl = block_exclusive_scan_u32(cnt, red);
+  const uint64_t off = uint64_t(blocksums[blockIdx.x]) + excl;
+  s_off[w][lane] = uint32_t(off);
+  s_rid[w][lane] = rid;
+  s_rect[w][lane] = rc;
+  const uint64_t wbeg = uint64_t(__shfl(uint32_t(off), 0));
+  const uint64_t wend = uint64_t(__shfl(uint32_t(off + cnt), 63));
+  const bool over = wend > uint64_t(cap_M);
+  __syncthreads();
+  if (over) {
+    if (lane == 0) atomicOr(overflow, 1u);
+    return;
+  }
+  for (uint64_t p = wbeg + lane; p < wend; p += 64) {
+    // last record of this wavefront whose run starts at or before p
+    int lo = 0, hi = 63;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (uint64_t(s_off[w][mid]) <= p)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const uint32_t id = s_rid[w][lo];
+    const uint2 q = s_rect[w][lo];
+    const uint32_t local = uint32_t(p - s_off[w][lo]);
+    const uint32_t tx0 = q.x & 0xFFFFu, tx1 = q.x >> 16, ty0 = q.y & 0xFFFFu;
+    const uint32_t wdt = tx1 - tx0 + 1u;
+    const uint32_t ty = ty0 + local / wdt, tx = tx0 + local % wdt;
+    const ViewDev& cam = vt.v[id / uint32_t(n)];
+    tkeys[p] = uint32_t(cam.tile_off) + ty * uint32_t(cam.tiles_x) + tx;
+    tvals[p] = id;
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // K5: tile ranges
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ranges(const uint64_t* keys, int64_t M, uint2* ranges) {
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* tkeys, const unsigned long long* count, int64_t cap,
+                                                uint2* ranges) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t M = clamp_count(count, cap);
   if (i >= M) return;
-  const uint32_t tile = uint32_t(keys[i] >> 32);
+  const uint32_t tile = tkeys[i];
   if (i == 0) {
     ranges[tile].x = 0;
   } else {
-    const uint32_t prev = uint32_t(keys[i - 1] >> 32);
+    const uint32_t prev = tkeys[i - 1];
     if (prev != tile) {
       ranges[prev].y = uint32_t(i);
       ranges[tile].x = uint32_t(i);
@@ -996,7 +1103,7 @@ inline unsigned blocks_for(int64_t n, int per) { return unsigned((n + per - 1) /
 // launchers
 // ------------------------------------------------------------------------------------
 hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru, int tile,
-                          const Records& rec, uint32_t* blocksums, int nblk, hipStream_t s) {
+                          const Records& rec, uint2* blocksums, int nblk, hipStream_t s) {
   if (nblk == 0) return hipSuccess;
   dim3 grid(nblk), block(kProjThreads);
   switch (deg) {
@@ -1008,45 +1115,41 @@ hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const
   return hipGetLastError();
 }
 
-hipError_t launch_scan_blocksums(uint32_t* blocksums, int count, unsigned long long* total, hipStream_t s) {
-  k_scan_blocksums<<<1, 1024, 0, s>>>(blocksums, count, total);
+hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* totals, hipStream_t s) {
+  k_scan_pairs<<<1, 1024, 0, s>>>(blocksums, count, totals);
   return hipGetLastError();
 }
 
-hipError_t launch_duplicate(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* blocksums,
-                            int nblk, uint64_t* keys, uint32_t* vals, uint64_t capacity, uint32_t* overflow,
-                            hipStream_t s) {
+hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
+                          uint32_t* dkeys, uint32_t* dvals, hipStream_t s) {
   if (nblk == 0) return hipSuccess;
-  k_duplicate<<<dim3(nblk, vt.nviews), kProjThreads, 0, s>>>(vt, n, rec, blocksums, nblk, keys, vals, capacity,
-                                                             overflow);
+  k_compact<<<dim3(nblk, views), kProjThreads, 0, s>>>(n, rec, blocksums, nblk, dkeys, dvals);
   return hipGetLastError();
 }
 
-hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-                             uint32_t* hist, uint32_t* digit_tot, int64_t M, int key_bits, bool* result_in_alt,
-                             int* passes, hipStream_t s, Timer* tm) {
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                             uint32_t* hist, uint32_t* digit_tot, const unsigned long long* count, int64_t cap,
+                             int key_bits, bool* result_in_alt, int* passes, hipStream_t s, Timer* tm) {
   const int np = (key_bits + 7) / 8;
-  *passes = np;
+  *passes = 0;
   *result_in_alt = false;
-  if (M <= 1) {
-    *passes = 0;
-    return hipSuccess;
-  }
-  const int nblk = int((M + kSortTile - 1) / kSortTile);
-  uint64_t* kin = keys;
+  if (cap <= 1 || np == 0) return hipSuccess;
+  *passes = np;
+  const int nblk = int((cap + kSortTile - 1) / kSortTile);
+  uint32_t* kin = keys;
   uint32_t* vin = vals;
-  uint64_t* kout = keys_alt;
+  uint32_t* kout = keys_alt;
   uint32_t* vout = vals_alt;
   for (int p = 0; p < np; ++p) {
     const int shift = 8 * p;
     if (tm) tm->begin(K_RADIX_HIST);
-    k_radix_hist<<<nblk, kSortThreads, 0, s>>>(kin, M, shift, hist, nblk);
+    k_radix_hist<<<nblk, kSortThreads, 0, s>>>(kin, count, cap, shift, hist, nblk);
     if (tm) tm->end(K_RADIX_HIST);
     if (tm) tm->begin(K_RADIX_ROWSCAN);
     k_radix_rowscan<<<256, kSortThreads, 0, s>>>(hist, nblk, digit_tot);
     if (tm) tm->end(K_RADIX_ROWSCAN);
     if (tm) tm->begin(K_RADIX_SCATTER);
-    k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(kin, vin, kout, vout, M, shift, hist, digit_tot, nblk);
+    k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(kin, vin, kout, vout, count, cap, shift, hist, digit_tot, nblk);
     if (tm) tm->end(K_RADIX_SCATTER);
     std::swap(kin, kout);
     std::swap(vin, vout);
@@ -1055,11 +1158,31 @@ hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
   return hipGetLastError();
 }
 
-hipError_t launch_ranges(const uint64_t* keys, int64_t M, uint2* ranges, int total_tiles, hipStream_t s) {
+hipError_t launch_duplicate(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* dvals,
+                            const unsigned long long* nvis, int64_t cap_vis, uint32_t* blocksums,
+                            unsigned long long* total, uint32_t* tkeys, uint32_t* tvals, int64_t cap_M,
+                            uint32_t* overflow, hipStream_t s, Timer* tm) {
+  if (cap_vis == 0) return hipSuccess;
+  const int nb = int((cap_vis + kProjThreads - 1) / kProjThreads);
+  if (tm) tm->begin(K_DUP_COUNT);
+  k_sorted_counts<<<nb, kProjThreads, 0, s>>>(dvals, rec.counts, nvis, cap_vis, blocksums);
+  if (tm) tm->end(K_DUP_COUNT);
+  if (tm) tm->begin(K_SCAN);
+  k_scan_u32<<<1, 1024, 0, s>>>(blocksums, nb, total);
+  if (tm) tm->end(K_SCAN);
+  if (tm) tm->begin(K_DUPLICATE);
+  k_duplicate<<<nb, kProjThreads, 0, s>>>(vt, n, rec, dvals, nvis, cap_vis, blocksums, tkeys, tvals, cap_M,
+                                          overflow);
+  if (tm) tm->end(K_DUPLICATE);
+  return hipGetLastError();
+}
+
+hipError_t launch_ranges(const uint32_t* tkeys, const unsigned long long* count, int64_t cap, uint2* ranges,
+                         int total_tiles, hipStream_t s) {
   if (total_tiles > 0)
     k_fill_u32<<<blocks_for(int64_t(total_tiles) * 2, 256), 256, 0, s>>>(reinterpret_cast<uint32_t*>(ranges), 0u,
                                                                           int64_t(total_tiles) * 2);
-  if (M > 0) k_ranges<<<blocks_for(M, 256), 256, 0, s>>>(keys, M, ranges);
+  if (cap > 0) k_ranges<<<blocks_for(cap, 256), 256, 0, s>>>(tkeys, count, cap, ranges);
   return hipGetLastError();
 }
 
