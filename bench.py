@@ -65,6 +65,32 @@ def kernel_bytes(name, st):
     return 0
 
 
+FP32_PEAK_TFLOPS = 157.3      # MI355X FP32 vector (packed); unpacked FMA issue is half of it
+FLOPS_EVAL = 13                 # one splat evaluation: dx, dy, the quadratic form, exp, o*G, compare
+FLOPS_FWD_CONTRIB = 12          # forward accumulation of one contributor (clamp, 4 FMA, T update)
+FLOPS_BWD_CONTRIB = 60          # backward of one contributor (O6 formulas, T recovery, blends)
+FLOPS_WAVE_SUM = 10 * 63        # ten 64-lane sums per (wavefront, splat)
+
+
+def kernel_roofline(name, st, alg_bytes, avg_us):
+    """Roofline entry for kernel `name`: HBM for the data-movement kernels, FP32 ALU for
+    the compositing kernels (algorithmic flops from the evaluated (pixel, splat) pairs)."""
+    sec = avg_us * 1e-6
+    if name in ("blend_fwd", "blend_bwd"):
+        if name == "blend_fwd":
+            flops = st["E_fwd"] * FLOPS_EVAL + st["E_used"] * FLOPS_FWD_CONTRIB
+        else:
+            flops = st["E_bwd"] * FLOPS_EVAL + st["E_used"] * FLOPS_BWD_CONTRIB + st["wave_hits"] * FLOPS_WAVE_SUM
+        ach = flops / sec / 1e12
+        return dict(bound="alu", kernel=name, achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None, alg_flops_per_launch=int(flops),
+                    alg_bytes_per_launch=int(alg_bytes), avg_launch_us=round(avg_us, 2))
+    ach = alg_bytes / sec / 1e9 if alg_bytes else 0.0
+    return dict(bound="hbm", kernel=name, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, alg_bytes_per_launch=int(alg_bytes),
+                avg_launch_us=round(avg_us, 2))
+
+
 def step_stats(R, params, cams, targets, settings):
     """One untimed step that exports the counts the work model needs."""
     import torch
@@ -99,11 +125,29 @@ def step_stats(R, params, cams, targets, settings):
         # backward: (wavefront, list entry) pairs, with the wavefront's longest contributor list
         wv = pad.reshape(ty, ts, tx, ts).transpose(0, 2, 1, 3).reshape(ty * tx, -1, 64).max(axis=2)
         wave_hits += int(wv.sum())
+    nc_all = dbg["n_contrib"].astype(np.int64)
+    # evaluated pairs: the forward walks each pixel's list to its stop (T < T_min) or to the
+    # end of the tile's list; contributors are the evaluated entries that passed the skip rule
+    e_fwd = 0
+    off = 0
+    for v, c in enumerate(cams):
+        H, W = c.height, c.width
+        tx = -(-W // ts)
+        t0 = sum(-(-cc.width // ts) * -(-cc.height // ts) for cc in cams[:v])
+        rng = dbg["ranges"][t0:t0 + tx * -(-H // ts)].astype(np.int64)
+        length = (rng[:, 1] - rng[:, 0]).reshape(-(-H // ts), tx)
+        ys, xs = np.mgrid[0:H, 0:W]
+        L = length[ys // ts, xs // ts]
+        nc = nc_all[off:off + H * W].reshape(H, W)
+        tf = dbg["T_final"][off:off + H * W].reshape(H, W)
+        e_fwd += int(np.where(tf < settings.T_min, nc, L).sum())
+        off += H * W
+    e_used = int(dbg["n_used"].astype(np.int64).sum()) if "n_used" in dbg else int(nc_all.sum())
     st = dict(N=int(params[0].shape[0]), V=len(cams), N_vis=int((dbg["tiles_touched"] > 0).sum()),
               M=int(inf["num_keys"]), P=int(inf["num_pixels"]), K=int(params[4].shape[1]),
               tiles=int(inf["num_tiles"]), sort_passes=int(inf["sort_passes"]), loaded_fwd=loaded_fwd,
               loaded_bwd=loaded_bwd, wave_hits=wave_hits,
-              E_bwd=int(dbg["n_contrib"].astype(np.int64).sum()))
+              E_bwd=int(nc_all.sum()), E_fwd=e_fwd, E_used=e_used)
     saved.free()
     return st
 
@@ -129,6 +173,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--autotune", type=int, default=1, help="pick (tile, batch) by timing first (1) or not (0)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); multi-GPU runs are "
@@ -146,7 +191,7 @@ def main():
     dev = torch.device("cuda", 0)
     params = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in w.gaussians.arrays()]
     targets = [(torch.from_numpy(tc).to(dev), torch.from_numpy(td).to(dev)) for tc, td in w.targets]
-    s = R.Settings(tile=args.tile, batch=args.batch)
+    s = R.Settings(tile=args.tile, batch=args.batch)  # replaced by the autotuner's choice unless --autotune 0
     grads = dict(means=torch.empty_like(params[0]), scales=torch.empty_like(params[1]),
                  quats=torch.empty_like(params[2]), opacities=torch.empty_like(params[3]),
                  sh=torch.empty_like(params[4]))
@@ -163,40 +208,36 @@ def main():
     head = [HEADLINE_VIEW]
     cam = w.cameras[HEADLINE_VIEW]
     px_head = cam.width * cam.height
+    if args.autotune:
+        os.environ.setdefault("GSR_AUTOTUNE_CACHE", os.path.join("/tmp", "gsr_bench_autotune.txt"))
+        s, tune_ms = R.autotune(*params, [cam], s, use_cache=False)
+        log(f"autotuned launch shape: tile {s.tile}, batch {s.batch} ({tune_ms:.3f} ms/step)")
     stats = step_stats(R, params, [cam], [targets[HEADLINE_VIEW]], s)
     log("headline stats", stats)
 
-    # headline: per-view fwd+loss+bwd, K timed steps
-    log(f"timing {args.steps} headline steps ({args.warmup} warm-up)")
-    ms = timed_steps(lambda: step(head), args.steps, args.warmup) * 1e3
-    # the same steps again with the per-kernel event timer on (kernel durations)
+    # headline, eager per-view calls (forward, loss, backward; one host read-back)
+    log(f"timing {args.steps} eager headline steps ({args.warmup} warm-up)")
+    ms_eager = timed_steps(lambda: step(head), args.steps, args.warmup) * 1e3
+    # the same steps with the per-kernel event timer on (kernel durations)
     ctx.set_timing(True)
     ctx.timing(reset=True)
     ms_timed = timed_steps(lambda: step(head), args.steps, 0) * 1e3
     ktimes = ctx.timing(reset=True)
     ctx.set_timing(False)
+    # headline, captured step replayed (the repeated iterations of one keyframe)
+    g1 = R.Graph(*params, [cam], [targets[HEADLINE_VIEW]], s, depth_weight=DEPTH_W)
+    log(f"timing {args.steps} graph-replayed headline steps")
+    ms = timed_steps(g1.launch, args.steps, args.warmup) * 1e3
+    g1.sync()
+    g1.free()
+
     per_kernel = {k: dict(ms_per_step=t / args.steps, launches_per_step=n / args.steps, avg_launch_us=1e3 * t / n)
                   for k, (t, n) in ktimes.items() if n > 0}
     dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_per_step"])
     alg = {k: kernel_bytes(k, stats) for k in per_kernel}
     step_bytes = sum(alg[k] * per_kernel[k]["launches_per_step"] for k in per_kernel)
     dk = per_kernel[dom]
-    achieved = alg[dom] / (dk["avg_launch_us"] * 1e-6) / 1e9 if alg[dom] else 0.0
-    traffic = None
-    prof = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(prof):
-        try:
-            tj = json.load(open(prof))
-            from paper_2408_12677_amd import build as B
-            import hashlib
-            src = hashlib.sha256(open(B.SOURCES[1], "rb").read()).hexdigest()[:16]
-            if tj.get("kernel") == dom and tj.get("kernels_sha") == src:
-                traffic = tj.get("bytes_per_launch")
-        except Exception:
-            traffic = None
-    roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    alg_bytes_per_launch=int(alg[dom]), avg_launch_us=round(dk["avg_launch_us"], 2))
+    roofline = kernel_roofline(dom, stats, alg[dom], dk["avg_launch_us"])
 
     out = {
         "metric": "fwd+bwd Mpixel/s at 500k Gaussians 640x480; batched vs per-view, HBM GB/s",
@@ -212,32 +253,40 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "500k-Gaussian quadtree-seeded room map (SH3), one 640x480 view: "
-                               "forward + L1(colour)+0.1 L1(depth) + backward",
+                               "forward + L1(colour)+0.1 L1(depth) + backward, captured step replayed",
                    "gaussians": stats["N"], "width": cam.width, "height": cam.height, "sh_degree": 3,
-                   "tile": s.tile, "batch": s.batch, "path": "per-view"},
+                   "tile": s.tile, "batch": s.batch, "path": "hipGraph, one view"},
+        "eager_per_view": {"ms_per_step": round(ms_eager, 4),
+                           "Mpixel_s": round(px_head / (ms_eager * 1e-3) / 1e6, 3)},
         "hbm": {"alg_bytes_per_step": int(step_bytes),
                 "alg_GBps": round(step_bytes / (ms * 1e-3) / 1e9, 1),
                 "frac_of_peak": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "roofline": roofline,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in per_kernel.items()},
         "ms_per_step_with_event_timer": round(ms_timed, 4),
-        "work": {k: stats[k] for k in ("N_vis", "M", "P", "tiles", "sort_passes", "E_bwd")},
+        "work": {k: stats[k] for k in ("N_vis", "M", "P", "tiles", "sort_passes", "E_bwd", "E_used")},
     }
 
     if not args.no_batched:
         allv = list(range(len(w.cameras)))
         px_all = sum(c.width * c.height for c in w.cameras)
         k2 = max(3, args.steps // 3)
-        log(f"timing batched (8 views, one call) and 8 sequential per-view steps, {k2} steps each")
-        ms_b = timed_steps(lambda: step(allv), k2, 2) * 1e3
+        log(f"timing the 8 views: one captured batched step vs 8 eager per-view steps, {k2} steps each")
+        gb = R.Graph(*params, w.cameras, targets, s, depth_weight=DEPTH_W)
+        ms_b = timed_steps(gb.launch, k2, 2) * 1e3
+        gb.sync()
+        binfo = gb.info()
+        gb.free()
 
         def seq():
             for i, v in enumerate(allv):
                 step([v], accumulate=i > 0)
         ms_s = timed_steps(seq, k2, 1) * 1e3
-        out["batched"] = {"views": len(allv), "pixels": px_all,
-                          "batched_ms": round(ms_b, 3), "batched_Mpixel_s": round(px_all / (ms_b * 1e-3) / 1e6, 2),
-                          "per_view_ms": round(ms_s, 3), "per_view_Mpixel_s": round(px_all / (ms_s * 1e-3) / 1e6, 2),
+        out["batched"] = {"views": len(allv), "pixels": px_all, "keys": binfo["num_keys"],
+                          "batched_graph_ms": round(ms_b, 3),
+                          "batched_graph_Mpixel_s": round(px_all / (ms_b * 1e-3) / 1e6, 2),
+                          "per_view_eager_ms": round(ms_s, 3),
+                          "per_view_eager_Mpixel_s": round(px_all / (ms_s * 1e-3) / 1e6, 2),
                           "steps": k2}
 
     if not args.no_cpu_baseline:

@@ -163,6 +163,7 @@ typedef struct {
   float* conic;       /* [V*N,3] inverse projected covariance (A, B, C) */
   float* color;       /* [V*N,3] SH colour */
   int32_t* rect;      /* [V*N,4] tile rectangle (tx0, tx1, ty0, ty1), inclusive */
+  uint32_t* n_used;   /* [num_pixels] contributors (list entries that passed the skip rule) */
 } gsr_debug;
 
 /* Library version of this header. */
@@ -221,6 +222,41 @@ gsr_status gsr_saved_free(gsr_saved* saved);
 
 /* Copy intermediate state to host memory (synchronises the stream). */
 gsr_status gsr_debug_export(gsr_ctx* ctx, const gsr_saved* saved, const gsr_debug* out);
+
+/* ---- Batched keyframes: one captured step -------------------------------------------
+ * Capture forward + L1 loss + backward of V views (uneven resolutions allowed) into a
+ * hipGraph: one concatenated tile space, one sort, persistent compositing kernels that
+ * take tiles longest-list-first from a device work queue, all counts kept on the device
+ * (keyframe replay and global optimisation, Sec. III-B-3).  Every pointer argument is
+ * bound at capture: a launch re-runs the step on the current contents of the same
+ * buffers (parameters, targets, images, gradients).  Buffers are sized from one eager
+ * forward of the given inputs times (1 + headroom).  A launch whose key or visible-record
+ * count exceeds those capacities sets a device flag; it is read back asynchronously and
+ * reported as GSR_ECAPACITY by the next gsr_graph_launch that finds the earlier step
+ * complete, or by gsr_graph_sync.  Gradients are overwritten on every launch. */
+gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
+                            const gsr_settings* s, const gsr_view_out* outs, const gsr_target* targets,
+                            float depth_weight, float* const* grad_color, float* const* grad_depth,
+                            const gsr_gaussian_grads* grads, float* loss_dev, float headroom, gsr_graph** out);
+/* Enqueue one step on the context's stream (asynchronous). */
+gsr_status gsr_graph_launch(gsr_graph* gr);
+/* Wait for the last launch; GSR_ECAPACITY if any launch overflowed. */
+gsr_status gsr_graph_sync(gsr_graph* gr);
+/* Sizes measured at creation, and the key / visible-record capacities. */
+gsr_status gsr_graph_info(const gsr_graph* gr, gsr_info* info, int64_t* cap_keys, int64_t* cap_visible);
+gsr_status gsr_graph_free(gsr_graph* gr);
+
+/* ---- Launch-shape autotuner -----------------------------------------------------------
+ * Time forward + backward at every (tile, batch) in {8,16,32} x {128,256} and write the
+ * fastest into s->tile / s->batch (other fields are kept).  Results are cached in the
+ * text file named by $GSR_AUTOTUNE_CACHE (default ~/.cache/gsr_autotune.txt), keyed by
+ * architecture, CU count, log2 of the total pixel count and of N, SH degree and V; a
+ * cached entry is used without timing unless GSR_AUTOTUNE_NO_CACHE is set.  The forward
+ * images do not depend on the choice (the extent keeps every splat value >= alpha_min
+ * inside its tile rectangle).  best_ms (may be NULL) receives the step time. */
+#define GSR_AUTOTUNE_NO_CACHE 1u
+gsr_status gsr_autotune(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
+                        gsr_settings* s, uint32_t flags, float* best_ms);
 
 /* Message of the last failing call on ctx ("" if none); ctx may be NULL for
  * failures that had no context. */

@@ -66,7 +66,8 @@ class Timing(ctypes.Structure):
 
 class Debug(ctypes.Structure):
     _fields_ = [("keys", P), ("values", P), ("ranges", P), ("T_final", P), ("n_contrib", P),
-                ("tiles_touched", P), ("mu", P), ("depth", P), ("conic", P), ("color", P), ("rect", P)]
+                ("tiles_touched", P), ("mu", P), ("depth", P), ("conic", P), ("color", P), ("rect", P),
+                ("n_used", P)]
 
 
 # every symbol include/gsr.h declares, with its ctypes signature
@@ -86,7 +87,15 @@ SIGNATURES = {
     "gsr_saved_free": (ctypes.c_int, [P]),
     "gsr_debug_export": (ctypes.c_int, [P, P, P]),
     "gsr_last_error": (ctypes.c_char_p, [P]),
+    "gsr_graph_create": (ctypes.c_int, [P, P, P, ctypes.c_int32, P, P, P, ctypes.c_float, P, P, P, P,
+                                        ctypes.c_float, P]),
+    "gsr_graph_launch": (ctypes.c_int, [P]),
+    "gsr_graph_sync": (ctypes.c_int, [P]),
+    "gsr_graph_info": (ctypes.c_int, [P, P, P, P]),
+    "gsr_graph_free": (ctypes.c_int, [P]),
+    "gsr_autotune": (ctypes.c_int, [P, P, P, ctypes.c_int32, P, ctypes.c_uint32, P]),
 }
+AUTOTUNE_NO_CACHE = 1
 
 _lib = None
 

@@ -1,12 +1,15 @@
 // Host side of the C ABI declared in gsr.h: argument validation, scratch memory from the
-// device's stream-ordered pool, and the launch sequences of the forward, loss and backward
-// passes.  All device work goes to the context's stream.
+// device's stream-ordered pool, the launch sequence of one optimisation step (forward,
+// loss, backward), its capture into a hipGraph, and the launch-shape autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -22,22 +25,8 @@ struct gsr_ctx {
   Timer timer;
 };
 
-namespace {
-const char* const kKernelNames[K_COUNT] = {
-    "project", "scan",   "compact", "sorted_counts", "duplicate", "radix_hist", "radix_rowscan", "radix_scatter",
-    "ranges",  "fill",   "blend_fwd", "loss_l1",     "blend_bwd", "project_bwd"};
-
-// Wraps one launch (or launch sequence) in the context's optional event timer.
-template <class F>
-hipError_t timed(gsr_ctx* ctx, int k, F&& f) {
-  ctx->timer.stream = ctx->stream;
-  ctx->timer.begin(k);
-  hipError_t e = f();
-  ctx->timer.end(k);
-  return e;
-}
-}  // namespace
-
+// All device state of one step.  Eager forwards size the sort buffers exactly and drop
+// the temporaries afterwards; a graph keeps every buffer at its capacity.
 struct gsr_saved {
   gsr_ctx* ctx = nullptr;
   int V = 0;
@@ -51,19 +40,46 @@ struct gsr_saved {
   int nblk = 0;
   uint2* blocksums = nullptr;
   unsigned long long* d_total = nullptr;  // [0] pairs M, [1] visible records, [2] pairs written
-  int64_t M = 0;
-  int64_t n_vis = 0;
-  uint32_t* tiles = nullptr;  // sorted tile id of every pair
-  uint32_t* vals = nullptr;   // sorted record id of every pair
+  int64_t M = 0, n_vis = 0;               // measured sizes (eager) or sizes at creation (graph)
+  int64_t cap_M = 0, cap_vis = 0;         // buffer capacities
+  // sort buffers
+  uint32_t *dk = nullptr, *dv = nullptr, *dk2 = nullptr, *dv2 = nullptr;
+  uint32_t *tk = nullptr, *tv = nullptr, *tk2 = nullptr, *tv2 = nullptr;
+  uint32_t *hist = nullptr, *dtot = nullptr, *bs2 = nullptr;
+  uint32_t* tiles = nullptr;  // sorted tile id of every pair (points at tk or tk2)
+  uint32_t* vals = nullptr;   // sorted record id of every pair (tv or tv2)
   uint2* ranges = nullptr;
+  uint32_t* order = nullptr;
+  uint32_t* bucket_of = nullptr;
+  uint32_t* ctrl = nullptr;
   float* T_final = nullptr;
   uint32_t* n_contrib = nullptr;
+  uint32_t* n_used = nullptr;  // contributors per pixel (statistics)
+  float* grad2d = nullptr;  // graph only (eager backward allocates its own)
   int64_t total_pix = 0;
   int sort_passes = 0;
-  std::vector<void*> blocks;  // every allocation, released on free
+  std::vector<void*> blocks;  // persistent allocations, released on free
+  std::vector<void*> temps;   // eager-forward temporaries
+};
+
+struct gsr_graph {
+  gsr_ctx* ctx = nullptr;
+  gsr_saved* sv = nullptr;
+  hipStream_t capture = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  uint32_t* h_flag = nullptr;  // pinned copy of the overflow word, written by the graph
+  bool launched = false;
+  bool overflowed = false;
 };
 
 namespace {
+
+const char* const kKernelNames[K_COUNT] = {"project",    "scan",      "compact",   "sorted_counts", "duplicate",
+                                           "radix_hist", "radix_rowscan", "radix_scatter", "ranges",
+                                           "tile_order", "fill",      "blend_fwd", "loss_l1",   "blend_bwd",
+                                           "project_bwd"};
 
 thread_local std::string g_noctx_err;
 
@@ -81,10 +97,20 @@ gsr_status fail(gsr_ctx* ctx, gsr_status st, const std::string& msg) {
     if (e_ != hipSuccess) return fail(ctx, GSR_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
   } while (0)
 
-gsr_status dev_alloc(gsr_ctx* ctx, void** p, size_t bytes) {
+// Wraps one launch (or launch sequence) in the context's optional event timer.
+template <class F>
+hipError_t timed(gsr_ctx* ctx, hipStream_t s, int k, F&& f) {
+  ctx->timer.stream = s;
+  ctx->timer.begin(k);
+  hipError_t e = f();
+  ctx->timer.end(k);
+  return e;
+}
+
+gsr_status dev_alloc(gsr_ctx* ctx, hipStream_t s, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) return GSR_OK;
-  hipError_t e = hipMallocAsync(p, bytes, ctx->stream);
+  hipError_t e = hipMallocAsync(p, bytes, s);
   if (e != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
@@ -95,19 +121,24 @@ gsr_status dev_alloc(gsr_ctx* ctx, void** p, size_t bytes) {
 }
 
 template <class T>
-gsr_status saved_alloc(gsr_saved* sv, T** p, size_t count) {
+gsr_status alloc_in(gsr_saved* sv, std::vector<void*>& list, T** p, size_t count) {
   void* q = nullptr;
-  gsr_status st = dev_alloc(sv->ctx, &q, count * sizeof(T));
+  gsr_status st = dev_alloc(sv->ctx, sv->ctx->stream, &q, count * sizeof(T));
   if (st != GSR_OK) return st;
-  if (q) sv->blocks.push_back(q);
+  if (q) list.push_back(q);
   *p = static_cast<T*>(q);
   return GSR_OK;
 }
 
+void free_list(gsr_saved* sv, std::vector<void*>& list) {
+  for (void* p : list) (void)hipFreeAsync(p, sv->ctx->stream);
+  list.clear();
+}
+
 void release(gsr_saved* sv) {
   if (!sv) return;
-  for (void* p : sv->blocks) (void)hipFreeAsync(p, sv->ctx->stream);
-  sv->blocks.clear();
+  free_list(sv, sv->temps);
+  free_list(sv, sv->blocks);
   delete sv;
 }
 
@@ -144,10 +175,269 @@ gsr_status check_camera(gsr_ctx* ctx, const gsr_camera& c, int v) {
   return GSR_OK;
 }
 
+gsr_status check_forward_args(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
+                              const gsr_settings* s, const gsr_view_out* outs) {
+  if (V < 1 || V > GSR_MAX_VIEWS) return fail(ctx, GSR_EINVAL, "V must be 1..16");
+  if (!cams || !outs) return fail(ctx, GSR_EINVAL, "cams/outs is NULL");
+  gsr_status st;
+  if ((st = check_settings(ctx, s)) != GSR_OK) return st;
+  if ((st = check_gaussians(ctx, g, V)) != GSR_OK) return st;
+  for (int v = 0; v < V; ++v) {
+    if ((st = check_camera(ctx, cams[v], v)) != GSR_OK) return st;
+    if (!outs[v].color) return fail(ctx, GSR_EINVAL, "outs[v].color is NULL");
+  }
+  return GSR_OK;
+}
+
 int bits_for(uint64_t maxval) {
   int b = 0;
   while (b < 64 && (maxval >> b) != 0) ++b;
   return b;
+}
+
+// A saved state with its view table and per-(view, Gaussian) buffers.
+gsr_status make_saved(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
+                      const gsr_settings* s, const gsr_view_out* outs, gsr_saved** out) {
+  gsr_saved* sv = new gsr_saved;
+  sv->ctx = ctx;
+  sv->V = V;
+  sv->N = g->n;
+  sv->deg = g->sh_degree;
+  sv->s = *s;
+  sv->g = GaussDev{g->means, g->scales, g->quats, g->opacities, g->sh, g->n};
+  sv->ru = Rules{s->extent_k, s->lowpass, s->alpha_min, s->alpha_max, s->T_min, s->guard, {s->bg[0], s->bg[1], s->bg[2]}};
+  ViewTable& vt = sv->vt;
+  std::memset(&vt, 0, sizeof(vt));
+  vt.nviews = V;
+  int64_t tiles = 0, pix = 0;
+  for (int v = 0; v < V; ++v) {
+    const gsr_camera& c = cams[v];
+    ViewDev& d = vt.v[v];
+    std::memcpy(d.R, c.R, sizeof d.R);
+    std::memcpy(d.t, c.t, sizeof d.t);
+    d.fx = c.fx;
+    d.fy = c.fy;
+    d.cx = c.cx;
+    d.cy = c.cy;
+    d.znear = c.znear;
+    for (int i = 0; i < 3; ++i)  // camera centre -R^T t
+      d.cam_pos[i] = float(-(double(c.R[0 * 3 + i]) * c.t[0] + double(c.R[1 * 3 + i]) * c.t[1] +
+                             double(c.R[2 * 3 + i]) * c.t[2]));
+    d.W = c.width;
+    d.H = c.height;
+    d.tiles_x = (c.width + s->tile - 1) / s->tile;
+    d.tiles_y = (c.height + s->tile - 1) / s->tile;
+    d.tile_off = int32_t(tiles);
+    d.pix_off = pix;
+    d.color = outs[v].color;
+    d.depth = outs[v].depth;
+    d.alpha = outs[v].alpha;
+    tiles += int64_t(d.tiles_x) * d.tiles_y;
+    pix += int64_t(c.width) * c.height;
+  }
+  vt.total_tiles = int32_t(tiles);
+  sv->total_pix = pix;
+  const int64_t VN = int64_t(V) * g->n;
+  sv->nblk = int((g->n + kProjThreads - 1) / kProjThreads);
+  std::vector<void*>& B = sv->blocks;
+  gsr_status st = GSR_OK;
+  if ((st = alloc_in(sv, B, &sv->rec.r0, VN)) != GSR_OK || (st = alloc_in(sv, B, &sv->rec.r1, VN)) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->rec.rgb, VN)) != GSR_OK || (st = alloc_in(sv, B, &sv->rec.rect, VN)) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->rec.counts, VN)) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->blocksums, size_t(V) * sv->nblk + 1)) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->d_total, 4)) != GSR_OK || (st = alloc_in(sv, B, &sv->ranges, size_t(tiles))) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->order, size_t(tiles))) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->bucket_of, size_t(tiles))) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->ctrl, kCtrlWords)) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->T_final, size_t(pix))) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->n_contrib, size_t(pix))) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->n_used, size_t(pix))) != GSR_OK) {
+    release(sv);
+    return st;
+  }
+  *out = sv;
+  return GSR_OK;
+}
+
+// Sort buffers for capacities (cap_vis, cap_M).  Eager forwards put all but the final
+// pair buffers in `temps`.
+gsr_status alloc_sort(gsr_saved* sv, int64_t cap_vis, int64_t cap_M, bool persistent) {
+  sv->cap_vis = cap_vis;
+  sv->cap_M = cap_M;
+  std::vector<void*>& T = persistent ? sv->blocks : sv->temps;
+  const int64_t sort_cap = std::max(cap_vis, cap_M);
+  const int64_t nb_sort = (sort_cap + kSortTile - 1) / kSortTile;
+  const int64_t nb_vis = (cap_vis + kProjThreads - 1) / kProjThreads;
+  gsr_status st = GSR_OK;
+  if ((st = alloc_in(sv, T, &sv->dk, cap_vis)) != GSR_OK || (st = alloc_in(sv, T, &sv->dv, cap_vis)) != GSR_OK ||
+      (st = alloc_in(sv, T, &sv->dk2, cap_vis)) != GSR_OK || (st = alloc_in(sv, T, &sv->dv2, cap_vis)) != GSR_OK ||
+      (st = alloc_in(sv, sv->blocks, &sv->tk, cap_M)) != GSR_OK ||
+      (st = alloc_in(sv, sv->blocks, &sv->tv, cap_M)) != GSR_OK ||
+      (st = alloc_in(sv, T, &sv->tk2, cap_M)) != GSR_OK || (st = alloc_in(sv, T, &sv->tv2, cap_M)) != GSR_OK ||
+      (st = alloc_in(sv, T, &sv->hist, size_t(nb_sort) * 256)) != GSR_OK ||
+      (st = alloc_in(sv, T, &sv->dtot, 256)) != GSR_OK || (st = alloc_in(sv, T, &sv->bs2, size_t(nb_vis) + 1)) != GSR_OK)
+    return st;
+  return GSR_OK;
+}
+
+// Phase A of a forward: clear the control words, project, scan the block sums.
+hipError_t enqueue_project(gsr_saved* sv, hipStream_t s, bool timing) {
+  gsr_ctx* ctx = sv->ctx;
+  auto T = [&](int k, auto f) { return timing ? timed(ctx, s, k, f) : f(); };
+  hipError_t e = T(K_FILL, [&] { return launch_fill_u32(sv->ctrl, 0u, kCtrlWords, s); });
+  if (e != hipSuccess || sv->N == 0) return e;
+  e = T(K_PROJECT, [&] {
+    return launch_project(sv->deg, sv->g, sv->vt, sv->ru, sv->s.tile, sv->rec, sv->blocksums, sv->nblk, s);
+  });
+  if (e == hipSuccess)
+    e = T(K_SCAN, [&] { return launch_scan_pairs(sv->blocksums, sv->V * sv->nblk, sv->d_total, s); });
+  return e;
+}
+
+// Phase B: the sort (depth digits on the visible records, duplication in depth order,
+// tile digits on the pairs), tile ranges, the tile queue and the forward compositing.
+hipError_t enqueue_sort_blend(gsr_saved* sv, hipStream_t s, bool timing) {
+  gsr_ctx* ctx = sv->ctx;
+  Timer* tm = (timing && ctx->timer.on) ? &ctx->timer : nullptr;
+  ctx->timer.stream = s;
+  auto T = [&](int k, auto f) { return timing ? timed(ctx, s, k, f) : f(); };
+  uint32_t* ovf = sv->ctrl + kOverflow;
+  hipError_t e = hipSuccess;
+  sv->tiles = sv->tk;
+  sv->vals = sv->tv;
+  sv->sort_passes = 0;
+  if (sv->cap_M > 0 && sv->cap_vis > 0) {
+    const int tile_bits = bits_for(uint64_t(sv->vt.total_tiles > 0 ? sv->vt.total_tiles - 1 : 0));
+    bool alt1 = false, alt2 = false;
+    int p1 = 0, p2 = 0;
+    e = T(K_COMPACT, [&] {
+      return launch_compact(sv->N, sv->V, sv->rec, sv->blocksums, sv->nblk, sv->dk, sv->dv, sv->cap_vis, ovf, s);
+    });
+    if (e == hipSuccess)
+      e = launch_radix_sort(sv->dk, sv->dv, sv->dk2, sv->dv2, sv->hist, sv->dtot, sv->d_total + 1, sv->cap_vis, ovf,
+                            32, &alt1, &p1, s, tm);
+    if (e == hipSuccess)
+      e = launch_duplicate(sv->vt, sv->N, sv->rec, alt1 ? sv->dv2 : sv->dv, sv->d_total + 1, sv->cap_vis, sv->bs2,
+                           sv->d_total + 2, sv->tk, sv->tv, sv->cap_M, ovf, s, tm);
+    if (e == hipSuccess)
+      e = launch_radix_sort(sv->tk, sv->tv, sv->tk2, sv->tv2, sv->hist, sv->dtot, sv->d_total, sv->cap_M, ovf,
+                            tile_bits, &alt2, &p2, s, tm);
+    if (alt2) {
+      sv->tiles = sv->tk2;
+      sv->vals = sv->tv2;
+    }
+    sv->sort_passes = p1 + p2;
+  }
+  if (e == hipSuccess)
+    e = T(K_RANGES, [&] {
+      return launch_ranges(sv->tiles, sv->d_total, sv->cap_M, ovf, sv->ranges, sv->vt.total_tiles, s);
+    });
+  if (e == hipSuccess)
+    e = T(K_TILE_ORDER, [&] {
+      return launch_tile_order(sv->ranges, sv->vt.total_tiles, sv->bucket_of, sv->order, sv->ctrl, s);
+    });
+  if (e == hipSuccess)
+    e = T(K_BLEND_FWD, [&] {
+      return launch_blend_fwd(sv->s.tile, sv->s.batch, sv->vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final,
+                              sv->n_contrib, sv->n_used, TileQueue{sv->order, sv->ctrl}, s);
+    });
+  return e;
+}
+
+// Backward launches for the view table `vt` (whose g_* pointers are set).
+hipError_t enqueue_backward(gsr_saved* sv, const ViewTable& vt, float* grad2d, const GradOut& go, hipStream_t s,
+                            bool timing) {
+  gsr_ctx* ctx = sv->ctx;
+  auto T = [&](int k, auto f) { return timing ? timed(ctx, s, k, f) : f(); };
+  const int64_t VN = int64_t(sv->V) * sv->N;
+  hipError_t e = T(K_FILL, [&] {
+    hipError_t r = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, VN * kGrad2D, s);
+    if (r == hipSuccess) r = launch_fill_u32(sv->ctrl + kHeadBwd, 0u, 1, s);
+    return r;
+  });
+  if (e == hipSuccess)
+    e = T(K_BLEND_BWD, [&] {
+      return launch_blend_bwd(sv->s.tile, sv->s.batch, vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final,
+                              sv->n_contrib, grad2d, TileQueue{sv->order, sv->ctrl}, s);
+    });
+  if (e == hipSuccess)
+    e = T(K_PROJECT_BWD, [&] { return launch_project_bwd(sv->deg, sv->g, vt, sv->ru, sv->rec, grad2d, go, s); });
+  return e;
+}
+
+// A full eager forward: phase A, one read-back of (M, visible), exact sort buffers, phase B.
+gsr_status forward_eager(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
+                         const gsr_settings* s, const gsr_view_out* outs, gsr_saved** out) {
+  gsr_saved* sv = nullptr;
+  gsr_status st = make_saved(ctx, g, cams, V, s, outs, &sv);
+  if (st != GSR_OK) return st;
+  hipStream_t strm = ctx->stream;
+  hipError_t e = enqueue_project(sv, strm, true);
+  int64_t M = 0, NV = 0;
+  if (e == hipSuccess && g->n > 0) {
+    e = hipMemcpyAsync(ctx->h_total, sv->d_total, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, strm);
+    if (e == hipSuccess) e = hipStreamSynchronize(strm);
+    M = int64_t(ctx->h_total[0]);
+    NV = int64_t(ctx->h_total[1]);
+  }
+  if (e != hipSuccess) {
+    release(sv);
+    return fail(ctx, GSR_EDEVICE, std::string("forward (projection) failed: ") + hipGetErrorString(e));
+  }
+  if (M >= (int64_t(1) << 32)) {
+    release(sv);
+    return fail(ctx, GSR_ECAPACITY, "more than 2^32 duplicated keys");
+  }
+  sv->M = M;
+  sv->n_vis = NV;
+  if ((st = alloc_sort(sv, NV, M, false)) != GSR_OK) {
+    release(sv);
+    return st;
+  }
+  e = enqueue_sort_blend(sv, strm, true);
+  if (e != hipSuccess) {
+    release(sv);
+    return fail(ctx, GSR_EDEVICE, std::string("forward (sort/blend) failed: ") + hipGetErrorString(e));
+  }
+  // keep the final sorted pair buffers, return every temporary to the pool
+  if (sv->tiles == sv->tk2) {
+    std::replace(sv->temps.begin(), sv->temps.end(), static_cast<void*>(sv->tk2), static_cast<void*>(sv->tk));
+    std::replace(sv->temps.begin(), sv->temps.end(), static_cast<void*>(sv->tv2), static_cast<void*>(sv->tv));
+    std::replace(sv->blocks.begin(), sv->blocks.end(), static_cast<void*>(sv->tk), static_cast<void*>(sv->tk2));
+    std::replace(sv->blocks.begin(), sv->blocks.end(), static_cast<void*>(sv->tv), static_cast<void*>(sv->tv2));
+  }
+  free_list(sv, sv->temps);
+  *out = sv;
+  return GSR_OK;
+}
+
+ViewTable with_grads(const gsr_saved* sv, const gsr_view_grad* grads) {
+  ViewTable vt = sv->vt;
+  for (int v = 0; v < vt.nviews; ++v) {
+    vt.v[v].g_color = grads[v].color;
+    vt.v[v].g_depth = grads[v].depth;
+    vt.v[v].g_alpha = grads[v].alpha;
+  }
+  return vt;
+}
+
+gsr_status loss_table(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_out* outs, const gsr_target* targets,
+                      float depth_weight, float* const* gcol, float* const* gdep, ViewTable* vt) {
+  if (!(depth_weight >= 0.f)) return fail(ctx, GSR_EINVAL, "depth_weight must be >= 0");
+  *vt = saved->vt;
+  for (int v = 0; v < vt->nviews; ++v) {
+    if (!outs[v].color || !targets[v].color || !gcol[v])
+      return fail(ctx, GSR_EINVAL, "colour image, target or gradient pointer is NULL");
+    if (targets[v].depth && (!outs[v].depth || !gdep || !gdep[v]))
+      return fail(ctx, GSR_EINVAL, "depth target given without rendered depth / gradient buffer");
+    vt->v[v].color = outs[v].color;
+    vt->v[v].depth = outs[v].depth;
+    vt->v[v].t_color = targets[v].color;
+    vt->v[v].t_depth = targets[v].depth;
+    vt->v[v].lg_color = gcol[v];
+    vt->v[v].lg_depth = gdep ? gdep[v] : nullptr;
+  }
+  return GSR_OK;
 }
 
 }  // namespace
@@ -245,187 +535,11 @@ gsr_status gsr_forward(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* c
                        const gsr_settings* s, const gsr_view_out* outs, gsr_saved** saved) {
   if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
   if (saved) *saved = nullptr;
-  if (V < 1 || V > GSR_MAX_VIEWS) return fail(ctx, GSR_EINVAL, "V must be 1..16");
-  if (!cams || !outs) return fail(ctx, GSR_EINVAL, "cams/outs is NULL");
-  gsr_status st;
-  if ((st = check_settings(ctx, s)) != GSR_OK) return st;
-  if ((st = check_gaussians(ctx, g, V)) != GSR_OK) return st;
-  for (int v = 0; v < V; ++v) {
-    if ((st = check_camera(ctx, cams[v], v)) != GSR_OK) return st;
-    if (!outs[v].color) return fail(ctx, GSR_EINVAL, "outs[v].color is NULL");
-  }
+  gsr_status st = check_forward_args(ctx, g, cams, V, s, outs);
+  if (st != GSR_OK) return st;
   ctx->err.clear();
-
-  gsr_saved* sv = new gsr_saved;
-  sv->ctx = ctx;
-  sv->V = V;
-  sv->N = g->n;
-  sv->deg = g->sh_degree;
-  sv->s = *s;
-  sv->g = GaussDev{g->means, g->scales, g->quats, g->opacities, g->sh, g->n};
-  sv->ru = Rules{s->extent_k, s->lowpass,  s->alpha_min, s->alpha_max,
-                 s->T_min,    s->guard,    {s->bg[0], s->bg[1], s->bg[2]}};
-  ViewTable& vt = sv->vt;
-  std::memset(&vt, 0, sizeof(vt));
-  vt.nviews = V;
-  int64_t tiles = 0, pix = 0;
-  for (int v = 0; v < V; ++v) {
-    const gsr_camera& c = cams[v];
-    ViewDev& d = vt.v[v];
-    std::memcpy(d.R, c.R, sizeof d.R);
-    std::memcpy(d.t, c.t, sizeof d.t);
-    d.fx = c.fx;
-    d.fy = c.fy;
-    d.cx = c.cx;
-    d.cy = c.cy;
-    d.znear = c.znear;
-    for (int i = 0; i < 3; ++i)  // camera centre -R^T t
-      d.cam_pos[i] = float(-(double(c.R[0 * 3 + i]) * c.t[0] + double(c.R[1 * 3 + i]) * c.t[1] +
-                             double(c.R[2 * 3 + i]) * c.t[2]));
-    d.W = c.width;
-    d.H = c.height;
-    d.tiles_x = (c.width + s->tile - 1) / s->tile;
-    d.tiles_y = (c.height + s->tile - 1) / s->tile;
-    d.tile_off = int32_t(tiles);
-    d.pix_off = pix;
-    d.color = outs[v].color;
-    d.depth = outs[v].depth;
-    d.alpha = outs[v].alpha;
-    tiles += int64_t(d.tiles_x) * d.tiles_y;
-    pix += int64_t(c.width) * c.height;
-  }
-  vt.total_tiles = int32_t(tiles);
-  sv->total_pix = pix;
-  const int64_t VN = int64_t(V) * g->n;
-  sv->nblk = int((g->n + kProjThreads - 1) / kProjThreads);
-  hipStream_t st_ = ctx->stream;
-
-#define TRY(x)             \
-  do {                     \
-    gsr_status t_ = (x);   \
-    if (t_ != GSR_OK) {    \
-      release(sv);         \
-      return t_;           \
-    }                      \
-  } while (0)
-#define TRYH(x)                                                                                    \
-  do {                                                                                             \
-    hipError_t e_ = (x);                                                                           \
-    if (e_ != hipSuccess) {                                                                        \
-      release(sv);                                                                                 \
-      return fail(ctx, GSR_EDEVICE, std::string(#x ": ") + hipGetErrorString(e_));                 \
-    }                                                                                              \
-  } while (0)
-
-  TRY(saved_alloc(sv, &sv->rec.r0, VN));
-  TRY(saved_alloc(sv, &sv->rec.r1, VN));
-  TRY(saved_alloc(sv, &sv->rec.rgb, VN));
-  TRY(saved_alloc(sv, &sv->rec.rect, VN));
-  TRY(saved_alloc(sv, &sv->rec.counts, VN));
-  TRY(saved_alloc(sv, &sv->blocksums, size_t(V) * sv->nblk + 1));
-  TRY(saved_alloc(sv, &sv->d_total, 4));
-  TRY(saved_alloc(sv, &sv->ranges, size_t(tiles)));
-  TRY(saved_alloc(sv, &sv->T_final, size_t(pix)));
-  TRY(saved_alloc(sv, &sv->n_contrib, size_t(pix)));
-
-  int64_t M = 0, NV = 0;
-  if (g->n > 0) {
-    TRYH(timed(ctx, K_PROJECT, [&] {
-      return launch_project(sv->deg, sv->g, vt, sv->ru, s->tile, sv->rec, sv->blocksums, sv->nblk, st_);
-    }));
-    TRYH(timed(ctx, K_SCAN, [&] { return launch_scan_pairs(sv->blocksums, V * sv->nblk, sv->d_total, st_); }));
-    TRYH(hipMemcpyAsync(ctx->h_total, sv->d_total, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st_));
-    TRYH(hipStreamSynchronize(st_));
-    M = int64_t(ctx->h_total[0]);
-    NV = int64_t(ctx->h_total[1]);
-    if (M >= (int64_t(1) << 32)) {
-      release(sv);
-      return fail(ctx, GSR_ECAPACITY, "more than 2^32 duplicated keys");
-    }
-  }
-  sv->M = M;
-  sv->n_vis = NV;
-  if (M > 0) {
-    // Stable LSD sort of the (tile << 32 | depth) keys: the depth digits on the NV records,
-    // then duplication in depth order, then the tile digits on the M pairs.
-    uint32_t *tk = nullptr, *tv = nullptr;
-    TRY(saved_alloc(sv, &tk, size_t(M)));
-    TRY(saved_alloc(sv, &tv, size_t(M)));
-    const int tile_bits = bits_for(uint64_t(tiles > 0 ? tiles - 1 : 0));
-    const int64_t sort_cap = std::max(NV, M);
-    const int nb_sort = int((sort_cap + kSortTile - 1) / kSortTile);
-    const int nb_vis = int((NV + kProjThreads - 1) / kProjThreads);
-    std::vector<void*> tmp;
-    auto tmp_alloc = [&](void** p, size_t bytes) -> gsr_status {
-      gsr_status r = dev_alloc(ctx, p, bytes);
-      if (r == GSR_OK && *p) tmp.push_back(*p);
-      return r;
-    };
-    auto free_tmp = [&]() {
-      for (void* p : tmp) (void)hipFreeAsync(p, st_);
-      tmp.clear();
-    };
-    void *dk = nullptr, *dv = nullptr, *dk2 = nullptr, *dv2 = nullptr, *tk2 = nullptr, *tv2 = nullptr;
-    void *hist = nullptr, *dtot = nullptr, *bs2 = nullptr, *ovf = nullptr;
-    gsr_status a = GSR_OK;
-    if ((a = tmp_alloc(&dk, size_t(NV) * 4)) != GSR_OK || (a = tmp_alloc(&dv, size_t(NV) * 4)) != GSR_OK ||
-        (a = tmp_alloc(&dk2, size_t(NV) * 4)) != GSR_OK || (a = tmp_alloc(&dv2, size_t(NV) * 4)) != GSR_OK ||
-        (a = tmp_alloc(&tk2, size_t(M) * 4)) != GSR_OK || (a = tmp_alloc(&tv2, size_t(M) * 4)) != GSR_OK ||
-        (a = tmp_alloc(&hist, size_t(nb_sort) * 256 * 4)) != GSR_OK ||
-        (a = tmp_alloc(&dtot, 256 * 4)) != GSR_OK || (a = tmp_alloc(&bs2, size_t(nb_vis + 1) * 4)) != GSR_OK ||
-        (a = tmp_alloc(&ovf, 4)) != GSR_OK) {
-      free_tmp();
-      release(sv);
-      return a;
-    }
-    Timer* tm = ctx->timer.on ? &ctx->timer : nullptr;
-    ctx->timer.stream = st_;
-    bool alt1 = false, alt2 = false;
-    int p1 = 0, p2 = 0;
-    hipError_t e = timed(ctx, K_FILL, [&] { return launch_fill_u32(static_cast<uint32_t*>(ovf), 0u, 1, st_); });
-    if (e == hipSuccess)
-      e = timed(ctx, K_COMPACT, [&] {
-        return launch_compact(g->n, V, sv->rec, sv->blocksums, sv->nblk, static_cast<uint32_t*>(dk),
-                              static_cast<uint32_t*>(dv), st_);
-      });
-    if (e == hipSuccess)
-      e = launch_radix_sort(static_cast<uint32_t*>(dk), static_cast<uint32_t*>(dv), static_cast<uint32_t*>(dk2),
-                            static_cast<uint32_t*>(dv2), static_cast<uint32_t*>(hist), static_cast<uint32_t*>(dtot),
-                            sv->d_total + 1, NV, 32, &alt1, &p1, st_, tm);
-    const uint32_t* dsorted = static_cast<const uint32_t*>(alt1 ? dv2 : dv);
-    if (e == hipSuccess)
-      e = launch_duplicate(vt, g->n, sv->rec, dsorted, sv->d_total + 1, NV, static_cast<uint32_t*>(bs2),
-                           sv->d_total + 2, tk, tv, M, static_cast<uint32_t*>(ovf), st_, tm);
-    if (e == hipSuccess)
-      e = launch_radix_sort(tk, tv, static_cast<uint32_t*>(tk2), static_cast<uint32_t*>(tv2),
-                            static_cast<uint32_t*>(hist), static_cast<uint32_t*>(dtot), sv->d_total, M, tile_bits,
-                            &alt2, &p2, st_, tm);
-    if (e != hipSuccess) {
-      free_tmp();
-      release(sv);
-      return fail(ctx, GSR_EDEVICE, std::string("sort launch failed: ") + hipGetErrorString(e));
-    }
-    if (alt2) {  // the sorted pairs ended in the second buffers: keep those, recycle the first
-      std::replace(sv->blocks.begin(), sv->blocks.end(), static_cast<void*>(tk), tk2);
-      std::replace(sv->blocks.begin(), sv->blocks.end(), static_cast<void*>(tv), tv2);
-      std::replace(tmp.begin(), tmp.end(), tk2, static_cast<void*>(tk));
-      std::replace(tmp.begin(), tmp.end(), tv2, static_cast<void*>(tv));
-      tk = static_cast<uint32_t*>(tk2);
-      tv = static_cast<uint32_t*>(tv2);
-    }
-    sv->tiles = tk;
-    sv->vals = tv;
-    sv->sort_passes = p1 + p2;
-    free_tmp();
-  }
-  TRYH(timed(ctx, K_RANGES,
-             [&] { return launch_ranges(sv->tiles, sv->d_total, M, sv->ranges, vt.total_tiles, st_); }));
-  TRYH(timed(ctx, K_BLEND_FWD, [&] {
-    return launch_blend_fwd(s->tile, s->batch, vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final,
-                            sv->n_contrib, st_);
-  }));
-#undef TRY
-#undef TRYH
+  gsr_saved* sv = nullptr;
+  if ((st = forward_eager(ctx, g, cams, V, s, outs, &sv)) != GSR_OK) return st;
   if (saved)
     *saved = sv;
   else
@@ -439,21 +553,10 @@ gsr_status gsr_loss_l1(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_out*
   if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
   if (!saved || !outs || !targets || !grad_color_out || !loss_dev)
     return fail(ctx, GSR_EINVAL, "NULL argument to gsr_loss_l1");
-  if (!(depth_weight >= 0.f)) return fail(ctx, GSR_EINVAL, "depth_weight must be >= 0");
-  ViewTable vt = saved->vt;
-  for (int v = 0; v < vt.nviews; ++v) {
-    if (!outs[v].color || !targets[v].color || !grad_color_out[v])
-      return fail(ctx, GSR_EINVAL, "colour image, target or gradient pointer is NULL");
-    if (targets[v].depth && (!outs[v].depth || !grad_depth_out || !grad_depth_out[v]))
-      return fail(ctx, GSR_EINVAL, "depth target given without rendered depth / gradient buffer");
-    vt.v[v].color = outs[v].color;
-    vt.v[v].depth = outs[v].depth;
-    vt.v[v].t_color = targets[v].color;
-    vt.v[v].t_depth = targets[v].depth;
-    vt.v[v].lg_color = grad_color_out[v];
-    vt.v[v].lg_depth = grad_depth_out ? grad_depth_out[v] : nullptr;
-  }
-  GSR_HIP(ctx, timed(ctx, K_LOSS, [&] { return launch_loss_l1(vt, depth_weight, loss_dev, ctx->stream); }));
+  ViewTable vt;
+  gsr_status st = loss_table(ctx, saved, outs, targets, depth_weight, grad_color_out, grad_depth_out, &vt);
+  if (st != GSR_OK) return st;
+  GSR_HIP(ctx, timed(ctx, ctx->stream, K_LOSS, [&] { return launch_loss_l1(vt, depth_weight, loss_dev, ctx->stream); }));
   return GSR_OK;
 }
 
@@ -462,30 +565,15 @@ gsr_status gsr_backward(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_gra
   if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
   if (!saved || !grads || !out) return fail(ctx, GSR_EINVAL, "NULL argument to gsr_backward");
   if (flags & ~GSR_ACCUMULATE) return fail(ctx, GSR_EINVAL, "unknown flag");
-  ViewTable vt = saved->vt;
-  for (int v = 0; v < vt.nviews; ++v) {
-    vt.v[v].g_color = grads[v].color;
-    vt.v[v].g_depth = grads[v].depth;
-    vt.v[v].g_alpha = grads[v].alpha;
-  }
-  const int64_t VN = int64_t(saved->V) * saved->N;
+  gsr_saved* sv = const_cast<gsr_saved*>(saved);
+  const ViewTable vt = with_grads(sv, grads);
+  const int64_t VN = int64_t(sv->V) * sv->N;
   void* g2 = nullptr;
-  gsr_status st = dev_alloc(ctx, &g2, size_t(VN) * kGrad2D * sizeof(float));
+  gsr_status st = dev_alloc(ctx, ctx->stream, &g2, size_t(VN) * kGrad2D * sizeof(float));
   if (st != GSR_OK) return st;
-  float* grad2d = static_cast<float*>(g2);
-  hipStream_t s = ctx->stream;
-  hipError_t e =
-      timed(ctx, K_FILL, [&] { return launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, VN * kGrad2D, s); });
-  if (e == hipSuccess)
-    e = timed(ctx, K_BLEND_BWD, [&] {
-      return launch_blend_bwd(saved->s.tile, saved->s.batch, vt, saved->ru, saved->rec, saved->ranges,
-                              saved->vals, saved->T_final, saved->n_contrib, grad2d, s);
-    });
   GradOut go{out->means, out->scales, out->quats, out->opacities, out->sh, int(flags & GSR_ACCUMULATE)};
-  if (e == hipSuccess)
-    e = timed(ctx, K_PROJECT_BWD,
-              [&] { return launch_project_bwd(saved->deg, saved->g, vt, saved->ru, saved->rec, grad2d, go, s); });
-  if (g2) (void)hipFreeAsync(g2, s);
+  hipError_t e = enqueue_backward(sv, vt, static_cast<float*>(g2), go, ctx->stream, true);
+  if (g2) (void)hipFreeAsync(g2, ctx->stream);
   if (e != hipSuccess) return fail(ctx, GSR_EDEVICE, std::string("backward launch failed: ") + hipGetErrorString(e));
   return GSR_OK;
 }
@@ -533,6 +621,7 @@ gsr_status gsr_debug_export(gsr_ctx* ctx, const gsr_saved* sv, const gsr_debug* 
   GSR_HIP(ctx, cp(out->ranges, sv->ranges, size_t(sv->vt.total_tiles) * 8));
   GSR_HIP(ctx, cp(out->T_final, sv->T_final, size_t(sv->total_pix) * 4));
   GSR_HIP(ctx, cp(out->n_contrib, sv->n_contrib, size_t(sv->total_pix) * 4));
+  GSR_HIP(ctx, cp(out->n_used, sv->n_used, size_t(sv->total_pix) * 4));
   GSR_HIP(ctx, cp(out->tiles_touched, sv->rec.counts, size_t(VN) * 4));
   if (out->mu || out->depth || out->conic || out->color || out->rect) {
     std::vector<float4> r0(VN), r1(VN), rgb(VN);
@@ -567,6 +656,270 @@ gsr_status gsr_debug_export(gsr_ctx* ctx, const gsr_saved* sv, const gsr_debug* 
         out->rect[i * 4 + 3] = vis ? int32_t(rc[i].y >> 16) : -1;
       }
     }
+  }
+  return GSR_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Captured step
+// ------------------------------------------------------------------------------------
+static void graph_destroy(gsr_graph* gr) {
+  if (!gr) return;
+  if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+  if (gr->graph) (void)hipGraphDestroy(gr->graph);
+  if (gr->done) (void)hipEventDestroy(gr->done);
+  if (gr->capture) (void)hipStreamDestroy(gr->capture);
+  if (gr->h_flag) (void)hipHostFree(gr->h_flag);
+  if (gr->sv) release(gr->sv);
+  delete gr;
+}
+
+gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
+                            const gsr_settings* s, const gsr_view_out* outs, const gsr_target* targets,
+                            float depth_weight, float* const* grad_color, float* const* grad_depth,
+                            const gsr_gaussian_grads* grads, float* loss_dev, float headroom, gsr_graph** out) {
+  if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
+  if (!out || !targets || !grads || !loss_dev || !grad_color)
+    return fail(ctx, GSR_EINVAL, "NULL argument to gsr_graph_create");
+  *out = nullptr;
+  if (!(headroom >= 0.f) || headroom > 16.f) return fail(ctx, GSR_EINVAL, "headroom must be in [0, 16]");
+  gsr_status st = check_forward_args(ctx, g, cams, V, s, outs);
+  if (st != GSR_OK) return st;
+  ctx->err.clear();
+  // one eager forward measures the sizes the capacities are derived from
+  gsr_saved* probe = nullptr;
+  if ((st = forward_eager(ctx, g, cams, V, s, outs, &probe)) != GSR_OK) return st;
+  const int64_t M = probe->M, NV = probe->n_vis;
+  release(probe);
+  const int64_t VN = int64_t(V) * g->n;
+  const int64_t cap_vis = std::min<int64_t>(VN, int64_t(std::ceil(double(NV) * (1.0 + headroom))) + 256);
+  int64_t cap_M = int64_t(std::ceil(double(M) * (1.0 + headroom))) + 4096;
+  cap_M = std::min<int64_t>(cap_M, (int64_t(1) << 32) - 1);
+
+  gsr_graph* gr = new gsr_graph;
+  gr->ctx = ctx;
+  if ((st = make_saved(ctx, g, cams, V, s, outs, &gr->sv)) != GSR_OK) {
+    delete gr;
+    return st;
+  }
+  gsr_saved* sv = gr->sv;
+  sv->M = M;
+  sv->n_vis = NV;
+  if ((st = alloc_sort(sv, cap_vis, cap_M, true)) != GSR_OK ||
+      (st = alloc_in(sv, sv->blocks, &sv->grad2d, size_t(VN) * kGrad2D)) != GSR_OK) {
+    graph_destroy(gr);
+    return st;
+  }
+  ViewTable lvt;
+  if ((st = loss_table(ctx, sv, outs, targets, depth_weight, grad_color, grad_depth, &lvt)) != GSR_OK) {
+    graph_destroy(gr);
+    return st;
+  }
+  std::vector<gsr_view_grad> vg(V);
+  for (int v = 0; v < V; ++v) vg[v] = gsr_view_grad{grad_color[v], grad_depth ? grad_depth[v] : nullptr, nullptr};
+  const ViewTable bvt = with_grads(sv, vg.data());
+  const GradOut go{grads->means, grads->scales, grads->quats, grads->opacities, grads->sh, 0};
+
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&gr->h_flag), sizeof(uint32_t), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&gr->done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&gr->capture, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);  // buffers allocated on ctx->stream are ready
+  if (e != hipSuccess) {
+    graph_destroy(gr);
+    return fail(ctx, GSR_EDEVICE, std::string("graph set-up failed: ") + hipGetErrorString(e));
+  }
+  *gr->h_flag = 0;
+  hipStream_t cs = gr->capture;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t k = enqueue_project(sv, cs, false);
+    if (k == hipSuccess) k = enqueue_sort_blend(sv, cs, false);
+    if (k == hipSuccess) k = launch_loss_l1(lvt, depth_weight, loss_dev, cs);
+    if (k == hipSuccess) k = enqueue_backward(sv, bvt, sv->grad2d, go, cs, false);
+    if (k == hipSuccess)
+      k = hipMemcpyAsync(gr->h_flag, sv->ctrl + kOverflow, sizeof(uint32_t), hipMemcpyDeviceToHost, cs);
+    e = hipStreamEndCapture(cs, &gr->graph);
+    if (k != hipSuccess) e = k;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    graph_destroy(gr);
+    return fail(ctx, GSR_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
+  }
+  *out = gr;
+  return GSR_OK;
+}
+
+gsr_status gsr_graph_launch(gsr_graph* gr) {
+  if (!gr) return fail(nullptr, GSR_EINVAL, "graph is NULL");
+  gsr_ctx* ctx = gr->ctx;
+  if (gr->launched && !gr->overflowed && hipEventQuery(gr->done) == hipSuccess && *gr->h_flag) gr->overflowed = true;
+  (void)hipGetLastError();
+  if (gr->overflowed) return fail(ctx, GSR_ECAPACITY, "a captured step exceeded its key capacity; re-create the graph");
+  GSR_HIP(ctx, hipGraphLaunch(gr->exec, ctx->stream));
+  GSR_HIP(ctx, hipEventRecord(gr->done, ctx->stream));
+  gr->launched = true;
+  return GSR_OK;
+}
+
+gsr_status gsr_graph_sync(gsr_graph* gr) {
+  if (!gr) return fail(nullptr, GSR_EINVAL, "graph is NULL");
+  gsr_ctx* ctx = gr->ctx;
+  if (gr->launched) GSR_HIP(ctx, hipEventSynchronize(gr->done));
+  if (gr->launched && *gr->h_flag) gr->overflowed = true;
+  if (gr->overflowed) return fail(ctx, GSR_ECAPACITY, "a captured step exceeded its key capacity; re-create the graph");
+  return GSR_OK;
+}
+
+gsr_status gsr_graph_info(const gsr_graph* gr, gsr_info* info, int64_t* cap_keys, int64_t* cap_visible) {
+  if (!gr || !info) return fail(nullptr, GSR_EINVAL, "NULL argument to gsr_graph_info");
+  gsr_saved_info(gr->sv, info);
+  if (cap_keys) *cap_keys = gr->sv->cap_M;
+  if (cap_visible) *cap_visible = gr->sv->cap_vis;
+  return GSR_OK;
+}
+
+gsr_status gsr_graph_free(gsr_graph* gr) {
+  if (!gr) return fail(nullptr, GSR_EINVAL, "graph is NULL");
+  if (gr->launched) (void)hipEventSynchronize(gr->done);
+  graph_destroy(gr);
+  return GSR_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Launch-shape autotuner
+// ------------------------------------------------------------------------------------
+static std::string autotune_key(int dev, const gsr_gaussians* g, const gsr_camera* cams, int V) {
+  hipDeviceProp_t p;
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDeviceProperties(&p, dev) == hipSuccess) {
+    arch = p.gcnArchName;
+    cus = p.multiProcessorCount;
+  }
+  int64_t pix = 0;
+  for (int v = 0; v < V; ++v) pix += int64_t(cams[v].width) * cams[v].height;
+  std::ostringstream k;
+  k << arch.substr(0, arch.find(':')) << "|cu" << cus << "|px" << bits_for(uint64_t(pix)) << "|n"
+    << bits_for(uint64_t(g->n)) << "|deg" << g->sh_degree << "|v" << V;
+  return k.str();
+}
+
+static std::string autotune_path() {
+  const char* p = std::getenv("GSR_AUTOTUNE_CACHE");
+  if (p && *p) return p;
+  const char* home = std::getenv("HOME");
+  return std::string(home ? home : "/tmp") + "/.cache/gsr_autotune.txt";
+}
+
+gsr_status gsr_autotune(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V, gsr_settings* s,
+                        uint32_t flags, float* best_ms) {
+  if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
+  if (!s) return fail(ctx, GSR_EINVAL, "settings is NULL");
+  if (flags & ~GSR_AUTOTUNE_NO_CACHE) return fail(ctx, GSR_EINVAL, "unknown flag");
+  std::vector<gsr_view_out> dummy(V > 0 ? V : 1, gsr_view_out{reinterpret_cast<float*>(16), nullptr, nullptr});
+  gsr_status st = check_forward_args(ctx, g, cams, V, s, dummy.data());
+  if (st != GSR_OK) return st;
+  const std::string key = autotune_key(ctx->device, g, cams, V);
+  const std::string path = autotune_path();
+  const bool use_cache = !(flags & GSR_AUTOTUNE_NO_CACHE);
+  if (use_cache) {
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      int t = 0, b = 0;
+      float ms = 0.f;
+      if ((ls >> k >> t >> b >> ms) && k == key && (t == 8 || t == 16 || t == 32) && (b == 128 || b == 256)) {
+        s->tile = t;
+        s->batch = b;
+        if (best_ms) *best_ms = ms;
+        return GSR_OK;
+      }
+    }
+  }
+  // scratch images, output gradients (dL/dcolour = 1/(3P)) and parameter gradients
+  hipStream_t strm = ctx->stream;
+  std::vector<void*> scratch;
+  auto salloc = [&](size_t bytes) -> float* {
+    void* p = nullptr;
+    if (dev_alloc(ctx, strm, &p, bytes) != GSR_OK) return nullptr;
+    if (p) scratch.push_back(p);
+    return static_cast<float*>(p);
+  };
+  auto sfree = [&]() {
+    for (void* p : scratch) (void)hipFreeAsync(p, strm);
+    (void)hipStreamSynchronize(strm);
+  };
+  std::vector<gsr_view_out> outs(V);
+  std::vector<gsr_view_grad> vg(V);
+  bool ok = true;
+  for (int v = 0; v < V && ok; ++v) {
+    const size_t P = size_t(cams[v].width) * cams[v].height;
+    float* img = salloc(P * 5 * sizeof(float));
+    float* gc = salloc(P * 3 * sizeof(float));
+    ok = img && gc;
+    if (!ok) break;
+    outs[v] = gsr_view_out{img, img + 3 * P, img + 4 * P};
+    const float val = 1.f / float(3 * P);
+    uint32_t bits;
+    std::memcpy(&bits, &val, 4);
+    ok = launch_fill_u32(reinterpret_cast<uint32_t*>(gc), bits, int64_t(3 * P), strm) == hipSuccess;
+    vg[v] = gsr_view_grad{gc, nullptr, nullptr};
+  }
+  const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
+  float* gbuf = ok ? salloc(size_t(std::max<int64_t>(g->n, 1)) * (14 + 3 * K) * sizeof(float)) : nullptr;
+  if (!ok || !gbuf) {
+    sfree();
+    return fail(ctx, GSR_ENOMEM, "autotune scratch allocation failed");
+  }
+  gsr_gaussian_grads gg{gbuf, gbuf + 3 * g->n, gbuf + 6 * g->n, gbuf + 10 * g->n, gbuf + 11 * g->n};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const bool timer_was = ctx->timer.on;
+  ctx->timer.on = false;
+  float best = 1e30f;
+  int bt = s->tile, bb = s->batch;
+  const int tiles[3] = {8, 16, 32}, batches[2] = {128, 256};
+  for (int ti = 0; ti < 3 && st == GSR_OK; ++ti)
+    for (int bi = 0; bi < 2 && st == GSR_OK; ++bi) {
+      gsr_settings c = *s;
+      c.tile = tiles[ti];
+      c.batch = batches[bi];
+      float total = 0.f;
+      for (int rep = 0; rep < 4 && st == GSR_OK; ++rep) {  // one warm-up, three timed
+        (void)hipEventRecord(e0, strm);
+        gsr_saved* sv = nullptr;
+        st = forward_eager(ctx, g, cams, V, &c, outs.data(), &sv);
+        if (st != GSR_OK) break;
+        st = gsr_backward(ctx, sv, vg.data(), &gg, 0);
+        release(sv);
+        (void)hipEventRecord(e1, strm);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) total += ms;
+      }
+      if (st == GSR_OK && total / 3.f < best) {
+        best = total / 3.f;
+        bt = c.tile;
+        bb = c.batch;
+      }
+    }
+  ctx->timer.on = timer_was;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  sfree();
+  if (st != GSR_OK) return st;
+  s->tile = bt;
+  s->batch = bb;
+  if (best_ms) *best_ms = best;
+  if (use_cache) {
+    std::ofstream o(path, std::ios::app);
+    if (o) o << key << " " << bt << " " << bb << " " << best << "\n";
   }
   return GSR_OK;
 }

@@ -20,6 +20,7 @@ enum KernelId {
   K_RADIX_ROWSCAN,
   K_RADIX_SCATTER,
   K_RANGES,
+  K_TILE_ORDER,
   K_FILL,
   K_BLEND_FWD,
   K_LOSS,
@@ -96,6 +97,11 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;  // keys per radix-sort block
 constexpr int kGrad2D = 12;  // floats per (view, Gaussian) 2D-gradient record (10 used)
+constexpr int kBuckets = 33;               // log2 buckets of tile list lengths
+constexpr int kHeadFwd = 2 * kBuckets;     // control words (see TileQueue)
+constexpr int kHeadBwd = 2 * kBuckets + 1;
+constexpr int kOverflow = 2 * kBuckets + 2;
+constexpr int kCtrlWords = 2 * kBuckets + 4;
 
 // One camera plus where its tiles and pixels live in the concatenated spaces.
 struct ViewDev {
@@ -148,6 +154,14 @@ struct Records {
   uint32_t* counts; // tiles touched, 0 when culled
 };
 
+// Longest-list-first tile order and the control words of the persistent compositing
+// kernels: [0, kBuckets) bucket counts, [kBuckets, 2 kBuckets) bucket fill, kHeadFwd /
+// kHeadBwd queue heads, kOverflow the capacity-overflow flag.
+struct TileQueue {
+  const uint32_t* order;
+  uint32_t* ctrl;
+};
+
 struct GradOut {
   float* means;
   float* scales;
@@ -164,23 +178,26 @@ hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const
                           const Records& rec, uint2* blocksums, int nblk, hipStream_t s);
 hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* totals, hipStream_t s);
 hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
-                          uint32_t* dkeys, uint32_t* dvals, hipStream_t s);
+                          uint32_t* dkeys, uint32_t* dvals, int64_t cap, uint32_t* overflow, hipStream_t s);
+hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* bucket_of, uint32_t* order,
+                             uint32_t* ctrl, hipStream_t s);
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                              uint32_t* hist, uint32_t* digit_tot, const unsigned long long* count, int64_t cap,
-                             int key_bits, bool* result_in_alt, int* passes, hipStream_t s, Timer* tm);
+                             const uint32_t* overflow, int key_bits, bool* result_in_alt, int* passes, hipStream_t s,
+                             Timer* tm);
 hipError_t launch_duplicate(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* dvals,
                             const unsigned long long* nvis, int64_t cap_vis, uint32_t* blocksums,
                             unsigned long long* total, uint32_t* tkeys, uint32_t* tvals, int64_t cap_M,
                             uint32_t* overflow, hipStream_t s, Timer* tm);
-hipError_t launch_ranges(const uint32_t* tkeys, const unsigned long long* count, int64_t cap, uint2* ranges,
-                         int total_tiles, hipStream_t s);
+hipError_t launch_ranges(const uint32_t* tkeys, const unsigned long long* count, int64_t cap,
+                         const uint32_t* overflow, uint2* ranges, int total_tiles, hipStream_t s);
 hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
-                            hipStream_t s);
+                            uint32_t* n_used, const TileQueue& q, hipStream_t s);
 hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* loss, hipStream_t s);
 hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, const float* T_final,
-                            const uint32_t* n_contrib, float* grad2d, hipStream_t s);
+                            const uint32_t* n_contrib, float* grad2d, const TileQueue& q, hipStream_t s);
 hipError_t launch_project_bwd(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru,
                               const Records& rec, const float* grad2d, const GradOut& out, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);

@@ -439,7 +439,12 @@ __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* a, int count, unsig
   if (t == 1023) *total = incl;
 }
 
-__device__ __forceinline__ uint32_t clamp_count(const unsigned long long* count, int64_t cap) {
+// A device-side count clamped to the capacity the grid and buffers were sized for; zero
+// once a capacity overflow has been flagged, so that nothing downstream of an overflow
+// reads partially written buffers.
+__device__ __forceinline__ uint32_t clamp_count(const unsigned long long* count, int64_t cap,
+                                                const uint32_t* overflow) {
+  if (*overflow) return 0u;
   const unsigned long long c = *count;
   return uint32_t(c < (unsigned long long)cap ? c : (unsigned long long)cap);
 }
@@ -448,7 +453,8 @@ __device__ __forceinline__ uint32_t clamp_count(const unsigned long long* count,
 // K3a: compaction of the visible records into (depth bits, record id) pairs, record order
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kProjThreads) void k_compact(int64_t n, Records rec, const uint2* blocksums, int nblk,
-                                                          uint32_t* dkeys, uint32_t* dvals) {
+                                                          uint32_t* dkeys, uint32_t* dvals, int64_t cap,
+                                                          uint32_t* overflow) {
   __shared__ uint32_t red[kProjThreads / 64];
   const int v = blockIdx.y;
   const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
@@ -457,6 +463,10 @@ __global__ __launch_bounds__(kProjThreads) void k_compact(int64_t n, Records rec
   const uint32_t excl = block_exclusive_scan_u32(vis, red);
   if (!vis) return;
   const uint32_t off = blocksums[int64_t(v) * nblk + blockIdx.x].y + excl;
+  if (int64_t(off) >= cap) {
+    atomicOr(overflow, 1u);
+    return;
+  }
   dkeys[off] = __float_as_uint(rec.r1[rid].z);
   dvals[off] = uint32_t(rid);
 }
@@ -471,11 +481,12 @@ __global__ __launch_bounds__(kProjThreads) void k_compact(int64_t n, Records rec
 //            across the four wavefronts through LDS) and writes them to their slots
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* keys, const unsigned long long* count,
-                                                             int64_t cap, int shift, uint32_t* hist, int nblk) {
+                                                             int64_t cap, const uint32_t* overflow, int shift,
+                                                             uint32_t* hist, int nblk) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t M = clamp_count(count, cap);
+  const int64_t M = clamp_count(count, cap, overflow);
   const int64_t base = int64_t(blockIdx.x) * kSortTile;
 #pragma unroll 4
   for (int i = 0; i < kSortItems; ++i) {
@@ -508,13 +519,14 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* hist, 
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* kin, const uint32_t* vin,
                                                                 uint32_t* kout, uint32_t* vout,
                                                                 const unsigned long long* count, int64_t cap,
-                                                                int shift, const uint32_t* hist,
-                                                                const uint32_t* digit_tot, int nblk) {
+                                                                const uint32_t* overflow, int shift,
+                                                                const uint32_t* hist, const uint32_t* digit_tot,
+                                                                int nblk) {
   __shared__ uint32_t base[256];
   __shared__ uint32_t wcnt[kSortThreads / 64][256];
   __shared__ uint32_t red[kSortThreads / 64];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int64_t M = clamp_count(count, cap);
+  const int64_t M = clamp_count(count, cap, overflow);
   const uint32_t ex = block_exclusive_scan_u32(digit_tot[t], red);
   base[t] = ex + hist[int64_t(t) * nblk + blockIdx.x];
 #pragma unroll
@@ -571,10 +583,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kProjThreads) void k_sorted_counts(const uint32_t* dvals, const uint32_t* counts,
                                                                 const unsigned long long* nvis, int64_t cap,
-                                                                uint32_t* blocksums) {
+                                                                const uint32_t* overflow, uint32_t* blocksums) {
   __shared__ uint32_t red[kProjThreads / 64];
   const int64_t r = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
-  const uint32_t c = r < int64_t(clamp_count(nvis, cap)) ? counts[dvals[r]] : 0u;
+  const uint32_t c = r < int64_t(clamp_count(nvis, cap, overflow)) ? counts[dvals[r]] : 0u;
   const uint32_t bs = block_sum_u32(c, red);
   if (threadIdx.x == 0) blocksums[blockIdx.x] = bs;
 }
@@ -593,7 +605,7 @@ __global__ __launch_bounds__(kProjThreads) void k_duplicate(ViewTable vt, int64_
   const int64_t r = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
   uint32_t rid = 0, cnt = 0;
   uint2 rc = make_uint2(0u, 0u);
-  if (r < int64_t(clamp_count(nvis, cap_vis))) {
+  if (r < int64_t(clamp_count(nvis, cap_vis, overflow))) {
     rid = dvals[r];
     cnt = rec.counts[rid];
     rc = rec.rect[rid];
@@ -637,17 +649,18 @@ __global__ __launch_bounds__(kProjThreads) void k_duplicate(ViewTable vt, int64_
 // K5: tile ranges
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* tkeys, const unsigned long long* count, int64_t cap,
-                                                uint2* ranges) {
+                                                const uint32_t* overflow, uint2* ranges, int total_tiles) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  const int64_t M = clamp_count(count, cap);
+  const int64_t M = clamp_count(count, cap, overflow);
   if (i >= M) return;
   const uint32_t tile = tkeys[i];
+  if (tile >= uint32_t(total_tiles)) return;
   if (i == 0) {
     ranges[tile].x = 0;
   } else {
     const uint32_t prev = tkeys[i - 1];
     if (prev != tile) {
-      ranges[prev].y = uint32_t(i);
+      if (prev < uint32_t(total_tiles)) ranges[prev].y = uint32_t(i);
       ranges[tile].x = uint32_t(i);
     }
   }
@@ -667,72 +680,133 @@ __device__ __forceinline__ int view_of_tile(const ViewTable& vt, int tile) {
 }
 
 // ------------------------------------------------------------------------------------
-// K6: forward compositing.  One block per tile, one thread per pixel; the tile's sorted
-// list is staged through LDS BATCH records at a time; the block leaves once every
-// pixel has reached T < T_min.
+// Tile work queue.  Tiles are ordered by decreasing list length (log2 buckets, a counting
+// sort) and the compositing kernels run as persistent blocks that take the next tile
+// from a device counter, so the longest lists start first and short ones fill the tail.
+// ctrl layout: [0..32] bucket counts, [33..65] bucket fill, [66] forward head,
+// [67] backward head, [68] overflow flag.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_tile_buckets(const uint2* ranges, int total, uint32_t* bucket_of,
+                                                      uint32_t* ctrl) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const uint2 r = ranges[i];
+  const uint32_t len = r.y - r.x;
+  const uint32_t b = len ? 32u - uint32_t(__clz(len)) : 0u;  // 0..32
+  bucket_of[i] = b;
+  atomicAdd(&ctrl[b], 1u);
+}
+
+__global__ __launch_bounds__(256) void k_tile_order(const uint32_t* bucket_of, int total, uint32_t* ctrl,
+                                                    uint32_t* order) {
+  __shared__ uint32_t start[kBuckets];
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = kBuckets - 1; b >= 0; --b) {
+      start[b] = run;
+      run += ctrl[b];
+    }
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const uint32_t b = bucket_of[i];
+  order[start[b] + atomicAdd(&ctrl[kBuckets + b], 1u)] = uint32_t(i);
+}
+
+// Block-uniform: the next tile of the queue, or -1 when it is exhausted.
+__device__ __forceinline__ int next_tile(const TileQueue& q, uint32_t* head, int total, int* s_item) {
+  __syncthreads();
+  if (threadIdx.x == 0) *s_item = int(atomicAdd(head, 1u));
+  __syncthreads();
+  const int item = *s_item;
+  return item < total ? int(q.order[item]) : -1;
+}
+
+// ------------------------------------------------------------------------------------
+// K6: forward compositing.  Persistent blocks take tiles from the queue; one thread per
+// pixel; the tile's sorted list is staged through LDS BATCH records at a time; a tile is
+// left once every pixel has reached T < T_min.
 // ------------------------------------------------------------------------------------
 template <int TS, int BATCH>
 __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Records rec, const uint2* ranges,
-                                                     const uint32_t* vals, float* T_final, uint32_t* n_contrib) {
+                                                     const uint32_t* vals, float* T_final, uint32_t* n_contrib,
+                                                     uint32_t* n_used, TileQueue q) {
   constexpr int NT = TS * TS;
   __shared__ float4 s_r0[BATCH];
   __shared__ float4 s_r1[BATCH];
   __shared__ float4 s_rgb[BATCH];
-  const int tile = blockIdx.x;
-  const ViewDev& cam = vt.v[view_of_tile(vt, tile)];
-  const int lt = tile - cam.tile_off;
-  const int ty = lt / cam.tiles_x, tx = lt - ty * cam.tiles_x;
-  const int px = tx * TS + int(threadIdx.x % TS), py = ty * TS + int(threadIdx.x / TS);
-  const bool inside = px < cam.W && py < cam.H;
-  const uint2 rg = ranges[tile];
-  const int n = int(rg.y - rg.x);
-  const float fpx = float(px), fpy = float(py);
-  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
-  uint32_t last = 0;
-  bool done = !inside;
-  for (int b0 = 0; b0 < n; b0 += BATCH) {
-    if (__syncthreads_count(!done) == 0) break;
-    for (int j = threadIdx.x; j < BATCH && b0 + j < n; j += NT) {
-      const uint32_t id = vals[rg.x + b0 + j];
-      s_r0[j] = rec.r0[id];
-      s_r1[j] = rec.r1[id];
-      s_rgb[j] = rec.rgb[id];
-    }
-    __syncthreads();
-    if (!done) {
-      const int cnt = min(BATCH, n - b0);
-      for (int j = 0; j < cnt; ++j) {
-        const float4 r0 = s_r0[j];
-        const float4 r1 = s_r1[j];
-        float G;
-        const float a = splat_alpha(fpx - r0.x, fpy - r0.y, r0.z, r0.w, r1.x, r1.y, G);
-        if (a < ru.amin) continue;
-        const float al = a < ru.amax ? a : ru.amax;
-        const float wgt = al * T;
-        const float4 c = s_rgb[j];
-        C0 += c.x * wgt;
-        C1 += c.y * wgt;
-        C2 += c.z * wgt;
-        D += r1.z * wgt;
-        T = T * (1.f - al);
-        last = uint32_t(b0 + j + 1);
-        if (T < ru.Tmin) {
-          done = true;
-          break;
+  __shared__ int s_item;
+  for (;;) {
+    const int tile = next_tile(q, q.ctrl + kHeadFwd, vt.total_tiles, &s_item);
+    if (tile < 0) return;
+    const ViewDev& cam = vt.v[view_of_tile(vt, tile)];
+    const int lt = tile - cam.tile_off;
+    const int ty = lt / cam.tiles_x, tx = lt - ty * cam.tiles_x;
+    const int px = tx * TS + int(threadIdx.x % TS), py = ty * TS + int(threadIdx.x / TS);
+    const bool inside = px < cam.W && py < cam.H;
+    const uint2 rg = ranges[tile];
+    const int n = int(rg.y - rg.x);
+    const float fpx = float(px), fpy = float(py);
+    float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
+    uint32_t last = 0, used = 0;
+    bool done = !inside;
+    for (int b0 = 0; b0 < n; b0 += BATCH) {
+      if (__syncthreads_count(!done) == 0) break;
+      for (int j = threadIdx.x; j < BATCH && b0 + j < n; j += NT) {
+        const uint32_t id = vals[rg.x + b0 + j];
+        s_r0[j] = rec.r0[id];
+        s_r1[j] = rec.r1[id];
+        s_rgb[j] = rec.rgb[id];
+      }
+      __syncthreads();
+      if (!done) {
+        const int cnt = min(BATCH, n - b0);
+        // splat values of four staged entries are independent of the running
+        // transmittance: evaluate them together, then composite strictly in list order
+        for (int j = 0; j < cnt && !done; j += 4) {
+          float a4[4], z4[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int jj = min(j + u, cnt - 1);
+            const float4 r0 = s_r0[jj];
+            const float4 r1 = s_r1[jj];
+            float G;
+            a4[u] = splat_alpha(fpx - r0.x, fpy - r0.y, r0.z, r0.w, r1.x, r1.y, G);
+            z4[u] = r1.z;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (j + u >= cnt || done) break;
+            const float a = a4[u];
+            if (a < ru.amin) continue;
+            const float al = a < ru.amax ? a : ru.amax;
+            const float wgt = al * T;
+            const float4 c = s_rgb[j + u];
+            C0 += c.x * wgt;
+            C1 += c.y * wgt;
+            C2 += c.z * wgt;
+            D += z4[u] * wgt;
+            T = T * (1.f - al);
+            last = uint32_t(b0 + j + u + 1);
+            ++used;
+            if (T < ru.Tmin) done = true;
+          }
         }
       }
     }
-  }
-  if (inside) {
-    const int64_t P = int64_t(cam.W) * cam.H;
-    const int64_t pix = int64_t(py) * cam.W + px;
-    cam.color[pix] = C0 + T * ru.bg[0];
-    cam.color[P + pix] = C1 + T * ru.bg[1];
-    cam.color[2 * P + pix] = C2 + T * ru.bg[2];
-    if (cam.depth) cam.depth[pix] = D;
-    if (cam.alpha) cam.alpha[pix] = 1.f - T;
-    T_final[cam.pix_off + pix] = T;
-    n_contrib[cam.pix_off + pix] = last;
+    if (inside) {
+      const int64_t P = int64_t(cam.W) * cam.H;
+      const int64_t pix = int64_t(py) * cam.W + px;
+      cam.color[pix] = C0 + T * ru.bg[0];
+      cam.color[P + pix] = C1 + T * ru.bg[1];
+      cam.color[2 * P + pix] = C2 + T * ru.bg[2];
+      if (cam.depth) cam.depth[pix] = D;
+      if (cam.alpha) cam.alpha[pix] = 1.f - T;
+      T_final[cam.pix_off + pix] = T;
+      n_contrib[cam.pix_off + pix] = last;
+      n_used[cam.pix_off + pix] = used;
+    }
   }
 }
 
@@ -791,7 +865,7 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 template <int TS, int BATCH>
 __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Records rec, const uint2* ranges,
                                                      const uint32_t* vals, const float* T_final,
-                                                     const uint32_t* n_contrib, float* grad2d) {
+                                                     const uint32_t* n_contrib, float* grad2d, TileQueue q) {
   constexpr int NT = TS * TS;
   constexpr bool kBlockSum = NT > 64;
   __shared__ float4 s_r0[BATCH];
@@ -800,7 +874,12 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
   __shared__ uint32_t s_id[BATCH];
   __shared__ float s_g[kBlockSum ? 10 : 1][kBlockSum ? BATCH : 1];
   __shared__ uint32_t s_max;
-  const int tile = blockIdx.x;
+  __shared__ int s_item;
+  if (kBlockSum)
+    for (int i = threadIdx.x; i < 10 * BATCH; i += NT) (&s_g[0][0])[i] = 0.f;
+  for (;;) {
+  const int tile = next_tile(q, q.ctrl + kHeadBwd, vt.total_tiles, &s_item);
+  if (tile < 0) return;
   const ViewDev& cam = vt.v[view_of_tile(vt, tile)];
   const int lt = tile - cam.tile_off;
   const int ty = lt / cam.tiles_x, tx = lt - ty * cam.tiles_x;
@@ -825,8 +904,6 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
   }
   const int wmax = int(wave_max_u32(last));
   if (threadIdx.x == 0) s_max = 0;
-  if (kBlockSum)
-    for (int i = threadIdx.x; i < 10 * BATCH; i += NT) (&s_g[0][0])[i] = 0.f;
   __syncthreads();
   if (lane == 0 && wmax) atomicMax(&s_max, uint32_t(wmax));
   __syncthreads();
@@ -935,6 +1012,7 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
         }
       }
     }
+  }
   }
 }
 
@@ -1121,15 +1199,16 @@ hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* to
 }
 
 hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
-                          uint32_t* dkeys, uint32_t* dvals, hipStream_t s) {
+                          uint32_t* dkeys, uint32_t* dvals, int64_t cap, uint32_t* overflow, hipStream_t s) {
   if (nblk == 0) return hipSuccess;
-  k_compact<<<dim3(nblk, views), kProjThreads, 0, s>>>(n, rec, blocksums, nblk, dkeys, dvals);
+  k_compact<<<dim3(nblk, views), kProjThreads, 0, s>>>(n, rec, blocksums, nblk, dkeys, dvals, cap, overflow);
   return hipGetLastError();
 }
 
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                              uint32_t* hist, uint32_t* digit_tot, const unsigned long long* count, int64_t cap,
-                             int key_bits, bool* result_in_alt, int* passes, hipStream_t s, Timer* tm) {
+                             const uint32_t* overflow, int key_bits, bool* result_in_alt, int* passes, hipStream_t s,
+                             Timer* tm) {
   const int np = (key_bits + 7) / 8;
   *passes = 0;
   *result_in_alt = false;
@@ -1143,13 +1222,14 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
   for (int p = 0; p < np; ++p) {
     const int shift = 8 * p;
     if (tm) tm->begin(K_RADIX_HIST);
-    k_radix_hist<<<nblk, kSortThreads, 0, s>>>(kin, count, cap, shift, hist, nblk);
+    k_radix_hist<<<nblk, kSortThreads, 0, s>>>(kin, count, cap, overflow, shift, hist, nblk);
     if (tm) tm->end(K_RADIX_HIST);
     if (tm) tm->begin(K_RADIX_ROWSCAN);
     k_radix_rowscan<<<256, kSortThreads, 0, s>>>(hist, nblk, digit_tot);
     if (tm) tm->end(K_RADIX_ROWSCAN);
     if (tm) tm->begin(K_RADIX_SCATTER);
-    k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(kin, vin, kout, vout, count, cap, shift, hist, digit_tot, nblk);
+    k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(kin, vin, kout, vout, count, cap, overflow, shift, hist, digit_tot,
+                                                  nblk);
     if (tm) tm->end(K_RADIX_SCATTER);
     std::swap(kin, kout);
     std::swap(vin, vout);
@@ -1165,7 +1245,7 @@ hipError_t launch_duplicate(const ViewTable& vt, int64_t n, const Records& rec, 
   if (cap_vis == 0) return hipSuccess;
   const int nb = int((cap_vis + kProjThreads - 1) / kProjThreads);
   if (tm) tm->begin(K_DUP_COUNT);
-  k_sorted_counts<<<nb, kProjThreads, 0, s>>>(dvals, rec.counts, nvis, cap_vis, blocksums);
+  k_sorted_counts<<<nb, kProjThreads, 0, s>>>(dvals, rec.counts, nvis, cap_vis, overflow, blocksums);
   if (tm) tm->end(K_DUP_COUNT);
   if (tm) tm->begin(K_SCAN);
   k_scan_u32<<<1, 1024, 0, s>>>(blocksums, nb, total);
@@ -1177,12 +1257,12 @@ hipError_t launch_duplicate(const ViewTable& vt, int64_t n, const Records& rec, 
   return hipGetLastError();
 }
 
-hipError_t launch_ranges(const uint32_t* tkeys, const unsigned long long* count, int64_t cap, uint2* ranges,
-                         int total_tiles, hipStream_t s) {
+hipError_t launch_ranges(const uint32_t* tkeys, const unsigned long long* count, int64_t cap,
+                         const uint32_t* overflow, uint2* ranges, int total_tiles, hipStream_t s) {
   if (total_tiles > 0)
     k_fill_u32<<<blocks_for(int64_t(total_tiles) * 2, 256), 256, 0, s>>>(reinterpret_cast<uint32_t*>(ranges), 0u,
                                                                           int64_t(total_tiles) * 2);
-  if (cap > 0) k_ranges<<<blocks_for(cap, 256), 256, 0, s>>>(tkeys, count, cap, ranges);
+  if (cap > 0) k_ranges<<<blocks_for(cap, 256), 256, 0, s>>>(tkeys, count, cap, overflow, ranges, total_tiles);
   return hipGetLastError();
 }
 
@@ -1191,24 +1271,50 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
   return hipGetLastError();
 }
 
+// Persistent grid: as many blocks as fit on the device at once, at most one per tile.
+template <class Kern>
+static int resident_blocks(Kern kern, int threads) {
+  static int cached = -1;
+  if (cached < 0) {
+    int per_cu = 0, cus = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    (void)hipGetLastError();
+    cached = per_cu * cus;
+  }
+  return cached;
+}
+
 template <int TS, int BATCH>
 static void blend_fwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
-                        const uint32_t* vals, float* T_final, uint32_t* n_contrib, hipStream_t s) {
-  k_blend_fwd<TS, BATCH><<<vt.total_tiles, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib);
+                        const uint32_t* vals, float* T_final, uint32_t* n_contrib, uint32_t* n_used,
+                        const TileQueue& q, hipStream_t s) {
+  const int grid = std::min(vt.total_tiles, resident_blocks(k_blend_fwd<TS, BATCH>, TS * TS));
+  k_blend_fwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q);
+}
+
+hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* bucket_of, uint32_t* order,
+                             uint32_t* ctrl, hipStream_t s) {
+  if (total_tiles == 0) return hipSuccess;
+  k_tile_buckets<<<blocks_for(total_tiles, 256), 256, 0, s>>>(ranges, total_tiles, bucket_of, ctrl);
+  k_tile_order<<<blocks_for(total_tiles, 256), 256, 0, s>>>(bucket_of, total_tiles, ctrl, order);
+  return hipGetLastError();
 }
 
 hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
-                            hipStream_t s) {
+                            uint32_t* n_used, const TileQueue& q, hipStream_t s) {
   if (vt.total_tiles == 0) return hipSuccess;
   const bool b256 = batch == 256;
   switch (tile) {
-    case 8: b256 ? blend_fwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, s)
-                 : blend_fwd_t<8, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, s); break;
-    case 32: b256 ? blend_fwd_t<32, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, s)
-                  : blend_fwd_t<32, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, s); break;
-    default: b256 ? blend_fwd_t<16, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, s)
-                  : blend_fwd_t<16, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, s); break;
+    case 8: b256 ? blend_fwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, s)
+                 : blend_fwd_t<8, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, s); break;
+    case 32: b256 ? blend_fwd_t<32, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, s)
+                  : blend_fwd_t<32, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, s); break;
+    default: b256 ? blend_fwd_t<16, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, s)
+                  : blend_fwd_t<16, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, s); break;
   }
   return hipGetLastError();
 }
@@ -1224,22 +1330,23 @@ hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* loss, hipSt
 template <int TS, int BATCH>
 static void blend_bwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
                         const uint32_t* vals, const float* T_final, const uint32_t* n_contrib, float* grad2d,
-                        hipStream_t s) {
-  k_blend_bwd<TS, BATCH><<<vt.total_tiles, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d);
+                        const TileQueue& q, hipStream_t s) {
+  const int grid = std::min(vt.total_tiles, resident_blocks(k_blend_bwd<TS, BATCH>, TS * TS));
+  k_blend_bwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q);
 }
 
 hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, const float* T_final,
-                            const uint32_t* n_contrib, float* grad2d, hipStream_t s) {
+                            const uint32_t* n_contrib, float* grad2d, const TileQueue& q, hipStream_t s) {
   if (vt.total_tiles == 0) return hipSuccess;
   const bool b256 = batch == 256;
   switch (tile) {
-    case 8: b256 ? blend_bwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, s)
-                 : blend_bwd_t<8, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, s); break;
-    case 32: b256 ? blend_bwd_t<32, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, s)
-                  : blend_bwd_t<32, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, s); break;
-    default: b256 ? blend_bwd_t<16, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, s)
-                  : blend_bwd_t<16, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, s); break;
+    case 8: b256 ? blend_bwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, s)
+                 : blend_bwd_t<8, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, s); break;
+    case 32: b256 ? blend_bwd_t<32, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, s)
+                  : blend_bwd_t<32, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, s); break;
+    default: b256 ? blend_bwd_t<16, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, s)
+                  : blend_bwd_t<16, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, s); break;
   }
   return hipGetLastError();
 }

@@ -148,7 +148,8 @@ class Saved:
                    T_final=np.zeros(P, np.float32), n_contrib=np.zeros(P, np.uint32),
                    tiles_touched=np.zeros(R, np.uint32), mu=np.zeros((R, 2), np.float32),
                    depth=np.zeros(R, np.float32), conic=np.zeros((R, 3), np.float32),
-                   color=np.zeros((R, 3), np.float32), rect=np.zeros((R, 4), np.int32))
+                   color=np.zeros((R, 3), np.float32), rect=np.zeros((R, 4), np.int32),
+                   n_used=np.zeros(P, np.uint32))
         d = N.Debug(*(ctypes.c_void_p(out[k].ctypes.data) for k, _ in N.Debug._fields_))
         N.check(self.ctx.lib.gsr_debug_export(self.ctx.h, self.h, ctypes.byref(d)), self.ctx.h)
         return out
@@ -289,3 +290,116 @@ def render(means, scales, quats, opacities, sh, cameras, settings: Settings | No
     """Autograd-enabled render; returns [(color, depth, alpha)] per camera."""
     flat = GSRasterize.apply(means, scales, quats, opacities, sh, list(cameras), settings or Settings())
     return [tuple(flat[3 * i:3 * i + 3]) for i in range(len(cameras))]
+
+
+def _param_checks(means, scales, quats, opacities, sh):
+    dev = means.device
+    n = means.shape[0]
+    deg = _sh_degree(sh)
+    _need(means, "means", (n, 3), dev)
+    _need(scales, "scales", (n, 3), dev)
+    _need(quats, "quats", (n, 4), dev)
+    _need(opacities, "opacities", (n,), dev)
+    _need(sh, "sh", (n, (deg + 1) ** 2, 3), dev)
+    if n and quats.data_ptr() % 16:
+        raise ValueError("quats must be 16-byte aligned")
+    return dev, n, deg
+
+
+class Graph:
+    """One forward + L1 loss + backward step of several views, captured in a hipGraph.
+
+    The parameter tensors, targets and the output buffers created here are bound at
+    capture; ``launch()`` re-runs the step on their current contents (update the
+    parameters in place between launches).  ``images``, ``grad_color``/``grad_depth``,
+    ``grads`` and ``loss`` hold the latest step's results once the stream reaches it.
+    """
+
+    def __init__(self, means, scales, quats, opacities, sh, cameras, targets, settings: Settings | None = None,
+                 depth_weight: float = 0.1, headroom: float = 0.25):
+        settings = settings or Settings()
+        dev, n, deg = _param_checks(means, scales, quats, opacities, sh)
+        self.ctx = context(dev)
+        lib = self.ctx.lib
+        self.cameras = list(cameras)
+        V = len(self.cameras)
+        self.params = (means, scales, quats, opacities, sh)
+        self.targets = [(tc, td) for tc, td in targets]
+        self.images, outs = [], (N.ViewOut * V)()
+        tg = (N.Target * V)()
+        self.grad_color, self.grad_depth = [], []
+        gcp, gdp = (ctypes.c_void_p * V)(), (ctypes.c_void_p * V)()
+        for i, c in enumerate(self.cameras):
+            H, W = int(c.height), int(c.width)
+            col = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+            dep = torch.empty((H, W), dtype=torch.float32, device=dev)
+            alp = torch.empty((H, W), dtype=torch.float32, device=dev)
+            self.images.append((col, dep, alp))
+            outs[i] = N.ViewOut(col.data_ptr(), dep.data_ptr(), alp.data_ptr())
+            tc, td = self.targets[i]
+            _need(tc, "target color", col.shape, dev)
+            if td is not None:
+                _need(td, "target depth", dep.shape, dev)
+            tg[i] = N.Target(tc.data_ptr(), None if td is None else td.data_ptr())
+            gc, gd = torch.empty_like(col), torch.empty_like(dep)
+            self.grad_color.append(gc)
+            self.grad_depth.append(gd)
+            gcp[i], gdp[i] = gc.data_ptr(), gd.data_ptr()
+        self.grads = dict(means=torch.empty_like(means), scales=torch.empty_like(scales),
+                          quats=torch.empty_like(quats), opacities=torch.empty_like(opacities),
+                          sh=torch.empty_like(sh))
+        gg = N.GaussianGrads(*(self.grads[k].data_ptr() for k in ("means", "scales", "quats", "opacities", "sh")))
+        self.loss = torch.zeros((), dtype=torch.float32, device=dev)
+        g = N.Gaussians(n, deg, means.data_ptr(), scales.data_ptr(), quats.data_ptr(), opacities.data_ptr(),
+                        sh.data_ptr())
+        s = settings.c()
+        self.settings = settings
+        h = ctypes.c_void_p()
+        N.check(lib.gsr_graph_create(self.ctx.h, ctypes.byref(g), _cams(self.cameras), V, ctypes.byref(s), outs, tg,
+                                     float(depth_weight), gcp, gdp, ctypes.byref(gg),
+                                     ctypes.c_void_p(self.loss.data_ptr()), float(headroom), ctypes.byref(h)),
+                self.ctx.h)
+        self.h = h
+
+    def launch(self):
+        N.check(self.ctx.lib.gsr_graph_launch(self.h), self.ctx.h)
+
+    def sync(self):
+        N.check(self.ctx.lib.gsr_graph_sync(self.h), self.ctx.h)
+
+    def info(self) -> dict:
+        inf = N.Info()
+        ck, cv = ctypes.c_int64(), ctypes.c_int64()
+        N.check(self.ctx.lib.gsr_graph_info(self.h, ctypes.byref(inf), ctypes.byref(ck), ctypes.byref(cv)),
+                self.ctx.h)
+        d = {k: getattr(inf, k) for k, _ in N.Info._fields_}
+        d.update(capacity_keys=ck.value, capacity_visible=cv.value)
+        return d
+
+    def free(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.ctx.lib.gsr_graph_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def autotune(means, scales, quats, opacities, sh, cameras, settings: Settings | None = None,
+             use_cache: bool = True):
+    """Pick (tile, batch) for this workload by timing forward + backward at every launch
+    shape (or from the cache).  Returns (settings with tile/batch set, step ms)."""
+    import dataclasses
+    settings = settings or Settings()
+    dev, n, deg = _param_checks(means, scales, quats, opacities, sh)
+    ctx = context(dev)
+    g = N.Gaussians(n, deg, means.data_ptr(), scales.data_ptr(), quats.data_ptr(), opacities.data_ptr(),
+                    sh.data_ptr())
+    s = settings.c()
+    ms = ctypes.c_float()
+    N.check(ctx.lib.gsr_autotune(ctx.h, ctypes.byref(g), _cams(cameras), len(cameras), ctypes.byref(s),
+                                 0 if use_cache else N.AUTOTUNE_NO_CACHE, ctypes.byref(ms)), ctx.h)
+    return dataclasses.replace(settings, tile=int(s.tile), batch=int(s.batch)), float(ms.value)

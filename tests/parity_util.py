@@ -95,6 +95,8 @@ def check_images(images, outs, dbg=None, cams=None, tol=IMG_TOL):
             H, W = dep.shape
             nc = dbg["n_contrib"][off:off + H * W].reshape(H, W)
             np.testing.assert_array_equal(nc[ok], o["n_contrib"][ok])
+            nu = dbg["n_used"][off:off + H * W].reshape(H, W)
+            np.testing.assert_array_equal(nu[ok], o["n_used"][ok])
             tf = dbg["T_final"][off:off + H * W].reshape(H, W)
             assert np.abs(tf[ok] - o["T_final"][ok]).max(initial=0) <= tol
             off += H * W
