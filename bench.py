@@ -174,6 +174,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--autotune", type=int, default=1, help="pick (tile, batch) by timing first (1) or not (0)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
+                    help="first run a plain device copy of this many MiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); multi-GPU runs are "
@@ -184,6 +186,17 @@ def main():
     import scenes
     from paper_2408_12677_amd import rasterize as R
 
+    if args.copy_probe:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters give the
+        # scale that turns the counters of the rasterizer kernels into HBM bytes
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 copies of {nbytes} bytes")
+        del src, dst
     log("generating the 500k-Gaussian room map and its 8 orbit views")
     t0 = time.perf_counter()
     w = scenes.make_cfg4()

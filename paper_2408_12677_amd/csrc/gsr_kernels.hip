@@ -47,6 +47,57 @@ __device__ __forceinline__ float wave_sum_to_lane63(float v) {
   return v;
 }
 
+// gfx950 lane-half / row swaps: (a, b) -> a's upper 32 lanes exchanged with b's lower 32
+// (permlane32), or a's odd 16-lane rows exchanged with b's even rows (permlane16).
+__device__ __forceinline__ void swap_halves(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(int, a), __builtin_bit_cast(int, b), false, false);
+  a = __builtin_bit_cast(float, int(r[0]));
+  b = __builtin_bit_cast(float, int(r[1]));
+}
+__device__ __forceinline__ void swap_rows(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(int, a), __builtin_bit_cast(int, b), false, false);
+  a = __builtin_bit_cast(float, int(r[0]));
+  b = __builtin_bit_cast(float, int(r[1]));
+}
+
+// Sums of ten per-lane values over the wavefront in 28 instructions: lane halves are folded
+// pairwise (5 swaps + 5 adds), then 16-lane rows (3 swaps + 3 adds), then each row is
+// reduced with 4 fused DPP adds.  Every lane of a row ends with its row's total:
+//   w0 rows 0..3 = sums of v0, v2, v1, v3;  w1 rows = v4, v6, v5, v7;  w2 rows = v8, v8, v9, v9.
+// Needs every lane active.
+__device__ __forceinline__ void wave_sum10(const float (&v)[10], float& w0, float& w1, float& w2) {
+  float u[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    float a = v[2 * i], b = v[2 * i + 1];
+    swap_halves(a, b);
+    u[i] = a + b;
+  }
+  float a = u[0], b = u[1];
+  swap_rows(a, b);
+  w0 = a + b;
+  a = u[2];
+  b = u[3];
+  swap_rows(a, b);
+  w1 = a + b;
+  a = u[4];
+  b = u[4];
+  swap_rows(a, b);
+  w2 = a + b;
+  w0 += dpp_move<0xB1, 0xF>(w0);
+  w1 += dpp_move<0xB1, 0xF>(w1);
+  w2 += dpp_move<0xB1, 0xF>(w2);
+  w0 += dpp_move<0x4E, 0xF>(w0);
+  w1 += dpp_move<0x4E, 0xF>(w1);
+  w2 += dpp_move<0x4E, 0xF>(w2);
+  w0 += dpp_move<0x141, 0xF>(w0);
+  w1 += dpp_move<0x141, 0xF>(w1);
+  w2 += dpp_move<0x141, 0xF>(w2);
+  w0 += dpp_move<0x140, 0xF>(w0);
+  w1 += dpp_move<0x140, 0xF>(w1);
+  w2 += dpp_move<0x140, 0xF>(w2);
+}
+
 __device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   const int nw = blockDim.x >> 6;
@@ -522,19 +573,24 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
                                                                 const uint32_t* overflow, int shift,
                                                                 const uint32_t* hist, const uint32_t* digit_tot,
                                                                 int nblk) {
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[kSortThreads / 64][256];
+  // bases and per-wavefront counters are double buffered so each round needs two barriers
+  __shared__ uint32_t base[2][256];
+  __shared__ uint32_t wcnt[2][kSortThreads / 64][256];
   __shared__ uint32_t red[kSortThreads / 64];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t M = clamp_count(count, cap, overflow);
   const uint32_t ex = block_exclusive_scan_u32(digit_tot[t], red);
-  base[t] = ex + hist[int64_t(t) * nblk + blockIdx.x];
+  base[0][t] = ex + hist[int64_t(t) * nblk + blockIdx.x];
 #pragma unroll
-  for (int i = 0; i < kSortThreads / 64; ++i) wcnt[i][t] = 0;
+  for (int i = 0; i < kSortThreads / 64; ++i) {
+    wcnt[0][i][t] = 0;
+    wcnt[1][i][t] = 0;
+  }
   __syncthreads();
   const int64_t b0 = int64_t(blockIdx.x) * kSortTile;
   const uint64_t lt_mask = (1ull << lane) - 1ull;
   for (int r = 0; r < kSortItems; ++r) {
+    const int b = r & 1;
     const int64_t idx = b0 + r * kSortThreads + t;
     const bool valid = idx < M;
     uint32_t key = 0, val = 0, d = 0;
@@ -551,26 +607,24 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
       peers &= on ? m : ~m;
     }
     const uint32_t rank = __popcll(peers & lt_mask);
-    if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+    if (valid && rank == 0) wcnt[b][w][d] = __popcll(peers);
     __syncthreads();
+    // digit t: offsets of the four wavefronts, next round's base, clear next round's counters
     uint32_t run = 0;
 #pragma unroll
     for (int i = 0; i < kSortThreads / 64; ++i) {
-      const uint32_t c = wcnt[i][t];
-      wcnt[i][t] = run;
+      const uint32_t c = wcnt[b][i][t];
+      wcnt[b][i][t] = run;
       run += c;
+      wcnt[b ^ 1][i][t] = 0;
     }
+    base[b ^ 1][t] = base[b][t] + run;
     __syncthreads();
     if (valid) {
-      const uint32_t dst = base[d] + wcnt[w][d] + rank;
+      const uint32_t dst = base[b][d] + wcnt[b][w][d] + rank;
       kout[dst] = key;
       vout[dst] = val;
     }
-    __syncthreads();
-    base[t] += run;
-#pragma unroll
-    for (int i = 0; i < kSortThreads / 64; ++i) wcnt[i][t] = 0;
-    __syncthreads();
   }
 }
 
@@ -852,7 +906,8 @@ __global__ void k_zero_f32(float* p) { *p = 0.f; }
 // final value; the colour/depth behind i is carried as a running blend.
 //
 // Each wavefront walks the staged batch only down from its own longest contributor list.
-// The ten per-(pixel, splat) partials are summed across the wavefront with DPP; with more
+// The ten per-(pixel, splat) partials are summed across the wavefront with lane swaps
+// and DPP (wave_sum10); with more
 // than one wavefront per tile the wavefront sums meet in LDS and the block adds each
 // splat's total to the 2D-gradient buffer once per batch, with the atomics spread over
 // all lanes.
@@ -963,40 +1018,21 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
         }
       }
       if (__ballot(act) != 0ull) {
-        g0 = wave_sum_to_lane63(g0);
-        g1 = wave_sum_to_lane63(g1);
-        g2 = wave_sum_to_lane63(g2);
-        g3 = wave_sum_to_lane63(g3);
-        g4 = wave_sum_to_lane63(g4);
-        g5 = wave_sum_to_lane63(g5);
-        g6 = wave_sum_to_lane63(g6);
-        g7 = wave_sum_to_lane63(g7);
-        g8 = wave_sum_to_lane63(g8);
-        g9 = wave_sum_to_lane63(g9);
-        if (lane == 63) {
+        const float gv[10] = {g0, g1, g2, g3, g4, g5, g6, g7, g8, g9};
+        float w0, w1, w2;
+        wave_sum10(gv, w0, w1, w2);
+        if ((lane & 15) == 0) {  // one lane per row adds its row's totals
+          const int row = lane >> 4;
+          const int k = row == 1 ? 2 : (row == 2 ? 1 : row);
           if (kBlockSum) {
-            atomicAdd(&s_g[0][j], g0);
-            atomicAdd(&s_g[1][j], g1);
-            atomicAdd(&s_g[2][j], g2);
-            atomicAdd(&s_g[3][j], g3);
-            atomicAdd(&s_g[4][j], g4);
-            atomicAdd(&s_g[5][j], g5);
-            atomicAdd(&s_g[6][j], g6);
-            atomicAdd(&s_g[7][j], g7);
-            atomicAdd(&s_g[8][j], g8);
-            atomicAdd(&s_g[9][j], g9);
+            atomicAdd(&s_g[k][j], w0);
+            atomicAdd(&s_g[4 + k][j], w1);
+            if (!(row & 1)) atomicAdd(&s_g[8 + (row >> 1)][j], w2);
           } else {
             float* dst = grad2d + int64_t(s_id[j]) * kGrad2D;
-            unsafeAtomicAdd(dst + 0, g0);
-            unsafeAtomicAdd(dst + 1, g1);
-            unsafeAtomicAdd(dst + 2, g2);
-            unsafeAtomicAdd(dst + 3, g3);
-            unsafeAtomicAdd(dst + 4, g4);
-            unsafeAtomicAdd(dst + 5, g5);
-            unsafeAtomicAdd(dst + 6, g6);
-            unsafeAtomicAdd(dst + 7, g7);
-            unsafeAtomicAdd(dst + 8, g8);
-            unsafeAtomicAdd(dst + 9, g9);
+            unsafeAtomicAdd(dst + k, w0);
+            unsafeAtomicAdd(dst + 4 + k, w1);
+            if (!(row & 1)) unsafeAtomicAdd(dst + 8 + (row >> 1), w2);
           }
         }
       }
@@ -1030,27 +1066,41 @@ template <int DEG>
 __global__ __launch_bounds__(kProjThreads) void k_project_bwd(GaussDev g, ViewTable vt, Rules ru, Records rec,
                                                               const float* grad2d, GradOut out) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
-  if (gi >= g.n) return;
-  float p[3], s[3], q[4], sh[K * 3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    p[i] = g.means[gi * 3 + i];
-    s[i] = g.scales[gi * 3 + i];
+  constexpr int KK = K * 3;        // SH floats per Gaussian
+  constexpr int STRIDE = KK | 1;   // odd LDS row stride: conflict-free per-thread rows
+  // the block's SH coefficients pass through LDS so that the global loads and stores of
+  // the [N, K, 3] array are contiguous across lanes
+  __shared__ float s_sh[kProjThreads * STRIDE];
+  const int64_t g0 = int64_t(blockIdx.x) * kProjThreads;
+  const int64_t gi = g0 + threadIdx.x;
+  const bool valid = gi < g.n;
+  const int nb = int(min<int64_t>(kProjThreads, g.n - g0));
+  for (int i = threadIdx.x; i < nb * KK; i += kProjThreads) {
+    const int r = i / KK;
+    s_sh[r * STRIDE + (i - r * KK)] = g.sh[g0 * KK + i];
   }
-  const float4 q4 = reinterpret_cast<const float4*>(g.quats)[gi];
-  q[0] = q4.x;
-  q[1] = q4.y;
-  q[2] = q4.z;
-  q[3] = q4.w;
-  const float* src = g.sh + gi * (K * 3);
+  __syncthreads();
+  float p[3] = {0.f, 0.f, 0.f}, s[3] = {1.f, 1.f, 1.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, sh[KK];
 #pragma unroll
-  for (int i = 0; i < K * 3; ++i) sh[i] = src[i];
+  for (int i = 0; i < KK; ++i) sh[i] = s_sh[threadIdx.x * STRIDE + i];
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      p[i] = g.means[gi * 3 + i];
+      s[i] = g.scales[gi * 3 + i];
+    }
+    const float4 q4 = reinterpret_cast<const float4*>(g.quats)[gi];
+    q[0] = q4.x;
+    q[1] = q4.y;
+    q[2] = q4.z;
+    q[3] = q4.w;
+  }
   float dp[3] = {0.f, 0.f, 0.f}, ds[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f}, dop = 0.f;
-  float dsh[K * 3];
+  float dsh[KK];
 #pragma unroll
-  for (int i = 0; i < K * 3; ++i) dsh[i] = 0.f;
+  for (int i = 0; i < KK; ++i) dsh[i] = 0.f;
   for (int v = 0; v < vt.nviews; ++v) {
+    if (!valid) break;
     const int64_t rid = int64_t(v) * g.n + gi;
     if (rec.counts[rid] == 0) continue;
     const ViewDev& cam = vt.v[v];
@@ -1161,16 +1211,25 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(GaussDev g, ViewTa
     dq[3] += (dqz - z * qd) * inq;
   }
   const int acc = out.accumulate;
-  if (out.means)
-    for (int i = 0; i < 3; ++i) store_grad(out.means + gi * 3 + i, dp[i], acc);
-  if (out.scales)
-    for (int i = 0; i < 3; ++i) store_grad(out.scales + gi * 3 + i, ds[i], acc);
-  if (out.quats)
-    for (int i = 0; i < 4; ++i) store_grad(out.quats + gi * 4 + i, dq[i], acc);
-  if (out.opac) store_grad(out.opac + gi, dop, acc);
-  if (out.sh)
+  if (valid) {
+    if (out.means)
+      for (int i = 0; i < 3; ++i) store_grad(out.means + gi * 3 + i, dp[i], acc);
+    if (out.scales)
+      for (int i = 0; i < 3; ++i) store_grad(out.scales + gi * 3 + i, ds[i], acc);
+    if (out.quats)
+      for (int i = 0; i < 4; ++i) store_grad(out.quats + gi * 4 + i, dq[i], acc);
+    if (out.opac) store_grad(out.opac + gi, dop, acc);
+  }
+  if (out.sh) {  // back through LDS for contiguous stores
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < K * 3; ++i) store_grad(out.sh + gi * (K * 3) + i, dsh[i], acc);
+    for (int i = 0; i < KK; ++i) s_sh[threadIdx.x * STRIDE + i] = dsh[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb * KK; i += kProjThreads) {
+      const int r = i / KK;
+      store_grad(out.sh + g0 * KK + i, s_sh[r * STRIDE + (i - r * KK)], acc);
+    }
+  }
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return unsigned((n + per - 1) / per); }
