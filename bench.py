@@ -16,6 +16,9 @@ of the dominant kernel; the FP64 CPU oracle timed on this host.
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ("paper_2408_12677_amd/csrc/gsr_kernels.hip", "paper_2408_12677_amd/csrc/gsr_internal.h")
 HEADLINE_VIEW = 2              # first 640x480 view of the 8-view orbit
 DEPTH_W = 0.1
 
@@ -65,6 +70,72 @@ def kernel_bytes(name, st):
     return 0
 
 
+# ------------------------------------------------------------------------------------
+# measured HBM traffic (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated by a plain copy)
+# ------------------------------------------------------------------------------------
+def kernels_sha():
+    """Digest of the kernel sources; stored traffic is only reported for the same sources."""
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def short_kernel_name(full):
+    """'void gsr::(anonymous namespace)::k_blend_bwd<16, 256>(...)' -> 'blend_bwd'."""
+    n = full.split("(gsr::")[0] if full.startswith("void gsr::") else full
+    n = n.replace("void ", "").replace("gsr::(anonymous namespace)::", "")
+    n = n.split("(")[0].split("<")[0].strip()
+    return n[2:] if n.startswith("k_") else n
+
+
+def traffic_from_counters(fetch_dir, write_dir, copy_mb):
+    """Per-kernel HBM bytes per dispatch from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE; both count KiB per dispatch).  Each counter is scaled by the factor that
+    makes it read the known size of the largest plain copy of ``copy_mb`` MiB in the run."""
+    def load(d, counter):
+        per = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    if row.get("Counter_Name") == counter:
+                        per.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]) * 1024.0)
+        return per
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy_bytes = copy_mb << 20
+    copies = [k for k in fetch if "copyBuffer" in k]
+    if not copies:
+        raise SystemExit("no copy kernel in the FETCH_SIZE run: profile bench.py --copy-probe MB")
+    ck = max(copies, key=lambda k: max(fetch[k]))
+    ff = copy_bytes / max(fetch[ck])
+    fw = copy_bytes / max(write.get(ck, [copy_bytes]))
+    kernels = {}
+    for k in fetch:
+        if "gsr::" not in k:
+            continue
+        fv, wv = fetch[k], write.get(k, [0.0])
+        name = short_kernel_name(k)
+        kernels[name] = dict(dispatches=len(fv), fetch_bytes=round(ff * sum(fv) / len(fv)),
+                             write_bytes=round(fw * sum(wv) / len(wv)))
+    return dict(kernels_sha=kernels_sha(), copy_kernel=ck, copy_bytes=copy_bytes,
+                fetch_factor=round(ff, 5), write_factor=round(fw, 5), kernels=kernels)
+
+
+def stored_traffic(name):
+    """Measured HBM bytes per launch of kernel ``name`` (fetch + write), or None when no
+    counters were taken for the current kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    k = t.get("kernels", {}).get(name)
+    if k is None or t.get("kernels_sha") != kernels_sha():
+        return None
+    return int(k["fetch_bytes"] + k["write_bytes"])
+
+
 FP32_PEAK_TFLOPS = 157.3      # MI355X FP32 vector (packed); unpacked FMA issue is half of it
 FLOPS_EVAL = 13                 # one splat evaluation: dx, dy, the quadratic form, exp, o*G, compare
 FLOPS_FWD_CONTRIB = 12          # forward accumulation of one contributor (clamp, 4 FMA, T update)
@@ -83,11 +154,12 @@ def kernel_roofline(name, st, alg_bytes, avg_us):
             flops = st["E_bwd"] * FLOPS_EVAL + st["E_used"] * FLOPS_BWD_CONTRIB + st["wave_hits"] * FLOPS_WAVE_SUM
         ach = flops / sec / 1e12
         return dict(bound="alu", kernel=name, achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=None, alg_flops_per_launch=int(flops),
+                    frac=round(ach / FP32_PEAK_TFLOPS, 4), traffic=stored_traffic(name),
+                    alg_flops_per_launch=int(flops),
                     alg_bytes_per_launch=int(alg_bytes), avg_launch_us=round(avg_us, 2))
     ach = alg_bytes / sec / 1e9 if alg_bytes else 0.0
     return dict(bound="hbm", kernel=name, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, alg_bytes_per_launch=int(alg_bytes),
+                frac=round(ach / HBM_PEAK_GBS, 4), traffic=stored_traffic(name), alg_bytes_per_launch=int(alg_bytes),
                 avg_launch_us=round(avg_us, 2))
 
 
@@ -176,7 +248,19 @@ def main():
     ap.add_argument("--autotune", type=int, default=1, help="pick (tile, batch) by timing first (1) or not (0)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of this many MiB (counter calibration under rocprofv3)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU: turn two rocprofv3 --pmc runs of bench.py --copy-probe MB into "
+                         "profiles/traffic.json and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        t = traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.copy_probe or 256)
+        with open(TRAFFIC_FILE, "w") as f:
+            json.dump(t, f, indent=1)
+            f.write("\n")
+        for k, v in sorted(t["kernels"].items(), key=lambda kv: -kv[1]["fetch_bytes"] - kv[1]["write_bytes"]):
+            print(f"{k:16s} x{v['dispatches']:4d}  fetch {v['fetch_bytes'] / 1e6:9.2f} MB  "
+                  f"write {v['write_bytes'] / 1e6:9.2f} MB")
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); multi-GPU runs are "
               "not part of it.", file=sys.stderr)
