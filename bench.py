@@ -49,14 +49,17 @@ def kernel_bytes(name, st):
     pg = 4 * (3 + 3 + 4 + 1 + 3 * K)            # parameter bytes per Gaussian
     if name == "project":
         return N * pg + V * N * 4 + Nv * (16 * 3 + 8)
-    if name == "duplicate":
-        return V * N * 4 + Nv * (8 + 16) + M * 12
-    if name == "radix_hist":
-        return M * 8
+    E1 = st["E_rows"]
+    if name == "radix_hist":                     # depth digits of the visible records
+        return Nv * 4
     if name == "radix_scatter":
-        return M * 12 * 2
+        return Nv * 16
+    if name == "bin_count":                      # mean of the row and the tile histogram launches
+        return (Nv * 12 + E1 * 8) / 2
+    if name == "bin_scatter":                    # mean of the row and the tile placement launches
+        return (Nv * 12 + E1 * 8 + E1 * 8 + M * 4) / 2
     if name == "ranges":
-        return M * 8 + st["tiles"] * 8
+        return st["tiles"] * 32
     if name == "blend_fwd":
         return st["loaded_fwd"] * (4 + 48) + P * 28
     if name == "blend_bwd":
@@ -215,10 +218,12 @@ def step_stats(R, params, cams, targets, settings):
         e_fwd += int(np.where(tf < settings.T_min, nc, L).sum())
         off += H * W
     e_used = int(dbg["n_used"].astype(np.int64).sum()) if "n_used" in dbg else int(nc_all.sum())
+    vis = dbg["tiles_touched"] > 0
+    e_rows = int((dbg["rect"][vis, 3] - dbg["rect"][vis, 2] + 1).astype(np.int64).sum())
     st = dict(N=int(params[0].shape[0]), V=len(cams), N_vis=int((dbg["tiles_touched"] > 0).sum()),
               M=int(inf["num_keys"]), P=int(inf["num_pixels"]), K=int(params[4].shape[1]),
               tiles=int(inf["num_tiles"]), sort_passes=int(inf["sort_passes"]), loaded_fwd=loaded_fwd,
-              loaded_bwd=loaded_bwd, wave_hits=wave_hits,
+              loaded_bwd=loaded_bwd, wave_hits=wave_hits, E_rows=e_rows,
               E_bwd=int(nc_all.sum()), E_fwd=e_fwd, E_used=e_used)
     saved.free()
     return st
@@ -361,7 +366,7 @@ def main():
         "roofline": roofline,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in per_kernel.items()},
         "ms_per_step_with_event_timer": round(ms_timed, 4),
-        "work": {k: stats[k] for k in ("N_vis", "M", "P", "tiles", "sort_passes", "E_bwd", "E_used")},
+        "work": {k: stats[k] for k in ("N_vis", "M", "E_rows", "P", "tiles", "sort_passes", "E_bwd", "E_used")},
     }
 
     if not args.no_batched:

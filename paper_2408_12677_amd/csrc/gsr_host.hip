@@ -42,15 +42,14 @@ struct gsr_saved {
   unsigned long long* d_total = nullptr;  // [0] pairs M, [1] visible records, [2] pairs written
   int64_t M = 0, n_vis = 0;               // measured sizes (eager) or sizes at creation (graph)
   int64_t cap_M = 0, cap_vis = 0;         // buffer capacities
-  // sort buffers
+  // depth sort and binning buffers
   uint32_t *dk = nullptr, *dv = nullptr, *dk2 = nullptr, *dv2 = nullptr;
-  uint32_t *tk = nullptr, *tv = nullptr, *tk2 = nullptr, *tv2 = nullptr;
-  uint32_t *hist = nullptr, *dtot = nullptr, *bs2 = nullptr;
-  uint32_t* tiles = nullptr;  // sorted tile id of every pair (points at tk or tk2)
-  uint32_t* vals = nullptr;   // sorted record id of every pair (tv or tv2)
+  uint32_t *hist = nullptr, *dtot = nullptr;
+  BinPlan plan{};
+  uint32_t* vals = nullptr;   // record id of every (tile, record) pair, in key order
   uint2* ranges = nullptr;
   uint32_t* order = nullptr;
-  uint32_t* bucket_of = nullptr;
+  float* loss_part = nullptr;  // block partial sums of the loss
   uint32_t* ctrl = nullptr;
   float* T_final = nullptr;
   uint32_t* n_contrib = nullptr;
@@ -76,10 +75,10 @@ struct gsr_graph {
 
 namespace {
 
-const char* const kKernelNames[K_COUNT] = {"project",    "scan",      "compact",   "sorted_counts", "duplicate",
-                                           "radix_hist", "radix_rowscan", "radix_scatter", "ranges",
-                                           "tile_order", "fill",      "blend_fwd", "loss_l1",   "blend_bwd",
-                                           "project_bwd"};
+const char* const kKernelNames[K_COUNT] = {"project",    "scan",          "compact",       "radix_hist",
+                                           "radix_rowscan", "radix_scatter", "bin_count",   "bin_scan",
+                                           "bin_scatter", "ranges",        "tile_order",    "fill",
+                                           "blend_fwd",  "loss_l1",       "blend_bwd",     "project_bwd"};
 
 thread_local std::string g_noctx_err;
 
@@ -209,7 +208,7 @@ gsr_status make_saved(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* ca
   ViewTable& vt = sv->vt;
   std::memset(&vt, 0, sizeof(vt));
   vt.nviews = V;
-  int64_t tiles = 0, pix = 0;
+  int64_t tiles = 0, pix = 0, rows = 0;
   for (int v = 0; v < V; ++v) {
     const gsr_camera& c = cams[v];
     ViewDev& d = vt.v[v];
@@ -228,14 +227,18 @@ gsr_status make_saved(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* ca
     d.tiles_x = (c.width + s->tile - 1) / s->tile;
     d.tiles_y = (c.height + s->tile - 1) / s->tile;
     d.tile_off = int32_t(tiles);
+    d.row_off = int32_t(rows);
     d.pix_off = pix;
     d.color = outs[v].color;
     d.depth = outs[v].depth;
     d.alpha = outs[v].alpha;
     tiles += int64_t(d.tiles_x) * d.tiles_y;
+    rows += d.tiles_y;
+    vt.max_tiles_x = std::max(vt.max_tiles_x, d.tiles_x);
     pix += int64_t(c.width) * c.height;
   }
   vt.total_tiles = int32_t(tiles);
+  vt.total_rows = int32_t(rows);
   sv->total_pix = pix;
   const int64_t VN = int64_t(V) * g->n;
   sv->nblk = int((g->n + kProjThreads - 1) / kProjThreads);
@@ -247,7 +250,7 @@ gsr_status make_saved(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* ca
       (st = alloc_in(sv, B, &sv->blocksums, size_t(V) * sv->nblk + 1)) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->d_total, 4)) != GSR_OK || (st = alloc_in(sv, B, &sv->ranges, size_t(tiles))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->order, size_t(tiles))) != GSR_OK ||
-      (st = alloc_in(sv, B, &sv->bucket_of, size_t(tiles))) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->loss_part, size_t(loss_partials(vt)))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->ctrl, kCtrlWords)) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->T_final, size_t(pix))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->n_contrib, size_t(pix))) != GSR_OK ||
@@ -259,23 +262,27 @@ gsr_status make_saved(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* ca
   return GSR_OK;
 }
 
-// Sort buffers for capacities (cap_vis, cap_M).  Eager forwards put all but the final
-// pair buffers in `temps`.
+// Depth-sort and binning buffers for capacities (cap_vis, cap_M).  The pair list is kept
+// with the saved state; eager forwards put everything else in `temps`.
 gsr_status alloc_sort(gsr_saved* sv, int64_t cap_vis, int64_t cap_M, bool persistent) {
   sv->cap_vis = cap_vis;
   sv->cap_M = cap_M;
   std::vector<void*>& T = persistent ? sv->blocks : sv->temps;
-  const int64_t sort_cap = std::max(cap_vis, cap_M);
-  const int64_t nb_sort = (sort_cap + kSortTile - 1) / kSortTile;
-  const int64_t nb_vis = (cap_vis + kProjThreads - 1) / kProjThreads;
+  const int64_t nb_sort = (cap_vis + kSortTile - 1) / kSortTile;
+  BinPlan& p = sv->plan;
+  p = bin_plan(sv->vt, cap_vis, cap_M);
+  const int64_t n1 = int64_t(p.rows) * p.nch1;
+  const int64_t nparts = (std::max(n1, p.cap_flat) + kScanTile - 1) / kScanTile;
   gsr_status st = GSR_OK;
   if ((st = alloc_in(sv, T, &sv->dk, cap_vis)) != GSR_OK || (st = alloc_in(sv, T, &sv->dv, cap_vis)) != GSR_OK ||
       (st = alloc_in(sv, T, &sv->dk2, cap_vis)) != GSR_OK || (st = alloc_in(sv, T, &sv->dv2, cap_vis)) != GSR_OK ||
-      (st = alloc_in(sv, sv->blocks, &sv->tk, cap_M)) != GSR_OK ||
-      (st = alloc_in(sv, sv->blocks, &sv->tv, cap_M)) != GSR_OK ||
-      (st = alloc_in(sv, T, &sv->tk2, cap_M)) != GSR_OK || (st = alloc_in(sv, T, &sv->tv2, cap_M)) != GSR_OK ||
       (st = alloc_in(sv, T, &sv->hist, size_t(nb_sort) * 256)) != GSR_OK ||
-      (st = alloc_in(sv, T, &sv->dtot, 256)) != GSR_OK || (st = alloc_in(sv, T, &sv->bs2, size_t(nb_vis) + 1)) != GSR_OK)
+      (st = alloc_in(sv, T, &sv->dtot, 256)) != GSR_OK || (st = alloc_in(sv, sv->blocks, &sv->vals, cap_M)) != GSR_OK ||
+      (st = alloc_in(sv, T, &p.cnt1, size_t(n1))) != GSR_OK || (st = alloc_in(sv, T, &p.rowlist, cap_M)) != GSR_OK ||
+      (st = alloc_in(sv, T, &p.rowinfo, size_t(p.rows))) != GSR_OK ||
+      (st = alloc_in(sv, T, &p.seg_start, size_t(p.rows) + 1)) != GSR_OK ||
+      (st = alloc_in(sv, T, &p.cntF, size_t(p.cap_flat))) != GSR_OK ||
+      (st = alloc_in(sv, T, &p.part, size_t(nparts))) != GSR_OK || (st = alloc_in(sv, T, &p.words, 4)) != GSR_OK)
     return st;
   return GSR_OK;
 }
@@ -294,8 +301,8 @@ hipError_t enqueue_project(gsr_saved* sv, hipStream_t s, bool timing) {
   return e;
 }
 
-// Phase B: the sort (depth digits on the visible records, duplication in depth order,
-// tile digits on the pairs), tile ranges, the tile queue and the forward compositing.
+// Phase B: the depth sort of the visible records, their stable binning into tile lists
+// (which also gives the tile ranges), the tile queue and the forward compositing.
 hipError_t enqueue_sort_blend(gsr_saved* sv, hipStream_t s, bool timing) {
   gsr_ctx* ctx = sv->ctx;
   Timer* tm = (timing && ctx->timer.on) ? &ctx->timer : nullptr;
@@ -303,38 +310,25 @@ hipError_t enqueue_sort_blend(gsr_saved* sv, hipStream_t s, bool timing) {
   auto T = [&](int k, auto f) { return timing ? timed(ctx, s, k, f) : f(); };
   uint32_t* ovf = sv->ctrl + kOverflow;
   hipError_t e = hipSuccess;
-  sv->tiles = sv->tk;
-  sv->vals = sv->tv;
   sv->sort_passes = 0;
+  const uint32_t* sorted = sv->dv;
   if (sv->cap_M > 0 && sv->cap_vis > 0) {
-    const int tile_bits = bits_for(uint64_t(sv->vt.total_tiles > 0 ? sv->vt.total_tiles - 1 : 0));
-    bool alt1 = false, alt2 = false;
-    int p1 = 0, p2 = 0;
+    bool alt = false;
     e = T(K_COMPACT, [&] {
-      return launch_compact(sv->N, sv->V, sv->rec, sv->blocksums, sv->nblk, sv->dk, sv->dv, sv->cap_vis, ovf, s);
+      return launch_compact(sv->N, sv->V, sv->rec, sv->blocksums, sv->nblk, sv->d_total, sv->cap_M, sv->dk, sv->dv,
+                            sv->cap_vis, ovf, s);
     });
     if (e == hipSuccess)
       e = launch_radix_sort(sv->dk, sv->dv, sv->dk2, sv->dv2, sv->hist, sv->dtot, sv->d_total + 1, sv->cap_vis, ovf,
-                            32, &alt1, &p1, s, tm);
-    if (e == hipSuccess)
-      e = launch_duplicate(sv->vt, sv->N, sv->rec, alt1 ? sv->dv2 : sv->dv, sv->d_total + 1, sv->cap_vis, sv->bs2,
-                           sv->d_total + 2, sv->tk, sv->tv, sv->cap_M, ovf, s, tm);
-    if (e == hipSuccess)
-      e = launch_radix_sort(sv->tk, sv->tv, sv->tk2, sv->tv2, sv->hist, sv->dtot, sv->d_total, sv->cap_M, ovf,
-                            tile_bits, &alt2, &p2, s, tm);
-    if (alt2) {
-      sv->tiles = sv->tk2;
-      sv->vals = sv->tv2;
-    }
-    sv->sort_passes = p1 + p2;
+                            32, &alt, &sv->sort_passes, s, tm);
+    if (alt) sorted = sv->dv2;
   }
   if (e == hipSuccess)
-    e = T(K_RANGES, [&] {
-      return launch_ranges(sv->tiles, sv->d_total, sv->cap_M, ovf, sv->ranges, sv->vt.total_tiles, s);
-    });
+    e = launch_bin(sv->vt, sv->N, sv->rec, sorted, sv->d_total + 1, sv->cap_vis, sv->plan, sv->vals, sv->ranges, ovf,
+                   s, tm);
   if (e == hipSuccess)
     e = T(K_TILE_ORDER, [&] {
-      return launch_tile_order(sv->ranges, sv->vt.total_tiles, sv->bucket_of, sv->order, sv->ctrl, s);
+      return launch_tile_order(sv->ranges, sv->vt.total_tiles, sv->order, s);
     });
   if (e == hipSuccess)
     e = T(K_BLEND_FWD, [&] {
@@ -399,13 +393,7 @@ gsr_status forward_eager(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera*
     release(sv);
     return fail(ctx, GSR_EDEVICE, std::string("forward (sort/blend) failed: ") + hipGetErrorString(e));
   }
-  // keep the final sorted pair buffers, return every temporary to the pool
-  if (sv->tiles == sv->tk2) {
-    std::replace(sv->temps.begin(), sv->temps.end(), static_cast<void*>(sv->tk2), static_cast<void*>(sv->tk));
-    std::replace(sv->temps.begin(), sv->temps.end(), static_cast<void*>(sv->tv2), static_cast<void*>(sv->tv));
-    std::replace(sv->blocks.begin(), sv->blocks.end(), static_cast<void*>(sv->tk), static_cast<void*>(sv->tk2));
-    std::replace(sv->blocks.begin(), sv->blocks.end(), static_cast<void*>(sv->tv), static_cast<void*>(sv->tv2));
-  }
+  // keep the pair list, return every temporary to the pool
   free_list(sv, sv->temps);
   *out = sv;
   return GSR_OK;
@@ -556,7 +544,7 @@ gsr_status gsr_loss_l1(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_out*
   ViewTable vt;
   gsr_status st = loss_table(ctx, saved, outs, targets, depth_weight, grad_color_out, grad_depth_out, &vt);
   if (st != GSR_OK) return st;
-  GSR_HIP(ctx, timed(ctx, ctx->stream, K_LOSS, [&] { return launch_loss_l1(vt, depth_weight, loss_dev, ctx->stream); }));
+  GSR_HIP(ctx, timed(ctx, ctx->stream, K_LOSS, [&] { return launch_loss_l1(vt, depth_weight, saved->loss_part, loss_dev, ctx->stream); }));
   return GSR_OK;
 }
 
@@ -606,15 +594,22 @@ gsr_status gsr_debug_export(gsr_ctx* ctx, const gsr_saved* sv, const gsr_debug* 
     return hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
   };
   if (out->keys && sv->M > 0) {  // key = tile << 32 | depth bits of the pair's record
-    std::vector<uint32_t> t(sv->M), v(sv->M);
+    const int64_t nt = sv->vt.total_tiles;
+    std::vector<uint32_t> v(sv->M);
+    std::vector<uint2> rg(nt);
     std::vector<float4> r1(VN);
-    GSR_HIP(ctx, cp(t.data(), sv->tiles, size_t(sv->M) * 4));
     GSR_HIP(ctx, cp(v.data(), sv->vals, size_t(sv->M) * 4));
+    GSR_HIP(ctx, cp(rg.data(), sv->ranges, size_t(nt) * 8));
     GSR_HIP(ctx, cp(r1.data(), sv->rec.r1, size_t(VN) * sizeof(float4)));
+    // the pair list holds no tile ids: each tile's range names the tile of its pairs
+    // (pairs outside every range keep tile id 0xFFFFFFFF)
+    for (int64_t i = 0; i < sv->M; ++i) out->keys[i] = uint64_t(0xFFFFFFFFu) << 32;
+    for (int64_t t = 0; t < nt; ++t)
+      for (uint32_t i = rg[t].x; i < rg[t].y && int64_t(i) < sv->M; ++i) out->keys[i] = uint64_t(t) << 32;
     for (int64_t i = 0; i < sv->M; ++i) {
-      uint32_t zb;
-      std::memcpy(&zb, &r1[v[i]].z, 4);
-      out->keys[i] = (uint64_t(t[i]) << 32) | zb;
+      uint32_t zb = 0;
+      if (int64_t(v[i]) < VN) std::memcpy(&zb, &r1[v[i]].z, 4);
+      out->keys[i] |= zb;
     }
   }
   GSR_HIP(ctx, cp(out->values, sv->vals, size_t(sv->M) * 4));
@@ -734,7 +729,7 @@ gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_came
   if (e == hipSuccess) {
     hipError_t k = enqueue_project(sv, cs, false);
     if (k == hipSuccess) k = enqueue_sort_blend(sv, cs, false);
-    if (k == hipSuccess) k = launch_loss_l1(lvt, depth_weight, loss_dev, cs);
+    if (k == hipSuccess) k = launch_loss_l1(lvt, depth_weight, sv->loss_part, loss_dev, cs);
     if (k == hipSuccess) k = enqueue_backward(sv, bvt, sv->grad2d, go, cs, false);
     if (k == hipSuccess)
       k = hipMemcpyAsync(gr->h_flag, sv->ctrl + kOverflow, sizeof(uint32_t), hipMemcpyDeviceToHost, cs);

@@ -14,11 +14,12 @@ enum KernelId {
   K_PROJECT = 0,
   K_SCAN,
   K_COMPACT,
-  K_DUP_COUNT,
-  K_DUPLICATE,
   K_RADIX_HIST,
   K_RADIX_ROWSCAN,
   K_RADIX_SCATTER,
+  K_BIN_COUNT,
+  K_BIN_SCAN,
+  K_BIN_SCATTER,
   K_RANGES,
   K_TILE_ORDER,
   K_FILL,
@@ -97,11 +98,13 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;  // keys per radix-sort block
 constexpr int kGrad2D = 12;  // floats per (view, Gaussian) 2D-gradient record (10 used)
-constexpr int kBuckets = 33;               // log2 buckets of tile list lengths
-constexpr int kHeadFwd = 2 * kBuckets;     // control words (see TileQueue)
-constexpr int kHeadBwd = 2 * kBuckets + 1;
-constexpr int kOverflow = 2 * kBuckets + 2;
-constexpr int kCtrlWords = 2 * kBuckets + 4;
+constexpr int kBuckets = 33;   // log2 buckets of tile list lengths
+constexpr int kHeadFwd = 0;    // control words (see TileQueue)
+constexpr int kHeadBwd = 1;
+constexpr int kOverflow = 2;
+constexpr int kCtrlWords = 4;
+constexpr int kScanTile = 4096;            // elements per block of the device-wide scans
+constexpr int64_t kMaxBinCounts = int64_t(1) << 22;  // entries of each binning count array (soft)
 
 // One camera plus where its tiles and pixels live in the concatenated spaces.
 struct ViewDev {
@@ -111,7 +114,7 @@ struct ViewDev {
   float cam_pos[3];  // camera centre in world coordinates
   int32_t W, H, tiles_x, tiles_y;
   int32_t tile_off;  // first global tile id of this view
-  int32_t pad;
+  int32_t row_off;   // first global tile row of this view
   int64_t pix_off;   // first pixel of this view in the per-pixel state arrays
   float* color;      // forward outputs
   float* depth;
@@ -129,6 +132,8 @@ struct ViewTable {
   ViewDev v[GSR_MAX_VIEWS];
   int32_t nviews;
   int32_t total_tiles;
+  int32_t total_rows;  // tile rows over all views
+  int32_t max_tiles_x;
 };
 
 struct Rules {
@@ -155,11 +160,34 @@ struct Records {
 };
 
 // Longest-list-first tile order and the control words of the persistent compositing
-// kernels: [0, kBuckets) bucket counts, [kBuckets, 2 kBuckets) bucket fill, kHeadFwd /
-// kHeadBwd queue heads, kOverflow the capacity-overflow flag.
+// kernels: kHeadFwd / kHeadBwd queue heads, kOverflow the capacity-overflow flag.
 struct TileQueue {
   const uint32_t* order;
   uint32_t* ctrl;
+};
+
+// Two-level stable binning of the depth-sorted records into per-tile lists.
+//   rows:  the records are cut into chunks of 64 * rounds1; per (tile row, chunk) counts,
+//          scanned row-major, place every (record, row) entry of a chunk after those of
+//          earlier chunks, giving each tile row a depth-ordered list of (record, tx0..tx1)
+//   tiles: each row list is cut into segments of 64 * rounds2 entries; per (tile, segment)
+//          counts, flattened tile-major (row, column, segment) and scanned, place every
+//          (record, tile) pair; the scan is in global tile order, so it also gives the ranges
+struct BinPlan {
+  int32_t rows;      // tile rows over all views
+  int32_t nch1;      // chunks of the depth-sorted records
+  int32_t rounds1;   // 64-record rounds per chunk
+  int32_t rounds2;   // 64-entry rounds per segment
+  int64_t cap_M;     // capacity of row entries and of pairs
+  int64_t cap_seg;   // capacity of segments
+  int64_t cap_flat;  // capacity of flat (tile, segment) counts
+  uint32_t* cnt1;        // [rows][nch1] counts, then exclusive offsets
+  uint2* rowlist;        // (record id, tx0 | tx1 << 16) per (record, row) entry
+  uint4* rowinfo;        // per row: (list start, list length, first segment, first flat index)
+  uint32_t* seg_start;   // [rows + 1] first segment of each row
+  uint32_t* cntF;        // flat (tile, segment) counts, then exclusive offsets
+  uint32_t* part;        // partial sums of the device-wide scans
+  unsigned long long* words;  // [0] row entries, [1] segments, [2] flat size, [3] pairs placed
 };
 
 struct GradOut {
@@ -178,23 +206,23 @@ hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const
                           const Records& rec, uint2* blocksums, int nblk, hipStream_t s);
 hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* totals, hipStream_t s);
 hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
-                          uint32_t* dkeys, uint32_t* dvals, int64_t cap, uint32_t* overflow, hipStream_t s);
-hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* bucket_of, uint32_t* order,
-                             uint32_t* ctrl, hipStream_t s);
+                          const unsigned long long* pairs, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
+                          int64_t cap, uint32_t* overflow, hipStream_t s);
+hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* order, hipStream_t s);
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                              uint32_t* hist, uint32_t* digit_tot, const unsigned long long* count, int64_t cap,
                              const uint32_t* overflow, int key_bits, bool* result_in_alt, int* passes, hipStream_t s,
                              Timer* tm);
-hipError_t launch_duplicate(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* dvals,
-                            const unsigned long long* nvis, int64_t cap_vis, uint32_t* blocksums,
-                            unsigned long long* total, uint32_t* tkeys, uint32_t* tvals, int64_t cap_M,
-                            uint32_t* overflow, hipStream_t s, Timer* tm);
-hipError_t launch_ranges(const uint32_t* tkeys, const unsigned long long* count, int64_t cap,
-                         const uint32_t* overflow, uint2* ranges, int total_tiles, hipStream_t s);
+// Sizes of a binning plan for capacities (cap_vis, cap_M); pointers are left null.
+BinPlan bin_plan(const ViewTable& vt, int64_t cap_vis, int64_t cap_M);
+hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* dvals,
+                      const unsigned long long* nvis, int64_t cap_vis, const BinPlan& plan, uint32_t* vals,
+                      uint2* ranges, uint32_t* overflow, hipStream_t s, Timer* tm);
 hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
                             uint32_t* n_used, const TileQueue& q, hipStream_t s);
-hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* loss, hipStream_t s);
+int loss_partials(const ViewTable& vt);  // block partial sums launch_loss_l1 writes
+hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* part, float* loss, hipStream_t s);
 hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, const float* T_final,
                             const uint32_t* n_contrib, float* grad2d, const TileQueue& q, hipStream_t s);

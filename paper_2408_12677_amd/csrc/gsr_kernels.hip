@@ -4,14 +4,13 @@
 //                       the 2D splat (Eq. 3), SH colour, frustum cull, tile rectangle, tile count,
 //                       block sums of the tile counts and of the visible records
 //   K2 k_scan_pairs     exclusive scans of those block sums (one block)
-//   K3/K4               the stable sort of the (tile id << 32 | depth bits) keys, in LSD order:
-//                       k_compact + k_radix_* sort the visible records by their depth bits
-//                       (the four low digits) before duplication, which commutes with a
-//                       stable depth sort; k_sorted_counts + k_duplicate then write
-//                       (tile id, record) pairs in depth order, and k_radix_* passes over the
-//                       tile digits finish the sort (8-bit digits: histogram / row scan /
-//                       ballot-multisplit scatter)
-//   K5 k_ranges         [start, end) of every tile in the sorted list
+//   K3/K4               the stable sort of the (tile id << 32 | depth bits) keys, without
+//                       materialising them: k_compact + k_radix_* sort the visible records by
+//                       depth bits (stable LSD, 8-bit digits: histogram / row scan /
+//                       ballot-multisplit scatter); k_bin_* then bin that depth order stably,
+//                       first into tile rows, then into the tiles of each row, so every
+//                       tile receives its records in ascending (depth, record) order
+//   K5                  the tile ranges come from the binning's scan (k_bin_ranges)
 //   K6 k_blend_fwd      per tile: front-to-back compositing, Eq. 11 with clamp/skip/stop
 //   K7 k_loss_l1        Eq. 12 (mean L1 colour) + weighted mean L1 depth, its gradient
 //   K8 k_blend_bwd      per tile, back to front: transmittance recovered by division,
@@ -34,17 +33,6 @@ template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_move(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK,
                                                                0xF, false));
-}
-
-// Sum over the 64 lanes; the total lands in lane 63.  Needs every lane active.
-__device__ __forceinline__ float wave_sum_to_lane63(float v) {
-  v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-  v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-  v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
-  v += dpp_move<0x140, 0xF>(v);  // row_mirror: every lane holds its 16-lane row sum
-  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-  return v;
 }
 
 // gfx950 lane-half / row swaps: (a, b) -> a's upper 32 lanes exchanged with b's lower 32
@@ -96,6 +84,26 @@ __device__ __forceinline__ void wave_sum10(const float (&v)[10], float& w0, floa
   w0 += dpp_move<0x140, 0xF>(w0);
   w1 += dpp_move<0x140, 0xF>(w1);
   w2 += dpp_move<0x140, 0xF>(w2);
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Minimum over the wavefront, returned as a wavefront-uniform value: each 16-lane row is
+// reduced with DPP (quad swaps, half-row and row mirrors), then the four row results are
+// read from lanes 0, 16, 32 and 48.  Needs every lane active.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  v = min(v, dpp_u32<0xB1>(v));
+  v = min(v, dpp_u32<0x4E>(v));
+  v = min(v, dpp_u32<0x141>(v));
+  v = min(v, dpp_u32<0x140>(v));
+  const uint32_t a = uint32_t(__builtin_amdgcn_readlane(int(v), 0));
+  const uint32_t b = uint32_t(__builtin_amdgcn_readlane(int(v), 16));
+  const uint32_t c = uint32_t(__builtin_amdgcn_readlane(int(v), 32));
+  const uint32_t d = uint32_t(__builtin_amdgcn_readlane(int(v), 48));
+  return min(min(a, b), min(c, d));
 }
 
 __device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* red) {
@@ -504,10 +512,14 @@ __device__ __forceinline__ uint32_t clamp_count(const unsigned long long* count,
 // K3a: compaction of the visible records into (depth bits, record id) pairs, record order
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kProjThreads) void k_compact(int64_t n, Records rec, const uint2* blocksums, int nblk,
+                                                          const unsigned long long* pairs, int64_t cap_M,
                                                           uint32_t* dkeys, uint32_t* dvals, int64_t cap,
                                                           uint32_t* overflow) {
   __shared__ uint32_t red[kProjThreads / 64];
   const int v = blockIdx.y;
+  // more (tile, record) pairs than the binning buffers hold: flag it before anything reads
+  // the flag (every later kernel then sees zero records)
+  if (blockIdx.x == 0 && v == 0 && threadIdx.x == 0 && *pairs > (unsigned long long)cap_M) atomicOr(overflow, 1u);
   const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
   const int64_t rid = int64_t(v) * n + gi;
   const uint32_t vis = (gi < n && rec.counts[rid] != 0u) ? 1u : 0u;
@@ -629,103 +641,81 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
 }
 
 // ------------------------------------------------------------------------------------
-// K3b: duplication of the depth-sorted records into (tile id, record id) pairs.
-//   k_sorted_counts: block sums of the tile counts in depth order
-//   k_duplicate:     each wavefront spreads its 64 records' tile runs over its lanes
-//                    (lane l writes pairs l, l+64, ...), so stores are contiguous and
-//                    records with many tiles do not serialise one lane
+// Device-wide exclusive scan of u32 counts, in place: per-block sums, one block scans the
+// sums (k_scan_u32), then each block scans its 4096 elements from its base.  The element
+// count is read from the device (clamped to the capacity the grid was sized for) when
+// `count` is given.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kProjThreads) void k_sorted_counts(const uint32_t* dvals, const uint32_t* counts,
-                                                                const unsigned long long* nvis, int64_t cap,
-                                                                const uint32_t* overflow, uint32_t* blocksums) {
-  __shared__ uint32_t red[kProjThreads / 64];
-  const int64_t r = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
-  const uint32_t c = r < int64_t(clamp_count(nvis, cap, overflow)) ? counts[dvals[r]] : 0u;
-  const uint32_t bs = block_sum_u32(c, red);
-  if (threadIdx.x == 0) blocksums[blockIdx.x] = bs;
+__device__ __forceinline__ int64_t scan_len(int64_t cap, const unsigned long long* count) {
+  if (!count) return cap;
+  const unsigned long long c = *count;
+  return c < (unsigned long long)cap ? int64_t(c) : cap;
 }
 
-__global__ __launch_bounds__(kProjThreads) void k_duplicate(ViewTable vt, int64_t n, Records rec,
-                                                            const uint32_t* dvals, const unsigned long long* nvis,
-                                                            int64_t cap_vis, const uint32_t* blocksums,
-                                                            uint32_t* tkeys, uint32_t* tvals, int64_t cap_M,
-                                                            uint32_t* overflow) {
-  constexpr int NW = kProjThreads / 64;
-  __shared__ uint32_t red[NW];
-  __shared__ uint32_t s_off[NW][64];
-  __shared__ uint32_t s_rid[NW][64];
-  __shared__ uint2 s_rect[NW][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t r = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
-  uint32_t rid = 0, cnt = 0;
-  uint2 rc = make_uint2(0u, 0u);
-  if (r < int64_t(clamp_count(nvis, cap_vis, overflow))) {
-    rid = dvals[r];
-    cnt = rec.counts[rid];
-    rc = rec.rect[rid];
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* a, int64_t cap, const unsigned long long* count,
+                                                     uint32_t* part) {
+  __shared__ uint32_t red[4];
+  const int64_t n = scan_len(cap, count);
+  const int64_t base = int64_t(blockIdx.x) * kScanTile;
+  uint32_t sum = 0;
+#pragma unroll 4
+  for (int i = 0; i < kScanTile / 256; ++i) {
+    const int64_t idx = base + i * 256 + threadIdx.x;
+    if (idx < n) sum += a[idx];
   }
-  const uint32_t excl = block_exclusive_scan_u32(cnt, red);
-  const uint64_t off = uint64_t(blocksums[blockIdx.x]) + excl;
-  s_off[w][lane] = uint32_t(off);
-  s_rid[w][lane] = rid;
-  s_rect[w][lane] = rc;
-  const uint64_t wbeg = uint64_t(__shfl(uint32_t(off), 0));
-  const uint64_t wend = uint64_t(__shfl(uint32_t(off + cnt), 63));
-  const bool over = wend > uint64_t(cap_M);
-  __syncthreads();
-  if (over) {
-    if (lane == 0) atomicOr(overflow, 1u);
-    return;
-  }
-  for (uint64_t p = wbeg + lane; p < wend; p += 64) {
-    // last record of this wavefront whose run starts at or before p
-    int lo = 0, hi = 63;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (uint64_t(s_off[w][mid]) <= p)
-        lo = mid;
-      else
-        hi = mid - 1;
+  const uint32_t tot = block_sum_u32(sum, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(uint32_t* a, int64_t cap, const unsigned long long* count,
+                                                   const uint32_t* part) {
+  __shared__ uint32_t red[4];
+  const int64_t n = scan_len(cap, count);
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * 16;
+  uint32_t x[16];
+  if (base + 16 <= n) {
+    const uint4* src = reinterpret_cast<const uint4*>(a + base);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint4 q = src[j];
+      x[4 * j] = q.x;
+      x[4 * j + 1] = q.y;
+      x[4 * j + 2] = q.z;
+      x[4 * j + 3] = q.w;
     }
-    const uint32_t id = s_rid[w][lo];
-    const uint2 q = s_rect[w][lo];
-    const uint32_t local = uint32_t(p - s_off[w][lo]);
-    const uint32_t tx0 = q.x & 0xFFFFu, tx1 = q.x >> 16, ty0 = q.y & 0xFFFFu;
-    const uint32_t wdt = tx1 - tx0 + 1u;
-    const uint32_t ty = ty0 + local / wdt, tx = tx0 + local % wdt;
-    const ViewDev& cam = vt.v[id / uint32_t(n)];
-    tkeys[p] = uint32_t(cam.tile_off) + ty * uint32_t(cam.tiles_x) + tx;
-    tvals[p] = id;
-  }
-}
-
-// ------------------------------------------------------------------------------------
-// K5: tile ranges
-// ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t* tkeys, const unsigned long long* count, int64_t cap,
-                                                const uint32_t* overflow, uint2* ranges, int total_tiles) {
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  const int64_t M = clamp_count(count, cap, overflow);
-  if (i >= M) return;
-  const uint32_t tile = tkeys[i];
-  if (tile >= uint32_t(total_tiles)) return;
-  if (i == 0) {
-    ranges[tile].x = 0;
   } else {
-    const uint32_t prev = tkeys[i - 1];
-    if (prev != tile) {
-      if (prev < uint32_t(total_tiles)) ranges[prev].y = uint32_t(i);
-      ranges[tile].x = uint32_t(i);
-    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = base + j < n ? a[base + j] : 0u;
   }
-  if (i == M - 1) ranges[tile].y = uint32_t(M);
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) sum += x[j];
+  uint32_t run = part[blockIdx.x] + block_exclusive_scan_u32(sum, red);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const uint32_t v = x[j];
+    x[j] = run;
+    run += v;
+  }
+  if (base + 16 <= n) {
+    uint4* dst = reinterpret_cast<uint4*>(a + base);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dst[j] = make_uint4(x[4 * j], x[4 * j + 1], x[4 * j + 2], x[4 * j + 3]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (base + j < n) a[base + j] = x[j];
+  }
 }
 
-__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (i < count) p[i] = value;
-}
-
+// ------------------------------------------------------------------------------------
+// K3/K4 binning (see BinPlan).  Both stages place items that cover a contiguous run of
+// bins [lo, hi] (tile rows of a record, tile columns of a row entry) stably: chunk by
+// chunk from scanned per-(bin, chunk) counts, and inside a chunk by one wavefront that
+// walks its 64 items' bins in ascending order; for each bin the covering lanes take
+// consecutive slots in lane order from the bin's next free slot, kept in LDS (loaded from
+// the scanned counts when the chunk starts).
+// ------------------------------------------------------------------------------------
 __device__ __forceinline__ int view_of_tile(const ViewTable& vt, int tile) {
   int v = 0;
   for (int i = 1; i < vt.nviews; ++i)
@@ -733,39 +723,273 @@ __device__ __forceinline__ int view_of_tile(const ViewTable& vt, int tile) {
   return v;
 }
 
-// ------------------------------------------------------------------------------------
-// Tile work queue.  Tiles are ordered by decreasing list length (log2 buckets, a counting
-// sort) and the compositing kernels run as persistent blocks that take the next tile
-// from a device counter, so the longest lists start first and short ones fill the tail.
-// ctrl layout: [0..32] bucket counts, [33..65] bucket fill, [66] forward head,
-// [67] backward head, [68] overflow flag.
-// ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_tile_buckets(const uint2* ranges, int total, uint32_t* bucket_of,
-                                                      uint32_t* ctrl) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= total) return;
-  const uint2 r = ranges[i];
-  const uint32_t len = r.y - r.x;
-  const uint32_t b = len ? 32u - uint32_t(__clz(len)) : 0u;  // 0..32
-  bucket_of[i] = b;
-  atomicAdd(&ctrl[b], 1u);
+__device__ __forceinline__ int view_of_row(const ViewTable& vt, uint32_t row) {
+  int v = 0;
+  for (int i = 1; i < vt.nviews; ++i)
+    if (int(row) >= vt.v[i].row_off) v = i;
+  return v;
 }
 
-__global__ __launch_bounds__(256) void k_tile_order(const uint32_t* bucket_of, int total, uint32_t* ctrl,
-                                                    uint32_t* order) {
-  __shared__ uint32_t start[kBuckets];
+__device__ __forceinline__ uint32_t view_of_record(const ViewTable& vt, uint32_t rid, int64_t n) {
+  return vt.nviews == 1 ? 0u : rid / uint32_t(n);
+}
+
+// stage 1 counts: tile-row histogram of one chunk of depth-sorted records
+__global__ __launch_bounds__(256) void k_bin_rows_count(ViewTable vt, int64_t n, Records rec, const uint32_t* dvals,
+                                                        const unsigned long long* nvis, int64_t cap_vis,
+                                                        const uint32_t* overflow, BinPlan plan) {
+  extern __shared__ uint32_t hist[];
+  const int R = plan.rows;
+  for (int i = threadIdx.x; i < R; i += 256) hist[i] = 0;
+  __syncthreads();
+  const int64_t NV = clamp_count(nvis, cap_vis, overflow);
+  const int64_t beg = int64_t(blockIdx.x) * 64 * plan.rounds1;
+  const int64_t end = min(NV, beg + int64_t(64) * plan.rounds1);
+  for (int64_t i = beg + threadIdx.x; i < end; i += 256) {
+    const uint32_t rid = dvals[i];
+    const uint2 rc = rec.rect[rid];
+    const int ro = vt.v[view_of_record(vt, rid, n)].row_off;
+    const int y0 = ro + int(rc.y & 0xFFFFu), y1 = min(ro + int(rc.y >> 16), R - 1);
+    for (int y = y0; y <= y1; ++y) atomicAdd(&hist[y], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < R; i += 256) plan.cnt1[int64_t(i) * plan.nch1 + blockIdx.x] = hist[i];
+}
+
+// stage 1 placement: one wavefront per chunk writes (record, column run) entries into the
+// row lists
+__global__ __launch_bounds__(64) void k_bin_rows_scatter(ViewTable vt, int64_t n, Records rec, const uint32_t* dvals,
+                                                         const unsigned long long* nvis, int64_t cap_vis,
+                                                         const uint32_t* overflow, BinPlan plan) {
+  extern __shared__ uint32_t next[];  // next free slot of each row for this chunk
+  const int R = plan.rows;
+  const int lane = threadIdx.x;
+  const int64_t NV = clamp_count(nvis, cap_vis, overflow);
+  const int64_t beg = int64_t(blockIdx.x) * 64 * plan.rounds1;
+  if (beg >= NV) return;
+  for (int i = lane; i < R; i += 64) next[i] = plan.cnt1[int64_t(i) * plan.nch1 + blockIdx.x];
+  __syncthreads();
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  for (int r = 0; r < plan.rounds1; ++r) {
+    const int64_t r0 = beg + int64_t(r) * 64;
+    if (r0 >= NV) break;
+    const int64_t i = r0 + lane;
+    uint32_t cur = 0xFFFFFFFFu, hi = 0u;
+    uint2 entry = make_uint2(0u, 0u);
+    if (i < NV) {
+      const uint32_t rid = dvals[i];
+      const uint2 rc = rec.rect[rid];
+      const int ro = vt.v[view_of_record(vt, rid, n)].row_off;
+      cur = uint32_t(ro) + (rc.y & 0xFFFFu);
+      hi = min(uint32_t(ro) + (rc.y >> 16), uint32_t(R - 1));
+      entry = make_uint2(rid, rc.x);
+    }
+    for (uint32_t y = wave_min_u32(cur); y != 0xFFFFFFFFu; y = wave_min_u32(cur)) {
+      const bool on = cur == y;
+      const uint64_t m = __ballot(on);
+      const uint32_t base = next[y];
+      if (on) {
+        const uint32_t dst = base + uint32_t(__popcll(m & lt_mask));
+        if (int64_t(dst) < plan.cap_M) plan.rowlist[dst] = entry;
+        cur = cur < hi ? cur + 1u : 0xFFFFFFFFu;
+      }
+      if (lane == 0) next[y] = base + uint32_t(__popcll(m));
+    }
+  }
+}
+
+// Per row: list start and length, its segments and its first flat (tile, segment) index;
+// totals of segments and of the flat array.  One block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_bin_rows_meta(ViewTable vt, BinPlan plan, uint32_t* overflow) {
+  __shared__ unsigned long long part[1024];
+  const int R = plan.rows, t = threadIdx.x;
+  const int per = (R + 1023) / 1024;
+  const int beg = min(R, t * per), end = min(R, beg + per);
+  const unsigned long long E1 = plan.words[0];
+  const uint32_t S2 = 64u * uint32_t(plan.rounds2);
+  auto row = [&](int r, uint32_t& start, uint32_t& len, uint32_t& nseg, uint32_t& w) {
+    start = plan.cnt1[int64_t(r) * plan.nch1];
+    const unsigned long long next = r + 1 < R ? plan.cnt1[int64_t(r + 1) * plan.nch1] : E1;
+    len = uint32_t(next - start);
+    nseg = (len + S2 - 1) / S2;
+    w = nseg * uint32_t(vt.v[view_of_row(vt, uint32_t(r))].tiles_x);
+  };
+  unsigned long long sseg = 0, sw = 0;
+  for (int r = beg; r < end; ++r) {
+    uint32_t a, l, ns, w;
+    row(r, a, l, ns, w);
+    sseg += ns;
+    sw += w;
+  }
+  const unsigned long long iseg = block_inclusive_scan_u64_1024(sseg, part);
+  __syncthreads();
+  const unsigned long long iw = block_inclusive_scan_u64_1024(sw, part);
+  unsigned long long seg = iseg - sseg, flat = iw - sw;
+  for (int r = beg; r < end; ++r) {
+    uint32_t a, l, ns, w;
+    row(r, a, l, ns, w);
+    plan.rowinfo[r] = make_uint4(a, l, uint32_t(seg), uint32_t(flat));
+    plan.seg_start[r] = uint32_t(seg);
+    seg += ns;
+    flat += w;
+  }
+  if (t == 1023) {
+    const bool over = iseg > (unsigned long long)plan.cap_seg || iw > (unsigned long long)plan.cap_flat;
+    if (over) atomicOr(overflow, 1u);
+    plan.seg_start[R] = uint32_t(over ? 0ull : iseg);
+    plan.words[1] = over ? 0ull : iseg;
+    plan.words[2] = over ? 0ull : iw;
+  }
+}
+
+// the row whose segments contain segment s: the last r with seg_start[r] <= s
+__device__ __forceinline__ int row_of_segment(const uint32_t* seg_start, int R, uint32_t s) {
+  int lo = 0, hi = R - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (seg_start[mid] <= s)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+struct Segment {
+  uint32_t beg, end;   // entries of the row list
+  uint32_t flat;       // flat index of (column 0, this segment)
+  uint32_t nseg;       // segments of the row (stride between columns)
+  int tiles_x;
+};
+
+__device__ __forceinline__ Segment segment_of(const ViewTable& vt, const BinPlan& plan, uint32_t s) {
+  const int r = row_of_segment(plan.seg_start, plan.rows, s);
+  const uint4 info = plan.rowinfo[r];
+  const uint32_t S2 = 64u * uint32_t(plan.rounds2);
+  Segment g;
+  const uint32_t sidx = s - info.z;
+  g.nseg = (info.y + S2 - 1) / S2;
+  g.beg = info.x + sidx * S2;
+  g.end = min(info.x + info.y, g.beg + S2);
+  g.flat = info.w + sidx;
+  g.tiles_x = vt.v[view_of_row(vt, uint32_t(r))].tiles_x;
+  return g;
+}
+
+// stage 2 counts: tile-column histogram of one segment of a row list
+__global__ __launch_bounds__(256) void k_bin_tiles_count(ViewTable vt, BinPlan plan) {
+  extern __shared__ uint32_t hist[];
+  const unsigned long long S = plan.words[1];
+  for (uint32_t s = blockIdx.x; s < S; s += gridDim.x) {
+    const Segment g = segment_of(vt, plan, s);
+    for (int i = threadIdx.x; i < g.tiles_x; i += 256) hist[i] = 0;
+    __syncthreads();
+    for (uint32_t i = g.beg + threadIdx.x; i < g.end; i += 256) {
+      const uint32_t cx = plan.rowlist[i].y;
+      const int x0 = int(cx & 0xFFFFu), x1 = min(int(cx >> 16), g.tiles_x - 1);
+      for (int x = x0; x <= x1; ++x) atomicAdd(&hist[x], 1u);
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < g.tiles_x; x += 256) plan.cntF[g.flat + uint32_t(x) * g.nseg] = hist[x];
+    __syncthreads();
+  }
+}
+
+// stage 2 placement: one wavefront per segment writes record ids into the tile lists
+__global__ __launch_bounds__(64) void k_bin_tiles_scatter(ViewTable vt, BinPlan plan, uint32_t* vals) {
+  extern __shared__ uint32_t next[];  // next free slot of each tile for this segment
+  const int lane = threadIdx.x;
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  const unsigned long long S = plan.words[1];
+  for (uint32_t s = blockIdx.x; s < S; s += gridDim.x) {
+    const Segment g = segment_of(vt, plan, s);
+    __syncthreads();
+    for (int i = lane; i < g.tiles_x; i += 64) next[i] = plan.cntF[g.flat + uint32_t(i) * g.nseg];
+    __syncthreads();
+    for (uint32_t r0 = g.beg; r0 < g.end; r0 += 64) {
+      const uint32_t i = r0 + uint32_t(lane);
+      uint32_t cur = 0xFFFFFFFFu, hi = 0u, rid = 0u;
+      if (i < g.end) {
+        const uint2 e = plan.rowlist[i];
+        rid = e.x;
+        cur = e.y & 0xFFFFu;
+        hi = min(e.y >> 16, uint32_t(g.tiles_x - 1));
+      }
+      for (uint32_t x = wave_min_u32(cur); x != 0xFFFFFFFFu; x = wave_min_u32(cur)) {
+        const bool on = cur == x;
+        const uint64_t m = __ballot(on);
+        const uint32_t base = next[x];
+        if (on) {
+          const uint32_t dst = base + uint32_t(__popcll(m & lt_mask));
+          if (int64_t(dst) < plan.cap_M) vals[dst] = rid;
+          cur = cur < hi ? cur + 1u : 0xFFFFFFFFu;
+        }
+        if (lane == 0) next[x] = base + uint32_t(__popcll(m));
+      }
+    }
+  }
+}
+
+// K5: [start, end) of every tile from the flat scan; empty tiles are [0, 0)
+__global__ __launch_bounds__(256) void k_bin_ranges(ViewTable vt, BinPlan plan, const uint32_t* overflow,
+                                                    uint2* ranges) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= vt.total_tiles) return;
+  if (*overflow) {  // nothing was binned
+    ranges[t] = make_uint2(0u, 0u);
+    return;
+  }
+  const ViewDev& cam = vt.v[view_of_tile(vt, t)];
+  const int local = t - cam.tile_off;
+  const int r = cam.row_off + local / cam.tiles_x, x = local % cam.tiles_x;
+  const uint4 info = plan.rowinfo[r];
+  const uint32_t S2 = 64u * uint32_t(plan.rounds2);
+  const uint32_t nseg = (info.y + S2 - 1) / S2;
+  uint2 out = make_uint2(0u, 0u);
+  if (nseg) {
+    const unsigned long long F = plan.words[2];
+    const uint32_t idx = info.w + uint32_t(x) * nseg;
+    const uint32_t a = plan.cntF[idx];
+    const uint32_t b = (unsigned long long)(idx + nseg) < F ? plan.cntF[idx + nseg] : uint32_t(plan.words[3]);
+    if (b > a) out = make_uint2(a, b);
+  }
+  ranges[t] = out;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < count) p[i] = value;
+}
+
+// ------------------------------------------------------------------------------------
+// Tile work queue.  Tiles are ordered by decreasing list length (a counting sort on
+// log2 buckets, in one block: the order inside a bucket is arbitrary) and the compositing
+// kernels run as persistent blocks that take the next tile from a device counter, so the
+// longest lists start first and short ones fill the tail.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2* ranges, int total, uint32_t* order) {
+  __shared__ uint32_t cnt[kBuckets], start[kBuckets];
+  if (threadIdx.x < kBuckets) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < total; i += 1024) {
+    const uint2 r = ranges[i];
+    const uint32_t len = r.y - r.x;
+    atomicAdd(&cnt[len ? 32u - uint32_t(__clz(len)) : 0u], 1u);
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t run = 0;
     for (int b = kBuckets - 1; b >= 0; --b) {
       start[b] = run;
-      run += ctrl[b];
+      run += cnt[b];
     }
   }
   __syncthreads();
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= total) return;
-  const uint32_t b = bucket_of[i];
-  order[start[b] + atomicAdd(&ctrl[kBuckets + b], 1u)] = uint32_t(i);
+  for (int i = threadIdx.x; i < total; i += 1024) {
+    const uint2 r = ranges[i];
+    const uint32_t len = r.y - r.x;
+    order[atomicAdd(&start[len ? 32u - uint32_t(__clz(len)) : 0u], 1u)] = uint32_t(i);
+  }
 }
 
 // Block-uniform: the next tile of the queue, or -1 when it is exhausted.
@@ -867,7 +1091,7 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
 // ------------------------------------------------------------------------------------
 // K7: L1 loss and its gradient with respect to the rendered colour and depth
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_loss_l1(ViewTable vt, float depth_w, float* loss) {
+__global__ __launch_bounds__(256) void k_loss_l1(ViewTable vt, float depth_w, float* partial) {
   __shared__ float red[4];
   const ViewDev& cam = vt.v[blockIdx.y];
   const int64_t P = int64_t(cam.W) * cam.H;
@@ -895,10 +1119,23 @@ __global__ __launch_bounds__(256) void k_loss_l1(ViewTable vt, float depth_w, fl
   for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(loss, red[0] + red[1] + red[2] + red[3]);
+  if (threadIdx.x == 0) partial[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ void k_zero_f32(float* p) { *p = 0.f; }
+// the loss: the block partial sums added in a fixed order (deterministic)
+__global__ __launch_bounds__(1024) void k_loss_sum(const float* part, int count, float* loss) {
+  __shared__ float red[16];
+  float v = 0.f;
+  for (int i = threadIdx.x; i < count; i += 1024) v += part[i];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int i = 0; i < 16; ++i) t += red[i];
+    *loss = t;
+  }
+}
 
 // ------------------------------------------------------------------------------------
 // K8: backward compositing.  Back to front over each pixel's contributors; the
@@ -1258,9 +1495,11 @@ hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* to
 }
 
 hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
-                          uint32_t* dkeys, uint32_t* dvals, int64_t cap, uint32_t* overflow, hipStream_t s) {
+                          const unsigned long long* pairs, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
+                          int64_t cap, uint32_t* overflow, hipStream_t s) {
   if (nblk == 0) return hipSuccess;
-  k_compact<<<dim3(nblk, views), kProjThreads, 0, s>>>(n, rec, blocksums, nblk, dkeys, dvals, cap, overflow);
+  k_compact<<<dim3(nblk, views), kProjThreads, 0, s>>>(n, rec, blocksums, nblk, pairs, cap_M, dkeys, dvals, cap,
+                                                        overflow);
   return hipGetLastError();
 }
 
@@ -1297,31 +1536,69 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
   return hipGetLastError();
 }
 
-hipError_t launch_duplicate(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* dvals,
-                            const unsigned long long* nvis, int64_t cap_vis, uint32_t* blocksums,
-                            unsigned long long* total, uint32_t* tkeys, uint32_t* tvals, int64_t cap_M,
-                            uint32_t* overflow, hipStream_t s, Timer* tm) {
-  if (cap_vis == 0) return hipSuccess;
-  const int nb = int((cap_vis + kProjThreads - 1) / kProjThreads);
-  if (tm) tm->begin(K_DUP_COUNT);
-  k_sorted_counts<<<nb, kProjThreads, 0, s>>>(dvals, rec.counts, nvis, cap_vis, overflow, blocksums);
-  if (tm) tm->end(K_DUP_COUNT);
-  if (tm) tm->begin(K_SCAN);
-  k_scan_u32<<<1, 1024, 0, s>>>(blocksums, nb, total);
-  if (tm) tm->end(K_SCAN);
-  if (tm) tm->begin(K_DUPLICATE);
-  k_duplicate<<<nb, kProjThreads, 0, s>>>(vt, n, rec, dvals, nvis, cap_vis, blocksums, tkeys, tvals, cap_M,
-                                          overflow);
-  if (tm) tm->end(K_DUPLICATE);
-  return hipGetLastError();
+BinPlan bin_plan(const ViewTable& vt, int64_t cap_vis, int64_t cap_M) {
+  // two 64-item rounds per wavefront when the count arrays stay within kMaxBinCounts
+  // entries; more rounds (fewer, longer chunks) beyond that
+  BinPlan p{};
+  p.rows = vt.total_rows;
+  const int64_t max_chunks = std::max<int64_t>(1, kMaxBinCounts / std::max(1, p.rows));
+  p.rounds1 = int(std::max<int64_t>(2, (cap_vis + 64 * max_chunks - 1) / (64 * max_chunks)));
+  p.nch1 = int(std::max<int64_t>(1, (cap_vis + 64 * p.rounds1 - 1) / (64 * p.rounds1)));
+  const int64_t max_segs = std::max<int64_t>(1024, kMaxBinCounts / std::max(1, vt.max_tiles_x));
+  p.rounds2 = int(std::max<int64_t>(2, (cap_M + 64 * max_segs - 1) / (64 * max_segs)));
+  const int64_t S2 = 64 * int64_t(p.rounds2);
+  const int64_t segs = (cap_M + S2 - 1) / S2;
+  p.cap_M = cap_M;
+  p.cap_seg = segs + p.rows;
+  p.cap_flat = int64_t(vt.max_tiles_x) * segs + vt.total_tiles;
+  return p;
 }
 
-hipError_t launch_ranges(const uint32_t* tkeys, const unsigned long long* count, int64_t cap,
-                         const uint32_t* overflow, uint2* ranges, int total_tiles, hipStream_t s) {
-  if (total_tiles > 0)
-    k_fill_u32<<<blocks_for(int64_t(total_tiles) * 2, 256), 256, 0, s>>>(reinterpret_cast<uint32_t*>(ranges), 0u,
-                                                                          int64_t(total_tiles) * 2);
-  if (cap > 0) k_ranges<<<blocks_for(cap, 256), 256, 0, s>>>(tkeys, count, cap, overflow, ranges, total_tiles);
+// exclusive scan of a[0, min(*count, cap)) (or of a[0, cap) without count); total to *total
+static void scan_u32(uint32_t* a, int64_t cap, const unsigned long long* count, uint32_t* part,
+                     unsigned long long* total, hipStream_t s) {
+  const int nb = int((cap + kScanTile - 1) / kScanTile);
+  k_scan_reduce<<<nb, 256, 0, s>>>(a, cap, count, part);
+  k_scan_u32<<<1, 1024, 0, s>>>(part, nb, total);
+  k_scan_down<<<nb, 256, 0, s>>>(a, cap, count, part);
+}
+
+hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* dvals,
+                      const unsigned long long* nvis, int64_t cap_vis, const BinPlan& plan, uint32_t* vals,
+                      uint2* ranges, uint32_t* overflow, hipStream_t s, Timer* tm) {
+  if (vt.total_tiles == 0) return hipSuccess;
+  if (cap_vis == 0 || plan.cap_M == 0 || plan.rows == 0) {
+    k_fill_u32<<<blocks_for(int64_t(vt.total_tiles) * 2, 256), 256, 0, s>>>(reinterpret_cast<uint32_t*>(ranges), 0u,
+                                                                             int64_t(vt.total_tiles) * 2);
+    return hipGetLastError();
+  }
+  auto B = [&](int k) { if (tm) tm->begin(k); };
+  auto E = [&](int k) { if (tm) tm->end(k); };
+  const size_t lds_rows = size_t(plan.rows) * 4, lds_cols = size_t(vt.max_tiles_x) * 4;
+  const int g_count = int(std::min<int64_t>(plan.cap_seg, 4096));
+  const int g_scatter = int(std::min<int64_t>(plan.cap_seg, 16384));
+  B(K_BIN_COUNT);
+  k_bin_rows_count<<<plan.nch1, 256, lds_rows, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
+  E(K_BIN_COUNT);
+  B(K_BIN_SCAN);
+  scan_u32(plan.cnt1, int64_t(plan.rows) * plan.nch1, nullptr, plan.part, plan.words, s);
+  k_bin_rows_meta<<<1, 1024, 0, s>>>(vt, plan, overflow);
+  E(K_BIN_SCAN);
+  B(K_BIN_SCATTER);
+  k_bin_rows_scatter<<<plan.nch1, 64, lds_rows, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
+  E(K_BIN_SCATTER);
+  B(K_BIN_COUNT);
+  k_bin_tiles_count<<<g_count, 256, lds_cols, s>>>(vt, plan);
+  E(K_BIN_COUNT);
+  B(K_BIN_SCAN);
+  scan_u32(plan.cntF, plan.cap_flat, plan.words + 2, plan.part, plan.words + 3, s);
+  E(K_BIN_SCAN);
+  B(K_BIN_SCATTER);
+  k_bin_tiles_scatter<<<g_scatter, 64, lds_cols, s>>>(vt, plan, vals);
+  E(K_BIN_SCATTER);
+  B(K_RANGES);
+  k_bin_ranges<<<blocks_for(vt.total_tiles, 256), 256, 0, s>>>(vt, plan, overflow, ranges);
+  E(K_RANGES);
   return hipGetLastError();
 }
 
@@ -1354,11 +1631,9 @@ static void blend_fwd_t(const ViewTable& vt, const Rules& ru, const Records& rec
   k_blend_fwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q);
 }
 
-hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* bucket_of, uint32_t* order,
-                             uint32_t* ctrl, hipStream_t s) {
+hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* order, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
-  k_tile_buckets<<<blocks_for(total_tiles, 256), 256, 0, s>>>(ranges, total_tiles, bucket_of, ctrl);
-  k_tile_order<<<blocks_for(total_tiles, 256), 256, 0, s>>>(bucket_of, total_tiles, ctrl, order);
+  k_tile_order<<<1, 1024, 0, s>>>(ranges, total_tiles, order);
   return hipGetLastError();
 }
 
@@ -1378,11 +1653,16 @@ hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rule
   return hipGetLastError();
 }
 
-hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* loss, hipStream_t s) {
-  k_zero_f32<<<1, 1, 0, s>>>(loss);
+int loss_partials(const ViewTable& vt) {
   int64_t maxp = 0;
   for (int v = 0; v < vt.nviews; ++v) maxp = std::max<int64_t>(maxp, int64_t(vt.v[v].W) * vt.v[v].H);
-  if (maxp > 0) k_loss_l1<<<dim3(blocks_for(maxp, 256), vt.nviews), 256, 0, s>>>(vt, depth_w, loss);
+  return int(blocks_for(maxp, 256)) * vt.nviews;
+}
+
+hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* part, float* loss, hipStream_t s) {
+  const int np = loss_partials(vt);
+  k_loss_l1<<<dim3(np / vt.nviews, vt.nviews), 256, 0, s>>>(vt, depth_w, part);
+  k_loss_sum<<<1, 1024, 0, s>>>(part, np, loss);
   return hipGetLastError();
 }
 
