@@ -46,6 +46,7 @@ struct gsr_saved {
   uint32_t *dk = nullptr, *dv = nullptr, *dk2 = nullptr, *dv2 = nullptr;
   uint32_t *hist = nullptr, *dtot = nullptr;
   BinPlan plan{};
+  Ckpt ck{};                  // forward checkpoints and backward work items
   uint32_t* vals = nullptr;   // record id of every (tile, record) pair, in key order
   uint2* ranges = nullptr;
   uint32_t* order = nullptr;
@@ -251,6 +252,9 @@ gsr_status make_saved(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* ca
       (st = alloc_in(sv, B, &sv->d_total, 4)) != GSR_OK || (st = alloc_in(sv, B, &sv->ranges, size_t(tiles))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->order, size_t(tiles))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->loss_part, size_t(loss_partials(vt)))) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->ck.slot_off, size_t(tiles))) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->ck.tile_nmax, size_t(tiles))) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->ck.acc, size_t(pix))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->ctrl, kCtrlWords)) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->T_final, size_t(pix))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->n_contrib, size_t(pix))) != GSR_OK ||
@@ -283,6 +287,14 @@ gsr_status alloc_sort(gsr_saved* sv, int64_t cap_vis, int64_t cap_M, bool persis
       (st = alloc_in(sv, T, &p.seg_start, size_t(p.rows) + 1)) != GSR_OK ||
       (st = alloc_in(sv, T, &p.cntF, size_t(p.cap_flat))) != GSR_OK ||
       (st = alloc_in(sv, T, &p.part, size_t(nparts))) != GSR_OK || (st = alloc_in(sv, T, &p.words, 4)) != GSR_OK)
+    return st;
+  // checkpoints (kept for the backward): worst case, every batch boundary of every tile
+  const int NT = sv->s.tile * sv->s.tile;
+  Ckpt& ck = sv->ck;
+  ck.cap_slots = ckpt_slots(cap_M, sv->s.batch);
+  ck.cap_items = bwd_items_cap(cap_M, sv->vt.total_tiles, sv->s.batch);
+  if ((st = alloc_in(sv, sv->blocks, &ck.state, size_t(ck.cap_slots) * 5 * NT)) != GSR_OK ||
+      (st = alloc_in(sv, sv->blocks, &ck.items, size_t(ck.cap_items))) != GSR_OK)
     return st;
   return GSR_OK;
 }
@@ -328,12 +340,12 @@ hipError_t enqueue_sort_blend(gsr_saved* sv, hipStream_t s, bool timing) {
                    s, tm);
   if (e == hipSuccess)
     e = T(K_TILE_ORDER, [&] {
-      return launch_tile_order(sv->ranges, sv->vt.total_tiles, sv->order, s);
+      return launch_tile_order(sv->ranges, sv->vt.total_tiles, sv->s.batch, sv->order, sv->ck, s);
     });
   if (e == hipSuccess)
     e = T(K_BLEND_FWD, [&] {
       return launch_blend_fwd(sv->s.tile, sv->s.batch, sv->vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final,
-                              sv->n_contrib, sv->n_used, TileQueue{sv->order, sv->ctrl}, s);
+                              sv->n_contrib, sv->n_used, TileQueue{sv->order, sv->ctrl}, sv->ck, s);
     });
   return e;
 }
@@ -352,7 +364,7 @@ hipError_t enqueue_backward(gsr_saved* sv, const ViewTable& vt, float* grad2d, c
   if (e == hipSuccess)
     e = T(K_BLEND_BWD, [&] {
       return launch_blend_bwd(sv->s.tile, sv->s.batch, vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final,
-                              sv->n_contrib, grad2d, TileQueue{sv->order, sv->ctrl}, s);
+                              sv->n_contrib, grad2d, TileQueue{sv->order, sv->ctrl}, sv->ck, s);
     });
   if (e == hipSuccess)
     e = T(K_PROJECT_BWD, [&] { return launch_project_bwd(sv->deg, sv->g, vt, sv->ru, sv->rec, grad2d, go, s); });

@@ -102,6 +102,7 @@ constexpr int kBuckets = 33;   // log2 buckets of tile list lengths
 constexpr int kHeadFwd = 0;    // control words (see TileQueue)
 constexpr int kHeadBwd = 1;
 constexpr int kOverflow = 2;
+constexpr int kItems = 3;      // backward work items listed
 constexpr int kCtrlWords = 4;
 constexpr int kScanTile = 4096;            // elements per block of the device-wide scans
 constexpr int64_t kMaxBinCounts = int64_t(1) << 22;  // entries of each binning count array (soft)
@@ -160,10 +161,26 @@ struct Records {
 };
 
 // Longest-list-first tile order and the control words of the persistent compositing
-// kernels: kHeadFwd / kHeadBwd queue heads, kOverflow the capacity-overflow flag.
+// kernels: kHeadFwd / kHeadBwd queue heads, kOverflow the capacity-overflow flag, kItems
+// the number of backward work items.
 struct TileQueue {
   const uint32_t* order;
   uint32_t* ctrl;
+};
+
+// What the forward keeps so that the backward can run a tile's list in independent
+// pieces of one LDS batch each: at every batch boundary the forward passes, per pixel,
+// the transmittance in front of it and the colour and depth accumulated up to it (a
+// "checkpoint"); per pixel the accumulated totals; per tile its longest contributor list.
+// The backward's work items are (tile, batch) pairs.
+struct Ckpt {
+  uint32_t* slot_off;   // [tiles] first checkpoint slot of each tile (batch boundary 1)
+  float* state;         // [slots][5][pixels of a tile]: T, colour (3), depth in front
+  float4* acc;          // [pixels] colour (3) and depth accumulated, without background
+  uint32_t* tile_nmax;  // [tiles] longest contributor list of the tile
+  uint2* items;         // [cap_items] backward work items (tile, batch)
+  int64_t cap_slots;
+  int64_t cap_items;
 };
 
 // Two-level stable binning of the depth-sorted records into per-tile lists.
@@ -208,7 +225,12 @@ hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* to
 hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
                           const unsigned long long* pairs, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
                           int64_t cap, uint32_t* overflow, hipStream_t s);
-hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* order, hipStream_t s);
+// Longest-list-first order of the tiles and the checkpoint slots of each tile.
+hipError_t launch_tile_order(const uint2* ranges, int total_tiles, int batch, uint32_t* order, const Ckpt& ck,
+                             hipStream_t s);
+// Checkpoint slots and work items the capacities (pairs, tiles) need at a batch size.
+int64_t ckpt_slots(int64_t cap_M, int batch);
+int64_t bwd_items_cap(int64_t cap_M, int total_tiles, int batch);
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                              uint32_t* hist, uint32_t* digit_tot, const unsigned long long* count, int64_t cap,
                              const uint32_t* overflow, int key_bits, bool* result_in_alt, int* passes, hipStream_t s,
@@ -220,12 +242,14 @@ hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const 
                       uint2* ranges, uint32_t* overflow, hipStream_t s, Timer* tm);
 hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
-                            uint32_t* n_used, const TileQueue& q, hipStream_t s);
+                            uint32_t* n_used, const TileQueue& q, const Ckpt& ck, hipStream_t s);
 int loss_partials(const ViewTable& vt);  // block partial sums launch_loss_l1 writes
 hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* part, float* loss, hipStream_t s);
+// Lists the backward's (tile, batch) work items, then runs them.
 hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, const float* T_final,
-                            const uint32_t* n_contrib, float* grad2d, const TileQueue& q, hipStream_t s);
+                            const uint32_t* n_contrib, float* grad2d, const TileQueue& q, const Ckpt& ck,
+                            hipStream_t s);
 hipError_t launch_project_bwd(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru,
                               const Records& rec, const float* grad2d, const GradOut& out, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);

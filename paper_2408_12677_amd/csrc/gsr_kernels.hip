@@ -106,6 +106,11 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   return min(min(a, b), min(c, d));
 }
 
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, uint32_t(__shfl_xor(v, off)));
+  return v;
+}
+
 __device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   const int nw = blockDim.x >> 6;
@@ -967,9 +972,11 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t value, i
 // kernels run as persistent blocks that take the next tile from a device counter, so the
 // longest lists start first and short ones fill the tail.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_tile_order(const uint2* ranges, int total, uint32_t* order) {
-  __shared__ uint32_t cnt[kBuckets], start[kBuckets];
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2* ranges, int total, int batch, uint32_t* order,
+                                                    uint32_t* slot_off) {
+  __shared__ uint32_t cnt[kBuckets], start[kBuckets], red[16], carry;
   if (threadIdx.x < kBuckets) cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int i = threadIdx.x; i < total; i += 1024) {
     const uint2 r = ranges[i];
@@ -990,14 +997,43 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2* ranges, int to
     const uint32_t len = r.y - r.x;
     order[atomicAdd(&start[len ? 32u - uint32_t(__clz(len)) : 0u], 1u)] = uint32_t(i);
   }
+  // checkpoint slots: a tile of n entries has ceil(n / batch) - 1 inner batch boundaries
+  for (int i0 = 0; i0 < total; i0 += 1024) {
+    const int i = i0 + threadIdx.x;
+    uint32_t k = 0;
+    if (i < total) {
+      const uint2 r = ranges[i];
+      const uint32_t nb = (r.y - r.x + uint32_t(batch) - 1u) / uint32_t(batch);
+      k = nb ? nb - 1u : 0u;
+    }
+    const uint32_t ex = block_exclusive_scan_u32(k, red);
+    const uint32_t c = carry;
+    if (i < total) slot_off[i] = c + ex;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = c + ex + k;
+    __syncthreads();
+  }
 }
 
-// Block-uniform: the next tile of the queue, or -1 when it is exhausted.
+// Block-uniform: the next tile of the queue, or -1 when it is exhausted.  The longest
+// lists (the head of the queue) bound the kernel's duration, so their wavefronts take a
+// higher issue priority over the short tiles sharing their SIMDs: 3 for the first
+// sixteenth of the queue, 2 up to an eighth, 1 up to a quarter.
 __device__ __forceinline__ int next_tile(const TileQueue& q, uint32_t* head, int total, int* s_item) {
   __syncthreads();
   if (threadIdx.x == 0) *s_item = int(atomicAdd(head, 1u));
   __syncthreads();
   const int item = *s_item;
+  if (item < total) {
+    if (item * 16 < total)
+      __builtin_amdgcn_s_setprio(3);
+    else if (item * 8 < total)
+      __builtin_amdgcn_s_setprio(2);
+    else if (item * 4 < total)
+      __builtin_amdgcn_s_setprio(1);
+    else
+      __builtin_amdgcn_s_setprio(0);
+  }
   return item < total ? int(q.order[item]) : -1;
 }
 
@@ -1009,15 +1045,17 @@ __device__ __forceinline__ int next_tile(const TileQueue& q, uint32_t* head, int
 template <int TS, int BATCH>
 __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Records rec, const uint2* ranges,
                                                      const uint32_t* vals, float* T_final, uint32_t* n_contrib,
-                                                     uint32_t* n_used, TileQueue q) {
+                                                     uint32_t* n_used, TileQueue q, Ckpt ck) {
   constexpr int NT = TS * TS;
   __shared__ float4 s_r0[BATCH];
   __shared__ float4 s_r1[BATCH];
   __shared__ float4 s_rgb[BATCH];
   __shared__ int s_item;
+  __shared__ uint32_t s_nmax;
   for (;;) {
     const int tile = next_tile(q, q.ctrl + kHeadFwd, vt.total_tiles, &s_item);
     if (tile < 0) return;
+    if (threadIdx.x == 0) s_nmax = 0;
     const ViewDev& cam = vt.v[view_of_tile(vt, tile)];
     const int lt = tile - cam.tile_off;
     const int ty = lt / cam.tiles_x, tx = lt - ty * cam.tiles_x;
@@ -1029,8 +1067,20 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
     uint32_t last = 0, used = 0;
     bool done = !inside;
+    const int64_t slot0 = int64_t(ck.slot_off[tile]) - 1;
     for (int b0 = 0; b0 < n; b0 += BATCH) {
       if (__syncthreads_count(!done) == 0) break;
+      if (b0 > 0) {  // checkpoint: the state in front of entry b0
+        const int64_t slot = slot0 + b0 / BATCH;
+        if (slot < ck.cap_slots) {
+          float* st = ck.state + slot * (5 * NT) + threadIdx.x;
+          st[0] = T;
+          st[NT] = C0;
+          st[2 * NT] = C1;
+          st[3 * NT] = C2;
+          st[4 * NT] = D;
+        }
+      }
       for (int j = threadIdx.x; j < BATCH && b0 + j < n; j += NT) {
         const uint32_t id = vals[rg.x + b0 + j];
         s_r0[j] = rec.r0[id];
@@ -1038,38 +1088,40 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
         s_rgb[j] = rec.rgb[id];
       }
       __syncthreads();
-      if (!done) {
-        const int cnt = min(BATCH, n - b0);
-        // splat values of four staged entries are independent of the running
-        // transmittance: evaluate them together, then composite strictly in list order
-        for (int j = 0; j < cnt && !done; j += 4) {
-          float a4[4], z4[4];
+      // four staged entries at a time: their splat values do not depend on the running
+      // transmittance, so they are evaluated together (loads and exponentials overlap);
+      // compositing then runs in list order, straight-line: a lane that has stopped, or
+      // for which the splat is below the skip threshold, adds exact zeros and keeps T.
+      // The wavefront leaves the batch once all its lanes have stopped.
+      const int cnt = min(BATCH, n - b0);
+      for (int j = 0; j < cnt; j += 4) {
+        if (__ballot(!done) == 0ull) break;
+        float a4[4], z4[4];
+        float4 c4[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int jj = min(j + u, cnt - 1);
-            const float4 r0 = s_r0[jj];
-            const float4 r1 = s_r1[jj];
-            float G;
-            a4[u] = splat_alpha(fpx - r0.x, fpy - r0.y, r0.z, r0.w, r1.x, r1.y, G);
-            z4[u] = r1.z;
-          }
+        for (int u = 0; u < 4; ++u) {
+          const int jj = min(j + u, cnt - 1);
+          const float4 r0 = s_r0[jj];
+          const float4 r1 = s_r1[jj];
+          c4[u] = s_rgb[jj];
+          float G;
+          a4[u] = splat_alpha(fpx - r0.x, fpy - r0.y, r0.z, r0.w, r1.x, r1.y, G);
+          z4[u] = r1.z;
+        }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            if (j + u >= cnt || done) break;
-            const float a = a4[u];
-            if (a < ru.amin) continue;
-            const float al = a < ru.amax ? a : ru.amax;
-            const float wgt = al * T;
-            const float4 c = s_rgb[j + u];
-            C0 += c.x * wgt;
-            C1 += c.y * wgt;
-            C2 += c.z * wgt;
-            D += z4[u] * wgt;
-            T = T * (1.f - al);
-            last = uint32_t(b0 + j + u + 1);
-            ++used;
-            if (T < ru.Tmin) done = true;
-          }
+        for (int u = 0; u < 4; ++u) {
+          const float a = a4[u];
+          const bool act = j + u < cnt && !done && !(a < ru.amin);
+          const float al = a < ru.amax ? a : ru.amax;
+          const float wgt = act ? al * T : 0.f;
+          C0 += c4[u].x * wgt;
+          C1 += c4[u].y * wgt;
+          C2 += c4[u].z * wgt;
+          D += z4[u] * wgt;
+          T = act ? T * (1.f - al) : T;
+          last = act ? uint32_t(b0 + j + u + 1) : last;
+          used += act ? 1u : 0u;
+          done = done || T < ru.Tmin;
         }
       }
     }
@@ -1084,7 +1136,13 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
       T_final[cam.pix_off + pix] = T;
       n_contrib[cam.pix_off + pix] = last;
       n_used[cam.pix_off + pix] = used;
+      ck.acc[cam.pix_off + pix] = make_float4(C0, C1, C2, D);
     }
+    const uint32_t wl = wave_max_u32(last);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) atomicMax(&s_nmax, wl);
+    __syncthreads();
+    if (threadIdx.x == 0) ck.tile_nmax[tile] = s_nmax;
   }
 }
 
@@ -1138,26 +1196,68 @@ __global__ __launch_bounds__(1024) void k_loss_sum(const float* part, int count,
 }
 
 // ------------------------------------------------------------------------------------
-// K8: backward compositing.  Back to front over each pixel's contributors; the
-// transmittance before contributor i is T_{i+1} / (1 - alpha_i), starting from the saved
-// final value; the colour/depth behind i is carried as a running blend.
+// K8: backward compositing, back to front over each pixel's contributors; the
+// transmittance before contributor i is T_{i+1} / (1 - alpha_i), and the colour/depth
+// behind i is carried as a running blend.  The work is cut into (tile, batch) items that
+// run independently: an item starts from the pixel's final state when its list ends in
+// the batch, else from the forward's checkpoint at the batch's end.  So no wavefront
+// walks more than one batch, however long the tile's lists are.
 //
 // Each wavefront walks the staged batch only down from its own longest contributor list.
 // The ten per-(pixel, splat) partials are summed across the wavefront with lane swaps
-// and DPP (wave_sum10); with more
-// than one wavefront per tile the wavefront sums meet in LDS and the block adds each
-// splat's total to the 2D-gradient buffer once per batch, with the atomics spread over
-// all lanes.
+// and DPP (wave_sum10); with more than one wavefront per tile the wavefront sums meet
+// in LDS and the block adds each splat's total to the 2D-gradient buffer once per item,
+// with the atomics spread over all lanes.
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-  for (int off = 32; off > 0; off >>= 1) v = max(v, uint32_t(__shfl_xor(v, off)));
-  return v;
+// Backward work items, in the tile queue's longest-first order: (tile, batch) for every
+// batch that holds a contributor of some pixel of the tile.  One block.
+__global__ __launch_bounds__(1024) void k_bwd_items(const uint32_t* order, int total, int batch, Ckpt ck,
+                                                   uint32_t* ctrl) {
+  __shared__ uint32_t red[16], carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int i0 = 0; i0 < total; i0 += 1024) {
+    const int i = i0 + threadIdx.x;
+    uint32_t t = 0, nb = 0;
+    if (i < total) {
+      t = order[i];
+      nb = (ck.tile_nmax[t] + uint32_t(batch) - 1u) / uint32_t(batch);
+    }
+    const uint32_t base = carry + block_exclusive_scan_u32(nb, red);
+    for (uint32_t k = 0; k < nb; ++k)
+      if (int64_t(base) + k < ck.cap_items) ck.items[base + k] = make_uint2(t, k);
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = base + nb;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ctrl[kItems] = uint32_t(min<int64_t>(carry, ck.cap_items));
+}
+
+// Block-uniform: the next backward work item, or -1; the first items (the longest tiles)
+// take a higher wave priority, as in next_tile.
+__device__ __forceinline__ int next_item(uint32_t* head, int total, int* s_item) {
+  __syncthreads();
+  if (threadIdx.x == 0) *s_item = int(atomicAdd(head, 1u));
+  __syncthreads();
+  const int item = *s_item;
+  if (item < total) {
+    if (item * 16 < total)
+      __builtin_amdgcn_s_setprio(3);
+    else if (item * 8 < total)
+      __builtin_amdgcn_s_setprio(2);
+    else if (item * 4 < total)
+      __builtin_amdgcn_s_setprio(1);
+    else
+      __builtin_amdgcn_s_setprio(0);
+  }
+  return item < total ? item : -1;
 }
 
 template <int TS, int BATCH>
 __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Records rec, const uint2* ranges,
                                                      const uint32_t* vals, const float* T_final,
-                                                     const uint32_t* n_contrib, float* grad2d, TileQueue q) {
+                                                     const uint32_t* n_contrib, float* grad2d, TileQueue q,
+                                                     Ckpt ck) {
   constexpr int NT = TS * TS;
   constexpr bool kBlockSum = NT > 64;
   __shared__ float4 s_r0[BATCH];
@@ -1169,120 +1269,129 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
   __shared__ int s_item;
   if (kBlockSum)
     for (int i = threadIdx.x; i < 10 * BATCH; i += NT) (&s_g[0][0])[i] = 0.f;
+  const int total = int(q.ctrl[kItems]);
   for (;;) {
-  const int tile = next_tile(q, q.ctrl + kHeadBwd, vt.total_tiles, &s_item);
-  if (tile < 0) return;
+  const int item = next_item(q.ctrl + kHeadBwd, total, &s_item);
+  if (item < 0) return;
+  const uint2 it = ck.items[item];
+  const int tile = int(it.x), bat = int(it.y);
   const ViewDev& cam = vt.v[view_of_tile(vt, tile)];
   const int lt = tile - cam.tile_off;
   const int ty = lt / cam.tiles_x, tx = lt - ty * cam.tiles_x;
   const int px = tx * TS + int(threadIdx.x % TS), py = ty * TS + int(threadIdx.x / TS);
   const bool inside = px < cam.W && py < cam.H;
   const uint2 rg = ranges[tile];
+  const int s0 = bat * BATCH;                        // first list entry of the item
+  const int cnt = min(BATCH, int(rg.y - rg.x) - s0);  // entries of the item's batch
   const int lane = threadIdx.x & 63;
   const int64_t P = int64_t(cam.W) * cam.H;
   const int64_t pix = int64_t(py) * cam.W + px;
-  float T = 1.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gA = 0.f;
-  uint32_t last = 0;
+  // this pixel's contributors in the batch: local positions [0, top); the state behind
+  // them is the final one when the pixel's list ends in the batch, else the checkpoint
+  // at the batch's end, with the colour/depth behind = (total - in front + T_final bg) / T
+  float T = 1.f, Tfin = 1.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gA = 0.f;
+  float BC0 = ru.bg[0], BC1 = ru.bg[1], BC2 = ru.bg[2], BD = 0.f;
+  int top = 0;
   if (inside) {
-    T = T_final[cam.pix_off + pix];
-    last = n_contrib[cam.pix_off + pix];
-    if (cam.g_color) {
-      gC0 = cam.g_color[pix];
-      gC1 = cam.g_color[P + pix];
-      gC2 = cam.g_color[2 * P + pix];
+    const int nc = int(n_contrib[cam.pix_off + pix]);
+    if (nc > s0) {
+      Tfin = T_final[cam.pix_off + pix];
+      if (cam.g_color) {
+        gC0 = cam.g_color[pix];
+        gC1 = cam.g_color[P + pix];
+        gC2 = cam.g_color[2 * P + pix];
+      }
+      if (cam.g_depth) gD = cam.g_depth[pix];
+      if (cam.g_alpha) gA = cam.g_alpha[pix];
+      if (nc <= s0 + BATCH) {
+        T = Tfin;
+        top = nc - s0;
+      } else {
+        const int64_t slot = int64_t(ck.slot_off[tile]) + bat;
+        const float* st = ck.state + slot * (5 * NT) + threadIdx.x;
+        const float4 acc = ck.acc[cam.pix_off + pix];
+        T = st[0];
+        const float inv = 1.f / T;
+        BC0 = (acc.x - st[NT] + Tfin * ru.bg[0]) * inv;
+        BC1 = (acc.y - st[2 * NT] + Tfin * ru.bg[1]) * inv;
+        BC2 = (acc.z - st[3 * NT] + Tfin * ru.bg[2]) * inv;
+        BD = (acc.w - st[4 * NT]) * inv;
+        top = BATCH;
+      }
     }
-    if (cam.g_depth) gD = cam.g_depth[pix];
-    if (cam.g_alpha) gA = cam.g_alpha[pix];
   }
-  const int wmax = int(wave_max_u32(last));
+  const int wmax = int(wave_max_u32(uint32_t(top)));
   if (threadIdx.x == 0) s_max = 0;
   __syncthreads();
   if (lane == 0 && wmax) atomicMax(&s_max, uint32_t(wmax));
   __syncthreads();
-  const int nmax = int(s_max);
-  const float Tfin = T;
+  const int nstage = min(cnt, int(s_max));
   const float fpx = float(px), fpy = float(py);
-  float BC0 = ru.bg[0], BC1 = ru.bg[1], BC2 = ru.bg[2], BD = 0.f;
-  for (int bend = nmax; bend > 0; bend -= BATCH) {
-    const int bstart = bend > BATCH ? bend - BATCH : 0;
-    const int cnt = bend - bstart;
-    __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += NT) {
-      const uint32_t id = vals[rg.x + bstart + j];
-      s_id[j] = id;
-      s_r0[j] = rec.r0[id];
-      s_r1[j] = rec.r1[id];
-      s_rgb[j] = rec.rgb[id];
-    }
-    __syncthreads();
-    const int jtop = min(cnt, wmax - bstart) - 1;  // wavefront-uniform
-    for (int j = jtop; j >= 0; --j) {
-      const int pos = bstart + j;
-      float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, g4 = 0.f, g5 = 0.f, g6 = 0.f, g7 = 0.f, g8 = 0.f, g9 = 0.f;
-      bool act = false;
-      if (pos < int(last)) {
-        const float4 r0 = s_r0[j];
-        const float4 r1 = s_r1[j];
-        const float dx = fpx - r0.x, dy = fpy - r0.y;
-        float G;
-        const float a = splat_alpha(dx, dy, r0.z, r0.w, r1.x, r1.y, G);
-        if (!(a < ru.amin)) {
-          act = true;
-          const float4 c = s_rgb[j];
-          const float al = a < ru.amax ? a : ru.amax;
-          const float om = 1.f - al;
-          const float iom = __builtin_amdgcn_rcpf(om);
-          T = T * iom;
-          const float wgt = al * T;
-          g6 = gC0 * wgt;
-          g7 = gC1 * wgt;
-          g8 = gC2 * wgt;
-          g9 = gD * wgt;
-          const float dal =
-              T * (gC0 * (c.x - BC0) + gC1 * (c.y - BC1) + gC2 * (c.z - BC2) + gD * (r1.z - BD)) + gA * Tfin * iom;
-          BC0 = al * c.x + om * BC0;
-          BC1 = al * c.y + om * BC1;
-          BC2 = al * c.z + om * BC2;
-          BD = al * r1.z + om * BD;
-          const float da = a <= ru.amax ? dal : 0.f;
-          g5 = da * G;
-          const float dpw = da * a;
-          g0 = dpw * (r0.z * dx + r0.w * dy);
-          g1 = dpw * (r0.w * dx + r1.x * dy);
-          g2 = -0.5f * dpw * dx * dx;
-          g3 = -dpw * dx * dy;
-          g4 = -0.5f * dpw * dy * dy;
-        }
-      }
-      if (__ballot(act) != 0ull) {
-        const float gv[10] = {g0, g1, g2, g3, g4, g5, g6, g7, g8, g9};
-        float w0, w1, w2;
-        wave_sum10(gv, w0, w1, w2);
-        if ((lane & 15) == 0) {  // one lane per row adds its row's totals
-          const int row = lane >> 4;
-          const int k = row == 1 ? 2 : (row == 2 ? 1 : row);
-          if (kBlockSum) {
-            atomicAdd(&s_g[k][j], w0);
-            atomicAdd(&s_g[4 + k][j], w1);
-            if (!(row & 1)) atomicAdd(&s_g[8 + (row >> 1)][j], w2);
-          } else {
-            float* dst = grad2d + int64_t(s_id[j]) * kGrad2D;
-            unsafeAtomicAdd(dst + k, w0);
-            unsafeAtomicAdd(dst + 4 + k, w1);
-            if (!(row & 1)) unsafeAtomicAdd(dst + 8 + (row >> 1), w2);
-          }
-        }
+  for (int j = threadIdx.x; j < nstage; j += NT) {
+    const uint32_t id = vals[rg.x + s0 + j];
+    s_id[j] = id;
+    s_r0[j] = rec.r0[id];
+    s_r1[j] = rec.r1[id];
+    s_rgb[j] = rec.rgb[id];
+  }
+  __syncthreads();
+  for (int j = min(cnt, wmax) - 1; j >= 0; --j) {
+    // straight-line for every lane: lanes that do not take part (past their list, or
+    // below the skip threshold) keep T and the running blends and add zeros
+    const float4 r0 = s_r0[j];
+    const float4 r1 = s_r1[j];
+    const float dx = fpx - r0.x, dy = fpy - r0.y;
+    float G;
+    const float a = splat_alpha(dx, dy, r0.z, r0.w, r1.x, r1.y, G);
+    const bool act = j < top && !(a < ru.amin);
+    if (__ballot(act) == 0ull) continue;
+    const float4 c = s_rgb[j];
+    const float al = a < ru.amax ? a : ru.amax;
+    const float om = 1.f - al;
+    const float iom = __builtin_amdgcn_rcpf(om);
+    T = act ? T * iom : T;
+    const float wgt = act ? al * T : 0.f;
+    const float g6 = gC0 * wgt, g7 = gC1 * wgt, g8 = gC2 * wgt, g9 = gD * wgt;
+    const float dal =
+        T * (gC0 * (c.x - BC0) + gC1 * (c.y - BC1) + gC2 * (c.z - BC2) + gD * (r1.z - BD)) + gA * Tfin * iom;
+    BC0 = act ? al * c.x + om * BC0 : BC0;
+    BC1 = act ? al * c.y + om * BC1 : BC1;
+    BC2 = act ? al * c.z + om * BC2 : BC2;
+    BD = act ? al * r1.z + om * BD : BD;
+    const float da = (act && a <= ru.amax) ? dal : 0.f;
+    const float g5 = da * G;
+    const float dpw = da * a;
+    const float g0 = dpw * (r0.z * dx + r0.w * dy);
+    const float g1 = dpw * (r0.w * dx + r1.x * dy);
+    const float g2 = -0.5f * dpw * dx * dx;
+    const float g3 = -dpw * dx * dy;
+    const float g4 = -0.5f * dpw * dy * dy;
+    const float gv[10] = {g0, g1, g2, g3, g4, g5, g6, g7, g8, g9};
+    float w0, w1, w2;
+    wave_sum10(gv, w0, w1, w2);
+    if ((lane & 15) == 0) {  // one lane per row adds its row's totals
+      const int row = lane >> 4;
+      const int k = row == 1 ? 2 : (row == 2 ? 1 : row);
+      if (kBlockSum) {
+        atomicAdd(&s_g[k][j], w0);
+        atomicAdd(&s_g[4 + k][j], w1);
+        if (!(row & 1)) atomicAdd(&s_g[8 + (row >> 1)][j], w2);
+      } else {
+        float* dst = grad2d + int64_t(s_id[j]) * kGrad2D;
+        unsafeAtomicAdd(dst + k, w0);
+        unsafeAtomicAdd(dst + 4 + k, w1);
+        if (!(row & 1)) unsafeAtomicAdd(dst + 8 + (row >> 1), w2);
       }
     }
-    if (kBlockSum) {
-      __syncthreads();
-      for (int i = threadIdx.x; i < 10 * cnt; i += NT) {
-        const int k = i / cnt, j = i - k * cnt;
-        const float v = s_g[k][j];
-        if (v != 0.f) {
-          unsafeAtomicAdd(grad2d + int64_t(s_id[j]) * kGrad2D + k, v);
-          s_g[k][j] = 0.f;
-        }
+  }
+  if (kBlockSum) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 10 * nstage; i += NT) {
+      const int k = i / nstage, j = i - k * nstage;
+      const float v = s_g[k][j];
+      if (v != 0.f) {
+        unsafeAtomicAdd(grad2d + int64_t(s_id[j]) * kGrad2D + k, v);
+        s_g[k][j] = 0.f;
       }
     }
   }
@@ -1626,29 +1735,34 @@ static int resident_blocks(Kern kern, int threads) {
 template <int TS, int BATCH>
 static void blend_fwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
                         const uint32_t* vals, float* T_final, uint32_t* n_contrib, uint32_t* n_used,
-                        const TileQueue& q, hipStream_t s) {
+                        const TileQueue& q, const Ckpt& ck, hipStream_t s) {
   const int grid = std::min(vt.total_tiles, resident_blocks(k_blend_fwd<TS, BATCH>, TS * TS));
-  k_blend_fwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q);
+  k_blend_fwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck);
 }
 
-hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* order, hipStream_t s) {
+hipError_t launch_tile_order(const uint2* ranges, int total_tiles, int batch, uint32_t* order, const Ckpt& ck,
+                             hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
-  k_tile_order<<<1, 1024, 0, s>>>(ranges, total_tiles, order);
+  k_tile_order<<<1, 1024, 0, s>>>(ranges, total_tiles, batch, order, ck.slot_off);
   return hipGetLastError();
 }
 
+int64_t ckpt_slots(int64_t cap_M, int batch) { return cap_M / batch + 1; }
+
+int64_t bwd_items_cap(int64_t cap_M, int total_tiles, int batch) { return cap_M / batch + total_tiles + 1; }
+
 hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
-                            uint32_t* n_used, const TileQueue& q, hipStream_t s) {
+                            uint32_t* n_used, const TileQueue& q, const Ckpt& ck, hipStream_t s) {
   if (vt.total_tiles == 0) return hipSuccess;
   const bool b256 = batch == 256;
   switch (tile) {
-    case 8: b256 ? blend_fwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, s)
-                 : blend_fwd_t<8, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, s); break;
-    case 32: b256 ? blend_fwd_t<32, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, s)
-                  : blend_fwd_t<32, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, s); break;
-    default: b256 ? blend_fwd_t<16, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, s)
-                  : blend_fwd_t<16, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, s); break;
+    case 8: b256 ? blend_fwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck, s)
+                 : blend_fwd_t<8, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck, s); break;
+    case 32: b256 ? blend_fwd_t<32, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck, s)
+                  : blend_fwd_t<32, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck, s); break;
+    default: b256 ? blend_fwd_t<16, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck, s)
+                  : blend_fwd_t<16, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck, s); break;
   }
   return hipGetLastError();
 }
@@ -1669,23 +1783,25 @@ hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* part, float
 template <int TS, int BATCH>
 static void blend_bwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
                         const uint32_t* vals, const float* T_final, const uint32_t* n_contrib, float* grad2d,
-                        const TileQueue& q, hipStream_t s) {
-  const int grid = std::min(vt.total_tiles, resident_blocks(k_blend_bwd<TS, BATCH>, TS * TS));
-  k_blend_bwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q);
+                        const TileQueue& q, const Ckpt& ck, hipStream_t s) {
+  const int grid = int(std::min<int64_t>(ck.cap_items, resident_blocks(k_blend_bwd<TS, BATCH>, TS * TS)));
+  k_blend_bwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck);
 }
 
 hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, const float* T_final,
-                            const uint32_t* n_contrib, float* grad2d, const TileQueue& q, hipStream_t s) {
+                            const uint32_t* n_contrib, float* grad2d, const TileQueue& q, const Ckpt& ck,
+                            hipStream_t s) {
   if (vt.total_tiles == 0) return hipSuccess;
+  k_bwd_items<<<1, 1024, 0, s>>>(q.order, vt.total_tiles, batch, ck, q.ctrl);
   const bool b256 = batch == 256;
   switch (tile) {
-    case 8: b256 ? blend_bwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, s)
-                 : blend_bwd_t<8, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, s); break;
-    case 32: b256 ? blend_bwd_t<32, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, s)
-                  : blend_bwd_t<32, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, s); break;
-    default: b256 ? blend_bwd_t<16, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, s)
-                  : blend_bwd_t<16, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, s); break;
+    case 8: b256 ? blend_bwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck, s)
+                 : blend_bwd_t<8, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck, s); break;
+    case 32: b256 ? blend_bwd_t<32, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck, s)
+                  : blend_bwd_t<32, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck, s); break;
+    default: b256 ? blend_bwd_t<16, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck, s)
+                  : blend_bwd_t<16, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck, s); break;
   }
   return hipGetLastError();
 }
