@@ -240,6 +240,8 @@ gsr_status make_saved(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* ca
   }
   vt.total_tiles = int32_t(tiles);
   vt.total_rows = int32_t(rows);
+  sv->ck.kmax = ckpt_per_tile(s->batch);
+  sv->ck.cap_items = bwd_items_cap(vt.total_tiles, s->batch);
   sv->total_pix = pix;
   const int64_t VN = int64_t(V) * g->n;
   sv->nblk = int((g->n + kProjThreads - 1) / kProjThreads);
@@ -252,9 +254,10 @@ gsr_status make_saved(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* ca
       (st = alloc_in(sv, B, &sv->d_total, 4)) != GSR_OK || (st = alloc_in(sv, B, &sv->ranges, size_t(tiles))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->order, size_t(tiles))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->loss_part, size_t(loss_partials(vt)))) != GSR_OK ||
-      (st = alloc_in(sv, B, &sv->ck.slot_off, size_t(tiles))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->ck.tile_nmax, size_t(tiles))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->ck.acc, size_t(pix))) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->ck.state, size_t(tiles) * sv->ck.kmax * 5 * s->tile * s->tile)) != GSR_OK ||
+      (st = alloc_in(sv, B, &sv->ck.items, size_t(sv->ck.cap_items))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->ctrl, kCtrlWords)) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->T_final, size_t(pix))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->n_contrib, size_t(pix))) != GSR_OK ||
@@ -287,14 +290,6 @@ gsr_status alloc_sort(gsr_saved* sv, int64_t cap_vis, int64_t cap_M, bool persis
       (st = alloc_in(sv, T, &p.seg_start, size_t(p.rows) + 1)) != GSR_OK ||
       (st = alloc_in(sv, T, &p.cntF, size_t(p.cap_flat))) != GSR_OK ||
       (st = alloc_in(sv, T, &p.part, size_t(nparts))) != GSR_OK || (st = alloc_in(sv, T, &p.words, 4)) != GSR_OK)
-    return st;
-  // checkpoints (kept for the backward): worst case, every batch boundary of every tile
-  const int NT = sv->s.tile * sv->s.tile;
-  Ckpt& ck = sv->ck;
-  ck.cap_slots = ckpt_slots(cap_M, sv->s.batch);
-  ck.cap_items = bwd_items_cap(cap_M, sv->vt.total_tiles, sv->s.batch);
-  if ((st = alloc_in(sv, sv->blocks, &ck.state, size_t(ck.cap_slots) * 5 * NT)) != GSR_OK ||
-      (st = alloc_in(sv, sv->blocks, &ck.items, size_t(ck.cap_items))) != GSR_OK)
     return st;
   return GSR_OK;
 }
@@ -340,7 +335,7 @@ hipError_t enqueue_sort_blend(gsr_saved* sv, hipStream_t s, bool timing) {
                    s, tm);
   if (e == hipSuccess)
     e = T(K_TILE_ORDER, [&] {
-      return launch_tile_order(sv->ranges, sv->vt.total_tiles, sv->s.batch, sv->order, sv->ck, s);
+      return launch_tile_order(sv->ranges, sv->vt.total_tiles, sv->order, s);
     });
   if (e == hipSuccess)
     e = T(K_BLEND_FWD, [&] {

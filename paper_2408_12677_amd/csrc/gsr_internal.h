@@ -169,17 +169,17 @@ struct TileQueue {
 };
 
 // What the forward keeps so that the backward can run a tile's list in independent
-// pieces of one LDS batch each: at every batch boundary the forward passes, per pixel,
-// the transmittance in front of it and the colour and depth accumulated up to it (a
-// "checkpoint"); per pixel the accumulated totals; per tile its longest contributor list.
-// The backward's work items are (tile, batch) pairs.
+// pieces of one LDS batch each: at the first `kmax` batch boundaries the forward passes,
+// per pixel, the transmittance in front of it and the colour and depth accumulated up
+// to it (a "checkpoint"); per pixel the accumulated totals; per tile its longest
+// contributor list.  The backward's work items are (tile, batch) pairs; batches past
+// the last checkpoint of a tile form one item that walks them all.
 struct Ckpt {
-  uint32_t* slot_off;   // [tiles] first checkpoint slot of each tile (batch boundary 1)
-  float* state;         // [slots][5][pixels of a tile]: T, colour (3), depth in front
+  float* state;         // [tiles][kmax][5][pixels of a tile]: T, colour (3), depth in front
   float4* acc;          // [pixels] colour (3) and depth accumulated, without background
   uint32_t* tile_nmax;  // [tiles] longest contributor list of the tile
-  uint2* items;         // [cap_items] backward work items (tile, batch)
-  int64_t cap_slots;
+  uint2* items;         // [cap_items] backward work items (tile, first batch)
+  int32_t kmax;         // checkpoints per tile
   int64_t cap_items;
 };
 
@@ -225,12 +225,10 @@ hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* to
 hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
                           const unsigned long long* pairs, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
                           int64_t cap, uint32_t* overflow, hipStream_t s);
-// Longest-list-first order of the tiles and the checkpoint slots of each tile.
-hipError_t launch_tile_order(const uint2* ranges, int total_tiles, int batch, uint32_t* order, const Ckpt& ck,
-                             hipStream_t s);
-// Checkpoint slots and work items the capacities (pairs, tiles) need at a batch size.
-int64_t ckpt_slots(int64_t cap_M, int batch);
-int64_t bwd_items_cap(int64_t cap_M, int total_tiles, int batch);
+hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* order, hipStream_t s);
+// Checkpoints per tile, and the backward work items of all tiles, at a batch size.
+int ckpt_per_tile(int batch);
+int64_t bwd_items_cap(int total_tiles, int batch);
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                              uint32_t* hist, uint32_t* digit_tot, const unsigned long long* count, int64_t cap,
                              const uint32_t* overflow, int key_bits, bool* result_in_alt, int* passes, hipStream_t s,

@@ -972,11 +972,9 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t value, i
 // kernels run as persistent blocks that take the next tile from a device counter, so the
 // longest lists start first and short ones fill the tail.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_tile_order(const uint2* ranges, int total, int batch, uint32_t* order,
-                                                    uint32_t* slot_off) {
-  __shared__ uint32_t cnt[kBuckets], start[kBuckets], red[16], carry;
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2* ranges, int total, uint32_t* order) {
+  __shared__ uint32_t cnt[kBuckets], start[kBuckets];
   if (threadIdx.x < kBuckets) cnt[threadIdx.x] = 0;
-  if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int i = threadIdx.x; i < total; i += 1024) {
     const uint2 r = ranges[i];
@@ -996,22 +994,6 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2* ranges, int to
     const uint2 r = ranges[i];
     const uint32_t len = r.y - r.x;
     order[atomicAdd(&start[len ? 32u - uint32_t(__clz(len)) : 0u], 1u)] = uint32_t(i);
-  }
-  // checkpoint slots: a tile of n entries has ceil(n / batch) - 1 inner batch boundaries
-  for (int i0 = 0; i0 < total; i0 += 1024) {
-    const int i = i0 + threadIdx.x;
-    uint32_t k = 0;
-    if (i < total) {
-      const uint2 r = ranges[i];
-      const uint32_t nb = (r.y - r.x + uint32_t(batch) - 1u) / uint32_t(batch);
-      k = nb ? nb - 1u : 0u;
-    }
-    const uint32_t ex = block_exclusive_scan_u32(k, red);
-    const uint32_t c = carry;
-    if (i < total) slot_off[i] = c + ex;
-    __syncthreads();
-    if (threadIdx.x == 1023) carry = c + ex + k;
-    __syncthreads();
   }
 }
 
@@ -1067,13 +1049,12 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
     uint32_t last = 0, used = 0;
     bool done = !inside;
-    const int64_t slot0 = int64_t(ck.slot_off[tile]) - 1;
     for (int b0 = 0; b0 < n; b0 += BATCH) {
       if (__syncthreads_count(!done) == 0) break;
       if (b0 > 0) {  // checkpoint: the state in front of entry b0
-        const int64_t slot = slot0 + b0 / BATCH;
-        if (slot < ck.cap_slots) {
-          float* st = ck.state + slot * (5 * NT) + threadIdx.x;
+        const int k = b0 / BATCH;
+        if (k <= ck.kmax) {
+          float* st = ck.state + (int64_t(tile) * ck.kmax + (k - 1)) * (5 * NT) + threadIdx.x;
           st[0] = T;
           st[NT] = C0;
           st[2 * NT] = C1;
@@ -1200,8 +1181,8 @@ __global__ __launch_bounds__(1024) void k_loss_sum(const float* part, int count,
 // transmittance before contributor i is T_{i+1} / (1 - alpha_i), and the colour/depth
 // behind i is carried as a running blend.  The work is cut into (tile, batch) items that
 // run independently: an item starts from the pixel's final state when its list ends in
-// the batch, else from the forward's checkpoint at the batch's end.  So no wavefront
-// walks more than one batch, however long the tile's lists are.
+// the item, else from the forward's checkpoint at the item's end.  So no wavefront walks
+// more than one batch until a tile's checkpoints run out.
 //
 // Each wavefront walks the staged batch only down from its own longest contributor list.
 // The ten per-(pixel, splat) partials are summed across the wavefront with lane swaps
@@ -1210,7 +1191,8 @@ __global__ __launch_bounds__(1024) void k_loss_sum(const float* part, int count,
 // with the atomics spread over all lanes.
 // ------------------------------------------------------------------------------------
 // Backward work items, in the tile queue's longest-first order: (tile, batch) for every
-// batch that holds a contributor of some pixel of the tile.  One block.
+// batch that holds a contributor of some pixel of the tile, up to the tile's last
+// checkpoint; one more item (tile, kmax) covers all later batches.  One block.
 __global__ __launch_bounds__(1024) void k_bwd_items(const uint32_t* order, int total, int batch, Ckpt ck,
                                                    uint32_t* ctrl) {
   __shared__ uint32_t red[16], carry;
@@ -1218,16 +1200,17 @@ __global__ __launch_bounds__(1024) void k_bwd_items(const uint32_t* order, int t
   __syncthreads();
   for (int i0 = 0; i0 < total; i0 += 1024) {
     const int i = i0 + threadIdx.x;
-    uint32_t t = 0, nb = 0;
+    uint32_t t = 0, ni = 0;
     if (i < total) {
       t = order[i];
-      nb = (ck.tile_nmax[t] + uint32_t(batch) - 1u) / uint32_t(batch);
+      const uint32_t nb = (ck.tile_nmax[t] + uint32_t(batch) - 1u) / uint32_t(batch);
+      ni = nb <= uint32_t(ck.kmax) ? nb : uint32_t(ck.kmax) + 1u;
     }
-    const uint32_t base = carry + block_exclusive_scan_u32(nb, red);
-    for (uint32_t k = 0; k < nb; ++k)
+    const uint32_t base = carry + block_exclusive_scan_u32(ni, red);
+    for (uint32_t k = 0; k < ni; ++k)
       if (int64_t(base) + k < ck.cap_items) ck.items[base + k] = make_uint2(t, k);
     __syncthreads();
-    if (threadIdx.x == 1023) carry = base + nb;
+    if (threadIdx.x == 1023) carry = base + ni;
     __syncthreads();
   }
   if (threadIdx.x == 0) ctrl[kItems] = uint32_t(min<int64_t>(carry, ck.cap_items));
@@ -1274,27 +1257,27 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
   const int item = next_item(q.ctrl + kHeadBwd, total, &s_item);
   if (item < 0) return;
   const uint2 it = ck.items[item];
-  const int tile = int(it.x), bat = int(it.y);
+  const int tile = int(it.x), bf = int(it.y);
   const ViewDev& cam = vt.v[view_of_tile(vt, tile)];
   const int lt = tile - cam.tile_off;
   const int ty = lt / cam.tiles_x, tx = lt - ty * cam.tiles_x;
   const int px = tx * TS + int(threadIdx.x % TS), py = ty * TS + int(threadIdx.x / TS);
   const bool inside = px < cam.W && py < cam.H;
   const uint2 rg = ranges[tile];
-  const int s0 = bat * BATCH;                        // first list entry of the item
-  const int cnt = min(BATCH, int(rg.y - rg.x) - s0);  // entries of the item's batch
+  const int lo = bf * BATCH;  // the item's list entries: [lo, hi)
+  const int hi = bf < ck.kmax ? lo + BATCH : int(rg.y - rg.x);
   const int lane = threadIdx.x & 63;
   const int64_t P = int64_t(cam.W) * cam.H;
   const int64_t pix = int64_t(py) * cam.W + px;
-  // this pixel's contributors in the batch: local positions [0, top); the state behind
-  // them is the final one when the pixel's list ends in the batch, else the checkpoint
-  // at the batch's end, with the colour/depth behind = (total - in front + T_final bg) / T
+  // this pixel's contributors in the item: positions [lo, top); the state behind them is
+  // the final one when the pixel's list ends inside the item, else the checkpoint at the
+  // item's end, with the colour/depth behind = (total - in front + T_final bg) / T
   float T = 1.f, Tfin = 1.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gA = 0.f;
   float BC0 = ru.bg[0], BC1 = ru.bg[1], BC2 = ru.bg[2], BD = 0.f;
   int top = 0;
   if (inside) {
     const int nc = int(n_contrib[cam.pix_off + pix]);
-    if (nc > s0) {
+    if (nc > lo) {
       Tfin = T_final[cam.pix_off + pix];
       if (cam.g_color) {
         gC0 = cam.g_color[pix];
@@ -1303,12 +1286,11 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
       }
       if (cam.g_depth) gD = cam.g_depth[pix];
       if (cam.g_alpha) gA = cam.g_alpha[pix];
-      if (nc <= s0 + BATCH) {
+      if (nc <= hi) {
         T = Tfin;
-        top = nc - s0;
-      } else {
-        const int64_t slot = int64_t(ck.slot_off[tile]) + bat;
-        const float* st = ck.state + slot * (5 * NT) + threadIdx.x;
+        top = nc;
+      } else {  // only single-batch items end before the list: checkpoint bf + 1 <= kmax
+        const float* st = ck.state + (int64_t(tile) * ck.kmax + bf) * (5 * NT) + threadIdx.x;
         const float4 acc = ck.acc[cam.pix_off + pix];
         T = st[0];
         const float inv = 1.f / T;
@@ -1316,7 +1298,7 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
         BC1 = (acc.y - st[2 * NT] + Tfin * ru.bg[1]) * inv;
         BC2 = (acc.z - st[3 * NT] + Tfin * ru.bg[2]) * inv;
         BD = (acc.w - st[4 * NT]) * inv;
-        top = BATCH;
+        top = hi;
       }
     }
   }
@@ -1325,73 +1307,78 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
   __syncthreads();
   if (lane == 0 && wmax) atomicMax(&s_max, uint32_t(wmax));
   __syncthreads();
-  const int nstage = min(cnt, int(s_max));
+  const int bmax = int(s_max);
   const float fpx = float(px), fpy = float(py);
-  for (int j = threadIdx.x; j < nstage; j += NT) {
-    const uint32_t id = vals[rg.x + s0 + j];
-    s_id[j] = id;
-    s_r0[j] = rec.r0[id];
-    s_r1[j] = rec.r1[id];
-    s_rgb[j] = rec.rgb[id];
-  }
-  __syncthreads();
-  for (int j = min(cnt, wmax) - 1; j >= 0; --j) {
-    // straight-line for every lane: lanes that do not take part (past their list, or
-    // below the skip threshold) keep T and the running blends and add zeros
-    const float4 r0 = s_r0[j];
-    const float4 r1 = s_r1[j];
-    const float dx = fpx - r0.x, dy = fpy - r0.y;
-    float G;
-    const float a = splat_alpha(dx, dy, r0.z, r0.w, r1.x, r1.y, G);
-    const bool act = j < top && !(a < ru.amin);
-    if (__ballot(act) == 0ull) continue;
-    const float4 c = s_rgb[j];
-    const float al = a < ru.amax ? a : ru.amax;
-    const float om = 1.f - al;
-    const float iom = __builtin_amdgcn_rcpf(om);
-    T = act ? T * iom : T;
-    const float wgt = act ? al * T : 0.f;
-    const float g6 = gC0 * wgt, g7 = gC1 * wgt, g8 = gC2 * wgt, g9 = gD * wgt;
-    const float dal =
-        T * (gC0 * (c.x - BC0) + gC1 * (c.y - BC1) + gC2 * (c.z - BC2) + gD * (r1.z - BD)) + gA * Tfin * iom;
-    BC0 = act ? al * c.x + om * BC0 : BC0;
-    BC1 = act ? al * c.y + om * BC1 : BC1;
-    BC2 = act ? al * c.z + om * BC2 : BC2;
-    BD = act ? al * r1.z + om * BD : BD;
-    const float da = (act && a <= ru.amax) ? dal : 0.f;
-    const float g5 = da * G;
-    const float dpw = da * a;
-    const float g0 = dpw * (r0.z * dx + r0.w * dy);
-    const float g1 = dpw * (r0.w * dx + r1.x * dy);
-    const float g2 = -0.5f * dpw * dx * dx;
-    const float g3 = -dpw * dx * dy;
-    const float g4 = -0.5f * dpw * dy * dy;
-    const float gv[10] = {g0, g1, g2, g3, g4, g5, g6, g7, g8, g9};
-    float w0, w1, w2;
-    wave_sum10(gv, w0, w1, w2);
-    if ((lane & 15) == 0) {  // one lane per row adds its row's totals
-      const int row = lane >> 4;
-      const int k = row == 1 ? 2 : (row == 2 ? 1 : row);
-      if (kBlockSum) {
-        atomicAdd(&s_g[k][j], w0);
-        atomicAdd(&s_g[4 + k][j], w1);
-        if (!(row & 1)) atomicAdd(&s_g[8 + (row >> 1)][j], w2);
-      } else {
-        float* dst = grad2d + int64_t(s_id[j]) * kGrad2D;
-        unsafeAtomicAdd(dst + k, w0);
-        unsafeAtomicAdd(dst + 4 + k, w1);
-        if (!(row & 1)) unsafeAtomicAdd(dst + 8 + (row >> 1), w2);
+  for (int bend = bmax; bend > lo; bend -= BATCH) {
+    const int bstart = max(lo, bend - BATCH);
+    const int nstage = bend - bstart;
+    __syncthreads();
+    for (int j = threadIdx.x; j < nstage; j += NT) {
+      const uint32_t id = vals[rg.x + bstart + j];
+      s_id[j] = id;
+      s_r0[j] = rec.r0[id];
+      s_r1[j] = rec.r1[id];
+      s_rgb[j] = rec.rgb[id];
+    }
+    __syncthreads();
+    for (int j = min(nstage, wmax - bstart) - 1; j >= 0; --j) {
+      // straight-line for every lane: lanes that do not take part (past their list, or
+      // below the skip threshold) keep T and the running blends and add zeros
+      const float4 r0 = s_r0[j];
+      const float4 r1 = s_r1[j];
+      const float dx = fpx - r0.x, dy = fpy - r0.y;
+      float G;
+      const float a = splat_alpha(dx, dy, r0.z, r0.w, r1.x, r1.y, G);
+      const bool act = bstart + j < top && !(a < ru.amin);
+      if (__ballot(act) == 0ull) continue;
+      const float4 c = s_rgb[j];
+      const float al = a < ru.amax ? a : ru.amax;
+      const float om = 1.f - al;
+      const float iom = __builtin_amdgcn_rcpf(om);
+      T = act ? T * iom : T;
+      const float wgt = act ? al * T : 0.f;
+      const float g6 = gC0 * wgt, g7 = gC1 * wgt, g8 = gC2 * wgt, g9 = gD * wgt;
+      const float dal =
+          T * (gC0 * (c.x - BC0) + gC1 * (c.y - BC1) + gC2 * (c.z - BC2) + gD * (r1.z - BD)) + gA * Tfin * iom;
+      BC0 = act ? al * c.x + om * BC0 : BC0;
+      BC1 = act ? al * c.y + om * BC1 : BC1;
+      BC2 = act ? al * c.z + om * BC2 : BC2;
+      BD = act ? al * r1.z + om * BD : BD;
+      const float da = (act && a <= ru.amax) ? dal : 0.f;
+      const float g5 = da * G;
+      const float dpw = da * a;
+      const float g0 = dpw * (r0.z * dx + r0.w * dy);
+      const float g1 = dpw * (r0.w * dx + r1.x * dy);
+      const float g2 = -0.5f * dpw * dx * dx;
+      const float g3 = -dpw * dx * dy;
+      const float g4 = -0.5f * dpw * dy * dy;
+      const float gv[10] = {g0, g1, g2, g3, g4, g5, g6, g7, g8, g9};
+      float w0, w1, w2;
+      wave_sum10(gv, w0, w1, w2);
+      if ((lane & 15) == 0) {  // one lane per row adds its row's totals
+        const int row = lane >> 4;
+        const int k = row == 1 ? 2 : (row == 2 ? 1 : row);
+        if (kBlockSum) {
+          atomicAdd(&s_g[k][j], w0);
+          atomicAdd(&s_g[4 + k][j], w1);
+          if (!(row & 1)) atomicAdd(&s_g[8 + (row >> 1)][j], w2);
+        } else {
+          float* dst = grad2d + int64_t(s_id[j]) * kGrad2D;
+          unsafeAtomicAdd(dst + k, w0);
+          unsafeAtomicAdd(dst + 4 + k, w1);
+          if (!(row & 1)) unsafeAtomicAdd(dst + 8 + (row >> 1), w2);
+        }
       }
     }
-  }
-  if (kBlockSum) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < 10 * nstage; i += NT) {
-      const int k = i / nstage, j = i - k * nstage;
-      const float v = s_g[k][j];
-      if (v != 0.f) {
-        unsafeAtomicAdd(grad2d + int64_t(s_id[j]) * kGrad2D + k, v);
-        s_g[k][j] = 0.f;
+    if (kBlockSum) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < 10 * nstage; i += NT) {
+        const int k = i / nstage, j = i - k * nstage;
+        const float v = s_g[k][j];
+        if (v != 0.f) {
+          unsafeAtomicAdd(grad2d + int64_t(s_id[j]) * kGrad2D + k, v);
+          s_g[k][j] = 0.f;
+        }
       }
     }
   }
@@ -1740,16 +1727,16 @@ static void blend_fwd_t(const ViewTable& vt, const Rules& ru, const Records& rec
   k_blend_fwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck);
 }
 
-hipError_t launch_tile_order(const uint2* ranges, int total_tiles, int batch, uint32_t* order, const Ckpt& ck,
-                             hipStream_t s) {
+hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* order, hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
-  k_tile_order<<<1, 1024, 0, s>>>(ranges, total_tiles, batch, order, ck.slot_off);
+  k_tile_order<<<1, 1024, 0, s>>>(ranges, total_tiles, order);
   return hipGetLastError();
 }
 
-int64_t ckpt_slots(int64_t cap_M, int batch) { return cap_M / batch + 1; }
+// checkpoints at the first 1536 list entries of each tile
+int ckpt_per_tile(int batch) { return std::max(1, 1536 / batch); }
 
-int64_t bwd_items_cap(int64_t cap_M, int total_tiles, int batch) { return cap_M / batch + total_tiles + 1; }
+int64_t bwd_items_cap(int total_tiles, int batch) { return int64_t(total_tiles) * (ckpt_per_tile(batch) + 1); }
 
 hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
