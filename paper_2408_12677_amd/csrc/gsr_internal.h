@@ -95,7 +95,7 @@ struct Timer {
 
 constexpr int kProjThreads = 256;  // Gaussians per block in the per-Gaussian kernels
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortItems = 4;
 constexpr int kSortTile = kSortThreads * kSortItems;  // keys per radix-sort block
 constexpr int kGrad2D = 12;  // floats per (view, Gaussian) 2D-gradient record (10 used)
 constexpr int kBuckets = 33;   // log2 buckets of tile list lengths
