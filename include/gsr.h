@@ -253,7 +253,8 @@ gsr_status gsr_graph_free(gsr_graph* gr);
  * architecture, CU count, log2 of the total pixel count and of N, SH degree and V; a
  * cached entry is used without timing unless GSR_AUTOTUNE_NO_CACHE is set.  The forward
  * images do not depend on the choice (the extent keeps every splat value >= alpha_min
- * inside its tile rectangle).  best_ms (may be NULL) receives the step time. */
+ * inside its tile rectangle).  Each shape is timed as the median of seven eager steps after
+ * two warm-up steps.  best_ms (may be NULL) receives that median for the chosen shape. */
 #define GSR_AUTOTUNE_NO_CACHE 1u
 gsr_status gsr_autotune(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
                         gsr_settings* s, uint32_t flags, float* best_ms);

@@ -891,8 +891,9 @@ gsr_status gsr_autotune(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* 
       gsr_settings c = *s;
       c.tile = tiles[ti];
       c.batch = batches[bi];
-      float total = 0.f;
-      for (int rep = 0; rep < 4 && st == GSR_OK; ++rep) {  // one warm-up, three timed
+      constexpr int kWarm = 2, kTimed = 7;  // the median of seven timed steps
+      float times[kTimed];
+      for (int rep = 0; rep < kWarm + kTimed && st == GSR_OK; ++rep) {
         (void)hipEventRecord(e0, strm);
         gsr_saved* sv = nullptr;
         st = forward_eager(ctx, g, cams, V, &c, outs.data(), &sv);
@@ -903,10 +904,12 @@ gsr_status gsr_autotune(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* 
         (void)hipEventSynchronize(e1);
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        if (rep > 0) total += ms;
+        if (rep >= kWarm) times[rep - kWarm] = ms;
       }
-      if (st == GSR_OK && total / 3.f < best) {
-        best = total / 3.f;
+      if (st != GSR_OK) break;
+      std::sort(times, times + kTimed);
+      if (times[kTimed / 2] < best) {
+        best = times[kTimed / 2];
         bt = c.tile;
         bb = c.batch;
       }
