@@ -169,10 +169,10 @@ struct TileQueue {
 };
 
 // What the forward keeps so that the backward can run a tile's list in independent
-// pieces of one LDS batch each: at the first `kmax` batch boundaries the forward passes,
+// pieces of half an LDS batch each: at the first `kmax` such boundaries the forward passes,
 // per pixel, the transmittance in front of it and the colour and depth accumulated up
 // to it (a "checkpoint"); per pixel the accumulated totals; per tile its longest
-// contributor list.  The backward's work items are (tile, batch) pairs; batches past
+// contributor list.  The backward's work items are (tile, stride) pairs; entries past
 // the last checkpoint of a tile form one item that walks them all.
 struct Ckpt {
   float* state;         // [tiles][kmax][5][pixels of a tile]: T, colour (3), depth in front
@@ -226,7 +226,9 @@ hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2*
                           const unsigned long long* pairs, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
                           int64_t cap, uint32_t* overflow, hipStream_t s);
 hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* order, hipStream_t s);
-// Checkpoints per tile, and the backward work items of all tiles, at a batch size.
+// Checkpoint stride and checkpoints per tile, and the backward work items of all tiles,
+// at a batch size.
+int ckpt_stride(int batch);
 int ckpt_per_tile(int batch);
 int64_t bwd_items_cap(int total_tiles, int batch);
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,

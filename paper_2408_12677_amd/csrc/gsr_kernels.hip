@@ -1029,14 +1029,27 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
                                                      const uint32_t* vals, float* T_final, uint32_t* n_contrib,
                                                      uint32_t* n_used, TileQueue q, Ckpt ck) {
   constexpr int NT = TS * TS;
+  constexpr int CK = BATCH / 2;  // checkpoint stride
   __shared__ float4 s_r0[BATCH];
   __shared__ float4 s_r1[BATCH];
   __shared__ float4 s_rgb[BATCH];
   __shared__ int s_item;
   __shared__ uint32_t s_nmax;
+  int tile_of_block = 0;
+  // checkpoint k: the state in front of list entry k * CK
+  auto checkpoint = [&](int k, float T, float C0, float C1, float C2, float D) {
+    if (k > ck.kmax) return;
+    float* st = ck.state + (int64_t(tile_of_block) * ck.kmax + (k - 1)) * (5 * NT) + threadIdx.x;
+    st[0] = T;
+    st[NT] = C0;
+    st[2 * NT] = C1;
+    st[3 * NT] = C2;
+    st[4 * NT] = D;
+  };
   for (;;) {
     const int tile = next_tile(q, q.ctrl + kHeadFwd, vt.total_tiles, &s_item);
     if (tile < 0) return;
+    tile_of_block = tile;
     if (threadIdx.x == 0) s_nmax = 0;
     const ViewDev& cam = vt.v[view_of_tile(vt, tile)];
     const int lt = tile - cam.tile_off;
@@ -1051,17 +1064,7 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
     bool done = !inside;
     for (int b0 = 0; b0 < n; b0 += BATCH) {
       if (__syncthreads_count(!done) == 0) break;
-      if (b0 > 0) {  // checkpoint: the state in front of entry b0
-        const int k = b0 / BATCH;
-        if (k <= ck.kmax) {
-          float* st = ck.state + (int64_t(tile) * ck.kmax + (k - 1)) * (5 * NT) + threadIdx.x;
-          st[0] = T;
-          st[NT] = C0;
-          st[2 * NT] = C1;
-          st[3 * NT] = C2;
-          st[4 * NT] = D;
-        }
-      }
+      if (b0 > 0) checkpoint(b0 / CK, T, C0, C1, C2, D);
       for (int j = threadIdx.x; j < BATCH && b0 + j < n; j += NT) {
         const uint32_t id = vals[rg.x + b0 + j];
         s_r0[j] = rec.r0[id];
@@ -1077,6 +1080,7 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
       const int cnt = min(BATCH, n - b0);
       for (int j = 0; j < cnt; j += 4) {
         if (__ballot(!done) == 0ull) break;
+        if (j == CK) checkpoint((b0 + CK) / CK, T, C0, C1, C2, D);
         float a4[4], z4[4];
         float4 c4[4];
 #pragma unroll
@@ -1190,9 +1194,9 @@ __global__ __launch_bounds__(1024) void k_loss_sum(const float* part, int count,
 // in LDS and the block adds each splat's total to the 2D-gradient buffer once per item,
 // with the atomics spread over all lanes.
 // ------------------------------------------------------------------------------------
-// Backward work items, in the tile queue's longest-first order: (tile, batch) for every
-// batch that holds a contributor of some pixel of the tile, up to the tile's last
-// checkpoint; one more item (tile, kmax) covers all later batches.  One block.
+// Backward work items, in the tile queue's longest-first order: (tile, k) for every
+// checkpoint stride k that holds a contributor of some pixel of the tile, up to the
+// tile's last checkpoint; one more item (tile, kmax) covers all later entries.  One block.
 __global__ __launch_bounds__(1024) void k_bwd_items(const uint32_t* order, int total, int batch, Ckpt ck,
                                                    uint32_t* ctrl) {
   __shared__ uint32_t red[16], carry;
@@ -1264,8 +1268,9 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
   const int px = tx * TS + int(threadIdx.x % TS), py = ty * TS + int(threadIdx.x / TS);
   const bool inside = px < cam.W && py < cam.H;
   const uint2 rg = ranges[tile];
-  const int lo = bf * BATCH;  // the item's list entries: [lo, hi)
-  const int hi = bf < ck.kmax ? lo + BATCH : int(rg.y - rg.x);
+  constexpr int CK = BATCH / 2;  // checkpoint stride of the forward
+  const int lo = bf * CK;        // the item's list entries: [lo, hi)
+  const int hi = bf < ck.kmax ? lo + CK : int(rg.y - rg.x);
   const int lane = threadIdx.x & 63;
   const int64_t P = int64_t(cam.W) * cam.H;
   const int64_t pix = int64_t(py) * cam.W + px;
@@ -1289,7 +1294,7 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
       if (nc <= hi) {
         T = Tfin;
         top = nc;
-      } else {  // only single-batch items end before the list: checkpoint bf + 1 <= kmax
+      } else {  // only single-stride items end before the list: checkpoint bf + 1 <= kmax
         const float* st = ck.state + (int64_t(tile) * ck.kmax + bf) * (5 * NT) + threadIdx.x;
         const float4 acc = ck.acc[cam.pix_off + pix];
         T = st[0];
@@ -1733,8 +1738,9 @@ hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* ord
   return hipGetLastError();
 }
 
-// checkpoints at the first 1536 list entries of each tile
-int ckpt_per_tile(int batch) { return std::max(1, 1536 / batch); }
+// checkpoints every half batch over the first 1024 list entries of each tile
+int ckpt_stride(int batch) { return batch / 2; }
+int ckpt_per_tile(int batch) { return std::max(1, 1024 / ckpt_stride(batch)); }
 
 int64_t bwd_items_cap(int total_tiles, int batch) { return int64_t(total_tiles) * (ckpt_per_tile(batch) + 1); }
 
@@ -1780,7 +1786,7 @@ hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rule
                             const uint32_t* n_contrib, float* grad2d, const TileQueue& q, const Ckpt& ck,
                             hipStream_t s) {
   if (vt.total_tiles == 0) return hipSuccess;
-  k_bwd_items<<<1, 1024, 0, s>>>(q.order, vt.total_tiles, batch, ck, q.ctrl);
+  k_bwd_items<<<1, 1024, 0, s>>>(q.order, vt.total_tiles, ckpt_stride(batch), ck, q.ctrl);
   const bool b256 = batch == 256;
   switch (tile) {
     case 8: b256 ? blend_bwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck, s)
