@@ -345,7 +345,8 @@ hipError_t enqueue_sort_blend(gsr_saved* sv, hipStream_t s, bool timing) {
   return e;
 }
 
-// Backward launches for the view table `vt` (whose g_* pointers are set).
+// Backward launches for the view table `vt` (whose g_* pointers are set).  grad2d holds
+// V*N rows of kGrad2D floats followed by N * 3 floats of scratch for the colour term.
 hipError_t enqueue_backward(gsr_saved* sv, const ViewTable& vt, float* grad2d, const GradOut& go, hipStream_t s,
                             bool timing) {
   gsr_ctx* ctx = sv->ctx;
@@ -362,7 +363,9 @@ hipError_t enqueue_backward(gsr_saved* sv, const ViewTable& vt, float* grad2d, c
                               sv->n_contrib, grad2d, TileQueue{sv->order, sv->ctrl}, sv->ck, s);
     });
   if (e == hipSuccess)
-    e = T(K_PROJECT_BWD, [&] { return launch_project_bwd(sv->deg, sv->g, vt, sv->ru, sv->rec, grad2d, go, s); });
+    e = T(K_PROJECT_BWD, [&] {
+      return launch_project_bwd(sv->deg, sv->g, vt, sv->ru, sv->rec, grad2d, grad2d + VN * kGrad2D, go, s);
+    });
   return e;
 }
 
@@ -564,7 +567,7 @@ gsr_status gsr_backward(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_gra
   const ViewTable vt = with_grads(sv, grads);
   const int64_t VN = int64_t(sv->V) * sv->N;
   void* g2 = nullptr;
-  gsr_status st = dev_alloc(ctx, ctx->stream, &g2, size_t(VN) * kGrad2D * sizeof(float));
+  gsr_status st = dev_alloc(ctx, ctx->stream, &g2, (size_t(VN) * kGrad2D + size_t(sv->N) * 3) * sizeof(float));
   if (st != GSR_OK) return st;
   GradOut go{out->means, out->scales, out->quats, out->opacities, out->sh, int(flags & GSR_ACCUMULATE)};
   hipError_t e = enqueue_backward(sv, vt, static_cast<float*>(g2), go, ctx->stream, true);
@@ -708,7 +711,7 @@ gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_came
   sv->M = M;
   sv->n_vis = NV;
   if ((st = alloc_sort(sv, cap_vis, cap_M, true)) != GSR_OK ||
-      (st = alloc_in(sv, sv->blocks, &sv->grad2d, size_t(VN) * kGrad2D)) != GSR_OK) {
+      (st = alloc_in(sv, sv->blocks, &sv->grad2d, size_t(VN) * kGrad2D + size_t(sv->N) * 3)) != GSR_OK) {
     graph_destroy(gr);
     return st;
   }

@@ -250,8 +250,10 @@ hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rule
                             const uint2* ranges, const uint32_t* vals, const float* T_final,
                             const uint32_t* n_contrib, float* grad2d, const TileQueue& q, const Ckpt& ck,
                             hipStream_t s);
+// grad2d holds V*N rows of kGrad2D floats; dp_sh is scratch for N * 3 floats.
 hipError_t launch_project_bwd(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru,
-                              const Records& rec, const float* grad2d, const GradOut& out, hipStream_t s);
+                              const Records& rec, const float* grad2d, float* dp_sh, const GradOut& out,
+                              hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 
 }  // namespace gsr

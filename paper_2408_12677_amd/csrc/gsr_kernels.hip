@@ -1400,89 +1400,131 @@ __device__ __forceinline__ void store_grad(float* p, float v, int acc) {
     *p = v;
 }
 
+// K9a: the colour term.  Four lanes per Gaussian, one per colour channel (the fourth
+// idles), so a lane holds one channel's K coefficients.  Per visible view: the basis at
+// the view direction, the channel's colour before the clamp, the coefficient gradient
+// Y_k * dL/dc (zero where the clamp is active) and the view-direction gradient, summed
+// over the channel lanes and taken through the normalisation to the mean (dp_sh).
+// Coefficients pass through LDS so the [N, K, 3] loads and stores are contiguous; a
+// Gaussian invisible in every view reads none and gets zero gradients.
+constexpr int kShGaussians = 64;  // Gaussians per block of k_project_bwd_sh
+
 template <int DEG>
-__global__ __launch_bounds__(kProjThreads) void k_project_bwd(GaussDev g, ViewTable vt, Rules ru, Records rec,
-                                                              const float* grad2d, GradOut out) {
+__global__ __launch_bounds__(256) void k_project_bwd_sh(GaussDev g, ViewTable vt, Records rec, const float* grad2d,
+                                                        GradOut out, float* dp_sh) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  constexpr int KK = K * 3;        // SH floats per Gaussian
-  constexpr int STRIDE = KK | 1;   // odd LDS row stride: conflict-free per-thread rows
-  // the block's SH coefficients pass through LDS so that the global loads and stores of
-  // the [N, K, 3] array are contiguous across lanes
-  __shared__ float s_sh[kProjThreads * STRIDE];
-  const int64_t g0 = int64_t(blockIdx.x) * kProjThreads;
-  const int64_t gi = g0 + threadIdx.x;
-  const bool valid = gi < g.n;
-  const int nb = int(min<int64_t>(kProjThreads, g.n - g0));
-  for (int i = threadIdx.x; i < nb * KK; i += kProjThreads) {
-    const int r = i / KK;
-    s_sh[r * STRIDE + (i - r * KK)] = g.sh[g0 * KK + i];
+  constexpr int KK = K * 3;
+  constexpr int STRIDE = KK | 1;
+  __shared__ float s_sh[kShGaussians * STRIDE];
+  __shared__ uint32_t s_vis[kShGaussians];
+  const int t = threadIdx.x;
+  const int64_t g0 = int64_t(blockIdx.x) * kShGaussians;
+  const int nb = int(min<int64_t>(kShGaussians, g.n - g0));
+  if (t < kShGaussians) {
+    uint32_t vis = 0;
+    if (t < nb)
+      for (int v = 0; v < vt.nviews; ++v) vis |= rec.counts[int64_t(v) * g.n + g0 + t];
+    s_vis[t] = vis;
   }
   __syncthreads();
-  float p[3] = {0.f, 0.f, 0.f}, s[3] = {1.f, 1.f, 1.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, sh[KK];
-#pragma unroll
-  for (int i = 0; i < KK; ++i) sh[i] = s_sh[threadIdx.x * STRIDE + i];
-  if (valid) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      p[i] = g.means[gi * 3 + i];
-      s[i] = g.scales[gi * 3 + i];
-    }
-    const float4 q4 = reinterpret_cast<const float4*>(g.quats)[gi];
-    q[0] = q4.x;
-    q[1] = q4.y;
-    q[2] = q4.z;
-    q[3] = q4.w;
+  for (int i = t; i < nb * KK; i += 256) {
+    const int r = i / KK;
+    s_sh[r * STRIDE + (i - r * KK)] = s_vis[r] ? g.sh[g0 * KK + i] : 0.f;
   }
-  float dp[3] = {0.f, 0.f, 0.f}, ds[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f}, dop = 0.f;
-  float dsh[KK];
+  __syncthreads();
+  const int gl = t >> 2, ch = t & 3;
+  const int64_t gi = g0 + gl;
+  const bool mine = gl < nb && s_vis[gl] != 0u;
+  float dsh[K], dp[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-  for (int i = 0; i < KK; ++i) dsh[i] = 0.f;
+  for (int k = 0; k < K; ++k) dsh[k] = 0.f;
+  if (mine && ch < 3) {
+    float shc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) shc[k] = s_sh[gl * STRIDE + k * 3 + ch];
+    const float p0 = g.means[gi * 3], p1 = g.means[gi * 3 + 1], p2 = g.means[gi * 3 + 2];
+    for (int v = 0; v < vt.nviews; ++v) {
+      const int64_t rid = int64_t(v) * g.n + gi;
+      if (rec.counts[rid] == 0) continue;
+      const ViewDev& cam = vt.v[v];
+      const float d0 = p0 - cam.cam_pos[0], d1 = p1 - cam.cam_pos[1], d2 = p2 - cam.cam_pos[2];
+      const float il = 1.f / __builtin_sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+      const float vx = d0 * il, vy = d1 * il, vz = d2 * il;
+      float Y[K];
+      sh_basis<DEG>(vx, vy, vz, Y);
+      float raw = 0.5f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) raw += shc[k] * Y[k];
+      const float dc = raw > 0.f ? grad2d[rid * kGrad2D + 6 + ch] : 0.f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) dsh[k] += Y[k] * dc;
+      if (DEG > 0) {
+        float wk[K], dv[3];
+#pragma unroll
+        for (int k = 0; k < K; ++k) wk[k] = shc[k] * dc;
+        sh_grad_dot<DEG>(vx, vy, vz, wk, dv);
+        const float vd = dv[0] * vx + dv[1] * vy + dv[2] * vz;
+        dp[0] += (dv[0] - vx * vd) * il;
+        dp[1] += (dv[1] - vy * vd) * il;
+        dp[2] += (dv[2] - vz * vd) * il;
+      }
+    }
+  }
+  // the direction term is linear in the coefficients: sum the channel lanes (a quad)
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    dp[i] += dpp_move<0xB1, 0xF>(dp[i]);
+    dp[i] += dpp_move<0x4E, 0xF>(dp[i]);
+  }
+  if (mine && ch == 0)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dp_sh[gi * 3 + i] = dp[i];
+  if (!out.sh) return;
+  __syncthreads();
+  if (gl < nb && ch < 3)
+#pragma unroll
+    for (int k = 0; k < K; ++k) s_sh[gl * STRIDE + k * 3 + ch] = dsh[k];
+  __syncthreads();
+  for (int i = t; i < nb * KK; i += 256) {
+    const int r = i / KK;
+    store_grad(out.sh + g0 * KK + i, s_sh[r * STRIDE + (i - r * KK)], out.accumulate);
+  }
+}
+
+// K9b: the geometric chain rule, one thread per Gaussian; adds the colour term's
+// gradient with respect to the mean (dp_sh, from K9a).
+__global__ __launch_bounds__(kProjThreads) void k_project_bwd_geo(GaussDev g, ViewTable vt, Rules ru, Records rec,
+                                                                  const float* grad2d, const float* dp_sh,
+                                                                  GradOut out) {
+  const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
+  if (gi >= g.n) return;
+  float p[3], s[3], q[4];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    p[i] = g.means[gi * 3 + i];
+    s[i] = g.scales[gi * 3 + i];
+  }
+  const float4 q4 = reinterpret_cast<const float4*>(g.quats)[gi];
+  q[0] = q4.x;
+  q[1] = q4.y;
+  q[2] = q4.z;
+  q[3] = q4.w;
+  float dp[3] = {0.f, 0.f, 0.f}, ds[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f}, dop = 0.f;
+  bool any = false;
   for (int v = 0; v < vt.nviews; ++v) {
-    if (!valid) break;
     const int64_t rid = int64_t(v) * g.n + gi;
     if (rec.counts[rid] == 0) continue;
+    any = true;
     const ViewDev& cam = vt.v[v];
     const float4* G4 = reinterpret_cast<const float4*>(grad2d + rid * kGrad2D);
     const float4 ga = G4[0], gb = G4[1], gc = G4[2];
     const float dmux = ga.x, dmuy = ga.y, dA = ga.z, dB = ga.w, dC = gb.x, dO = gb.y;
-    const float dcol[3] = {gb.z, gb.w, gc.x};
     const float dz = gc.y;
     Proj pr;
     discrete_stage(p, s, q, cam, ru.k, ru.lowpass, ru.guard, pr);
     float A, B, C;
     conic_of(pr.a, pr.b, pr.c, A, B, C);
     dop += dO;
-    // colour: c = max(0, 0.5 + sum_k sh_k Y_k(d)), d = (p - centre)/|p - centre|
-    const float d0 = p[0] - cam.cam_pos[0], d1 = p[1] - cam.cam_pos[1], d2 = p[2] - cam.cam_pos[2];
-    const float len = __builtin_sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
-    const float il = 1.f / len;
-    const float vx = d0 * il, vy = d1 * il, vz = d2 * il;
-    float Y[K];
-    sh_basis<DEG>(vx, vy, vz, Y);
-    float dcm[3];
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      float raw = 0.5f;
-#pragma unroll
-      for (int kk = 0; kk < K; ++kk) raw += sh[kk * 3 + ch] * Y[kk];
-      dcm[ch] = raw > 0.f ? dcol[ch] : 0.f;
-    }
-    float wk[K];
-#pragma unroll
-    for (int kk = 0; kk < K; ++kk) {
-      dsh[kk * 3 + 0] += Y[kk] * dcm[0];
-      dsh[kk * 3 + 1] += Y[kk] * dcm[1];
-      dsh[kk * 3 + 2] += Y[kk] * dcm[2];
-      wk[kk] = sh[kk * 3 + 0] * dcm[0] + sh[kk * 3 + 1] * dcm[1] + sh[kk * 3 + 2] * dcm[2];
-    }
-    if (DEG > 0) {
-      float dv[3];
-      sh_grad_dot<DEG>(vx, vy, vz, wk, dv);
-      const float vd = dv[0] * vx + dv[1] * vy + dv[2] * vz;
-      dp[0] += (dv[0] - vx * vd) * il;
-      dp[1] += (dv[1] - vy * vd) * il;
-      dp[2] += (dv[2] - vz * vd) * il;
-    }
     // conic -> projected covariance: dS = -Q G_Q Q with G_Q = [[dA, dB/2], [dB/2, dC]]
     const float hB = 0.5f * dB;
     const float QG00 = A * dA + B * hB, QG01 = A * hB + B * dC;
@@ -1548,26 +1590,18 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd(GaussDev g, ViewTa
     dq[2] += (dqy - y * qd) * inq;
     dq[3] += (dqz - z * qd) * inq;
   }
-  const int acc = out.accumulate;
-  if (valid) {
-    if (out.means)
-      for (int i = 0; i < 3; ++i) store_grad(out.means + gi * 3 + i, dp[i], acc);
-    if (out.scales)
-      for (int i = 0; i < 3; ++i) store_grad(out.scales + gi * 3 + i, ds[i], acc);
-    if (out.quats)
-      for (int i = 0; i < 4; ++i) store_grad(out.quats + gi * 4 + i, dq[i], acc);
-    if (out.opac) store_grad(out.opac + gi, dop, acc);
-  }
-  if (out.sh) {  // back through LDS for contiguous stores
-    __syncthreads();
+  if (any) {
 #pragma unroll
-    for (int i = 0; i < KK; ++i) s_sh[threadIdx.x * STRIDE + i] = dsh[i];
-    __syncthreads();
-    for (int i = threadIdx.x; i < nb * KK; i += kProjThreads) {
-      const int r = i / KK;
-      store_grad(out.sh + g0 * KK + i, s_sh[r * STRIDE + (i - r * KK)], acc);
-    }
+    for (int i = 0; i < 3; ++i) dp[i] += dp_sh[gi * 3 + i];
   }
+  const int acc = out.accumulate;
+  if (out.means)
+    for (int i = 0; i < 3; ++i) store_grad(out.means + gi * 3 + i, dp[i], acc);
+  if (out.scales)
+    for (int i = 0; i < 3; ++i) store_grad(out.scales + gi * 3 + i, ds[i], acc);
+  if (out.quats)
+    for (int i = 0; i < 4; ++i) store_grad(out.quats + gi * 4 + i, dq[i], acc);
+  if (out.opac) store_grad(out.opac + gi, dop, acc);
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return unsigned((n + per - 1) / per); }
@@ -1800,15 +1834,17 @@ hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rule
 }
 
 hipError_t launch_project_bwd(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru,
-                              const Records& rec, const float* grad2d, const GradOut& out, hipStream_t s) {
+                              const Records& rec, const float* grad2d, float* dp_sh, const GradOut& out,
+                              hipStream_t s) {
   if (g.n == 0) return hipSuccess;
-  dim3 grid(blocks_for(g.n, kProjThreads)), block(kProjThreads);
+  const dim3 gsh(blocks_for(g.n, kShGaussians));
   switch (deg) {
-    case 0: k_project_bwd<0><<<grid, block, 0, s>>>(g, vt, ru, rec, grad2d, out); break;
-    case 1: k_project_bwd<1><<<grid, block, 0, s>>>(g, vt, ru, rec, grad2d, out); break;
-    case 2: k_project_bwd<2><<<grid, block, 0, s>>>(g, vt, ru, rec, grad2d, out); break;
-    default: k_project_bwd<3><<<grid, block, 0, s>>>(g, vt, ru, rec, grad2d, out); break;
+    case 0: k_project_bwd_sh<0><<<gsh, 256, 0, s>>>(g, vt, rec, grad2d, out, dp_sh); break;
+    case 1: k_project_bwd_sh<1><<<gsh, 256, 0, s>>>(g, vt, rec, grad2d, out, dp_sh); break;
+    case 2: k_project_bwd_sh<2><<<gsh, 256, 0, s>>>(g, vt, rec, grad2d, out, dp_sh); break;
+    default: k_project_bwd_sh<3><<<gsh, 256, 0, s>>>(g, vt, rec, grad2d, out, dp_sh); break;
   }
+  k_project_bwd_geo<<<blocks_for(g.n, kProjThreads), kProjThreads, 0, s>>>(g, vt, ru, rec, grad2d, dp_sh, out);
   return hipGetLastError();
 }
 
