@@ -274,13 +274,29 @@ __device__ __forceinline__ void conic_of(float a, float b, float c, float& A, fl
   C = a * inv;
 }
 
-// Splat value a = o * exp(-q/2), q = A dx^2 + 2 B dx dy + C dy^2, as one fixed instruction
-// sequence: the forward skip decision and its recomputation in the backward agree bitwise.
-__device__ __forceinline__ float splat_alpha(float dx, float dy, float A, float B, float C, float o, float& G) {
+// Splat value a = o * exp(-q/2), q = A dx^2 + 2 B dx dy + C dy^2.  The compositing kernels
+// stage each record with its conic scaled by -log2(e)/2, (a', b', c') = (A, 2B, C) * k,
+// so that exp(-q/2) = exp2(q') with q' = (a' dx + b' dy) dx + c' dy^2: five operations and
+// one exp2.  One fixed instruction sequence, so the forward skip decision and its
+// recomputation in the backward agree bitwise.
+constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
+
+__device__ __forceinline__ float splat_alpha(float dx, float dy, float ap, float bp, float cp, float o, float& G) {
 #pragma clang fp contract(off)
-  const float q = __builtin_fmaf(A * dx, dx, __builtin_fmaf(C * dy, dy, 2.f * (B * dx) * dy));
-  G = __expf(-0.5f * q);
+  const float q = __builtin_fmaf(__builtin_fmaf(ap, dx, bp * dy), dx, (cp * dy) * dy);
+  G = __builtin_amdgcn_exp2f(q);
   return o * G;
+}
+
+// LDS copy of record id for the compositing kernels: r0 = (mu_x, mu_y, a', b'),
+// r1 = (c', opacity, depth, 2 a'), rgb = (r, g, b, 2 c') with (a', b', c') as above.
+__device__ __forceinline__ void stage_record(const Records& rec, uint32_t id, float4& r0, float4& r1, float4& rgb) {
+  const float4 g0 = rec.r0[id], g1 = rec.r1[id];
+  const float ap = kNegHalfLog2e * g0.z, cp = kNegHalfLog2e * g1.x;
+  r0 = make_float4(g0.x, g0.y, ap, (2.f * kNegHalfLog2e) * g0.w);
+  r1 = make_float4(cp, g1.y, g1.z, ap + ap);
+  const float4 c = rec.rgb[id];
+  rgb = make_float4(c.x, c.y, c.z, cp + cp);
 }
 
 // ------------------------------------------------------------------------------------
@@ -997,25 +1013,12 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2* ranges, int to
   }
 }
 
-// Block-uniform: the next tile of the queue, or -1 when it is exhausted.  The longest
-// lists (the head of the queue) bound the kernel's duration, so their wavefronts take a
-// higher issue priority over the short tiles sharing their SIMDs: 3 for the first
-// sixteenth of the queue, 2 up to an eighth, 1 up to a quarter.
+// Block-uniform: the next tile of the queue, or -1 when it is exhausted.
 __device__ __forceinline__ int next_tile(const TileQueue& q, uint32_t* head, int total, int* s_item) {
   __syncthreads();
   if (threadIdx.x == 0) *s_item = int(atomicAdd(head, 1u));
   __syncthreads();
   const int item = *s_item;
-  if (item < total) {
-    if (item * 16 < total)
-      __builtin_amdgcn_s_setprio(3);
-    else if (item * 8 < total)
-      __builtin_amdgcn_s_setprio(2);
-    else if (item * 4 < total)
-      __builtin_amdgcn_s_setprio(1);
-    else
-      __builtin_amdgcn_s_setprio(0);
-  }
   return item < total ? int(q.order[item]) : -1;
 }
 
@@ -1062,15 +1065,20 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
     uint32_t last = 0, used = 0;
     bool done = !inside;
+    __builtin_amdgcn_s_setprio(0);
     for (int b0 = 0; b0 < n; b0 += BATCH) {
       if (__syncthreads_count(!done) == 0) break;
+      // a tile still running after several batches has long lists: it bounds the
+      // kernel's duration, so its wavefronts take issue priority over newer tiles
+      if (b0 == BATCH)
+        __builtin_amdgcn_s_setprio(1);
+      else if (b0 == 2 * BATCH)
+        __builtin_amdgcn_s_setprio(2);
+      else if (b0 == 3 * BATCH)
+        __builtin_amdgcn_s_setprio(3);
       if (b0 > 0) checkpoint(b0 / CK, T, C0, C1, C2, D);
-      for (int j = threadIdx.x; j < BATCH && b0 + j < n; j += NT) {
-        const uint32_t id = vals[rg.x + b0 + j];
-        s_r0[j] = rec.r0[id];
-        s_r1[j] = rec.r1[id];
-        s_rgb[j] = rec.rgb[id];
-      }
+      for (int j = threadIdx.x; j < BATCH && b0 + j < n; j += NT)
+        stage_record(rec, vals[rg.x + b0 + j], s_r0[j], s_r1[j], s_rgb[j]);
       __syncthreads();
       // four staged entries at a time: their splat values do not depend on the running
       // transmittance, so they are evaluated together (loads and exponentials overlap);
@@ -1097,13 +1105,13 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
         for (int u = 0; u < 4; ++u) {
           const float a = a4[u];
           const bool act = j + u < cnt && !done && !(a < ru.amin);
-          const float al = a < ru.amax ? a : ru.amax;
-          const float wgt = act ? al * T : 0.f;
+          const float al = act ? (a < ru.amax ? a : ru.amax) : 0.f;  // 0: adds nothing, keeps T
+          const float wgt = al * T;
           C0 += c4[u].x * wgt;
           C1 += c4[u].y * wgt;
           C2 += c4[u].z * wgt;
           D += z4[u] * wgt;
-          T = act ? T * (1.f - al) : T;
+          T = T * (1.f - al);
           last = act ? uint32_t(b0 + j + u + 1) : last;
           used += act ? 1u : 0u;
           done = done || T < ru.Tmin;
@@ -1321,9 +1329,7 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
     for (int j = threadIdx.x; j < nstage; j += NT) {
       const uint32_t id = vals[rg.x + bstart + j];
       s_id[j] = id;
-      s_r0[j] = rec.r0[id];
-      s_r1[j] = rec.r1[id];
-      s_rgb[j] = rec.rgb[id];
+      stage_record(rec, id, s_r0[j], s_r1[j], s_rgb[j]);
     }
     __syncthreads();
     for (int j = min(nstage, wmax - bstart) - 1; j >= 0; --j) {
@@ -1352,8 +1358,10 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
       const float da = (act && a <= ru.amax) ? dal : 0.f;
       const float g5 = da * G;
       const float dpw = da * a;
-      const float g0 = dpw * (r0.z * dx + r0.w * dy);
-      const float g1 = dpw * (r0.w * dx + r1.x * dy);
+      // (A dx + B dy, B dx + C dy) = -ln 2 (2a' dx + b' dy, b' dx + 2c' dy)
+      const float dpl = -0.69314718055994531f * dpw;
+      const float g0 = dpl * (r1.w * dx + r0.w * dy);
+      const float g1 = dpl * (r0.w * dx + c.w * dy);
       const float g2 = -0.5f * dpw * dx * dx;
       const float g3 = -dpw * dx * dy;
       const float g4 = -0.5f * dpw * dy * dy;
