@@ -301,7 +301,9 @@ hipError_t enqueue_project(gsr_saved* sv, hipStream_t s, bool timing) {
   hipError_t e = T(K_FILL, [&] { return launch_fill_u32(sv->ctrl, 0u, kCtrlWords, s); });
   if (e != hipSuccess || sv->N == 0) return e;
   e = T(K_PROJECT, [&] {
-    return launch_project(sv->deg, sv->g, sv->vt, sv->ru, sv->s.tile, sv->rec, sv->blocksums, sv->nblk, s);
+    // a captured step zeroes its 2D-gradient rows here, for the records that are visible
+    return launch_project(sv->deg, sv->g, sv->vt, sv->ru, sv->s.tile, sv->rec, sv->blocksums, sv->nblk, sv->grad2d,
+                          s);
   });
   if (e == hipSuccess)
     e = T(K_SCAN, [&] { return launch_scan_pairs(sv->blocksums, sv->V * sv->nblk, sv->d_total, s); });
@@ -352,11 +354,9 @@ hipError_t enqueue_backward(gsr_saved* sv, const ViewTable& vt, float* grad2d, c
   gsr_ctx* ctx = sv->ctx;
   auto T = [&](int k, auto f) { return timing ? timed(ctx, s, k, f) : f(); };
   const int64_t VN = int64_t(sv->V) * sv->N;
-  hipError_t e = T(K_FILL, [&] {
-    hipError_t r = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, VN * kGrad2D, s);
-    if (r == hipSuccess) r = launch_fill_u32(sv->ctrl + kHeadBwd, 0u, 1, s);
-    return r;
-  });
+  hipError_t e = hipSuccess;
+  if (grad2d != sv->grad2d)  // the captured step's rows were zeroed by the projection
+    e = T(K_FILL, [&] { return launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, VN * kGrad2D, s); });
   if (e == hipSuccess)
     e = T(K_BLEND_BWD, [&] {
       return launch_blend_bwd(sv->s.tile, sv->s.batch, vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final,
@@ -554,7 +554,8 @@ gsr_status gsr_loss_l1(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_out*
   ViewTable vt;
   gsr_status st = loss_table(ctx, saved, outs, targets, depth_weight, grad_color_out, grad_depth_out, &vt);
   if (st != GSR_OK) return st;
-  GSR_HIP(ctx, timed(ctx, ctx->stream, K_LOSS, [&] { return launch_loss_l1(vt, depth_weight, saved->loss_part, loss_dev, ctx->stream); }));
+  GSR_HIP(ctx, timed(ctx, ctx->stream, K_LOSS,
+                     [&] { return launch_loss_l1(vt, depth_weight, saved->loss_part, loss_dev, ctx->stream); }));
   return GSR_OK;
 }
 

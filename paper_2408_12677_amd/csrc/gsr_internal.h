@@ -219,8 +219,9 @@ struct GradOut {
 // ---- launchers (gsr_kernels.hip) --------------------------------------------------
 // Device-side counts (unsigned long long) are clamped by each kernel to the capacity its
 // grid and buffers were sized for.
+// zero_rows (may be null): 2D-gradient rows (kGrad2D floats) zeroed for every visible record
 hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru, int tile,
-                          const Records& rec, uint2* blocksums, int nblk, hipStream_t s);
+                          const Records& rec, uint2* blocksums, int nblk, float* zero_rows, hipStream_t s);
 hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* totals, hipStream_t s);
 hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
                           const unsigned long long* pairs, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
@@ -245,7 +246,7 @@ hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rule
                             uint32_t* n_used, const TileQueue& q, const Ckpt& ck, hipStream_t s);
 int loss_partials(const ViewTable& vt);  // block partial sums launch_loss_l1 writes
 hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* part, float* loss, hipStream_t s);
-// Lists the backward's (tile, batch) work items, then runs them.
+// Lists the backward's (tile, stride) work items, then runs them.
 hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, const float* T_final,
                             const uint32_t* n_contrib, float* grad2d, const TileQueue& q, const Ckpt& ck,

@@ -394,7 +394,8 @@ __device__ __forceinline__ void sh_grad_dot(float x, float y, float z, const flo
 // ------------------------------------------------------------------------------------
 template <int DEG>
 __global__ __launch_bounds__(kProjThreads) void k_project(GaussDev g, ViewTable vt, Rules ru, int tile,
-                                                          Records rec, uint2* blocksums, int nblk) {
+                                                          Records rec, uint2* blocksums, int nblk,
+                                                          float* zero_rows) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ uint32_t red[kProjThreads / 64];
   const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
@@ -448,6 +449,12 @@ __global__ __launch_bounds__(kProjThreads) void k_project(GaussDev g, ViewTable 
         rec.r1[rid] = make_float4(C, op, pr.tz, 0.f);
         rec.rgb[rid] = make_float4(col[0], col[1], col[2], 0.f);
         rec.rect[rid] = make_uint2(uint32_t(tx0) | (uint32_t(tx1) << 16), uint32_t(ty0) | (uint32_t(ty1) << 16));
+        if (zero_rows) {  // the backward's 2D-gradient row of this record starts at zero
+          float4* z = reinterpret_cast<float4*>(zero_rows + rid * kGrad2D);
+          z[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+          z[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+          z[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
       }
       rec.counts[rid] = cnt;
     }
@@ -1232,7 +1239,13 @@ __global__ __launch_bounds__(1024) void k_bwd_items(const uint32_t* order, int t
 // take a higher wave priority, as in next_tile.
 __device__ __forceinline__ int next_item(uint32_t* head, int total, int* s_item) {
   __syncthreads();
-  if (threadIdx.x == 0) *s_item = int(atomicAdd(head, 1u));
+  if (threadIdx.x == 0) {
+    // every block takes exactly one value past the end, so the taker of the last one
+    // is the last to touch the head: it resets it for the next backward
+    const uint32_t v = atomicAdd(head, 1u);
+    *s_item = int(v);
+    if (v == uint32_t(total) + gridDim.x - 1u) *head = 0u;
+  }
   __syncthreads();
   const int item = *s_item;
   if (item < total) {
@@ -1620,14 +1633,14 @@ inline unsigned blocks_for(int64_t n, int per) { return unsigned((n + per - 1) /
 // launchers
 // ------------------------------------------------------------------------------------
 hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru, int tile,
-                          const Records& rec, uint2* blocksums, int nblk, hipStream_t s) {
+                          const Records& rec, uint2* blocksums, int nblk, float* zero_rows, hipStream_t s) {
   if (nblk == 0) return hipSuccess;
   dim3 grid(nblk), block(kProjThreads);
   switch (deg) {
-    case 0: k_project<0><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk); break;
-    case 1: k_project<1><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk); break;
-    case 2: k_project<2><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk); break;
-    default: k_project<3><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk); break;
+    case 0: k_project<0><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows); break;
+    case 1: k_project<1><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows); break;
+    case 2: k_project<2><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows); break;
+    default: k_project<3><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows); break;
   }
   return hipGetLastError();
 }
