@@ -31,8 +31,9 @@
  *  - Keys: (global tile id << 32) | bits(float32 depth), sorted ascending and stably;
  *    a global tile id is the view's tile offset plus ty*tiles_x+tx.
  *  - Streams: all device work is enqueued on the context's HIP stream.  Only
- *    gsr_forward (one 8-byte read-back of the duplicated-key count) and
- *    gsr_debug_export synchronise with the host.  A context is not thread-safe.
+ *    gsr_forward (one 16-byte read-back of the pair and visible-record counts),
+ *    gsr_seed (an 8-byte read-back of the Gaussian count) and gsr_debug_export
+ *    synchronise with the host.  A context is not thread-safe.
  *  - Errors: every call returns a gsr_status; arguments are validated before any
  *    device work; a failing call leaves outputs unspecified but the context usable.
  *    gsr_last_error() gives a message.  NaN/Inf inputs are not rejected.
@@ -258,6 +259,54 @@ gsr_status gsr_graph_free(gsr_graph* gr);
 #define GSR_AUTOTUNE_NO_CACHE 1u
 gsr_status gsr_autotune(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
                         gsr_settings* s, uint32_t flags, float* best_ms);
+
+/* ---- Quadtree seeding and Gaussian initialisation (Sec. III-B-2, Eq. 10) --------------
+ * One RGB-D frame is cut into a quadtree: root cells of 64x64 pixels aligned at (0,0)
+ * and clipped at the border split into their four quadrants while the cell's measure
+ * passes `threshold` and its side exceeds `min_side`.  Measures:
+ *   GSR_SEED_CONTRAST        range (max - min) of the mean of the three colour channels;
+ *                            a cell splits when it is >= threshold (the paper's rule:
+ *                            every leaf has contrast below the threshold, 0.1 in Sec. IV)
+ *   GSR_SEED_DEPTH_VARIANCE  population variance (m^2) of the valid depths (> 0); a cell
+ *                            splits when it is > threshold; cells without a valid depth
+ *                            are dropped
+ * Every leaf (x0, y0, w, h) whose centre pixel (x0 + w/2, y0 + h/2) has a valid depth d
+ * gives one Gaussian (the paragraph after Eq. 10): mean = T_WC pi^-1(centre, d) with the
+ * camera's world->camera (R, t); scales = (s, s, s) with s the distance from the
+ * back-projected centre to the back-projected top-left pixel (x0, y0) at depth d;
+ * rotation (1, 0, 0, 0); opacity `opacity`; SH DC coefficients (c - 0.5) / Y_00 from the
+ * centre pixel's colour c (Y_00 = 1/(2 sqrt(pi))), all other coefficients 0.  Gaussians
+ * are written root by root in raster order and depth-first (top-left, top-right,
+ * bottom-left, bottom-right) inside a root.  The voxel-weight neighbourhood check of the
+ * paper needs the TSDF map and is left to the caller.  Statistics are binary64; the
+ * threshold is the binary32 value given. */
+#define GSR_SEED_CONTRAST 0
+#define GSR_SEED_DEPTH_VARIANCE 1
+typedef struct gsr_seed_settings {
+  int32_t measure;    /* GSR_SEED_CONTRAST (default) or GSR_SEED_DEPTH_VARIANCE */
+  float threshold;    /* 0.1 */
+  int32_t min_side;   /* smallest cell side: 1, 2, 4 (default), 8, 16, 32 or 64 */
+  float opacity;      /* 0.5 */
+  int32_t sh_degree;  /* 0..3: coefficients written per Gaussian (K = (deg+1)^2) */
+} gsr_seed_settings;
+
+typedef struct gsr_seed_out {  /* device buffers of `capacity` Gaussians */
+  float* means;      /* [capacity,3] */
+  float* scales;     /* [capacity,3] */
+  float* quats;      /* [capacity,4] */
+  float* opacities;  /* [capacity] */
+  float* sh;         /* [capacity,K,3] */
+  int32_t* leaves;   /* [capacity,4] (x0, y0, w, h) of each Gaussian's cell, or NULL */
+} gsr_seed_out;
+
+gsr_status gsr_seed_settings_default(gsr_seed_settings* s);
+/* rgb [3,H,W] in [0,1] and depth [H,W] in metres (<= 0: no depth) are device images of
+ * cam's size.  Writes the Gaussians into `out` and their number into *count (host).
+ * When more than `capacity` would be written, writes nothing, sets *count to the number
+ * needed and returns GSR_ECAPACITY.  capacity ceil(W/min_side)*ceil(H/min_side) always
+ * suffices.  Synchronises once to read the count. */
+gsr_status gsr_seed(gsr_ctx* ctx, const gsr_camera* cam, const float* rgb, const float* depth,
+                    const gsr_seed_settings* s, const gsr_seed_out* out, int64_t capacity, int64_t* count);
 
 /* Message of the last failing call on ctx ("" if none); ctx may be NULL for
  * failures that had no context. */

@@ -70,6 +70,17 @@ class Debug(ctypes.Structure):
                 ("n_used", P)]
 
 
+class SeedSettings(ctypes.Structure):
+    _fields_ = [("measure", ctypes.c_int32), ("threshold", ctypes.c_float), ("min_side", ctypes.c_int32),
+                ("opacity", ctypes.c_float), ("sh_degree", ctypes.c_int32)]
+
+
+class SeedOut(ctypes.Structure):
+    _fields_ = [("means", P), ("scales", P), ("quats", P), ("opacities", P), ("sh", P), ("leaves", P)]
+
+
+SEED_CONTRAST, SEED_DEPTH_VARIANCE = 0, 1
+
 # every symbol include/gsr.h declares, with its ctypes signature
 SIGNATURES = {
     "gsr_abi_version": (ctypes.c_int32, []),
@@ -94,6 +105,8 @@ SIGNATURES = {
     "gsr_graph_info": (ctypes.c_int, [P, P, P, P]),
     "gsr_graph_free": (ctypes.c_int, [P]),
     "gsr_autotune": (ctypes.c_int, [P, P, P, ctypes.c_int32, P, ctypes.c_uint32, P]),
+    "gsr_seed_settings_default": (ctypes.c_int, [P]),
+    "gsr_seed": (ctypes.c_int, [P, P, P, P, P, P, ctypes.c_int64, P]),
 }
 AUTOTUNE_NO_CACHE = 1
 

@@ -933,4 +933,63 @@ gsr_status gsr_autotune(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* 
   return GSR_OK;
 }
 
+gsr_status gsr_seed_settings_default(gsr_seed_settings* s) {
+  if (!s) return fail(nullptr, GSR_EINVAL, "settings is NULL");
+  s->measure = GSR_SEED_CONTRAST;
+  s->threshold = 0.1f;
+  s->min_side = 4;
+  s->opacity = 0.5f;
+  s->sh_degree = 0;
+  return GSR_OK;
+}
+
+gsr_status gsr_seed(gsr_ctx* ctx, const gsr_camera* cam, const float* rgb, const float* depth,
+                    const gsr_seed_settings* s, const gsr_seed_out* out, int64_t capacity, int64_t* count) {
+  if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
+  if (!cam || !rgb || !depth || !s || !out || !count) return fail(ctx, GSR_EINVAL, "NULL argument to gsr_seed");
+  gsr_status st = check_camera(ctx, *cam, 0);
+  if (st != GSR_OK) return st;
+  if (s->measure != GSR_SEED_CONTRAST && s->measure != GSR_SEED_DEPTH_VARIANCE)
+    return fail(ctx, GSR_EINVAL, "unknown seeding measure");
+  const int ms = s->min_side;
+  if (ms != 1 && ms != 2 && ms != 4 && ms != 8 && ms != 16 && ms != 32 && ms != 64)
+    return fail(ctx, GSR_EINVAL, "min_side must be a power of two in 1..64");
+  if (!(s->threshold >= 0.f) || !(s->opacity >= 0.f && s->opacity <= 1.f))
+    return fail(ctx, GSR_EINVAL, "threshold or opacity out of range");
+  if (s->sh_degree < 0 || s->sh_degree > 3) return fail(ctx, GSR_EINVAL, "sh_degree must be 0..3");
+  if (capacity < 0) return fail(ctx, GSR_EINVAL, "capacity < 0");
+  if (capacity > 0 && (!out->means || !out->scales || !out->quats || !out->opacities || !out->sh))
+    return fail(ctx, GSR_EINVAL, "an output pointer is NULL");
+  *count = 0;
+  SeedImage im{rgb, depth, cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy, {}, {}};
+  std::memcpy(im.R, cam->R, sizeof im.R);
+  std::memcpy(im.t, cam->t, sizeof im.t);
+  const SeedRules rules{s->measure, s->threshold, s->min_side, s->opacity, s->sh_degree};
+  const SeedOut so{out->means, out->scales, out->quats, out->opacities, out->sh, out->leaves, capacity};
+  const int roots = seed_roots(cam->width, cam->height);
+  hipStream_t strm = ctx->stream;
+  // per-root counts, then the 8-byte total at the next 8-byte boundary
+  const size_t total_at = (size_t(roots) * 4 + 7) & ~size_t(7);
+  void* buf = nullptr;
+  if ((st = dev_alloc(ctx, strm, &buf, total_at + 8)) != GSR_OK) return st;
+  uint32_t* counts = static_cast<uint32_t*>(buf);
+  auto* total = reinterpret_cast<unsigned long long*>(static_cast<char*>(buf) + total_at);
+  hipError_t e = launch_seed_count(im, rules, counts, strm);
+  if (e == hipSuccess) e = launch_scan_small(counts, roots, total, strm);
+  if (e == hipSuccess) e = hipMemcpyAsync(ctx->h_total, total, sizeof(unsigned long long), hipMemcpyDeviceToHost, strm);
+  if (e == hipSuccess) e = hipStreamSynchronize(strm);
+  const int64_t n = int64_t(ctx->h_total[0]);
+  bool over = false;
+  if (e == hipSuccess) {
+    over = n > capacity;
+    if (!over && n > 0) e = launch_seed_emit(im, rules, counts, so, strm);
+  }
+  (void)hipFreeAsync(buf, strm);
+  if (e != hipSuccess) return fail(ctx, GSR_EDEVICE, std::string("seeding failed: ") + hipGetErrorString(e));
+  *count = n;
+  if (over) return fail(ctx, GSR_ECAPACITY, "seeding needs " + std::to_string(n) + " Gaussians, capacity is " +
+                                                std::to_string(capacity));
+  return GSR_OK;
+}
+
 }  // extern "C"

@@ -216,7 +216,44 @@ struct GradOut {
   int accumulate;
 };
 
+// Quadtree seeding (gsr_seed.hip): one RGB-D frame and its camera.
+struct SeedImage {
+  const float* rgb;    // [3,H,W]
+  const float* depth;  // [H,W]
+  int32_t W, H;
+  double fx, fy, cx, cy;
+  float R[9], t[3];    // world -> camera
+};
+
+struct SeedRules {
+  int32_t measure;  // GSR_SEED_CONTRAST or GSR_SEED_DEPTH_VARIANCE
+  float threshold;
+  int32_t min_side;
+  float opacity;
+  int32_t sh_degree;
+};
+
+struct SeedOut {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opac;
+  float* sh;
+  int32_t* leaves;
+  int64_t capacity;
+};
+
+int seed_roots(int W, int H);  // 64-pixel root cells of a W x H image
+// per-root Gaussian counts into root_counts[seed_roots]
+hipError_t launch_seed_count(const SeedImage& im, const SeedRules& r, uint32_t* root_counts, hipStream_t s);
+// writes the Gaussians at the exclusive-scanned root offsets
+hipError_t launch_seed_emit(const SeedImage& im, const SeedRules& r, const uint32_t* root_offsets,
+                            const SeedOut& out, hipStream_t s);
+
 // ---- launchers (gsr_kernels.hip) --------------------------------------------------
+// In-place exclusive scan of a[0, count) by one block (count up to a few 10^4); the total
+// goes to *total.
+hipError_t launch_scan_small(uint32_t* a, int count, unsigned long long* total, hipStream_t s);
 // Device-side counts (unsigned long long) are clamped by each kernel to the capacity its
 // grid and buffers were sized for.
 // zero_rows (may be null): 2D-gradient rows (kGrad2D floats) zeroed for every visible record

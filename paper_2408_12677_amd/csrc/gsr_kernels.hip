@@ -1645,6 +1645,11 @@ hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const
   return hipGetLastError();
 }
 
+hipError_t launch_scan_small(uint32_t* a, int count, unsigned long long* total, hipStream_t s) {
+  k_scan_u32<<<1, 1024, 0, s>>>(a, count, total);
+  return hipGetLastError();
+}
+
 hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* totals, hipStream_t s) {
   k_scan_pairs<<<1, 1024, 0, s>>>(blocksums, count, totals);
   return hipGetLastError();

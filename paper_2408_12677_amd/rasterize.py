@@ -403,3 +403,30 @@ def autotune(means, scales, quats, opacities, sh, cameras, settings: Settings | 
     N.check(ctx.lib.gsr_autotune(ctx.h, ctypes.byref(g), _cams(cameras), len(cameras), ctypes.byref(s),
                                  0 if use_cache else N.AUTOTUNE_NO_CACHE, ctypes.byref(ms)), ctx.h)
     return dataclasses.replace(settings, tile=int(s.tile), batch=int(s.batch)), float(ms.value)
+
+
+def seed(rgb, depth, camera, measure: str = "contrast", threshold: float = 0.1, min_side: int = 4,
+         opacity: float = 0.5, sh_degree: int = 0):
+    """Quadtree seeding and Gaussian initialisation of one RGB-D frame (gsr_seed).
+
+    rgb [3,H,W] and depth [H,W] are float32 device tensors of the camera's size.  Returns
+    a dict of means [n,3], scales [n,3], quats [n,4], opacities [n], sh [n,K,3] and the
+    cells' leaves [n,4] (x0, y0, w, h)."""
+    H, W = int(camera.height), int(camera.width)
+    dev = rgb.device
+    _need(rgb, "rgb", (3, H, W), dev)
+    _need(depth, "depth", (H, W), dev)
+    m = {"contrast": N.SEED_CONTRAST, "depth_variance": N.SEED_DEPTH_VARIANCE}[measure]
+    s = N.SeedSettings(m, float(threshold), int(min_side), float(opacity), int(sh_degree))
+    cap = (-(-W // int(min_side))) * (-(-H // int(min_side)))
+    K = (int(sh_degree) + 1) ** 2
+    f = dict(device=dev, dtype=torch.float32)
+    out = dict(means=torch.empty((cap, 3), **f), scales=torch.empty((cap, 3), **f), quats=torch.empty((cap, 4), **f),
+               opacities=torch.empty(cap, **f), sh=torch.empty((cap, K, 3), **f),
+               leaves=torch.empty((cap, 4), dtype=torch.int32, device=dev))
+    so = N.SeedOut(*(out[k].data_ptr() for k in ("means", "scales", "quats", "opacities", "sh", "leaves")))
+    ctx = context(dev)
+    n = ctypes.c_int64()
+    N.check(ctx.lib.gsr_seed(ctx.h, ctypes.byref(_cams([camera])[0]), _ptr(rgb), _ptr(depth), ctypes.byref(s),
+                             ctypes.byref(so), cap, ctypes.byref(n)), ctx.h)
+    return {k: v[:n.value] for k, v in out.items()}

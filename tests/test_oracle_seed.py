@@ -79,8 +79,7 @@ def test_depth_variance_matches_integral_image_seeder():
     # the workload seeder computes the same quadtree from integral images
     room = scenes.Room(np.random.default_rng(7), (6.0, 5.0, 3.0), 20)
     cam = room.random_camera(np.random.default_rng(8), 320, 240)
-    depth, color = room.raycast(cam)
-    rgb = np.ascontiguousarray(np.moveaxis(color, -1, 0)) if color.shape[-1] == 3 else color
+    depth, rgb = room.raycast(cam)   # depth [H,W], colour [3,H,W]
     leaves, cells = S.quadtree(rgb, depth, "depth_variance", 0.01, root=64, min_side=4)
     ref = scenes.quadtree_leaves(depth, root=64, min_side=4, var_thresh=0.01)
     near = [c for c in cells if abs(c[4] - 0.01) < 1e-9]
