@@ -9,7 +9,8 @@ every Gaussian parameter.  A "step" is that whole path; ``value`` is Mpixel/s of
 
 Also reported: the same 8 views as one batched call against 8 sequential per-view
 steps; per-kernel device time from HIP events on the library's stream; the roofline
-of the dominant kernel; the FP64 CPU oracle timed on this host.
+of the dominant kernel; quadtree seeding of one frame (640x480 and 1752x1168); the
+FP64 CPU oracle timed on this host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -229,6 +230,37 @@ def step_stats(R, params, cams, targets, settings):
     return st
 
 
+def seeding_leg(R, torch, dev, log):
+    """Quadtree seeding + initialisation (gsr_seed) of ray-cast room frames at the headline
+    and the paper's full resolution: Mpixel/s per frame (host-timed, the call synchronises
+    once) and the algorithmic HBM rate of its two passes over the frame."""
+    import scenes
+    res = {}
+    for W, H in ((640, 480), (1752, 1168)):
+        room = scenes.Room(np.random.default_rng(21), (6.0, 5.0, 3.0), 20)
+        cam = room.random_camera(np.random.default_rng(22), W, H)
+        depth, rgb = room.raycast(cam, perturbed=True)
+        rgb_d = torch.from_numpy(np.ascontiguousarray(rgb, np.float32)).to(dev)
+        depth_d = torch.from_numpy(depth.astype(np.float32)).to(dev)
+        for _ in range(3):
+            g = R.seed(rgb_d, depth_d, cam, "contrast", 0.1, 4, 0.5, 3)
+        torch.cuda.synchronize()
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g = R.seed(rgb_d, depth_d, cam, "contrast", 0.1, 4, 0.5, 3)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        n = int(g["means"].shape[0])
+        alg = W * H * 16 * 2 + n * (3 + 3 + 4 + 1 + 48 + 4) * 4   # two reads of rgb + depth; the Gaussians
+        res[f"{W}x{H}"] = {"ms": round(sec * 1e3, 4), "Mpixel_s": round(W * H / sec / 1e6, 1), "gaussians": n,
+                           "alg_GBps": round(alg / sec / 1e9, 1),
+                           "frac_of_hbm_peak": round(alg / sec / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"seeding {W}x{H}: {res[f'{W}x{H}']}")
+    res["workload"] = "ray-cast room frames, contrast threshold 0.1, min side 4, SH degree 3 outputs"
+    return res
+
+
 def timed_steps(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -250,6 +282,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-seed", action="store_true", help="skip the quadtree seeding measurement")
     ap.add_argument("--autotune", type=int, default=1, help="pick (tile, batch) by timing first (1) or not (0)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of this many MiB (counter calibration under rocprofv3)")
@@ -390,6 +423,9 @@ def main():
                           "per_view_eager_ms": round(ms_s, 3),
                           "per_view_eager_Mpixel_s": round(px_all / (ms_s * 1e-3) / 1e6, 2),
                           "steps": k2}
+
+    if not args.no_seed:
+        out["seeding"] = seeding_leg(R, torch, dev, log)
 
     if not args.no_cpu_baseline:
         import oracle
