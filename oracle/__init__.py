@@ -76,7 +76,7 @@ def _load():
         lib.or_get_keys.argtypes = [P, P, P, P]
         lib.or_get_records.argtypes = [P] * 8
         lib.or_forward.argtypes = [P] * 8
-        lib.or_backward.argtypes = [P] * 10
+        lib.or_backward.argtypes = [P] * 11
         lib.or_sh_eval.argtypes = [ctypes.c_int32, P, ctypes.c_int64, P, P]
         _lib = lib
     return _lib
@@ -200,8 +200,12 @@ class Oracle:
                              ambiguous=m.astype(bool)))
         return outs
 
-    def backward(self, g_color=None, g_depth=None, g_alpha=None):
-        """Gradients of sum over views of <g, outputs>; inputs are per-view lists (None = 0)."""
+    def backward(self, g_color=None, g_depth=None, g_alpha=None, ambiguous_pixels=None):
+        """Gradients of sum over views of <g, outputs>; inputs are per-view lists (None = 0).
+
+        ambiguous_pixels: optional per-view boolean [H,W] masks of pixels whose output
+        gradient is not unique (an L1 sign at a tie); Gaussians contributing there are
+        flagged like those near a skip, stop or clamp edge."""
         def cat(lst, ch):
             if lst is None:
                 return None
@@ -211,7 +215,11 @@ class Oracle:
         d = dict(means=np.zeros((n, 3)), scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
                  opacities=np.zeros(n), sh=np.zeros((n, K, 3)))
         flagged = np.zeros(n, np.uint8)
-        self.lib.or_backward(self.h, _ptr(gc), _ptr(gd), _ptr(ga), _ptr(d["means"]), _ptr(d["scales"]),
+        pa = None
+        if ambiguous_pixels is not None:
+            pa = np.ascontiguousarray(np.concatenate([np.asarray(m, bool).reshape(-1) for m in ambiguous_pixels]),
+                                      np.uint8)
+        self.lib.or_backward(self.h, _ptr(gc), _ptr(gd), _ptr(ga), _ptr(pa), _ptr(d["means"]), _ptr(d["scales"]),
                              _ptr(d["quats"]), _ptr(d["opacities"]), _ptr(d["sh"]), _ptr(flagged))
         d["flagged"] = flagged.astype(bool)
         return d

@@ -673,9 +673,12 @@ void or_forward(void* h, double* color, double* depth, double* alpha, double* T_
 // or_forward (NULL = zero).  Writes dL/d(parameters) in the parameter layouts, and per
 // Gaussian a flag that is set when a contributing event sat within the ambiguity
 // margin of a discrete rule (skip, stop or clamp edge), so its gradient is not unique.
+// pix_amb (NULL = none; one byte per pixel, views concatenated) marks pixels whose
+// output gradient is itself not unique (the L1 loss of Eq. 12 changes sign where the
+// rendered value meets the target); every Gaussian contributing there is flagged too.
 void or_backward(void* h, const double* g_color, const double* g_depth, const double* g_alpha,
-                 double* d_means, double* d_scales, double* d_quats, double* d_opac, double* d_sh,
-                 uint8_t* flagged) {
+                 const uint8_t* pix_amb, double* d_means, double* d_scales, double* d_quats, double* d_opac,
+                 double* d_sh, uint8_t* flagged) {
   const Ctx& c = *static_cast<Ctx*>(h);
   const int V = int(c.cams.size());
   const int64_t N = c.n;
@@ -707,6 +710,7 @@ void or_backward(void* h, const double* g_color, const double* g_depth, const do
           int32_t n, nu;
           bool amb;
           composite(c, tile, x, y, out, n, nu, amb, &hits);
+          if (pix_amb && pix_amb[base + pix]) amb = true;
           const double Tfin = out[4];
           double BC[3] = {c.set.bg[0], c.set.bg[1], c.set.bg[2]}, BD = 0.0;
           for (size_t i = hits.size(); i-- > 0;) {

@@ -8,6 +8,8 @@ Tolerances (FP32 kernels against the FP64 oracle):
     its threshold or a stop event (T vs 1e-4) within a relative 1e-4 (about ten times
     the binary32 error of each); at most 0.5% of pixels may be ambiguous and
     there the colour/alpha difference stays within 1/255 + 1e-4;
+  * loss and its output gradients: the oracle's L1 loss of the oracle's own images; the
+    sign must agree wherever the oracle's value is more than LOSS_MARGIN from the target;
   * gradients: per parameter group ||g - g_ref||_2 <= 1e-3 ||g_ref||_2, and per element
     |g - g_ref| <= 1e-3 max(|g_ref|, 1e-2 max|g_ref|) for every Gaussian whose
     contributions avoided ambiguous pixels and the opacity-clamp edge.
@@ -22,6 +24,11 @@ from paper_2408_12677_amd import rasterize as R
 
 IMG_TOL = 1e-4
 GRAD_REL = 1e-3
+# the L1 loss gradient (Eq. 12) is sign(rendered - target): where the oracle's rendered
+# value lies within this margin of the target the sign is not unique (about five times
+# the largest image difference measured between the two sides); depth uses it relative
+# to max(1, |target|)
+LOSS_MARGIN = 2e-5
 AMB_FRACTION = 5e-3
 NAMES = ("means", "scales", "quats", "opacities", "sh")
 
@@ -133,3 +140,39 @@ def check_grads(gpu, ref, rel=GRAD_REL, names=NAMES):
         report[name] = norm_rel
     report["flagged"] = int(flagged.sum())
     return report
+
+
+def oracle_loss(outs, targets, depth_weight=0.1):
+    """The oracle's L1 loss of its own images (nothing from the GPU).
+
+    Returns (loss, [dL/dC], [dL/dD], [pixel masks]) where a mask marks the pixels whose
+    loss gradient is not unique: a colour or valid depth within LOSS_MARGIN of its
+    target, or a pixel whose forward decisions were already ambiguous."""
+    L, gcs, gds, amb = 0.0, [], [], []
+    for o, (tc, td) in zip(outs, targets):
+        tc = np.asarray(tc, np.float64)
+        td = np.asarray(td, np.float64)
+        l, gC, gD = oracle.l1_loss(o["color"], o["depth"], tc, td, depth_weight)
+        L += l
+        gcs.append(gC)
+        gds.append(gD)
+        near = (np.abs(o["color"] - tc) <= LOSS_MARGIN).any(0)
+        near |= (td > 0) & (np.abs(o["depth"] - td) <= LOSS_MARGIN * np.maximum(1.0, np.abs(td)))
+        amb.append(near | o["ambiguous"])
+    return L, gcs, gds, amb
+
+
+def check_loss_grads(gc, gd, ref_gc, ref_gd, amb):
+    """GPU loss gradients (per-view torch lists) against oracle_loss's: equal where unique,
+    and no larger than the oracle's magnitude where not."""
+    for v, (a, b, c, d, m) in enumerate(zip(gc, gd, ref_gc, ref_gd, amb)):
+        a = a.detach().cpu().numpy().astype(np.float64)
+        c = np.asarray(c)
+        ok = np.broadcast_to(~m, a.shape)
+        np.testing.assert_allclose(a[ok], c[ok], rtol=1e-6, atol=0, err_msg=f"view {v} colour")
+        assert (np.abs(a[~ok]) <= np.abs(c).max() * (1 + 1e-6)).all()
+        if b is not None:
+            b = b.detach().cpu().numpy().astype(np.float64)
+            d = np.asarray(d)
+            np.testing.assert_allclose(b[~m], d[~m], rtol=1e-6, atol=0, err_msg=f"view {v} depth")
+            assert (np.abs(b[m]) <= np.abs(d).max() * (1 + 1e-6)).all()

@@ -19,7 +19,8 @@ import scenes
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-from parity_util import check_grads, check_images, check_keys, oracle_for, settings, to_dev  # noqa: E402
+from parity_util import (check_grads, check_images, check_keys, check_loss_grads, oracle_for,  # noqa: E402
+                         oracle_loss, settings, to_dev)
 
 NAMES = ("means", "scales", "quats", "opacities", "sh")
 
@@ -95,10 +96,12 @@ def test_batched_step_matches_oracle(R):
     images, loss, grads, saved = eager_step(R, params, cams, dev_targets(targets), s)
     orc = oracle_for(g, cams, s)
     check_keys(saved.debug_export(), orc)
-    check_images(images, orc.forward())
+    outs = orc.forward()
+    check_images(images, outs)
     _, gc, gd = R.loss_l1(saved, images, dev_targets(targets), 0.1)
-    ref = orc.backward([x.cpu().numpy().astype(np.float64) for x in gc],
-                       [x.cpu().numpy().astype(np.float64) for x in gd], None)
+    L, ref_gc, ref_gd, amb = oracle_loss(outs, targets, 0.1)
+    check_loss_grads(gc, gd, ref_gc, ref_gd, amb)
+    ref = orc.backward(ref_gc, ref_gd, None, ambiguous_pixels=amb)
     check_grads(grads, ref)
 
 
