@@ -32,7 +32,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = ("paper_2408_12677_amd/csrc/gsr_kernels.hip", "paper_2408_12677_amd/csrc/gsr_internal.h")
+KERNEL_SOURCES = ("paper_2408_12677_amd/csrc/gsr_kernels.hip", "paper_2408_12677_amd/csrc/gsr_internal.h",
+                  "paper_2408_12677_amd/csrc/gsr_optim.hip", "paper_2408_12677_amd/csrc/gsr_adam.h",
+                  "paper_2408_12677_amd/csrc/gsr_tsdf.hip", "paper_2408_12677_amd/csrc/gsr_tsdf.h")
 HEADLINE_VIEW = 2              # first 640x480 view of the 8-view orbit
 DEPTH_W = 0.1
 
@@ -261,6 +263,107 @@ def seeding_leg(R, torch, dev, log):
     return res
 
 
+def optimiser_leg(R, torch, params, cam, target, s, steps, warmup, log):
+    """Adam over the whole map (every parameter row, 28 HBM bytes per element: value,
+    gradient and both moments read, value and moments written): the standalone step with
+    its roofline, and one captured iteration with the step fused into the backward
+    projection against the same iteration followed by the standalone step."""
+    work = [p.clone() for p in params]
+    opt = R.Adam(*work)
+    gen = torch.Generator(device=work[0].device).manual_seed(5)
+    grads = {k: torch.randn(p.shape, device=p.device, generator=gen) * 1e-3 for k, p in zip(R.GROUPS, work)}
+    ctx = R.context(work[0].device)
+    for _ in range(warmup):
+        opt.step(work, grads)
+    ctx.set_timing(True)
+    ctx.timing(reset=True)
+    sec = timed_steps(lambda: opt.step(work, grads), steps, 0)
+    ms_k, n_k = ctx.timing(reset=True)["adam"]
+    ctx.set_timing(False)
+    avg_us = 1e3 * ms_k / max(n_k, 1)
+    elems = sum(p.numel() for p in work)
+    alg = elems * 28
+    ach = alg / (avg_us * 1e-6) / 1e9
+    roof = dict(bound="hbm", kernel="adam", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(ach / HBM_PEAK_GBS, 4), traffic=stored_traffic("adam"), alg_bytes_per_launch=int(alg),
+                avg_launch_us=round(avg_us, 2))
+    log(f"adam step over {elems} elements: {avg_us:.1f} us per launch, {ach:.0f} GB/s")
+    px = cam.width * cam.height
+    g_plain = R.Graph(*work, [cam], [target], s, depth_weight=DEPTH_W)
+
+    def unfused():
+        g_plain.launch()
+        opt.step(work, g_plain.grads)
+    ms_unfused = timed_steps(unfused, steps, warmup) * 1e3
+    g_plain.sync()
+    g_plain.free()
+    g_fused = R.Graph(*work, [cam], [target], s, depth_weight=DEPTH_W, optimizer=opt)
+    ms_fused = timed_steps(g_fused.launch, steps, warmup) * 1e3
+    g_fused.sync()
+    g_fused.free()
+    log(f"iteration with Adam: fused {ms_fused:.3f} ms, graph + standalone step {ms_unfused:.3f} ms")
+    return {"workload": "Adam (3D Gaussian splatting rates) over the headline map: every parameter row",
+            "elements": elems, "standalone_step_ms": round(sec * 1e3, 4), "roofline": roof,
+            "iteration_fused_ms": round(ms_fused, 4), "iteration_fused_Mpixel_s": round(px / ms_fused / 1e3, 3),
+            "iteration_unfused_ms": round(ms_unfused, 4),
+            "iteration_unfused_Mpixel_s": round(px / ms_unfused / 1e3, 3)}
+
+
+def tsdf_leg(R, torch, dev, log):
+    """TSDF fusion (Eq. 6-9) of ray-cast depth frames of the room at 1 cm voxels, at the
+    headline and the paper's full resolution: ms and Mpixel/s per fused frame once the
+    map holds the scene (host-timed), and the roofline of the per-voxel update kernel
+    (16 bytes per voxel of a met block: distance and weight read and written, plus one
+    depth read per pixel)."""
+    import scenes
+    res = {}
+    for W, H in ((640, 480), (1752, 1168)):
+        room = scenes.Room(np.random.default_rng(31), (6.0, 5.0, 3.0), 20)
+        frames = []
+        for k in range(8):
+            cam = room.random_camera(np.random.default_rng(3100 + k), W, H)
+            depth, _ = room.raycast(cam, with_color=False)
+            frames.append((cam, torch.from_numpy(depth.astype(np.float32)).to(dev)))
+        m = R.TsdfMap(dev, max_blocks=1 << 18)
+        met = []
+        for cam, d in frames:                     # first pass: allocation of the scene
+            m.integrate(d, cam)
+            met.append(m.info()["met_last"])
+        reps = 5
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for cam, d in frames:
+                m.integrate(d, cam)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / (reps * len(frames))
+        ctx = R.context(dev)
+        ctx.set_timing(True)
+        ctx.timing(reset=True)
+        for _ in range(reps):
+            for cam, d in frames:
+                m.integrate(d, cam)
+        kt = ctx.timing(reset=True)
+        ctx.set_timing(False)
+        inf = m.info()
+        m.free()
+        fuse_us = 1e3 * kt["tsdf_fuse"][0] / max(kt["tsdf_fuse"][1], 1)
+        alloc_us = 1e3 * kt["tsdf_alloc"][0] / max(kt["tsdf_alloc"][1], 1)
+        alg = float(np.mean(met)) * 512 * 16 + W * H * 4
+        ach = alg / (fuse_us * 1e-6) / 1e9
+        key = f"{W}x{H}"
+        res[key] = {"ms_per_frame": round(sec * 1e3, 4), "Mpixel_s": round(W * H / sec / 1e6, 1),
+                    "blocks": inf["blocks"], "met_blocks_per_frame": int(np.mean(met)),
+                    "alloc_us": round(alloc_us, 2), "fuse_us": round(fuse_us, 2),
+                    "fuse_roofline": dict(bound="hbm", kernel="tsdf_fuse", achieved=round(ach, 1),
+                                          peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
+                                          traffic=stored_traffic("tsdf_integrate"),
+                                          alg_bytes_per_launch=int(alg), avg_launch_us=round(fuse_us, 2))}
+        log(f"tsdf {key}: {res[key]}")
+    res["workload"] = "8 ray-cast depth frames of the room, 1 cm voxels, band 8 cm, 17 samples per pixel, each fused 5 more times"
+    return res
+
+
 def timed_steps(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -283,6 +386,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-seed", action="store_true", help="skip the quadtree seeding measurement")
+    ap.add_argument("--no-optim", action="store_true", help="skip the optimiser-step measurement")
+    ap.add_argument("--no-tsdf", action="store_true", help="skip the TSDF fusion measurement")
     ap.add_argument("--autotune", type=int, default=1, help="pick (tile, batch) by timing first (1) or not (0)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of this many MiB (counter calibration under rocprofv3)")
@@ -365,7 +470,6 @@ def main():
     ms = timed_steps(g1.launch, args.steps, args.warmup) * 1e3
     g1.sync()
     g1.free()
-
     per_kernel = {k: dict(ms_per_step=t / args.steps, launches_per_step=n / args.steps, avg_launch_us=1e3 * t / n)
                   for k, (t, n) in ktimes.items() if n > 0}
     dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_per_step"])
@@ -424,8 +528,15 @@ def main():
                           "per_view_eager_Mpixel_s": round(px_all / (ms_s * 1e-3) / 1e6, 2),
                           "steps": k2}
 
+    if not args.no_optim:
+        out["optimiser"] = optimiser_leg(R, torch, params, cam, targets[HEADLINE_VIEW], s, args.steps,
+                                         args.warmup, log)
+
     if not args.no_seed:
         out["seeding"] = seeding_leg(R, torch, dev, log)
+
+    if not args.no_tsdf:
+        out["tsdf"] = tsdf_leg(R, torch, dev, log)
 
     if not args.no_cpu_baseline:
         import oracle

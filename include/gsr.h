@@ -143,7 +143,7 @@ typedef struct {
 
 /* Per-kernel device time accumulated by the optional event timer (see
  * gsr_ctx_set_timing); entry i belongs to the kernel gsr_kernel_name(i). */
-#define GSR_MAX_KERNELS 16
+#define GSR_MAX_KERNELS 32
 typedef struct {
   double ms[GSR_MAX_KERNELS];         /* summed launch durations, milliseconds */
   int64_t launches[GSR_MAX_KERNELS];  /* launches timed */
@@ -224,6 +224,48 @@ gsr_status gsr_saved_free(gsr_saved* saved);
 /* Copy intermediate state to host memory (synchronises the stream). */
 gsr_status gsr_debug_export(gsr_ctx* ctx, const gsr_saved* saved, const gsr_debug* out);
 
+/* ---- Optimiser step (Sec. III-B-3) -----------------------------------------------------
+ * The parameters are optimised directly by gradient descent on the loss; the optimiser
+ * is Adam (Kingma and Ba, Algorithm 1).  Per element with gradient g at step t:
+ *   m <- b1 m + (1-b1) g,  v <- b2 v + (1-b2) g^2,
+ *   x <- x - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * The optimised variables are the means, log(scales), the quaternions (unnormalised),
+ * logit(opacities) and the SH coefficients; the stored parameters stay activated, so a
+ * step maps a scale s to u = log s with gradient s dL/ds, updates u and stores exp(u),
+ * and an opacity o to w = log(o/(1-o)) with gradient o(1-o) dL/do, storing
+ * 1/(1+exp(-w)) clamped to [2^-24, 1-2^-24].  SH coefficients k = 0 (DC) use lr_sh_dc,
+ * the others lr_sh_rest.  Every element is updated at every step (an element without
+ * gradient still moves by its momentum).  The moments are caller-owned device arrays in
+ * the parameter layouts, and `state` four device words (zero before the first step) in
+ * which the library keeps the step count and the step's bias corrections; the count
+ * advances on the device, so a captured graph steps correctly on every replay. */
+typedef struct gsr_adam {
+  float lr_means;     /* 1.6e-4 */
+  float lr_scales;    /* 5e-3 (on log scale) */
+  float lr_quats;     /* 1e-3 */
+  float lr_opacities; /* 0.05 (on the logit) */
+  float lr_sh_dc;     /* 2.5e-3 */
+  float lr_sh_rest;   /* 1.25e-4 */
+  float beta1;        /* 0.9 */
+  float beta2;        /* 0.999 */
+  float eps;          /* 1e-15 */
+  gsr_gaussian_grads m;  /* first moments (all five arrays required) */
+  gsr_gaussian_grads v;  /* second moments */
+  uint32_t* state;       /* [4] device: steps taken, then binary32 bias corrections */
+} gsr_adam;
+
+/* Default rates and betas (the 3D Gaussian splatting values above); pointers NULL. */
+gsr_status gsr_adam_default(gsr_adam* a);
+/* One Adam step of n Gaussians (SH degree 0..3): params are updated in place from grads
+ * (both in the parameter layouts; gsr_gaussian_grads here simply names five device arrays). */
+gsr_status gsr_adam_step(gsr_ctx* ctx, int64_t n, int32_t sh_degree, const gsr_gaussian_grads* params,
+                         const gsr_gaussian_grads* grads, const gsr_adam* opt);
+/* gsr_backward fused with one Adam step: each Gaussian's parameter gradient is formed as
+ * in gsr_backward and applied at once to the Gaussian arrays given to gsr_forward (which
+ * must be writable) instead of being written out. */
+gsr_status gsr_backward_adam(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_grad* grads,
+                             const gsr_adam* opt);
+
 /* ---- Batched keyframes: one captured step -------------------------------------------
  * Capture forward + L1 loss + backward of V views (uneven resolutions allowed) into a
  * hipGraph: one concatenated tile space, one sort, persistent compositing kernels that
@@ -234,11 +276,15 @@ gsr_status gsr_debug_export(gsr_ctx* ctx, const gsr_saved* saved, const gsr_debu
  * forward of the given inputs times (1 + headroom).  A launch whose key or visible-record
  * count exceeds those capacities sets a device flag; it is read back asynchronously and
  * reported as GSR_ECAPACITY by the next gsr_graph_launch that finds the earlier step
- * complete, or by gsr_graph_sync.  Gradients are overwritten on every launch. */
+ * complete, or by gsr_graph_sync.  Gradients are overwritten on every launch.  With opt
+ * (may be NULL) the step ends with one Adam step fused into the backward, as in
+ * gsr_backward_adam: every launch is then one complete optimisation iteration that updates
+ * the Gaussian arrays of g in place, and grads may be NULL. */
 gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
                             const gsr_settings* s, const gsr_view_out* outs, const gsr_target* targets,
                             float depth_weight, float* const* grad_color, float* const* grad_depth,
-                            const gsr_gaussian_grads* grads, float* loss_dev, float headroom, gsr_graph** out);
+                            const gsr_gaussian_grads* grads, float* loss_dev, float headroom,
+                            const gsr_adam* opt, gsr_graph** out);
 /* Enqueue one step on the context's stream (asynchronous). */
 gsr_status gsr_graph_launch(gsr_graph* gr);
 /* Wait for the last launch; GSR_ECAPACITY if any launch overflowed. */
@@ -299,14 +345,102 @@ typedef struct gsr_seed_out {  /* device buffers of `capacity` Gaussians */
   int32_t* leaves;   /* [capacity,4] (x0, y0, w, h) of each Gaussian's cell, or NULL */
 } gsr_seed_out;
 
+typedef struct gsr_tsdf gsr_tsdf; /* a TSDF voxel-block map (below) */
+
 gsr_status gsr_seed_settings_default(gsr_seed_settings* s);
 /* rgb [3,H,W] in [0,1] and depth [H,W] in metres (<= 0: no depth) are device images of
- * cam's size.  Writes the Gaussians into `out` and their number into *count (host).
- * When more than `capacity` would be written, writes nothing, sets *count to the number
- * needed and returns GSR_ECAPACITY.  capacity ceil(W/min_side)*ceil(H/min_side) always
- * suffices.  Synchronises once to read the count. */
+ * cam's size.  With map != NULL (the frame fused into it first, gsr_tsdf_integrate) a
+ * leaf also needs the voxel that holds its mean to have weight exactly 1, i.e. to be seen
+ * for the first time by that frame (the paper's check against duplicating primitives);
+ * map == NULL skips the check.  Writes the Gaussians into `out` and their number into
+ * *count (host).  When more than `capacity` would be written, writes nothing, sets
+ * *count to the number needed and returns GSR_ECAPACITY.  capacity
+ * ceil(W/min_side)*ceil(H/min_side) always suffices.  Synchronises once to read the count. */
 gsr_status gsr_seed(gsr_ctx* ctx, const gsr_camera* cam, const float* rgb, const float* depth,
-                    const gsr_seed_settings* s, const gsr_seed_out* out, int64_t capacity, int64_t* count);
+                    const gsr_seed_settings* s, const gsr_tsdf* map, const gsr_seed_out* out, int64_t capacity,
+                    int64_t* count);
+
+/* ---- TSDF fusion (Sec. III-B-1, Eq. 6-9) -----------------------------------------------
+ * A map of voxel blocks (8x8x8 voxels of side `voxel`) found through a device hash table
+ * of block coordinates.  Fusing a depth frame: every pixel with depth d > 0 marches its
+ * viewing ray through the band [d - trunc, d + trunc] at camera depths
+ * (d - trunc) + i * step, i = 0 .. floor(2 trunc / step), and allocates the blocks its
+ * samples fall in; then every voxel of those blocks is projected (nearest pixel,
+ * floor(u + 0.5)) and, where that pixel has depth D > 0,
+ *   sdf = D - z_v (Eq. 6),  tsdf = clamp(sdf / trunc, -1, 1) (Eq. 7),
+ *   w_k = min(w_max, w_(k-1) + 1) (Eq. 8),
+ *   tsdf_k = (tsdf_(k-1) w_(k-1) + tsdf w_k) / (w_(k-1) + w_k)   (GSR_TSDF_EQ9, as printed)
+ *         or (tsdf_(k-1) w_(k-1) + tsdf) / (w_(k-1) + 1)          (GSR_TSDF_UNIT_WEIGHT, the
+ *            running average the text describes).
+ * Voxels start at tsdf 0, weight 0.  Block selection and voxel projection are fixed
+ * sequences of correctly rounded binary32 operations (so they are reproducible bit for
+ * bit); the values are binary32.  Defaults: voxel 0.01 m (Sec. IV-A), trunc 0.08 m,
+ * w_max 100, step 0.01 m, GSR_TSDF_EQ9. */
+#define GSR_TSDF_EQ9 0
+#define GSR_TSDF_UNIT_WEIGHT 1
+typedef struct gsr_tsdf_settings {
+  float voxel;        /* voxel side, metres */
+  float trunc;        /* truncation band eps, metres */
+  float w_max;        /* weight cap, >= 1 */
+  float step;         /* ray-march step in camera depth, metres */
+  int32_t weighting;  /* GSR_TSDF_EQ9 or GSR_TSDF_UNIT_WEIGHT */
+} gsr_tsdf_settings;
+
+gsr_status gsr_tsdf_settings_default(gsr_tsdf_settings* s);
+/* A map with room for max_blocks blocks (1 .. 2^28; 4 KiB of device memory per block plus
+ * a hash table of at least twice as many 16-byte slots), all voxels at zero. */
+gsr_status gsr_tsdf_create(gsr_ctx* ctx, const gsr_tsdf_settings* s, int64_t max_blocks, gsr_tsdf** out);
+gsr_status gsr_tsdf_free(gsr_tsdf* map);
+/* Fuse the depth image [H,W] (device, cam's size) seen from cam.  Asynchronous.  Blocks
+ * beyond the map's capacity (or a full table) are not allocated and set a flag bit that
+ * gsr_tsdf_info reports (1 table full, 2 pool full, 4 coordinates out of range). */
+gsr_status gsr_tsdf_integrate(gsr_ctx* ctx, gsr_tsdf* map, const gsr_camera* cam, const float* depth);
+/* Allocated blocks, blocks met by the last fused frame and the flag bits (synchronises). */
+gsr_status gsr_tsdf_info(gsr_ctx* ctx, const gsr_tsdf* map, int64_t* blocks, int64_t* met_last, uint32_t* flags);
+/* Host copies of the allocated blocks (synchronises): coords [n,3] block coordinates
+ * (a block holds voxels 8*coords + (0..7)), tsdf and weight [n,512] with x fastest, then
+ * y, then z.  *count = n always; GSR_ECAPACITY when capacity < n (nothing copied); NULL
+ * arrays are skipped. */
+gsr_status gsr_tsdf_export(gsr_ctx* ctx, const gsr_tsdf* map, int32_t* coords, float* tsdf, float* weight,
+                           int64_t capacity, int64_t* count);
+/* out[i] (device) = weight of the voxel that holds points[i] (device [n,3]; the voxel index
+ * is floor(p / voxel) in binary32); 0 where no block is allocated. */
+gsr_status gsr_tsdf_weights(gsr_ctx* ctx, const gsr_tsdf* map, const float* points, int64_t n, float* out);
+
+/* ---- Keyframe-list optimisation schedule (Sec. III-B-3; settings of Sec. IV-A) --------
+ * Host-only bookkeeping of which view each optimisation iteration of a time step renders.
+ * The number of Gaussians the seeding of a frame added measures its information gain:
+ *   - count > threshold: the frame is a keyframe, joins the keyframe list and gets m
+ *     iterations;
+ *   - otherwise it gets n iterations, followed by one iteration on each of the first
+ *     min(m - n, list length) keyframes of the list after a shuffle.
+ * With store_all every frame joins the list (after its own draw) while m or n still
+ * follows the threshold (the paper's ScanNet++ setting: m 10, n 1, every frame kept; its
+ * Replica setting: m 5, n 3, threshold 50).  A negative threshold makes every frame a
+ * keyframe.  The shuffle gives list entry i (0-based, insertion order) the key
+ * h(h(seed, frame + 1), i + 1), h(s, k) being the k-th output of SplitMix64 seeded with s
+ * (s + k * 0x9E3779B97F4A7C15 through its 64-bit mixing function), and orders the list
+ * by (key, i).  Offline optimisation after scanning iterates over gsr_schedule_keyframes. */
+typedef struct gsr_schedule gsr_schedule;
+typedef struct gsr_schedule_settings {
+  int32_t m;          /* iterations of a keyframe, >= n */
+  int32_t n;          /* iterations of another frame, >= 0 */
+  int64_t threshold;  /* keyframe when the frame's new Gaussians exceed it (50) */
+  int32_t store_all;  /* nonzero: every frame joins the keyframe list */
+  uint64_t seed;      /* seed of the keyframe draw */
+} gsr_schedule_settings;
+
+/* EINVAL unless 0 <= n <= m <= 10^6. */
+gsr_status gsr_schedule_create(const gsr_schedule_settings* s, gsr_schedule** out);
+gsr_status gsr_schedule_free(gsr_schedule* sch);
+/* The iterations of time step `frame` (>= 0) whose seeding added new_gaussians (>= 0):
+ * writes the frame rendered by each iteration, in order, into iters[0, *count) (host,
+ * cap >= m) and whether the frame is a keyframe into *is_keyframe (may be NULL). */
+gsr_status gsr_schedule_step(gsr_schedule* sch, int64_t frame, int64_t new_gaussians, int64_t* iters, int32_t cap,
+                             int32_t* count, int32_t* is_keyframe);
+/* The keyframe list in insertion order: *count always, out[0, count) when out != NULL
+ * (EINVAL when cap is smaller). */
+gsr_status gsr_schedule_keyframes(const gsr_schedule* sch, int64_t* out, int64_t cap, int64_t* count);
 
 /* Message of the last failing call on ctx ("" if none); ctx may be NULL for
  * failures that had no context. */

@@ -32,8 +32,10 @@ Readings where the paper is silent (each is an argument):
 * colour = 0.5 + sh_0 * Y_00 (the rasterizer's SH convention), so sh_0 = (c - 0.5) / Y_00
   with Y_00 = 1 / (2 sqrt(pi)); the other coefficients are zero.
 
-The voxel-weight neighbourhood check needs the TSDF map, which is not part of this
-build; the oracle returns every leaf's Gaussian.
+The check against duplicating primitives (the paragraph after Eq. 10): given a TSDF map
+that has fused the frame (oracle/tsdf.py), a Gaussian is kept only where the voxel holding
+its mean (rounded to binary32) has weight exactly 1, i.e. was observed for the first time;
+without a map every leaf with a valid centre depth gives one.
 """
 from __future__ import annotations
 
@@ -90,9 +92,10 @@ def quadtree(rgb, depth, measure="contrast", threshold=0.1, root=64, min_side=4)
     return np.array(leaves, np.int64).reshape(-1, 4), cells
 
 
-def initial_gaussians(leaves, rgb, depth, cam, opacity=0.5, sh_degree=0):
-    """Gaussians of the leaves whose centre depth is valid: dict of means [n,3],
-    scales [n,3], quats [n,4], opacities [n], sh [n,K,3], and the kept leaves."""
+def initial_gaussians(leaves, rgb, depth, cam, opacity=0.5, sh_degree=0, tsdf_map=None):
+    """Gaussians of the leaves whose centre depth is valid (and, with a TSDF map, whose
+    mean's voxel has weight 1): dict of means [n,3], scales [n,3], quats [n,4],
+    opacities [n], sh [n,K,3], and the kept leaves."""
     R = np.asarray(cam.R, np.float64).reshape(3, 3)   # world -> camera
     t = np.asarray(cam.t, np.float64)
     K = (sh_degree + 1) ** 2
@@ -104,7 +107,10 @@ def initial_gaussians(leaves, rgb, depth, cam, opacity=0.5, sh_degree=0):
             continue
         pc = np.array([(xc - cam.cx) / cam.fx * d, (yc - cam.cy) / cam.fy * d, d])   # pi^-1(u_q, D[u_q])
         corner = np.array([(x0 - cam.cx) / cam.fx * d, (y0 - cam.cy) / cam.fy * d, d])
-        means.append(R.T @ (pc - t))                                                   # T_WC
+        mean = R.T @ (pc - t)                                                          # T_WC
+        if tsdf_map is not None and tsdf_map.voxel_weight(mean.astype(np.float32)[None])[0] != 1.0:
+            continue                                                                   # seen before
+        means.append(mean)
         scales.append(np.linalg.norm(pc - corner))
         c = np.zeros((K, 3))
         c[0] = (rgb[:, yc, xc].astype(np.float64) - 0.5) / Y00

@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(PKG, "libgsr.so")
 
 P = ctypes.c_void_p
 MAX_VIEWS = 16
+MAX_KERNELS = 32
 
 OK, EINVAL, ENOMEM, EDEVICE, ECAPACITY, EINTERNAL = range(6)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ECAPACITY", 5: "EINTERNAL"}
@@ -61,7 +62,8 @@ class Info(ctypes.Structure):
 
 
 class Timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 16), ("launches", ctypes.c_int64 * 16), ("count", ctypes.c_int32)]
+    _fields_ = [("ms", ctypes.c_double * MAX_KERNELS), ("launches", ctypes.c_int64 * MAX_KERNELS),
+                ("count", ctypes.c_int32)]
 
 
 class Debug(ctypes.Structure):
@@ -79,6 +81,24 @@ class SeedOut(ctypes.Structure):
     _fields_ = [("means", P), ("scales", P), ("quats", P), ("opacities", P), ("sh", P), ("leaves", P)]
 
 
+class Adam(ctypes.Structure):
+    _fields_ = [("lr_means", ctypes.c_float), ("lr_scales", ctypes.c_float), ("lr_quats", ctypes.c_float),
+                ("lr_opacities", ctypes.c_float), ("lr_sh_dc", ctypes.c_float), ("lr_sh_rest", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("m", GaussianGrads), ("v", GaussianGrads), ("state", P)]
+
+
+class ScheduleSettings(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("threshold", ctypes.c_int64),
+                ("store_all", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class TsdfSettings(ctypes.Structure):
+    _fields_ = [("voxel", ctypes.c_float), ("trunc", ctypes.c_float), ("w_max", ctypes.c_float),
+                ("step", ctypes.c_float), ("weighting", ctypes.c_int32)]
+
+
+TSDF_EQ9, TSDF_UNIT_WEIGHT = 0, 1
 SEED_CONTRAST, SEED_DEPTH_VARIANCE = 0, 1
 
 # every symbol include/gsr.h declares, with its ctypes signature
@@ -99,14 +119,28 @@ SIGNATURES = {
     "gsr_debug_export": (ctypes.c_int, [P, P, P]),
     "gsr_last_error": (ctypes.c_char_p, [P]),
     "gsr_graph_create": (ctypes.c_int, [P, P, P, ctypes.c_int32, P, P, P, ctypes.c_float, P, P, P, P,
-                                        ctypes.c_float, P]),
+                                        ctypes.c_float, P, P]),
     "gsr_graph_launch": (ctypes.c_int, [P]),
     "gsr_graph_sync": (ctypes.c_int, [P]),
     "gsr_graph_info": (ctypes.c_int, [P, P, P, P]),
     "gsr_graph_free": (ctypes.c_int, [P]),
     "gsr_autotune": (ctypes.c_int, [P, P, P, ctypes.c_int32, P, ctypes.c_uint32, P]),
     "gsr_seed_settings_default": (ctypes.c_int, [P]),
-    "gsr_seed": (ctypes.c_int, [P, P, P, P, P, P, ctypes.c_int64, P]),
+    "gsr_seed": (ctypes.c_int, [P, P, P, P, P, P, P, ctypes.c_int64, P]),
+    "gsr_tsdf_settings_default": (ctypes.c_int, [P]),
+    "gsr_tsdf_create": (ctypes.c_int, [P, P, ctypes.c_int64, P]),
+    "gsr_tsdf_free": (ctypes.c_int, [P]),
+    "gsr_tsdf_integrate": (ctypes.c_int, [P, P, P, P]),
+    "gsr_tsdf_info": (ctypes.c_int, [P, P, P, P, P]),
+    "gsr_tsdf_export": (ctypes.c_int, [P, P, P, P, P, ctypes.c_int64, P]),
+    "gsr_tsdf_weights": (ctypes.c_int, [P, P, P, ctypes.c_int64, P]),
+    "gsr_adam_default": (ctypes.c_int, [P]),
+    "gsr_adam_step": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_int32, P, P, P]),
+    "gsr_backward_adam": (ctypes.c_int, [P, P, P, P]),
+    "gsr_schedule_create": (ctypes.c_int, [P, P]),
+    "gsr_schedule_free": (ctypes.c_int, [P]),
+    "gsr_schedule_step": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int32, P, P]),
+    "gsr_schedule_keyframes": (ctypes.c_int, [P, P, ctypes.c_int64, P]),
 }
 AUTOTUNE_NO_CACHE = 1
 

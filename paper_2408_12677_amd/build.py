@@ -10,8 +10,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgsr.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("gsr_host.hip", "gsr_kernels.hip", "gsr_seed.hip")]
-HEADERS = [os.path.join(ROOT, "include", "gsr.h"), os.path.join(CSRC, "gsr_internal.h")]
+SOURCES = [os.path.join(CSRC, f) for f in ("gsr_host.hip", "gsr_kernels.hip", "gsr_seed.hip", "gsr_optim.hip", "gsr_tsdf.hip",
+                                           "gsr_schedule.hip")]
+HEADERS = [os.path.join(ROOT, "include", "gsr.h"), os.path.join(CSRC, "gsr_internal.h"), os.path.join(CSRC, "gsr_adam.h"),
+           os.path.join(CSRC, "gsr_tsdf.h")]
 ARCH = os.environ.get("GSR_OFFLOAD_ARCH", "gfx950")
 
 

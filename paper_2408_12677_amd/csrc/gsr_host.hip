@@ -23,6 +23,8 @@ struct gsr_ctx {
   std::string err;
   unsigned long long* h_total = nullptr;  // pinned read-back slots: pair count M, visible records
   Timer timer;
+  void* bwd_scratch = nullptr;  // the eager backward's 2D-gradient rows, kept between calls (grow-only)
+  size_t bwd_scratch_bytes = 0;
 };
 
 // All device state of one step.  Eager forwards size the sort buffers exactly and drop
@@ -74,12 +76,22 @@ struct gsr_graph {
   bool overflowed = false;
 };
 
+struct gsr_tsdf {
+  gsr_ctx* ctx = nullptr;
+  gsr_tsdf_settings s{};
+  TsdfDev dev{};
+  TsdfRules ru{};
+  uint32_t frame = 0;
+  std::vector<void*> blocks;
+};
+
 namespace {
 
 const char* const kKernelNames[K_COUNT] = {"project",    "scan",          "compact",       "radix_hist",
                                            "radix_rowscan", "radix_scatter", "bin_count",   "bin_scan",
                                            "bin_scatter", "ranges",        "tile_order",    "fill",
-                                           "blend_fwd",  "loss_l1",       "blend_bwd",     "project_bwd"};
+                                           "blend_fwd",  "loss_l1",       "blend_bwd",     "project_bwd",
+                                           "adam",       "tsdf_alloc",    "tsdf_fuse"};
 
 thread_local std::string g_noctx_err;
 
@@ -350,7 +362,7 @@ hipError_t enqueue_sort_blend(gsr_saved* sv, hipStream_t s, bool timing) {
 // Backward launches for the view table `vt` (whose g_* pointers are set).  grad2d holds
 // V*N rows of kGrad2D floats followed by N * 3 floats of scratch for the colour term.
 hipError_t enqueue_backward(gsr_saved* sv, const ViewTable& vt, float* grad2d, const GradOut& go, hipStream_t s,
-                            bool timing) {
+                            bool timing, const AdamDev& adam = AdamDev{}, uint32_t* adam_state = nullptr) {
   gsr_ctx* ctx = sv->ctx;
   auto T = [&](int k, auto f) { return timing ? timed(ctx, s, k, f) : f(); };
   const int64_t VN = int64_t(sv->V) * sv->N;
@@ -362,11 +374,65 @@ hipError_t enqueue_backward(gsr_saved* sv, const ViewTable& vt, float* grad2d, c
       return launch_blend_bwd(sv->s.tile, sv->s.batch, vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final,
                               sv->n_contrib, grad2d, TileQueue{sv->order, sv->ctrl}, sv->ck, s);
     });
+  if (e == hipSuccess && adam.on) e = launch_adam_tick(adam_state, adam.b1, adam.b2, s);
   if (e == hipSuccess)
     e = T(K_PROJECT_BWD, [&] {
-      return launch_project_bwd(sv->deg, sv->g, vt, sv->ru, sv->rec, grad2d, grad2d + VN * kGrad2D, go, s);
+      return launch_project_bwd(sv->deg, sv->g, vt, sv->ru, sv->rec, grad2d, grad2d + VN * kGrad2D, go, adam, s);
     });
   return e;
+}
+
+// Checks an optimiser description and fills the kernels' view of it for the parameter
+// arrays p.
+gsr_status adam_dev(gsr_ctx* ctx, const gsr_adam* o, float* const p[G_COUNT], AdamDev* a) {
+  if (!o) return fail(ctx, GSR_EINVAL, "optimiser is NULL");
+  const gsr_gaussian_grads* mv[2] = {&o->m, &o->v};
+  for (const gsr_gaussian_grads* x : mv)
+    if (!x->means || !x->scales || !x->quats || !x->opacities || !x->sh)
+      return fail(ctx, GSR_EINVAL, "every optimiser moment array is required");
+  if (!o->state) return fail(ctx, GSR_EINVAL, "optimiser state is NULL");
+  const float lr[G_COUNT + 1] = {o->lr_means, o->lr_scales, o->lr_quats, o->lr_opacities, o->lr_sh_dc, o->lr_sh_rest};
+  for (float r : lr)
+    if (!(r >= 0.f) || !std::isfinite(r)) return fail(ctx, GSR_EINVAL, "learning rates must be finite and >= 0");
+  if (!(o->beta1 >= 0.f && o->beta1 < 1.f) || !(o->beta2 >= 0.f && o->beta2 < 1.f))
+    return fail(ctx, GSR_EINVAL, "betas must be in [0, 1)");
+  if (!(o->eps >= 0.f) || !std::isfinite(o->eps)) return fail(ctx, GSR_EINVAL, "eps must be finite and >= 0");
+  *a = AdamDev{};
+  for (int i = 0; i < G_COUNT; ++i) a->p[i] = p[i];
+  float* const m[G_COUNT] = {o->m.means, o->m.scales, o->m.quats, o->m.opacities, o->m.sh};
+  float* const v[G_COUNT] = {o->v.means, o->v.scales, o->v.quats, o->v.opacities, o->v.sh};
+  for (int i = 0; i < G_COUNT; ++i) {
+    a->m[i] = m[i];
+    a->v[i] = v[i];
+  }
+  for (int i = 0; i <= G_COUNT; ++i) a->lr[i] = lr[i];
+  a->bc = reinterpret_cast<const float*>(o->state + 1);
+  a->b1 = o->beta1;
+  a->b2 = o->beta2;
+  a->eps = o->eps;
+  a->on = 1;
+  return GSR_OK;
+}
+
+// The eager backward's 2D-gradient rows live in a context buffer that only grows:
+// repeated steps reuse the same memory instead of a fresh allocation per call.
+gsr_status bwd_scratch(gsr_ctx* ctx, size_t need) {
+  if (need <= ctx->bwd_scratch_bytes) return GSR_OK;
+  if (ctx->bwd_scratch) (void)hipFreeAsync(ctx->bwd_scratch, ctx->stream);
+  ctx->bwd_scratch = nullptr;
+  ctx->bwd_scratch_bytes = 0;
+  gsr_status st = dev_alloc(ctx, ctx->stream, &ctx->bwd_scratch, need + need / 8);
+  if (st == GSR_OK) ctx->bwd_scratch_bytes = need + need / 8;
+  return st;
+}
+
+// The saved forward's Gaussian arrays, which a fused optimiser step writes.
+void saved_params(const gsr_saved* sv, float* p[G_COUNT]) {
+  p[G_MEANS] = const_cast<float*>(sv->g.means);
+  p[G_SCALES] = const_cast<float*>(sv->g.scales);
+  p[G_QUATS] = const_cast<float*>(sv->g.quats);
+  p[G_OPAC] = const_cast<float*>(sv->g.opac);
+  p[G_SH] = const_cast<float*>(sv->g.sh);
 }
 
 // A full eager forward: phase A, one read-back of (M, visible), exact sort buffers, phase B.
@@ -494,6 +560,7 @@ gsr_status gsr_ctx_create(int32_t device, void* hip_stream, gsr_ctx** out) {
 gsr_status gsr_ctx_destroy(gsr_ctx* ctx) {
   if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->bwd_scratch) (void)hipFree(ctx->bwd_scratch);
   ctx->timer.destroy();
   if (ctx->h_total) (void)hipHostFree(ctx->h_total);
   delete ctx;
@@ -567,13 +634,64 @@ gsr_status gsr_backward(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_gra
   gsr_saved* sv = const_cast<gsr_saved*>(saved);
   const ViewTable vt = with_grads(sv, grads);
   const int64_t VN = int64_t(sv->V) * sv->N;
-  void* g2 = nullptr;
-  gsr_status st = dev_alloc(ctx, ctx->stream, &g2, (size_t(VN) * kGrad2D + size_t(sv->N) * 3) * sizeof(float));
+  gsr_status st = bwd_scratch(ctx, (size_t(VN) * kGrad2D + size_t(sv->N) * 3) * sizeof(float));
   if (st != GSR_OK) return st;
   GradOut go{out->means, out->scales, out->quats, out->opacities, out->sh, int(flags & GSR_ACCUMULATE)};
-  hipError_t e = enqueue_backward(sv, vt, static_cast<float*>(g2), go, ctx->stream, true);
-  if (g2) (void)hipFreeAsync(g2, ctx->stream);
+  hipError_t e = enqueue_backward(sv, vt, static_cast<float*>(ctx->bwd_scratch), go, ctx->stream, true);
   if (e != hipSuccess) return fail(ctx, GSR_EDEVICE, std::string("backward launch failed: ") + hipGetErrorString(e));
+  return GSR_OK;
+}
+
+gsr_status gsr_backward_adam(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_grad* grads,
+                             const gsr_adam* opt) {
+  if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
+  if (!saved || !grads || !opt) return fail(ctx, GSR_EINVAL, "NULL argument to gsr_backward_adam");
+  gsr_saved* sv = const_cast<gsr_saved*>(saved);
+  float* p[G_COUNT];
+  saved_params(sv, p);
+  AdamDev ad;
+  gsr_status st = adam_dev(ctx, opt, p, &ad);
+  if (st != GSR_OK) return st;
+  const ViewTable vt = with_grads(sv, grads);
+  const int64_t VN = int64_t(sv->V) * sv->N;
+  if ((st = bwd_scratch(ctx, (size_t(VN) * kGrad2D + size_t(sv->N) * 3) * sizeof(float))) != GSR_OK) return st;
+  const GradOut go{nullptr, nullptr, nullptr, nullptr, nullptr, 0};
+  hipError_t e = enqueue_backward(sv, vt, static_cast<float*>(ctx->bwd_scratch), go, ctx->stream, true, ad,
+                                  opt->state);
+  if (e != hipSuccess) return fail(ctx, GSR_EDEVICE, std::string("backward launch failed: ") + hipGetErrorString(e));
+  return GSR_OK;
+}
+
+gsr_status gsr_adam_default(gsr_adam* a) {
+  if (!a) return fail(nullptr, GSR_EINVAL, "NULL argument to gsr_adam_default");
+  *a = gsr_adam{};
+  a->lr_means = 1.6e-4f;
+  a->lr_scales = 5e-3f;
+  a->lr_quats = 1e-3f;
+  a->lr_opacities = 0.05f;
+  a->lr_sh_dc = 2.5e-3f;
+  a->lr_sh_rest = 2.5e-3f / 20.f;
+  a->beta1 = 0.9f;
+  a->beta2 = 0.999f;
+  a->eps = 1e-15f;
+  return GSR_OK;
+}
+
+gsr_status gsr_adam_step(gsr_ctx* ctx, int64_t n, int32_t sh_degree, const gsr_gaussian_grads* params,
+                         const gsr_gaussian_grads* grads, const gsr_adam* opt) {
+  if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
+  if (!params || !grads || !opt) return fail(ctx, GSR_EINVAL, "NULL argument to gsr_adam_step");
+  if (n < 0 || sh_degree < 0 || sh_degree > 3) return fail(ctx, GSR_EINVAL, "n must be >= 0 and sh_degree in 0..3");
+  float* const p[G_COUNT] = {params->means, params->scales, params->quats, params->opacities, params->sh};
+  const float* const g[G_COUNT] = {grads->means, grads->scales, grads->quats, grads->opacities, grads->sh};
+  for (int i = 0; i < G_COUNT; ++i)
+    if (n > 0 && (!p[i] || !g[i])) return fail(ctx, GSR_EINVAL, "every parameter and gradient array is required");
+  AdamDev ad;
+  gsr_status st = adam_dev(ctx, opt, p, &ad);
+  if (st != GSR_OK) return st;
+  hipStream_t s = ctx->stream;
+  GSR_HIP(ctx, launch_adam_tick(opt->state, ad.b1, ad.b2, s));
+  GSR_HIP(ctx, timed(ctx, s, K_ADAM, [&] { return launch_adam(ad, g, n, sh_degree, s); }));
   return GSR_OK;
 }
 
@@ -683,9 +801,10 @@ static void graph_destroy(gsr_graph* gr) {
 gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
                             const gsr_settings* s, const gsr_view_out* outs, const gsr_target* targets,
                             float depth_weight, float* const* grad_color, float* const* grad_depth,
-                            const gsr_gaussian_grads* grads, float* loss_dev, float headroom, gsr_graph** out) {
+                            const gsr_gaussian_grads* grads, float* loss_dev, float headroom,
+                            const gsr_adam* opt, gsr_graph** out) {
   if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
-  if (!out || !targets || !grads || !loss_dev || !grad_color)
+  if (!out || !targets || (!grads && !opt) || !loss_dev || !grad_color)
     return fail(ctx, GSR_EINVAL, "NULL argument to gsr_graph_create");
   *out = nullptr;
   if (!(headroom >= 0.f) || headroom > 16.f) return fail(ctx, GSR_EINVAL, "headroom must be in [0, 16]");
@@ -724,7 +843,17 @@ gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_came
   std::vector<gsr_view_grad> vg(V);
   for (int v = 0; v < V; ++v) vg[v] = gsr_view_grad{grad_color[v], grad_depth ? grad_depth[v] : nullptr, nullptr};
   const ViewTable bvt = with_grads(sv, vg.data());
-  const GradOut go{grads->means, grads->scales, grads->quats, grads->opacities, grads->sh, 0};
+  const GradOut go = grads ? GradOut{grads->means, grads->scales, grads->quats, grads->opacities, grads->sh, 0}
+                           : GradOut{nullptr, nullptr, nullptr, nullptr, nullptr, 0};
+  AdamDev ad{};
+  if (opt) {
+    float* p[G_COUNT];
+    saved_params(sv, p);
+    if ((st = adam_dev(ctx, opt, p, &ad)) != GSR_OK) {
+      graph_destroy(gr);
+      return st;
+    }
+  }
 
   hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&gr->h_flag), sizeof(uint32_t), hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&gr->done, hipEventDisableTiming);
@@ -741,7 +870,7 @@ gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_came
     hipError_t k = enqueue_project(sv, cs, false);
     if (k == hipSuccess) k = enqueue_sort_blend(sv, cs, false);
     if (k == hipSuccess) k = launch_loss_l1(lvt, depth_weight, sv->loss_part, loss_dev, cs);
-    if (k == hipSuccess) k = enqueue_backward(sv, bvt, sv->grad2d, go, cs, false);
+    if (k == hipSuccess) k = enqueue_backward(sv, bvt, sv->grad2d, go, cs, false, ad, opt ? opt->state : nullptr);
     if (k == hipSuccess)
       k = hipMemcpyAsync(gr->h_flag, sv->ctrl + kOverflow, sizeof(uint32_t), hipMemcpyDeviceToHost, cs);
     e = hipStreamEndCapture(cs, &gr->graph);
@@ -944,7 +1073,8 @@ gsr_status gsr_seed_settings_default(gsr_seed_settings* s) {
 }
 
 gsr_status gsr_seed(gsr_ctx* ctx, const gsr_camera* cam, const float* rgb, const float* depth,
-                    const gsr_seed_settings* s, const gsr_seed_out* out, int64_t capacity, int64_t* count) {
+                    const gsr_seed_settings* s, const gsr_tsdf* map, const gsr_seed_out* out, int64_t capacity,
+                    int64_t* count) {
   if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
   if (!cam || !rgb || !depth || !s || !out || !count) return fail(ctx, GSR_EINVAL, "NULL argument to gsr_seed");
   gsr_status st = check_camera(ctx, *cam, 0);
@@ -964,7 +1094,9 @@ gsr_status gsr_seed(gsr_ctx* ctx, const gsr_camera* cam, const float* rgb, const
   SeedImage im{rgb, depth, cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy, {}, {}};
   std::memcpy(im.R, cam->R, sizeof im.R);
   std::memcpy(im.t, cam->t, sizeof im.t);
-  const SeedRules rules{s->measure, s->threshold, s->min_side, s->opacity, s->sh_degree};
+  if (map && map->ctx != ctx) return fail(ctx, GSR_EINVAL, "the map belongs to another context");
+  const SeedRules rules{s->measure, s->threshold, s->min_side, s->opacity, s->sh_degree, map ? 1 : 0,
+                        map ? map->dev : TsdfDev{}};
   const SeedOut so{out->means, out->scales, out->quats, out->opacities, out->sh, out->leaves, capacity};
   const int roots = seed_roots(cam->width, cam->height);
   hipStream_t strm = ctx->stream;
@@ -989,6 +1121,153 @@ gsr_status gsr_seed(gsr_ctx* ctx, const gsr_camera* cam, const float* rgb, const
   *count = n;
   if (over) return fail(ctx, GSR_ECAPACITY, "seeding needs " + std::to_string(n) + " Gaussians, capacity is " +
                                                 std::to_string(capacity));
+  return GSR_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// TSDF map
+// ------------------------------------------------------------------------------------
+gsr_status gsr_tsdf_settings_default(gsr_tsdf_settings* s) {
+  if (!s) return fail(nullptr, GSR_EINVAL, "NULL argument to gsr_tsdf_settings_default");
+  *s = gsr_tsdf_settings{0.01f, 0.08f, 100.f, 0.01f, GSR_TSDF_EQ9};
+  return GSR_OK;
+}
+
+static void tsdf_release(gsr_tsdf* m) {
+  for (void* p : m->blocks) (void)hipFreeAsync(p, m->ctx->stream);
+  (void)hipStreamSynchronize(m->ctx->stream);
+  delete m;
+}
+
+gsr_status gsr_tsdf_create(gsr_ctx* ctx, const gsr_tsdf_settings* s, int64_t max_blocks, gsr_tsdf** out) {
+  if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
+  if (!s || !out) return fail(ctx, GSR_EINVAL, "NULL argument to gsr_tsdf_create");
+  *out = nullptr;
+  if (!(s->voxel > 0.f) || !(s->trunc > 0.f) || !(s->step > 0.f) || !(s->w_max >= 1.f) || !std::isfinite(s->voxel) ||
+      !std::isfinite(s->trunc) || !std::isfinite(s->step) || !std::isfinite(s->w_max))
+    return fail(ctx, GSR_EINVAL, "voxel, trunc and step must be > 0 and w_max >= 1");
+  if (s->weighting != GSR_TSDF_EQ9 && s->weighting != GSR_TSDF_UNIT_WEIGHT)
+    return fail(ctx, GSR_EINVAL, "unknown weighting");
+  const int n_samples = tsdf_band_samples(s->trunc, s->step);
+  if (n_samples > 4096) return fail(ctx, GSR_EINVAL, "more than 4096 band samples per pixel");
+  if (max_blocks < 1 || max_blocks > (int64_t(1) << 28)) return fail(ctx, GSR_EINVAL, "max_blocks must be in 1..2^28");
+  int64_t slots = 1024;
+  while (slots < 2 * max_blocks) slots *= 2;
+  gsr_tsdf* m = new gsr_tsdf;
+  m->ctx = ctx;
+  m->s = *s;
+  m->ru = TsdfRules{s->trunc, s->step, s->w_max, n_samples, s->weighting == GSR_TSDF_UNIT_WEIGHT ? 1 : 0};
+  TsdfDev& d = m->dev;
+  d.slot_mask = uint32_t(slots - 1);
+  d.cap_blocks = uint32_t(max_blocks);
+  d.voxel = s->voxel;
+  hipStream_t strm = ctx->stream;
+  gsr_status st = GSR_OK;
+  auto get = [&](void** p, size_t bytes) {
+    if (st != GSR_OK) return;
+    st = dev_alloc(ctx, strm, p, bytes);
+    if (st == GSR_OK) m->blocks.push_back(*p);
+  };
+  const size_t vox = size_t(max_blocks) * kBlockVoxels;
+  get(reinterpret_cast<void**>(&d.keys), size_t(slots) * 8);
+  get(reinterpret_cast<void**>(&d.vals), size_t(slots) * 4);
+  get(reinterpret_cast<void**>(&d.stamp), size_t(slots) * 4);
+  get(reinterpret_cast<void**>(&d.tsdf), vox * 4);
+  get(reinterpret_cast<void**>(&d.weight), vox * 4);
+  get(reinterpret_cast<void**>(&d.coords), size_t(max_blocks) * sizeof(int4));
+  get(reinterpret_cast<void**>(&d.met), size_t(max_blocks) * 4);
+  get(reinterpret_cast<void**>(&d.ctrl), TSDF_CTRL_WORDS * 4);
+  if (st != GSR_OK) {
+    tsdf_release(m);
+    return st;
+  }
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(d.keys), 0xFFFFFFFFu, slots * 2, strm);
+  if (e == hipSuccess) e = launch_fill_u32(d.vals, kUnassigned, slots, strm);
+  if (e == hipSuccess) e = launch_fill_u32(d.stamp, 0xFFFFFFFFu, slots, strm);
+  if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t*>(d.tsdf), 0u, int64_t(vox), strm);
+  if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t*>(d.weight), 0u, int64_t(vox), strm);
+  if (e == hipSuccess) e = launch_fill_u32(d.ctrl, 0u, TSDF_CTRL_WORDS, strm);
+  if (e != hipSuccess) {
+    tsdf_release(m);
+    return fail(ctx, GSR_EDEVICE, std::string("map set-up failed: ") + hipGetErrorString(e));
+  }
+  *out = m;
+  return GSR_OK;
+}
+
+gsr_status gsr_tsdf_free(gsr_tsdf* m) {
+  if (!m) return fail(nullptr, GSR_EINVAL, "map is NULL");
+  tsdf_release(m);
+  return GSR_OK;
+}
+
+gsr_status gsr_tsdf_integrate(gsr_ctx* ctx, gsr_tsdf* m, const gsr_camera* cam, const float* depth) {
+  if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
+  if (!m || !cam || !depth) return fail(ctx, GSR_EINVAL, "NULL argument to gsr_tsdf_integrate");
+  if (m->ctx != ctx) return fail(ctx, GSR_EINVAL, "the map belongs to another context");
+  gsr_status st = check_camera(ctx, *cam, 0);
+  if (st != GSR_OK) return st;
+  TsdfCam c{};
+  std::memcpy(c.R, cam->R, sizeof c.R);
+  std::memcpy(c.t, cam->t, sizeof c.t);
+  c.fx = cam->fx;
+  c.fy = cam->fy;
+  c.cx = cam->cx;
+  c.cy = cam->cy;
+  c.W = cam->width;
+  c.H = cam->height;
+  hipStream_t strm = ctx->stream;
+  GSR_HIP(ctx, timed(ctx, strm, K_TSDF_ALLOC, [&] { return launch_tsdf_alloc(depth, c, m->dev, m->ru, m->frame, strm); }));
+  GSR_HIP(ctx, timed(ctx, strm, K_TSDF_FUSE, [&] { return launch_tsdf_fuse(depth, c, m->dev, m->ru, strm); }));
+  ++m->frame;
+  if (m->frame == 0xFFFFFFFFu) m->frame = 0;  // never the value that marks an unstamped slot
+  return GSR_OK;
+}
+
+gsr_status gsr_tsdf_info(gsr_ctx* ctx, const gsr_tsdf* m, int64_t* blocks, int64_t* met_last, uint32_t* flags) {
+  if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
+  if (!m) return fail(ctx, GSR_EINVAL, "map is NULL");
+  uint32_t w[TSDF_CTRL_WORDS];
+  GSR_HIP(ctx, hipMemcpyAsync(w, m->dev.ctrl, sizeof w, hipMemcpyDeviceToHost, ctx->stream));
+  GSR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (blocks) *blocks = std::min<int64_t>(w[TSDF_ALLOCATED], m->dev.cap_blocks);
+  if (met_last) *met_last = w[TSDF_MET];
+  if (flags) *flags = w[TSDF_FLAGS];
+  return GSR_OK;
+}
+
+gsr_status gsr_tsdf_export(gsr_ctx* ctx, const gsr_tsdf* m, int32_t* coords, float* tsdf, float* weight,
+                           int64_t capacity, int64_t* count) {
+  if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
+  if (!m || !count) return fail(ctx, GSR_EINVAL, "NULL argument to gsr_tsdf_export");
+  int64_t n = 0;
+  gsr_status st = gsr_tsdf_info(ctx, m, &n, nullptr, nullptr);
+  if (st != GSR_OK) return st;
+  *count = n;
+  if (!coords && !tsdf && !weight) return GSR_OK;
+  if (capacity < n) return fail(ctx, GSR_ECAPACITY, "export needs room for " + std::to_string(n) + " blocks");
+  hipStream_t strm = ctx->stream;
+  if (coords && n > 0) {
+    std::vector<int4> c(static_cast<size_t>(n));
+    GSR_HIP(ctx, hipMemcpyAsync(c.data(), m->dev.coords, size_t(n) * sizeof(int4), hipMemcpyDeviceToHost, strm));
+    GSR_HIP(ctx, hipStreamSynchronize(strm));
+    for (int64_t i = 0; i < n; ++i) {
+      coords[i * 3] = c[size_t(i)].x;
+      coords[i * 3 + 1] = c[size_t(i)].y;
+      coords[i * 3 + 2] = c[size_t(i)].z;
+    }
+  }
+  const size_t vb = size_t(n) * kBlockVoxels * sizeof(float);
+  if (tsdf && n > 0) GSR_HIP(ctx, hipMemcpyAsync(tsdf, m->dev.tsdf, vb, hipMemcpyDeviceToHost, strm));
+  if (weight && n > 0) GSR_HIP(ctx, hipMemcpyAsync(weight, m->dev.weight, vb, hipMemcpyDeviceToHost, strm));
+  GSR_HIP(ctx, hipStreamSynchronize(strm));
+  return GSR_OK;
+}
+
+gsr_status gsr_tsdf_weights(gsr_ctx* ctx, const gsr_tsdf* m, const float* points, int64_t n, float* out) {
+  if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
+  if (!m || (n > 0 && (!points || !out)) || n < 0) return fail(ctx, GSR_EINVAL, "bad argument to gsr_tsdf_weights");
+  GSR_HIP(ctx, launch_tsdf_weights(m->dev, points, n, out, ctx->stream));
   return GSR_OK;
 }
 

@@ -6,6 +6,8 @@
 #include <vector>
 
 #include "gsr.h"
+#include "gsr_adam.h"
+#include "gsr_tsdf.h"
 
 namespace gsr {
 
@@ -27,6 +29,9 @@ enum KernelId {
   K_LOSS,
   K_BLEND_BWD,
   K_PROJECT_BWD,
+  K_ADAM,
+  K_TSDF_ALLOC,
+  K_TSDF_FUSE,
   K_COUNT
 };
 
@@ -231,6 +236,8 @@ struct SeedRules {
   int32_t min_side;
   float opacity;
   int32_t sh_degree;
+  int32_t check;    // nonzero: keep a leaf only where the map's voxel at its mean has weight 1
+  TsdfDev map;
 };
 
 struct SeedOut {
@@ -288,10 +295,30 @@ hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rule
                             const uint2* ranges, const uint32_t* vals, const float* T_final,
                             const uint32_t* n_contrib, float* grad2d, const TileQueue& q, const Ckpt& ck,
                             hipStream_t s);
-// grad2d holds V*N rows of kGrad2D floats; dp_sh is scratch for N * 3 floats.
+// grad2d holds V*N rows of kGrad2D floats; dp_sh is scratch for N * 3 floats.  With
+// adam.on the parameter gradients are not written to `out` but applied to the parameters
+// by one Adam step (adam.bc must already hold the step's bias corrections).
 hipError_t launch_project_bwd(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru,
                               const Records& rec, const float* grad2d, float* dp_sh, const GradOut& out,
-                              hipStream_t s);
+                              const AdamDev& adam, hipStream_t s);
+
+// ---- TSDF fusion (gsr_tsdf.hip) -----------------------------------------------------
+int tsdf_band_samples(float eps, float step);
+// Band allocation of one depth frame [H, W] and the pool assignment / met-block list.
+hipError_t launch_tsdf_alloc(const float* depth, const TsdfCam& cam, const TsdfDev& m, const TsdfRules& ru,
+                             uint32_t frame, hipStream_t s);
+// Eq. 6-9 for every voxel of the blocks the frame met.
+hipError_t launch_tsdf_fuse(const float* depth, const TsdfCam& cam, const TsdfDev& m, const TsdfRules& ru,
+                            hipStream_t s);
+// out[i] = weight of the voxel holding pts[i] (0 where unallocated).
+hipError_t launch_tsdf_weights(const TsdfDev& m, const float* pts, int64_t n, float* out, hipStream_t s);
+
+// ---- optimiser (gsr_optim.hip) ------------------------------------------------------
+// Advances the step counter state[0] and writes the new step's bias corrections to
+// state[1], state[2] (as binary32).
+hipError_t launch_adam_tick(uint32_t* state, float b1, float b2, hipStream_t s);
+// One Adam step over all groups of n Gaussians of SH degree deg, gradients grads[group].
+hipError_t launch_adam(const AdamDev& a, const float* const grads[G_COUNT], int64_t n, int deg, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 
 }  // namespace gsr

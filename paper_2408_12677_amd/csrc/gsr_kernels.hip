@@ -1432,7 +1432,7 @@ constexpr int kShGaussians = 64;  // Gaussians per block of k_project_bwd_sh
 
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd_sh(GaussDev g, ViewTable vt, Records rec, const float* grad2d,
-                                                        GradOut out, float* dp_sh) {
+                                                        GradOut out, float* dp_sh, AdamDev adam) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   constexpr int KK = K * 3;
   constexpr int STRIDE = KK | 1;
@@ -1500,12 +1500,22 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(GaussDev g, ViewTable vt
   if (mine && ch == 0)
 #pragma unroll
     for (int i = 0; i < 3; ++i) dp_sh[gi * 3 + i] = dp[i];
-  if (!out.sh) return;
+  if (!out.sh && !adam.on) return;
   __syncthreads();
   if (gl < nb && ch < 3)
 #pragma unroll
     for (int k = 0; k < K; ++k) s_sh[gl * STRIDE + k * 3 + ch] = dsh[k];
   __syncthreads();
+  if (adam.on) {  // one Adam step of every coefficient of the block's Gaussians, in place
+    const float bc1 = adam.bc[0], bc2 = adam.bc[1];
+    for (int i = t; i < nb * KK; i += 256) {
+      const int r = i / KK, j = i - r * KK;
+      const int64_t e = g0 * KK + i;
+      adam_apply<G_SH>(adam, e, adam.p[G_SH][e], s_sh[r * STRIDE + j], j < 3 ? adam.lr[G_SH] : adam.lr[G_SH + 1],
+                       bc1, bc2);
+    }
+    return;
+  }
   for (int i = t; i < nb * KK; i += 256) {
     const int r = i / KK;
     store_grad(out.sh + g0 * KK + i, s_sh[r * STRIDE + (i - r * KK)], out.accumulate);
@@ -1516,7 +1526,7 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(GaussDev g, ViewTable vt
 // gradient with respect to the mean (dp_sh, from K9a).
 __global__ __launch_bounds__(kProjThreads) void k_project_bwd_geo(GaussDev g, ViewTable vt, Rules ru, Records rec,
                                                                   const float* grad2d, const float* dp_sh,
-                                                                  GradOut out) {
+                                                                  GradOut out, AdamDev adam) {
   const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
   if (gi >= g.n) return;
   float p[3], s[3], q[4];
@@ -1614,6 +1624,17 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd_geo(GaussDev g, Vi
   if (any) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) dp[i] += dp_sh[gi * 3 + i];
+  }
+  if (adam.on) {  // one Adam step of the Gaussian's geometry, in place
+    const float bc1 = adam.bc[0], bc2 = adam.bc[1];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) adam_apply<G_MEANS>(adam, gi * 3 + i, p[i], dp[i], adam.lr[G_MEANS], bc1, bc2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) adam_apply<G_SCALES>(adam, gi * 3 + i, s[i], ds[i], adam.lr[G_SCALES], bc1, bc2);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) adam_apply<G_QUATS>(adam, gi * 4 + i, q[i], dq[i], adam.lr[G_QUATS], bc1, bc2);
+    adam_apply<G_OPAC>(adam, gi, g.opac[gi], dop, adam.lr[G_OPAC], bc1, bc2);
+    return;
   }
   const int acc = out.accumulate;
   if (out.means)
@@ -1861,16 +1882,17 @@ hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rule
 
 hipError_t launch_project_bwd(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru,
                               const Records& rec, const float* grad2d, float* dp_sh, const GradOut& out,
-                              hipStream_t s) {
+                              const AdamDev& adam, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
   const dim3 gsh(blocks_for(g.n, kShGaussians));
   switch (deg) {
-    case 0: k_project_bwd_sh<0><<<gsh, 256, 0, s>>>(g, vt, rec, grad2d, out, dp_sh); break;
-    case 1: k_project_bwd_sh<1><<<gsh, 256, 0, s>>>(g, vt, rec, grad2d, out, dp_sh); break;
-    case 2: k_project_bwd_sh<2><<<gsh, 256, 0, s>>>(g, vt, rec, grad2d, out, dp_sh); break;
-    default: k_project_bwd_sh<3><<<gsh, 256, 0, s>>>(g, vt, rec, grad2d, out, dp_sh); break;
+    case 0: k_project_bwd_sh<0><<<gsh, 256, 0, s>>>(g, vt, rec, grad2d, out, dp_sh, adam); break;
+    case 1: k_project_bwd_sh<1><<<gsh, 256, 0, s>>>(g, vt, rec, grad2d, out, dp_sh, adam); break;
+    case 2: k_project_bwd_sh<2><<<gsh, 256, 0, s>>>(g, vt, rec, grad2d, out, dp_sh, adam); break;
+    default: k_project_bwd_sh<3><<<gsh, 256, 0, s>>>(g, vt, rec, grad2d, out, dp_sh, adam); break;
   }
-  k_project_bwd_geo<<<blocks_for(g.n, kProjThreads), kProjThreads, 0, s>>>(g, vt, ru, rec, grad2d, dp_sh, out);
+  k_project_bwd_geo<<<blocks_for(g.n, kProjThreads), kProjThreads, 0, s>>>(g, vt, ru, rec, grad2d, dp_sh, out,
+                                                                           adam);
   return hipGetLastError();
 }
 

@@ -76,10 +76,26 @@ __device__ __forceinline__ int morton_x(int t) {
 }
 __device__ __forceinline__ int morton_y(int t) { return morton_x(t >> 1); }
 
-// Initial Gaussian of the leaf (x0, y0, w, h); false when its centre depth is not valid.
-__device__ __forceinline__ bool leaf_valid(const SeedImage& im, int x0, int y0, int w, int h) {
+// Mean of the leaf's Gaussian: T_WC pi^-1(centre, D[centre]), i.e. R^T (p_c - t) for the
+// world-to-camera (R, t), in binary64 and rounded once to binary32.
+__device__ __forceinline__ void leaf_mean(const SeedImage& im, int xc, int yc, double d, float mean[3]) {
+  const double pc[3] = {(double(xc) - im.cx) / im.fx * d, (double(yc) - im.cy) / im.fy * d, d};
+  const double q0 = pc[0] - im.t[0], q1 = pc[1] - im.t[1], q2 = pc[2] - im.t[2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) mean[c] = float(double(im.R[c]) * q0 + double(im.R[3 + c]) * q1 + double(im.R[6 + c]) * q2);
+}
+
+// Whether the leaf (x0, y0, w, h) gets a Gaussian: its centre depth is valid and, with the
+// map check on, the voxel nearest its mean was first observed by the latest fused frame
+// (weight exactly 1; Sec. III-B-2).
+__device__ __forceinline__ bool leaf_valid(const SeedImage& im, const SeedRules& r, int x0, int y0, int w, int h) {
   const int xc = x0 + w / 2, yc = y0 + h / 2;
-  return im.depth[int64_t(yc) * im.W + xc] > 0.f;
+  const float d = im.depth[int64_t(yc) * im.W + xc];
+  if (!(d > 0.f)) return false;
+  if (!r.check) return true;
+  float mean[3];
+  leaf_mean(im, xc, yc, double(d), mean);
+  return voxel_weight_at(r.map, mean[0], mean[1], mean[2]) == 1.f;
 }
 
 __device__ void write_gaussian(const SeedImage& im, const SeedRules& r, const SeedOut& out, int64_t k, int x0,
@@ -87,14 +103,12 @@ __device__ void write_gaussian(const SeedImage& im, const SeedRules& r, const Se
   const int xc = x0 + w / 2, yc = y0 + h / 2;
   const int64_t i = int64_t(yc) * im.W + xc, P = int64_t(im.W) * im.H;
   const double d = double(im.depth[i]);
-  const double pc[3] = {(double(xc) - im.cx) / im.fx * d, (double(yc) - im.cy) / im.fy * d, d};
   const double ox = (double(xc - x0)) / im.fx * d, oy = (double(yc - y0)) / im.fy * d;
   const double scale = sqrt(ox * ox + oy * oy);
-  // T_WC: p_w = R^T (p_c - t) for the world-to-camera (R, t)
-  const double q0 = pc[0] - im.t[0], q1 = pc[1] - im.t[1], q2 = pc[2] - im.t[2];
+  float mean[3];
+  leaf_mean(im, xc, yc, d, mean);
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
-    out.means[k * 3 + c] = float(double(im.R[c]) * q0 + double(im.R[3 + c]) * q1 + double(im.R[6 + c]) * q2);
+  for (int c = 0; c < 3; ++c) out.means[k * 3 + c] = mean[c];
 #pragma unroll
   for (int c = 0; c < 3; ++c) out.scales[k * 3 + c] = float(scale);
   out.quats[k * 4] = 1.f;
@@ -221,7 +235,7 @@ __global__ __launch_bounds__(256) void k_seed(SeedImage im, SeedRules r, uint32_
   // clipped to the image, keeping the leaves whose centre depth is valid
   uint32_t cnt = 0;
   for_each_leaf([&](int x0, int y0, int side) {
-    if (leaf_valid(im, x0, y0, min(side, im.W - x0), min(side, im.H - y0))) ++cnt;
+    if (leaf_valid(im, r, x0, y0, min(side, im.W - x0), min(side, im.H - y0))) ++cnt;
   });
   if (PASS == 0) {
     const uint32_t total = seed_block_sum(cnt, red);
@@ -231,7 +245,7 @@ __global__ __launch_bounds__(256) void k_seed(SeedImage im, SeedRules r, uint32_
   int64_t k = int64_t(root_counts[blockIdx.x]) + seed_block_excl_scan(cnt, red);
   for_each_leaf([&](int x0, int y0, int side) {
     const int w = min(side, im.W - x0), h = min(side, im.H - y0);
-    if (!leaf_valid(im, x0, y0, w, h)) return;
+    if (!leaf_valid(im, r, x0, y0, w, h)) return;
     if (k < out.capacity) write_gaussian(im, r, out, k, x0, y0, w, h);
     ++k;
   });

@@ -1,0 +1,170 @@
+// TSDF fusion of one depth frame into the voxel-block map (Sec. III-B-1, Eq. 6-9).
+//
+//   k_tsdf_alloc      one thread per pixel: march the viewing ray through the band
+//                     [d - eps, d + eps] and insert every block a sample falls in (a key is
+//                     read before any compare-and-swap, so the common case of a block
+//                     already present costs one load); stamp the block's slot with the frame
+//   k_tsdf_assign     one thread per table slot: give new keys a pool index (one counter
+//                     atomic per new block, no thread waits on another) and list the blocks
+//                     stamped with this frame
+//   k_tsdf_integrate  one 512-thread block per listed map block, one thread per voxel:
+//                     project the voxel centre, read the nearest pixel's depth, and apply
+//                     Eq. 6-9 to the voxel's distance and weight (coalesced, HBM bound)
+//   k_tsdf_weights    the weight of the voxel holding each query point (seeding check)
+//
+// The block of a sample and the pixel of a voxel are integer decisions taken from
+// binary32 values; contraction is off so each operation rounds once, in the order of the
+// comments, and the same inputs give the same blocks and pixels as any other
+// implementation of that sequence.
+#include <hip/hip_runtime.h>
+
+#include "gsr_internal.h"
+#include "gsr_tsdf.h"
+
+namespace gsr {
+namespace {
+
+constexpr int kAllocThreads = 256;
+constexpr int kIntegrateGrid = 2048;  // persistent blocks of k_tsdf_integrate
+
+// Inserts `key` (or finds it) and stamps its slot with the frame.
+__device__ inline void insert_block(const TsdfDev& m, unsigned long long key, uint32_t frame) {
+  uint32_t h = slot_of(key, m.slot_mask);
+  for (uint32_t probe = 0; probe <= m.slot_mask; ++probe) {
+    unsigned long long k = m.keys[h];
+    if (k == kEmptyKey) k = atomicCAS(&m.keys[h], kEmptyKey, key);
+    if (k == kEmptyKey || k == key) {  // inserted here, or already present
+      m.stamp[h] = frame;
+      return;
+    }
+    h = (h + 1) & m.slot_mask;
+  }
+  atomicOr(&m.ctrl[TSDF_FLAGS], TSDF_TABLE_FULL);
+}
+
+__global__ __launch_bounds__(kAllocThreads) void k_tsdf_alloc(const float* depth, TsdfCam cam, TsdfDev m,
+                                                              TsdfRules ru, uint32_t frame) {
+#pragma clang fp contract(off)
+  const int64_t p = int64_t(blockIdx.x) * kAllocThreads + threadIdx.x;
+  if (p >= int64_t(cam.W) * cam.H) return;
+  const float d = depth[p];
+  if (!(d > 0.f)) return;
+  const int u = int(p % cam.W), v = int(p / cam.W);
+  const float xn = (float(u) - cam.cx) / cam.fx;
+  const float yn = (float(v) - cam.cy) / cam.fy;
+  const float a = d - ru.eps;
+  const float bsize = 8.f * m.voxel;
+  unsigned long long last = kEmptyKey;
+  for (int i = 0; i < ru.n_samples; ++i) {
+    const float z = a + float(i) * ru.step;
+    if (!(z > 0.f)) continue;
+    const float dx = xn * z - cam.t[0], dy = yn * z - cam.t[1], dz = z - cam.t[2];
+    // world point R^T (camera point - t), one row of R^T (a column of R) per axis
+    const float wx = (cam.R[0] * dx + cam.R[3] * dy) + cam.R[6] * dz;
+    const float wy = (cam.R[1] * dx + cam.R[4] * dy) + cam.R[7] * dz;
+    const float wz = (cam.R[2] * dx + cam.R[5] * dy) + cam.R[8] * dz;
+    const float fx = floorf(wx / bsize), fy = floorf(wy / bsize), fz = floorf(wz / bsize);
+    unsigned long long key;
+    if (!(fabsf(fx) < 1.0e6f && fabsf(fy) < 1.0e6f && fabsf(fz) < 1.0e6f) ||
+        !pack_block(int(fx), int(fy), int(fz), &key)) {
+      atomicOr(&m.ctrl[TSDF_FLAGS], TSDF_OUT_OF_RANGE);
+      continue;
+    }
+    if (key == last) continue;  // consecutive samples in one block
+    last = key;
+    insert_block(m, key, frame);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tsdf_assign(TsdfDev m, uint32_t frame) {
+  const uint32_t h = blockIdx.x * 256u + threadIdx.x;
+  if (h > m.slot_mask) return;
+  const unsigned long long key = m.keys[h];
+  if (key == kEmptyKey) return;
+  uint32_t b = m.vals[h];
+  if (b == kUnassigned) {
+    const uint32_t nb = atomicAdd(&m.ctrl[TSDF_ALLOCATED], 1u);
+    if (nb >= m.cap_blocks) {
+      atomicOr(&m.ctrl[TSDF_FLAGS], TSDF_POOL_FULL);
+      return;
+    }
+    b = nb;
+    m.vals[h] = b;
+    m.coords[b] = unpack_block(key);
+  }
+  if (m.stamp[h] == frame) m.met[atomicAdd(&m.ctrl[TSDF_MET], 1u)] = b;
+}
+
+__global__ __launch_bounds__(kBlockVoxels) void k_tsdf_integrate(const float* depth, TsdfCam cam, TsdfDev m,
+                                                                 TsdfRules ru) {
+#pragma clang fp contract(off)
+  const uint32_t n_met = min(m.ctrl[TSDF_MET], m.cap_blocks);
+  const int t = threadIdx.x;
+  const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
+  for (uint32_t i = blockIdx.x; i < n_met; i += gridDim.x) {
+    const uint32_t b = m.met[i];
+    const int4 c = m.coords[b];
+    // voxel centre ((g + 0.5) voxel), then the camera point R p + t (sums left to right)
+    const float px = (float(c.x * kBlockSide + lx) + 0.5f) * m.voxel;
+    const float py = (float(c.y * kBlockSide + ly) + 0.5f) * m.voxel;
+    const float pz = (float(c.z * kBlockSide + lz) + 0.5f) * m.voxel;
+    const float x = ((cam.R[0] * px + cam.R[1] * py) + cam.R[2] * pz) + cam.t[0];
+    const float y = ((cam.R[3] * px + cam.R[4] * py) + cam.R[5] * pz) + cam.t[1];
+    const float z = ((cam.R[6] * px + cam.R[7] * py) + cam.R[8] * pz) + cam.t[2];
+    if (!(z > 0.f)) continue;
+    const float uh = (cam.fx * (x / z) + cam.cx) + 0.5f;  // nearest pixel: floor(u + 0.5)
+    const float vh = (cam.fy * (y / z) + cam.cy) + 0.5f;
+    if (!(uh >= 0.f && uh < float(cam.W) && vh >= 0.f && vh < float(cam.H))) continue;
+    const float D = depth[int64_t(floorf(vh)) * cam.W + int64_t(floorf(uh))];
+    if (!(D > 0.f)) continue;
+    const float sdf = D - z;                                                    // Eq. 6
+    const float q = sdf / ru.eps;
+    const float tsdf = sdf > 0.f ? fminf(1.f, q) : fmaxf(-1.f, q);               // Eq. 7
+    const size_t idx = size_t(b) * kBlockVoxels + t;
+    const float w = m.weight[idx], tv = m.tsdf[idx];
+    const float wn = fminf(ru.w_max, w + 1.f);                                  // Eq. 8
+    m.tsdf[idx] = ru.unit_weight ? (tv * w + tsdf) / (w + 1.f)                   // running average
+                                 : (tv * w + tsdf * wn) / (w + wn);               // Eq. 9
+    m.weight[idx] = wn;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tsdf_weights(TsdfDev m, const float* pts, int64_t n, float* out) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  out[i] = voxel_weight_at(m, pts[i * 3], pts[i * 3 + 1], pts[i * 3 + 2]);
+}
+
+}  // namespace
+
+int tsdf_band_samples(float eps, float step) {
+#pragma clang fp contract(off)
+  const float two_eps = 2.f * eps;
+  return int(floorf(two_eps / step)) + 1;
+}
+
+hipError_t launch_tsdf_alloc(const float* depth, const TsdfCam& cam, const TsdfDev& m, const TsdfRules& ru,
+                             uint32_t frame, hipStream_t s) {
+  // the met-block count starts at zero (a fill kernel, so the sequence may be captured)
+  hipError_t e = launch_fill_u32(m.ctrl + TSDF_MET, 0u, 1, s);
+  if (e != hipSuccess) return e;
+  const int64_t P = int64_t(cam.W) * cam.H;
+  if (P > 0) k_tsdf_alloc<<<unsigned((P + kAllocThreads - 1) / kAllocThreads), kAllocThreads, 0, s>>>(depth, cam, m,
+                                                                                                    ru, frame);
+  k_tsdf_assign<<<unsigned((uint64_t(m.slot_mask) + 256) / 256), 256, 0, s>>>(m, frame);
+  return hipGetLastError();
+}
+
+hipError_t launch_tsdf_fuse(const float* depth, const TsdfCam& cam, const TsdfDev& m, const TsdfRules& ru,
+                            hipStream_t s) {
+  k_tsdf_integrate<<<kIntegrateGrid, kBlockVoxels, 0, s>>>(depth, cam, m, ru);
+  return hipGetLastError();
+}
+
+hipError_t launch_tsdf_weights(const TsdfDev& m, const float* pts, int64_t n, float* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_tsdf_weights<<<unsigned((n + 255) / 256), 256, 0, s>>>(m, pts, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace gsr

@@ -316,7 +316,7 @@ class Graph:
     """
 
     def __init__(self, means, scales, quats, opacities, sh, cameras, targets, settings: Settings | None = None,
-                 depth_weight: float = 0.1, headroom: float = 0.25):
+                 depth_weight: float = 0.1, headroom: float = 0.25, optimizer: "Adam | None" = None):
         settings = settings or Settings()
         dev, n, deg = _param_checks(means, scales, quats, opacities, sh)
         self.ctx = context(dev)
@@ -345,10 +345,16 @@ class Graph:
             self.grad_color.append(gc)
             self.grad_depth.append(gd)
             gcp[i], gdp[i] = gc.data_ptr(), gd.data_ptr()
-        self.grads = dict(means=torch.empty_like(means), scales=torch.empty_like(scales),
-                          quats=torch.empty_like(quats), opacities=torch.empty_like(opacities),
-                          sh=torch.empty_like(sh))
-        gg = N.GaussianGrads(*(self.grads[k].data_ptr() for k in ("means", "scales", "quats", "opacities", "sh")))
+        self.optimizer = optimizer
+        if optimizer is None:
+            self.grads = dict(means=torch.empty_like(means), scales=torch.empty_like(scales),
+                              quats=torch.empty_like(quats), opacities=torch.empty_like(opacities),
+                              sh=torch.empty_like(sh))
+            gg = ctypes.byref(N.GaussianGrads(*(self.grads[k].data_ptr() for k in GROUPS)))
+        else:   # each launch ends with one Adam step applied to the parameters in place
+            optimizer._check(self.params)
+            self.grads = None
+            gg = None
         self.loss = torch.zeros((), dtype=torch.float32, device=dev)
         g = N.Gaussians(n, deg, means.data_ptr(), scales.data_ptr(), quats.data_ptr(), opacities.data_ptr(),
                         sh.data_ptr())
@@ -356,8 +362,10 @@ class Graph:
         self.settings = settings
         h = ctypes.c_void_p()
         N.check(lib.gsr_graph_create(self.ctx.h, ctypes.byref(g), _cams(self.cameras), V, ctypes.byref(s), outs, tg,
-                                     float(depth_weight), gcp, gdp, ctypes.byref(gg),
-                                     ctypes.c_void_p(self.loss.data_ptr()), float(headroom), ctypes.byref(h)),
+                                     float(depth_weight), gcp, gdp, gg,
+                                     ctypes.c_void_p(self.loss.data_ptr()), float(headroom),
+                                     None if optimizer is None else ctypes.byref(optimizer.c),
+                                     ctypes.byref(h)),
                 self.ctx.h)
         self.h = h
 
@@ -406,12 +414,13 @@ def autotune(means, scales, quats, opacities, sh, cameras, settings: Settings | 
 
 
 def seed(rgb, depth, camera, measure: str = "contrast", threshold: float = 0.1, min_side: int = 4,
-         opacity: float = 0.5, sh_degree: int = 0):
+         opacity: float = 0.5, sh_degree: int = 0, tsdf: "TsdfMap | None" = None):
     """Quadtree seeding and Gaussian initialisation of one RGB-D frame (gsr_seed).
 
-    rgb [3,H,W] and depth [H,W] are float32 device tensors of the camera's size.  Returns
-    a dict of means [n,3], scales [n,3], quats [n,4], opacities [n], sh [n,K,3] and the
-    cells' leaves [n,4] (x0, y0, w, h)."""
+    rgb [3,H,W] and depth [H,W] are float32 device tensors of the camera's size.  With a
+    TSDF map (that has fused this frame) a leaf is kept only where the voxel at its mean
+    has weight 1.  Returns a dict of means [n,3], scales [n,3], quats [n,4], opacities
+    [n], sh [n,K,3] and the cells' leaves [n,4] (x0, y0, w, h)."""
     H, W = int(camera.height), int(camera.width)
     dev = rgb.device
     _need(rgb, "rgb", (3, H, W), dev)
@@ -428,5 +437,167 @@ def seed(rgb, depth, camera, measure: str = "contrast", threshold: float = 0.1, 
     ctx = context(dev)
     n = ctypes.c_int64()
     N.check(ctx.lib.gsr_seed(ctx.h, ctypes.byref(_cams([camera])[0]), _ptr(rgb), _ptr(depth), ctypes.byref(s),
-                             ctypes.byref(so), cap, ctypes.byref(n)), ctx.h)
+                             None if tsdf is None else tsdf.h, ctypes.byref(so), cap, ctypes.byref(n)), ctx.h)
     return {k: v[:n.value] for k, v in out.items()}
+
+
+GROUPS = ("means", "scales", "quats", "opacities", "sh")
+
+
+class Adam:
+    """Adam over one Gaussian map (gsr_adam): the moments, in the parameter layouts, and
+    the device step counter live here.  Rates and betas default to gsr_adam_default's
+    (keyword arguments lr_means, lr_scales, lr_quats, lr_opacities, lr_sh_dc, lr_sh_rest,
+    beta1, beta2, eps override them)."""
+
+    def __init__(self, means, scales, quats, opacities, sh, **hyper):
+        dev, n, deg = _param_checks(means, scales, quats, opacities, sh)
+        self.device, self.n, self.sh_degree = dev, n, deg
+        params = (means, scales, quats, opacities, sh)
+        self.shapes = tuple(p.shape for p in params)
+        self.m = {k: torch.zeros_like(p) for k, p in zip(GROUPS, params)}
+        self.v = {k: torch.zeros_like(p) for k, p in zip(GROUPS, params)}
+        self.state = torch.zeros(4, dtype=torch.int32, device=dev)
+        self.ctx = context(dev)
+        c = N.Adam()
+        N.check(self.ctx.lib.gsr_adam_default(ctypes.byref(c)))
+        for k, val in hyper.items():
+            if k not in {f for f, _ in N.Adam._fields_[:9]}:
+                raise TypeError(f"unknown Adam setting {k!r}")
+            setattr(c, k, float(val))
+        c.m = N.GaussianGrads(*(self.m[k].data_ptr() for k in GROUPS))
+        c.v = N.GaussianGrads(*(self.v[k].data_ptr() for k in GROUPS))
+        c.state = self.state.data_ptr()
+        self.c = c
+
+    def _check(self, params):
+        if tuple(p.shape for p in params) != self.shapes:
+            raise ValueError("parameter shapes differ from the optimiser's")
+
+    @property
+    def steps(self) -> int:
+        return int(self.state[0].item())
+
+    def step(self, params, grads: dict):
+        """One Adam step of params (means, scales, quats, opacities, sh; updated in place)
+        from grads (dict of the same layouts)."""
+        self._check(params)
+        for k, p in zip(GROUPS, params):
+            _need(grads[k], f"grad {k}", p.shape, self.device)
+        pp = N.GaussianGrads(*(p.data_ptr() for p in params))
+        gg = N.GaussianGrads(*(grads[k].data_ptr() for k in GROUPS))
+        N.check(self.ctx.lib.gsr_adam_step(self.ctx.h, self.n, self.sh_degree, ctypes.byref(pp), ctypes.byref(gg),
+                                           ctypes.byref(self.c)), self.ctx.h)
+
+
+def backward_adam(saved: Saved, opt: Adam, g_color, g_depth=None, g_alpha=None):
+    """gsr_backward_adam: the backward of `saved` with one Adam step applied at once to
+    the parameter tensors given to forward (updated in place; no gradients are written)."""
+    ctx = saved.ctx
+    opt._check(saved.keep)
+    V = len(saved.cameras)
+    gv = (N.ViewGrad * V)()
+    keep = []
+    for i in range(V):
+        def p(lst):
+            if lst is None or lst[i] is None:
+                return None
+            t = lst[i].contiguous().float()
+            keep.append(t)
+            return t.data_ptr()
+        gv[i] = N.ViewGrad(p(g_color), p(g_depth), p(g_alpha))
+    N.check(ctx.lib.gsr_backward_adam(ctx.h, saved.h, gv, ctypes.byref(opt.c)), ctx.h)
+
+
+class Schedule:
+    """The keyframe-list optimisation schedule (gsr_schedule): step(frame, new_gaussians)
+    returns (is_keyframe, [frame rendered by each iteration])."""
+
+    def __init__(self, m: int, n: int, threshold: int = 50, store_all: bool = False, seed: int = 0):
+        self.lib = N.load()
+        s = N.ScheduleSettings(int(m), int(n), int(threshold), int(bool(store_all)), int(seed) & (2 ** 64 - 1))
+        h = ctypes.c_void_p()
+        N.check(self.lib.gsr_schedule_create(ctypes.byref(s), ctypes.byref(h)))
+        self.h, self.m = h, int(m)
+        self._buf = (ctypes.c_int64 * max(1, self.m))()
+
+    def step(self, frame: int, new_gaussians: int):
+        cnt, kf = ctypes.c_int32(), ctypes.c_int32()
+        N.check(self.lib.gsr_schedule_step(self.h, int(frame), int(new_gaussians), self._buf, max(1, self.m),
+                                           ctypes.byref(cnt), ctypes.byref(kf)))
+        return bool(kf.value), [int(self._buf[i]) for i in range(cnt.value)]
+
+    @property
+    def keyframes(self) -> list:
+        cnt = ctypes.c_int64()
+        N.check(self.lib.gsr_schedule_keyframes(self.h, None, 0, ctypes.byref(cnt)))
+        buf = (ctypes.c_int64 * max(1, cnt.value))()
+        N.check(self.lib.gsr_schedule_keyframes(self.h, buf, cnt.value, ctypes.byref(cnt)))
+        return [int(buf[i]) for i in range(cnt.value)]
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.gsr_schedule_free(h)
+            self.h = None
+
+
+class TsdfMap:
+    """A TSDF voxel-block map on one device (gsr_tsdf_*).  integrate(depth, camera) fuses a
+    depth frame; export() copies the allocated blocks to the host."""
+
+    def __init__(self, device=None, voxel: float = 0.01, trunc: float = 0.08, w_max: float = 100.0,
+                 step: float = 0.01, weighting: str = "eq9", max_blocks: int = 1 << 16):
+        self.ctx = context(device)
+        s = N.TsdfSettings(float(voxel), float(trunc), float(w_max), float(step),
+                           {"eq9": N.TSDF_EQ9, "unit": N.TSDF_UNIT_WEIGHT}[weighting])
+        h = ctypes.c_void_p()
+        N.check(self.ctx.lib.gsr_tsdf_create(self.ctx.h, ctypes.byref(s), int(max_blocks), ctypes.byref(h)),
+                self.ctx.h)
+        self.h = h
+        self.max_blocks = int(max_blocks)
+
+    def integrate(self, depth, camera):
+        H, W = int(camera.height), int(camera.width)
+        _need(depth, "depth", (H, W), depth.device)
+        N.check(self.ctx.lib.gsr_tsdf_integrate(self.ctx.h, self.h, ctypes.byref(_cams([camera])[0]), _ptr(depth)),
+                self.ctx.h)
+
+    def info(self) -> dict:
+        b, m, f = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint32()
+        N.check(self.ctx.lib.gsr_tsdf_info(self.ctx.h, self.h, ctypes.byref(b), ctypes.byref(m), ctypes.byref(f)),
+                self.ctx.h)
+        return dict(blocks=b.value, met_last=m.value, flags=f.value)
+
+    def export(self):
+        """(coords [n,3] int32, tsdf [n,8,8,8], weight [n,8,8,8]) as numpy arrays, voxels
+        indexed [z, y, x] within a block."""
+        import numpy as np
+        n = self.info()["blocks"]
+        c = np.zeros((n, 3), np.int32)
+        t = np.zeros((n, 8, 8, 8), np.float32)
+        w = np.zeros((n, 8, 8, 8), np.float32)
+        cnt = ctypes.c_int64()
+        N.check(self.ctx.lib.gsr_tsdf_export(self.ctx.h, self.h, c.ctypes.data_as(ctypes.c_void_p),
+                                             t.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p),
+                                             n, ctypes.byref(cnt)), self.ctx.h)
+        return c, t, w
+
+    def weights(self, points):
+        """Weight of the voxel holding each point (points: float32 device tensor [n,3])."""
+        _need(points, "points", (points.shape[0], 3), points.device)
+        out = torch.empty(points.shape[0], dtype=torch.float32, device=points.device)
+        N.check(self.ctx.lib.gsr_tsdf_weights(self.ctx.h, self.h, _ptr(points), int(points.shape[0]), _ptr(out)),
+                self.ctx.h)
+        return out
+
+    def free(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.ctx.lib.gsr_tsdf_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

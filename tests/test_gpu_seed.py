@@ -96,7 +96,7 @@ def test_capacity_too_small_is_reported():
     rgb_d, depth_d = torch.from_numpy(rgb).to(DEV), torch.from_numpy(depth).to(DEV)
     cams = R._cams([cam])
     st = ctx.lib.gsr_seed(ctx.h, ctypes.byref(cams[0]), ctypes.c_void_p(rgb_d.data_ptr()),
-                          ctypes.c_void_p(depth_d.data_ptr()), ctypes.byref(s), ctypes.byref(so), cap,
+                          ctypes.c_void_p(depth_d.data_ptr()), ctypes.byref(s), None, ctypes.byref(so), cap,
                           ctypes.byref(n))
     torch.cuda.synchronize()
     assert st == N.ECAPACITY and n.value == need

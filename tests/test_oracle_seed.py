@@ -142,3 +142,24 @@ def test_back_projection_matches_workload_seeder():
 def test_y00_is_the_normalised_constant():
     # integral of Y00^2 over the unit sphere is 1
     assert 4 * math.pi * S.Y00 ** 2 == pytest.approx(1.0, rel=1e-15)
+
+
+def test_voxel_weight_check_against_a_fused_map():
+    # a wall facing the camera: after the frame is fused every leaf's mean sits in a voxel
+    # first seen by that frame (weight 1), so every leaf gives a Gaussian; fusing the
+    # same frame again raises the weights to 2 and the check then keeps none
+    from oracle import tsdf as T
+    W, H = 64, 48
+    cam = _cam(W, H, 50.0)
+    rng = np.random.default_rng(4)
+    rgb = rng.random((3, H, W)).astype(np.float32)
+    depth = np.full((H, W), 1.5, np.float32)
+    leaves, _ = S.quadtree(rgb, depth, "contrast", 0.3, root=16, min_side=4)
+    m = T.TsdfMap(voxel=0.01)
+    m.integrate(depth, cam)
+    first = S.initial_gaussians(leaves, rgb, depth, cam, tsdf_map=m)
+    assert len(first["means"]) == len(leaves) > 10
+    m.integrate(depth, cam)
+    assert len(S.initial_gaussians(leaves, rgb, depth, cam, tsdf_map=m)["means"]) == 0
+    # a fresh map that never saw the frame: weight 0 everywhere, no Gaussians either
+    assert len(S.initial_gaussians(leaves, rgb, depth, cam, tsdf_map=T.TsdfMap(voxel=0.01))["means"]) == 0
