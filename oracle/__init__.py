@@ -55,7 +55,8 @@ class _Set(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("extent_k", ctypes.c_float), ("lowpass", ctypes.c_float),
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("T_min", ctypes.c_float),
                 ("guard", ctypes.c_float), ("bg", ctypes.c_float * 3), ("mu_fp32", ctypes.c_int32),
-                ("threads", ctypes.c_int32), ("amb_rel_a", ctypes.c_float), ("amb_rel_T", ctypes.c_float)]
+                ("threads", ctypes.c_int32), ("amb_rel_a", ctypes.c_float), ("amb_rel_T", ctypes.c_float),
+                ("exact_tiles", ctypes.c_int32)]
 
 
 _lib = None
@@ -103,11 +104,12 @@ class Settings:
     threads: int = 1
     amb_rel_a: float = 1e-5     # binary32 a = o exp(-q/2) is good to ~5e-6 relative
     amb_rel_T: float = 1e-4     # binary32 T accumulates ~100 rounded products
+    exact_tiles: bool = False   # per tile row, only the columns the ellipse can reach
 
     def _c(self):
         return _Set(self.tile, self.extent_k, self.lowpass, self.alpha_min, self.alpha_max, self.T_min, self.guard,
                     (ctypes.c_float * 3)(*self.bg), int(self.mu_fp32), int(self.threads), self.amb_rel_a,
-                    self.amb_rel_T)
+                    self.amb_rel_T, int(self.exact_tiles))
 
 
 def _cams(cameras):

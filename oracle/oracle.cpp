@@ -47,6 +47,7 @@ typedef struct {
   int32_t threads;     // worker threads for the pixel loop (>=1)
   float amb_rel_a;     // relative margin around alpha_min that flags a skip decision as ambiguous
   float amb_rel_T;     // relative margin around T_min that flags a stop decision as ambiguous
+  int32_t exact_tiles; // 1: a tile row keeps only the columns its ellipse can reach (row_run)
 } or_settings;
 
 }  // extern "C"
@@ -269,6 +270,72 @@ Disc discrete_stage(const float p[3], const float s[3], const float q[4], const 
   return d;
 }
 
+// The tile columns of tile row `ty` that can hold a pixel of the ellipse
+// (u - mu)^T Q (u - mu) <= k^2 (Q the binary32 conic: det = a c - b b, inv = 1 / det,
+// Q = (c, -b, a) * inv).  Over the row's pixel band y in [ty*ts, min(ty*ts + ts - 1, H - 1)]
+// the ellipse reaches furthest right at dy = clamp(-B k / sqrt(C det_Q), u0, u1) and
+// furthest left at dy = clamp(B k / sqrt(C det_Q), u0, u1), where its x offsets are
+// (+-sqrt(max(0, A k^2 - det_Q dy^2)) - B dy) / A; pixels from ceil(mu_x + left) to
+// floor(mu_x + right), kept inside the rectangle's columns, give the tiles.  One correctly
+// rounded binary32 operation per line; false when the row keeps no tile.  A degenerate
+// conic (det_Q or C det_Q not > 0) or a NaN keeps the rectangle's columns.
+bool row_run(const Disc& d, float k, int ts, int ty, int W, int H, int tx0, int tx1, int* lo, int* hi) {
+  *lo = tx0;
+  *hi = tx1;
+  float det = d.ca * d.cc;
+  det = det - d.cb * d.cb;
+  const float inv = 1.f / det;
+  const float A = d.cc * inv;
+  const float B = (-d.cb) * inv;
+  const float C = d.ca * inv;
+  float dq = A * C;
+  dq = dq - B * B;
+  if (!(dq > 0.f)) return true;
+  float sq = C * dq;
+  sq = std::sqrt(sq);
+  if (!(sq > 0.f)) return true;
+  float q = B * k;
+  q = q / sq;
+  const float dyr = -q, dyl = q;
+  const int ylast = std::min(ty * ts + ts - 1, H - 1);
+  const float u0 = float(ty * ts) - d.muy;
+  const float u1 = float(ylast) - d.muy;
+  const float ur = std::min(std::max(dyr, u0), u1);
+  const float ul = std::min(std::max(dyl, u0), u1);
+  float ak = k * k;
+  ak = A * ak;
+  // right edge
+  float e = ur * ur;
+  e = dq * e;
+  e = ak - e;
+  e = std::max(e, 0.f);
+  float sr = std::sqrt(e);
+  float xr = B * ur;
+  xr = sr - xr;
+  xr = xr / A;
+  // left edge
+  e = ul * ul;
+  e = dq * e;
+  e = ak - e;
+  e = std::max(e, 0.f);
+  float sl = std::sqrt(e);
+  float xl = B * ul;
+  xl = (-sl) - xl;
+  xl = xl / A;
+  float pl = d.mux + xl;
+  pl = std::ceil(pl);
+  float pr = d.mux + xr;
+  pr = std::floor(pr);
+  const float xa = float(tx0 * ts);
+  const float xb = float(std::min(tx1 * ts + ts - 1, W - 1));
+  if (!(pl >= xa)) pl = xa;  // also a NaN
+  if (!(pr <= xb)) pr = xb;
+  if (!(pl <= pr)) return false;
+  *lo = int(pl) / ts;
+  *hi = int(pr) / ts;
+  return true;
+}
+
 uint32_t f32_bits(float v) {
   uint32_t u;
   std::memcpy(&u, &v, 4);
@@ -444,12 +511,17 @@ void build(Ctx& c) {
       c.disc[size_t(v) * N + g] = d;
       if (!d.vis) continue;
       const int tx0 = d.x0 / ts, tx1 = d.x1 / ts, ty0 = d.y0 / ts, ty1 = d.y1 / ts;
-      for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) {
+      for (int ty = ty0; ty <= ty1; ++ty) {
+        int lo = tx0, hi = tx1;
+        if (c.set.exact_tiles &&
+            !row_run(d, c.set.extent_k, ts, ty, c.cams[v].width, c.cams[v].height, tx0, tx1, &lo, &hi))
+          continue;
+        for (int tx = lo; tx <= hi; ++tx) {
           const uint64_t tile = uint64_t(c.tile_off[v] + int64_t(ty) * c.tiles_x[v] + tx);
           keys.push_back((tile << 32) | f32_bits(d.z));
           vals.push_back(uint32_t(int64_t(v) * N + g));
         }
+      }
     }
   // stable ascending sort by key
   std::vector<size_t> order(keys.size());

@@ -491,3 +491,62 @@ def test_loss_l1_gradient():
         assert (oracle.l1_loss(Cp, D, tc, td)[0] - L) / h == pytest.approx(gC[idx], rel=1e-5)
     assert np.all(gD[0, :4] == 0)
     assert L == pytest.approx(np.abs(C - tc).mean() + 0.1 * np.abs(D - td)[td > 0].sum() / D.size)
+
+
+# ---------------------------------------------------------------------------------------
+# exact ellipse-tile culling (a variant of the tile lists: same images, fewer pairs)
+# ---------------------------------------------------------------------------------------
+
+def _thin_scene(seed, n=120, deg=0):
+    rng = np.random.default_rng(seed)
+    means = np.stack([rng.uniform(-1, 1, n), rng.uniform(-0.8, 0.8, n), rng.uniform(1, 4, n)], 1)
+    g = scenes.random_gaussians(rng, means * 0.5, deg)
+    g.scales *= 3
+    g.scales[:, 0] *= 4                           # elongated splats, most of their rectangle empty
+    return g
+
+
+@pytest.mark.parametrize("tile", [8, 16])
+def test_exact_tiles_equal_brute_force_and_the_rectangle_path(tile):
+    g = _thin_scene(30 + tile)
+    c = cam(56, 40, 30.0, cx=27.5, cy=19.75)
+    box = oracle.Oracle(g.arrays(), 0, [c], oracle.Settings(mu_fp32=False, tile=tile))
+    ex = oracle.Oracle(g.arrays(), 0, [c], oracle.Settings(mu_fp32=False, tile=tile, exact_tiles=True))
+    ob, oe = box.forward()[0], ex.forward()[0]
+    b = brute.render(g.arrays(), 0, c)
+    for k in ("color", "depth", "alpha", "T_final"):
+        np.testing.assert_allclose(oe[k], b[k], atol=1e-12, err_msg=k)
+        np.testing.assert_array_equal(oe[k], ob[k], err_msg=k)      # same contributors, same order
+    np.testing.assert_array_equal(oe["n_used"], ob["n_used"])
+    kb, vb, _ = box.keys()
+    ke, ve, _ = ex.keys()
+    pb = set(zip((kb >> np.uint64(32)).tolist(), vb.tolist()))
+    pe = set(zip((ke >> np.uint64(32)).tolist(), ve.tolist()))
+    assert pe <= pb and len(pe) < 0.9 * len(pb)
+
+
+def test_dropped_tiles_hold_no_pixel_of_the_ellipse():
+    # every (tile, Gaussian) pair the exact lists drop has no pixel centre with
+    # d^T Q d <= k^2 (FP64, conic from the binary32 covariance), so dropping it cannot
+    # change any pixel; pairs kept beyond that are allowed (the band test is conservative)
+    g = _thin_scene(41, n=80)
+    c = cam(64, 48, 36.0, cx=31.5, cy=23.5)
+    ts, k = 8, np.float64(np.float32(3.33))
+    box = oracle.Oracle(g.arrays(), 0, [c], oracle.Settings(tile=ts))
+    ex = oracle.Oracle(g.arrays(), 0, [c], oracle.Settings(tile=ts, exact_tiles=True))
+    kb, vb, _ = box.keys()
+    ke, ve, _ = ex.keys()
+    dropped = set(zip((kb >> np.uint64(32)).tolist(), vb.tolist())) - set(zip((ke >> np.uint64(32)).tolist(), ve.tolist()))
+    assert len(dropped) > 50
+    r = box.records()
+    tx_n = -(-64 // ts)
+    for tile, gi in dropped:
+        a, b_, cc = (float(x) for x in r["cov"][gi])
+        det = a * cc - b_ * b_
+        Q = np.array([[cc, -b_], [-b_, a]]) / det
+        mx, my = (float(x) for x in r["mu"][gi])
+        ty, tx = divmod(tile, tx_n)
+        ys, xs = np.mgrid[ty * ts:min(ty * ts + ts, 48), tx * ts:min(tx * ts + ts, 64)]
+        dx, dy = xs - mx, ys - my
+        qv = Q[0, 0] * dx * dx + 2 * Q[0, 1] * dx * dy + Q[1, 1] * dy * dy
+        assert qv.min() > k * k * (1 - 1e-5), (tile, gi, qv.min())
