@@ -470,6 +470,18 @@ def main():
     ms = timed_steps(g1.launch, args.steps, args.warmup) * 1e3
     g1.sync()
     g1.free()
+    # the same step with exact ellipse-tile lists (same images, shorter lists)
+    import dataclasses
+    sx = dataclasses.replace(s, exact_tiles=True)
+    gx = R.Graph(*params, [cam], [targets[HEADLINE_VIEW]], sx, depth_weight=DEPTH_W)
+    log(f"timing {args.steps} graph-replayed headline steps with exact tile lists")
+    ms_exact = timed_steps(gx.launch, args.steps, args.warmup) * 1e3
+    gx.sync()
+    gx.free()
+    _, saved_x = R.forward(*params, [cam], sx)
+    pairs_exact = int(saved_x.debug_export()["ranges"][:, 1].max(initial=0))
+    saved_x.free()
+
     per_kernel = {k: dict(ms_per_step=t / args.steps, launches_per_step=n / args.steps, avg_launch_us=1e3 * t / n)
                   for k, (t, n) in ktimes.items() if n > 0}
     dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_per_step"])
@@ -495,6 +507,8 @@ def main():
                                "forward + L1(colour)+0.1 L1(depth) + backward, captured step replayed",
                    "gaussians": stats["N"], "width": cam.width, "height": cam.height, "sh_degree": 3,
                    "tile": s.tile, "batch": s.batch, "path": "hipGraph, one view"},
+        "exact_tiles": {"ms_per_step": round(ms_exact, 4), "Mpixel_s": round(px_head / (ms_exact * 1e-3) / 1e6, 3),
+                        "pairs": pairs_exact, "pairs_rectangles": stats["M"]},
         "eager_per_view": {"ms_per_step": round(ms_eager, 4),
                            "Mpixel_s": round(px_head / (ms_eager * 1e-3) / 1e6, 3)},
         "hbm": {"alg_bytes_per_step": int(step_bytes),

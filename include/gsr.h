@@ -100,8 +100,16 @@ typedef struct {
   float T_min;
   float guard;       /* >= 0 */
   float bg[3];
-  uint32_t flags;    /* reserved, must be 0 */
+  uint32_t flags;    /* 0 or GSR_EXACT_TILES */
 } gsr_settings;
+
+/* settings.flags: tile lists hold, per tile row of a splat's rectangle, only the columns
+ * that its ellipse d^T Q d <= extent_k^2 reaches inside the row's pixel band (the rest of
+ * the rectangle holds no pixel the splat can reach).  The images, and every pixel's
+ * processed contributors, are the same as with the full rectangles; the lists are shorter.
+ * gsr_info.num_keys stays the rectangles' pair count (an upper bound); the pairs in use are
+ * those inside the tile ranges. */
+#define GSR_EXACT_TILES 1u
 
 typedef struct {
   float* color; /* [3,H,W] */

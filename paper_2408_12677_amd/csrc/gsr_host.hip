@@ -161,7 +161,7 @@ gsr_status check_settings(gsr_ctx* ctx, const gsr_settings* s) {
   if (!(s->extent_k > 0.f) || !(s->lowpass >= 0.f) || !(s->alpha_min >= 0.f) || !(s->alpha_max > 0.f) ||
       !(s->alpha_max < 1.f) || !(s->T_min >= 0.f) || !(s->T_min < 1.f) || !(s->guard >= 0.f))
     return fail(ctx, GSR_EINVAL, "rule value out of range");
-  if (s->flags != 0) return fail(ctx, GSR_EINVAL, "settings.flags must be 0");
+  if (s->flags & ~GSR_EXACT_TILES) return fail(ctx, GSR_EINVAL, "unknown settings flag");
   return GSR_OK;
 }
 
@@ -346,7 +346,7 @@ hipError_t enqueue_sort_blend(gsr_saved* sv, hipStream_t s, bool timing) {
   }
   if (e == hipSuccess)
     e = launch_bin(sv->vt, sv->N, sv->rec, sorted, sv->d_total + 1, sv->cap_vis, sv->plan, sv->vals, sv->ranges, ovf,
-                   s, tm);
+                   (sv->s.flags & GSR_EXACT_TILES) ? sv->ru.k : 0.f, sv->s.tile, s, tm);
   if (e == hipSuccess)
     e = T(K_TILE_ORDER, [&] {
       return launch_tile_order(sv->ranges, sv->vt.total_tiles, sv->order, s);

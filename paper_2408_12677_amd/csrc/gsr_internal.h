@@ -282,9 +282,10 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                              Timer* tm);
 // Sizes of a binning plan for capacities (cap_vis, cap_M); pointers are left null.
 BinPlan bin_plan(const ViewTable& vt, int64_t cap_vis, int64_t cap_M);
+// exact_k > 0: per tile row only the columns the ellipse d^T Q d <= exact_k^2 reaches
 hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* dvals,
                       const unsigned long long* nvis, int64_t cap_vis, const BinPlan& plan, uint32_t* vals,
-                      uint2* ranges, uint32_t* overflow, hipStream_t s, Timer* tm);
+                      uint2* ranges, uint32_t* overflow, float exact_k, int tile, hipStream_t s, Timer* tm);
 hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
                             uint32_t* n_used, const TileQueue& q, const Ckpt& ck, hipStream_t s);

@@ -274,6 +274,49 @@ __device__ __forceinline__ void conic_of(float a, float b, float c, float& A, fl
   C = a * inv;
 }
 
+// Exact tile culling: the tile columns [lo, hi] of tile row ty (local) that the ellipse
+// d^T Q d <= k^2 of a splat can reach within the row's pixel band, Q = (A, B; B, C) its
+// binary32 conic.  Over the band's offsets [u0, u1] from the centre, the boundary's
+// rightmost point lies at dy = clamp(-B k / sqrt(C det_Q), u0, u1) and the leftmost at
+// dy = clamp(B k / sqrt(C det_Q), u0, u1), with x offsets (+-sqrt(max(0, A k^2 - det_Q
+// dy^2)) - B dy) / A; the pixels between ceil and floor of the two edges, kept inside the
+// rectangle's columns, name the tiles.  One correctly rounded operation per line (the
+// kernels compile with contraction off here), so the lists are reproducible bit for bit;
+// a degenerate conic or a NaN keeps the rectangle's columns.  False when the row keeps
+// no tile.
+__device__ __forceinline__ bool row_run(float mux, float muy, float A, float B, float C, float k, int ts, int ty,
+                                        int W, int H, int tx0, int tx1, int& lo, int& hi) {
+#pragma clang fp contract(off)
+  lo = tx0;
+  hi = tx1;
+  const float dq = A * C - B * B;
+  if (!(dq > 0.f)) return true;
+  const float sq = __builtin_sqrtf(C * dq);
+  if (!(sq > 0.f)) return true;
+  const float q = (B * k) / sq;
+  const float dyr = -q, dyl = q;
+  const int ylast = min(ty * ts + ts - 1, H - 1);
+  const float u0 = float(ty * ts) - muy;
+  const float u1 = float(ylast) - muy;
+  const float ur = fminf(fmaxf(dyr, u0), u1);
+  const float ul = fminf(fmaxf(dyl, u0), u1);
+  const float ak = A * (k * k);
+  const float sr = __builtin_sqrtf(fmaxf(ak - dq * (ur * ur), 0.f));
+  const float xr = (sr - B * ur) / A;
+  const float sl = __builtin_sqrtf(fmaxf(ak - dq * (ul * ul), 0.f));
+  const float xl = ((-sl) - B * ul) / A;
+  float pl = ceilf(mux + xl);
+  float pr = floorf(mux + xr);
+  const float xa = float(tx0 * ts);
+  const float xb = float(min(tx1 * ts + ts - 1, W - 1));
+  if (!(pl >= xa)) pl = xa;  // also a NaN
+  if (!(pr <= xb)) pr = xb;
+  if (!(pl <= pr)) return false;
+  lo = int(pl) / ts;
+  hi = int(pr) / ts;
+  return true;
+}
+
 // Splat value a = o * exp(-q/2), q = A dx^2 + 2 B dx dy + C dy^2.  The compositing kernels
 // stage each record with its conic scaled by -log2(e)/2, (a', b', c') = (A, 2B, C) * k,
 // so that exp(-q/2) = exp2(q') with q' = (a' dx + b' dy) dx + c' dy^2: five operations and
@@ -788,7 +831,8 @@ __global__ __launch_bounds__(256) void k_bin_rows_count(ViewTable vt, int64_t n,
 // row lists
 __global__ __launch_bounds__(64) void k_bin_rows_scatter(ViewTable vt, int64_t n, Records rec, const uint32_t* dvals,
                                                          const unsigned long long* nvis, int64_t cap_vis,
-                                                         const uint32_t* overflow, BinPlan plan) {
+                                                         const uint32_t* overflow, BinPlan plan, float exact_k,
+                                                         int tile) {
   extern __shared__ uint32_t next[];  // next free slot of each row for this chunk
   const int R = plan.rows;
   const int lane = threadIdx.x;
@@ -804,13 +848,23 @@ __global__ __launch_bounds__(64) void k_bin_rows_scatter(ViewTable vt, int64_t n
     const int64_t i = r0 + lane;
     uint32_t cur = 0xFFFFFFFFu, hi = 0u;
     uint2 entry = make_uint2(0u, 0u);
+    int ro = 0, W = 0, H = 0;
+    float4 sp = make_float4(0.f, 0.f, 0.f, 0.f);  // splat centre and conic A, B
+    float cc = 0.f;
     if (i < NV) {
       const uint32_t rid = dvals[i];
       const uint2 rc = rec.rect[rid];
-      const int ro = vt.v[view_of_record(vt, rid, n)].row_off;
+      const ViewDev& cam = vt.v[view_of_record(vt, rid, n)];
+      ro = cam.row_off;
+      W = cam.W;
+      H = cam.H;
       cur = uint32_t(ro) + (rc.y & 0xFFFFu);
       hi = min(uint32_t(ro) + (rc.y >> 16), uint32_t(R - 1));
       entry = make_uint2(rid, rc.x);
+      if (exact_k > 0.f) {
+        sp = rec.r0[rid];
+        cc = rec.r1[rid].x;
+      }
     }
     for (uint32_t y = wave_min_u32(cur); y != 0xFFFFFFFFu; y = wave_min_u32(cur)) {
       const bool on = cur == y;
@@ -818,7 +872,16 @@ __global__ __launch_bounds__(64) void k_bin_rows_scatter(ViewTable vt, int64_t n
       const uint32_t base = next[y];
       if (on) {
         const uint32_t dst = base + uint32_t(__popcll(m & lt_mask));
-        if (int64_t(dst) < plan.cap_M) plan.rowlist[dst] = entry;
+        if (exact_k > 0.f) {  // this row's columns only; an empty run is marked lo > hi
+          int lo, hi2;
+          const int tx0 = int(entry.y & 0xFFFFu), tx1 = int(entry.y >> 16);
+          const bool any = row_run(sp.x, sp.y, sp.z, sp.w, cc, exact_k, tile, int(y) - ro, W, H, tx0, tx1, lo, hi2);
+          const uint2 e = any ? make_uint2(entry.x, uint32_t(lo) | (uint32_t(hi2) << 16))
+                              : make_uint2(entry.x, 0xFFFFu);
+          if (int64_t(dst) < plan.cap_M) plan.rowlist[dst] = e;
+        } else if (int64_t(dst) < plan.cap_M) {
+          plan.rowlist[dst] = entry;
+        }
         cur = cur < hi ? cur + 1u : 0xFFFFFFFFu;
       }
       if (lane == 0) next[y] = base + uint32_t(__popcll(m));
@@ -942,6 +1005,7 @@ __global__ __launch_bounds__(64) void k_bin_tiles_scatter(ViewTable vt, BinPlan 
         rid = e.x;
         cur = e.y & 0xFFFFu;
         hi = min(e.y >> 16, uint32_t(g.tiles_x - 1));
+        if (cur > hi) cur = 0xFFFFFFFFu;  // a row the ellipse does not reach
       }
       for (uint32_t x = wave_min_u32(cur); x != 0xFFFFFFFFu; x = wave_min_u32(cur)) {
         const bool on = cur == x;
@@ -1747,7 +1811,7 @@ static void scan_u32(uint32_t* a, int64_t cap, const unsigned long long* count, 
 
 hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* dvals,
                       const unsigned long long* nvis, int64_t cap_vis, const BinPlan& plan, uint32_t* vals,
-                      uint2* ranges, uint32_t* overflow, hipStream_t s, Timer* tm) {
+                      uint2* ranges, uint32_t* overflow, float exact_k, int tile, hipStream_t s, Timer* tm) {
   if (vt.total_tiles == 0) return hipSuccess;
   if (cap_vis == 0 || plan.cap_M == 0 || plan.rows == 0) {
     k_fill_u32<<<blocks_for(int64_t(vt.total_tiles) * 2, 256), 256, 0, s>>>(reinterpret_cast<uint32_t*>(ranges), 0u,
@@ -1767,7 +1831,8 @@ hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const 
   k_bin_rows_meta<<<1, 1024, 0, s>>>(vt, plan, overflow);
   E(K_BIN_SCAN);
   B(K_BIN_SCATTER);
-  k_bin_rows_scatter<<<plan.nch1, 64, lds_rows, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
+  k_bin_rows_scatter<<<plan.nch1, 64, lds_rows, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan, exact_k,
+                                                      tile);
   E(K_BIN_SCATTER);
   B(K_BIN_COUNT);
   k_bin_tiles_count<<<g_count, 256, lds_cols, s>>>(vt, plan);

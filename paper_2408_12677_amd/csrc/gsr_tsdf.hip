@@ -34,7 +34,7 @@ __device__ inline void insert_block(const TsdfDev& m, unsigned long long key, ui
     unsigned long long k = m.keys[h];
     if (k == kEmptyKey) k = atomicCAS(&m.keys[h], kEmptyKey, key);
     if (k == kEmptyKey || k == key) {  // inserted here, or already present
-      m.stamp[h] = frame;
+      if (m.stamp[h] != frame) m.stamp[h] = frame;  // most samples find it stamped already
       return;
     }
     h = (h + 1) & m.slot_mask;
@@ -76,23 +76,37 @@ __global__ __launch_bounds__(kAllocThreads) void k_tsdf_alloc(const float* depth
   }
 }
 
-__global__ __launch_bounds__(256) void k_tsdf_assign(TsdfDev m, uint32_t frame) {
-  const uint32_t h = blockIdx.x * 256u + threadIdx.x;
-  if (h > m.slot_mask) return;
-  const unsigned long long key = m.keys[h];
-  if (key == kEmptyKey) return;
-  uint32_t b = m.vals[h];
-  if (b == kUnassigned) {
-    const uint32_t nb = atomicAdd(&m.ctrl[TSDF_ALLOCATED], 1u);
-    if (nb >= m.cap_blocks) {
-      atomicOr(&m.ctrl[TSDF_FLAGS], TSDF_POOL_FULL);
-      return;
-    }
-    b = nb;
-    m.vals[h] = b;
-    m.coords[b] = unpack_block(key);
+// Reserves `count` consecutive entries of a counter for the lanes in `mask` with one atomic
+// per wavefront; returns this lane's entry (rank among the mask's lanes below it).
+__device__ inline uint32_t wave_reserve(uint32_t* counter, uint64_t mask, bool mine) {
+  const int lane = threadIdx.x & 63;
+  uint32_t base = 0;
+  if (mask) {
+    const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+    if (lane == leader) base = atomicAdd(counter, uint32_t(__popcll(mask)));
+    base = __shfl(base, leader);
   }
-  if (m.stamp[h] == frame) m.met[atomicAdd(&m.ctrl[TSDF_MET], 1u)] = b;
+  return mine ? base + uint32_t(__popcll(mask & ((1ull << lane) - 1ull))) : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_tsdf_assign(TsdfDev m, uint32_t frame) {
+  const uint32_t h = blockIdx.x * 256u + threadIdx.x;  // the grid covers the slots exactly
+  const unsigned long long key = h <= m.slot_mask ? m.keys[h] : kEmptyKey;
+  uint32_t b = key != kEmptyKey ? m.vals[h] : kUnassigned;
+  const bool fresh = key != kEmptyKey && b == kUnassigned;
+  const uint32_t nb = wave_reserve(&m.ctrl[TSDF_ALLOCATED], __ballot(fresh), fresh);
+  if (fresh) {
+    if (nb < m.cap_blocks) {
+      b = nb;
+      m.vals[h] = b;
+      m.coords[b] = unpack_block(key);
+    } else {
+      atomicOr(&m.ctrl[TSDF_FLAGS], TSDF_POOL_FULL);
+    }
+  }
+  const bool met = b != kUnassigned && m.stamp[h] == frame;
+  const uint32_t at = wave_reserve(&m.ctrl[TSDF_MET], __ballot(met), met);
+  if (met) m.met[at] = b;
 }
 
 __global__ __launch_bounds__(kBlockVoxels) void k_tsdf_integrate(const float* depth, TsdfCam cam, TsdfDev m,

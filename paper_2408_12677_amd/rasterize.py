@@ -35,10 +35,12 @@ class Settings:
     T_min: float = 1e-4
     guard: float = 0.15
     bg: tuple = (0.0, 0.0, 0.0)
+    exact_tiles: bool = False   # GSR_EXACT_TILES: per tile row, only the columns the ellipse reaches
 
     def c(self) -> N.Settings:
         return N.Settings(self.tile, self.batch, self.extent_k, self.lowpass, self.alpha_min, self.alpha_max,
-                          self.T_min, self.guard, (ctypes.c_float * 3)(*self.bg), 0)
+                          self.T_min, self.guard, (ctypes.c_float * 3)(*self.bg),
+                          N.EXACT_TILES if self.exact_tiles else 0)
 
 
 @dataclass
@@ -152,6 +154,8 @@ class Saved:
                    n_used=np.zeros(P, np.uint32))
         d = N.Debug(*(ctypes.c_void_p(out[k].ctypes.data) for k, _ in N.Debug._fields_))
         N.check(self.ctx.lib.gsr_debug_export(self.ctx.h, self.h, ctypes.byref(d)), self.ctx.h)
+        used = int(out["ranges"][:, 1].max(initial=0))   # pairs in use (fewer with exact tiles)
+        out["keys"], out["values"] = out["keys"][:used], out["values"][:used]
         return out
 
     def free(self):

@@ -209,3 +209,24 @@ def test_cfg4_all_views_graph_vs_eager(R):
         close(graph.grads, e_grads)
     say("cfg4 batched", inf, graph.info())
     graph.free()
+
+
+def test_graph_with_exact_tiles_matches_eager(R):
+    g, cams, targets = small_views()
+    params = to_dev(g)
+    tg = dev_targets(targets)
+    s = settings(exact_tiles=True)
+    e_images, e_loss, e_grads, _ = eager_step(R, params, cams, tg, s)
+    b_images, _, _, _ = eager_step(R, params, cams, tg, settings())
+    for a, b in zip(e_images, b_images):          # the same images as the rectangle lists
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+    graph = R.Graph(*params, cams, tg, s)
+    for rep in range(3):
+        graph.launch()
+        graph.sync()
+        for a, b in zip(graph.images, e_images):
+            for x, y in zip(a, b):
+                assert torch.equal(x, y), f"replay {rep}"
+        close(graph.grads, e_grads)
+    graph.free()

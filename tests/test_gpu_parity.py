@@ -90,11 +90,12 @@ def test_cfg1_forward_parity(R):
     say("cfg1", rep, saved.info())
 
 
+@pytest.mark.parametrize("exact", [False, True])
 @pytest.mark.parametrize("tile", [8, 16, 32])
-def test_keys_bitexact_every_tile_size(R, tile):
+def test_keys_bitexact_every_tile_size(R, tile, exact):
     w = scenes.make_cfg1()
-    s = settings(tile=tile)
-    say("keys tile", tile)
+    s = settings(tile=tile, exact_tiles=exact)
+    say("keys tile", tile, "exact", exact)
     _, _, saved = run_fwd(R, w.gaussians, w.cameras, s)
     dbg = saved.debug_export()
     check_keys(dbg, oracle_for(w.gaussians, w.cameras, s))
@@ -106,8 +107,9 @@ def test_forward_bitwise_invariant_across_autotune_points(R):
     say("autotune invariance")
     ref = None
     for tile in (8, 16, 32):
-        for batch in (128, 256):
-            _, images, _ = run_fwd(R, w.gaussians, cams, settings(tile=tile, batch=batch), save=False)
+        for batch, exact in ((128, False), (256, False), (256, True)):
+            _, images, _ = run_fwd(R, w.gaussians, cams, settings(tile=tile, batch=batch, exact_tiles=exact),
+                                   save=False)
             cur = [t.cpu().numpy() for img in images for t in img]
             if ref is None:
                 ref = cur
@@ -290,3 +292,38 @@ def test_headline_view_full_size(R):
     say("headline", w.gaussians.n, cam.width, cam.height)
     rep, grep = fwd_bwd_parity(R, w.gaussians, [cam], settings(), targets=[w.targets[v]], threads=8)
     say("headline", rep, grep)
+
+
+# ---------------------------------------------------------------------------------------
+# exact ellipse-tile culling: shorter lists, the same images and gradients
+# ---------------------------------------------------------------------------------------
+
+def test_exact_tiles_multiview_fwd_bwd(R):
+    w = scenes.make_cfg1()
+    c = w.cameras[0]
+    R1, t1 = scenes.look_at([0.2, 0.1, -0.3], [0.0, 0.0, 3.0], up=(0, -1, 0))
+    cams = [c, scenes.Camera(100, 75, 90.0, 90.0, 50.3, 37.6, R1, t1), c.crop(13, 7, 37, 29)]
+    for tile in (8, 16):
+        say("exact tiles multiview, tile", tile)
+        rep, grep = fwd_bwd_parity(R, w.gaussians, cams, settings(tile=tile, exact_tiles=True))
+        say(rep, grep)
+
+
+def test_exact_tiles_cfg2_with_loss(R):
+    w = scenes.make_cfg2()
+    s = settings(exact_tiles=True)
+    rep, grep = fwd_bwd_parity(R, w.gaussians, w.cameras, s, targets=w.targets)
+    _, _, box = run_fwd(R, w.gaussians, w.cameras, settings())
+    _, _, ex = run_fwd(R, w.gaussians, w.cameras, s)
+    nb, ne = len(box.debug_export()["keys"]), len(ex.debug_export()["keys"])
+    say("cfg2 exact tiles", rep, grep, "pairs", nb, "->", ne)
+    assert ne < nb
+
+
+def test_headline_view_full_size_exact_tiles(R):
+    w = scenes.make_cfg4()
+    v = scenes.HEADLINE_VIEW
+    cam = w.cameras[v]
+    rep, grep = fwd_bwd_parity(R, w.gaussians, [cam], settings(exact_tiles=True), targets=[w.targets[v]],
+                               threads=8)
+    say("headline exact tiles", rep, grep)
