@@ -56,7 +56,7 @@ class _Set(ctypes.Structure):
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("T_min", ctypes.c_float),
                 ("guard", ctypes.c_float), ("bg", ctypes.c_float * 3), ("mu_fp32", ctypes.c_int32),
                 ("threads", ctypes.c_int32), ("amb_rel_a", ctypes.c_float), ("amb_rel_T", ctypes.c_float),
-                ("exact_tiles", ctypes.c_int32)]
+                ("exact_tiles", ctypes.c_int32), ("normalized_depth", ctypes.c_int32)]
 
 
 _lib = None
@@ -105,11 +105,12 @@ class Settings:
     amb_rel_a: float = 1e-5     # binary32 a = o exp(-q/2) is good to ~5e-6 relative
     amb_rel_T: float = 1e-4     # binary32 T accumulates ~100 rounded products
     exact_tiles: bool = False   # per tile row, only the columns the ellipse can reach
+    normalized_depth: bool = False   # depth output D / (1 - T_final)
 
     def _c(self):
         return _Set(self.tile, self.extent_k, self.lowpass, self.alpha_min, self.alpha_max, self.T_min, self.guard,
                     (ctypes.c_float * 3)(*self.bg), int(self.mu_fp32), int(self.threads), self.amb_rel_a,
-                    self.amb_rel_T, int(self.exact_tiles))
+                    self.amb_rel_T, int(self.exact_tiles), int(self.normalized_depth))
 
 
 def _cams(cameras):

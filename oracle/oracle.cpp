@@ -48,6 +48,7 @@ typedef struct {
   float amb_rel_a;     // relative margin around alpha_min that flags a skip decision as ambiguous
   float amb_rel_T;     // relative margin around T_min that flags a stop decision as ambiguous
   int32_t exact_tiles; // 1: a tile row keeps only the columns its ellipse can reach (row_run)
+  int32_t normalized_depth;  // 1: the depth output is D / (1 - T_final) (0 where nothing is hit)
 } or_settings;
 
 }  // extern "C"
@@ -308,7 +309,7 @@ bool row_run(const Disc& d, float k, int ts, int ty, int W, int H, int tx0, int 
   float e = ur * ur;
   e = dq * e;
   e = ak - e;
-  e = std::max(e, 0.f);
+  e = e > 0.f ? e : 0.f;  // also a NaN
   float sr = std::sqrt(e);
   float xr = B * ur;
   xr = sr - xr;
@@ -317,7 +318,7 @@ bool row_run(const Disc& d, float k, int ts, int ty, int W, int H, int tx0, int 
   e = ul * ul;
   e = dq * e;
   e = ak - e;
-  e = std::max(e, 0.f);
+  e = e > 0.f ? e : 0.f;  // also a NaN
   float sl = std::sqrt(e);
   float xl = B * ul;
   xl = (-sl) - xl;
@@ -579,6 +580,12 @@ struct Hit {
 
 // Front-to-back compositing of one pixel over its tile's sorted list.
 // Returns the processed contributors (skipped entries omitted).
+// Depth normalised by the accumulated opacity: D / (1 - T_final), 0 where nothing is hit.
+double normalized(double D, double T) {
+  const double A = 1.0 - T;
+  return A > 0.0 ? D / A : 0.0;
+}
+
 void composite(const Ctx& c, int64_t tile, double px, double py, double out[5], int32_t& ncontrib,
                int32_t& nused, bool& ambiguous, std::vector<Hit>* hits) {
   const uint32_t s = c.ranges[tile * 2], e = c.ranges[tile * 2 + 1];
@@ -730,7 +737,7 @@ void or_forward(void* h, double* color, double* depth, double* alpha, double* T_
           const int64_t base = c.pix_off[v];
           if (color)
             for (int ch = 0; ch < 3; ++ch) color[base * 3 + ch * P + pix] = out[ch];
-          if (depth) depth[base + pix] = out[3];
+          if (depth) depth[base + pix] = c.set.normalized_depth ? normalized(out[3], out[4]) : out[3];
           if (alpha) alpha[base + pix] = 1.0 - out[4];
           if (T_final) T_final[base + pix] = out[4];
           if (n_contrib) n_contrib[base + pix] = n;
@@ -784,6 +791,19 @@ void or_backward(void* h, const double* g_color, const double* g_depth, const do
           composite(c, tile, x, y, out, n, nu, amb, &hits);
           if (pix_amb && pix_amb[base + pix]) amb = true;
           const double Tfin = out[4];
+          if (c.set.normalized_depth) {
+            // Dn = D / A with A = 1 - T_final: dL/dD = g / A, and dL/dA gains -g D / A^2
+            // = -g Dn / A; through A = 1 - T_final that is +g Dn / A on the alpha
+            // output's gradient route (A is the alpha output)
+            const double A = 1.0 - Tfin;
+            if (A > 0.0) {
+              const double Dn = out[3] / A;
+              gA += -gD * Dn / A;
+              gD = gD / A;
+            } else {
+              gD = 0.0;
+            }
+          }
           double BC[3] = {c.set.bg[0], c.set.bg[1], c.set.bg[2]}, BD = 0.0;
           for (size_t i = hits.size(); i-- > 0;) {
             const Hit& hh = hits[i];

@@ -433,10 +433,11 @@ def _fd_scene(deg, seed):
     return g, c
 
 
+@pytest.mark.parametrize("norm", [False, True])
 @pytest.mark.parametrize("deg,seed", [(0, 20), (3, 21)])
-def test_backward_matches_central_differences(deg, seed):
+def test_backward_matches_central_differences(deg, seed, norm):
     g, c = _fd_scene(deg, seed)
-    s = oracle.Settings(mu_fp32=False, tile=8, bg=(0.1, 0.2, 0.3))
+    s = oracle.Settings(mu_fp32=False, tile=8, bg=(0.1, 0.2, 0.3), normalized_depth=norm)
     rng = np.random.default_rng(seed + 100)
     H, W = c.height, c.width
     wC, wD, wA = rng.standard_normal((3, H, W)), rng.standard_normal((H, W)), rng.standard_normal((H, W))
@@ -550,3 +551,25 @@ def test_dropped_tiles_hold_no_pixel_of_the_ellipse():
         dx, dy = xs - mx, ys - my
         qv = Q[0, 0] * dx * dx + 2 * Q[0, 1] * dx * dy + Q[1, 1] * dy * dy
         assert qv.min() > k * k * (1 - 1e-5), (tile, gi, qv.min())
+
+
+def test_normalized_depth_closed_forms():
+    # one Gaussian alone on a pixel: D = z a, A = a, so D / A = z whatever its opacity;
+    # two on the same line of sight: the alpha-weighted mean of their depths
+    c = cam(16, 16, 20.0, cx=8.0, cy=8.0)    # pixel (8, 8) sits on both centres: G = 1
+    g1 = gaussians([[0.0, 0.0, 2.0]], [[0.3, 0.3, 0.3]], opac=[0.37])
+    o = oracle.Oracle(g1, 0, [c], oracle.Settings(normalized_depth=True)).forward()[0]
+    hit = o["alpha"] > 0
+    assert hit.sum() > 20
+    np.testing.assert_allclose(o["depth"][hit], np.float64(np.float32(2.0)), rtol=1e-12)
+    assert (o["depth"][~hit] == 0).all()
+    g2 = gaussians([[0.0, 0.0, 2.0], [0.0, 0.0, 3.0]], [[0.3, 0.3, 0.3], [0.5, 0.5, 0.5]], opac=[0.4, 0.6])
+    raw = oracle.Oracle(g2, 0, [c], oracle.Settings()).forward()[0]
+    nrm = oracle.Oracle(g2, 0, [c], oracle.Settings(normalized_depth=True)).forward()[0]
+    hit = raw["alpha"] > 0
+    np.testing.assert_allclose(nrm["depth"][hit], raw["depth"][hit] / raw["alpha"][hit], rtol=1e-12)
+    assert ((nrm["depth"][hit] > 2.0 - 1e-6) & (nrm["depth"][hit] < 3.0 + 1e-6)).all()
+    centre = nrm["depth"][8, 8]
+    a1 = 0.4
+    a2 = 0.6
+    assert centre == pytest.approx((2.0 * a1 + 3.0 * a2 * (1 - a1)) / (a1 + a2 * (1 - a1)), rel=1e-6)
