@@ -100,7 +100,7 @@ typedef struct {
   float T_min;
   float guard;       /* >= 0 */
   float bg[3];
-  uint32_t flags;    /* 0 or GSR_EXACT_TILES */
+  uint32_t flags;    /* GSR_EXACT_TILES | GSR_NORMALIZED_DEPTH, or 0 */
 } gsr_settings;
 
 /* settings.flags: tile lists hold, per tile row of a splat's rectangle, only the columns
@@ -110,6 +110,10 @@ typedef struct {
  * gsr_info.num_keys stays the rectangles' pair count (an upper bound); the pairs in use are
  * those inside the tile ranges. */
 #define GSR_EXACT_TILES 1u
+/* settings.flags: the depth output is D / (1 - T_final), the depth of the surface the
+ * pixel sees as an opacity-weighted mean (0 where nothing is hit), instead of the
+ * accumulated D = sum z alpha T; the backward takes its gradient through the division. */
+#define GSR_NORMALIZED_DEPTH 2u
 
 typedef struct {
   float* color; /* [3,H,W] */

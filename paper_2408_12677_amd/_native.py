@@ -15,6 +15,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ECAPACITY, EINTERNAL = range(6)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ECAPACITY", 5: "EINTERNAL"}
 ACCUMULATE = 1
 EXACT_TILES = 1
+NORMALIZED_DEPTH = 2
 
 
 class GsrError(RuntimeError):

@@ -161,7 +161,7 @@ gsr_status check_settings(gsr_ctx* ctx, const gsr_settings* s) {
   if (!(s->extent_k > 0.f) || !(s->lowpass >= 0.f) || !(s->alpha_min >= 0.f) || !(s->alpha_max > 0.f) ||
       !(s->alpha_max < 1.f) || !(s->T_min >= 0.f) || !(s->T_min < 1.f) || !(s->guard >= 0.f))
     return fail(ctx, GSR_EINVAL, "rule value out of range");
-  if (s->flags & ~GSR_EXACT_TILES) return fail(ctx, GSR_EINVAL, "unknown settings flag");
+  if (s->flags & ~(GSR_EXACT_TILES | GSR_NORMALIZED_DEPTH)) return fail(ctx, GSR_EINVAL, "unknown settings flag");
   return GSR_OK;
 }
 
@@ -217,7 +217,8 @@ gsr_status make_saved(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* ca
   sv->deg = g->sh_degree;
   sv->s = *s;
   sv->g = GaussDev{g->means, g->scales, g->quats, g->opacities, g->sh, g->n};
-  sv->ru = Rules{s->extent_k, s->lowpass, s->alpha_min, s->alpha_max, s->T_min, s->guard, {s->bg[0], s->bg[1], s->bg[2]}};
+  sv->ru = Rules{s->extent_k, s->lowpass, s->alpha_min, s->alpha_max, s->T_min, s->guard,
+                 {s->bg[0], s->bg[1], s->bg[2]}, (s->flags & GSR_NORMALIZED_DEPTH) ? 1 : 0};
   ViewTable& vt = sv->vt;
   std::memset(&vt, 0, sizeof(vt));
   vt.nviews = V;

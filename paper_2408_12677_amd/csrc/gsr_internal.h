@@ -145,6 +145,7 @@ struct ViewTable {
 struct Rules {
   float k, lowpass, amin, amax, Tmin, guard;
   float bg[3];
+  int32_t norm_depth;  // depth output D / (1 - T_final) (GSR_NORMALIZED_DEPTH)
 };
 
 struct GaussDev {

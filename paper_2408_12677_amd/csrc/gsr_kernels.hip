@@ -1195,7 +1195,7 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
       cam.color[pix] = C0 + T * ru.bg[0];
       cam.color[P + pix] = C1 + T * ru.bg[1];
       cam.color[2 * P + pix] = C2 + T * ru.bg[2];
-      if (cam.depth) cam.depth[pix] = D;
+      if (cam.depth) cam.depth[pix] = !ru.norm_depth ? D : (T < 1.f ? D / (1.f - T) : 0.f);
       if (cam.alpha) cam.alpha[pix] = 1.f - T;
       T_final[cam.pix_off + pix] = T;
       n_contrib[cam.pix_off + pix] = last;
@@ -1376,6 +1376,16 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
       }
       if (cam.g_depth) gD = cam.g_depth[pix];
       if (cam.g_alpha) gA = cam.g_alpha[pix];
+      if (ru.norm_depth) {  // output Dn = D / A, A = 1 - T_final: dL/dD = g / A, dL/dA -= g Dn / A
+        const float A = 1.f - Tfin;
+        if (A > 0.f) {
+          const float Dn = ck.acc[cam.pix_off + pix].w / A;
+          gA -= gD * Dn / A;
+          gD = gD / A;
+        } else {
+          gD = 0.f;
+        }
+      }
       if (nc <= hi) {
         T = Tfin;
         top = nc;

@@ -327,3 +327,32 @@ def test_headline_view_full_size_exact_tiles(R):
     rep, grep = fwd_bwd_parity(R, w.gaussians, [cam], settings(exact_tiles=True), targets=[w.targets[v]],
                                threads=8)
     say("headline exact tiles", rep, grep)
+
+
+# ---------------------------------------------------------------------------------------
+# variants: normalised depth output, a 3-sigma (lossy) splat extent
+# ---------------------------------------------------------------------------------------
+
+def test_normalized_depth_fwd_bwd(R):
+    w = scenes.make_cfg1()
+    c = w.cameras[0]
+    cams = [c, c.crop(9, 5, 61, 47)]
+    say("normalised depth, random output gradients")
+    rep, grep = fwd_bwd_parity(R, w.gaussians, cams, settings(normalized_depth=True, bg=(0.2, 0.1, 0.0)))
+    say(rep, grep)
+    w2 = scenes.make_cfg2()
+    say("normalised depth, cfg2 with loss")
+    rep, grep = fwd_bwd_parity(R, w2.gaussians, w2.cameras, settings(normalized_depth=True, exact_tiles=True),
+                               targets=w2.targets)
+    say(rep, grep)
+
+
+def test_lossy_extent_three_sigma(R):
+    # extent k = 3 < sqrt(2 ln 255): rectangles cut splat tails that would pass the skip
+    # rule, so the images depend on the tiles; the oracle follows the same rectangles
+    w = scenes.make_cfg1()
+    for tile in (8, 16):
+        s = settings(tile=tile, extent_k=3.0)
+        say("extent 3, tile", tile)
+        rep, grep = fwd_bwd_parity(R, w.gaussians, w.cameras, s)
+        say(rep, grep)
