@@ -383,6 +383,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--exact-tiles", action="store_true", help="exact ellipse-tile lists (with --autotune 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-seed", action="store_true", help="skip the quadtree seeding measurement")
@@ -431,7 +432,8 @@ def main():
     dev = torch.device("cuda", 0)
     params = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in w.gaussians.arrays()]
     targets = [(torch.from_numpy(tc).to(dev), torch.from_numpy(td).to(dev)) for tc, td in w.targets]
-    s = R.Settings(tile=args.tile, batch=args.batch)  # replaced by the autotuner's choice unless --autotune 0
+    # replaced by the autotuner's choice unless --autotune 0
+    s = R.Settings(tile=args.tile, batch=args.batch, exact_tiles=args.exact_tiles)
     grads = dict(means=torch.empty_like(params[0]), scales=torch.empty_like(params[1]),
                  quats=torch.empty_like(params[2]), opacities=torch.empty_like(params[3]),
                  sh=torch.empty_like(params[4]))
@@ -451,7 +453,8 @@ def main():
     if args.autotune:
         os.environ.setdefault("GSR_AUTOTUNE_CACHE", os.path.join("/tmp", "gsr_bench_autotune.txt"))
         s, tune_ms = R.autotune(*params, [cam], s, use_cache=False)
-        log(f"autotuned launch shape: tile {s.tile}, batch {s.batch} ({tune_ms:.3f} ms/step)")
+        log(f"autotuned launch shape: tile {s.tile}, batch {s.batch}, exact tiles {s.exact_tiles} "
+            f"({tune_ms:.3f} ms/step)")
     stats = step_stats(R, params, [cam], [targets[HEADLINE_VIEW]], s)
     log("headline stats", stats)
 
@@ -470,17 +473,21 @@ def main():
     ms = timed_steps(g1.launch, args.steps, args.warmup) * 1e3
     g1.sync()
     g1.free()
-    # the same step with exact ellipse-tile lists (same images, shorter lists)
+    # the same step with the other kind of tile list (rectangles / exact ellipse-tile
+    # lists: the same images, different list lengths)
     import dataclasses
-    sx = dataclasses.replace(s, exact_tiles=True)
+    sx = dataclasses.replace(s, exact_tiles=not s.exact_tiles)
     gx = R.Graph(*params, [cam], [targets[HEADLINE_VIEW]], sx, depth_weight=DEPTH_W)
-    log(f"timing {args.steps} graph-replayed headline steps with exact tile lists")
-    ms_exact = timed_steps(gx.launch, args.steps, args.warmup) * 1e3
+    log(f"timing {args.steps} graph-replayed headline steps with exact tile lists {sx.exact_tiles}")
+    ms_other = timed_steps(gx.launch, args.steps, args.warmup) * 1e3
     gx.sync()
     gx.free()
-    _, saved_x = R.forward(*params, [cam], sx)
-    pairs_exact = int(saved_x.debug_export()["ranges"][:, 1].max(initial=0))
-    saved_x.free()
+    pairs = {}
+    for kind in (s, sx):
+        _, sv = R.forward(*params, [cam], kind)
+        pairs[kind.exact_tiles] = int(sv.debug_export()["ranges"][:, 1].max(initial=0))
+        sv.free()
+    ms_kind = {s.exact_tiles: ms, sx.exact_tiles: ms_other}
 
     per_kernel = {k: dict(ms_per_step=t / args.steps, launches_per_step=n / args.steps, avg_launch_us=1e3 * t / n)
                   for k, (t, n) in ktimes.items() if n > 0}
@@ -506,9 +513,10 @@ def main():
         "config": {"workload": "500k-Gaussian quadtree-seeded room map (SH3), one 640x480 view: "
                                "forward + L1(colour)+0.1 L1(depth) + backward, captured step replayed",
                    "gaussians": stats["N"], "width": cam.width, "height": cam.height, "sh_degree": 3,
-                   "tile": s.tile, "batch": s.batch, "path": "hipGraph, one view"},
-        "exact_tiles": {"ms_per_step": round(ms_exact, 4), "Mpixel_s": round(px_head / (ms_exact * 1e-3) / 1e6, 3),
-                        "pairs": pairs_exact, "pairs_rectangles": stats["M"]},
+                   "tile": s.tile, "batch": s.batch, "exact_tiles": s.exact_tiles, "path": "hipGraph, one view"},
+        "tile_lists": {("exact" if k else "rectangles"): {"ms_per_step": round(v, 4),
+                                                         "Mpixel_s": round(px_head / (v * 1e-3) / 1e6, 3),
+                                                         "pairs": pairs[k]} for k, v in ms_kind.items()},
         "eager_per_view": {"ms_per_step": round(ms_eager, 4),
                            "Mpixel_s": round(px_head / (ms_eager * 1e-3) / 1e6, 3)},
         "hbm": {"alg_bytes_per_step": int(step_bytes),

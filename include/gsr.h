@@ -306,14 +306,15 @@ gsr_status gsr_graph_info(const gsr_graph* gr, gsr_info* info, int64_t* cap_keys
 gsr_status gsr_graph_free(gsr_graph* gr);
 
 /* ---- Launch-shape autotuner -----------------------------------------------------------
- * Time forward + backward at every (tile, batch) in {8,16,32} x {128,256} and write the
- * fastest into s->tile / s->batch (other fields are kept).  Results are cached in the
+ * Time forward + backward at every (tile, batch, list kind) in {8,16,32} x {128,256} x
+ * {rectangles, GSR_EXACT_TILES} and write the fastest into s->tile / s->batch and the
+ * GSR_EXACT_TILES bit of s->flags (other fields and bits are kept).  Results are cached in the
  * text file named by $GSR_AUTOTUNE_CACHE (default ~/.cache/gsr_autotune.txt), keyed by
  * architecture, CU count, log2 of the total pixel count and of N, SH degree and V; a
  * cached entry is used without timing unless GSR_AUTOTUNE_NO_CACHE is set.  The forward
  * images do not depend on the choice (the extent keeps every splat value >= alpha_min
- * inside its tile rectangle).  Each shape is timed as the median of seven eager steps after
- * two warm-up steps.  best_ms (may be NULL) receives that median for the chosen shape. */
+ * inside its tile rectangle).  Each choice is timed as the median of seven eager steps after
+ * two warm-up steps, a step's time being the sum of its kernels' durations.  best_ms (may be NULL) receives that median for the chosen shape. */
 #define GSR_AUTOTUNE_NO_CACHE 1u
 gsr_status gsr_autotune(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
                         gsr_settings* s, uint32_t flags, float* best_ms);

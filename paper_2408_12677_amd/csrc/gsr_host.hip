@@ -938,7 +938,7 @@ static std::string autotune_key(int dev, const gsr_gaussians* g, const gsr_camer
   for (int v = 0; v < V; ++v) pix += int64_t(cams[v].width) * cams[v].height;
   std::ostringstream k;
   k << arch.substr(0, arch.find(':')) << "|cu" << cus << "|px" << bits_for(uint64_t(pix)) << "|n"
-    << bits_for(uint64_t(g->n)) << "|deg" << g->sh_degree << "|v" << V;
+    << bits_for(uint64_t(g->n)) << "|deg" << g->sh_degree << "|v" << V << "|x2";
   return k.str();
 }
 
@@ -966,11 +966,13 @@ gsr_status gsr_autotune(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* 
     while (std::getline(in, line)) {
       std::istringstream ls(line);
       std::string k;
-      int t = 0, b = 0;
+      int t = 0, b = 0, x = 0;
       float ms = 0.f;
-      if ((ls >> k >> t >> b >> ms) && k == key && (t == 8 || t == 16 || t == 32) && (b == 128 || b == 256)) {
+      if ((ls >> k >> t >> b >> x >> ms) && k == key && (t == 8 || t == 16 || t == 32) && (b == 128 || b == 256) &&
+          (x == 0 || x == 1)) {
         s->tile = t;
         s->batch = b;
+        s->flags = (s->flags & ~GSR_EXACT_TILES) | (x ? GSR_EXACT_TILES : 0u);
         if (best_ms) *best_ms = ms;
         return GSR_OK;
       }
@@ -1012,33 +1014,39 @@ gsr_status gsr_autotune(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* 
     return fail(ctx, GSR_ENOMEM, "autotune scratch allocation failed");
   }
   gsr_gaussian_grads gg{gbuf, gbuf + 3 * g->n, gbuf + 6 * g->n, gbuf + 10 * g->n, gbuf + 11 * g->n};
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
+  // each candidate is timed by the sum of its kernels' durations (the context's event
+  // timer), so the host-side gap of the eager forward's count read-back does not count
   const bool timer_was = ctx->timer.on;
-  ctx->timer.on = false;
+  ctx->timer.collect();
+  double saved_ms[K_COUNT];
+  long long saved_n[K_COUNT];
+  std::copy(ctx->timer.ms, ctx->timer.ms + K_COUNT, saved_ms);
+  std::copy(ctx->timer.launches, ctx->timer.launches + K_COUNT, saved_n);
+  ctx->timer.on = true;
   float best = 1e30f;
-  int bt = s->tile, bb = s->batch;
+  int bt = s->tile, bb = s->batch, bx = 0;
   const int tiles[3] = {8, 16, 32}, batches[2] = {128, 256};
+  for (int xi = 0; xi < 2 && st == GSR_OK; ++xi)
   for (int ti = 0; ti < 3 && st == GSR_OK; ++ti)
     for (int bi = 0; bi < 2 && st == GSR_OK; ++bi) {
       gsr_settings c = *s;
       c.tile = tiles[ti];
       c.batch = batches[bi];
+      c.flags = (s->flags & ~GSR_EXACT_TILES) | (xi ? GSR_EXACT_TILES : 0u);
       constexpr int kWarm = 2, kTimed = 7;  // the median of seven timed steps
       float times[kTimed];
       for (int rep = 0; rep < kWarm + kTimed && st == GSR_OK; ++rep) {
-        (void)hipEventRecord(e0, strm);
+        ctx->timer.reset();
         gsr_saved* sv = nullptr;
         st = forward_eager(ctx, g, cams, V, &c, outs.data(), &sv);
         if (st != GSR_OK) break;
         st = gsr_backward(ctx, sv, vg.data(), &gg, 0);
         release(sv);
-        (void)hipEventRecord(e1, strm);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (rep >= kWarm) times[rep - kWarm] = ms;
+        (void)hipStreamSynchronize(strm);
+        ctx->timer.collect();
+        double ms = 0.0;
+        for (int k = 0; k < K_COUNT; ++k) ms += ctx->timer.ms[k];
+        if (rep >= kWarm) times[rep - kWarm] = float(ms);
       }
       if (st != GSR_OK) break;
       std::sort(times, times + kTimed);
@@ -1046,19 +1054,21 @@ gsr_status gsr_autotune(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* 
         best = times[kTimed / 2];
         bt = c.tile;
         bb = c.batch;
+        bx = xi;
       }
     }
   ctx->timer.on = timer_was;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  std::copy(saved_ms, saved_ms + K_COUNT, ctx->timer.ms);
+  std::copy(saved_n, saved_n + K_COUNT, ctx->timer.launches);
   sfree();
   if (st != GSR_OK) return st;
   s->tile = bt;
   s->batch = bb;
+  s->flags = (s->flags & ~GSR_EXACT_TILES) | (bx ? GSR_EXACT_TILES : 0u);
   if (best_ms) *best_ms = best;
   if (use_cache) {
     std::ofstream o(path, std::ios::app);
-    if (o) o << key << " " << bt << " " << bb << " " << best << "\n";
+    if (o) o << key << " " << bt << " " << bb << " " << bx << " " << best << "\n";
   }
   return GSR_OK;
 }

@@ -831,8 +831,7 @@ __global__ __launch_bounds__(256) void k_bin_rows_count(ViewTable vt, int64_t n,
 // row lists
 __global__ __launch_bounds__(64) void k_bin_rows_scatter(ViewTable vt, int64_t n, Records rec, const uint32_t* dvals,
                                                          const unsigned long long* nvis, int64_t cap_vis,
-                                                         const uint32_t* overflow, BinPlan plan, float exact_k,
-                                                         int tile) {
+                                                         const uint32_t* overflow, BinPlan plan) {
   extern __shared__ uint32_t next[];  // next free slot of each row for this chunk
   const int R = plan.rows;
   const int lane = threadIdx.x;
@@ -848,23 +847,13 @@ __global__ __launch_bounds__(64) void k_bin_rows_scatter(ViewTable vt, int64_t n
     const int64_t i = r0 + lane;
     uint32_t cur = 0xFFFFFFFFu, hi = 0u;
     uint2 entry = make_uint2(0u, 0u);
-    int ro = 0, W = 0, H = 0;
-    float4 sp = make_float4(0.f, 0.f, 0.f, 0.f);  // splat centre and conic A, B
-    float cc = 0.f;
     if (i < NV) {
       const uint32_t rid = dvals[i];
       const uint2 rc = rec.rect[rid];
-      const ViewDev& cam = vt.v[view_of_record(vt, rid, n)];
-      ro = cam.row_off;
-      W = cam.W;
-      H = cam.H;
+      const int ro = vt.v[view_of_record(vt, rid, n)].row_off;
       cur = uint32_t(ro) + (rc.y & 0xFFFFu);
       hi = min(uint32_t(ro) + (rc.y >> 16), uint32_t(R - 1));
       entry = make_uint2(rid, rc.x);
-      if (exact_k > 0.f) {
-        sp = rec.r0[rid];
-        cc = rec.r1[rid].x;
-      }
     }
     for (uint32_t y = wave_min_u32(cur); y != 0xFFFFFFFFu; y = wave_min_u32(cur)) {
       const bool on = cur == y;
@@ -872,16 +861,7 @@ __global__ __launch_bounds__(64) void k_bin_rows_scatter(ViewTable vt, int64_t n
       const uint32_t base = next[y];
       if (on) {
         const uint32_t dst = base + uint32_t(__popcll(m & lt_mask));
-        if (exact_k > 0.f) {  // this row's columns only; an empty run is marked lo > hi
-          int lo, hi2;
-          const int tx0 = int(entry.y & 0xFFFFu), tx1 = int(entry.y >> 16);
-          const bool any = row_run(sp.x, sp.y, sp.z, sp.w, cc, exact_k, tile, int(y) - ro, W, H, tx0, tx1, lo, hi2);
-          const uint2 e = any ? make_uint2(entry.x, uint32_t(lo) | (uint32_t(hi2) << 16))
-                              : make_uint2(entry.x, 0xFFFFu);
-          if (int64_t(dst) < plan.cap_M) plan.rowlist[dst] = e;
-        } else if (int64_t(dst) < plan.cap_M) {
-          plan.rowlist[dst] = entry;
-        }
+        if (int64_t(dst) < plan.cap_M) plan.rowlist[dst] = entry;
         cur = cur < hi ? cur + 1u : 0xFFFFFFFFu;
       }
       if (lane == 0) next[y] = base + uint32_t(__popcll(m));
@@ -951,6 +931,7 @@ struct Segment {
   uint32_t flat;       // flat index of (column 0, this segment)
   uint32_t nseg;       // segments of the row (stride between columns)
   int tiles_x;
+  int row;             // global tile row
 };
 
 __device__ __forceinline__ Segment segment_of(const ViewTable& vt, const BinPlan& plan, uint32_t s) {
@@ -964,11 +945,16 @@ __device__ __forceinline__ Segment segment_of(const ViewTable& vt, const BinPlan
   g.end = min(info.x + info.y, g.beg + S2);
   g.flat = info.w + sidx;
   g.tiles_x = vt.v[view_of_row(vt, uint32_t(r))].tiles_x;
+  g.row = r;
   return g;
 }
 
-// stage 2 counts: tile-column histogram of one segment of a row list
-__global__ __launch_bounds__(256) void k_bin_tiles_count(ViewTable vt, BinPlan plan) {
+// stage 2 counts: tile-column histogram of one segment of a row list.  With exact tiles
+// (exact_k > 0) each entry's column run is first cut to the columns its ellipse reaches in
+// this row (row_run) and written back, so the placement below sees the same run; a row
+// the ellipse misses keeps an empty run (lo > hi).
+__global__ __launch_bounds__(256) void k_bin_tiles_count(ViewTable vt, BinPlan plan, Records rec, float exact_k,
+                                                         int tile) {
   extern __shared__ uint32_t hist[];
   const unsigned long long S = plan.words[1];
   for (uint32_t s = blockIdx.x; s < S; s += gridDim.x) {
@@ -976,7 +962,18 @@ __global__ __launch_bounds__(256) void k_bin_tiles_count(ViewTable vt, BinPlan p
     for (int i = threadIdx.x; i < g.tiles_x; i += 256) hist[i] = 0;
     __syncthreads();
     for (uint32_t i = g.beg + threadIdx.x; i < g.end; i += 256) {
-      const uint32_t cx = plan.rowlist[i].y;
+      uint32_t cx = plan.rowlist[i].y;
+      if (exact_k > 0.f) {
+        const uint32_t rid = plan.rowlist[i].x;
+        const ViewDev& cam = vt.v[view_of_row(vt, uint32_t(g.row))];
+        const float4 sp = rec.r0[rid];  // centre and conic A, B
+        const float cc = rec.r1[rid].x;
+        int lo, hi;
+        const bool any = row_run(sp.x, sp.y, sp.z, sp.w, cc, exact_k, tile, g.row - cam.row_off, cam.W, cam.H,
+                                 int(cx & 0xFFFFu), int(cx >> 16), lo, hi);
+        cx = any ? uint32_t(lo) | (uint32_t(hi) << 16) : 0xFFFFu;
+        plan.rowlist[i].y = cx;
+      }
       const int x0 = int(cx & 0xFFFFu), x1 = min(int(cx >> 16), g.tiles_x - 1);
       for (int x = x0; x <= x1; ++x) atomicAdd(&hist[x], 1u);
     }
@@ -1841,11 +1838,10 @@ hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const 
   k_bin_rows_meta<<<1, 1024, 0, s>>>(vt, plan, overflow);
   E(K_BIN_SCAN);
   B(K_BIN_SCATTER);
-  k_bin_rows_scatter<<<plan.nch1, 64, lds_rows, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan, exact_k,
-                                                      tile);
+  k_bin_rows_scatter<<<plan.nch1, 64, lds_rows, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
   E(K_BIN_SCATTER);
   B(K_BIN_COUNT);
-  k_bin_tiles_count<<<g_count, 256, lds_cols, s>>>(vt, plan);
+  k_bin_tiles_count<<<g_count, 256, lds_cols, s>>>(vt, plan, rec, exact_k, tile);
   E(K_BIN_COUNT);
   B(K_BIN_SCAN);
   scan_u32(plan.cntF, plan.cap_flat, plan.words + 2, plan.part, plan.words + 3, s);
@@ -1864,9 +1860,11 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
   return hipGetLastError();
 }
 
-// Persistent grid: as many blocks as fit on the device at once, at most one per tile.
+// Persistent grid: blocks resident at once, at most `cap_per_cu` per compute unit (the
+// compositing kernels ran fastest below full occupancy on the headline view: blend_fwd at
+// 4 and blend_bwd at 5 blocks per CU, against 6 and more that fit).
 template <class Kern>
-static int resident_blocks(Kern kern, int threads) {
+static int resident_blocks(Kern kern, int threads, int cap_per_cu) {
   static int cached = -1;
   if (cached < 0) {
     int per_cu = 0, cus = 0, dev = 0;
@@ -1875,16 +1873,18 @@ static int resident_blocks(Kern kern, int threads) {
       per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
     (void)hipGetLastError();
-    cached = per_cu * cus;
+    cached = std::min(per_cu, cap_per_cu) * cus;
   }
   return cached;
 }
+constexpr int kFwdBlocksPerCU = 4;
+constexpr int kBwdBlocksPerCU = 5;
 
 template <int TS, int BATCH>
 static void blend_fwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
                         const uint32_t* vals, float* T_final, uint32_t* n_contrib, uint32_t* n_used,
                         const TileQueue& q, const Ckpt& ck, hipStream_t s) {
-  const int grid = std::min(vt.total_tiles, resident_blocks(k_blend_fwd<TS, BATCH>, TS * TS));
+  const int grid = std::min(vt.total_tiles, resident_blocks(k_blend_fwd<TS, BATCH>, TS * TS, kFwdBlocksPerCU));
   k_blend_fwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck);
 }
 
@@ -1933,7 +1933,8 @@ template <int TS, int BATCH>
 static void blend_bwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
                         const uint32_t* vals, const float* T_final, const uint32_t* n_contrib, float* grad2d,
                         const TileQueue& q, const Ckpt& ck, hipStream_t s) {
-  const int grid = int(std::min<int64_t>(ck.cap_items, resident_blocks(k_blend_bwd<TS, BATCH>, TS * TS)));
+  const int grid =
+      int(std::min<int64_t>(ck.cap_items, resident_blocks(k_blend_bwd<TS, BATCH>, TS * TS, kBwdBlocksPerCU)));
   k_blend_bwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck);
 }
 

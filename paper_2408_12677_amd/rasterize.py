@@ -403,8 +403,8 @@ class Graph:
 
 def autotune(means, scales, quats, opacities, sh, cameras, settings: Settings | None = None,
              use_cache: bool = True):
-    """Pick (tile, batch) for this workload by timing forward + backward at every launch
-    shape (or from the cache).  Returns (settings with tile/batch set, step ms)."""
+    """Pick (tile, batch, exact tile lists or not) for this workload by timing forward +
+    backward at every choice (or from the cache).  Returns (settings, step ms)."""
     import dataclasses
     settings = settings or Settings()
     dev, n, deg = _param_checks(means, scales, quats, opacities, sh)
@@ -415,7 +415,8 @@ def autotune(means, scales, quats, opacities, sh, cameras, settings: Settings | 
     ms = ctypes.c_float()
     N.check(ctx.lib.gsr_autotune(ctx.h, ctypes.byref(g), _cams(cameras), len(cameras), ctypes.byref(s),
                                  0 if use_cache else N.AUTOTUNE_NO_CACHE, ctypes.byref(ms)), ctx.h)
-    return dataclasses.replace(settings, tile=int(s.tile), batch=int(s.batch)), float(ms.value)
+    return (dataclasses.replace(settings, tile=int(s.tile), batch=int(s.batch),
+                                exact_tiles=bool(s.flags & N.EXACT_TILES)), float(ms.value))
 
 
 def seed(rgb, depth, camera, measure: str = "contrast", threshold: float = 0.1, min_side: int = 4,
