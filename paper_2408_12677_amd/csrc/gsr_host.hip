@@ -1186,7 +1186,6 @@ gsr_status gsr_tsdf_create(gsr_ctx* ctx, const gsr_tsdf_settings* s, int64_t max
   get(reinterpret_cast<void**>(&d.tsdf), vox * 4);
   get(reinterpret_cast<void**>(&d.weight), vox * 4);
   get(reinterpret_cast<void**>(&d.coords), size_t(max_blocks) * sizeof(int4));
-  get(reinterpret_cast<void**>(&d.met), size_t(max_blocks) * 4);
   get(reinterpret_cast<void**>(&d.ctrl), TSDF_CTRL_WORDS * 4);
   if (st != GSR_OK) {
     tsdf_release(m);
@@ -1229,7 +1228,7 @@ gsr_status gsr_tsdf_integrate(gsr_ctx* ctx, gsr_tsdf* m, const gsr_camera* cam, 
   c.H = cam->height;
   hipStream_t strm = ctx->stream;
   GSR_HIP(ctx, timed(ctx, strm, K_TSDF_ALLOC, [&] { return launch_tsdf_alloc(depth, c, m->dev, m->ru, m->frame, strm); }));
-  GSR_HIP(ctx, timed(ctx, strm, K_TSDF_FUSE, [&] { return launch_tsdf_fuse(depth, c, m->dev, m->ru, strm); }));
+  GSR_HIP(ctx, timed(ctx, strm, K_TSDF_FUSE, [&] { return launch_tsdf_fuse(depth, c, m->dev, m->ru, m->frame, strm); }));
   ++m->frame;
   if (m->frame == 0xFFFFFFFFu) m->frame = 0;  // never the value that marks an unstamped slot
   return GSR_OK;

@@ -306,12 +306,12 @@ hipError_t launch_project_bwd(int deg, const GaussDev& g, const ViewTable& vt, c
 
 // ---- TSDF fusion (gsr_tsdf.hip) -----------------------------------------------------
 int tsdf_band_samples(float eps, float step);
-// Band allocation of one depth frame [H, W] and the pool assignment / met-block list.
+// Band allocation of one depth frame [H, W] (blocks stamped with the frame) and pool assignment.
 hipError_t launch_tsdf_alloc(const float* depth, const TsdfCam& cam, const TsdfDev& m, const TsdfRules& ru,
                              uint32_t frame, hipStream_t s);
 // Eq. 6-9 for every voxel of the blocks the frame met.
 hipError_t launch_tsdf_fuse(const float* depth, const TsdfCam& cam, const TsdfDev& m, const TsdfRules& ru,
-                            hipStream_t s);
+                            uint32_t frame, hipStream_t s);
 // out[i] = weight of the voxel holding pts[i] (0 where unallocated).
 hipError_t launch_tsdf_weights(const TsdfDev& m, const float* pts, int64_t n, float* out, hipStream_t s);
 

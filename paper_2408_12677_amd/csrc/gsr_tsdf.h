@@ -45,7 +45,6 @@ struct TsdfDev {
   float* tsdf;               // [cap_blocks * 512]
   float* weight;             // [cap_blocks * 512]
   int4* coords;              // [cap_blocks] block coordinates
-  uint32_t* met;             // [cap_blocks] pool indices of the blocks met by the current frame
   uint32_t* ctrl;            // TSDF_* words
   uint32_t slot_mask;        // slots - 1 (a power of two)
   uint32_t cap_blocks;

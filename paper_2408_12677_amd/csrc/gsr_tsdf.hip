@@ -5,11 +5,11 @@
 //                     read before any compare-and-swap, so the common case of a block
 //                     already present costs one load); stamp the block's slot with the frame
 //   k_tsdf_assign     one thread per table slot: give new keys a pool index (one counter
-//                     atomic per new block, no thread waits on another) and list the blocks
-//                     stamped with this frame
-//   k_tsdf_integrate  one 512-thread block per listed map block, one thread per voxel:
-//                     project the voxel centre, read the nearest pixel's depth, and apply
-//                     Eq. 6-9 to the voxel's distance and weight (coalesced, HBM bound)
+//                     atomic per wavefront with new keys, no thread waits on another)
+//   k_tsdf_integrate  a 512-thread block per 512 table slots, one thread per voxel of
+//                     each map block stamped with this frame: project the voxel centre, read
+//                     the nearest pixel's depth, and apply Eq. 6-9 to the voxel's distance
+//                     and weight (coalesced, HBM bound)
 //   k_tsdf_weights    the weight of the voxel holding each query point (seeding check)
 //
 // The block of a sample and the pixel of a voxel are integer decisions taken from
@@ -25,7 +25,6 @@ namespace gsr {
 namespace {
 
 constexpr int kAllocThreads = 256;
-constexpr int kIntegrateGrid = 2048;  // persistent blocks of k_tsdf_integrate
 
 // Inserts `key` (or finds it) and stamps its slot with the frame.
 __device__ inline void insert_block(const TsdfDev& m, unsigned long long key, uint32_t frame) {
@@ -89,35 +88,63 @@ __device__ inline uint32_t wave_reserve(uint32_t* counter, uint64_t mask, bool m
   return mine ? base + uint32_t(__popcll(mask & ((1ull << lane) - 1ull))) : 0u;
 }
 
-__global__ __launch_bounds__(256) void k_tsdf_assign(TsdfDev m, uint32_t frame) {
+__global__ __launch_bounds__(256) void k_tsdf_assign(TsdfDev m) {
   const uint32_t h = blockIdx.x * 256u + threadIdx.x;  // the grid covers the slots exactly
   const unsigned long long key = h <= m.slot_mask ? m.keys[h] : kEmptyKey;
-  uint32_t b = key != kEmptyKey ? m.vals[h] : kUnassigned;
-  const bool fresh = key != kEmptyKey && b == kUnassigned;
+  const bool fresh = key != kEmptyKey && m.vals[h] == kUnassigned;
   const uint32_t nb = wave_reserve(&m.ctrl[TSDF_ALLOCATED], __ballot(fresh), fresh);
-  if (fresh) {
-    if (nb < m.cap_blocks) {
-      b = nb;
-      m.vals[h] = b;
-      m.coords[b] = unpack_block(key);
-    } else {
-      atomicOr(&m.ctrl[TSDF_FLAGS], TSDF_POOL_FULL);
-    }
+  if (!fresh) return;
+  if (nb < m.cap_blocks) {
+    m.vals[h] = nb;
+    m.coords[nb] = unpack_block(key);
+  } else {
+    atomicOr(&m.ctrl[TSDF_FLAGS], TSDF_POOL_FULL);
   }
-  const bool met = b != kUnassigned && m.stamp[h] == frame;
-  const uint32_t at = wave_reserve(&m.ctrl[TSDF_MET], __ballot(met), met);
-  if (met) m.met[at] = b;
 }
 
+// One 512-thread block per 512 table slots: every thread reads its slot's stamp
+// and pool index, the block gathers the slots stamped with this frame into LDS (ballot
+// ranks and a prefix over the eight wavefronts) with their coordinates, then every thread
+// updates its voxel of
+// each gathered block.  The number of met blocks is added once per block.
+constexpr int kSlotsPerBlock = 512;
+
 __global__ __launch_bounds__(kBlockVoxels) void k_tsdf_integrate(const float* depth, TsdfCam cam, TsdfDev m,
-                                                                 TsdfRules ru) {
+                                                                 TsdfRules ru, uint32_t frame) {
 #pragma clang fp contract(off)
-  const uint32_t n_met = min(m.ctrl[TSDF_MET], m.cap_blocks);
+  __shared__ uint32_t s_blk[kSlotsPerBlock];
+  __shared__ int4 s_crd[kSlotsPerBlock];
+  __shared__ uint32_t s_cnt[kSlotsPerBlock / 64];
   const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  const uint32_t h = blockIdx.x * uint32_t(kSlotsPerBlock) + uint32_t(t);
+  bool met = false;
+  uint32_t b = kUnassigned;
+  if (t < kSlotsPerBlock && h <= m.slot_mask && m.stamp[h] == frame) {
+    b = m.vals[h];
+    met = b < m.cap_blocks;  // a block without a pool index (pool full) is skipped
+  }
+  const uint64_t mask = __ballot(met);
+  if (t < kSlotsPerBlock && lane == 0) s_cnt[wv] = uint32_t(__popcll(mask));
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+#pragma unroll
+  for (int i = 0; i < kSlotsPerBlock / 64; ++i) {
+    before += i < wv ? s_cnt[i] : 0u;
+    total += s_cnt[i];
+  }
+  if (met) {
+    const uint32_t at = before + uint32_t(__popcll(mask & ((1ull << lane) - 1ull)));
+    s_blk[at] = b;
+    s_crd[at] = m.coords[b];
+  }
+  __syncthreads();
   const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
-  for (uint32_t i = blockIdx.x; i < n_met; i += gridDim.x) {
-    const uint32_t b = m.met[i];
-    const int4 c = m.coords[b];
+  for (uint32_t i = 0; i < total; ++i) {
+    const uint32_t blk = s_blk[i];
+    const int4 c = s_crd[i];
+    const size_t idx = size_t(blk) * kBlockVoxels + t;
+    const float w = m.weight[idx], tv = m.tsdf[idx];  // in flight with the depth read below
     // voxel centre ((g + 0.5) voxel), then the camera point R p + t (sums left to right)
     const float px = (float(c.x * kBlockSide + lx) + 0.5f) * m.voxel;
     const float py = (float(c.y * kBlockSide + ly) + 0.5f) * m.voxel;
@@ -134,13 +161,12 @@ __global__ __launch_bounds__(kBlockVoxels) void k_tsdf_integrate(const float* de
     const float sdf = D - z;                                                    // Eq. 6
     const float q = sdf / ru.eps;
     const float tsdf = sdf > 0.f ? fminf(1.f, q) : fmaxf(-1.f, q);               // Eq. 7
-    const size_t idx = size_t(b) * kBlockVoxels + t;
-    const float w = m.weight[idx], tv = m.tsdf[idx];
     const float wn = fminf(ru.w_max, w + 1.f);                                  // Eq. 8
     m.tsdf[idx] = ru.unit_weight ? (tv * w + tsdf) / (w + 1.f)                   // running average
                                  : (tv * w + tsdf * wn) / (w + wn);               // Eq. 9
     m.weight[idx] = wn;
   }
+  if (t == 0 && total) atomicAdd(&m.ctrl[TSDF_MET], total);
 }
 
 __global__ __launch_bounds__(256) void k_tsdf_weights(TsdfDev m, const float* pts, int64_t n, float* out) {
@@ -165,13 +191,14 @@ hipError_t launch_tsdf_alloc(const float* depth, const TsdfCam& cam, const TsdfD
   const int64_t P = int64_t(cam.W) * cam.H;
   if (P > 0) k_tsdf_alloc<<<unsigned((P + kAllocThreads - 1) / kAllocThreads), kAllocThreads, 0, s>>>(depth, cam, m,
                                                                                                     ru, frame);
-  k_tsdf_assign<<<unsigned((uint64_t(m.slot_mask) + 256) / 256), 256, 0, s>>>(m, frame);
+  k_tsdf_assign<<<unsigned((uint64_t(m.slot_mask) + 256) / 256), 256, 0, s>>>(m);
   return hipGetLastError();
 }
 
 hipError_t launch_tsdf_fuse(const float* depth, const TsdfCam& cam, const TsdfDev& m, const TsdfRules& ru,
-                            hipStream_t s) {
-  k_tsdf_integrate<<<kIntegrateGrid, kBlockVoxels, 0, s>>>(depth, cam, m, ru);
+                            uint32_t frame, hipStream_t s) {
+  k_tsdf_integrate<<<unsigned((uint64_t(m.slot_mask) + kSlotsPerBlock) / kSlotsPerBlock), kBlockVoxels, 0, s>>>(
+      depth, cam, m, ru, frame);
   return hipGetLastError();
 }
 
