@@ -32,9 +32,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = ("paper_2408_12677_amd/csrc/gsr_kernels.hip", "paper_2408_12677_amd/csrc/gsr_internal.h",
-                  "paper_2408_12677_amd/csrc/gsr_optim.hip", "paper_2408_12677_amd/csrc/gsr_adam.h",
-                  "paper_2408_12677_amd/csrc/gsr_tsdf.hip", "paper_2408_12677_amd/csrc/gsr_tsdf.h")
+CSRC = "paper_2408_12677_amd/csrc/"
+KERNEL_HEADERS = ("gsr_internal.h", "gsr_adam.h", "gsr_tsdf.h")
+
+
+def kernel_source(name):
+    """The source file that holds kernel ``name`` (short name, as short_kernel_name gives)."""
+    if name.startswith("tsdf"):
+        return "gsr_tsdf.hip"
+    if name.startswith("adam"):
+        return "gsr_optim.hip"
+    if name.startswith("seed"):
+        return "gsr_seed.hip"
+    return "gsr_kernels.hip"
 HEADLINE_VIEW = 2              # first 640x480 view of the 8-view orbit
 DEPTH_W = 0.1
 
@@ -79,11 +89,12 @@ def kernel_bytes(name, st):
 # ------------------------------------------------------------------------------------
 # measured HBM traffic (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated by a plain copy)
 # ------------------------------------------------------------------------------------
-def kernels_sha():
-    """Digest of the kernel sources; stored traffic is only reported for the same sources."""
+def kernels_sha(name="blend_bwd"):
+    """Digest of the sources of kernel ``name`` (its file and the internal headers); stored
+    traffic is only reported for the same sources."""
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
+    for rel in (kernel_source(name),) + KERNEL_HEADERS:
+        with open(os.path.join(ROOT, CSRC, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -123,8 +134,8 @@ def traffic_from_counters(fetch_dir, write_dir, copy_mb):
         fv, wv = fetch[k], write.get(k, [0.0])
         name = short_kernel_name(k)
         kernels[name] = dict(dispatches=len(fv), fetch_bytes=round(ff * sum(fv) / len(fv)),
-                             write_bytes=round(fw * sum(wv) / len(wv)))
-    return dict(kernels_sha=kernels_sha(), copy_kernel=ck, copy_bytes=copy_bytes,
+                             write_bytes=round(fw * sum(wv) / len(wv)), sources_sha=kernels_sha(name))
+    return dict(copy_kernel=ck, copy_bytes=copy_bytes,
                 fetch_factor=round(ff, 5), write_factor=round(fw, 5), kernels=kernels)
 
 
@@ -137,7 +148,7 @@ def stored_traffic(name):
     except (OSError, ValueError):
         return None
     k = t.get("kernels", {}).get(name)
-    if k is None or t.get("kernels_sha") != kernels_sha():
+    if k is None or k.get("sources_sha") != kernels_sha(name):
         return None
     return int(k["fetch_bytes"] + k["write_bytes"])
 
