@@ -297,7 +297,8 @@ gsr_status alloc_sort(gsr_saved* sv, int64_t cap_vis, int64_t cap_M, bool persis
   if ((st = alloc_in(sv, T, &sv->dk, cap_vis)) != GSR_OK || (st = alloc_in(sv, T, &sv->dv, cap_vis)) != GSR_OK ||
       (st = alloc_in(sv, T, &sv->dk2, cap_vis)) != GSR_OK || (st = alloc_in(sv, T, &sv->dv2, cap_vis)) != GSR_OK ||
       (st = alloc_in(sv, T, &sv->hist, size_t(nb_sort) * 256)) != GSR_OK ||
-      (st = alloc_in(sv, T, &sv->dtot, 256)) != GSR_OK || (st = alloc_in(sv, sv->blocks, &sv->vals, cap_M)) != GSR_OK ||
+      (st = alloc_in(sv, T, &sv->dtot, 256)) != GSR_OK ||
+      (st = alloc_in(sv, sv->blocks, &sv->vals, cap_M)) != GSR_OK ||
       (st = alloc_in(sv, T, &p.cnt1, size_t(n1))) != GSR_OK || (st = alloc_in(sv, T, &p.rowlist, cap_M)) != GSR_OK ||
       (st = alloc_in(sv, T, &p.rowinfo, size_t(p.rows))) != GSR_OK ||
       (st = alloc_in(sv, T, &p.seg_start, size_t(p.rows) + 1)) != GSR_OK ||
@@ -1023,40 +1024,59 @@ gsr_status gsr_autotune(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* 
   std::copy(ctx->timer.ms, ctx->timer.ms + K_COUNT, saved_ms);
   std::copy(ctx->timer.launches, ctx->timer.launches + K_COUNT, saved_n);
   ctx->timer.on = true;
+  // candidates: every (list kind, tile, batch); after two warm-up steps each, the
+  // candidates take turns, one step per turn, so slow drift of the clocks or of the
+  // memory system reaches all of them alike; each is scored by its median step
+  struct Cand {
+    gsr_settings c;
+    int xi;
+  };
+  std::vector<Cand> cands;
+  const int tiles[3] = {8, 16, 32}, batches[2] = {128, 256};
+  for (int xi = 0; xi < 2; ++xi)
+    for (int ti = 0; ti < 3; ++ti)
+      for (int bi = 0; bi < 2; ++bi) {
+        gsr_settings c = *s;
+        c.tile = tiles[ti];
+        c.batch = batches[bi];
+        c.flags = (s->flags & ~GSR_EXACT_TILES) | (xi ? GSR_EXACT_TILES : 0u);
+        cands.push_back({c, xi});
+      }
+  constexpr int kWarm = 2, kTimed = 9;
+  std::vector<float> times(cands.size() * kTimed);
+  auto one_step = [&](const gsr_settings& c, float* ms_out) -> gsr_status {
+    ctx->timer.reset();
+    gsr_saved* sv = nullptr;
+    gsr_status r = forward_eager(ctx, g, cams, V, &c, outs.data(), &sv);
+    if (r != GSR_OK) return r;
+    r = gsr_backward(ctx, sv, vg.data(), &gg, 0);
+    release(sv);
+    (void)hipStreamSynchronize(strm);
+    ctx->timer.collect();
+    double ms = 0.0;
+    for (int k = 0; k < K_COUNT; ++k) ms += ctx->timer.ms[k];
+    *ms_out = float(ms);
+    return r;
+  };
+  for (size_t i = 0; i < cands.size() && st == GSR_OK; ++i)
+    for (int rep = 0; rep < kWarm && st == GSR_OK; ++rep) {
+      float ms;
+      st = one_step(cands[i].c, &ms);
+    }
+  for (int rep = 0; rep < kTimed && st == GSR_OK; ++rep)
+    for (size_t i = 0; i < cands.size() && st == GSR_OK; ++i) st = one_step(cands[i].c, &times[i * kTimed + rep]);
   float best = 1e30f;
   int bt = s->tile, bb = s->batch, bx = 0;
-  const int tiles[3] = {8, 16, 32}, batches[2] = {128, 256};
-  for (int xi = 0; xi < 2 && st == GSR_OK; ++xi)
-  for (int ti = 0; ti < 3 && st == GSR_OK; ++ti)
-    for (int bi = 0; bi < 2 && st == GSR_OK; ++bi) {
-      gsr_settings c = *s;
-      c.tile = tiles[ti];
-      c.batch = batches[bi];
-      c.flags = (s->flags & ~GSR_EXACT_TILES) | (xi ? GSR_EXACT_TILES : 0u);
-      constexpr int kWarm = 2, kTimed = 7;  // the median of seven timed steps
-      float times[kTimed];
-      for (int rep = 0; rep < kWarm + kTimed && st == GSR_OK; ++rep) {
-        ctx->timer.reset();
-        gsr_saved* sv = nullptr;
-        st = forward_eager(ctx, g, cams, V, &c, outs.data(), &sv);
-        if (st != GSR_OK) break;
-        st = gsr_backward(ctx, sv, vg.data(), &gg, 0);
-        release(sv);
-        (void)hipStreamSynchronize(strm);
-        ctx->timer.collect();
-        double ms = 0.0;
-        for (int k = 0; k < K_COUNT; ++k) ms += ctx->timer.ms[k];
-        if (rep >= kWarm) times[rep - kWarm] = float(ms);
-      }
-      if (st != GSR_OK) break;
-      std::sort(times, times + kTimed);
-      if (times[kTimed / 2] < best) {
-        best = times[kTimed / 2];
-        bt = c.tile;
-        bb = c.batch;
-        bx = xi;
-      }
+  for (size_t i = 0; i < cands.size() && st == GSR_OK; ++i) {
+    float* t = &times[i * kTimed];
+    std::sort(t, t + kTimed);
+    if (t[kTimed / 2] < best) {
+      best = t[kTimed / 2];
+      bt = cands[i].c.tile;
+      bb = cands[i].c.batch;
+      bx = cands[i].xi;
     }
+  }
   ctx->timer.on = timer_was;
   std::copy(saved_ms, saved_ms + K_COUNT, ctx->timer.ms);
   std::copy(saved_n, saved_n + K_COUNT, ctx->timer.launches);
