@@ -106,6 +106,15 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   return min(min(a, b), min(c, d));
 }
 
+// A VALU copy of v.  Registers read by readlane inside a loop that also stores to
+// global memory are copied once after their load, so the loop does not wait for its own
+// stores (memory counter) before each readlane.
+__device__ __forceinline__ uint32_t valu_copy(uint32_t v) {
+  uint32_t r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+  return r;
+}
+
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   for (int off = 32; off > 0; off >>= 1) v = max(v, uint32_t(__shfl_xor(v, off)));
   return v;
@@ -869,6 +878,64 @@ __global__ __launch_bounds__(64) void k_bin_rows_scatter(ViewTable vt, int64_t n
   }
 }
 
+// The same placement with the rows' next free slots in registers (row lane + 64 k in
+// register k of that lane, read with readlane) for at most 64 * NREG rows: each round
+// walks the rows from the wavefront's lowest to its highest with one ballot per row.
+template <int NREG>
+__global__ __launch_bounds__(64) void k_bin_rows_scatter_r(ViewTable vt, int64_t n, Records rec,
+                                                           const uint32_t* dvals, const unsigned long long* nvis,
+                                                           int64_t cap_vis, const uint32_t* overflow, BinPlan plan) {
+  const int R = plan.rows;
+  const int lane = threadIdx.x;
+  const int64_t NV = clamp_count(nvis, cap_vis, overflow);
+  const int64_t beg = int64_t(blockIdx.x) * 64 * plan.rounds1;
+  if (beg >= NV) return;
+  uint32_t nx[NREG];
+#pragma unroll
+  for (int k = 0; k < NREG; ++k) {
+    const int y = lane + 64 * k;
+    nx[k] = valu_copy(y < R ? plan.cnt1[int64_t(y) * plan.nch1 + blockIdx.x] : 0u);
+  }
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  for (int r = 0; r < plan.rounds1; ++r) {
+    const int64_t r0 = beg + int64_t(r) * 64;
+    if (r0 >= NV) break;
+    const int64_t i = r0 + lane;
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    uint2 entry = make_uint2(0u, 0u);
+    if (i < NV) {
+      const uint32_t rid = dvals[i];
+      const uint2 rc = rec.rect[rid];
+      const int ro = vt.v[view_of_record(vt, rid, n)].row_off;
+      lo = uint32_t(ro) + (rc.y & 0xFFFFu);
+      hi = min(uint32_t(ro) + (rc.y >> 16), uint32_t(R - 1));
+      if (lo > hi) lo = 0xFFFFFFFFu;
+      entry = make_uint2(rid, rc.x);
+    }
+    const uint32_t y0 = wave_min_u32(lo);
+    if (y0 == 0xFFFFFFFFu) continue;
+    const uint32_t y1 = uint32_t(__builtin_amdgcn_readfirstlane(int(wave_max_u32(lo != 0xFFFFFFFFu ? hi : 0u))));
+    for (uint32_t y = y0; y <= y1; ++y) {
+      const bool on = lo <= y && y <= hi;
+      const uint64_t m = __ballot(on);
+      if (!m) continue;
+      const int src = int(y & 63u), ky = int(y >> 6);
+      uint32_t base = 0;
+#pragma unroll
+      for (int k = 0; k < NREG; ++k)
+        if (k == ky) base = uint32_t(__builtin_amdgcn_readlane(int(nx[k]), src));
+      if (on) {
+        const uint32_t dst = base + uint32_t(__popcll(m & lt_mask));
+        if (int64_t(dst) < plan.cap_M) plan.rowlist[dst] = entry;
+      }
+      const uint32_t c = uint32_t(__popcll(m));
+#pragma unroll
+      for (int k = 0; k < NREG; ++k)
+        if (k == ky && lane == src) nx[k] += c;
+    }
+  }
+}
+
 // Per row: list start and length, its segments and its first flat (tile, segment) index;
 // totals of segments and of the flat array.  One block of 1024 threads.
 __global__ __launch_bounds__(1024) void k_bin_rows_meta(ViewTable vt, BinPlan plan, uint32_t* overflow) {
@@ -1014,6 +1081,56 @@ __global__ __launch_bounds__(64) void k_bin_tiles_scatter(ViewTable vt, BinPlan 
           cur = cur < hi ? cur + 1u : 0xFFFFFFFFu;
         }
         if (lane == 0) next[x] = base + uint32_t(__popcll(m));
+      }
+    }
+  }
+}
+
+// The same placement with the tiles' next free slots in registers (column lane + 64 k
+// in register k of that lane) for rows of at most 64 * NREG tiles.
+template <int NREG>
+__global__ __launch_bounds__(64) void k_bin_tiles_scatter_r(ViewTable vt, BinPlan plan, uint32_t* vals) {
+  const int lane = threadIdx.x;
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  const unsigned long long S = plan.words[1];
+  for (uint32_t s = blockIdx.x; s < S; s += gridDim.x) {
+    const Segment g = segment_of(vt, plan, s);
+    uint32_t nx[NREG];
+#pragma unroll
+    for (int k = 0; k < NREG; ++k) {
+      const int x = lane + 64 * k;
+      nx[k] = valu_copy(x < g.tiles_x ? plan.cntF[g.flat + uint32_t(x) * g.nseg] : 0u);
+    }
+    for (uint32_t r0 = g.beg; r0 < g.end; r0 += 64) {
+      const uint32_t i = r0 + uint32_t(lane);
+      uint32_t lo = 0xFFFFFFFFu, hi = 0u, rid = 0u;
+      if (i < g.end) {
+        const uint2 e = plan.rowlist[i];
+        rid = e.x;
+        lo = e.y & 0xFFFFu;
+        hi = min(e.y >> 16, uint32_t(g.tiles_x - 1));
+        if (lo > hi) lo = 0xFFFFFFFFu;  // a row the ellipse does not reach
+      }
+      const uint32_t x0 = wave_min_u32(lo);
+      if (x0 == 0xFFFFFFFFu) continue;
+      const uint32_t x1 = uint32_t(__builtin_amdgcn_readfirstlane(int(wave_max_u32(lo != 0xFFFFFFFFu ? hi : 0u))));
+      for (uint32_t x = x0; x <= x1; ++x) {
+        const bool on = lo <= x && x <= hi;
+        const uint64_t m = __ballot(on);
+        if (!m) continue;
+        const int src = int(x & 63u), kx = int(x >> 6);
+        uint32_t base = 0;
+#pragma unroll
+        for (int k = 0; k < NREG; ++k)
+          if (k == kx) base = uint32_t(__builtin_amdgcn_readlane(int(nx[k]), src));
+        if (on) {
+          const uint32_t dst = base + uint32_t(__popcll(m & lt_mask));
+          if (int64_t(dst) < plan.cap_M) vals[dst] = rid;
+        }
+        const uint32_t c = uint32_t(__popcll(m));
+#pragma unroll
+        for (int k = 0; k < NREG; ++k)
+          if (k == kx && lane == src) nx[k] += c;
       }
     }
   }
@@ -1838,7 +1955,14 @@ hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const 
   k_bin_rows_meta<<<1, 1024, 0, s>>>(vt, plan, overflow);
   E(K_BIN_SCAN);
   B(K_BIN_SCATTER);
-  k_bin_rows_scatter<<<plan.nch1, 64, lds_rows, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
+  if (plan.rows <= 64)
+    k_bin_rows_scatter_r<1><<<plan.nch1, 64, 0, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
+  else if (plan.rows <= 128)
+    k_bin_rows_scatter_r<2><<<plan.nch1, 64, 0, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
+  else if (plan.rows <= 256)
+    k_bin_rows_scatter_r<4><<<plan.nch1, 64, 0, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
+  else
+    k_bin_rows_scatter<<<plan.nch1, 64, lds_rows, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
   E(K_BIN_SCATTER);
   B(K_BIN_COUNT);
   k_bin_tiles_count<<<g_count, 256, lds_cols, s>>>(vt, plan, rec, exact_k, tile);
@@ -1847,7 +1971,14 @@ hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const 
   scan_u32(plan.cntF, plan.cap_flat, plan.words + 2, plan.part, plan.words + 3, s);
   E(K_BIN_SCAN);
   B(K_BIN_SCATTER);
-  k_bin_tiles_scatter<<<g_scatter, 64, lds_cols, s>>>(vt, plan, vals);
+  if (vt.max_tiles_x <= 64)
+    k_bin_tiles_scatter_r<1><<<g_scatter, 64, 0, s>>>(vt, plan, vals);
+  else if (vt.max_tiles_x <= 128)
+    k_bin_tiles_scatter_r<2><<<g_scatter, 64, 0, s>>>(vt, plan, vals);
+  else if (vt.max_tiles_x <= 256)
+    k_bin_tiles_scatter_r<4><<<g_scatter, 64, 0, s>>>(vt, plan, vals);
+  else
+    k_bin_tiles_scatter<<<g_scatter, 64, lds_cols, s>>>(vt, plan, vals);
   E(K_BIN_SCATTER);
   B(K_RANGES);
   k_bin_ranges<<<blocks_for(vt.total_tiles, 256), 256, 0, s>>>(vt, plan, overflow, ranges);
