@@ -25,7 +25,18 @@ struct gsr_ctx {
   Timer timer;
   void* bwd_scratch = nullptr;  // the eager backward's 2D-gradient rows, kept between calls (grow-only)
   size_t bwd_scratch_bytes = 0;
+  // Per tile grid (tile size and view sizes), the last eager forward's longest
+  // contributor count of every tile: the next forward over the same tiles orders its tile
+  // queue by it.  Scheduling only; results do not depend on it.
+  struct WorkHint {
+    std::vector<int> grid;
+    uint32_t* tiles = nullptr;
+    int64_t count = 0;
+  };
+  std::vector<WorkHint> hints;
+  size_t next_hint = 0;  // the entry replaced next once kMaxHints are held
 };
+constexpr size_t kMaxHints = 8;
 
 // All device state of one step.  Eager forwards size the sort buffers exactly and drop
 // the temporaries afterwards; a graph keeps every buffer at its capacity.
@@ -47,6 +58,7 @@ struct gsr_saved {
   // depth sort and binning buffers
   uint32_t *dk = nullptr, *dv = nullptr, *dk2 = nullptr, *dv2 = nullptr;
   uint32_t *hist = nullptr, *dtot = nullptr;
+  const uint32_t* order_hint = nullptr;  // per-tile work of a previous forward, or null
   BinPlan plan{};
   Ckpt ck{};                  // forward checkpoints and backward work items
   uint32_t* vals = nullptr;   // record id of every (tile, record) pair, in key order
@@ -56,7 +68,6 @@ struct gsr_saved {
   uint32_t* ctrl = nullptr;
   float* T_final = nullptr;
   uint32_t* n_contrib = nullptr;
-  uint32_t* n_used = nullptr;  // contributors per pixel (statistics)
   float* grad2d = nullptr;  // graph only (eager backward allocates its own)
   int64_t total_pix = 0;
   int sort_passes = 0;
@@ -273,8 +284,7 @@ gsr_status make_saved(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* ca
       (st = alloc_in(sv, B, &sv->ck.items, size_t(sv->ck.cap_items))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->ctrl, kCtrlWords)) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->T_final, size_t(pix))) != GSR_OK ||
-      (st = alloc_in(sv, B, &sv->n_contrib, size_t(pix))) != GSR_OK ||
-      (st = alloc_in(sv, B, &sv->n_used, size_t(pix))) != GSR_OK) {
+      (st = alloc_in(sv, B, &sv->n_contrib, size_t(pix))) != GSR_OK) {
     release(sv);
     return st;
   }
@@ -306,6 +316,63 @@ gsr_status alloc_sort(gsr_saved* sv, int64_t cap_vis, int64_t cap_M, bool persis
       (st = alloc_in(sv, T, &p.part, size_t(nparts))) != GSR_OK || (st = alloc_in(sv, T, &p.words, 4)) != GSR_OK)
     return st;
   return GSR_OK;
+}
+
+TileQueue queue_of(const gsr_saved* sv) { return TileQueue{sv->order, sv->ctrl, sv->order_hint ? 1 : 0}; }
+
+// The tile grid of a forward: tile size and every view's size.
+std::vector<int> tile_grid(const gsr_saved* sv) {
+  std::vector<int> g{sv->s.tile, sv->V};
+  for (int v = 0; v < sv->V; ++v) {
+    g.push_back(sv->vt.v[v].W);
+    g.push_back(sv->vt.v[v].H);
+  }
+  return g;
+}
+
+// The context's work hint for this forward's tile grid, or null.
+const uint32_t* find_hint(gsr_ctx* ctx, const gsr_saved* sv) {
+  const std::vector<int> g = tile_grid(sv);
+  for (auto& h : ctx->hints)
+    if (h.grid == g && h.count == sv->vt.total_tiles) return h.tiles;
+  return nullptr;
+}
+
+// Keeps this forward's per-tile work (enqueued after its compositing) as the hint for the
+// next forward over the same tiles.  Failure to keep it only loses the hint.
+void keep_hint(gsr_ctx* ctx, const gsr_saved* sv, hipStream_t s) {
+  const int64_t T = sv->vt.total_tiles;
+  if (T == 0) return;
+  const std::vector<int> g = tile_grid(sv);
+  gsr_ctx::WorkHint* slot = nullptr;
+  for (auto& h : ctx->hints)
+    if (h.grid == g) slot = &h;
+  if (!slot) {
+    if (ctx->hints.size() < kMaxHints) {
+      ctx->hints.emplace_back();
+      slot = &ctx->hints.back();
+    } else {
+      slot = &ctx->hints[ctx->next_hint];
+      ctx->next_hint = (ctx->next_hint + 1) % kMaxHints;
+    }
+    slot->grid = g;
+  }
+  if (slot->count < T) {
+    if (slot->tiles) (void)hipFreeAsync(slot->tiles, s);
+    slot->tiles = nullptr;
+    slot->count = 0;
+    if (hipMallocAsync(reinterpret_cast<void**>(&slot->tiles), size_t(T) * sizeof(uint32_t), s) != hipSuccess) {
+      (void)hipGetLastError();
+      slot->grid.clear();
+      return;
+    }
+  }
+  slot->count = T;
+  if (hipMemcpyAsync(slot->tiles, sv->ck.tile_nmax, size_t(T) * sizeof(uint32_t), hipMemcpyDeviceToDevice, s) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    slot->grid.clear();
+  }
 }
 
 // Phase A of a forward: clear the control words, project, scan the block sums.
@@ -351,12 +418,12 @@ hipError_t enqueue_sort_blend(gsr_saved* sv, hipStream_t s, bool timing) {
                    (sv->s.flags & GSR_EXACT_TILES) ? sv->ru.k : 0.f, sv->s.tile, s, tm);
   if (e == hipSuccess)
     e = T(K_TILE_ORDER, [&] {
-      return launch_tile_order(sv->ranges, sv->vt.total_tiles, sv->order, s);
+      return launch_tile_order(sv->ranges, sv->order_hint, sv->vt.total_tiles, sv->order, s);
     });
   if (e == hipSuccess)
     e = T(K_BLEND_FWD, [&] {
       return launch_blend_fwd(sv->s.tile, sv->s.batch, sv->vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final,
-                              sv->n_contrib, sv->n_used, TileQueue{sv->order, sv->ctrl}, sv->ck, s);
+                              sv->n_contrib, queue_of(sv), sv->ck, s);
     });
   return e;
 }
@@ -374,7 +441,7 @@ hipError_t enqueue_backward(gsr_saved* sv, const ViewTable& vt, float* grad2d, c
   if (e == hipSuccess)
     e = T(K_BLEND_BWD, [&] {
       return launch_blend_bwd(sv->s.tile, sv->s.batch, vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final,
-                              sv->n_contrib, grad2d, TileQueue{sv->order, sv->ctrl}, sv->ck, s);
+                              sv->n_contrib, grad2d, queue_of(sv), sv->ck, s);
     });
   if (e == hipSuccess && adam.on) e = launch_adam_tick(adam_state, adam.b1, adam.b2, s);
   if (e == hipSuccess)
@@ -466,11 +533,13 @@ gsr_status forward_eager(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera*
     release(sv);
     return st;
   }
+  sv->order_hint = find_hint(ctx, sv);
   e = enqueue_sort_blend(sv, strm, true);
   if (e != hipSuccess) {
     release(sv);
     return fail(ctx, GSR_EDEVICE, std::string("forward (sort/blend) failed: ") + hipGetErrorString(e));
   }
+  keep_hint(ctx, sv, strm);
   // keep the pair list, return every temporary to the pool
   free_list(sv, sv->temps);
   *out = sv;
@@ -563,6 +632,8 @@ gsr_status gsr_ctx_destroy(gsr_ctx* ctx) {
   if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->bwd_scratch) (void)hipFree(ctx->bwd_scratch);
+  for (auto& h : ctx->hints)
+    if (h.tiles) (void)hipFree(h.tiles);
   ctx->timer.destroy();
   if (ctx->h_total) (void)hipHostFree(ctx->h_total);
   delete ctx;
@@ -747,7 +818,16 @@ gsr_status gsr_debug_export(gsr_ctx* ctx, const gsr_saved* sv, const gsr_debug* 
   GSR_HIP(ctx, cp(out->ranges, sv->ranges, size_t(sv->vt.total_tiles) * 8));
   GSR_HIP(ctx, cp(out->T_final, sv->T_final, size_t(sv->total_pix) * 4));
   GSR_HIP(ctx, cp(out->n_contrib, sv->n_contrib, size_t(sv->total_pix) * 4));
-  GSR_HIP(ctx, cp(out->n_used, sv->n_used, size_t(sv->total_pix) * 4));
+  if (out->n_used && sv->total_pix > 0) {  // counted on demand, off the forward's path
+    uint32_t* nu = nullptr;
+    GSR_HIP(ctx, hipMalloc(reinterpret_cast<void**>(&nu), size_t(sv->total_pix) * 4));
+    hipError_t e = launch_count_used(sv->vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->n_contrib, sv->s.tile,
+                                     sv->total_pix, nu, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = cp(out->n_used, nu, size_t(sv->total_pix) * 4);
+    (void)hipFree(nu);
+    GSR_HIP(ctx, e);
+  }
   GSR_HIP(ctx, cp(out->tiles_touched, sv->rec.counts, size_t(VN) * 4));
   if (out->mu || out->depth || out->conic || out->color || out->rect) {
     std::vector<float4> r0(VN), r1(VN), rgb(VN);
@@ -836,6 +916,15 @@ gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_came
       (st = alloc_in(sv, sv->blocks, &sv->grad2d, size_t(VN) * kGrad2D + size_t(sv->N) * 3)) != GSR_OK) {
     graph_destroy(gr);
     return st;
+  }
+  // the captured forward orders its tiles by the per-tile work of the replay before it;
+  // the first replay uses the measuring forward's
+  if (const uint32_t* h = find_hint(ctx, sv)) {
+    if (hipMemcpyAsync(sv->ck.tile_nmax, h, size_t(sv->vt.total_tiles) * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                       ctx->stream) == hipSuccess)
+      sv->order_hint = sv->ck.tile_nmax;
+    else
+      (void)hipGetLastError();
   }
   ViewTable lvt;
   if ((st = loss_table(ctx, sv, outs, targets, depth_weight, grad_color, grad_depth, &lvt)) != GSR_OK) {

@@ -103,7 +103,6 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 4;
 constexpr int kSortTile = kSortThreads * kSortItems;  // keys per radix-sort block
 constexpr int kGrad2D = 12;  // floats per (view, Gaussian) 2D-gradient record (10 used)
-constexpr int kBuckets = 33;   // log2 buckets of tile list lengths
 constexpr int kHeadFwd = 0;    // control words (see TileQueue)
 constexpr int kHeadBwd = 1;
 constexpr int kOverflow = 2;
@@ -172,6 +171,7 @@ struct Records {
 struct TileQueue {
   const uint32_t* order;
   uint32_t* ctrl;
+  int32_t by_work;  // the order comes from measured per-tile work: queue position sets priority
 };
 
 // What the forward keeps so that the backward can run a tile's list in independent
@@ -271,7 +271,10 @@ hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* to
 hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
                           const unsigned long long* pairs, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
                           int64_t cap, uint32_t* overflow, hipStream_t s);
-hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* order, hipStream_t s);
+// Tile queue order by decreasing expected work: hint[t] (a previous forward's longest
+// contributor count of tile t) when given, else the list length.
+hipError_t launch_tile_order(const uint2* ranges, const uint32_t* hint, int total_tiles, uint32_t* order,
+                             hipStream_t s);
 // Checkpoint stride and checkpoints per tile, and the backward work items of all tiles,
 // at a batch size.
 int ckpt_stride(int batch);
@@ -289,7 +292,11 @@ hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const 
                       uint2* ranges, uint32_t* overflow, float exact_k, int tile, hipStream_t s, Timer* tm);
 hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
-                            uint32_t* n_used, const TileQueue& q, const Ckpt& ck, hipStream_t s);
+                            const TileQueue& q, const Ckpt& ck, hipStream_t s);
+// Per pixel, the entries before its last contributor that passed the skip rule.
+hipError_t launch_count_used(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
+                             const uint32_t* vals, const uint32_t* n_contrib, int tile, int64_t total_pix,
+                             uint32_t* n_used, hipStream_t s);
 int loss_partials(const ViewTable& vt);  // block partial sums launch_loss_l1 writes
 hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* part, float* loss, hipStream_t s);
 // Lists the backward's (tile, stride) work items, then runs them.

@@ -1168,42 +1168,71 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t value, i
 }
 
 // ------------------------------------------------------------------------------------
-// Tile work queue.  Tiles are ordered by decreasing list length (a counting sort on
-// log2 buckets, in one block: the order inside a bucket is arbitrary) and the compositing
-// kernels run as persistent blocks that take the next tile from a device counter, so the
-// longest lists start first and short ones fill the tail.
+// Tile work queue.  Tiles are ordered by decreasing expected work (a counting sort on
+// buckets of eight steps per octave, in one block: the order inside a bucket is
+// arbitrary) and the compositing kernels run as persistent blocks that take the next tile
+// from a device counter, so the heaviest tiles start first and light ones fill the tail.
+// A tile's work is its longest per-pixel contributor count, which the list length does
+// not predict (a pixel stops once its transmittance is spent); when a previous forward
+// of the same tiles left those counts (`hint`), they are the key, else the list length.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_tile_order(const uint2* ranges, int total, uint32_t* order) {
-  __shared__ uint32_t cnt[kBuckets], start[kBuckets];
-  if (threadIdx.x < kBuckets) cnt[threadIdx.x] = 0;
-  __syncthreads();
-  for (int i = threadIdx.x; i < total; i += 1024) {
-    const uint2 r = ranges[i];
-    const uint32_t len = r.y - r.x;
-    atomicAdd(&cnt[len ? 32u - uint32_t(__clz(len)) : 0u], 1u);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int b = kBuckets - 1; b >= 0; --b) {
-      start[b] = run;
-      run += cnt[b];
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < total; i += 1024) {
-    const uint2 r = ranges[i];
-    const uint32_t len = r.y - r.x;
-    order[atomicAdd(&start[len ? 32u - uint32_t(__clz(len)) : 0u], 1u)] = uint32_t(i);
-  }
+constexpr int kOrderBuckets = 257;
+
+__device__ __forceinline__ uint32_t work_bucket(uint32_t w) {
+  if (w == 0) return 0;
+  const uint32_t e = 31u - uint32_t(__clz(w));
+  const uint32_t m = e >= 3 ? (w >> (e - 3)) & 7u : (w << (3 - e)) & 7u;
+  return 1u + 8u * e + m;
 }
 
-// Block-uniform: the next tile of the queue, or -1 when it is exhausted.
-__device__ __forceinline__ int next_tile(const TileQueue& q, uint32_t* head, int total, int* s_item) {
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2* ranges, const uint32_t* hint, int total,
+                                                    uint32_t* order) {
+  __shared__ uint32_t cnt[kOrderBuckets], start[kOrderBuckets];
+  __shared__ uint32_t red[16];
+  const int t = threadIdx.x;
+  if (t < kOrderBuckets) cnt[t] = 0;
+  __syncthreads();
+  auto key = [&](int i) {
+    const uint2 r = ranges[i];
+    return work_bucket(hint ? hint[i] : r.y - r.x);
+  };
+  for (int i = t; i < total; i += 1024) atomicAdd(&cnt[key(i)], 1u);
+  __syncthreads();
+  // heaviest bucket first: thread t takes bucket kOrderBuckets - 1 - t
+  const int bk = kOrderBuckets - 1 - t;
+  const uint32_t c = bk >= 0 ? cnt[bk] : 0u;
+  const uint32_t ex = block_exclusive_scan_u32(c, red);
+  if (bk >= 0) start[bk] = ex;
+  __syncthreads();
+  for (int i = t; i < total; i += 1024) order[atomicAdd(&start[key(i)], 1u)] = uint32_t(i);
+}
+
+// Wave priority 0..3 (s_setprio takes an immediate).
+__device__ __forceinline__ void set_wave_prio(int p) {
+  if (p >= 3)
+    __builtin_amdgcn_s_setprio(3);
+  else if (p == 2)
+    __builtin_amdgcn_s_setprio(2);
+  else if (p == 1)
+    __builtin_amdgcn_s_setprio(1);
+  else
+    __builtin_amdgcn_s_setprio(0);
+}
+
+// Priority of a queue position: the first sixteenth of the items (the heaviest) 3, the
+// rest of the first eighth 2, of the first quarter 1, else 0.
+__device__ __forceinline__ int queue_prio(int item, int total) {
+  return item * 16 < total ? 3 : (item * 8 < total ? 2 : (item * 4 < total ? 1 : 0));
+}
+
+// Block-uniform: the next tile of the queue, or -1 when it is exhausted; *prio is the
+// queue position's priority.
+__device__ __forceinline__ int next_tile(const TileQueue& q, uint32_t* head, int total, int* s_item, int* prio) {
   __syncthreads();
   if (threadIdx.x == 0) *s_item = int(atomicAdd(head, 1u));
   __syncthreads();
   const int item = *s_item;
+  *prio = item < total && q.by_work ? queue_prio(item, total) : 0;
   return item < total ? int(q.order[item]) : -1;
 }
 
@@ -1215,7 +1244,7 @@ __device__ __forceinline__ int next_tile(const TileQueue& q, uint32_t* head, int
 template <int TS, int BATCH>
 __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Records rec, const uint2* ranges,
                                                      const uint32_t* vals, float* T_final, uint32_t* n_contrib,
-                                                     uint32_t* n_used, TileQueue q, Ckpt ck) {
+                                                     TileQueue q, Ckpt ck) {
   constexpr int NT = TS * TS;
   constexpr int CK = BATCH / 2;  // checkpoint stride
   __shared__ float4 s_r0[BATCH];
@@ -1235,7 +1264,8 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
     st[4 * NT] = D;
   };
   for (;;) {
-    const int tile = next_tile(q, q.ctrl + kHeadFwd, vt.total_tiles, &s_item);
+    int qprio;
+    const int tile = next_tile(q, q.ctrl + kHeadFwd, vt.total_tiles, &s_item, &qprio);
     if (tile < 0) return;
     tile_of_block = tile;
     if (threadIdx.x == 0) s_nmax = 0;
@@ -1248,29 +1278,32 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
     const int n = int(rg.y - rg.x);
     const float fpx = float(px), fpy = float(py);
     float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
-    uint32_t last = 0, used = 0;
+    uint32_t last = 0;
     bool done = !inside;
-    __builtin_amdgcn_s_setprio(0);
+    // the heaviest tiles (first in the queue) bound the kernel's duration: their
+    // wavefronts take issue priority from the start; any tile still running after
+    // several batches is raised too
+    set_wave_prio(qprio);
     for (int b0 = 0; b0 < n; b0 += BATCH) {
       if (__syncthreads_count(!done) == 0) break;
-      // a tile still running after several batches has long lists: it bounds the
-      // kernel's duration, so its wavefronts take issue priority over newer tiles
-      if (b0 == BATCH)
-        __builtin_amdgcn_s_setprio(1);
-      else if (b0 == 2 * BATCH)
-        __builtin_amdgcn_s_setprio(2);
-      else if (b0 == 3 * BATCH)
-        __builtin_amdgcn_s_setprio(3);
+      if (b0 > 0 && b0 <= 3 * BATCH && b0 % BATCH == 0) set_wave_prio(max(qprio, b0 / BATCH));
       if (b0 > 0) checkpoint(b0 / CK, T, C0, C1, C2, D);
+      const int cnt = min(BATCH, n - b0);
       for (int j = threadIdx.x; j < BATCH && b0 + j < n; j += NT)
         stage_record(rec, vals[rg.x + b0 + j], s_r0[j], s_r1[j], s_rgb[j]);
+      // a partial batch is padded to a multiple of four with splats of opacity -1, whose
+      // alpha (-1) is below any skip threshold (which is >= 0): no pixel takes them
+      for (int j = cnt + int(threadIdx.x); j < ((cnt + 3) & ~3); j += NT) {
+        s_r0[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_r1[j] = make_float4(0.f, -1.f, 0.f, 0.f);
+        s_rgb[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
       __syncthreads();
       // four staged entries at a time: their splat values do not depend on the running
       // transmittance, so they are evaluated together (loads and exponentials overlap);
       // compositing then runs in list order, straight-line: a lane that has stopped, or
       // for which the splat is below the skip threshold, adds exact zeros and keeps T.
       // The wavefront leaves the batch once all its lanes have stopped.
-      const int cnt = min(BATCH, n - b0);
       for (int j = 0; j < cnt; j += 4) {
         if (__ballot(!done) == 0ull) break;
         if (j == CK) checkpoint((b0 + CK) / CK, T, C0, C1, C2, D);
@@ -1278,10 +1311,9 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
         float4 c4[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int jj = min(j + u, cnt - 1);
-          const float4 r0 = s_r0[jj];
-          const float4 r1 = s_r1[jj];
-          c4[u] = s_rgb[jj];
+          const float4 r0 = s_r0[j + u];
+          const float4 r1 = s_r1[j + u];
+          c4[u] = s_rgb[j + u];
           float G;
           a4[u] = splat_alpha(fpx - r0.x, fpy - r0.y, r0.z, r0.w, r1.x, r1.y, G);
           z4[u] = r1.z;
@@ -1289,8 +1321,8 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const float a = a4[u];
-          const bool act = j + u < cnt && !done && !(a < ru.amin);
-          const float al = act ? (a < ru.amax ? a : ru.amax) : 0.f;  // 0: adds nothing, keeps T
+          const bool act = !done && !(a < ru.amin);
+          const float al = act ? fminf(a, ru.amax) : 0.f;  // 0: adds nothing, keeps T
           const float wgt = al * T;
           C0 += c4[u].x * wgt;
           C1 += c4[u].y * wgt;
@@ -1298,7 +1330,6 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
           D += z4[u] * wgt;
           T = T * (1.f - al);
           last = act ? uint32_t(b0 + j + u + 1) : last;
-          used += act ? 1u : 0u;
           done = done || T < ru.Tmin;
         }
       }
@@ -1313,7 +1344,6 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
       if (cam.alpha) cam.alpha[pix] = 1.f - T;
       T_final[cam.pix_off + pix] = T;
       n_contrib[cam.pix_off + pix] = last;
-      n_used[cam.pix_off + pix] = used;
       ck.acc[cam.pix_off + pix] = make_float4(C0, C1, C2, D);
     }
     const uint32_t wl = wave_max_u32(last);
@@ -1322,6 +1352,34 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
     __syncthreads();
     if (threadIdx.x == 0) ck.tile_nmax[tile] = s_nmax;
   }
+}
+
+// Per pixel, the list entries in front of its last contributor that passed the skip rule
+// (a statistic of the forward, for inspection): the forward's alpha of each entry
+// (the same staged values and splat evaluation) compared with the threshold.
+__global__ __launch_bounds__(256) void k_count_used(ViewTable vt, Rules ru, Records rec, const uint2* ranges,
+                                                   const uint32_t* vals, const uint32_t* n_contrib, int tile,
+                                                   int64_t total_pix, uint32_t* n_used) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= total_pix) return;
+  int v = 0;
+  for (int k = 1; k < vt.nviews; ++k)
+    if (i >= vt.v[k].pix_off) v = k;
+  const ViewDev& cam = vt.v[v];
+  const int64_t pix = i - cam.pix_off;
+  const int py = int(pix / cam.W), px = int(pix - int64_t(py) * cam.W);
+  const uint2 rg = ranges[cam.tile_off + (py / tile) * cam.tiles_x + px / tile];
+  const uint32_t nc = n_contrib[i];
+  const float fpx = float(px), fpy = float(py);
+  uint32_t used = 0;
+  for (uint32_t j = 0; j < nc && rg.x + j < rg.y; ++j) {
+    float4 r0, r1, rgb;
+    stage_record(rec, vals[rg.x + j], r0, r1, rgb);
+    float G;
+    const float a = splat_alpha(fpx - r0.x, fpy - r0.y, r0.z, r0.w, r1.x, r1.y, G);
+    used += !(a < ru.amin) ? 1u : 0u;
+  }
+  n_used[i] = used;
 }
 
 // ------------------------------------------------------------------------------------
@@ -1413,8 +1471,8 @@ __global__ __launch_bounds__(1024) void k_bwd_items(const uint32_t* order, int t
   if (threadIdx.x == 0) ctrl[kItems] = uint32_t(min<int64_t>(carry, ck.cap_items));
 }
 
-// Block-uniform: the next backward work item, or -1; the first items (the longest tiles)
-// take a higher wave priority, as in next_tile.
+// Block-uniform: the next backward work item, or -1; the first items (the heaviest
+// tiles) take a higher wave priority, as in the forward.
 __device__ __forceinline__ int next_item(uint32_t* head, int total, int* s_item) {
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1426,16 +1484,7 @@ __device__ __forceinline__ int next_item(uint32_t* head, int total, int* s_item)
   }
   __syncthreads();
   const int item = *s_item;
-  if (item < total) {
-    if (item * 16 < total)
-      __builtin_amdgcn_s_setprio(3);
-    else if (item * 8 < total)
-      __builtin_amdgcn_s_setprio(2);
-    else if (item * 4 < total)
-      __builtin_amdgcn_s_setprio(1);
-    else
-      __builtin_amdgcn_s_setprio(0);
-  }
+  if (item < total) set_wave_prio(queue_prio(item, total));
   return item < total ? item : -1;
 }
 
@@ -2013,15 +2062,25 @@ constexpr int kBwdBlocksPerCU = 5;
 
 template <int TS, int BATCH>
 static void blend_fwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
-                        const uint32_t* vals, float* T_final, uint32_t* n_contrib, uint32_t* n_used,
-                        const TileQueue& q, const Ckpt& ck, hipStream_t s) {
+                        const uint32_t* vals, float* T_final, uint32_t* n_contrib, const TileQueue& q,
+                        const Ckpt& ck, hipStream_t s) {
   const int grid = std::min(vt.total_tiles, resident_blocks(k_blend_fwd<TS, BATCH>, TS * TS, kFwdBlocksPerCU));
-  k_blend_fwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck);
+  k_blend_fwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, q, ck);
 }
 
-hipError_t launch_tile_order(const uint2* ranges, int total_tiles, uint32_t* order, hipStream_t s) {
+hipError_t launch_count_used(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
+                             const uint32_t* vals, const uint32_t* n_contrib, int tile, int64_t total_pix,
+                             uint32_t* n_used, hipStream_t s) {
+  if (total_pix == 0) return hipSuccess;
+  k_count_used<<<unsigned((total_pix + 255) / 256), 256, 0, s>>>(vt, ru, rec, ranges, vals, n_contrib, tile, total_pix,
+                                                                 n_used);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_order(const uint2* ranges, const uint32_t* hint, int total_tiles, uint32_t* order,
+                             hipStream_t s) {
   if (total_tiles == 0) return hipSuccess;
-  k_tile_order<<<1, 1024, 0, s>>>(ranges, total_tiles, order);
+  k_tile_order<<<1, 1024, 0, s>>>(ranges, hint, total_tiles, order);
   return hipGetLastError();
 }
 
@@ -2033,16 +2092,16 @@ int64_t bwd_items_cap(int total_tiles, int batch) { return int64_t(total_tiles) 
 
 hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
-                            uint32_t* n_used, const TileQueue& q, const Ckpt& ck, hipStream_t s) {
+                            const TileQueue& q, const Ckpt& ck, hipStream_t s) {
   if (vt.total_tiles == 0) return hipSuccess;
   const bool b256 = batch == 256;
   switch (tile) {
-    case 8: b256 ? blend_fwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck, s)
-                 : blend_fwd_t<8, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck, s); break;
-    case 32: b256 ? blend_fwd_t<32, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck, s)
-                  : blend_fwd_t<32, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck, s); break;
-    default: b256 ? blend_fwd_t<16, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck, s)
-                  : blend_fwd_t<16, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, n_used, q, ck, s); break;
+    case 8: b256 ? blend_fwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, q, ck, s)
+                 : blend_fwd_t<8, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, q, ck, s); break;
+    case 32: b256 ? blend_fwd_t<32, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, q, ck, s)
+                  : blend_fwd_t<32, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, q, ck, s); break;
+    default: b256 ? blend_fwd_t<16, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, q, ck, s)
+                  : blend_fwd_t<16, 128>(vt, ru, rec, ranges, vals, T_final, n_contrib, q, ck, s); break;
   }
   return hipGetLastError();
 }
