@@ -1499,7 +1499,7 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
   __shared__ float4 s_r1[BATCH];
   __shared__ float4 s_rgb[BATCH];
   __shared__ uint32_t s_id[BATCH];
-  __shared__ float s_g[kBlockSum ? 10 : 1][kBlockSum ? BATCH : 1];
+  __shared__ float s_g[kBlockSum ? BATCH : 1][kBlockSum ? 10 : 1];  // per staged splat, its ten sums
   __shared__ uint32_t s_max;
   __shared__ int s_item;
   if (kBlockSum)
@@ -1622,9 +1622,9 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
         const int row = lane >> 4;
         const int k = row == 1 ? 2 : (row == 2 ? 1 : row);
         if (kBlockSum) {
-          atomicAdd(&s_g[k][j], w0);
-          atomicAdd(&s_g[4 + k][j], w1);
-          if (!(row & 1)) atomicAdd(&s_g[8 + (row >> 1)][j], w2);
+          atomicAdd(&s_g[j][k], w0);
+          atomicAdd(&s_g[j][4 + k], w1);
+          if (!(row & 1)) atomicAdd(&s_g[j][8 + (row >> 1)], w2);
         } else {
           float* dst = grad2d + int64_t(s_id[j]) * kGrad2D;
           unsafeAtomicAdd(dst + k, w0);
@@ -1635,16 +1635,207 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
     }
     if (kBlockSum) {
       __syncthreads();
+      // splat-major: the lanes of a wavefront add consecutive sums of a few splats, so
+      // one atomic instruction touches a few gradient rows (cache lines), not 64
       for (int i = threadIdx.x; i < 10 * nstage; i += NT) {
-        const int k = i / nstage, j = i - k * nstage;
-        const float v = s_g[k][j];
+        const int j = i / 10, k = i - 10 * j;
+        float* g = &(&s_g[0][0])[i];
+        const float v = *g;
         if (v != 0.f) {
           unsafeAtomicAdd(grad2d + int64_t(s_id[j]) * kGrad2D + k, v);
-          s_g[k][j] = 0.f;
+          *g = 0.f;
         }
       }
     }
   }
+  }
+}
+
+// K8 with two vertically adjacent pixels per lane (tiles of 16 and 32): a wavefront
+// covers 128 pixels, so each splat's ten partials are reduced across the wavefront once
+// for twice the pixels (the pair's partials are added first).  Same per-pixel arithmetic
+// and work items as k_blend_bwd.
+struct BwdPixel {
+  float T, Tfin, gC0, gC1, gC2, gD, gA, BC0, BC1, BC2, BD, fpy;
+  int top;
+};
+
+// A pixel's state at the end of work item (tile, bf): as in k_blend_bwd.
+template <int TS>
+__device__ __forceinline__ void bwd_pixel_setup(BwdPixel& s, const ViewDev& cam, const Rules& ru, const Ckpt& ck,
+                                                const float* T_final, const uint32_t* n_contrib, int tile, int bf,
+                                                int lo, int hi, int px, int py, int q) {
+  constexpr int NP = TS * TS;  // pixels of a tile
+  const bool inside = px < cam.W && py < cam.H;
+  const int64_t P = int64_t(cam.W) * cam.H;
+  const int64_t pix = int64_t(py) * cam.W + px;
+  s.T = 1.f;
+  s.Tfin = 1.f;
+  s.gC0 = s.gC1 = s.gC2 = s.gD = s.gA = 0.f;
+  s.BC0 = ru.bg[0];
+  s.BC1 = ru.bg[1];
+  s.BC2 = ru.bg[2];
+  s.BD = 0.f;
+  s.top = 0;
+  s.fpy = float(py);
+  if (!inside) return;
+  const int nc = int(n_contrib[cam.pix_off + pix]);
+  if (nc <= lo) return;
+  s.Tfin = T_final[cam.pix_off + pix];
+  if (cam.g_color) {
+    s.gC0 = cam.g_color[pix];
+    s.gC1 = cam.g_color[P + pix];
+    s.gC2 = cam.g_color[2 * P + pix];
+  }
+  if (cam.g_depth) s.gD = cam.g_depth[pix];
+  if (cam.g_alpha) s.gA = cam.g_alpha[pix];
+  if (ru.norm_depth) {  // output Dn = D / A, A = 1 - T_final: dL/dD = g / A, dL/dA -= g Dn / A
+    const float A = 1.f - s.Tfin;
+    if (A > 0.f) {
+      const float Dn = ck.acc[cam.pix_off + pix].w / A;
+      s.gA -= s.gD * Dn / A;
+      s.gD = s.gD / A;
+    } else {
+      s.gD = 0.f;
+    }
+  }
+  if (nc <= hi) {
+    s.T = s.Tfin;
+    s.top = nc;
+  } else {  // only single-stride items end before the list: checkpoint bf + 1 <= kmax
+    const float* st = ck.state + (int64_t(tile) * ck.kmax + bf) * (5 * NP) + q;
+    const float4 acc = ck.acc[cam.pix_off + pix];
+    s.T = st[0];
+    const float inv = 1.f / s.T;
+    s.BC0 = (acc.x - st[NP] + s.Tfin * ru.bg[0]) * inv;
+    s.BC1 = (acc.y - st[2 * NP] + s.Tfin * ru.bg[1]) * inv;
+    s.BC2 = (acc.z - st[3 * NP] + s.Tfin * ru.bg[2]) * inv;
+    s.BD = (acc.w - st[4 * NP]) * inv;
+    s.top = hi;
+  }
+}
+
+// One (pixel, splat) step back to front: updates the pixel's state and adds its ten
+// partials to g (the same arithmetic as k_blend_bwd's loop body).
+__device__ __forceinline__ void bwd_pixel_step(BwdPixel& s, bool act, float a, float G, float dx, float dy,
+                                               const float4& r0, const float4& r1, const float4& c, const Rules& ru,
+                                               float (&g)[10]) {
+  const float al = a < ru.amax ? a : ru.amax;
+  const float om = 1.f - al;
+  const float iom = __builtin_amdgcn_rcpf(om);
+  s.T = act ? s.T * iom : s.T;
+  const float wgt = act ? al * s.T : 0.f;
+  g[6] += s.gC0 * wgt;
+  g[7] += s.gC1 * wgt;
+  g[8] += s.gC2 * wgt;
+  g[9] += s.gD * wgt;
+  const float dal = s.T * (s.gC0 * (c.x - s.BC0) + s.gC1 * (c.y - s.BC1) + s.gC2 * (c.z - s.BC2) +
+                           s.gD * (r1.z - s.BD)) +
+                    s.gA * s.Tfin * iom;
+  s.BC0 = act ? al * c.x + om * s.BC0 : s.BC0;
+  s.BC1 = act ? al * c.y + om * s.BC1 : s.BC1;
+  s.BC2 = act ? al * c.z + om * s.BC2 : s.BC2;
+  s.BD = act ? al * r1.z + om * s.BD : s.BD;
+  const float da = (act && a <= ru.amax) ? dal : 0.f;
+  g[5] += da * G;
+  const float dpw = da * a;
+  // (A dx + B dy, B dx + C dy) = -ln 2 (2a' dx + b' dy, b' dx + 2c' dy)
+  const float dpl = -0.69314718055994531f * dpw;
+  g[0] += dpl * (r1.w * dx + r0.w * dy);
+  g[1] += dpl * (r0.w * dx + c.w * dy);
+  g[2] += -0.5f * dpw * dx * dx;
+  g[3] += -dpw * dx * dy;
+  g[4] += -0.5f * dpw * dy * dy;
+}
+
+template <int TS, int BATCH>
+__global__ __launch_bounds__(TS* TS / 2) void k_blend_bwd2(ViewTable vt, Rules ru, Records rec, const uint2* ranges,
+                                                          const uint32_t* vals, const float* T_final,
+                                                          const uint32_t* n_contrib, float* grad2d, TileQueue q,
+                                                          Ckpt ck) {
+  constexpr int NT = TS * TS / 2;  // threads: pixels (2r, c) and (2r + 1, c) for t = r TS + c
+  __shared__ float4 s_r0[BATCH];
+  __shared__ float4 s_r1[BATCH];
+  __shared__ float4 s_rgb[BATCH];
+  __shared__ uint32_t s_id[BATCH];
+  __shared__ float s_g[BATCH][10];  // per staged splat, its ten sums
+  __shared__ uint32_t s_max;
+  __shared__ int s_item;
+  for (int i = threadIdx.x; i < 10 * BATCH; i += NT) (&s_g[0][0])[i] = 0.f;
+  const int total = int(q.ctrl[kItems]);
+  const int lane = threadIdx.x & 63;
+  const int cx = int(threadIdx.x % TS), ry = 2 * int(threadIdx.x / TS);
+  for (;;) {
+    const int item = next_item(q.ctrl + kHeadBwd, total, &s_item);
+    if (item < 0) return;
+    const uint2 it = ck.items[item];
+    const int tile = int(it.x), bf = int(it.y);
+    const ViewDev& cam = vt.v[view_of_tile(vt, tile)];
+    const int lt = tile - cam.tile_off;
+    const int ty = lt / cam.tiles_x, tx = lt - ty * cam.tiles_x;
+    const int px = tx * TS + cx, py = ty * TS + ry;
+    const uint2 rg = ranges[tile];
+    constexpr int CK = BATCH / 2;  // checkpoint stride of the forward
+    const int lo = bf * CK;        // the item's list entries: [lo, hi)
+    const int hi = bf < ck.kmax ? lo + CK : int(rg.y - rg.x);
+    BwdPixel p0, p1;
+    bwd_pixel_setup<TS>(p0, cam, ru, ck, T_final, n_contrib, tile, bf, lo, hi, px, py, ry * TS + cx);
+    bwd_pixel_setup<TS>(p1, cam, ru, ck, T_final, n_contrib, tile, bf, lo, hi, px, py + 1, (ry + 1) * TS + cx);
+    const int wmax = int(wave_max_u32(uint32_t(max(p0.top, p1.top))));
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    if (lane == 0 && wmax) atomicMax(&s_max, uint32_t(wmax));
+    __syncthreads();
+    const int bmax = int(s_max);
+    const float fpx = float(px);
+    for (int bend = bmax; bend > lo; bend -= BATCH) {
+      const int bstart = max(lo, bend - BATCH);
+      const int nstage = bend - bstart;
+      __syncthreads();
+      for (int j = threadIdx.x; j < nstage; j += NT) {
+        const uint32_t id = vals[rg.x + bstart + j];
+        s_id[j] = id;
+        stage_record(rec, id, s_r0[j], s_r1[j], s_rgb[j]);
+      }
+      __syncthreads();
+      for (int j = min(nstage, wmax - bstart) - 1; j >= 0; --j) {
+        const float4 r0 = s_r0[j];
+        const float4 r1 = s_r1[j];
+        const float dx = fpx - r0.x;
+        const float dy0 = p0.fpy - r0.y, dy1 = p1.fpy - r0.y;
+        float G0, G1;
+        const float a0 = splat_alpha(dx, dy0, r0.z, r0.w, r1.x, r1.y, G0);
+        const float a1 = splat_alpha(dx, dy1, r0.z, r0.w, r1.x, r1.y, G1);
+        const bool act0 = bstart + j < p0.top && !(a0 < ru.amin);
+        const bool act1 = bstart + j < p1.top && !(a1 < ru.amin);
+        if (__ballot(act0 || act1) == 0ull) continue;
+        const float4 c = s_rgb[j];
+        float gv[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        bwd_pixel_step(p0, act0, a0, G0, dx, dy0, r0, r1, c, ru, gv);
+        bwd_pixel_step(p1, act1, a1, G1, dx, dy1, r0, r1, c, ru, gv);
+        float w0, w1, w2;
+        wave_sum10(gv, w0, w1, w2);
+        if ((lane & 15) == 0) {  // one lane per row adds its row's totals
+          const int row = lane >> 4;
+          const int k = row == 1 ? 2 : (row == 2 ? 1 : row);
+          atomicAdd(&s_g[j][k], w0);
+          atomicAdd(&s_g[j][4 + k], w1);
+          if (!(row & 1)) atomicAdd(&s_g[j][8 + (row >> 1)], w2);
+        }
+      }
+      __syncthreads();
+      // splat-major: the lanes of a wavefront add consecutive sums of a few splats, so
+      // one atomic instruction touches a few gradient rows (cache lines), not 64
+      for (int i = threadIdx.x; i < 10 * nstage; i += NT) {
+        const int j = i / 10, k = i - 10 * j;
+        float* g = &(&s_g[0][0])[i];
+        const float v = *g;
+        if (v != 0.f) {
+          unsafeAtomicAdd(grad2d + int64_t(s_id[j]) * kGrad2D + k, v);
+          *g = 0.f;
+        }
+      }
+    }
   }
 }
 
@@ -2042,14 +2233,15 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
 
 // Persistent grid: blocks resident at once, at most `cap_per_cu` per compute unit (the
 // compositing kernels ran fastest below full occupancy on the headline view: blend_fwd at
-// 4 and blend_bwd at 5 blocks per CU, against 6 and more that fit).
-template <class Kern>
-static int resident_blocks(Kern kern, int threads, int cap_per_cu) {
-  static int cached = -1;
+// 4 blocks per CU, blend_bwd at 5 (one pixel per lane) and 7 (two pixels per lane, blocks
+// of half the size), against more that fit).
+template <auto KERN>
+static int resident_blocks(int threads, int cap_per_cu) {
+  static int cached = -1;  // one per kernel
   if (cached < 0) {
     int per_cu = 0, cus = 0, dev = 0;
     (void)hipGetDevice(&dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, KERN, threads, 0) != hipSuccess || per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
     (void)hipGetLastError();
@@ -2059,12 +2251,13 @@ static int resident_blocks(Kern kern, int threads, int cap_per_cu) {
 }
 constexpr int kFwdBlocksPerCU = 4;
 constexpr int kBwdBlocksPerCU = 5;
+constexpr int kBwd2BlocksPerCU = 7;
 
 template <int TS, int BATCH>
 static void blend_fwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
                         const uint32_t* vals, float* T_final, uint32_t* n_contrib, const TileQueue& q,
                         const Ckpt& ck, hipStream_t s) {
-  const int grid = std::min(vt.total_tiles, resident_blocks(k_blend_fwd<TS, BATCH>, TS * TS, kFwdBlocksPerCU));
+  const int grid = std::min(vt.total_tiles, resident_blocks<k_blend_fwd<TS, BATCH>>(TS * TS, kFwdBlocksPerCU));
   k_blend_fwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, q, ck);
 }
 
@@ -2123,9 +2316,15 @@ template <int TS, int BATCH>
 static void blend_bwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
                         const uint32_t* vals, const float* T_final, const uint32_t* n_contrib, float* grad2d,
                         const TileQueue& q, const Ckpt& ck, hipStream_t s) {
-  const int grid =
-      int(std::min<int64_t>(ck.cap_items, resident_blocks(k_blend_bwd<TS, BATCH>, TS * TS, kBwdBlocksPerCU)));
-  k_blend_bwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck);
+  if constexpr (TS >= 16) {  // two pixels per lane
+    const int grid = int(std::min<int64_t>(
+        ck.cap_items, resident_blocks<k_blend_bwd2<TS, BATCH>>(TS * TS / 2, kBwd2BlocksPerCU)));
+    k_blend_bwd2<TS, BATCH><<<grid, TS * TS / 2, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck);
+  } else {
+    const int grid =
+        int(std::min<int64_t>(ck.cap_items, resident_blocks<k_blend_bwd<TS, BATCH>>(TS * TS, kBwdBlocksPerCU)));
+    k_blend_bwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck);
+  }
 }
 
 hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
