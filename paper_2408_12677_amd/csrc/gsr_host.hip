@@ -379,12 +379,12 @@ void keep_hint(gsr_ctx* ctx, const gsr_saved* sv, hipStream_t s) {
 hipError_t enqueue_project(gsr_saved* sv, hipStream_t s, bool timing) {
   gsr_ctx* ctx = sv->ctx;
   auto T = [&](int k, auto f) { return timing ? timed(ctx, s, k, f) : f(); };
-  hipError_t e = T(K_FILL, [&] { return launch_fill_u32(sv->ctrl, 0u, kCtrlWords, s); });
-  if (e != hipSuccess || sv->N == 0) return e;
-  e = T(K_PROJECT, [&] {
+  // the projection clears the control words; without Gaussians a fill does
+  if (sv->N == 0) return T(K_FILL, [&] { return launch_fill_u32(sv->ctrl, 0u, kCtrlWords, s); });
+  hipError_t e = T(K_PROJECT, [&] {
     // a captured step zeroes its 2D-gradient rows here, for the records that are visible
     return launch_project(sv->deg, sv->g, sv->vt, sv->ru, sv->s.tile, sv->rec, sv->blocksums, sv->nblk, sv->grad2d,
-                          s);
+                          sv->ctrl, s);
   });
   if (e == hipSuccess)
     e = T(K_SCAN, [&] { return launch_scan_pairs(sv->blocksums, sv->V * sv->nblk, sv->d_total, s); });
@@ -431,7 +431,8 @@ hipError_t enqueue_sort_blend(gsr_saved* sv, hipStream_t s, bool timing) {
 // Backward launches for the view table `vt` (whose g_* pointers are set).  grad2d holds
 // V*N rows of kGrad2D floats followed by N * 3 floats of scratch for the colour term.
 hipError_t enqueue_backward(gsr_saved* sv, const ViewTable& vt, float* grad2d, const GradOut& go, hipStream_t s,
-                            bool timing, const AdamDev& adam = AdamDev{}, uint32_t* adam_state = nullptr) {
+                            bool timing, const AdamDev& adam = AdamDev{}, uint32_t* adam_state = nullptr,
+                            float* loss = nullptr) {
   gsr_ctx* ctx = sv->ctx;
   auto T = [&](int k, auto f) { return timing ? timed(ctx, s, k, f) : f(); };
   const int64_t VN = int64_t(sv->V) * sv->N;
@@ -441,7 +442,8 @@ hipError_t enqueue_backward(gsr_saved* sv, const ViewTable& vt, float* grad2d, c
   if (e == hipSuccess)
     e = T(K_BLEND_BWD, [&] {
       return launch_blend_bwd(sv->s.tile, sv->s.batch, vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final,
-                              sv->n_contrib, grad2d, queue_of(sv), sv->ck, s);
+                              sv->n_contrib, grad2d, queue_of(sv), sv->ck, s, sv->loss_part,
+                              loss ? loss_partials(vt) : 0, loss);
     });
   if (e == hipSuccess && adam.on) e = launch_adam_tick(adam_state, adam.b1, adam.b2, s);
   if (e == hipSuccess)
@@ -960,8 +962,10 @@ gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_came
   if (e == hipSuccess) {
     hipError_t k = enqueue_project(sv, cs, false);
     if (k == hipSuccess) k = enqueue_sort_blend(sv, cs, false);
-    if (k == hipSuccess) k = launch_loss_l1(lvt, depth_weight, sv->loss_part, loss_dev, cs);
-    if (k == hipSuccess) k = enqueue_backward(sv, bvt, sv->grad2d, go, cs, false, ad, opt ? opt->state : nullptr);
+    // the loss total is added up by the backward's first kernel
+    if (k == hipSuccess) k = launch_loss_l1(lvt, depth_weight, sv->loss_part, nullptr, cs);
+    if (k == hipSuccess)
+      k = enqueue_backward(sv, bvt, sv->grad2d, go, cs, false, ad, opt ? opt->state : nullptr, loss_dev);
     if (k == hipSuccess)
       k = hipMemcpyAsync(gr->h_flag, sv->ctrl + kOverflow, sizeof(uint32_t), hipMemcpyDeviceToHost, cs);
     e = hipStreamEndCapture(cs, &gr->graph);

@@ -264,9 +264,11 @@ hipError_t launch_seed_emit(const SeedImage& im, const SeedRules& r, const uint3
 hipError_t launch_scan_small(uint32_t* a, int count, unsigned long long* total, hipStream_t s);
 // Device-side counts (unsigned long long) are clamped by each kernel to the capacity its
 // grid and buffers were sized for.
-// zero_rows (may be null): 2D-gradient rows (kGrad2D floats) zeroed for every visible record
+// zero_rows (may be null): 2D-gradient rows (kGrad2D floats) zeroed for every visible record;
+// the first block also zeroes the kCtrlWords control words `ctrl`
 hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru, int tile,
-                          const Records& rec, uint2* blocksums, int nblk, float* zero_rows, hipStream_t s);
+                          const Records& rec, uint2* blocksums, int nblk, float* zero_rows, uint32_t* ctrl,
+                          hipStream_t s);
 hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* totals, hipStream_t s);
 hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
                           const unsigned long long* pairs, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
@@ -298,12 +300,16 @@ hipError_t launch_count_used(const ViewTable& vt, const Rules& ru, const Records
                              const uint32_t* vals, const uint32_t* n_contrib, int tile, int64_t total_pix,
                              uint32_t* n_used, hipStream_t s);
 int loss_partials(const ViewTable& vt);  // block partial sums launch_loss_l1 writes
+// Loss partial sums, and their total into *loss unless loss is null (then the caller has
+// launch_blend_bwd add them up).
 hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* part, float* loss, hipStream_t s);
-// Lists the backward's (tile, stride) work items, then runs them.
+// Lists the backward's (tile, stride) work items, then runs them; with loss non-null the
+// listing kernel also writes the total of the loss_np partial sums loss_part to *loss.
 hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, const float* T_final,
                             const uint32_t* n_contrib, float* grad2d, const TileQueue& q, const Ckpt& ck,
-                            hipStream_t s);
+                            hipStream_t s, const float* loss_part = nullptr, int loss_np = 0,
+                            float* loss = nullptr);
 // grad2d holds V*N rows of kGrad2D floats; dp_sh is scratch for N * 3 floats.  With
 // adam.on the parameter gradients are not written to `out` but applied to the parameters
 // by one Adam step (adam.bc must already hold the step's bias corrections).

@@ -447,9 +447,11 @@ __device__ __forceinline__ void sh_grad_dot(float x, float y, float z, const flo
 template <int DEG>
 __global__ __launch_bounds__(kProjThreads) void k_project(GaussDev g, ViewTable vt, Rules ru, int tile,
                                                           Records rec, uint2* blocksums, int nblk,
-                                                          float* zero_rows) {
+                                                          float* zero_rows, uint32_t* ctrl) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ uint32_t red[kProjThreads / 64];
+  // the step's control words start at zero (no kernel before the projection reads them)
+  if (blockIdx.x == 0 && threadIdx.x < kCtrlWords) ctrl[threadIdx.x] = 0u;
   const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
   const bool valid = gi < g.n;
   float p[3] = {0.f, 0.f, 0.f}, s[3] = {1.f, 1.f, 1.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, op = 0.f;
@@ -1416,9 +1418,9 @@ __global__ __launch_bounds__(256) void k_loss_l1(ViewTable vt, float depth_w, fl
   if (threadIdx.x == 0) partial[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// the loss: the block partial sums added in a fixed order (deterministic)
-__global__ __launch_bounds__(1024) void k_loss_sum(const float* part, int count, float* loss) {
-  __shared__ float red[16];
+// the loss: the block partial sums added in a fixed order (deterministic), by a block of
+// 1024 threads
+__device__ __forceinline__ void sum_loss_partials(const float* part, int count, float* loss, float* red) {
   float v = 0.f;
   for (int i = threadIdx.x; i < count; i += 1024) v += part[i];
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -1429,6 +1431,11 @@ __global__ __launch_bounds__(1024) void k_loss_sum(const float* part, int count,
     for (int i = 0; i < 16; ++i) t += red[i];
     *loss = t;
   }
+}
+
+__global__ __launch_bounds__(1024) void k_loss_sum(const float* part, int count, float* loss) {
+  __shared__ float red[16];
+  sum_loss_partials(part, count, loss, red);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1449,8 +1456,12 @@ __global__ __launch_bounds__(1024) void k_loss_sum(const float* part, int count,
 // checkpoint stride k that holds a contributor of some pixel of the tile, up to the
 // tile's last checkpoint; one more item (tile, kmax) covers all later entries.  One block.
 __global__ __launch_bounds__(1024) void k_bwd_items(const uint32_t* order, int total, int batch, Ckpt ck,
-                                                   uint32_t* ctrl) {
+                                                   uint32_t* ctrl, const float* loss_part, int loss_np,
+                                                   float* loss) {
   __shared__ uint32_t red[16], carry;
+  __shared__ float fred[16];
+  // a captured step also adds up its loss here (one launch fewer)
+  if (loss) sum_loss_partials(loss_part, loss_np, loss, fred);
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (int i0 = 0; i0 < total; i0 += 1024) {
@@ -2082,14 +2093,15 @@ inline unsigned blocks_for(int64_t n, int per) { return unsigned((n + per - 1) /
 // launchers
 // ------------------------------------------------------------------------------------
 hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru, int tile,
-                          const Records& rec, uint2* blocksums, int nblk, float* zero_rows, hipStream_t s) {
+                          const Records& rec, uint2* blocksums, int nblk, float* zero_rows, uint32_t* ctrl,
+                          hipStream_t s) {
   if (nblk == 0) return hipSuccess;
   dim3 grid(nblk), block(kProjThreads);
   switch (deg) {
-    case 0: k_project<0><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows); break;
-    case 1: k_project<1><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows); break;
-    case 2: k_project<2><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows); break;
-    default: k_project<3><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows); break;
+    case 0: k_project<0><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl); break;
+    case 1: k_project<1><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl); break;
+    case 2: k_project<2><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl); break;
+    default: k_project<3><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl); break;
   }
   return hipGetLastError();
 }
@@ -2308,7 +2320,7 @@ int loss_partials(const ViewTable& vt) {
 hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* part, float* loss, hipStream_t s) {
   const int np = loss_partials(vt);
   k_loss_l1<<<dim3(np / vt.nviews, vt.nviews), 256, 0, s>>>(vt, depth_w, part);
-  k_loss_sum<<<1, 1024, 0, s>>>(part, np, loss);
+  if (loss) k_loss_sum<<<1, 1024, 0, s>>>(part, np, loss);
   return hipGetLastError();
 }
 
@@ -2330,9 +2342,9 @@ static void blend_bwd_t(const ViewTable& vt, const Rules& ru, const Records& rec
 hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, const float* T_final,
                             const uint32_t* n_contrib, float* grad2d, const TileQueue& q, const Ckpt& ck,
-                            hipStream_t s) {
+                            hipStream_t s, const float* loss_part, int loss_np, float* loss) {
   if (vt.total_tiles == 0) return hipSuccess;
-  k_bwd_items<<<1, 1024, 0, s>>>(q.order, vt.total_tiles, ckpt_stride(batch), ck, q.ctrl);
+  k_bwd_items<<<1, 1024, 0, s>>>(q.order, vt.total_tiles, ckpt_stride(batch), ck, q.ctrl, loss_part, loss_np, loss);
   const bool b256 = batch == 256;
   switch (tile) {
     case 8: b256 ? blend_bwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck, s)
