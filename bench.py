@@ -104,7 +104,11 @@ def short_kernel_name(full):
     n = full.split("(gsr::")[0] if full.startswith("void gsr::") else full
     n = n.replace("void ", "").replace("gsr::(anonymous namespace)::", "")
     n = n.split("(")[0].split("<")[0].strip()
-    return n[2:] if n.startswith("k_") else n
+    n = n[2:] if n.startswith("k_") else n
+    # variants of one kernel (two pixels per lane, slots in registers) share its name
+    if n.endswith("_r"):
+        n = n[:-2]
+    return "blend_bwd" if n == "blend_bwd2" else n
 
 
 def traffic_from_counters(fetch_dir, write_dir, copy_mb):
