@@ -1662,10 +1662,11 @@ __global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Re
   }
 }
 
-// K8 with two vertically adjacent pixels per lane (tiles of 16 and 32): a wavefront
-// covers 128 pixels, so each splat's ten partials are reduced across the wavefront once
-// for twice the pixels (the pair's partials are added first).  Same per-pixel arithmetic
-// and work items as k_blend_bwd.
+// K8 with PPL vertically adjacent pixels per lane (tiles of 16 and 32): with two, a
+// wavefront covers 128 pixels, so each splat's ten partials are reduced across the
+// wavefront once for twice the pixels (the pair's partials are added first).  Same
+// per-pixel arithmetic and work items as k_blend_bwd.  Two per lane is the build's
+// choice (kBwdPixelsPerLane); four ran slower on the headline view.
 struct BwdPixel {
   float T, Tfin, gC0, gC1, gC2, gD, gA, BC0, BC1, BC2, BD, fpy;
   int top;
@@ -1759,12 +1760,12 @@ __device__ __forceinline__ void bwd_pixel_step(BwdPixel& s, bool act, float a, f
   g[4] += -0.5f * dpw * dy * dy;
 }
 
-template <int TS, int BATCH>
-__global__ __launch_bounds__(TS* TS / 2) void k_blend_bwd2(ViewTable vt, Rules ru, Records rec, const uint2* ranges,
-                                                          const uint32_t* vals, const float* T_final,
-                                                          const uint32_t* n_contrib, float* grad2d, TileQueue q,
-                                                          Ckpt ck) {
-  constexpr int NT = TS * TS / 2;  // threads: pixels (2r, c) and (2r + 1, c) for t = r TS + c
+template <int TS, int BATCH, int PPL>
+__global__ __launch_bounds__(TS* TS / PPL) void k_blend_bwd2(ViewTable vt, Rules ru, Records rec,
+                                                            const uint2* ranges, const uint32_t* vals,
+                                                            const float* T_final, const uint32_t* n_contrib,
+                                                            float* grad2d, TileQueue q, Ckpt ck) {
+  constexpr int NT = TS * TS / PPL;  // threads: pixels (PPL r + i, c), i < PPL, for t = r TS + c
   __shared__ float4 s_r0[BATCH];
   __shared__ float4 s_r1[BATCH];
   __shared__ float4 s_rgb[BATCH];
@@ -1775,7 +1776,7 @@ __global__ __launch_bounds__(TS* TS / 2) void k_blend_bwd2(ViewTable vt, Rules r
   for (int i = threadIdx.x; i < 10 * BATCH; i += NT) (&s_g[0][0])[i] = 0.f;
   const int total = int(q.ctrl[kItems]);
   const int lane = threadIdx.x & 63;
-  const int cx = int(threadIdx.x % TS), ry = 2 * int(threadIdx.x / TS);
+  const int cx = int(threadIdx.x % TS), ry = PPL * int(threadIdx.x / TS);
   for (;;) {
     const int item = next_item(q.ctrl + kHeadBwd, total, &s_item);
     if (item < 0) return;
@@ -1789,10 +1790,14 @@ __global__ __launch_bounds__(TS* TS / 2) void k_blend_bwd2(ViewTable vt, Rules r
     constexpr int CK = BATCH / 2;  // checkpoint stride of the forward
     const int lo = bf * CK;        // the item's list entries: [lo, hi)
     const int hi = bf < ck.kmax ? lo + CK : int(rg.y - rg.x);
-    BwdPixel p0, p1;
-    bwd_pixel_setup<TS>(p0, cam, ru, ck, T_final, n_contrib, tile, bf, lo, hi, px, py, ry * TS + cx);
-    bwd_pixel_setup<TS>(p1, cam, ru, ck, T_final, n_contrib, tile, bf, lo, hi, px, py + 1, (ry + 1) * TS + cx);
-    const int wmax = int(wave_max_u32(uint32_t(max(p0.top, p1.top))));
+    BwdPixel p[PPL];
+    int ptop = 0;
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+      bwd_pixel_setup<TS>(p[i], cam, ru, ck, T_final, n_contrib, tile, bf, lo, hi, px, py + i, (ry + i) * TS + cx);
+      ptop = max(ptop, p[i].top);
+    }
+    const int wmax = int(wave_max_u32(uint32_t(ptop)));
     if (threadIdx.x == 0) s_max = 0;
     __syncthreads();
     if (lane == 0 && wmax) atomicMax(&s_max, uint32_t(wmax));
@@ -1813,17 +1818,21 @@ __global__ __launch_bounds__(TS* TS / 2) void k_blend_bwd2(ViewTable vt, Rules r
         const float4 r0 = s_r0[j];
         const float4 r1 = s_r1[j];
         const float dx = fpx - r0.x;
-        const float dy0 = p0.fpy - r0.y, dy1 = p1.fpy - r0.y;
-        float G0, G1;
-        const float a0 = splat_alpha(dx, dy0, r0.z, r0.w, r1.x, r1.y, G0);
-        const float a1 = splat_alpha(dx, dy1, r0.z, r0.w, r1.x, r1.y, G1);
-        const bool act0 = bstart + j < p0.top && !(a0 < ru.amin);
-        const bool act1 = bstart + j < p1.top && !(a1 < ru.amin);
-        if (__ballot(act0 || act1) == 0ull) continue;
+        float dy[PPL], a[PPL], G[PPL];
+        bool act[PPL];
+        bool any = false;
+#pragma unroll
+        for (int i = 0; i < PPL; ++i) {
+          dy[i] = p[i].fpy - r0.y;
+          a[i] = splat_alpha(dx, dy[i], r0.z, r0.w, r1.x, r1.y, G[i]);
+          act[i] = bstart + j < p[i].top && !(a[i] < ru.amin);
+          any = any || act[i];
+        }
+        if (__ballot(any) == 0ull) continue;
         const float4 c = s_rgb[j];
         float gv[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        bwd_pixel_step(p0, act0, a0, G0, dx, dy0, r0, r1, c, ru, gv);
-        bwd_pixel_step(p1, act1, a1, G1, dx, dy1, r0, r1, c, ru, gv);
+#pragma unroll
+        for (int i = 0; i < PPL; ++i) bwd_pixel_step(p[i], act[i], a[i], G[i], dx, dy[i], r0, r1, c, ru, gv);
         float w0, w1, w2;
         wave_sum10(gv, w0, w1, w2);
         if ((lane & 15) == 0) {  // one lane per row adds its row's totals
@@ -2264,6 +2273,7 @@ static int resident_blocks(int threads, int cap_per_cu) {
 constexpr int kFwdBlocksPerCU = 4;
 constexpr int kBwdBlocksPerCU = 5;
 constexpr int kBwd2BlocksPerCU = 7;
+constexpr int kBwdPixelsPerLane = 2;
 
 template <int TS, int BATCH>
 static void blend_fwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
@@ -2328,10 +2338,12 @@ template <int TS, int BATCH>
 static void blend_bwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
                         const uint32_t* vals, const float* T_final, const uint32_t* n_contrib, float* grad2d,
                         const TileQueue& q, const Ckpt& ck, hipStream_t s) {
-  if constexpr (TS >= 16) {  // two pixels per lane
+  if constexpr (TS >= 16) {  // kBwdPixelsPerLane pixels per lane
+    constexpr int PPL = kBwdPixelsPerLane;
     const int grid = int(std::min<int64_t>(
-        ck.cap_items, resident_blocks<k_blend_bwd2<TS, BATCH>>(TS * TS / 2, kBwd2BlocksPerCU)));
-    k_blend_bwd2<TS, BATCH><<<grid, TS * TS / 2, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck);
+        ck.cap_items, resident_blocks<k_blend_bwd2<TS, BATCH, PPL>>(TS * TS / PPL, kBwd2BlocksPerCU)));
+    k_blend_bwd2<TS, BATCH, PPL><<<grid, TS * TS / PPL, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d,
+                                                                q, ck);
   } else {
     const int grid =
         int(std::min<int64_t>(ck.cap_items, resident_blocks<k_blend_bwd<TS, BATCH>>(TS * TS, kBwdBlocksPerCU)));
