@@ -2258,33 +2258,50 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
 }
 
 // Persistent grid: blocks resident at once, at most `cap_per_cu` per compute unit (the
-// compositing kernels ran fastest below full occupancy on the headline view: blend_fwd at
-// 4 blocks per CU, blend_bwd at 5 (one pixel per lane) and 7 (two pixels per lane, blocks
-// of half the size), against more that fit).
+// compositing kernels ran fastest below full occupancy: blend_fwd at 2 blocks per CU on
+// one 640x480 view, where its heaviest tiles' single-wavefront chains bound it and then
+// share a SIMD with fewer others, and at 4 with many tiles per CU (eight views);
+// blend_bwd at 5 (one pixel per lane) and 8 (two pixels per lane, blocks of half the
+// size), against more that fit).
 template <auto KERN>
 static int resident_blocks(int threads, int cap_per_cu) {
-  static int cached = -1;  // one per kernel
-  if (cached < 0) {
-    int per_cu = 0, cus = 0, dev = 0;
+  static int per_cu = -1, cus = 1;  // one pair per kernel
+  if (per_cu < 0) {
+    int p = 0, c = 0, dev = 0;
     (void)hipGetDevice(&dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, KERN, threads, 0) != hipSuccess || per_cu < 1)
-      per_cu = 1;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, KERN, threads, 0) != hipSuccess || p < 1) p = 1;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) c = 1;
     (void)hipGetLastError();
-    cached = std::min(per_cu, cap_per_cu) * cus;
+    cus = c;
+    per_cu = p;
   }
-  return cached;
+  return std::min(per_cu, cap_per_cu) * cus;
 }
-constexpr int kFwdBlocksPerCU = 4;
+
+static int device_cus() {
+  static int cus = -1;
+  if (cus < 0) {
+    int c = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) c = 1;
+    (void)hipGetLastError();
+    cus = c;
+  }
+  return cus;
+}
+constexpr int kFwdBlocksPerCU = 2;        // up to kFwdManyTilesPerCU tiles per CU
+constexpr int kFwdBlocksPerCUMany = 4;    // beyond
+constexpr int kFwdManyTilesPerCU = 16;
 constexpr int kBwdBlocksPerCU = 5;
-constexpr int kBwd2BlocksPerCU = 7;
+constexpr int kBwd2BlocksPerCU = 8;
 constexpr int kBwdPixelsPerLane = 2;
 
 template <int TS, int BATCH>
 static void blend_fwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
                         const uint32_t* vals, float* T_final, uint32_t* n_contrib, const TileQueue& q,
                         const Ckpt& ck, hipStream_t s) {
-  const int grid = std::min(vt.total_tiles, resident_blocks<k_blend_fwd<TS, BATCH>>(TS * TS, kFwdBlocksPerCU));
+  const int cap = vt.total_tiles > kFwdManyTilesPerCU * device_cus() ? kFwdBlocksPerCUMany : kFwdBlocksPerCU;
+  const int grid = std::min(vt.total_tiles, resident_blocks<k_blend_fwd<TS, BATCH>>(TS * TS, cap));
   k_blend_fwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, q, ck);
 }
 
