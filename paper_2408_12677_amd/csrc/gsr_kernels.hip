@@ -1325,20 +1325,35 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
           a4[u] = splat_alpha(fpx - r0.x, fpy - r0.y, r0.z, r0.w, r1.x, r1.y, G);
           z4[u] = r1.z;
         }
+        // The group in list order with a short dependency chain: Tk[u] is the
+        // transmittance in front of entry u as if no stop came first (a plain chain of
+        // products); since transmittance never rises, the pixel has stopped before
+        // entry u exactly when it was stopped on entry or Tk[u] < T_min, and up to that
+        // entry Tk[u] is the true transmittance.  So every entry's decision and weight
+        // are those of the entry-by-entry recurrence (same products, same order), and
+        // the transmittance after the group is Tk at the first stopped position.
+        float Tk[kFwdGroup + 1], alv[kFwdGroup];
+        Tk[0] = T;
 #pragma unroll
         for (int u = 0; u < kFwdGroup; ++u) {
-          const float a = a4[u];
-          const bool act = !done && !(a < ru.amin);
-          const float al = act ? fminf(a, ru.amax) : 0.f;  // 0: adds nothing, keeps T
-          const float wgt = al * T;
+          alv[u] = !(a4[u] < ru.amin) ? fminf(a4[u], ru.amax) : 0.f;  // 0: skipped, keeps T
+          Tk[u + 1] = Tk[u] * (1.f - alv[u]);
+        }
+        float Tn = Tk[kFwdGroup];
+#pragma unroll
+        for (int u = kFwdGroup - 1; u >= 0; --u) Tn = (done || Tk[u] < ru.Tmin) ? Tk[u] : Tn;
+#pragma unroll
+        for (int u = 0; u < kFwdGroup; ++u) {
+          const bool act = !(done || Tk[u] < ru.Tmin) && !(a4[u] < ru.amin);
+          const float wgt = act ? alv[u] * Tk[u] : 0.f;
           C0 += c4[u].x * wgt;
           C1 += c4[u].y * wgt;
           C2 += c4[u].z * wgt;
           D += z4[u] * wgt;
-          T = T * (1.f - al);
           last = act ? uint32_t(b0 + j + u + 1) : last;
-          done = done || T < ru.Tmin;
         }
+        T = Tn;
+        done = done || Tn < ru.Tmin;
       }
     }
     if (inside) {
