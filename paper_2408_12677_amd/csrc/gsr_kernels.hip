@@ -2188,15 +2188,16 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
 }
 
 BinPlan bin_plan(const ViewTable& vt, int64_t cap_vis, int64_t cap_M) {
-  // two 64-item rounds per wavefront when the count arrays stay within kMaxBinCounts
-  // entries; more rounds (fewer, longer chunks) beyond that
+  // one 64-item round per wavefront (chunks and segments of 64: the most placement waves
+  // in parallel) while the count arrays stay within kMaxBinCounts entries; more rounds
+  // (fewer, longer chunks) beyond that
   BinPlan p{};
   p.rows = vt.total_rows;
   const int64_t max_chunks = std::max<int64_t>(1, kMaxBinCounts / std::max(1, p.rows));
-  p.rounds1 = int(std::max<int64_t>(2, (cap_vis + 64 * max_chunks - 1) / (64 * max_chunks)));
+  p.rounds1 = int(std::max<int64_t>(1, (cap_vis + 64 * max_chunks - 1) / (64 * max_chunks)));
   p.nch1 = int(std::max<int64_t>(1, (cap_vis + 64 * p.rounds1 - 1) / (64 * p.rounds1)));
   const int64_t max_segs = std::max<int64_t>(1024, kMaxBinCounts / std::max(1, vt.max_tiles_x));
-  p.rounds2 = int(std::max<int64_t>(2, (cap_M + 64 * max_segs - 1) / (64 * max_segs)));
+  p.rounds2 = int(std::max<int64_t>(1, (cap_M + 64 * max_segs - 1) / (64 * max_segs)));
   const int64_t S2 = 64 * int64_t(p.rounds2);
   const int64_t segs = (cap_M + S2 - 1) / S2;
   p.cap_M = cap_M;
@@ -2226,7 +2227,7 @@ hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const 
   auto B = [&](int k) { if (tm) tm->begin(k); };
   auto E = [&](int k) { if (tm) tm->end(k); };
   const size_t lds_rows = size_t(plan.rows) * 4, lds_cols = size_t(vt.max_tiles_x) * 4;
-  const int g_count = int(std::min<int64_t>(plan.cap_seg, 4096));
+  const int g_count = int(std::min<int64_t>(plan.cap_seg, 16384));
   const int g_scatter = int(std::min<int64_t>(plan.cap_seg, 16384));
   B(K_BIN_COUNT);
   k_bin_rows_count<<<plan.nch1, 256, lds_rows, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
