@@ -313,8 +313,10 @@ gsr_status gsr_graph_free(gsr_graph* gr);
  * architecture, CU count, log2 of the total pixel count and of N, SH degree and V; a
  * cached entry is used without timing unless GSR_AUTOTUNE_NO_CACHE is set.  The forward
  * images do not depend on the choice (the extent keeps every splat value >= alpha_min
- * inside its tile rectangle).  Each choice is timed as the median of seven eager steps after
- * two warm-up steps, a step's time being the sum of its kernels' durations.  best_ms (may be NULL) receives that median for the chosen shape. */
+ * inside its tile rectangle).  After two warm-up steps each, the candidates take turns, one
+ * eager step per turn, nine turns; each is scored by the median of its nine steps, a step's
+ * time being the sum of its kernels' durations.  best_ms (may be NULL) receives that median
+ * for the chosen shape. */
 #define GSR_AUTOTUNE_NO_CACHE 1u
 gsr_status gsr_autotune(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
                         gsr_settings* s, uint32_t flags, float* best_ms);
