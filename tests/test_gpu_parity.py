@@ -127,6 +127,26 @@ def test_forward_is_deterministic(R):
         assert torch.equal(x, y)
 
 
+def test_work_ordered_queue_leaves_results_unchanged(R):
+    """A forward over the same tiles as an earlier one orders its tile queue by the earlier
+    one's per-tile work and raises the heaviest tiles' wave priority: scheduling only, so
+    the images and every per-pixel count are bit-identical to a forward without that
+    order (the first one over a tile grid no other test uses)."""
+    w = scenes.make_cfg1()
+    cam = w.cameras[0].crop(5, 3, 117, 89)   # a grid of its own: the first forward has no order hint
+    s = settings(tile=8)
+    _, a, sa = run_fwd(R, w.gaussians, [cam], s)
+    da = sa.debug_export()
+    _, b, sb = run_fwd(R, w.gaussians, [cam], s)
+    db = sb.debug_export()
+    for x, y in zip(a[0], b[0]):
+        assert torch.equal(x, y)
+    for k in ("n_contrib", "n_used", "T_final", "ranges", "values"):
+        np.testing.assert_array_equal(da[k], db[k], err_msg=k)
+    sa.free()
+    sb.free()
+
+
 # ---------------------------------------------------------------------------------------
 # forward + backward
 # ---------------------------------------------------------------------------------------
