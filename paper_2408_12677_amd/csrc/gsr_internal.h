@@ -165,9 +165,9 @@ struct Records {
   uint32_t* counts; // tiles touched, 0 when culled
 };
 
-// Longest-list-first tile order and the control words of the persistent compositing
-// kernels: kHeadFwd / kHeadBwd queue heads, kOverflow the capacity-overflow flag, kItems
-// the number of backward work items.
+// Heaviest-first tile order (k_tile_order) and the control words of the persistent
+// compositing kernels: kHeadFwd / kHeadBwd queue heads, kOverflow the capacity-overflow
+// flag, kItems the number of backward work items.
 struct TileQueue {
   const uint32_t* order;
   uint32_t* ctrl;

@@ -10,12 +10,14 @@
 //                       ballot-multisplit scatter); k_bin_* then bin that depth order stably,
 //                       first into tile rows, then into the tiles of each row, so every
 //                       tile receives its records in ascending (depth, record) order
-//   K5                  the tile ranges come from the binning's scan (k_bin_ranges)
+//   K5                  the tile ranges come from the binning's scan (k_bin_ranges);
+//                       k_tile_order queues the tiles heaviest first
 //   K6 k_blend_fwd      per tile: front-to-back compositing, Eq. 11 with clamp/skip/stop
 //   K7 k_loss_l1        Eq. 12 (mean L1 colour) + weighted mean L1 depth, its gradient
-//   K8 k_blend_bwd      per tile, back to front: transmittance recovered by division,
-//                       per-(pixel, splat) partials reduced across the wavefront with DPP
-//                       and added with one set of float atomics per (wavefront, splat)
+//   K8 k_blend_bwd2     per (tile, stride) item, back to front: transmittance recovered by
+//      (k_blend_bwd)    division, per-(pixel, splat) partials of two pixels per lane
+//                       (one for tiles of 8) reduced across the wavefront with DPP, summed
+//                       per splat in LDS and added with float atomics, splat-major
 //   K9 k_project_bwd    per Gaussian, loop over views: chain rule to means, scales,
 //                       rotations, opacities and SH coefficients
 //
