@@ -9,7 +9,7 @@
  * depth inside every screen tile, alpha-blends them front to back (Eq. 11) into
  * colour, depth and alpha images, evaluates the L1 loss of Eq. 12 (plus an optional
  * weighted L1 depth term), and propagates the loss gradient back to every Gaussian
- * parameter ("all the gradients for parameters are explicitly derived").
+ * parameter in closed form (Sec. III-B-3, the optimisation paragraph).
  *
  * Conventions
  *  - Every buffer pointer handed to the library is DEVICE memory on the context's
@@ -87,7 +87,7 @@ typedef struct {
  * outside its tile rectangle), low-pass 0.3 px^2 on the projected covariance,
  * alpha_min 1/255 (strictly smaller values are skipped), alpha_max 0.99 (clamp),
  * T_min 1e-4 (stop after the Gaussian that takes transmittance below it), guard 0.15
- * (only Gaussians "lying in the current view frustum" are rendered: the projected
+ * (only Gaussians inside the view frustum are rendered, Sec. III-B-3: the projected
  * centre must fall inside the image widened by guard x its width/height on each
  * side, and the depth must exceed znear), black background. */
 typedef struct {
@@ -223,10 +223,16 @@ gsr_status gsr_loss_l1(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_out*
 
 #define GSR_ACCUMULATE 1u /* add into the gradient buffers instead of overwriting */
 
-/* Backward pass: given dL/d(outputs) per view, write dL/d(parameters) of the
- * Gaussians saved by gsr_forward, summed over views.  Transmittance is recovered
- * per pixel from the saved final value; no per-(pixel, Gaussian) state is stored.
- * Floating-point atomics make the summation order (not the value) nondeterministic. */
+/* Backward pass (Sec. III-B-3: the closed-form gradients of the blended images of Eq. 11
+ * with respect to every Gaussian parameter, taken back through the projection of Eq. 3-5
+ * and the SH colour): given dL/d(outputs) per view (grads[V], device images of the view's
+ * shape, NULL members = zero), write dL/d(parameters) of the Gaussians saved by
+ * gsr_forward, summed over views, into out (parameter layouts; a NULL member skips that
+ * group).  flags: GSR_ACCUMULATE adds into out instead of overwriting it.  Transmittance
+ * is recovered per pixel from the saved final value and per-tile checkpoints; no
+ * per-(pixel, Gaussian) state is stored.  Floating-point atomics make the summation order
+ * (not the value) nondeterministic.  EINVAL for NULL saved/grads/out or unknown flags;
+ * the saved state stays valid and may be used again. */
 gsr_status gsr_backward(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_grad* grads,
                         const gsr_gaussian_grads* out, uint32_t flags);
 
@@ -286,12 +292,14 @@ gsr_status gsr_backward_adam(gsr_ctx* ctx, const gsr_saved* saved, const gsr_vie
  * bound at capture: a launch re-runs the step on the current contents of the same
  * buffers (parameters, targets, images, gradients).  Buffers are sized from one eager
  * forward of the given inputs times (1 + headroom).  A launch whose key or visible-record
- * count exceeds those capacities sets a device flag; it is read back asynchronously and
- * reported as GSR_ECAPACITY by the next gsr_graph_launch that finds the earlier step
- * complete, or by gsr_graph_sync.  Gradients are overwritten on every launch.  With opt
- * (may be NULL) the step ends with one Adam step fused into the backward, as in
+ * count exceeds those capacities sets a device flag that stays set for the graph's
+ * lifetime; it is read back asynchronously and reported as GSR_ECAPACITY by the next
+ * gsr_graph_launch that finds an earlier step complete, and by gsr_graph_sync (the graph
+ * must then be re-created).  Gradients are overwritten on every launch.  With opt (may be
+ * NULL) the step ends with one Adam step fused into the backward, as in
  * gsr_backward_adam: every launch is then one complete optimisation iteration that updates
- * the Gaussian arrays of g in place, and grads may be NULL. */
+ * the Gaussian arrays of g in place, and grads may be NULL; a launch that overflowed, and
+ * every launch after it, leaves the parameters, the moments and the step count unchanged. */
 gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
                             const gsr_settings* s, const gsr_view_out* outs, const gsr_target* targets,
                             float depth_weight, float* const* grad_color, float* const* grad_depth,

@@ -28,6 +28,7 @@ struct AdamDev {
   float lr[G_COUNT + 1];  // means, log-scales, quaternions, opacity logits, SH DC, SH rest
   float b1, b2, eps;
   int on;
+  const uint32_t* skip;  // device word or null: the fused update leaves everything unchanged when it is set
 };
 
 // Step counter words (device, caller-owned): [0] steps taken (u32), [1] bc1, [2] bc2.

@@ -71,6 +71,7 @@ struct gsr_saved {
   float* grad2d = nullptr;  // graph only (eager backward allocates its own)
   int64_t total_pix = 0;
   int sort_passes = 0;
+  bool graph = false;  // a captured step: the sticky overflow word survives its steps
   std::vector<void*> blocks;  // persistent allocations, released on free
   std::vector<void*> temps;   // eager-forward temporaries
 };
@@ -379,12 +380,14 @@ void keep_hint(gsr_ctx* ctx, const gsr_saved* sv, hipStream_t s) {
 hipError_t enqueue_project(gsr_saved* sv, hipStream_t s, bool timing) {
   gsr_ctx* ctx = sv->ctx;
   auto T = [&](int k, auto f) { return timing ? timed(ctx, s, k, f) : f(); };
-  // the projection clears the control words; without Gaussians a fill does
-  if (sv->N == 0) return T(K_FILL, [&] { return launch_fill_u32(sv->ctrl, 0u, kCtrlWords, s); });
+  // the projection clears the control words (a captured step keeps its sticky overflow
+  // word); without Gaussians a fill does
+  const int clear = sv->graph ? kStepWords : kCtrlWords;
+  if (sv->N == 0) return T(K_FILL, [&] { return launch_fill_u32(sv->ctrl, 0u, clear, s); });
   hipError_t e = T(K_PROJECT, [&] {
     // a captured step zeroes its 2D-gradient rows here, for the records that are visible
     return launch_project(sv->deg, sv->g, sv->vt, sv->ru, sv->s.tile, sv->rec, sv->blocksums, sv->nblk, sv->grad2d,
-                          sv->ctrl, s);
+                          sv->ctrl, clear, s);
   });
   if (e == hipSuccess)
     e = T(K_SCAN, [&] { return launch_scan_pairs(sv->blocksums, sv->V * sv->nblk, sv->d_total, s); });
@@ -445,7 +448,7 @@ hipError_t enqueue_backward(gsr_saved* sv, const ViewTable& vt, float* grad2d, c
                               sv->n_contrib, grad2d, queue_of(sv), sv->ck, s, sv->loss_part,
                               loss ? loss_partials(vt) : 0, loss);
     });
-  if (e == hipSuccess && adam.on) e = launch_adam_tick(adam_state, adam.b1, adam.b2, s);
+  if (e == hipSuccess && adam.on) e = launch_adam_tick(adam_state, adam.b1, adam.b2, adam.skip, s);
   if (e == hipSuccess)
     e = T(K_PROJECT_BWD, [&] {
       return launch_project_bwd(sv->deg, sv->g, vt, sv->ru, sv->rec, grad2d, grad2d + VN * kGrad2D, go, adam, s);
@@ -727,6 +730,7 @@ gsr_status gsr_backward_adam(gsr_ctx* ctx, const gsr_saved* saved, const gsr_vie
   AdamDev ad;
   gsr_status st = adam_dev(ctx, opt, p, &ad);
   if (st != GSR_OK) return st;
+  ad.skip = sv->ctrl + kOverflowSticky;
   const ViewTable vt = with_grads(sv, grads);
   const int64_t VN = int64_t(sv->V) * sv->N;
   if ((st = bwd_scratch(ctx, (size_t(VN) * kGrad2D + size_t(sv->N) * 3) * sizeof(float))) != GSR_OK) return st;
@@ -765,7 +769,7 @@ gsr_status gsr_adam_step(gsr_ctx* ctx, int64_t n, int32_t sh_degree, const gsr_g
   gsr_status st = adam_dev(ctx, opt, p, &ad);
   if (st != GSR_OK) return st;
   hipStream_t s = ctx->stream;
-  GSR_HIP(ctx, launch_adam_tick(opt->state, ad.b1, ad.b2, s));
+  GSR_HIP(ctx, launch_adam_tick(opt->state, ad.b1, ad.b2, nullptr, s));
   GSR_HIP(ctx, timed(ctx, s, K_ADAM, [&] { return launch_adam(ad, g, n, sh_degree, s); }));
   return GSR_OK;
 }
@@ -912,6 +916,7 @@ gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_came
     return st;
   }
   gsr_saved* sv = gr->sv;
+  sv->graph = true;
   sv->M = M;
   sv->n_vis = NV;
   if ((st = alloc_sort(sv, cap_vis, cap_M, true)) != GSR_OK ||
@@ -946,9 +951,12 @@ gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_came
       graph_destroy(gr);
       return st;
     }
+    ad.skip = sv->ctrl + kOverflowSticky;  // no update once any launch has overflowed
   }
 
   hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&gr->h_flag), sizeof(uint32_t), hipHostMallocDefault);
+  // every control word starts at zero once; the steps clear only their own words
+  if (e == hipSuccess) e = launch_fill_u32(sv->ctrl, 0u, kCtrlWords, ctx->stream);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&gr->done, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&gr->capture, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);  // buffers allocated on ctx->stream are ready
@@ -967,7 +975,7 @@ gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_came
     if (k == hipSuccess)
       k = enqueue_backward(sv, bvt, sv->grad2d, go, cs, false, ad, opt ? opt->state : nullptr, loss_dev);
     if (k == hipSuccess)
-      k = hipMemcpyAsync(gr->h_flag, sv->ctrl + kOverflow, sizeof(uint32_t), hipMemcpyDeviceToHost, cs);
+      k = hipMemcpyAsync(gr->h_flag, sv->ctrl + kOverflowSticky, sizeof(uint32_t), hipMemcpyDeviceToHost, cs);
     e = hipStreamEndCapture(cs, &gr->graph);
     if (k != hipSuccess) e = k;
   }

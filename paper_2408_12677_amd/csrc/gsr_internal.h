@@ -107,7 +107,12 @@ constexpr int kHeadFwd = 0;    // control words (see TileQueue)
 constexpr int kHeadBwd = 1;
 constexpr int kOverflow = 2;
 constexpr int kItems = 3;      // backward work items listed
-constexpr int kCtrlWords = 4;
+constexpr int kStepWords = 4;  // words 0..3 start at zero in every step (cleared by the projection)
+// set together with kOverflow and never cleared by a step: a captured graph zeroes it once
+// at creation, so it records an overflow of any launch since, and the fused optimiser
+// step reads it to leave the parameters alone once one happened
+constexpr int kOverflowSticky = 4;
+constexpr int kCtrlWords = 8;
 constexpr int kScanTile = 4096;            // elements per block of the device-wide scans
 constexpr int64_t kMaxBinCounts = int64_t(1) << 22;  // entries of each binning count array (soft)
 
@@ -265,10 +270,10 @@ hipError_t launch_scan_small(uint32_t* a, int count, unsigned long long* total, 
 // Device-side counts (unsigned long long) are clamped by each kernel to the capacity its
 // grid and buffers were sized for.
 // zero_rows (may be null): 2D-gradient rows (kGrad2D floats) zeroed for every visible record;
-// the first block also zeroes the kCtrlWords control words `ctrl`
+// the first block also zeroes the first clear_words control words `ctrl`
 hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru, int tile,
                           const Records& rec, uint2* blocksums, int nblk, float* zero_rows, uint32_t* ctrl,
-                          hipStream_t s);
+                          int clear_words, hipStream_t s);
 hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* totals, hipStream_t s);
 hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
                           const unsigned long long* pairs, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
@@ -330,8 +335,8 @@ hipError_t launch_tsdf_weights(const TsdfDev& m, const float* pts, int64_t n, fl
 
 // ---- optimiser (gsr_optim.hip) ------------------------------------------------------
 // Advances the step counter state[0] and writes the new step's bias corrections to
-// state[1], state[2] (as binary32).
-hipError_t launch_adam_tick(uint32_t* state, float b1, float b2, hipStream_t s);
+// state[1], state[2] (as binary32); does nothing when skip is non-null and *skip != 0.
+hipError_t launch_adam_tick(uint32_t* state, float b1, float b2, const uint32_t* skip, hipStream_t s);
 // One Adam step over all groups of n Gaussians of SH degree deg, gradients grads[group].
 hipError_t launch_adam(const AdamDev& a, const float* const grads[G_COUNT], int64_t n, int deg, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);

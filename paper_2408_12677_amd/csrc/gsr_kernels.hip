@@ -449,11 +449,11 @@ __device__ __forceinline__ void sh_grad_dot(float x, float y, float z, const flo
 template <int DEG>
 __global__ __launch_bounds__(kProjThreads) void k_project(GaussDev g, ViewTable vt, Rules ru, int tile,
                                                           Records rec, uint2* blocksums, int nblk,
-                                                          float* zero_rows, uint32_t* ctrl) {
+                                                          float* zero_rows, uint32_t* ctrl, int clear_words) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ uint32_t red[kProjThreads / 64];
   // the step's control words start at zero (no kernel before the projection reads them)
-  if (blockIdx.x == 0 && threadIdx.x < kCtrlWords) ctrl[threadIdx.x] = 0u;
+  if (blockIdx.x == 0 && int(threadIdx.x) < clear_words) ctrl[threadIdx.x] = 0u;
   const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
   const bool valid = gi < g.n;
   float p[3] = {0.f, 0.f, 0.f}, s[3] = {1.f, 1.f, 1.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, op = 0.f;
@@ -582,6 +582,12 @@ __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* a, int count, unsig
   if (t == 1023) *total = incl;
 }
 
+// Flags a capacity overflow: the step's word and the sticky copy next to it.
+__device__ __forceinline__ void raise_overflow(uint32_t* overflow) {
+  atomicOr(overflow, 1u);
+  atomicOr(overflow + (kOverflowSticky - kOverflow), 1u);
+}
+
 // A device-side count clamped to the capacity the grid and buffers were sized for; zero
 // once a capacity overflow has been flagged, so that nothing downstream of an overflow
 // reads partially written buffers.
@@ -603,7 +609,7 @@ __global__ __launch_bounds__(kProjThreads) void k_compact(int64_t n, Records rec
   const int v = blockIdx.y;
   // more (tile, record) pairs than the binning buffers hold: flag it before anything reads
   // the flag (every later kernel then sees zero records)
-  if (blockIdx.x == 0 && v == 0 && threadIdx.x == 0 && *pairs > (unsigned long long)cap_M) atomicOr(overflow, 1u);
+  if (blockIdx.x == 0 && v == 0 && threadIdx.x == 0 && *pairs > (unsigned long long)cap_M) raise_overflow(overflow);
   const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
   const int64_t rid = int64_t(v) * n + gi;
   const uint32_t vis = (gi < n && rec.counts[rid] != 0u) ? 1u : 0u;
@@ -611,7 +617,7 @@ __global__ __launch_bounds__(kProjThreads) void k_compact(int64_t n, Records rec
   if (!vis) return;
   const uint32_t off = blocksums[int64_t(v) * nblk + blockIdx.x].y + excl;
   if (int64_t(off) >= cap) {
-    atomicOr(overflow, 1u);
+    raise_overflow(overflow);
     return;
   }
   dkeys[off] = __float_as_uint(rec.r1[rid].z);
@@ -977,7 +983,7 @@ __global__ __launch_bounds__(1024) void k_bin_rows_meta(ViewTable vt, BinPlan pl
   }
   if (t == 1023) {
     const bool over = iseg > (unsigned long long)plan.cap_seg || iw > (unsigned long long)plan.cap_flat;
-    if (over) atomicOr(overflow, 1u);
+    if (over) raise_overflow(overflow);
     plan.seg_start[R] = uint32_t(over ? 0ull : iseg);
     plan.words[1] = over ? 0ull : iseg;
     plan.words[2] = over ? 0ull : iw;
@@ -1977,6 +1983,7 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(GaussDev g, ViewTable vt
     for (int k = 0; k < K; ++k) s_sh[gl * STRIDE + k * 3 + ch] = dsh[k];
   __syncthreads();
   if (adam.on) {  // one Adam step of every coefficient of the block's Gaussians, in place
+    if (adam.skip && *adam.skip) return;  // the step overflowed: parameters stay as they are
     const float bc1 = adam.bc[0], bc2 = adam.bc[1];
     for (int i = t; i < nb * KK; i += 256) {
       const int r = i / KK, j = i - r * KK;
@@ -2096,6 +2103,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd_geo(GaussDev g, Vi
     for (int i = 0; i < 3; ++i) dp[i] += dp_sh[gi * 3 + i];
   }
   if (adam.on) {  // one Adam step of the Gaussian's geometry, in place
+    if (adam.skip && *adam.skip) return;  // the step overflowed: parameters stay as they are
     const float bc1 = adam.bc[0], bc2 = adam.bc[1];
 #pragma unroll
     for (int i = 0; i < 3; ++i) adam_apply<G_MEANS>(adam, gi * 3 + i, p[i], dp[i], adam.lr[G_MEANS], bc1, bc2);
@@ -2125,14 +2133,15 @@ inline unsigned blocks_for(int64_t n, int per) { return unsigned((n + per - 1) /
 // ------------------------------------------------------------------------------------
 hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru, int tile,
                           const Records& rec, uint2* blocksums, int nblk, float* zero_rows, uint32_t* ctrl,
-                          hipStream_t s) {
+                          int clear_words, hipStream_t s) {
   if (nblk == 0) return hipSuccess;
   dim3 grid(nblk), block(kProjThreads);
+  const int cw = clear_words;
   switch (deg) {
-    case 0: k_project<0><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl); break;
-    case 1: k_project<1><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl); break;
-    case 2: k_project<2><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl); break;
-    default: k_project<3><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl); break;
+    case 0: k_project<0><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl, cw); break;
+    case 1: k_project<1><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl, cw); break;
+    case 2: k_project<2><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl, cw); break;
+    default: k_project<3><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl, cw); break;
   }
   return hipGetLastError();
 }

@@ -21,9 +21,10 @@ constexpr int kAdamThreads = 256;
 constexpr int kAdamPer = 4;  // elements per thread
 constexpr int kAdamBlock = kAdamThreads * kAdamPer;
 
-__global__ __launch_bounds__(64) void k_adam_tick(uint32_t* state, float b1, float b2) {
+__global__ __launch_bounds__(64) void k_adam_tick(uint32_t* state, float b1, float b2, const uint32_t* skip) {
   const int lane = threadIdx.x;
   if (lane != 0) return;
+  if (skip && *skip) return;  // a step that overflowed its capacities updates nothing
   const uint32_t t = state[lane] + 1u;
   state[lane] = t;
   float* bc = reinterpret_cast<float*>(state + 1);
@@ -103,8 +104,8 @@ inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 
 }  // namespace
 
-hipError_t launch_adam_tick(uint32_t* state, float b1, float b2, hipStream_t s) {
-  k_adam_tick<<<1, 64, 0, s>>>(state, b1, b2);
+hipError_t launch_adam_tick(uint32_t* state, float b1, float b2, const uint32_t* skip, hipStream_t s) {
+  k_adam_tick<<<1, 64, 0, s>>>(state, b1, b2, skip);
   return hipGetLastError();
 }
 

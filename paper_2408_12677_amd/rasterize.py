@@ -243,25 +243,44 @@ def loss_l1(saved: Saved, images, targets, depth_weight: float = 0.1):
     return loss, gcs, gds
 
 
+def _view_grads(saved: Saved, g_color, g_depth, g_alpha, keep: list):
+    """The per-view dL/d(outputs) as a gsr_view_grad array; every given tensor must have its
+    view's image shape ([3,H,W] colour, [H,W] depth and alpha) on the parameters' device."""
+    V = len(saved.cameras)
+    dev = saved.keep[0].device
+    gv = (N.ViewGrad * V)()
+    for i, cam in enumerate(saved.cameras):
+        H, W = int(cam.height), int(cam.width)
+
+        def p(lst, name, shape):
+            if lst is None or lst[i] is None:
+                return None
+            t = lst[i]
+            if not isinstance(t, torch.Tensor):
+                raise TypeError(f"{name}[{i}] must be a torch.Tensor")
+            if tuple(t.shape) != shape or t.device != dev:
+                raise ValueError(f"{name}[{i}] must have shape {shape} on {dev}, got {tuple(t.shape)} on {t.device}")
+            t = t.contiguous().float()
+            keep.append(t)
+            return t.data_ptr()
+        gv[i] = N.ViewGrad(p(g_color, "g_color", (3, H, W)), p(g_depth, "g_depth", (H, W)),
+                           p(g_alpha, "g_alpha", (H, W)))
+    return gv
+
+
 def backward(saved: Saved, g_color, g_depth=None, g_alpha=None, grads=None, accumulate: bool = False):
     """dL/d(means, scales, quats, opacities, sh) for dL/d(outputs) given per view (None = 0)."""
     ctx = saved.ctx
     means, scales, quats, opacities, sh = saved.keep
-    V = len(saved.cameras)
-    gv = (N.ViewGrad * V)()
     keep = []
-    for i in range(V):
-        def p(lst):
-            if lst is None or lst[i] is None:
-                return None
-            t = lst[i].contiguous().float()
-            keep.append(t)
-            return t.data_ptr()
-        gv[i] = N.ViewGrad(p(g_color), p(g_depth), p(g_alpha))
+    gv = _view_grads(saved, g_color, g_depth, g_alpha, keep)
     if grads is None:
         grads = dict(means=torch.empty_like(means), scales=torch.empty_like(scales), quats=torch.empty_like(quats),
                      opacities=torch.empty_like(opacities), sh=torch.empty_like(sh))
         accumulate = False
+    for k, ref in zip(GROUPS, saved.keep):
+        if grads.get(k) is not None:
+            _need(grads[k], f"grads[{k!r}]", ref.shape, ref.device)
     go = N.GaussianGrads(*(None if grads.get(k) is None else grads[k].data_ptr()
                            for k in ("means", "scales", "quats", "opacities", "sh")))
     N.check(ctx.lib.gsr_backward(ctx.h, saved.h, gv, ctypes.byref(go), N.ACCUMULATE if accumulate else 0), ctx.h)
@@ -501,17 +520,8 @@ def backward_adam(saved: Saved, opt: Adam, g_color, g_depth=None, g_alpha=None):
     the parameter tensors given to forward (updated in place; no gradients are written)."""
     ctx = saved.ctx
     opt._check(saved.keep)
-    V = len(saved.cameras)
-    gv = (N.ViewGrad * V)()
     keep = []
-    for i in range(V):
-        def p(lst):
-            if lst is None or lst[i] is None:
-                return None
-            t = lst[i].contiguous().float()
-            keep.append(t)
-            return t.data_ptr()
-        gv[i] = N.ViewGrad(p(g_color), p(g_depth), p(g_alpha))
+    gv = _view_grads(saved, g_color, g_depth, g_alpha, keep)
     N.check(ctx.lib.gsr_backward_adam(ctx.h, saved.h, gv, ctypes.byref(opt.c)), ctx.h)
 
 

@@ -176,6 +176,38 @@ def test_graph_capacity_overflow_is_reported(R):
     say("overflow test capacities", info)
 
 
+def test_graph_overflow_with_fused_adam_leaves_parameters_unchanged(R):
+    # the same forced overflow, with the optimiser step fused into the captured step and two
+    # launches queued back to back: both are reported, and neither moves a parameter, a
+    # moment or the step counter (the overflow word is sticky across launches)
+    from paper_2408_12677_amd._native import GsrError, ECAPACITY
+    g, cams, targets = small_views()
+    params = to_dev(g)
+    tg = dev_targets(targets)
+    with torch.no_grad():
+        params[1].mul_(0.01)
+    opt = R.Adam(*params)
+    graph = R.Graph(*params, cams, tg, settings(), headroom=0.0, optimizer=opt)
+    with torch.no_grad():
+        params[1].mul_(2000.0)
+    before = [p.clone() for p in params]
+    graph.launch()
+    try:
+        graph.launch()      # may already see the first launch's overflow
+    except GsrError as e:
+        assert e.status == ECAPACITY
+    with pytest.raises(GsrError) as ei:
+        graph.sync()
+    assert ei.value.status == ECAPACITY
+    for a, b in zip(params, before):
+        assert torch.equal(a, b)
+    assert opt.steps == 0
+    for k in NAMES:
+        assert not opt.m[k].any() and not opt.v[k].any()
+    graph.free()
+    torch.cuda.synchronize()
+
+
 def test_autotune_picks_a_launch_shape_and_caches_it(R, tmp_path, monkeypatch):
     monkeypatch.setenv("GSR_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
     g, cams, _ = small_views()
