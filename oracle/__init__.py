@@ -30,6 +30,10 @@ from dataclasses import dataclass
 
 import numpy as np
 
+# near_a / near_T count values within this many times the ambiguity margins (kWide in
+# oracle.cpp): a window this much narrower holds 1/NEAR_WIDE of them on average
+NEAR_WIDE = 100.0
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
@@ -76,8 +80,8 @@ def _load():
         lib.or_num_tiles.argtypes = [P]
         lib.or_get_keys.argtypes = [P, P, P, P]
         lib.or_get_records.argtypes = [P] * 8
-        lib.or_forward.argtypes = [P] * 8
-        lib.or_backward.argtypes = [P] * 11
+        lib.or_forward.argtypes = [P] * 12
+        lib.or_backward.argtypes = [P] * 16
         lib.or_sh_eval.argtypes = [ctypes.c_int32, P, ctypes.c_int64, P, P]
         _lib = lib
     return _lib
@@ -188,43 +192,71 @@ class Oracle:
         return res
 
     def forward(self):
-        """Per view: dict(color[3,H,W], depth, alpha, T_final, n_contrib, n_used, ambiguous)."""
+        """Per view: dict(color[3,H,W], depth, alpha, T_final, n_contrib, n_used, ambiguous,
+        lo[5,H,W], hi[5,H,W], events, near_a, near_T).
+
+        ``ambiguous`` marks pixels with a skip or stop decision inside its margin; lo/hi bound
+        (colour 3, depth, alpha) over every correct outcome of those decisions (equal to the
+        values elsewhere); ``events`` counts such decisions (-1: too many to enumerate, the
+        bounds then hold the reference outcome only); near_a / near_T count the values within
+        ``NEAR_WIDE`` times the margins."""
         P = sum(c.width * c.height for c in self.cameras)
         color = np.zeros(3 * P)
         depth, alpha, T = np.zeros(P), np.zeros(P), np.zeros(P)
         nc = np.zeros(P, np.int32)
         nu = np.zeros(P, np.int32)
         amb = np.zeros(P, np.uint8)
-        self.lib.or_forward(self.h, _ptr(color), _ptr(depth), _ptr(alpha), _ptr(T), _ptr(nc), _ptr(nu), _ptr(amb))
+        lo, hi = np.zeros((P, 5)), np.zeros((P, 5))
+        ev = np.zeros(P, np.int32)
+        near = np.zeros((P, 2), np.int32)
+        self.lib.or_forward(self.h, _ptr(color), _ptr(depth), _ptr(alpha), _ptr(T), _ptr(nc), _ptr(nu), _ptr(amb),
+                            _ptr(lo), _ptr(hi), _ptr(ev), _ptr(near))
         cols = self._split(color, 3)
         outs = []
-        for v, (d, a, t, n, u, m) in enumerate(zip(*(self._split(x, 1) for x in (depth, alpha, T, nc, nu, amb)))):
+        off = 0
+        split = [self._split(x, 1) for x in (depth, alpha, T, nc, nu, amb, ev)]
+        for v, (d, a, t, n, u, m, e) in enumerate(zip(*split)):
+            H, W = d.shape
+            sl = slice(off, off + H * W)
+            off += H * W
             outs.append(dict(color=cols[v], depth=d, alpha=a, T_final=t, n_contrib=n, n_used=u,
-                             ambiguous=m.astype(bool)))
+                             ambiguous=m.astype(bool), events=e,
+                             lo=lo[sl].T.reshape(5, H, W), hi=hi[sl].T.reshape(5, H, W),
+                             near_a=near[sl, 0].reshape(H, W), near_T=near[sl, 1].reshape(H, W)))
         return outs
 
     def backward(self, g_color=None, g_depth=None, g_alpha=None, ambiguous_pixels=None):
         """Gradients of sum over views of <g, outputs>; inputs are per-view lists (None = 0).
 
-        ambiguous_pixels: optional per-view boolean [H,W] masks of pixels whose output
-        gradient is not unique (an L1 sign at a tie); Gaussians contributing there are
-        flagged like those near a skip, stop or clamp edge."""
+        ambiguous_pixels: optional per-view [H,W] masks of pixels whose output gradient is
+        not unique (an L1 sign at a tie: such an output gradient may change by up to twice
+        its value): uint8 bit k set for output k (colour 0-2, depth 3, alpha 4), or boolean
+        (every output of a marked pixel).  Returns the gradients, ``envelope`` (same layouts: how far
+        any correct gradient can lie from these, over the correct outcomes of every decision
+        inside its margin and the non-unique output gradients) and ``flagged`` (Gaussians
+        contributing to a pixel whose outcomes were too many to enumerate)."""
         def cat(lst, ch):
             if lst is None:
                 return None
             return np.ascontiguousarray(np.concatenate([np.asarray(x, np.float64).reshape(-1) for x in lst]))
         gc, gd, ga = cat(g_color, 3), cat(g_depth, 1), cat(g_alpha, 1)
         n, K = self.n, self.K
-        d = dict(means=np.zeros((n, 3)), scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
-                 opacities=np.zeros(n), sh=np.zeros((n, K, 3)))
+        shapes = dict(means=(n, 3), scales=(n, 3), quats=(n, 4), opacities=(n,), sh=(n, K, 3))
+        d = {k: np.zeros(s) for k, s in shapes.items()}
+        env = {k: np.zeros(s) for k, s in shapes.items()}
         flagged = np.zeros(n, np.uint8)
         pa = None
         if ambiguous_pixels is not None:
-            pa = np.ascontiguousarray(np.concatenate([np.asarray(m, bool).reshape(-1) for m in ambiguous_pixels]),
-                                      np.uint8)
+            def bits(m):
+                m = np.asarray(m)
+                return np.where(m, 31, 0).astype(np.uint8) if m.dtype == bool else m.astype(np.uint8)
+            pa = np.ascontiguousarray(np.concatenate([bits(m).reshape(-1) for m in ambiguous_pixels]), np.uint8)
         self.lib.or_backward(self.h, _ptr(gc), _ptr(gd), _ptr(ga), _ptr(pa), _ptr(d["means"]), _ptr(d["scales"]),
-                             _ptr(d["quats"]), _ptr(d["opacities"]), _ptr(d["sh"]), _ptr(flagged))
+                             _ptr(d["quats"]), _ptr(d["opacities"]), _ptr(d["sh"]), _ptr(flagged),
+                             _ptr(env["means"]), _ptr(env["scales"]), _ptr(env["quats"]), _ptr(env["opacities"]),
+                             _ptr(env["sh"]))
         d["flagged"] = flagged.astype(bool)
+        d["envelope"] = env
         return d
 
 

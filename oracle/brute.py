@@ -124,6 +124,8 @@ def render(params, sh_degree, cam, alpha_min=1 / 255, alpha_max=0.99, T_min=1e-4
     C = np.zeros((3, H, W))
     D = np.zeros((H, W))
     done = np.zeros((H, W), bool)
+    last = np.full((H, W), -1, np.int64)   # Gaussian index of the last contributor
+    count = np.zeros((H, W), np.int64)     # contributors
     amin = float(np.float32(alpha_min))
     amax = float(np.float32(alpha_max))
     tmin = float(np.float32(T_min))
@@ -140,6 +142,8 @@ def render(params, sh_degree, cam, alpha_min=1 / 255, alpha_max=0.99, T_min=1e-4
         C += pr["color"][g][:, None, None] * w
         D += pr["z"][g] * w
         T = np.where(use, T * (1.0 - alpha), T)
+        last = np.where(use, g, last)
+        count += use
         done |= use & (T < tmin)
     C += np.asarray(bg, np.float64)[:, None, None] * T
-    return dict(color=C, depth=D, alpha=1.0 - T, T_final=T)
+    return dict(color=C, depth=D, alpha=1.0 - T, T_final=T, last=last, count=count, stopped=done)

@@ -17,11 +17,13 @@
 //
 // Build: g++ -O2 -std=c++17 -ffp-contract=off -fno-fast-math -shared -fPIC
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <numeric>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 extern "C" {
@@ -578,23 +580,42 @@ struct Hit {
   double G, a, alpha, T, dx, dy;
 };
 
-// Front-to-back compositing of one pixel over its tile's sorted list.
-// Returns the processed contributors (skipped entries omitted).
 // Depth normalised by the accumulated opacity: D / (1 - T_final), 0 where nothing is hit.
 double normalized(double D, double T) {
   const double A = 1.0 - T;
   return A > 0.0 ? D / A : 0.0;
 }
 
-void composite(const Ctx& c, int64_t tile, double px, double py, double out[5], int32_t& ncontrib,
-               int32_t& nused, bool& ambiguous, std::vector<Hit>* hits) {
+// One front-to-back pass of a pixel over its tile's sorted list (Eq. 11 with the
+// clamp, skip and stop rules).
+struct Pass {
+  double out[5];       // colour (3), accumulated depth D, final transmittance
+  int32_t ncontrib = 0;  // one past the list position of the last contributor
+  int32_t nused = 0;     // contributors
+  int events = 0;        // skip/stop decisions met within the ambiguity margins
+  int32_t near_a = 0;    // splat values within kWide times the skip margin of alpha_min
+  int32_t near_T = 0;    // transmittances within kWide times the stop margin of T_min
+};
+
+// A decision whose operands lie within a relative margin of the threshold (about ten
+// times the binary32 rounding of a = o exp(-q/2) and of T) may fall either way in a
+// binary32 renderer, and both outcomes are correct.  `flip` inverts the k-th such
+// decision met along the pass (bit k), so every correct outcome of a pixel can be
+// enumerated.  near_a / near_T count the values within kWide times the margins: the
+// density of values near a threshold, from which the expected number of ambiguous
+// decisions follows (a kWide-times narrower window holds 1/kWide of them).
+constexpr double kWide = 100.0;
+
+void composite(const Ctx& c, int64_t tile, double px, double py, uint32_t flip, Pass& p, std::vector<Hit>* hits) {
   const uint32_t s = c.ranges[tile * 2], e = c.ranges[tile * 2 + 1];
   const double amin = c.set.alpha_min, amax = c.set.alpha_max, Tmin = c.set.T_min;
   const double rel_a = c.set.amb_rel_a, rel_T = c.set.amb_rel_T;
   double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
-  int32_t n = 0;
-  nused = 0;
-  ambiguous = false;
+  p.ncontrib = 0;
+  p.nused = 0;
+  p.events = 0;
+  p.near_a = 0;
+  p.near_T = 0;
   for (uint32_t i = s; i < e; ++i) {
     const uint32_t ri = c.vals[i];
     const Rec& r = c.rec[ri];
@@ -602,22 +623,118 @@ void composite(const Ctx& c, int64_t tile, double px, double py, double out[5], 
     const double power = -0.5 * (r.A * dx * dx + 2.0 * r.B * dx * dy + r.C * dy * dy);
     const double G = std::exp(power);
     const double a = r.opacity * G;
-    if (std::fabs(a - amin) <= rel_a * amin) ambiguous = true;
-    if (a < amin) continue;
+    const double da_rel = std::fabs(a - amin);
+    if (da_rel <= kWide * rel_a * amin) ++p.near_a;
+    bool skip = a < amin;
+    if (da_rel <= rel_a * amin) {
+      if (p.events < 32 && ((flip >> p.events) & 1u)) skip = !skip;
+      ++p.events;
+    }
+    if (skip) continue;
     const double alpha = a < amax ? a : amax;
     if (hits) hits->push_back(Hit{ri, G, a, alpha, T, dx, dy});
     for (int ch = 0; ch < 3; ++ch) C[ch] += r.color[ch] * alpha * T;
     D += r.z * alpha * T;
     T = T * (1.0 - alpha);
-    n = int32_t(i - s + 1);
-    ++nused;
-    if (std::fabs(T - Tmin) <= rel_T * Tmin) ambiguous = true;
-    if (T < Tmin) break;
+    p.ncontrib = int32_t(i - s + 1);
+    ++p.nused;
+    const double dT_rel = std::fabs(T - Tmin);
+    if (dT_rel <= kWide * rel_T * Tmin) ++p.near_T;
+    bool stop = T < Tmin;
+    if (dT_rel <= rel_T * Tmin) {
+      if (p.events < 32 && ((flip >> p.events) & 1u)) stop = !stop;
+      ++p.events;
+    }
+    if (stop) break;
   }
-  for (int ch = 0; ch < 3; ++ch) out[ch] = C[ch] + T * double(c.set.bg[ch]);
-  out[3] = D;
-  out[4] = T;
-  ncontrib = n;
+  for (int ch = 0; ch < 3; ++ch) p.out[ch] = C[ch] + T * double(c.set.bg[ch]);
+  p.out[3] = D;
+  p.out[4] = T;
+}
+
+// Every correct outcome of a pixel: calls f(pass, flip) for the reference pass (flip 0)
+// and for each other combination of its ambiguous decisions (a combination counts when
+// each flipped decision is met).  Returns false, after the reference pass only, when some
+// combination meets more than kMaxFlips such decisions.
+constexpr int kMaxFlips = 8;
+
+template <class F>
+bool outcomes(const Ctx& c, int64_t tile, double px, double py, std::vector<Hit>* hits, F&& f) {
+  Pass p;
+  if (hits) hits->clear();
+  composite(c, tile, px, py, 0u, p, hits);
+  f(p, hits, 0u);
+  if (p.events > kMaxFlips) return false;
+  int E = p.events;
+  std::vector<Hit> hq;
+  for (uint32_t m = 1; m < (1u << E); ++m) {
+    Pass q;
+    hq.clear();
+    composite(c, tile, px, py, m, q, hits ? &hq : nullptr);
+    if (q.events > kMaxFlips) return false;
+    if (q.events > E) E = q.events;       // a flip exposed further decisions: enumerate them too
+    if ((m >> q.events) != 0u) continue;  // flips a decision this pass never met
+    f(q, hits ? &hq : nullptr, m);
+  }
+  return true;
+}
+
+// The reverse sweep of one pixel pass (O6): back to front over the processed
+// contributors, emit(record, t, alt) with the contributor's additive 2D-gradient terms t
+// (dmu 2, dconic 3, dopacity, dcolour 3, ddepth) for the output gradients (gC, gD, gA),
+// and alt = the same terms under the opposite clamp decision when its splat value lies
+// within the ambiguity margin of alpha_max (else NULL).
+template <class Emit>
+void sweep(const Ctx& c, const Pass& p, const std::vector<Hit>& hits, const double* gC_in, double gD, double gA,
+           Emit&& emit) {
+  const double amax = c.set.alpha_max, rel = c.set.amb_rel_a;
+  const double Tfin = p.out[4];
+  const double gC[3] = {gC_in[0], gC_in[1], gC_in[2]};
+  if (c.set.normalized_depth) {
+    // Dn = D / A with A = 1 - T_final: dL/dD = g / A, and dL/dA gains -g D / A^2
+    // = -g Dn / A; through A = 1 - T_final that is +g Dn / A on the alpha
+    // output's gradient route (A is the alpha output)
+    const double A = 1.0 - Tfin;
+    if (A > 0.0) {
+      const double Dn = p.out[3] / A;
+      gA += -gD * Dn / A;
+      gD = gD / A;
+    } else {
+      gD = 0.0;
+    }
+  }
+  double BC[3] = {c.set.bg[0], c.set.bg[1], c.set.bg[2]}, BD = 0.0;
+  for (size_t i = hits.size(); i-- > 0;) {
+    const Hit& hh = hits[i];
+    const Rec& r = c.rec[hh.rec];
+    double t[10], alt[10];
+    double dal = 0.0;
+    for (int ch = 0; ch < 3; ++ch) dal += gC[ch] * (r.color[ch] - BC[ch]);
+    dal += gD * (r.z - BD);
+    dal *= hh.T;
+    dal += gA * Tfin / (1.0 - hh.alpha);
+    for (int ch = 0; ch < 3; ++ch) t[6 + ch] = gC[ch] * hh.alpha * hh.T;
+    t[9] = gD * hh.alpha * hh.T;
+    for (int ch = 0; ch < 3; ++ch) BC[ch] = hh.alpha * r.color[ch] + (1.0 - hh.alpha) * BC[ch];
+    BD = hh.alpha * r.z + (1.0 - hh.alpha) * BD;
+    auto splat_terms = [&](double da, double* o) {
+      o[5] = da * hh.G;
+      const double dpow = da * hh.a;
+      o[0] = dpow * (r.A * hh.dx + r.B * hh.dy);
+      o[1] = dpow * (r.B * hh.dx + r.C * hh.dy);
+      o[2] = -0.5 * dpow * hh.dx * hh.dx;
+      o[3] = -dpow * hh.dx * hh.dy;
+      o[4] = -0.5 * dpow * hh.dy * hh.dy;
+    };
+    const bool unclamped = hh.a <= amax;
+    splat_terms(unclamped ? dal : 0.0, t);
+    const bool edge = std::fabs(hh.a - amax) <= rel * amax;
+    if (edge) {
+      splat_terms(unclamped ? 0.0 : dal, alt);
+      for (int k = 6; k < 10; ++k) alt[k] = t[k];
+    }
+    emit(hh.rec, t, edge ? alt : nullptr);
+  }
 }
 
 template <class F>
@@ -640,6 +757,112 @@ int view_of_tile(const Ctx& c, int64_t tile) {
   int v = 0;
   while (c.tile_off[v + 1] <= tile) ++v;
   return v;
+}
+
+// Per-Gaussian gradient accumulators in the parameter layouts.
+struct Grad3 {
+  double dp[3] = {0, 0, 0}, ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dop = 0.0;
+  std::vector<double> dk;
+  explicit Grad3(int K) : dk(size_t(K) * 3, 0.0) {}
+};
+
+// Chain rule of one (view, Gaussian) record (O7): its 2D gradient G (dmu 2, dconic 3,
+// dopacity, dcolour 3, ddepth) taken back to the Gaussian's parameters and added to out.
+// Linear in G for a fixed Gaussian and camera.
+void chain(const Ctx& c, const SHBasis& sh, std::vector<double>& Y, double (*dY)[3], int v, int64_t g, const double* G,
+           Grad3& out) {
+    const or_camera& cam = c.cams[v];
+    Geo o;
+    make_geo(c, v, g, o);
+    // opacity
+    out.dop += G[5];
+    // colour through SH, with the clamp at zero masking the gradient
+    sh.eval(o.v, Y.data(), dY);
+    double dv[3] = {0, 0, 0};
+    for (int ch = 0; ch < 3; ++ch) {
+      double raw = 0.5;
+      for (int k = 0; k < c.K; ++k) raw += c.sh[(g * c.K + k) * 3 + ch] * Y[k];
+      if (!(raw > 0.0)) continue;
+      const double gc = G[6 + ch];
+      for (int k = 0; k < c.K; ++k) {
+        out.dk[k * 3 + ch] += Y[k] * gc;
+        const double kc = c.sh[(g * c.K + k) * 3 + ch] * gc;
+        for (int i = 0; i < 3; ++i) dv[i] += kc * dY[k][i];
+      }
+    }
+    const double vdot = dv[0] * o.v[0] + dv[1] * o.v[1] + dv[2] * o.v[2];
+    for (int i = 0; i < 3; ++i) out.dp[i] += (dv[i] - o.v[i] * vdot) / o.dnorm;
+    // conic -> projected covariance: dS = -Q G_Q Q
+    const double Q[4] = {o.A, o.B, o.B, o.C};
+    const double GQ[4] = {G[2], 0.5 * G[3], 0.5 * G[3], G[4]};
+    double QG[4], dS[4];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) QG[i * 2 + j] = Q[i * 2 + 0] * GQ[0 * 2 + j] + Q[i * 2 + 1] * GQ[1 * 2 + j];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) dS[i * 2 + j] = -(QG[i * 2 + 0] * Q[0 * 2 + j] + QG[i * 2 + 1] * Q[1 * 2 + j]);
+    // Sigma_hat = T Sigma T^T: dSigma = T^T dS T, dT = 2 dS T Sigma
+    double dSig[9], dT[6];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double a = 0;
+        for (int k = 0; k < 2; ++k)
+          for (int l = 0; l < 2; ++l) a += o.T[k * 3 + i] * dS[k * 2 + l] * o.T[l * 3 + j];
+        dSig[i * 3 + j] = a;
+      }
+    double TSig[6];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double a = 0;
+        for (int k = 0; k < 3; ++k) a += o.T[i * 3 + k] * o.Sig[k * 3 + j];
+        TSig[i * 3 + j] = a;
+      }
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 3; ++j) dT[i * 3 + j] = 2.0 * (dS[i * 2 + 0] * TSig[0 * 3 + j] + dS[i * 2 + 1] * TSig[1 * 3 + j]);
+    // T = J W: dJ = dT W^T
+    double dJ[6];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double a = 0;
+        for (int k = 0; k < 3; ++k) a += dT[i * 3 + k] * o.W[j * 3 + k];
+        dJ[i * 3 + j] = a;
+      }
+    const double fx = cam.fx, fy = cam.fy, tx = o.t[0], ty = o.t[1], tz = o.t[2];
+    double dt[3] = {0, 0, 0};
+    dt[0] += dJ[2] * (-fx / (tz * tz));
+    dt[1] += dJ[5] * (-fy / (tz * tz));
+    dt[2] += dJ[0] * (-fx / (tz * tz)) + dJ[2] * (2.0 * fx * tx / (tz * tz * tz)) + dJ[4] * (-fy / (tz * tz)) +
+             dJ[5] * (2.0 * fy * ty / (tz * tz * tz));
+    // splat centre (Eq. 4) and depth
+    dt[0] += G[0] * fx / tz;
+    dt[2] += -G[0] * fx * tx / (tz * tz);
+    dt[1] += G[1] * fy / tz;
+    dt[2] += -G[1] * fy * ty / (tz * tz);
+    dt[2] += G[9];
+    for (int i = 0; i < 3; ++i) out.dp[i] += o.W[0 * 3 + i] * dt[0] + o.W[1 * 3 + i] * dt[1] + o.W[2 * 3 + i] * dt[2];
+    // Sigma = M M^T: dM = 2 dSigma M; M = R diag(s)
+    double dM[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double a = 0;
+        for (int k = 0; k < 3; ++k) a += dSig[i * 3 + k] * o.M[k * 3 + j];
+        dM[i * 3 + j] = 2.0 * a;
+      }
+    double dR[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        out.ds[j] += dM[i * 3 + j] * o.R[i * 3 + j];
+        dR[i * 3 + j] = dM[i * 3 + j] * o.s[j];
+      }
+    double gR[4][9];
+    quat_rot_grad(o.qn, gR);
+    double dqn[4];
+    for (int a = 0; a < 4; ++a) {
+      double s = 0;
+      for (int i = 0; i < 9; ++i) s += gR[a][i] * dR[i];
+      dqn[a] = s;
+    }
+    const double qd = dqn[0] * o.qn[0] + dqn[1] * o.qn[1] + dqn[2] * o.qn[2] + dqn[3] * o.qn[3];
+    for (int a = 0; a < 4; ++a) out.dq[a] += (dqn[a] - o.qn[a] * qd) / o.qnorm;
 }
 
 }  // namespace
@@ -716,8 +939,15 @@ void or_get_records(void* h, uint8_t* vis, float* mu, float* z, float* cov, int3
 // Forward render of every view.  Image outputs are concatenated over views:
 // color [3,H,W] per view, the others [H,W] per view.  n_contrib is one past the
 // list position of the last contributor; n_used counts the contributors.
+// Every further output may be NULL.  ambiguous (byte per pixel) is set where a skip or
+// stop decision lies within its margin.  lo/hi [P,5] (views concatenated) bound each
+// output value (colour 3, depth, alpha) over every correct outcome of the pixel's
+// ambiguous decisions (both equal the value elsewhere); events [P] is the number of such
+// decisions the reference pass met, -1 where a combination met more than kMaxFlips (its
+// bounds then cover the reference pass only); near [P,2] counts the splat values and
+// transmittances within kWide times the margins.
 void or_forward(void* h, double* color, double* depth, double* alpha, double* T_final, int32_t* n_contrib,
-                int32_t* n_used, uint8_t* ambiguous) {
+                int32_t* n_used, uint8_t* ambiguous, double* lo, double* hi, int32_t* events, int32_t* near) {
   const Ctx& c = *static_cast<Ctx*>(h);
   const int ts = c.set.tile;
   parallel_tiles(c, [&](int, int64_t t0, int64_t t1) {
@@ -729,48 +959,81 @@ void or_forward(void* h, double* color, double* depth, double* alpha, double* T_
       const int64_t P = int64_t(W) * H;
       for (int y = ty * ts; y < std::min(H, (ty + 1) * ts); ++y)
         for (int x = tx * ts; x < std::min(W, (tx + 1) * ts); ++x) {
-          double out[5];
-          int32_t n, nu;
-          bool amb;
-          composite(c, tile, x, y, out, n, nu, amb, nullptr);
           const int64_t pix = int64_t(y) * W + x;
           const int64_t base = c.pix_off[v];
+          double l[5], u[5];
+          Pass ref;
+          const bool bounded = outcomes(c, tile, x, y, nullptr, [&](const Pass& p, const std::vector<Hit>*, uint32_t m) {
+            const double val[5] = {p.out[0], p.out[1], p.out[2],
+                                   c.set.normalized_depth ? normalized(p.out[3], p.out[4]) : p.out[3], 1.0 - p.out[4]};
+            if (m == 0u) {
+              ref = p;
+              for (int k = 0; k < 5; ++k) l[k] = u[k] = val[k];
+            } else {
+              for (int k = 0; k < 5; ++k) {
+                l[k] = std::min(l[k], val[k]);
+                u[k] = std::max(u[k], val[k]);
+              }
+            }
+          });
           if (color)
-            for (int ch = 0; ch < 3; ++ch) color[base * 3 + ch * P + pix] = out[ch];
-          if (depth) depth[base + pix] = c.set.normalized_depth ? normalized(out[3], out[4]) : out[3];
-          if (alpha) alpha[base + pix] = 1.0 - out[4];
-          if (T_final) T_final[base + pix] = out[4];
-          if (n_contrib) n_contrib[base + pix] = n;
-          if (n_used) n_used[base + pix] = nu;
-          if (ambiguous) ambiguous[base + pix] = amb;
+            for (int ch = 0; ch < 3; ++ch) color[base * 3 + ch * P + pix] = ref.out[ch];
+          if (depth) depth[base + pix] = c.set.normalized_depth ? normalized(ref.out[3], ref.out[4]) : ref.out[3];
+          if (alpha) alpha[base + pix] = 1.0 - ref.out[4];
+          if (T_final) T_final[base + pix] = ref.out[4];
+          if (n_contrib) n_contrib[base + pix] = ref.ncontrib;
+          if (n_used) n_used[base + pix] = ref.nused;
+          if (ambiguous) ambiguous[base + pix] = ref.events > 0;
+          if (lo)
+            for (int k = 0; k < 5; ++k) lo[(base + pix) * 5 + k] = l[k];
+          if (hi)
+            for (int k = 0; k < 5; ++k) hi[(base + pix) * 5 + k] = u[k];
+          if (events) events[base + pix] = bounded ? ref.events : -1;
+          if (near) {
+            near[(base + pix) * 2] = ref.near_a;
+            near[(base + pix) * 2 + 1] = ref.near_T;
+          }
         }
     }
   });
 }
 
 // Reverse pass.  g_color/g_depth/g_alpha are dL/d(output) with the layouts of
-// or_forward (NULL = zero).  Writes dL/d(parameters) in the parameter layouts, and per
-// Gaussian a flag that is set when a contributing event sat within the ambiguity
-// margin of a discrete rule (skip, stop or clamp edge), so its gradient is not unique.
-// pix_amb (NULL = none; one byte per pixel, views concatenated) marks pixels whose
-// output gradient is itself not unique (the L1 loss of Eq. 12 changes sign where the
-// rendered value meets the target); every Gaussian contributing there is flagged too.
+// or_forward (NULL = zero).  Writes dL/d(parameters) in the parameter layouts.
+//
+// Several results are correct where a pixel's skip or stop decision, or a contributor's
+// clamp decision, lies within its ambiguity margin, and where the output gradient itself
+// is not unique (pix_amb: NULL = none, one byte per pixel, views concatenated, bit k set
+// when output k (colour 0-2, depth 3, alpha 4) has a non-unique gradient; the L1 loss of
+// Eq. 12 changes sign where the rendered value meets the target, so such an output
+// gradient may change by up to twice its value).  e_* (same layouts, may be NULL)
+// receive a bound on how far any correct gradient can lie from the one written: per
+// pixel, the largest change of each contributor's 2D-gradient terms over every correct
+// outcome (and the sum of the changes of each non-unique output gradient), summed over
+// pixels, taken to the parameters through the absolute value of each term's chain rule.
+// flagged (per Gaussian) marks Gaussians contributing to a pixel whose outcomes could not
+// be enumerated (more than kMaxFlips ambiguous decisions); no bound covers those.
 void or_backward(void* h, const double* g_color, const double* g_depth, const double* g_alpha,
                  const uint8_t* pix_amb, double* d_means, double* d_scales, double* d_quats, double* d_opac,
-                 double* d_sh, uint8_t* flagged) {
+                 double* d_sh, uint8_t* flagged, double* e_means, double* e_scales, double* e_quats, double* e_opac,
+                 double* e_sh) {
   const Ctx& c = *static_cast<Ctx*>(h);
   const int V = int(c.cams.size());
   const int64_t N = c.n;
   const int ts = c.set.tile;
   const int nth = c.set.threads < 1 ? 1 : c.set.threads;
+  using Terms = std::array<double, 10>;
+  using TermMap = std::unordered_map<uint32_t, Terms>;
   // per-thread accumulators of the 2D gradients: dmu(2), dconic(3), dopacity, dcolor(3), ddepth
   std::vector<std::vector<double>> acc(nth, std::vector<double>(size_t(V) * N * 10, 0.0));
   std::vector<std::vector<uint8_t>> flag(nth, std::vector<uint8_t>(size_t(V) * N, 0));
-  const double amax = c.set.alpha_max, rel = c.set.amb_rel_a;
+  std::vector<TermMap> env(nth);  // per record: bound of the 2D-gradient change
   parallel_tiles(c, [&](int w, int64_t t0, int64_t t1) {
     std::vector<Hit> hits;
     std::vector<double>& G2 = acc[w];
     std::vector<uint8_t>& F = flag[w];
+    TermMap& E = env[w];
+    TermMap ref_terms, pix_env;
     for (int64_t tile = t0; tile < t1; ++tile) {
       const int v = view_of_tile(c, tile);
       const int64_t lt = tile - c.tile_off[v];
@@ -780,53 +1043,72 @@ void or_backward(void* h, const double* g_color, const double* g_depth, const do
       for (int y = ty * ts; y < std::min(H, (ty + 1) * ts); ++y)
         for (int x = tx * ts; x < std::min(W, (tx + 1) * ts); ++x) {
           const int64_t pix = int64_t(y) * W + x;
-          double gC[3], gD, gA;
+          double gC[3];
           for (int ch = 0; ch < 3; ++ch) gC[ch] = g_color ? g_color[base * 3 + ch * P + pix] : 0.0;
-          gD = g_depth ? g_depth[base + pix] : 0.0;
-          gA = g_alpha ? g_alpha[base + pix] : 0.0;
-          hits.clear();
-          double out[5];
-          int32_t n, nu;
-          bool amb;
-          composite(c, tile, x, y, out, n, nu, amb, &hits);
-          if (pix_amb && pix_amb[base + pix]) amb = true;
-          const double Tfin = out[4];
-          if (c.set.normalized_depth) {
-            // Dn = D / A with A = 1 - T_final: dL/dD = g / A, and dL/dA gains -g D / A^2
-            // = -g Dn / A; through A = 1 - T_final that is +g Dn / A on the alpha
-            // output's gradient route (A is the alpha output)
-            const double A = 1.0 - Tfin;
-            if (A > 0.0) {
-              const double Dn = out[3] / A;
-              gA += -gD * Dn / A;
-              gD = gD / A;
-            } else {
-              gD = 0.0;
-            }
+          const double gD = g_depth ? g_depth[base + pix] : 0.0;
+          const double gA = g_alpha ? g_alpha[base + pix] : 0.0;
+          const uint32_t tie = pix_amb ? pix_amb[base + pix] : 0u;
+          bool multi = false;  // the pixel has more than one correct outcome
+          Pass ref;
+          ref_terms.clear();
+          pix_env.clear();
+          const bool bounded =
+              outcomes(c, tile, x, y, &hits, [&](const Pass& p, const std::vector<Hit>* hp, uint32_t m) {
+                if (m == 0u) {
+                  ref = p;
+                  multi = p.events > 0;
+                  sweep(c, p, *hp, gC, gD, gA, [&](uint32_t rec, const double* t, const double* alt) {
+                    double* g = &G2[size_t(rec) * 10];
+                    for (int k = 0; k < 10; ++k) g[k] += t[k];
+                    if (alt) {  // the opposite clamp decision
+                      Terms& e = E[rec];
+                      for (int k = 0; k < 10; ++k) e[k] += std::fabs(alt[k] - t[k]);
+                    }
+                    if (multi) {
+                      Terms& r = ref_terms[rec];
+                      for (int k = 0; k < 10; ++k) r[k] = t[k];
+                    }
+                  });
+                  return;
+                }
+                // another correct outcome: the change of every record's terms
+                TermMap alt_terms;
+                sweep(c, p, *hp, gC, gD, gA, [&](uint32_t rec, const double* t, const double*) {
+                  Terms& r = alt_terms[rec];
+                  for (int k = 0; k < 10; ++k) r[k] = t[k];
+                });
+                auto widen = [&](uint32_t rec, const Terms& a, const Terms* b) {
+                  Terms& e = pix_env[rec];
+                  for (int k = 0; k < 10; ++k) e[k] = std::max(e[k], std::fabs(a[k] - (b ? (*b)[k] : 0.0)));
+                };
+                for (const auto& kv : alt_terms) {
+                  auto it = ref_terms.find(kv.first);
+                  widen(kv.first, kv.second, it == ref_terms.end() ? nullptr : &it->second);
+                }
+                for (const auto& kv : ref_terms)
+                  if (!alt_terms.count(kv.first)) widen(kv.first, kv.second, nullptr);
+              });
+          if (!bounded) {
+            for (const Hit& hh : hits) F[hh.rec] = 1;
+            continue;
           }
-          double BC[3] = {c.set.bg[0], c.set.bg[1], c.set.bg[2]}, BD = 0.0;
-          for (size_t i = hits.size(); i-- > 0;) {
-            const Hit& hh = hits[i];
-            const Rec& r = c.rec[hh.rec];
-            double* g = &G2[size_t(hh.rec) * 10];
-            if (amb || std::fabs(hh.a - amax) <= rel * amax) F[hh.rec] = 1;
-            double dal = 0.0;
-            for (int ch = 0; ch < 3; ++ch) dal += gC[ch] * (r.color[ch] - BC[ch]);
-            dal += gD * (r.z - BD);
-            dal *= hh.T;
-            dal += gA * Tfin / (1.0 - hh.alpha);
-            for (int ch = 0; ch < 3; ++ch) g[6 + ch] += gC[ch] * hh.alpha * hh.T;
-            g[9] += gD * hh.alpha * hh.T;
-            for (int ch = 0; ch < 3; ++ch) BC[ch] = hh.alpha * r.color[ch] + (1.0 - hh.alpha) * BC[ch];
-            BD = hh.alpha * r.z + (1.0 - hh.alpha) * BD;
-            const double da = hh.a <= amax ? dal : 0.0;
-            g[5] += da * hh.G;
-            const double dpow = da * hh.a;
-            g[0] += dpow * (r.A * hh.dx + r.B * hh.dy);
-            g[1] += dpow * (r.B * hh.dx + r.C * hh.dy);
-            g[2] += -0.5 * dpow * hh.dx * hh.dx;
-            g[3] += -dpow * hh.dx * hh.dy;
-            g[4] += -0.5 * dpow * hh.dy * hh.dy;
+          for (const auto& kv : pix_env) {
+            Terms& e = E[kv.first];
+            for (int k = 0; k < 10; ++k) e[k] += kv.second[k];
+          }
+          if (tie) {
+            // each output gradient may move by up to 2|g|: the terms are linear in it
+            const double gout[5] = {gC[0], gC[1], gC[2], gD, gA};
+            for (int ch = 0; ch < 5; ++ch) {
+              if (!((tie >> ch) & 1u) || gout[ch] == 0.0) continue;
+              double u[5] = {0, 0, 0, 0, 0};
+              u[ch] = 1.0;
+              const double scale = 2.0 * std::fabs(gout[ch]);
+              sweep(c, ref, hits, u, u[3], u[4], [&](uint32_t rec, const double* t, const double*) {
+                Terms& e = E[rec];
+                for (int k = 0; k < 10; ++k) e[k] += scale * std::fabs(t[k]);
+              });
+            }
           }
         }
     }
@@ -834,124 +1116,62 @@ void or_backward(void* h, const double* g_color, const double* g_depth, const do
   for (int w = 1; w < nth; ++w) {
     for (size_t i = 0; i < acc[0].size(); ++i) acc[0][i] += acc[w][i];
     for (size_t i = 0; i < flag[0].size(); ++i) flag[0][i] |= flag[w][i];
+    for (const auto& kv : env[w]) {
+      Terms& e = env[0][kv.first];
+      for (int k = 0; k < 10; ++k) e[k] += kv.second[k];
+    }
   }
   const std::vector<double>& G2 = acc[0];
+  const TermMap& E2 = env[0];
+  const bool want_env = e_means || e_scales || e_quats || e_opac || e_sh;
   // chain rule per Gaussian, summed over views in view order
   SHBasis sh(c.deg);
   std::vector<double> Y(c.K);
   std::vector<double> dYbuf(size_t(c.K) * 3);
   double (*dY)[3] = reinterpret_cast<double (*)[3]>(dYbuf.data());
   for (int64_t g = 0; g < N; ++g) {
-    double dp[3] = {0, 0, 0}, ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dop = 0.0;
-    std::vector<double> dk(size_t(c.K) * 3, 0.0);
+    Grad3 acc3(c.K), bound(c.K);
     uint8_t fl = 0;
     for (int v = 0; v < V; ++v) {
       const size_t ri = size_t(v) * N + g;
       if (!c.disc[ri].vis) continue;
       fl |= flag[0][ri];
       const double* G = &G2[ri * 10];
-      const or_camera& cam = c.cams[v];
-      Geo o;
-      make_geo(c, v, g, o);
-      // opacity
-      dop += G[5];
-      // colour through SH, with the clamp at zero masking the gradient
-      sh.eval(o.v, Y.data(), dY);
-      double dv[3] = {0, 0, 0};
-      for (int ch = 0; ch < 3; ++ch) {
-        double raw = 0.5;
-        for (int k = 0; k < c.K; ++k) raw += c.sh[(g * c.K + k) * 3 + ch] * Y[k];
-        if (!(raw > 0.0)) continue;
-        const double gc = G[6 + ch];
-        for (int k = 0; k < c.K; ++k) {
-          dk[k * 3 + ch] += Y[k] * gc;
-          const double kc = c.sh[(g * c.K + k) * 3 + ch] * gc;
-          for (int i = 0; i < 3; ++i) dv[i] += kc * dY[k][i];
+      chain(c, sh, Y, dY, v, g, G, acc3);
+      if (!want_env) continue;
+      auto it = E2.find(uint32_t(ri));
+      if (it == E2.end()) continue;
+      for (int k = 0; k < 10; ++k) {
+        if (!(it->second[k] > 0.0)) continue;
+        double Gk[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        Gk[k] = it->second[k];
+        Grad3 one(c.K);
+        chain(c, sh, Y, dY, v, g, Gk, one);
+        for (int i = 0; i < 3; ++i) {
+          bound.dp[i] += std::fabs(one.dp[i]);
+          bound.ds[i] += std::fabs(one.ds[i]);
         }
+        for (int i = 0; i < 4; ++i) bound.dq[i] += std::fabs(one.dq[i]);
+        bound.dop += std::fabs(one.dop);
+        for (size_t i = 0; i < one.dk.size(); ++i) bound.dk[i] += std::fabs(one.dk[i]);
       }
-      const double vdot = dv[0] * o.v[0] + dv[1] * o.v[1] + dv[2] * o.v[2];
-      for (int i = 0; i < 3; ++i) dp[i] += (dv[i] - o.v[i] * vdot) / o.dnorm;
-      // conic -> projected covariance: dS = -Q G_Q Q
-      const double Q[4] = {o.A, o.B, o.B, o.C};
-      const double GQ[4] = {G[2], 0.5 * G[3], 0.5 * G[3], G[4]};
-      double QG[4], dS[4];
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) QG[i * 2 + j] = Q[i * 2 + 0] * GQ[0 * 2 + j] + Q[i * 2 + 1] * GQ[1 * 2 + j];
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) dS[i * 2 + j] = -(QG[i * 2 + 0] * Q[0 * 2 + j] + QG[i * 2 + 1] * Q[1 * 2 + j]);
-      // Sigma_hat = T Sigma T^T: dSigma = T^T dS T, dT = 2 dS T Sigma
-      double dSig[9], dT[6];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          double a = 0;
-          for (int k = 0; k < 2; ++k)
-            for (int l = 0; l < 2; ++l) a += o.T[k * 3 + i] * dS[k * 2 + l] * o.T[l * 3 + j];
-          dSig[i * 3 + j] = a;
-        }
-      double TSig[6];
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 3; ++j) {
-          double a = 0;
-          for (int k = 0; k < 3; ++k) a += o.T[i * 3 + k] * o.Sig[k * 3 + j];
-          TSig[i * 3 + j] = a;
-        }
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 3; ++j) dT[i * 3 + j] = 2.0 * (dS[i * 2 + 0] * TSig[0 * 3 + j] + dS[i * 2 + 1] * TSig[1 * 3 + j]);
-      // T = J W: dJ = dT W^T
-      double dJ[6];
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 3; ++j) {
-          double a = 0;
-          for (int k = 0; k < 3; ++k) a += dT[i * 3 + k] * o.W[j * 3 + k];
-          dJ[i * 3 + j] = a;
-        }
-      const double fx = cam.fx, fy = cam.fy, tx = o.t[0], ty = o.t[1], tz = o.t[2];
-      double dt[3] = {0, 0, 0};
-      dt[0] += dJ[2] * (-fx / (tz * tz));
-      dt[1] += dJ[5] * (-fy / (tz * tz));
-      dt[2] += dJ[0] * (-fx / (tz * tz)) + dJ[2] * (2.0 * fx * tx / (tz * tz * tz)) + dJ[4] * (-fy / (tz * tz)) +
-               dJ[5] * (2.0 * fy * ty / (tz * tz * tz));
-      // splat centre (Eq. 4) and depth
-      dt[0] += G[0] * fx / tz;
-      dt[2] += -G[0] * fx * tx / (tz * tz);
-      dt[1] += G[1] * fy / tz;
-      dt[2] += -G[1] * fy * ty / (tz * tz);
-      dt[2] += G[9];
-      for (int i = 0; i < 3; ++i) dp[i] += o.W[0 * 3 + i] * dt[0] + o.W[1 * 3 + i] * dt[1] + o.W[2 * 3 + i] * dt[2];
-      // Sigma = M M^T: dM = 2 dSigma M; M = R diag(s)
-      double dM[9];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          double a = 0;
-          for (int k = 0; k < 3; ++k) a += dSig[i * 3 + k] * o.M[k * 3 + j];
-          dM[i * 3 + j] = 2.0 * a;
-        }
-      double dR[9];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          ds[j] += dM[i * 3 + j] * o.R[i * 3 + j];
-          dR[i * 3 + j] = dM[i * 3 + j] * o.s[j];
-        }
-      double gR[4][9];
-      quat_rot_grad(o.qn, gR);
-      double dqn[4];
-      for (int a = 0; a < 4; ++a) {
-        double s = 0;
-        for (int i = 0; i < 9; ++i) s += gR[a][i] * dR[i];
-        dqn[a] = s;
-      }
-      const double qd = dqn[0] * o.qn[0] + dqn[1] * o.qn[1] + dqn[2] * o.qn[2] + dqn[3] * o.qn[3];
-      for (int a = 0; a < 4; ++a) dq[a] += (dqn[a] - o.qn[a] * qd) / o.qnorm;
     }
     for (int i = 0; i < 3; ++i) {
-      if (d_means) d_means[g * 3 + i] = dp[i];
-      if (d_scales) d_scales[g * 3 + i] = ds[i];
+      if (d_means) d_means[g * 3 + i] = acc3.dp[i];
+      if (d_scales) d_scales[g * 3 + i] = acc3.ds[i];
+      if (e_means) e_means[g * 3 + i] = bound.dp[i];
+      if (e_scales) e_scales[g * 3 + i] = bound.ds[i];
     }
-    if (d_quats)
-      for (int i = 0; i < 4; ++i) d_quats[g * 4 + i] = dq[i];
-    if (d_opac) d_opac[g] = dop;
-    if (d_sh)
-      for (int i = 0; i < c.K * 3; ++i) d_sh[g * c.K * 3 + i] = dk[i];
+    for (int i = 0; i < 4; ++i) {
+      if (d_quats) d_quats[g * 4 + i] = acc3.dq[i];
+      if (e_quats) e_quats[g * 4 + i] = bound.dq[i];
+    }
+    if (d_opac) d_opac[g] = acc3.dop;
+    if (e_opac) e_opac[g] = bound.dop;
+    for (int i = 0; i < c.K * 3; ++i) {
+      if (d_sh) d_sh[g * c.K * 3 + i] = acc3.dk[i];
+      if (e_sh) e_sh[g * c.K * 3 + i] = bound.dk[i];
+    }
     if (flagged) flagged[g] = fl;
   }
 }

@@ -3,16 +3,26 @@
 Tolerances (FP32 kernels against the FP64 oracle):
   * tile keys, sorted record order and tile ranges: bit-exact;
   * splat centre, depth bits and tile rectangles: bit-exact (same binary32 op sequence);
-  * images: max |diff| <= 1e-4 on every pixel whose per-pixel decisions are unique;
-    a pixel is ambiguous when a skip event (a vs 1/255) sits within a relative 1e-5 of
-    its threshold or a stop event (T vs 1e-4) within a relative 1e-4 (about ten times
-    the binary32 error of each); at most 0.5% of pixels may be ambiguous and
-    there the colour/alpha difference stays within 1/255 + 1e-4;
+  * images: max |diff| <= 1e-4 on every pixel whose per-pixel decisions are unique.  A
+    decision is ambiguous when its operands lie within a relative margin of the threshold
+    (a skip value a within 1e-5 of 1/255, a transmittance within 1e-4 of 1e-4: about ten
+    times the binary32 error of each), and then either outcome is correct: the oracle
+    enumerates every combination of a pixel's ambiguous decisions and the GPU value must
+    lie within 1e-4 of the range they span.  The number of ambiguous pixels is held to what
+    the margins predict: the oracle counts the values within 100 times the margins, a
+    window 100 times wider, so lambda = that count / 100 decisions are expected and at most
+    lambda + 4 sqrt(lambda) + 5 pixels may be ambiguous (a Poisson count's upper tail);
   * loss and its output gradients: the oracle's L1 loss of the oracle's own images; the
-    sign must agree wherever the oracle's value is more than LOSS_MARGIN from the target;
-  * gradients: per parameter group ||g - g_ref||_2 <= 1e-3 ||g_ref||_2, and per element
-    |g - g_ref| <= 1e-3 max(|g_ref|, 1e-2 max|g_ref|) for every Gaussian whose
-    contributions avoided ambiguous pixels and the opacity-clamp edge.
+    sign must agree wherever the target lies more than LOSS_MARGIN outside the range of
+    the pixel's correct outcomes;
+  * gradients: per parameter group ||g - g_ref||_2 <= 1e-3 ||g_ref||_2 + ||env||_2, and per
+    element |g - g_ref| <= 1e-3 max(|g_ref|, 1e-2 max|g_ref|) + env, where env is the
+    oracle's bound on how far a correct gradient can lie from g_ref over the correct
+    outcomes of every ambiguous decision (skip, stop, opacity clamp) and every non-unique
+    loss gradient.  At most 5% of the Gaussians with a gradient may have env above the
+    1e-3 relative term in some element (the check stays a 1e-3 check on the rest), and
+    at most 1% may contribute to a pixel with too many ambiguous decisions to enumerate
+    (flagged: those are left out of the per-element check).
 """
 from __future__ import annotations
 
@@ -29,7 +39,8 @@ GRAD_REL = 1e-3
 # the largest image difference measured between the two sides); depth uses it relative
 # to max(1, |target|)
 LOSS_MARGIN = 2e-5
-AMB_FRACTION = 5e-3
+WIDENED_FRACTION = 0.05  # Gaussians whose bound exceeds the 1e-3 relative term
+FLAGGED_FRACTION = 0.01  # Gaussians at pixels whose outcomes were not enumerated
 NAMES = ("means", "scales", "quats", "opacities", "sh")
 
 
@@ -81,9 +92,15 @@ def check_records(dbg, orc, tile):
     np.testing.assert_allclose(dbg["color"][vis], rec["color"][vis], atol=1e-5)
 
 
+def ambiguity_cap(outs):
+    """(lambda, cap): the ambiguous decisions the margins predict and the Poisson cap."""
+    lam = sum(float(o["near_a"].sum() + o["near_T"].sum()) for o in outs) / oracle.NEAR_WIDE
+    return lam, lam + 4.0 * np.sqrt(lam) + 5.0
+
+
 def check_images(images, outs, dbg=None, cams=None, tol=IMG_TOL):
     """Compare per-view GPU images with the oracle's; returns a small report dict."""
-    report = dict(max_diff=0.0, ambiguous=0, pixels=0)
+    report = dict(max_diff=0.0, ambiguous=0, unbounded=0, pixels=0)
     off = 0
     for v, ((col, dep, alp), o) in enumerate(zip(images, outs)):
         col, dep, alp = (t.detach().cpu().numpy().astype(np.float64) for t in (col, dep, alp))
@@ -95,9 +112,19 @@ def check_images(images, outs, dbg=None, cams=None, tol=IMG_TOL):
         worst = max(dc[ok].max(initial=0), dd[ok].max(initial=0), da[ok].max(initial=0))
         assert worst <= tol, f"view {v}: max diff {worst:.3g} > {tol} (colour {dc[ok].max(initial=0):.3g}, " \
                              f"depth {dd[ok].max(initial=0):.3g}, alpha {da[ok].max(initial=0):.3g})"
-        assert amb.mean() <= AMB_FRACTION, f"view {v}: {amb.mean():.2%} ambiguous pixels"
         if amb.any():
-            assert dc[amb].max() <= 1 / 255 + tol and da[amb].max() <= 1 / 255 + tol
+            # every ambiguous pixel lies within tol of the range of its correct outcomes ...
+            gpu = np.concatenate([col, dep[None], alp[None]], 0)
+            bounded = o["events"] >= 0
+            out_of_range = np.maximum(o["lo"] - tol - gpu, gpu - o["hi"] - tol).max(0)
+            bad = amb & bounded & (out_of_range > 0)
+            assert not bad.any(), f"view {v}: {bad.sum()} ambiguous pixels outside their outcomes' range " \
+                                  f"(worst {out_of_range[bad].max():.3g})"
+            # ... and where they were too many to enumerate, within one skipped splat
+            unb = amb & ~bounded
+            if unb.any():
+                assert dc[unb].max() <= 1 / 255 + tol and da[unb].max() <= 1 / 255 + tol
+            report["unbounded"] += int(unb.sum())
         if dbg is not None:
             H, W = dep.shape
             nc = dbg["n_contrib"][off:off + H * W].reshape(H, W)
@@ -110,11 +137,15 @@ def check_images(images, outs, dbg=None, cams=None, tol=IMG_TOL):
         report["max_diff"] = max(report["max_diff"], float(worst))
         report["ambiguous"] += int(amb.sum())
         report["pixels"] += amb.size
+    lam, cap = ambiguity_cap(outs)
+    report["expected_ambiguous"] = round(lam, 1)
+    assert report["ambiguous"] <= cap, f"{report['ambiguous']} ambiguous pixels, the margins predict {lam:.1f}"
+    assert report["unbounded"] <= max(2, 1e-4 * report["pixels"]), report
     return report
 
 
 def check_grads(gpu, ref, rel=GRAD_REL, names=NAMES):
-    """gpu: dict of torch tensors, ref: oracle backward dict (with 'flagged').
+    """gpu: dict of torch tensors, ref: oracle backward dict (with 'envelope', 'flagged').
 
     A group whose reference is negligible next to the whole gradient (e.g. the rotation
     gradient of isotropic Gaussians, zero analytically) is measured on the scale of the
@@ -122,32 +153,46 @@ def check_grads(gpu, ref, rel=GRAD_REL, names=NAMES):
     1e-4 max|g_ref(all groups)|.
     """
     flagged = ref["flagged"]
+    n = len(flagged)
     report = {}
-    all_norm = np.sqrt(sum(np.linalg.norm(ref[n]) ** 2 for n in names))
-    all_max = max(np.abs(ref[n]).max(initial=0) for n in names)
+    all_norm = np.sqrt(sum(np.linalg.norm(ref[k]) ** 2 for k in names))
+    all_max = max(np.abs(ref[k]).max(initial=0) for k in names)
+    widened = np.zeros(n, bool)
+    has_grad = np.zeros(n, bool)
     for name in names:
-        g = gpu[name].detach().cpu().numpy().astype(np.float64).reshape(len(flagged), -1)
-        r = ref[name].reshape(len(flagged), -1)
+        g = gpu[name].detach().cpu().numpy().astype(np.float64).reshape(n, -1)
+        r = ref[name].reshape(n, -1)
+        env = ref["envelope"][name].reshape(n, -1)
         d = g - r
         nr = max(np.linalg.norm(r), 1e-3 * all_norm)
         norm_rel = np.linalg.norm(d) / max(nr, 1e-30)
-        assert norm_rel <= rel, f"{name}: ||diff||/||ref|| = {norm_rel:.3g}"
+        assert np.linalg.norm(d) <= rel * nr + np.linalg.norm(env), f"{name}: ||diff||/||ref|| = {norm_rel:.3g}"
+        base = rel * np.maximum(np.maximum(np.abs(r), 1e-2 * np.abs(r).max(initial=0)), 1e-4 * all_max)
         keep = ~flagged
-        thr = rel * np.maximum(np.maximum(np.abs(r[keep]), 1e-2 * np.abs(r).max(initial=0)), 1e-4 * all_max)
+        thr = base[keep] + env[keep]
         bad = np.abs(d[keep]) > thr
         assert not bad.any(), f"{name}: {bad.sum()} elements outside tolerance, worst " \
                               f"{(np.abs(d[keep]) / np.maximum(thr, 1e-30)).max():.3g}x"
+        widened |= (env > base).any(1)
+        has_grad |= (r != 0).any(1)
         report[name] = norm_rel
+    contributing = max(int(has_grad.sum()), 1)
+    report["contributing"] = contributing
+    report["widened"] = int((widened & has_grad).sum())
     report["flagged"] = int(flagged.sum())
+    assert report["widened"] <= WIDENED_FRACTION * contributing, report
+    assert report["flagged"] <= FLAGGED_FRACTION * contributing, report
     return report
 
 
 def oracle_loss(outs, targets, depth_weight=0.1):
     """The oracle's L1 loss of its own images (nothing from the GPU).
 
-    Returns (loss, [dL/dC], [dL/dD], [pixel masks]) where a mask marks the pixels whose
-    loss gradient is not unique: a colour or valid depth within LOSS_MARGIN of its
-    target, or a pixel whose forward decisions were already ambiguous."""
+    Returns (loss, [dL/dC], [dL/dD], [pixel masks]) where a mask (uint8, bit k for colour
+    channel k = 0..2, bit 3 for depth) marks the outputs whose loss gradient is not unique:
+    a colour or valid target depth within LOSS_MARGIN of the range the pixel's correct
+    outcomes span (just the value where its decisions are unique); every bit is set at a
+    pixel whose outcomes were too many to enumerate."""
     L, gcs, gds, amb = 0.0, [], [], []
     for o, (tc, td) in zip(outs, targets):
         tc = np.asarray(tc, np.float64)
@@ -156,9 +201,14 @@ def oracle_loss(outs, targets, depth_weight=0.1):
         L += l
         gcs.append(gC)
         gds.append(gD)
-        near = (np.abs(o["color"] - tc) <= LOSS_MARGIN).any(0)
-        near |= (td > 0) & (np.abs(o["depth"] - td) <= LOSS_MARGIN * np.maximum(1.0, np.abs(td)))
-        amb.append(near | o["ambiguous"])
+        # a tie: the target within LOSS_MARGIN of the range of the pixel's correct outcomes
+        lo, hi = o["lo"], o["hi"]
+        near_c = (tc >= lo[:3] - LOSS_MARGIN) & (tc <= hi[:3] + LOSS_MARGIN)
+        dm = LOSS_MARGIN * np.maximum(1.0, np.abs(td))
+        near_d = (td > 0) & (td >= lo[3] - dm) & (td <= hi[3] + dm)
+        m = near_c[0] * 1 + near_c[1] * 2 + near_c[2] * 4 + near_d * 8
+        m = np.where(o["events"] < 0, 31, m)
+        amb.append(m.astype(np.uint8))
     return L, gcs, gds, amb
 
 
@@ -168,11 +218,13 @@ def check_loss_grads(gc, gd, ref_gc, ref_gd, amb):
     for v, (a, b, c, d, m) in enumerate(zip(gc, gd, ref_gc, ref_gd, amb)):
         a = a.detach().cpu().numpy().astype(np.float64)
         c = np.asarray(c)
-        ok = np.broadcast_to(~m, a.shape)
+        tied = np.stack([(m >> k) & 1 for k in range(3)]).astype(bool)
+        ok = ~tied
         np.testing.assert_allclose(a[ok], c[ok], rtol=1e-6, atol=0, err_msg=f"view {v} colour")
-        assert (np.abs(a[~ok]) <= np.abs(c).max() * (1 + 1e-6)).all()
+        assert (np.abs(a[tied]) <= np.abs(c).max() * (1 + 1e-6)).all()
         if b is not None:
             b = b.detach().cpu().numpy().astype(np.float64)
             d = np.asarray(d)
-            np.testing.assert_allclose(b[~m], d[~m], rtol=1e-6, atol=0, err_msg=f"view {v} depth")
-            assert (np.abs(b[m]) <= np.abs(d).max() * (1 + 1e-6)).all()
+            td = ((m >> 3) & 1).astype(bool)
+            np.testing.assert_allclose(b[~td], d[~td], rtol=1e-6, atol=0, err_msg=f"view {v} depth")
+            assert (np.abs(b[td]) <= np.abs(d).max() * (1 + 1e-6)).all()

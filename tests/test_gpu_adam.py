@@ -169,7 +169,9 @@ def _fused_tolerance(p0, g, m0, v0, t, flagged, all_max):
     for k in GROUPS:
         x, gk = p0[k].astype(np.float64), g[k]
         gmax = np.abs(gk).max(initial=0)
-        dg = GRAD_REL * np.maximum(np.maximum(np.abs(gk), 1e-2 * gmax), 1e-4 * all_max)
+        # the gradient bar of the parity tests, widened by the oracle's bound of the other
+        # correct gradients (decisions inside their margins, non-unique loss signs)
+        dg = GRAD_REL * np.maximum(np.maximum(np.abs(gk), 1e-2 * gmax), 1e-4 * all_max) + g["envelope"][k]
         if k == "scales":
             c = x
         elif k == "opacities":

@@ -433,11 +433,10 @@ def _fd_scene(deg, seed):
     return g, c
 
 
-@pytest.mark.parametrize("norm", [False, True])
-@pytest.mark.parametrize("deg,seed", [(0, 20), (3, 21)])
-def test_backward_matches_central_differences(deg, seed, norm):
-    g, c = _fd_scene(deg, seed)
-    s = oracle.Settings(mu_fp32=False, tile=8, bg=(0.1, 0.2, 0.3), normalized_depth=norm)
+def _fd_check(g, c, deg, s, seed, trials=100):
+    """Central differences (h = 1e-6, FP64) of <w, outputs> at random parameters against the
+    analytic gradient; stencils that change a discrete decision (keys, order, contributors
+    or the stop position) are left out.  Returns the checked (group, index) pairs."""
     rng = np.random.default_rng(seed + 100)
     H, W = c.height, c.width
     wC, wD, wA = rng.standard_normal((3, H, W)), rng.standard_normal((H, W)), rng.standard_normal((H, W))
@@ -458,8 +457,8 @@ def test_backward_matches_central_differences(deg, seed, norm):
 
     names = ["means", "scales", "quats", "opacities", "sh"]
     h = 1e-6
-    checked = 0
-    for trial in range(100):
+    checked = []
+    for trial in range(trials):
         gi = trial % 5
         arr = base[gi]
         idx = tuple(rng.integers(0, d) for d in arr.shape)
@@ -475,8 +474,17 @@ def test_backward_matches_central_differences(deg, seed, norm):
         a = an[names[gi]][idx]
         scale = max(abs(a), 1e-2 * np.abs(an[names[gi]]).max(), 1e-6)
         assert abs(fd - a) <= 1e-4 * scale, (names[gi], idx, fd, a)
-        checked += 1
-    assert checked >= 80
+        checked.append((gi, idx, a))
+    return checked, ref_out
+
+
+@pytest.mark.parametrize("norm", [False, True])
+@pytest.mark.parametrize("deg,seed", [(0, 20), (3, 21)])
+def test_backward_matches_central_differences(deg, seed, norm):
+    g, c = _fd_scene(deg, seed)
+    s = oracle.Settings(mu_fp32=False, tile=8, bg=(0.1, 0.2, 0.3), normalized_depth=norm)
+    checked, _ = _fd_check(g, c, deg, s, seed)
+    assert len(checked) >= 80
 
 
 def test_loss_l1_gradient():
@@ -573,3 +581,168 @@ def test_normalized_depth_closed_forms():
     a1 = 0.4
     a2 = 0.6
     assert centre == pytest.approx((2.0 * a1 + 3.0 * a2 * (1 - a1)) / (a1 + a2 * (1 - a1)), rel=1e-6)
+
+
+# ---------------------------------------------------------------------------------------
+# dense scenes where most pixels stop (T < T_min, the crossing Gaussian included)
+# ---------------------------------------------------------------------------------------
+
+T_MIN32 = float(np.float32(1e-4))
+
+
+def _dense_scene(seed, n, deg):
+    """n large, nearly opaque Gaussians (opacity 0.9-0.99) piled on a 32x24 image."""
+    rng = np.random.default_rng(seed)
+    means = np.stack([rng.uniform(-0.5, 0.5, n), rng.uniform(-0.4, 0.4, n), rng.uniform(1.5, 3.0, n)], 1)
+    g = scenes.random_gaussians(rng, means, deg)
+    g.scales = np.exp(rng.uniform(np.log(0.15), np.log(0.4), (n, 3))).astype(np.float32)
+    g.opacities = rng.uniform(0.9, 0.99, n).astype(np.float32)
+    return g, cam(32, 24, 30.0, cx=15.7, cy=11.4)
+
+
+@pytest.mark.parametrize("deg,seed", [(0, 30), (3, 31)])
+def test_dense_stopping_scene_equals_brute_force(deg, seed):
+    g, c = _dense_scene(seed, 300, deg)
+    orc = oracle.Oracle(g.arrays(), deg, [c], oracle.Settings(mu_fp32=False, tile=8))
+    out = orc.forward()[0]
+    b = brute.render(g.arrays(), deg, c)
+    assert b["stopped"].mean() >= 0.5, b["stopped"].mean()
+    np.testing.assert_array_equal(out["T_final"] < T_MIN32, b["stopped"])
+    for k in ("color", "depth", "alpha", "T_final"):
+        np.testing.assert_allclose(out[k], b[k], atol=1e-12, rtol=0, err_msg=k)
+    # the same contributors, and the same Gaussian last (where a pixel stopped: the one
+    # that took T below T_min)
+    np.testing.assert_array_equal(out["n_used"], b["count"])
+    _, vals, ranges = orc.keys()
+    H, W = c.height, c.width
+    tiles_x = (W + 7) // 8
+    last = np.full((H, W), -1, np.int64)
+    for y in range(H):
+        for x in range(W):
+            k = out["n_contrib"][y, x]
+            if k > 0:
+                last[y, x] = vals[ranges[(y // 8) * tiles_x + x // 8, 0] + k - 1] % g.n
+    np.testing.assert_array_equal(last, b["last"])
+
+
+@pytest.mark.parametrize("deg,seed", [(0, 40), (3, 41)])
+def test_backward_matches_central_differences_where_pixels_stop(deg, seed):
+    g, c = _dense_scene(seed, 120, deg)
+    s = oracle.Settings(mu_fp32=False, tile=8, bg=(0.1, 0.2, 0.3))
+    checked, out = _fd_check(g, c, deg, s, seed, trials=140)
+    stopped = out["T_final"] < T_MIN32
+    assert stopped.mean() >= 0.3, stopped.mean()
+    assert len(checked) >= 80
+    # the check reaches Gaussians whose reverse pass starts at a stopped pixel
+    _, vals, ranges = oracle.Oracle(g.arrays(), deg, [c], s).keys()
+    tiles_x = (c.width + 7) // 8
+    crossing = set()
+    for y, x in zip(*np.nonzero(stopped)):
+        k = out["n_contrib"][y, x]
+        crossing.add(int(vals[ranges[(y // 8) * tiles_x + x // 8, 0] + k - 1] % g.n))
+    hit = [a for gi, idx, a in checked if idx[0] in crossing and a != 0.0]
+    assert len(hit) >= 20, len(hit)
+
+
+# ---------------------------------------------------------------------------------------
+# several correct results: every outcome of a decision inside its margin is enumerated
+# ---------------------------------------------------------------------------------------
+
+A_MIN32 = float(np.float32(1 / 255))
+A_MAX32 = float(np.float32(0.99))
+
+
+def _stack(opac, rgb=None):
+    """Four wide Gaussians on the optical axis at depths 1.5, 2, 2.5, 3 (front to back);
+    at the principal point (12, 10) each splat value equals its opacity exactly."""
+    n = len(opac)
+    means = [[0.0, 0.0, 1.5 + 0.5 * i] for i in range(n)]
+    scales = [[0.6 + 0.1 * i, 0.5, 0.4] for i in range(n)]
+    rgb = rgb or [[0.9, 0.1, 0.2], [0.2, 0.8, 0.3], [0.1, 0.3, 0.9], [0.7, 0.6, 0.1]][:n]
+    p = gaussians(means, scales, rgb=rgb)
+    p[3] = np.asarray(opac, np.float64)   # opacities in binary64: the oracle takes them as given
+    return [np.asarray(a, np.float64) for a in p]
+
+
+def _run(p, gC=None):
+    c = cam(24, 20, 40.0, cx=12.0, cy=10.0)
+    s = oracle.Settings(mu_fp32=True, tile=8)
+    orc = oracle.Oracle(p, 0, [c], s)
+    out = orc.forward()[0]
+    rng = np.random.default_rng(5)
+    gC = rng.standard_normal((3, 20, 24)) if gC is None else gC
+    gD = rng.standard_normal((20, 24))
+    return orc, out, gC, gD
+
+
+def _covers(out_ref, out_alt, bck_ref, bck_alt, slack_img=0.0, slack_grad=0.0):
+    """The alternative outcome lies inside the reference's bounds (image and gradients)."""
+    gpu_like = np.concatenate([out_alt["color"], out_alt["depth"][None], out_alt["alpha"][None]], 0)
+    assert (gpu_like >= out_ref["lo"] - slack_img).all() and (gpu_like <= out_ref["hi"] + slack_img).all()
+    biggest = 0.0
+    for k in ("means", "scales", "quats", "opacities", "sh"):
+        d = np.abs(bck_alt[k] - bck_ref[k])
+        env = bck_ref["envelope"][k]
+        assert (d <= env * (1 + 1e-9) + slack_grad + 1e-15).all(), (k, (d - env).max())
+        biggest = max(biggest, d.max())
+    # the change is real, and well above the slack the alternative's own input change needs
+    assert biggest > 10.0 * slack_grad and biggest > 0.0
+    assert not bck_ref["flagged"].any()
+
+
+def test_envelope_covers_the_other_skip_decision():
+    # splat 1 sits at alpha_min (1 + 3e-6) at the principal point: included there, but a
+    # binary32 renderer may skip it; with alpha_min (1 - 1e-9) it is skipped
+    o = [0.5, A_MIN32 * (1 + 3e-6), 0.6, 0.7]
+    orc, out, gC, gD = _run(_stack(o))
+    assert out["events"][10, 12] == 1 and out["ambiguous"].sum() == 1
+    assert (out["hi"] - out["lo"]).max() > 1e-4          # the two outcomes differ visibly
+    bref = orc.backward([gC], [gD])
+    o_alt = list(o)
+    o_alt[1] = A_MIN32 * (1 - 1e-9)
+    orc2, out2, _, _ = _run(_stack(o_alt), gC)
+    # the skipped splat contributes nowhere, so this is exactly the other outcome
+    _covers(out, out2, bref, orc2.backward([gC], [gD]))
+
+
+def test_envelope_covers_the_other_stop_decision():
+    # T after splat 2 is T_min (1 + 5e-5): the pass goes on to splat 3, but it may stop there
+    a0, a1 = 0.95, 0.9
+    T_prev = (1 - a0) * (1 - a1)
+    a2 = 1 - T_MIN32 * (1 + 5e-5) / T_prev
+    orc, out, gC, gD = _run(_stack([a0, a1, a2, 0.6]))
+    assert out["events"][10, 12] == 1
+    assert out["n_used"][10, 12] == 4
+    bref = orc.backward([gC], [gD])
+    a2_alt = 1 - T_MIN32 * (1 - 1e-9) / T_prev
+    orc2, out2, _, _ = _run(_stack([a0, a1, a2_alt, 0.6]), gC)
+    assert out2["n_used"][10, 12] == 3
+    assert (out["hi"] - out["lo"])[:, 10, 12].max() > 1e-5   # splat 3 behind the stop is visible
+    # the alternative moved splat 2's opacity by ~1e-6 relative as well (every pixel)
+    scale = max(np.abs(bref[k]).max() for k in ("means", "scales", "opacities", "sh"))
+    _covers(out, out2, bref, orc2.backward([gC], [gD]), slack_img=1e-6, slack_grad=1e-5 * scale)
+
+
+def test_envelope_covers_the_other_clamp_decision():
+    # splat 0 sits at alpha_max (1 + 2e-6) at the principal point: clamped, so its value
+    # gradient there is 0; unclamped (alpha_max (1 - 1e-9)) it is not
+    orc, out, gC, gD = _run(_stack([A_MAX32 * (1 + 2e-6), 0.5]))
+    assert out["events"][10, 12] == 0          # a clamp changes no value, only a gradient
+    bref = orc.backward([gC], [gD])
+    orc2, out2, _, _ = _run(_stack([A_MAX32 * (1 - 1e-9), 0.5]), gC)
+    # the alternative moved splat 0's opacity by 2e-6 relative (every pixel)
+    scale = max(np.abs(bref[k]).max() for k in ("means", "scales", "opacities", "sh"))
+    _covers(out, out2, bref, orc2.backward([gC], [gD]), slack_img=1e-5, slack_grad=1e-5 * scale)
+
+
+def test_envelope_covers_a_flipped_loss_sign():
+    # output 0 (red) of one pixel has a non-unique gradient: its sign may flip
+    orc, out, gC, gD = _run(_stack([0.5, 0.6, 0.3]))
+    tie = np.zeros((20, 24), np.uint8)
+    tie[9, 13] = 1
+    bref = orc.backward([gC], [gD], ambiguous_pixels=[tie])
+    gC2 = gC.copy()
+    gC2[0, 9, 13] = -gC[0, 9, 13]
+    _covers(out, out, bref, orc.backward([gC2], [gD]))
+    # a pixel without a mark keeps its gradient unique
+    assert sum(np.abs(orc.backward([gC], [gD])["envelope"][k]).max() for k in ("means", "sh")) == 0.0
