@@ -60,7 +60,8 @@ class _Set(ctypes.Structure):
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("T_min", ctypes.c_float),
                 ("guard", ctypes.c_float), ("bg", ctypes.c_float * 3), ("mu_fp32", ctypes.c_int32),
                 ("threads", ctypes.c_int32), ("amb_rel_a", ctypes.c_float), ("amb_rel_T", ctypes.c_float),
-                ("exact_tiles", ctypes.c_int32), ("normalized_depth", ctypes.c_int32)]
+                ("exact_tiles", ctypes.c_int32), ("normalized_depth", ctypes.c_int32),
+                ("window", ctypes.c_int32 * 4), ("jclamp", ctypes.c_float)]
 
 
 _lib = None
@@ -110,11 +111,19 @@ class Settings:
     amb_rel_T: float = 1e-4     # binary32 T accumulates ~100 rounded products
     exact_tiles: bool = False   # per tile row, only the columns the ellipse can reach
     normalized_depth: bool = False   # depth output D / (1 - T_final)
+    # (x0, y0, x1, y1): only pixels x0 <= x < x1, y0 <= y < y1 of every view are rendered and
+    # differentiated (outputs elsewhere stay 0); None: every pixel
+    window: tuple | None = None
+    # > 0: x/z and y/z clamped inside the projection's Jacobian to +-jclamp W / (2 fx) and
+    # +-jclamp H / (2 fy) (a guard band; 0: Eq. 5 as printed)
+    jclamp: float = 0.0
 
     def _c(self):
+        w = (0, 0, 0, 0) if self.window is None else tuple(int(x) for x in self.window)
         return _Set(self.tile, self.extent_k, self.lowpass, self.alpha_min, self.alpha_max, self.T_min, self.guard,
                     (ctypes.c_float * 3)(*self.bg), int(self.mu_fp32), int(self.threads), self.amb_rel_a,
-                    self.amb_rel_T, int(self.exact_tiles), int(self.normalized_depth))
+                    self.amb_rel_T, int(self.exact_tiles), int(self.normalized_depth), (ctypes.c_int32 * 4)(*w),
+                    float(self.jclamp))
 
 
 def _cams(cameras):

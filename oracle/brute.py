@@ -61,7 +61,7 @@ def quat_to_rot(q):
     return R
 
 
-def project(params, sh_degree, cam, lowpass=0.3, guard=0.15):
+def project(params, sh_degree, cam, lowpass=0.3, guard=0.15, jclamp=0.0):
     """FP64 splat parameters of every Gaussian: dict(mu, conic, z, color, opacity, front).
 
     ``front`` marks the Gaussians in the view frustum: binary32 depth above znear and
@@ -77,10 +77,19 @@ def project(params, sh_degree, cam, lowpass=0.3, guard=0.15):
     Sigma = S @ np.transpose(S, (0, 2, 1))               # Eq. 2
     fx, fy = float(np.float32(cam.fx)), float(np.float32(cam.fy))
     J = np.zeros((means.shape[0], 2, 3))
+    txj, tyj = tx, ty
+    if jclamp > 0:   # guard band inside J: x/z, y/z clamped to +-jclamp times the half field of view
+        f = np.float32
+        limx = float(f(jclamp) * (f(0.5) * f(cam.width) / f(cam.fx)))
+        limy = float(f(jclamp) * (f(0.5) * f(cam.height) / f(cam.fy)))
+        txj = np.clip(tx / tz, -limx, limx) * tz
+        tyj = np.clip(ty / tz, -limy, limy) * tz
+        txj = np.where(np.abs(tx / tz) > limx, txj, tx)
+        tyj = np.where(np.abs(ty / tz) > limy, tyj, ty)
     J[:, 0, 0] = fx / tz
-    J[:, 0, 2] = -fx * tx / tz ** 2
+    J[:, 0, 2] = -fx * txj / tz ** 2
     J[:, 1, 1] = fy / tz
-    J[:, 1, 2] = -fy * ty / tz ** 2
+    J[:, 1, 2] = -fy * tyj / tz ** 2
     JW = J @ W
     cov = JW @ Sigma @ np.transpose(JW, (0, 2, 1)) + float(np.float32(lowpass)) * np.eye(2)   # Eq. 5
     conic = np.linalg.inv(cov)
@@ -112,9 +121,9 @@ def project(params, sh_degree, cam, lowpass=0.3, guard=0.15):
 
 
 def render(params, sh_degree, cam, alpha_min=1 / 255, alpha_max=0.99, T_min=1e-4, bg=(0, 0, 0), lowpass=0.3,
-           guard=0.15):
+           guard=0.15, jclamp=0.0):
     """Per-pixel front-to-back compositing over all Gaussians in the frustum (no tiles)."""
-    pr = project(params, sh_degree, cam, lowpass, guard)
+    pr = project(params, sh_degree, cam, lowpass, guard, jclamp)
     idx = np.nonzero(pr["front"])[0]
     zb = pr["z32"][idx].view(np.uint32)
     order = idx[np.lexsort((idx, zb))]

@@ -45,12 +45,17 @@ typedef struct {
   float T_min;         // stop once transmittance falls below this
   float guard;         // frustum guard band, as a fraction of the image size per side
   float bg[3];         // background colour
-  int32_t mu_fp32;     // 1: value stage uses the binary32 splat centre of the discrete stage
+  int32_t mu_fp32;     // 1: value stage uses the binary32 splat centre and projected covariance
+                       //    of the discrete stage (the conic is their binary64 inverse)
   int32_t threads;     // worker threads for the pixel loop (>=1)
   float amb_rel_a;     // relative margin around alpha_min that flags a skip decision as ambiguous
   float amb_rel_T;     // relative margin around T_min that flags a stop decision as ambiguous
   int32_t exact_tiles; // 1: a tile row keeps only the columns its ellipse can reach (row_run)
   int32_t normalized_depth;  // 1: the depth output is D / (1 - T_final) (0 where nothing is hit)
+  int32_t window[4];   // pixels x0 <= x < x1, y0 <= y < y1 of every view are rendered and
+                       // differentiated (outputs elsewhere untouched); x1 <= x0: every pixel
+  float jclamp;        // > 0: inside the projection's Jacobian, x/z and y/z are clamped to
+                       // +-jclamp times the half field of view, W / (2 fx) and H / (2 fy)
 } or_settings;
 
 }  // extern "C"
@@ -168,8 +173,15 @@ struct Disc {
   int x0 = 0, x1 = -1, y0 = 0, y1 = -1;  // inclusive pixel rectangle
 };
 
+// Guard-band limits of x/z and y/z inside the Jacobian (binary32): jclamp (W / 2) / fx and
+// jclamp (H / 2) / fy.
+void clamp_limits(const or_camera& cam, float jclamp, float& limx, float& limy) {
+  limx = jclamp * ((0.5f * float(cam.width)) / cam.fx);
+  limy = jclamp * ((0.5f * float(cam.height)) / cam.fy);
+}
+
 Disc discrete_stage(const float p[3], const float s[3], const float q[4], const or_camera& cam,
-                    float k, float lowpass, float guard) {
+                    float k, float lowpass, float guard, float jclamp) {
   Disc d;
   const float* W = cam.R;
   // camera-space mean, each row summed left to right
@@ -213,8 +225,19 @@ Disc discrete_stage(const float p[3], const float s[3], const float q[4], const 
   const float tz2 = tz * tz;
   const float j00 = cam.fx / tz;
   const float j11 = cam.fy / tz;
-  const float j02 = -(cam.fx * tx) / tz2;
-  const float j12 = -(cam.fy * ty) / tz2;
+  // with the guard-band clamp, an offset beyond the limit enters J as limit * z
+  float txj = tx, tyj = ty;
+  if (jclamp > 0.f) {
+    float limx, limy;
+    clamp_limits(cam, jclamp, limx, limy);
+    const float ux = tx / tz, uy = ty / tz;
+    if (ux < -limx) txj = -limx * tz;
+    else if (ux > limx) txj = limx * tz;
+    if (uy < -limy) tyj = -limy * tz;
+    else if (uy > limy) tyj = limy * tz;
+  }
+  const float j02 = -(cam.fx * txj) / tz2;
+  const float j12 = -(cam.fy * tyj) / tz2;
   // T = J W (2x3)
   float T[6];
   for (int c = 0; c < 3; ++c) {
@@ -389,6 +412,7 @@ struct Geo {
   double R[9], M[9], Sig[9];      // rotation, R diag(s), Sigma = M M^T (Eq. 2)
   double W[9], t[3];              // camera rotation, camera-space mean
   double J[6], T[6];              // Jacobian (2x3) and T = J W
+  bool clx, cly;                  // x/z, y/z clamped inside J (guard band)
   double S2[3];                   // projected covariance (a, b, c) incl. low-pass (Eq. 5)
   double det, A, B, C;            // conic
   double mux, muy;
@@ -437,12 +461,27 @@ void make_geo(const Ctx& c, int v, int64_t g, Geo& o) {
   for (int i = 0; i < 3; ++i)
     o.t[i] = o.W[i * 3 + 0] * o.p[0] + o.W[i * 3 + 1] * o.p[1] + o.W[i * 3 + 2] * o.p[2] + double(cam.t[i]);
   const double fx = cam.fx, fy = cam.fy, tx = o.t[0], ty = o.t[1], tz = o.t[2];
+  double txj = tx, tyj = ty;
+  o.clx = o.cly = false;
+  if (c.set.jclamp > 0.f) {
+    float limx, limy;
+    clamp_limits(cam, c.set.jclamp, limx, limy);
+    const double ux = tx / tz, uy = ty / tz;
+    if (ux < -double(limx) || ux > double(limx)) {
+      o.clx = true;
+      txj = (ux < 0 ? -double(limx) : double(limx)) * tz;
+    }
+    if (uy < -double(limy) || uy > double(limy)) {
+      o.cly = true;
+      tyj = (uy < 0 ? -double(limy) : double(limy)) * tz;
+    }
+  }
   o.J[0] = fx / tz;
   o.J[1] = 0;
-  o.J[2] = -fx * tx / (tz * tz);
+  o.J[2] = -fx * txj / (tz * tz);
   o.J[3] = 0;
   o.J[4] = fy / tz;
-  o.J[5] = -fy * ty / (tz * tz);
+  o.J[5] = -fy * tyj / (tz * tz);
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 3; ++j) {
       double acc = 0;
@@ -510,7 +549,7 @@ void build(Ctx& c) {
         s[i] = float(c.scales[g * 3 + i]);
       }
       for (int i = 0; i < 4; ++i) q[i] = float(c.quats[g * 4 + i]);
-      Disc d = discrete_stage(p, s, q, c.cams[v], c.set.extent_k, c.set.lowpass, c.set.guard);
+      Disc d = discrete_stage(p, s, q, c.cams[v], c.set.extent_k, c.set.lowpass, c.set.guard, c.set.jclamp);
       c.disc[size_t(v) * N + g] = d;
       if (!d.vis) continue;
       const int tx0 = d.x0 / ts, tx1 = d.x1 / ts, ty0 = d.y0 / ts, ty1 = d.y1 / ts;
@@ -562,9 +601,19 @@ void build(Ctx& c) {
         r.muy = o.muy;
       }
       r.z = o.t[2];
-      r.A = o.A;
-      r.B = o.B;
-      r.C = o.C;
+      if (c.set.mu_fp32) {
+        // the projected covariance as the fixed binary32 sequence leaves it (the same bits
+        // on both sides), inverted in binary64
+        const double a = d.ca, b = d.cb, cc = d.cc;
+        const double det = a * cc - b * b;
+        r.A = cc / det;
+        r.B = -b / det;
+        r.C = a / det;
+      } else {
+        r.A = o.A;
+        r.B = o.B;
+        r.C = o.C;
+      }
       r.opacity = c.opac[g];
       sh.eval(o.v, Y.data(), nullptr);
       for (int ch = 0; ch < 3; ++ch) {
@@ -737,6 +786,24 @@ void sweep(const Ctx& c, const Pass& p, const std::vector<Hit>& hits, const doub
   }
 }
 
+// The pixels [xa, xb) x [ya, yb) of tile (tx, ty) inside the settings' window (the whole
+// tile when the window is empty); false when none.
+bool window_of_tile(const Ctx& c, int tx, int ty, int W, int H, int& xa, int& xb, int& ya, int& yb) {
+  const int ts = c.set.tile;
+  xa = tx * ts;
+  ya = ty * ts;
+  xb = std::min(W, (tx + 1) * ts);
+  yb = std::min(H, (ty + 1) * ts);
+  const int32_t* w = c.set.window;
+  if (w[2] > w[0] && w[3] > w[1]) {
+    xa = std::max(xa, int(w[0]));
+    ya = std::max(ya, int(w[1]));
+    xb = std::min(xb, int(w[2]));
+    yb = std::min(yb, int(w[3]));
+  }
+  return xa < xb && ya < yb;
+}
+
 template <class F>
 void parallel_tiles(const Ctx& c, F&& f) {
   const int64_t tiles = c.tile_off.back();
@@ -828,10 +895,12 @@ void chain(const Ctx& c, const SHBasis& sh, std::vector<double>& Y, double (*dY)
       }
     const double fx = cam.fx, fy = cam.fy, tx = o.t[0], ty = o.t[1], tz = o.t[2];
     double dt[3] = {0, 0, 0};
-    dt[0] += dJ[2] * (-fx / (tz * tz));
-    dt[1] += dJ[5] * (-fy / (tz * tz));
-    dt[2] += dJ[0] * (-fx / (tz * tz)) + dJ[2] * (2.0 * fx * tx / (tz * tz * tz)) + dJ[4] * (-fy / (tz * tz)) +
-             dJ[5] * (2.0 * fy * ty / (tz * tz * tz));
+    // J02 = -fx x'/z^2 with x' = x, or +-limit z where clamped (then J02 = -+fx limit / z);
+    // likewise J12: d/dx of a clamped entry is 0, and d/dz is -J02/z instead of -2 J02/z
+    dt[0] += o.clx ? 0.0 : dJ[2] * (-fx / (tz * tz));
+    dt[1] += o.cly ? 0.0 : dJ[5] * (-fy / (tz * tz));
+    dt[2] += dJ[0] * (-fx / (tz * tz)) + dJ[2] * (o.clx ? -o.J[2] / tz : 2.0 * fx * tx / (tz * tz * tz)) +
+             dJ[4] * (-fy / (tz * tz)) + dJ[5] * (o.cly ? -o.J[5] / tz : 2.0 * fy * ty / (tz * tz * tz));
     // splat centre (Eq. 4) and depth
     dt[0] += G[0] * fx / tz;
     dt[2] += -G[0] * fx * tx / (tz * tz);
@@ -957,8 +1026,10 @@ void or_forward(void* h, double* color, double* depth, double* alpha, double* T_
       const int W = c.cams[v].width, H = c.cams[v].height;
       const int tx = int(lt % c.tiles_x[v]), ty = int(lt / c.tiles_x[v]);
       const int64_t P = int64_t(W) * H;
-      for (int y = ty * ts; y < std::min(H, (ty + 1) * ts); ++y)
-        for (int x = tx * ts; x < std::min(W, (tx + 1) * ts); ++x) {
+      int xa, xb, ya, yb;
+      if (!window_of_tile(c, tx, ty, W, H, xa, xb, ya, yb)) continue;
+      for (int y = ya; y < yb; ++y)
+        for (int x = xa; x < xb; ++x) {
           const int64_t pix = int64_t(y) * W + x;
           const int64_t base = c.pix_off[v];
           double l[5], u[5];
@@ -1040,8 +1111,10 @@ void or_backward(void* h, const double* g_color, const double* g_depth, const do
       const int W = c.cams[v].width, H = c.cams[v].height;
       const int tx = int(lt % c.tiles_x[v]), ty = int(lt / c.tiles_x[v]);
       const int64_t P = int64_t(W) * H, base = c.pix_off[v];
-      for (int y = ty * ts; y < std::min(H, (ty + 1) * ts); ++y)
-        for (int x = tx * ts; x < std::min(W, (tx + 1) * ts); ++x) {
+      int xa, xb, ya, yb;
+      if (!window_of_tile(c, tx, ty, W, H, xa, xb, ya, yb)) continue;
+      for (int y = ya; y < yb; ++y)
+        for (int x = xa; x < xb; ++x) {
           const int64_t pix = int64_t(y) * W + x;
           double gC[3];
           for (int ch = 0; ch < 3; ++ch) gC[ch] = g_color ? g_color[base * 3 + ch * P + pix] : 0.0;

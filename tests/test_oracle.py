@@ -746,3 +746,97 @@ def test_envelope_covers_a_flipped_loss_sign():
     _covers(out, out, bref, orc.backward([gC2], [gD]))
     # a pixel without a mark keeps its gradient unique
     assert sum(np.abs(orc.backward([gC], [gD])["envelope"][k]).max() for k in ("means", "sh")) == 0.0
+
+
+def test_window_renders_and_differentiates_only_its_pixels():
+    # a window of a view equals the same pixels of the full render, and its gradient is the
+    # full gradient of output gradients that vanish outside the window
+    w = scenes.make_cfg1(n=400)
+    g, c = w.gaussians, w.cameras[0]
+    s = oracle.Settings(mu_fp32=True, tile=16)
+    full = oracle.Oracle(g.arrays(), 0, [c], s)
+    win = (37, 21, 101, 70)
+    sw = oracle.Settings(mu_fp32=True, tile=16, window=win)
+    part = oracle.Oracle(g.arrays(), 0, [c], sw)
+    a, b = full.forward()[0], part.forward()[0]
+    x0, y0, x1, y1 = win
+    for k in ("color", "depth", "alpha", "T_final", "lo", "hi"):
+        np.testing.assert_array_equal(a[k][..., y0:y1, x0:x1], b[k][..., y0:y1, x0:x1])
+        outside = np.ones(b[k].shape[-2:], bool)
+        outside[y0:y1, x0:x1] = False
+        assert (b[k][..., outside] == 0).all()
+    rng = np.random.default_rng(3)
+    gC = rng.standard_normal((3, c.height, c.width))
+    gD = rng.standard_normal((c.height, c.width))
+    mask = np.zeros((c.height, c.width))
+    mask[y0:y1, x0:x1] = 1
+    ga = full.backward([gC * mask], [gD * mask])
+    gb = part.backward([gC], [gD])
+    for k in ("means", "scales", "quats", "opacities", "sh"):
+        np.testing.assert_allclose(gb[k], ga[k], rtol=1e-12, atol=1e-14 * np.abs(ga[k]).max())
+
+
+# ---------------------------------------------------------------------------------------
+# guard-band clamp of the projection's Jacobian (x/z, y/z clamped to 1.3 half-FOVs)
+# ---------------------------------------------------------------------------------------
+
+def _offcentre_scene(seed, n=150, deg=0):
+    """Gaussians in front of a camera whose principal point sits near the left edge, so
+    that many lie beyond 1.3 half fields of view to the right of the optical axis."""
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(1.5, 3.0, n)
+    means = np.stack([rng.uniform(-0.3, 1.6, n) * z, rng.uniform(-0.5, 0.5, n) * z, z], 1)
+    g = scenes.random_gaussians(rng, means, deg)
+    g.scales = (g.scales * 4).astype(np.float32)
+    c = cam(40, 32, 30.0, cx=6.0, cy=16.0)
+    return g, c
+
+
+def test_jacobian_clamp_closed_form():
+    # an axis-aligned Gaussian at x/z = 1.6 > 1.3 W / (2 fx) = 1.04: J's x/z entry is held at the limit
+    W, H, f, z = 64, 48, 40.0, 2.0
+    lim = float(np.float32(1.3) * (np.float32(0.5 * W) / np.float32(f)))
+    p = gaussians([[1.6 * z, 0.0, z]], [[0.05, 0.04, 0.3]])
+    c = cam(W, H, f, cx=0.0, cy=24.0)
+    rec = oracle.Oracle(p, 0, [c], oracle.Settings(mu_fp32=False, jclamp=1.3, guard=10.0)).records()
+    s32 = np.float32([0.05, 0.04, 0.3]).astype(np.float64)
+    zz = float(np.float32(z))
+    sxx = (f / zz) ** 2 * s32[0] ** 2 + (f * lim / zz) ** 2 * s32[2] ** 2 + float(np.float32(0.3))
+    syy = (f / zz) ** 2 * s32[1] ** 2 + float(np.float32(0.3))
+    np.testing.assert_allclose(rec["conic"][0], [1 / sxx, 0.0, 1 / syy], rtol=1e-12, atol=1e-15)
+    # unclamped the x/z entry would be 1.6 (a wider splat)
+    rec0 = oracle.Oracle(p, 0, [c], oracle.Settings(mu_fp32=False, guard=10.0)).records()
+    assert rec0["conic"][0][0] < rec["conic"][0][0]
+
+
+@pytest.mark.parametrize("deg", [0, 3])
+def test_jacobian_clamp_equals_brute_force(deg):
+    g, c = _offcentre_scene(50 + deg, deg=deg)
+    out = oracle.Oracle(g.arrays(), deg, [c], oracle.Settings(mu_fp32=False, tile=8, jclamp=1.3)).forward()[0]
+    b = brute.render(g.arrays(), deg, c, jclamp=1.3)
+    for k in ("color", "depth", "alpha", "T_final"):
+        np.testing.assert_allclose(out[k], b[k], atol=1e-12, rtol=0, err_msg=k)
+    # the clamp acts on rendered Gaussians here and changes the image
+    pr = brute.project(g.arrays(), deg, c)
+    lim = float(np.float32(1.3) * (np.float32(0.5 * c.width) / np.float32(c.fx)))
+    t = np.asarray(g.means, np.float64) @ np.eye(3).T
+    assert (pr["front"] & (t[:, 0] / t[:, 2] > lim)).sum() >= 10
+    b0 = brute.render(g.arrays(), deg, c)
+    assert np.abs(b0["color"] - b["color"]).max() > 1e-3
+    # a limit nobody reaches changes nothing
+    far = oracle.Oracle(g.arrays(), deg, [c], oracle.Settings(mu_fp32=False, tile=8, jclamp=100.0)).forward()[0]
+    off = oracle.Oracle(g.arrays(), deg, [c], oracle.Settings(mu_fp32=False, tile=8)).forward()[0]
+    np.testing.assert_array_equal(far["color"], off["color"])
+
+
+@pytest.mark.parametrize("deg,seed", [(0, 60), (3, 61)])
+def test_jacobian_clamp_backward_matches_central_differences(deg, seed):
+    g, c = _offcentre_scene(seed, n=40, deg=deg)
+    s = oracle.Settings(mu_fp32=False, tile=8, jclamp=1.3)
+    checked, _ = _fd_check(g, c, deg, s, seed, trials=120)
+    assert len(checked) >= 80
+    lim = float(np.float32(1.3) * (np.float32(0.5 * c.width) / np.float32(c.fx)))
+    t = np.asarray(g.means, np.float64)
+    clamped = set(np.nonzero(t[:, 0] / t[:, 2] > lim)[0].tolist())
+    hit = [a for gi, idx, a in checked if gi in (0, 1, 2) and idx[0] in clamped and a != 0.0]
+    assert len(hit) >= 10, len(hit)
