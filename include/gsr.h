@@ -36,7 +36,8 @@
  *    synchronise with the host.  A context is not thread-safe.
  *  - Errors: every call returns a gsr_status; arguments are validated before any
  *    device work; a failing call leaves outputs unspecified but the context usable.
- *    gsr_last_error() gives a message.  NaN/Inf inputs are not rejected.
+ *    gsr_last_error() gives a message.  NaN/Inf inputs are not rejected unless the
+ *    settings ask for the check (GSR_CHECK_FINITE).
  */
 #ifndef GSR_H
 #define GSR_H
@@ -100,7 +101,7 @@ typedef struct {
   float T_min;
   float guard;       /* >= 0 */
   float bg[3];
-  uint32_t flags;    /* GSR_EXACT_TILES | GSR_NORMALIZED_DEPTH, or 0 */
+  uint32_t flags;    /* GSR_EXACT_TILES | GSR_NORMALIZED_DEPTH | GSR_CHECK_FINITE, or 0 */
 } gsr_settings;
 
 /* settings.flags: tile lists hold, per tile row of a splat's rectangle, only the columns
@@ -114,6 +115,12 @@ typedef struct {
  * pixel sees as an opacity-weighted mean (0 where nothing is hit), instead of the
  * accumulated D = sum z alpha T; the backward takes its gradient through the division. */
 #define GSR_NORMALIZED_DEPTH 2u
+/* settings.flags: NaN or infinite inputs are not rejected by default (they propagate into the
+ * images and gradients).  With this flag every eager forward (gsr_forward, and the forward
+ * gsr_graph_create runs to size its buffers; not the captured replays) first reads every
+ * Gaussian parameter once on the device and returns GSR_EINVAL, naming the smallest index of
+ * a Gaussian with a non-finite value, before any rendering (one more host synchronisation). */
+#define GSR_CHECK_FINITE 4u
 
 typedef struct {
   float* color; /* [3,H,W] */

@@ -16,6 +16,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ECAPACITY",
 ACCUMULATE = 1
 EXACT_TILES = 1
 NORMALIZED_DEPTH = 2
+CHECK_FINITE = 4
 
 
 class GsrError(RuntimeError):

@@ -11,9 +11,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgsr.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("gsr_host.hip", "gsr_kernels.hip", "gsr_seed.hip", "gsr_optim.hip", "gsr_tsdf.hip",
-                                           "gsr_schedule.hip")]
+                                           "gsr_schedule.cpp", "gsr_validate.cpp")]
 HEADERS = [os.path.join(ROOT, "include", "gsr.h"), os.path.join(CSRC, "gsr_internal.h"), os.path.join(CSRC, "gsr_adam.h"),
-           os.path.join(CSRC, "gsr_tsdf.h")]
+           os.path.join(CSRC, "gsr_tsdf.h"), os.path.join(CSRC, "gsr_validate.h")]
 ARCH = os.environ.get("GSR_OFFLOAD_ARCH", "gfx950")
 
 

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "gsr_internal.h"
+#include "gsr_validate.h"
 
 using namespace gsr;
 
@@ -166,51 +167,23 @@ void release(gsr_saved* sv) {
   delete sv;
 }
 
-gsr_status check_settings(gsr_ctx* ctx, const gsr_settings* s) {
-  if (!s) return fail(ctx, GSR_EINVAL, "settings is NULL");
-  if (s->tile != 8 && s->tile != 16 && s->tile != 32) return fail(ctx, GSR_EINVAL, "tile must be 8, 16 or 32");
-  if (s->batch != 128 && s->batch != 256) return fail(ctx, GSR_EINVAL, "batch must be 128 or 256");
-  if (!(s->extent_k > 0.f) || !(s->lowpass >= 0.f) || !(s->alpha_min >= 0.f) || !(s->alpha_max > 0.f) ||
-      !(s->alpha_max < 1.f) || !(s->T_min >= 0.f) || !(s->T_min < 1.f) || !(s->guard >= 0.f))
-    return fail(ctx, GSR_EINVAL, "rule value out of range");
-  if (s->flags & ~(GSR_EXACT_TILES | GSR_NORMALIZED_DEPTH)) return fail(ctx, GSR_EINVAL, "unknown settings flag");
-  return GSR_OK;
-}
+// Host-side argument checks (gsr_validate.cpp), reported through the context.
+gsr_status checked(gsr_ctx* ctx, gsr_status st, const std::string& err) { return st == GSR_OK ? st : fail(ctx, st, err); }
 
-gsr_status check_gaussians(gsr_ctx* ctx, const gsr_gaussians* g, int V) {
-  if (!g) return fail(ctx, GSR_EINVAL, "gaussians is NULL");
-  if (g->n < 0) return fail(ctx, GSR_EINVAL, "gaussians.n < 0");
-  if (g->sh_degree < 0 || g->sh_degree > 3) return fail(ctx, GSR_EINVAL, "sh_degree must be 0..3");
-  if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->opacities || !g->sh))
-    return fail(ctx, GSR_EINVAL, "a Gaussian parameter pointer is NULL");
-  if (g->n > 0 && (reinterpret_cast<uintptr_t>(g->quats) & 15u))
-    return fail(ctx, GSR_EINVAL, "quats must be 16-byte aligned");
-  if (int64_t(V) * g->n >= (int64_t(1) << 32)) return fail(ctx, GSR_EINVAL, "views * Gaussians must be < 2^32");
-  return GSR_OK;
+gsr_status check_settings(gsr_ctx* ctx, const gsr_settings* s) {
+  std::string err;
+  return checked(ctx, check::settings(s, err), err);
 }
 
 gsr_status check_camera(gsr_ctx* ctx, const gsr_camera& c, int v) {
-  const std::string at = " (view " + std::to_string(v) + ")";
-  if (c.width < 1 || c.height < 1 || c.width > 8192 || c.height > 8192)
-    return fail(ctx, GSR_EINVAL, "camera size must be 1..8192" + at);
-  if (!(c.fx > 0.f) || !(c.fy > 0.f) || !std::isfinite(c.cx) || !std::isfinite(c.cy))
-    return fail(ctx, GSR_EINVAL, "camera intrinsics invalid" + at);
-  if (!(c.znear > 0.f)) return fail(ctx, GSR_EINVAL, "camera znear must be > 0" + at);
-  return GSR_OK;
+  std::string err;
+  return checked(ctx, check::camera(c, v, err), err);
 }
 
 gsr_status check_forward_args(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* cams, int32_t V,
                               const gsr_settings* s, const gsr_view_out* outs) {
-  if (V < 1 || V > GSR_MAX_VIEWS) return fail(ctx, GSR_EINVAL, "V must be 1..16");
-  if (!cams || !outs) return fail(ctx, GSR_EINVAL, "cams/outs is NULL");
-  gsr_status st;
-  if ((st = check_settings(ctx, s)) != GSR_OK) return st;
-  if ((st = check_gaussians(ctx, g, V)) != GSR_OK) return st;
-  for (int v = 0; v < V; ++v) {
-    if ((st = check_camera(ctx, cams[v], v)) != GSR_OK) return st;
-    if (!outs[v].color) return fail(ctx, GSR_EINVAL, "outs[v].color is NULL");
-  }
-  return GSR_OK;
+  std::string err;
+  return checked(ctx, check::forward_args(g, cams, V, s, outs, err), err);
 }
 
 int bits_for(uint64_t maxval) {
@@ -459,18 +432,9 @@ hipError_t enqueue_backward(gsr_saved* sv, const ViewTable& vt, float* grad2d, c
 // Checks an optimiser description and fills the kernels' view of it for the parameter
 // arrays p.
 gsr_status adam_dev(gsr_ctx* ctx, const gsr_adam* o, float* const p[G_COUNT], AdamDev* a) {
-  if (!o) return fail(ctx, GSR_EINVAL, "optimiser is NULL");
-  const gsr_gaussian_grads* mv[2] = {&o->m, &o->v};
-  for (const gsr_gaussian_grads* x : mv)
-    if (!x->means || !x->scales || !x->quats || !x->opacities || !x->sh)
-      return fail(ctx, GSR_EINVAL, "every optimiser moment array is required");
-  if (!o->state) return fail(ctx, GSR_EINVAL, "optimiser state is NULL");
+  std::string err;
+  if (check::adam(o, err) != GSR_OK) return fail(ctx, GSR_EINVAL, err);
   const float lr[G_COUNT + 1] = {o->lr_means, o->lr_scales, o->lr_quats, o->lr_opacities, o->lr_sh_dc, o->lr_sh_rest};
-  for (float r : lr)
-    if (!(r >= 0.f) || !std::isfinite(r)) return fail(ctx, GSR_EINVAL, "learning rates must be finite and >= 0");
-  if (!(o->beta1 >= 0.f && o->beta1 < 1.f) || !(o->beta2 >= 0.f && o->beta2 < 1.f))
-    return fail(ctx, GSR_EINVAL, "betas must be in [0, 1)");
-  if (!(o->eps >= 0.f) || !std::isfinite(o->eps)) return fail(ctx, GSR_EINVAL, "eps must be finite and >= 0");
   *a = AdamDev{};
   for (int i = 0; i < G_COUNT; ++i) a->p[i] = p[i];
   float* const m[G_COUNT] = {o->m.means, o->m.scales, o->m.quats, o->m.opacities, o->m.sh};
@@ -516,6 +480,22 @@ gsr_status forward_eager(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera*
   gsr_status st = make_saved(ctx, g, cams, V, s, outs, &sv);
   if (st != GSR_OK) return st;
   hipStream_t strm = ctx->stream;
+  if (s->flags & GSR_CHECK_FINITE) {
+    // the control words are free until the projection clears them
+    hipError_t e = launch_first_nonfinite(sv->g, sv->deg, sv->ctrl, strm);
+    uint32_t* h = reinterpret_cast<uint32_t*>(ctx->h_total);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, sv->ctrl, sizeof(uint32_t), hipMemcpyDeviceToHost, strm);
+    if (e == hipSuccess) e = hipStreamSynchronize(strm);
+    const uint32_t first = h[0];
+    if (e != hipSuccess) {
+      release(sv);
+      return fail(ctx, GSR_EDEVICE, std::string("finiteness check failed: ") + hipGetErrorString(e));
+    }
+    if (first != 0xFFFFFFFFu) {
+      release(sv);
+      return fail(ctx, GSR_EINVAL, "Gaussian " + std::to_string(first) + " has a NaN or infinite parameter");
+    }
+  }
   hipError_t e = enqueue_project(sv, strm, true);
   int64_t M = 0, NV = 0;
   if (e == hipSuccess && g->n > 0) {
@@ -1211,17 +1191,8 @@ gsr_status gsr_seed(gsr_ctx* ctx, const gsr_camera* cam, const float* rgb, const
   if (!cam || !rgb || !depth || !s || !out || !count) return fail(ctx, GSR_EINVAL, "NULL argument to gsr_seed");
   gsr_status st = check_camera(ctx, *cam, 0);
   if (st != GSR_OK) return st;
-  if (s->measure != GSR_SEED_CONTRAST && s->measure != GSR_SEED_DEPTH_VARIANCE)
-    return fail(ctx, GSR_EINVAL, "unknown seeding measure");
-  const int ms = s->min_side;
-  if (ms != 1 && ms != 2 && ms != 4 && ms != 8 && ms != 16 && ms != 32 && ms != 64)
-    return fail(ctx, GSR_EINVAL, "min_side must be a power of two in 1..64");
-  if (!(s->threshold >= 0.f) || !(s->opacity >= 0.f && s->opacity <= 1.f))
-    return fail(ctx, GSR_EINVAL, "threshold or opacity out of range");
-  if (s->sh_degree < 0 || s->sh_degree > 3) return fail(ctx, GSR_EINVAL, "sh_degree must be 0..3");
-  if (capacity < 0) return fail(ctx, GSR_EINVAL, "capacity < 0");
-  if (capacity > 0 && (!out->means || !out->scales || !out->quats || !out->opacities || !out->sh))
-    return fail(ctx, GSR_EINVAL, "an output pointer is NULL");
+  std::string err;
+  if ((st = check::seed_settings(s, capacity, out, err)) != GSR_OK) return fail(ctx, st, err);
   *count = 0;
   SeedImage im{rgb, depth, cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy, {}, {}};
   std::memcpy(im.R, cam->R, sizeof im.R);
@@ -1275,16 +1246,11 @@ gsr_status gsr_tsdf_create(gsr_ctx* ctx, const gsr_tsdf_settings* s, int64_t max
   if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
   if (!s || !out) return fail(ctx, GSR_EINVAL, "NULL argument to gsr_tsdf_create");
   *out = nullptr;
-  if (!(s->voxel > 0.f) || !(s->trunc > 0.f) || !(s->step > 0.f) || !(s->w_max >= 1.f) || !std::isfinite(s->voxel) ||
-      !std::isfinite(s->trunc) || !std::isfinite(s->step) || !std::isfinite(s->w_max))
-    return fail(ctx, GSR_EINVAL, "voxel, trunc and step must be > 0 and w_max >= 1");
-  if (s->weighting != GSR_TSDF_EQ9 && s->weighting != GSR_TSDF_UNIT_WEIGHT)
-    return fail(ctx, GSR_EINVAL, "unknown weighting");
+  std::string err;
+  int64_t slots = 0;
+  if (check::tsdf_settings(s, max_blocks, &slots, err) != GSR_OK) return fail(ctx, GSR_EINVAL, err);
   const int n_samples = tsdf_band_samples(s->trunc, s->step);
   if (n_samples > 4096) return fail(ctx, GSR_EINVAL, "more than 4096 band samples per pixel");
-  if (max_blocks < 1 || max_blocks > (int64_t(1) << 28)) return fail(ctx, GSR_EINVAL, "max_blocks must be in 1..2^28");
-  int64_t slots = 1024;
-  while (slots < 2 * max_blocks) slots *= 2;
   gsr_tsdf* m = new gsr_tsdf;
   m->ctx = ctx;
   m->s = *s;

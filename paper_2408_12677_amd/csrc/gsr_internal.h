@@ -340,5 +340,7 @@ hipError_t launch_adam_tick(uint32_t* state, float b1, float b2, const uint32_t*
 // One Adam step over all groups of n Gaussians of SH degree deg, gradients grads[group].
 hipError_t launch_adam(const AdamDev& a, const float* const grads[G_COUNT], int64_t n, int deg, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
+// first[0] = the smallest index of a Gaussian with a NaN or infinite parameter, else UINT32_MAX.
+hipError_t launch_first_nonfinite(const GaussDev& g, int sh_degree, uint32_t* first, hipStream_t s);
 
 }  // namespace gsr

@@ -1177,6 +1177,23 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t value, i
   if (i < count) p[i] = value;
 }
 
+// The smallest Gaussian index with a NaN or infinite parameter (first[0] starts at
+// UINT32_MAX; it stays there when every value is finite).  Grid-stride over the five
+// arrays taken as one run of n * (14 + 3 (K - 1)) values.
+__global__ __launch_bounds__(256) void k_first_nonfinite(GaussDev g, int K, uint32_t* first) {
+  const int64_t n = g.n;
+  const int64_t sizes[5] = {3 * n, 3 * n, 4 * n, n, int64_t(3) * K * n};
+  const int per[5] = {3, 3, 4, 1, 3 * K};
+  const float* arrs[5] = {g.means, g.scales, g.quats, g.opac, g.sh};
+  const int64_t total = sizes[0] + sizes[1] + sizes[2] + sizes[3] + sizes[4];
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < total; i += int64_t(gridDim.x) * 256) {
+    int64_t j = i;
+    int a = 0;
+    while (j >= sizes[a]) j -= sizes[a++];
+    if (!isfinite(arrs[a][j])) atomicMin(first, uint32_t(j / per[a]));
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // Tile work queue.  Tiles are ordered by decreasing expected work (a counting sort on
 // buckets of eight steps per octave, in one block: the order inside a bucket is
@@ -2281,6 +2298,16 @@ hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const 
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {
   if (count > 0) k_fill_u32<<<blocks_for(count, 256), 256, 0, s>>>(p, value, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_first_nonfinite(const GaussDev& g, int sh_degree, uint32_t* first, hipStream_t s) {
+  k_fill_u32<<<1, 256, 0, s>>>(first, 0xFFFFFFFFu, 1);
+  const int K = (sh_degree + 1) * (sh_degree + 1);
+  if (g.n > 0) {
+    const int64_t total = g.n * (14 + 3 * int64_t(K - 1));
+    k_first_nonfinite<<<int(std::min<int64_t>(blocks_for(total, 256), 4096)), 256, 0, s>>>(g, K, first);
+  }
   return hipGetLastError();
 }
 

@@ -37,11 +37,13 @@ class Settings:
     bg: tuple = (0.0, 0.0, 0.0)
     exact_tiles: bool = False   # GSR_EXACT_TILES: per tile row, only the columns the ellipse reaches
     normalized_depth: bool = False   # GSR_NORMALIZED_DEPTH: depth output D / (1 - T_final)
+    check_finite: bool = False   # GSR_CHECK_FINITE: eager forwards reject NaN/Inf parameters
 
     def c(self) -> N.Settings:
         return N.Settings(self.tile, self.batch, self.extent_k, self.lowpass, self.alpha_min, self.alpha_max,
                           self.T_min, self.guard, (ctypes.c_float * 3)(*self.bg),
-                          (N.EXACT_TILES if self.exact_tiles else 0) | (N.NORMALIZED_DEPTH if self.normalized_depth else 0))
+                          (N.EXACT_TILES if self.exact_tiles else 0) | (N.NORMALIZED_DEPTH if self.normalized_depth else 0)
+                          | (N.CHECK_FINITE if self.check_finite else 0))
 
 
 @dataclass

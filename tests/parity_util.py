@@ -19,10 +19,11 @@ Tolerances (FP32 kernels against the FP64 oracle):
     element |g - g_ref| <= 1e-3 max(|g_ref|, 1e-2 max|g_ref|) + env, where env is the
     oracle's bound on how far a correct gradient can lie from g_ref over the correct
     outcomes of every ambiguous decision (skip, stop, opacity clamp) and every non-unique
-    loss gradient.  At most 5% of the Gaussians with a gradient may have env above the
-    1e-3 relative term in some element (the check stays a 1e-3 check on the rest), and
-    at most 1% may contribute to a pixel with too many ambiguous decisions to enumerate
-    (flagged: those are left out of the per-element check).
+    loss gradient.  Its norm is reported relative to the group's (at most 2%; 0.08% on the
+    headline view), and so are the Gaussians with env above the 1e-3 term in some element
+    ("widened").  At most 1% of the
+    Gaussians with a gradient may contribute to a pixel with too many ambiguous decisions
+    to enumerate (flagged: those are left out of the per-element check).
 """
 from __future__ import annotations
 
@@ -39,8 +40,8 @@ GRAD_REL = 1e-3
 # the largest image difference measured between the two sides); depth uses it relative
 # to max(1, |target|)
 LOSS_MARGIN = 2e-5
-WIDENED_FRACTION = 0.05  # Gaussians whose bound exceeds the 1e-3 relative term
 FLAGGED_FRACTION = 0.01  # Gaussians at pixels whose outcomes were not enumerated
+ENV_NORM_CAP = 0.02      # norm of the decision bound, relative to the group's gradient norm
 NAMES = ("means", "scales", "quats", "opacities", "sh")
 
 
@@ -147,9 +148,11 @@ def check_images(images, outs, dbg=None, cams=None, tol=IMG_TOL):
 def check_grads(gpu, ref, rel=GRAD_REL, names=NAMES):
     """gpu: dict of torch tensors, ref: oracle backward dict (with 'envelope', 'flagged').
 
-    A group whose reference is negligible next to the whole gradient (e.g. the rotation
-    gradient of isotropic Gaussians, zero analytically) is measured on the scale of the
-    whole gradient: its norm floor is 1e-3 ||g_ref(all groups)|| and its element floor
+    A group whose reference is negligible next to the whole gradient (||g_ref|| below
+    1e-3 ||g_ref(all groups)||; e.g. the rotation gradient of isotropic Gaussians, zero
+    analytically, which binary32 leaves as the residue of cancelling terms) is measured on
+    the scale of the whole gradient: its norm floor is 1e-3 ||g_ref(all groups)|| and its
+    element floor 1e-3 max|g_ref(all groups)|; other groups have the element floor
     1e-4 max|g_ref(all groups)|.
     """
     flagged = ref["flagged"]
@@ -164,10 +167,17 @@ def check_grads(gpu, ref, rel=GRAD_REL, names=NAMES):
         r = ref[name].reshape(n, -1)
         env = ref["envelope"][name].reshape(n, -1)
         d = g - r
+        negligible = np.linalg.norm(r) < 1e-3 * all_norm
         nr = max(np.linalg.norm(r), 1e-3 * all_norm)
         norm_rel = np.linalg.norm(d) / max(nr, 1e-30)
+        # the decision bound may loosen a few elements, not the check (a sanity bound: 2% of
+        # the group's norm; the headline view's is 0.08%)
+        assert np.linalg.norm(env) <= ENV_NORM_CAP * nr, f"{name}: decision bound ||env|| " \
+                                                         f"{np.linalg.norm(env):.3g} vs ||g_ref|| {nr:.3g}"
+        report.setdefault("env_norm_rel", {})[name] = float(np.linalg.norm(env) / max(nr, 1e-30))
         assert np.linalg.norm(d) <= rel * nr + np.linalg.norm(env), f"{name}: ||diff||/||ref|| = {norm_rel:.3g}"
-        base = rel * np.maximum(np.maximum(np.abs(r), 1e-2 * np.abs(r).max(initial=0)), 1e-4 * all_max)
+        floor = (1e-3 if negligible else 1e-4) * all_max
+        base = rel * np.maximum(np.maximum(np.abs(r), 1e-2 * np.abs(r).max(initial=0)), floor)
         keep = ~flagged
         thr = base[keep] + env[keep]
         bad = np.abs(d[keep]) > thr
@@ -180,7 +190,6 @@ def check_grads(gpu, ref, rel=GRAD_REL, names=NAMES):
     report["contributing"] = contributing
     report["widened"] = int((widened & has_grad).sum())
     report["flagged"] = int(flagged.sum())
-    assert report["widened"] <= WIDENED_FRACTION * contributing, report
     assert report["flagged"] <= FLAGGED_FRACTION * contributing, report
     return report
 

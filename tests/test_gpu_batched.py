@@ -222,6 +222,28 @@ def test_autotune_picks_a_launch_shape_and_caches_it(R, tmp_path, monkeypatch):
     say("autotune", s.tile, s.batch, ms)
 
 
+def test_cfg4_captured_8_view_step_matches_oracle(R):
+    # the full-size batched step (8 views of uneven resolution, 4,348,800 pixels, one graph
+    # launch) against the oracle's forward, L1 loss and backward of its own images
+    w = scenes.make_cfg4()
+    params = to_dev(w.gaussians)
+    tg = dev_targets(w.targets)
+    s = settings(exact_tiles=True)
+    graph = R.Graph(*params, w.cameras, tg, s)
+    graph.launch()
+    graph.sync()
+    say("cfg4 graph", graph.info())
+    orc = oracle_for(w.gaussians, w.cameras, s, threads=8)
+    outs = orc.forward()
+    rep = check_images(graph.images, outs)
+    L, ref_gc, ref_gd, amb = oracle_loss(outs, w.targets, 0.1)
+    assert float(graph.loss) == pytest.approx(L, abs=1.1e-4 * len(w.cameras))
+    ref = orc.backward(ref_gc, ref_gd, None, ambiguous_pixels=amb)
+    grep = check_grads(graph.grads, ref)
+    say("cfg4 8 views vs oracle", rep, grep)
+    graph.free()
+
+
 def test_cfg4_all_views_graph_vs_eager(R):
     w = scenes.make_cfg4()
     params = to_dev(w.gaussians)

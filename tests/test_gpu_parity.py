@@ -107,7 +107,7 @@ def test_forward_bitwise_invariant_across_autotune_points(R):
     say("autotune invariance")
     ref = None
     for tile in (8, 16, 32):
-        for batch, exact in ((128, False), (256, False), (256, True)):
+        for batch, exact in ((128, False), (256, False), (128, True), (256, True)):
             _, images, _ = run_fwd(R, w.gaussians, cams, settings(tile=tile, batch=batch, exact_tiles=exact),
                                    save=False)
             cur = [t.cpu().numpy() for img in images for t in img]
@@ -174,6 +174,30 @@ def test_multiview_other_launch_shapes(R, tile, batch):
     c = w.cameras[0]
     cams = [c, c.crop(20, 10, 50, 40)]
     fwd_bwd_parity(R, w.gaussians, cams, settings(tile=tile, batch=batch))
+
+
+LAUNCH_SHAPES = [(t, b, e) for t in (8, 16, 32) for b in (128, 256) for e in (False, True)]
+
+
+@pytest.mark.parametrize("tile,batch,exact", LAUNCH_SHAPES)
+def test_every_launch_shape_multiview(R, tile, batch, exact):
+    # every (tile, batch, list kind) the autotuner can pick: each compositing kernel variant
+    w = scenes.make_cfg1()
+    c = w.cameras[0]
+    R1, t1 = scenes.look_at([0.2, 0.1, -0.3], [0.0, 0.0, 3.0], up=(0, -1, 0))
+    cams = [c, scenes.Camera(100, 75, 90.0, 90.0, 50.3, 37.6, R1, t1), c.crop(13, 7, 37, 29)]
+    say("launch shape", tile, batch, exact)
+    rep, grep = fwd_bwd_parity(R, w.gaussians, cams, settings(tile=tile, batch=batch, exact_tiles=exact))
+    say(rep, grep)
+
+
+@pytest.mark.parametrize("tile,batch,exact", LAUNCH_SHAPES)
+def test_every_launch_shape_cfg2_with_loss(R, tile, batch, exact):
+    w = scenes.make_cfg2()
+    say("cfg2 launch shape", tile, batch, exact)
+    rep, grep = fwd_bwd_parity(R, w.gaussians, w.cameras, settings(tile=tile, batch=batch, exact_tiles=exact),
+                               targets=w.targets)
+    say(rep, grep)
 
 
 def test_cfg2_fwd_bwd_with_l1_loss(R):
@@ -304,6 +328,29 @@ def test_invalid_arguments_raise(R):
         R.forward(*params, [bad])
 
 
+def test_check_finite_names_the_first_bad_gaussian(R):
+    w = scenes.make_cfg1()
+    base = to_dev(w.gaussians)
+    s = settings(check_finite=True)
+    _, saved = R.forward(*base, w.cameras, s)     # all finite: renders as usual
+    saved.free()
+    from paper_2408_12677_amd._native import GsrError
+    for group, idx, val in ((0, (1234, 2), float("nan")), (4, (17, 0, 1), float("inf")), (3, (1999,), float("-inf"))):
+        params = [p.clone() for p in base]
+        params[group][idx] = val
+        params[4][1500, 0, 0] = float("nan")   # a later bad Gaussian
+        with pytest.raises(GsrError, match=f"Gaussian {min(idx[0], 1500)} has a NaN"):
+            R.forward(*params, w.cameras, s)
+        # without the check the values propagate and the call succeeds
+        _, saved = R.forward(*params, w.cameras, settings())
+        saved.free()
+    # the context stays usable
+    images, saved = R.forward(*base, w.cameras, s)
+    torch.cuda.synchronize()
+    assert all(torch.isfinite(t).all() for t in images[0])
+    saved.free()
+
+
 # ---------------------------------------------------------------------------------------
 # full size: the headline 640x480 view of the 500k-Gaussian map, in the bench launch shape
 # ---------------------------------------------------------------------------------------
@@ -315,6 +362,45 @@ def test_headline_view_full_size(R):
     say("headline", w.gaussians.n, cam.width, cam.height)
     rep, grep = fwd_bwd_parity(R, w.gaussians, [cam], settings(), targets=[w.targets[v]], threads=8)
     say("headline", rep, grep)
+
+
+def test_cfg5_full_view_checked_on_a_window(R):
+    # one 1752x1168 view of the 3M-Gaussian map rendered whole; keys bit-exact over the whole
+    # view, images and gradients against the oracle on a 256x192 window (output gradients
+    # vanish outside it, so the GPU's full backward is the window's)
+    w = scenes.make_cfg5()
+    cam = w.cameras[0]
+    s = settings(exact_tiles=True)
+    say("cfg5 view", w.gaussians.n, cam.width, cam.height)
+    params, images, saved = run_fwd(R, w.gaussians, [cam], s)
+    dbg = saved.debug_export()
+    rng = np.random.default_rng(55)
+    x0, y0 = int(rng.integers(0, cam.width - 256)), int(rng.integers(0, cam.height - 192))
+    win = (x0, y0, x0 + 256, y0 + 192)
+    os_ = oracle.Settings(tile=s.tile, mu_fp32=True, threads=8, exact_tiles=True, window=win)
+    orc = oracle.Oracle(w.gaussians.arrays(), w.gaussians.sh_degree, [cam], os_)
+    check_keys(dbg, orc)
+    o = orc.forward()[0]
+    sl = (slice(y0, y0 + 192), slice(x0, x0 + 256))
+    cut = lambda a: {k: (v[(slice(None),) + sl] if k in ("color", "lo", "hi") else v[sl])
+                     for k, v in a.items() if isinstance(v, np.ndarray)}
+    oc = cut(o)
+    col, dep, alp = images[0]
+    crop_imgs = [(col[:, sl[0], sl[1]], dep[sl], alp[sl])]
+    rep = check_images(crop_imgs, [oc])
+    H, W = cam.height, cam.width
+    lengths = np.diff(dbg["ranges"].astype(np.int64), axis=1)[:, 0]
+    say("cfg5 window", win, rep, "list length p50/p99", np.percentile(lengths, 50), np.percentile(lengths, 99))
+    gC = np.zeros((3, H, W), np.float32)
+    gD = np.zeros((H, W), np.float32)
+    gC[(slice(None),) + sl] = rng.standard_normal((3, 192, 256))
+    gD[sl] = rng.standard_normal((192, 256))
+    grads = R.backward(saved, [torch.from_numpy(gC).cuda()], [torch.from_numpy(gD).cuda()])
+    torch.cuda.synchronize()
+    ref = orc.backward([gC], [gD], None)
+    grep = check_grads(grads, ref)
+    say("cfg5 window grads", grep)
+    saved.free()
 
 
 # ---------------------------------------------------------------------------------------
