@@ -243,6 +243,22 @@ gsr_status gsr_loss_l1(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_out*
 gsr_status gsr_backward(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_grad* grads,
                         const gsr_gaussian_grads* out, uint32_t flags);
 
+/* ---- Allocation-free backward ------------------------------------------------------------
+ * For callers that cannot allocate device memory while a step runs: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, result and
+ * kernels as gsr_backward, but the per-record gradient rows that gsr_backward takes from the
+ * stream-ordered pool live in one fixed device array of GSR_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends; the call allocates and frees
+ * nothing.  It needs (V*N*12 + N*3)*4 bytes of that array (V views and N Gaussians of the
+ * saved forward: 30 MB for one view of 500k Gaussians; one view of at most 1,118,481);
+ * a larger saved state gives GSR_EINVAL before any device work.  The array is cleared by a
+ * kernel on every call (never by a memset).  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (two streams, two contexts or two threads) race, so the caller
+ * serialises them. */
+#define GSR_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+gsr_status gsr_backward_noalloc(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_grad* grads,
+                                const gsr_gaussian_grads* out, uint32_t flags);
+
 gsr_status gsr_saved_info(const gsr_saved* saved, gsr_info* info);
 gsr_status gsr_saved_free(gsr_saved* saved);
 

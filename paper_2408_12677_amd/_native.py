@@ -14,6 +14,7 @@ MAX_KERNELS = 32
 OK, EINVAL, ENOMEM, EDEVICE, ECAPACITY, EINTERNAL = range(6)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ECAPACITY", 5: "EINTERNAL"}
 ACCUMULATE = 1
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024  # GSR_NOALLOC_SCRATCH_BYTES
 EXACT_TILES = 1
 NORMALIZED_DEPTH = 2
 CHECK_FINITE = 4
@@ -117,6 +118,7 @@ SIGNATURES = {
     "gsr_forward": (ctypes.c_int, [P, P, P, ctypes.c_int32, P, P, P]),
     "gsr_loss_l1": (ctypes.c_int, [P, P, P, P, ctypes.c_float, P, P, P]),
     "gsr_backward": (ctypes.c_int, [P, P, P, P, ctypes.c_uint32]),
+    "gsr_backward_noalloc": (ctypes.c_int, [P, P, P, P, ctypes.c_uint32]),
     "gsr_saved_info": (ctypes.c_int, [P, P]),
     "gsr_saved_free": (ctypes.c_int, [P]),
     "gsr_debug_export": (ctypes.c_int, [P, P, P]),

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -26,6 +27,7 @@ struct gsr_ctx {
   Timer timer;
   void* bwd_scratch = nullptr;  // the eager backward's 2D-gradient rows, kept between calls (grow-only)
   size_t bwd_scratch_bytes = 0;
+  void* noalloc_scratch = nullptr;  // this device's address of the fixed array `scratch`
   // Per tile grid (tile size and view sizes), the last eager forward's longest
   // contributor count of every tile: the next forward over the same tiles orders its tile
   // queue by it.  Scheduling only; results do not depend on it.
@@ -97,6 +99,13 @@ struct gsr_tsdf {
   uint32_t frame = 0;
   std::vector<void*> blocks;
 };
+
+// The fixed device array of gsr_backward_noalloc: the per-record 2D-gradient rows and the
+// colour term's mean gradient of one backward.  Every GPU the library runs on holds its own
+// copy until the process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host it names a stand-in, not device memory): it uses the device address that
+// noalloc_scratch_address() looks up once per device.
+static __device__ __align__(256) float scratch[GSR_NOALLOC_SCRATCH_BYTES / sizeof(float)];
 
 namespace {
 
@@ -452,6 +461,27 @@ gsr_status adam_dev(gsr_ctx* ctx, const gsr_adam* o, float* const p[G_COUNT], Ad
   return GSR_OK;
 }
 
+// Device address of `scratch` on `device` (which must be current), looked up once per
+// device and kept for the life of the process.
+std::mutex g_noalloc_mu;
+std::vector<void*> g_noalloc_ptr;
+
+gsr_status noalloc_scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr.size() <= size_t(device)) g_noalloc_ptr.resize(size_t(device) + 1, nullptr);
+  if (!g_noalloc_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(nullptr, GSR_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    }
+    g_noalloc_ptr[device] = p;
+  }
+  *out = g_noalloc_ptr[device];
+  return GSR_OK;
+}
+
 // The eager backward's 2D-gradient rows live in a context buffer that only grows:
 // repeated steps reuse the same memory instead of a fresh allocation per call.
 gsr_status bwd_scratch(gsr_ctx* ctx, size_t need) {
@@ -594,8 +624,12 @@ gsr_status gsr_ctx_create(int32_t device, void* hip_stream, gsr_ctx** out) {
   }
   if (device < 0 || device >= ndev) return fail(nullptr, GSR_EINVAL, "device index out of range");
   if (hipSetDevice(device) != hipSuccess) return fail(nullptr, GSR_EDEVICE, "hipSetDevice failed");
+  void* fixed = nullptr;
+  gsr_status st = noalloc_scratch_address(device, &fixed);
+  if (st != GSR_OK) return st;
   gsr_ctx* c = new gsr_ctx;
   c->device = device;
+  c->noalloc_scratch = fixed;
   c->stream = static_cast<hipStream_t>(hip_stream);
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_total), 2 * sizeof(unsigned long long), hipHostMallocDefault) !=
       hipSuccess) {
@@ -696,6 +730,28 @@ gsr_status gsr_backward(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_gra
   if (st != GSR_OK) return st;
   GradOut go{out->means, out->scales, out->quats, out->opacities, out->sh, int(flags & GSR_ACCUMULATE)};
   hipError_t e = enqueue_backward(sv, vt, static_cast<float*>(ctx->bwd_scratch), go, ctx->stream, true);
+  if (e != hipSuccess) return fail(ctx, GSR_EDEVICE, std::string("backward launch failed: ") + hipGetErrorString(e));
+  return GSR_OK;
+}
+
+gsr_status gsr_backward_noalloc(gsr_ctx* ctx, const gsr_saved* saved, const gsr_view_grad* grads,
+                                const gsr_gaussian_grads* out, uint32_t flags) {
+  if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
+  if (!saved || !grads || !out) return fail(ctx, GSR_EINVAL, "NULL argument to gsr_backward_noalloc");
+  if (flags & ~GSR_ACCUMULATE) return fail(ctx, GSR_EINVAL, "unknown flag");
+  gsr_saved* sv = const_cast<gsr_saved*>(saved);
+  if (sv->ctx->device != ctx->device) return fail(ctx, GSR_EINVAL, "saved state belongs to another device");
+  const int64_t VN = int64_t(sv->V) * sv->N;
+  const size_t need = (size_t(VN) * kGrad2D + size_t(sv->N) * 3) * sizeof(float);
+  if (need > size_t(GSR_NOALLOC_SCRATCH_BYTES))
+    return fail(ctx, GSR_EINVAL, "gsr_backward_noalloc needs " + std::to_string(need) +
+                                     " bytes of scratch (views * Gaussians * 48 + Gaussians * 12); the fixed array "
+                                     "holds " + std::to_string(size_t(GSR_NOALLOC_SCRATCH_BYTES)));
+  if (!ctx->noalloc_scratch) return fail(ctx, GSR_EDEVICE, "no fixed scratch address for this device");
+  const ViewTable vt = with_grads(sv, grads);
+  GradOut go{out->means, out->scales, out->quats, out->opacities, out->sh, int(flags & GSR_ACCUMULATE)};
+  // no event timer here: its events are created on demand
+  hipError_t e = enqueue_backward(sv, vt, static_cast<float*>(ctx->noalloc_scratch), go, ctx->stream, false);
   if (e != hipSuccess) return fail(ctx, GSR_EDEVICE, std::string("backward launch failed: ") + hipGetErrorString(e));
   return GSR_OK;
 }

@@ -270,8 +270,12 @@ def _view_grads(saved: Saved, g_color, g_depth, g_alpha, keep: list):
     return gv
 
 
-def backward(saved: Saved, g_color, g_depth=None, g_alpha=None, grads=None, accumulate: bool = False):
-    """dL/d(means, scales, quats, opacities, sh) for dL/d(outputs) given per view (None = 0)."""
+def backward(saved: Saved, g_color, g_depth=None, g_alpha=None, grads=None, accumulate: bool = False,
+             noalloc: bool = False):
+    """dL/d(means, scales, quats, opacities, sh) for dL/d(outputs) given per view (None = 0).
+
+    noalloc: run gsr_backward_noalloc (the library's fixed device scratch array instead of
+    pool memory; pass `grads` too for a call that allocates nothing)."""
     ctx = saved.ctx
     means, scales, quats, opacities, sh = saved.keep
     keep = []
@@ -285,7 +289,8 @@ def backward(saved: Saved, g_color, g_depth=None, g_alpha=None, grads=None, accu
             _need(grads[k], f"grads[{k!r}]", ref.shape, ref.device)
     go = N.GaussianGrads(*(None if grads.get(k) is None else grads[k].data_ptr()
                            for k in ("means", "scales", "quats", "opacities", "sh")))
-    N.check(ctx.lib.gsr_backward(ctx.h, saved.h, gv, ctypes.byref(go), N.ACCUMULATE if accumulate else 0), ctx.h)
+    fn = ctx.lib.gsr_backward_noalloc if noalloc else ctx.lib.gsr_backward
+    N.check(fn(ctx.h, saved.h, gv, ctypes.byref(go), N.ACCUMULATE if accumulate else 0), ctx.h)
     return grads
 
 
