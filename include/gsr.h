@@ -102,7 +102,16 @@ typedef struct {
   float guard;       /* >= 0 */
   float bg[3];
   uint32_t flags;    /* GSR_EXACT_TILES | GSR_NORMALIZED_DEPTH | GSR_CHECK_FINITE, or 0 */
+  float jclamp;      /* >= 0; > 0: guard-band clamp inside the projection's Jacobian (below) */
 } gsr_settings;
+
+/* settings.jclamp: with jclamp > 0 the Jacobian J of the perspective projection (Eq. 5) is
+ * evaluated with x/z and y/z clamped to +-jclamp W / (2 fx) and +-jclamp H / (2 fy) (jclamp
+ * times the half field of view; 1.3 is the usual choice): a Gaussian far off the optical
+ * axis then gets the projected covariance it would have at the limit, instead of one
+ * stretched by J's growth with x/z.  The splat centre is not clamped.  The limits are
+ * binary32 jclamp ((W / 2) / fx); the clamp decision is taken on tx / tz in binary32 inside
+ * the fixed discrete-stage sequence.  0 (default) is Eq. 5 as printed. */
 
 /* settings.flags: tile lists hold, per tile row of a splat's rectangle, only the columns
  * that its ellipse d^T Q d <= extent_k^2 reaches inside the row's pixel band (the rest of
@@ -192,10 +201,27 @@ int32_t gsr_abi_version(void);
 /* Fill *s with the default rules above.  EINVAL if s is NULL. */
 gsr_status gsr_settings_default(gsr_settings* s);
 
+/* A caller's device allocator.  Every device buffer the library allocates for itself
+ * (scratch, saved forward state, graph buffers, TSDF maps, seeding counts) is taken from
+ * alloc and returned through free:
+ *   alloc(user, bytes, hip_stream) returns `bytes` (> 0) of device memory on the context's
+ *     device, usable by work enqueued on hip_stream after the call (stream-ordered, like
+ *     hipMallocAsync), 256-byte aligned, or NULL when it cannot (the call that needed it
+ *     then fails with GSR_ENOMEM and the context stays usable);
+ *   free(user, ptr, hip_stream) gives back a block once the work enqueued on hip_stream
+ *     before the call is done with it (like hipFreeAsync).
+ * Both are called from the thread that calls the library, never from device work. */
+typedef struct gsr_alloc {
+  void* (*alloc)(void* user, size_t bytes, void* hip_stream);
+  void (*free)(void* user, void* ptr, void* hip_stream);
+  void* user;
+} gsr_alloc;
+
 /* Create a context on HIP device `device` enqueuing on `hip_stream` (a hipStream_t;
- * NULL = the null stream).  Scratch memory comes from the device's stream-ordered
- * memory pool.  EDEVICE when the device cannot be used. */
-gsr_status gsr_ctx_create(int32_t device, void* hip_stream, gsr_ctx** out);
+ * NULL = the null stream).  alloc (copied; may be NULL): the caller's allocator for the
+ * library's device memory; NULL takes it from the device's stream-ordered memory pool.
+ * EDEVICE when the device cannot be used; EINVAL for an allocator without both functions. */
+gsr_status gsr_ctx_create(int32_t device, void* hip_stream, const gsr_alloc* alloc, gsr_ctx** out);
 gsr_status gsr_ctx_destroy(gsr_ctx* ctx);
 gsr_status gsr_ctx_set_stream(gsr_ctx* ctx, void* hip_stream);
 

@@ -26,6 +26,15 @@ class GsrError(RuntimeError):
         self.status = status
 
 
+# gsr_alloc: a caller's device allocator (see include/gsr.h)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Alloc(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", P)]
+
+
 class Gaussians(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("means", P), ("scales", P),
                 ("quats", P), ("opacities", P), ("sh", P)]
@@ -41,7 +50,7 @@ class Settings(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("batch", ctypes.c_int32), ("extent_k", ctypes.c_float),
                 ("lowpass", ctypes.c_float), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("T_min", ctypes.c_float), ("guard", ctypes.c_float), ("bg", ctypes.c_float * 3),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("jclamp", ctypes.c_float)]
 
 
 class ViewOut(ctypes.Structure):
@@ -109,7 +118,7 @@ SEED_CONTRAST, SEED_DEPTH_VARIANCE = 0, 1
 SIGNATURES = {
     "gsr_abi_version": (ctypes.c_int32, []),
     "gsr_settings_default": (ctypes.c_int, [P]),
-    "gsr_ctx_create": (ctypes.c_int, [ctypes.c_int32, P, P]),
+    "gsr_ctx_create": (ctypes.c_int, [ctypes.c_int32, P, P, P]),
     "gsr_ctx_destroy": (ctypes.c_int, [P]),
     "gsr_ctx_set_stream": (ctypes.c_int, [P, P]),
     "gsr_ctx_set_timing": (ctypes.c_int, [P, ctypes.c_int32]),

@@ -22,6 +22,7 @@ using namespace gsr;
 struct gsr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  gsr_alloc alloc{};  // the caller's allocator; alloc.alloc == nullptr: the stream-ordered pool
   std::string err;
   unsigned long long* h_total = nullptr;  // pinned read-back slots: pair count M, visible records
   Timer timer;
@@ -141,9 +142,17 @@ hipError_t timed(gsr_ctx* ctx, hipStream_t s, int k, F&& f) {
   return e;
 }
 
+// Device memory of the library: from the caller's allocator when the context has one,
+// else from the device's stream-ordered pool; released the same way, stream-ordered.
 gsr_status dev_alloc(gsr_ctx* ctx, hipStream_t s, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) return GSR_OK;
+  if (ctx->alloc.alloc) {
+    *p = ctx->alloc.alloc(ctx->alloc.user, bytes, s);
+    if (!*p) return fail(ctx, GSR_ENOMEM, "the caller's allocator returned no memory for " + std::to_string(bytes) +
+                                              " bytes");
+    return GSR_OK;
+  }
   hipError_t e = hipMallocAsync(p, bytes, s);
   if (e != hipSuccess) {
     *p = nullptr;
@@ -152,6 +161,14 @@ gsr_status dev_alloc(gsr_ctx* ctx, hipStream_t s, void** p, size_t bytes) {
                                      hipGetErrorString(e));
   }
   return GSR_OK;
+}
+
+void dev_free(gsr_ctx* ctx, void* p, hipStream_t s) {
+  if (!p) return;
+  if (ctx->alloc.free)
+    ctx->alloc.free(ctx->alloc.user, p, s);
+  else
+    (void)hipFreeAsync(p, s);
 }
 
 template <class T>
@@ -165,7 +182,7 @@ gsr_status alloc_in(gsr_saved* sv, std::vector<void*>& list, T** p, size_t count
 }
 
 void free_list(gsr_saved* sv, std::vector<void*>& list) {
-  for (void* p : list) (void)hipFreeAsync(p, sv->ctx->stream);
+  for (void* p : list) dev_free(sv->ctx, p, sv->ctx->stream);
   list.clear();
 }
 
@@ -211,7 +228,7 @@ gsr_status make_saved(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* ca
   sv->deg = g->sh_degree;
   sv->s = *s;
   sv->g = GaussDev{g->means, g->scales, g->quats, g->opacities, g->sh, g->n};
-  sv->ru = Rules{s->extent_k, s->lowpass, s->alpha_min, s->alpha_max, s->T_min, s->guard,
+  sv->ru = Rules{s->extent_k, s->lowpass, s->alpha_min, s->alpha_max, s->T_min, s->guard, s->jclamp,
                  {s->bg[0], s->bg[1], s->bg[2]}, (s->flags & GSR_NORMALIZED_DEPTH) ? 1 : 0};
   ViewTable& vt = sv->vt;
   std::memset(&vt, 0, sizeof(vt));
@@ -341,14 +358,17 @@ void keep_hint(gsr_ctx* ctx, const gsr_saved* sv, hipStream_t s) {
     slot->grid = g;
   }
   if (slot->count < T) {
-    if (slot->tiles) (void)hipFreeAsync(slot->tiles, s);
+    dev_free(ctx, slot->tiles, s);
     slot->tiles = nullptr;
     slot->count = 0;
-    if (hipMallocAsync(reinterpret_cast<void**>(&slot->tiles), size_t(T) * sizeof(uint32_t), s) != hipSuccess) {
-      (void)hipGetLastError();
+    void* p = nullptr;
+    const std::string err = ctx->err;
+    if (dev_alloc(ctx, s, &p, size_t(T) * sizeof(uint32_t)) != GSR_OK) {  // a hint is optional
+      ctx->err = err;
       slot->grid.clear();
       return;
     }
+    slot->tiles = static_cast<uint32_t*>(p);
   }
   slot->count = T;
   if (hipMemcpyAsync(slot->tiles, sv->ck.tile_nmax, size_t(T) * sizeof(uint32_t), hipMemcpyDeviceToDevice, s) !=
@@ -486,7 +506,7 @@ gsr_status noalloc_scratch_address(int device, void** out) {
 // repeated steps reuse the same memory instead of a fresh allocation per call.
 gsr_status bwd_scratch(gsr_ctx* ctx, size_t need) {
   if (need <= ctx->bwd_scratch_bytes) return GSR_OK;
-  if (ctx->bwd_scratch) (void)hipFreeAsync(ctx->bwd_scratch, ctx->stream);
+  dev_free(ctx, ctx->bwd_scratch, ctx->stream);
   ctx->bwd_scratch = nullptr;
   ctx->bwd_scratch_bytes = 0;
   gsr_status st = dev_alloc(ctx, ctx->stream, &ctx->bwd_scratch, need + need / 8);
@@ -608,14 +628,17 @@ gsr_status gsr_settings_default(gsr_settings* s) {
   s->guard = 0.15f;
   s->bg[0] = s->bg[1] = s->bg[2] = 0.f;
   s->flags = 0;
+  s->jclamp = 0.f;
   return GSR_OK;
 }
 
 const char* gsr_last_error(const gsr_ctx* ctx) { return ctx ? ctx->err.c_str() : g_noctx_err.c_str(); }
 
-gsr_status gsr_ctx_create(int32_t device, void* hip_stream, gsr_ctx** out) {
+gsr_status gsr_ctx_create(int32_t device, void* hip_stream, const gsr_alloc* alloc, gsr_ctx** out) {
   if (!out) return fail(nullptr, GSR_EINVAL, "out is NULL");
   *out = nullptr;
+  if (alloc && (!alloc->alloc || !alloc->free))
+    return fail(nullptr, GSR_EINVAL, "an allocator needs both its alloc and free functions");
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess || ndev == 0) {
@@ -631,6 +654,7 @@ gsr_status gsr_ctx_create(int32_t device, void* hip_stream, gsr_ctx** out) {
   c->device = device;
   c->noalloc_scratch = fixed;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  if (alloc) c->alloc = *alloc;
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_total), 2 * sizeof(unsigned long long), hipHostMallocDefault) !=
       hipSuccess) {
     delete c;
@@ -650,9 +674,9 @@ gsr_status gsr_ctx_create(int32_t device, void* hip_stream, gsr_ctx** out) {
 gsr_status gsr_ctx_destroy(gsr_ctx* ctx) {
   if (!ctx) return fail(nullptr, GSR_EINVAL, "ctx is NULL");
   (void)hipStreamSynchronize(ctx->stream);
-  if (ctx->bwd_scratch) (void)hipFree(ctx->bwd_scratch);
-  for (auto& h : ctx->hints)
-    if (h.tiles) (void)hipFree(h.tiles);
+  dev_free(ctx, ctx->bwd_scratch, ctx->stream);
+  for (auto& h : ctx->hints) dev_free(ctx, h.tiles, ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);
   ctx->timer.destroy();
   if (ctx->h_total) (void)hipHostFree(ctx->h_total);
   delete ctx;
@@ -861,13 +885,15 @@ gsr_status gsr_debug_export(gsr_ctx* ctx, const gsr_saved* sv, const gsr_debug* 
   GSR_HIP(ctx, cp(out->T_final, sv->T_final, size_t(sv->total_pix) * 4));
   GSR_HIP(ctx, cp(out->n_contrib, sv->n_contrib, size_t(sv->total_pix) * 4));
   if (out->n_used && sv->total_pix > 0) {  // counted on demand, off the forward's path
-    uint32_t* nu = nullptr;
-    GSR_HIP(ctx, hipMalloc(reinterpret_cast<void**>(&nu), size_t(sv->total_pix) * 4));
+    void* nuv = nullptr;
+    gsr_status st = dev_alloc(ctx, s, &nuv, size_t(sv->total_pix) * 4);
+    if (st != GSR_OK) return st;
+    uint32_t* nu = static_cast<uint32_t*>(nuv);
     hipError_t e = launch_count_used(sv->vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->n_contrib, sv->s.tile,
                                      sv->total_pix, nu, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = cp(out->n_used, nu, size_t(sv->total_pix) * 4);
-    (void)hipFree(nu);
+    dev_free(ctx, nu, s);
     GSR_HIP(ctx, e);
   }
   GSR_HIP(ctx, cp(out->tiles_touched, sv->rec.counts, size_t(VN) * 4));
@@ -1126,7 +1152,7 @@ gsr_status gsr_autotune(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* 
     return static_cast<float*>(p);
   };
   auto sfree = [&]() {
-    for (void* p : scratch) (void)hipFreeAsync(p, strm);
+    for (void* p : scratch) dev_free(ctx, p, strm);
     (void)hipStreamSynchronize(strm);
   };
   std::vector<gsr_view_out> outs(V);
@@ -1275,7 +1301,7 @@ gsr_status gsr_seed(gsr_ctx* ctx, const gsr_camera* cam, const float* rgb, const
     over = n > capacity;
     if (!over && n > 0) e = launch_seed_emit(im, rules, counts, so, strm);
   }
-  (void)hipFreeAsync(buf, strm);
+  dev_free(ctx, buf, strm);
   if (e != hipSuccess) return fail(ctx, GSR_EDEVICE, std::string("seeding failed: ") + hipGetErrorString(e));
   *count = n;
   if (over) return fail(ctx, GSR_ECAPACITY, "seeding needs " + std::to_string(n) + " Gaussians, capacity is " +
@@ -1293,7 +1319,7 @@ gsr_status gsr_tsdf_settings_default(gsr_tsdf_settings* s) {
 }
 
 static void tsdf_release(gsr_tsdf* m) {
-  for (void* p : m->blocks) (void)hipFreeAsync(p, m->ctx->stream);
+  for (void* p : m->blocks) dev_free(m->ctx, p, m->ctx->stream);
   (void)hipStreamSynchronize(m->ctx->stream);
   delete m;
 }

@@ -148,6 +148,7 @@ struct ViewTable {
 
 struct Rules {
   float k, lowpass, amin, amax, Tmin, guard;
+  float jclamp;  // > 0: x/z, y/z clamped inside J to +-jclamp half fields of view
   float bg[3];
   int32_t norm_depth;  // depth output D / (1 - T_final) (GSR_NORMALIZED_DEPTH)
 };

@@ -161,6 +161,8 @@ struct Proj {
   float T[6];  // J W
   float U[6];  // T M
   float a, b, c;  // projected covariance + low-pass
+  float txj, tyj;  // the offsets J uses: tx, ty, or +-limit * tz where clamped
+  bool clx, cly;   // clamped
   float mux, muy;
   int x0, x1, y0, y1;  // inclusive pixel rectangle
   bool vis;
@@ -168,7 +170,7 @@ struct Proj {
 
 __device__ __forceinline__ void discrete_stage(const float p[3], const float s[3], const float q[4],
                                                const ViewDev& cam, float k, float lowpass, float guard,
-                                               Proj& o) {
+                                               float jclamp, Proj& o) {
 #pragma clang fp contract(off)
   const float* W = cam.R;
   o.vis = false;
@@ -217,8 +219,32 @@ __device__ __forceinline__ void discrete_stage(const float p[3], const float s[3
   const float tz2 = tz * tz;
   const float j00 = cam.fx / tz;
   const float j11 = cam.fy / tz;
-  const float j02 = -(cam.fx * tx) / tz2;
-  const float j12 = -(cam.fy * ty) / tz2;
+  // guard-band clamp: an offset beyond jclamp half fields of view enters J as limit * tz
+  float txj = tx, tyj = ty;
+  o.clx = o.cly = false;
+  if (jclamp > 0.f) {
+    const float limx = jclamp * ((0.5f * float(cam.W)) / cam.fx);
+    const float limy = jclamp * ((0.5f * float(cam.H)) / cam.fy);
+    const float ux = tx / tz, uy = ty / tz;
+    if (ux < -limx) {
+      txj = -limx * tz;
+      o.clx = true;
+    } else if (ux > limx) {
+      txj = limx * tz;
+      o.clx = true;
+    }
+    if (uy < -limy) {
+      tyj = -limy * tz;
+      o.cly = true;
+    } else if (uy > limy) {
+      tyj = limy * tz;
+      o.cly = true;
+    }
+  }
+  o.txj = txj;
+  o.tyj = tyj;
+  const float j02 = -(cam.fx * txj) / tz2;
+  const float j12 = -(cam.fy * tyj) / tz2;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     o.T[c] = j00 * W[c] + j02 * W[6 + c];
@@ -482,7 +508,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project(GaussDev g, ViewTable 
     uint32_t cnt = 0;
     if (valid) {
       Proj pr;
-      discrete_stage(p, s, q, cam, ru.k, ru.lowpass, ru.guard, pr);
+      discrete_stage(p, s, q, cam, ru.k, ru.lowpass, ru.guard, ru.jclamp, pr);
       const int64_t rid = int64_t(v) * g.n + gi;
       if (pr.vis) {
         const int tx0 = pr.x0 / tile, tx1 = pr.x1 / tile, ty0 = pr.y0 / tile, ty1 = pr.y1 / tile;
@@ -1544,180 +1570,28 @@ __device__ __forceinline__ int next_item(uint32_t* head, int total, int* s_item)
   return item < total ? item : -1;
 }
 
-template <int TS, int BATCH>
-__global__ __launch_bounds__(TS* TS) void k_blend_bwd(ViewTable vt, Rules ru, Records rec, const uint2* ranges,
-                                                     const uint32_t* vals, const float* T_final,
-                                                     const uint32_t* n_contrib, float* grad2d, TileQueue q,
-                                                     Ckpt ck) {
-  constexpr int NT = TS * TS;
-  constexpr bool kBlockSum = NT > 64;
-  __shared__ float4 s_r0[BATCH];
-  __shared__ float4 s_r1[BATCH];
-  __shared__ float4 s_rgb[BATCH];
-  __shared__ uint32_t s_id[BATCH];
-  __shared__ float s_g[kBlockSum ? BATCH : 1][kBlockSum ? 10 : 1];  // per staged splat, its ten sums
-  __shared__ uint32_t s_max;
-  __shared__ int s_item;
-  if (kBlockSum)
-    for (int i = threadIdx.x; i < 10 * BATCH; i += NT) (&s_g[0][0])[i] = 0.f;
-  const int total = int(q.ctrl[kItems]);
-  for (;;) {
-  const int item = next_item(q.ctrl + kHeadBwd, total, &s_item);
-  if (item < 0) return;
-  const uint2 it = ck.items[item];
-  const int tile = int(it.x), bf = int(it.y);
-  const ViewDev& cam = vt.v[view_of_tile(vt, tile)];
-  const int lt = tile - cam.tile_off;
-  const int ty = lt / cam.tiles_x, tx = lt - ty * cam.tiles_x;
-  const int px = tx * TS + int(threadIdx.x % TS), py = ty * TS + int(threadIdx.x / TS);
-  const bool inside = px < cam.W && py < cam.H;
-  const uint2 rg = ranges[tile];
-  constexpr int CK = BATCH / 2;  // checkpoint stride of the forward
-  const int lo = bf * CK;        // the item's list entries: [lo, hi)
-  const int hi = bf < ck.kmax ? lo + CK : int(rg.y - rg.x);
-  const int lane = threadIdx.x & 63;
-  const int64_t P = int64_t(cam.W) * cam.H;
-  const int64_t pix = int64_t(py) * cam.W + px;
-  // this pixel's contributors in the item: positions [lo, top); the state behind them is
-  // the final one when the pixel's list ends inside the item, else the checkpoint at the
-  // item's end, with the colour/depth behind = (total - in front + T_final bg) / T
-  float T = 1.f, Tfin = 1.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gA = 0.f;
-  float BC0 = ru.bg[0], BC1 = ru.bg[1], BC2 = ru.bg[2], BD = 0.f;
-  int top = 0;
-  if (inside) {
-    const int nc = int(n_contrib[cam.pix_off + pix]);
-    if (nc > lo) {
-      Tfin = T_final[cam.pix_off + pix];
-      if (cam.g_color) {
-        gC0 = cam.g_color[pix];
-        gC1 = cam.g_color[P + pix];
-        gC2 = cam.g_color[2 * P + pix];
-      }
-      if (cam.g_depth) gD = cam.g_depth[pix];
-      if (cam.g_alpha) gA = cam.g_alpha[pix];
-      if (ru.norm_depth) {  // output Dn = D / A, A = 1 - T_final: dL/dD = g / A, dL/dA -= g Dn / A
-        const float A = 1.f - Tfin;
-        if (A > 0.f) {
-          const float Dn = ck.acc[cam.pix_off + pix].w / A;
-          gA -= gD * Dn / A;
-          gD = gD / A;
-        } else {
-          gD = 0.f;
-        }
-      }
-      if (nc <= hi) {
-        T = Tfin;
-        top = nc;
-      } else {  // only single-stride items end before the list: checkpoint bf + 1 <= kmax
-        const float* st = ck.state + (int64_t(tile) * ck.kmax + bf) * (5 * NT) + threadIdx.x;
-        const float4 acc = ck.acc[cam.pix_off + pix];
-        T = st[0];
-        const float inv = 1.f / T;
-        BC0 = (acc.x - st[NT] + Tfin * ru.bg[0]) * inv;
-        BC1 = (acc.y - st[2 * NT] + Tfin * ru.bg[1]) * inv;
-        BC2 = (acc.z - st[3 * NT] + Tfin * ru.bg[2]) * inv;
-        BD = (acc.w - st[4 * NT]) * inv;
-        top = hi;
-      }
-    }
-  }
-  const int wmax = int(wave_max_u32(uint32_t(top)));
-  if (threadIdx.x == 0) s_max = 0;
-  __syncthreads();
-  if (lane == 0 && wmax) atomicMax(&s_max, uint32_t(wmax));
-  __syncthreads();
-  const int bmax = int(s_max);
-  const float fpx = float(px), fpy = float(py);
-  for (int bend = bmax; bend > lo; bend -= BATCH) {
-    const int bstart = max(lo, bend - BATCH);
-    const int nstage = bend - bstart;
-    __syncthreads();
-    for (int j = threadIdx.x; j < nstage; j += NT) {
-      const uint32_t id = vals[rg.x + bstart + j];
-      s_id[j] = id;
-      stage_record(rec, id, s_r0[j], s_r1[j], s_rgb[j]);
-    }
-    __syncthreads();
-    for (int j = min(nstage, wmax - bstart) - 1; j >= 0; --j) {
-      // straight-line for every lane: lanes that do not take part (past their list, or
-      // below the skip threshold) keep T and the running blends and add zeros
-      const float4 r0 = s_r0[j];
-      const float4 r1 = s_r1[j];
-      const float dx = fpx - r0.x, dy = fpy - r0.y;
-      float G;
-      const float a = splat_alpha(dx, dy, r0.z, r0.w, r1.x, r1.y, G);
-      const bool act = bstart + j < top && !(a < ru.amin);
-      if (__ballot(act) == 0ull) continue;
-      const float4 c = s_rgb[j];
-      const float al = a < ru.amax ? a : ru.amax;
-      const float om = 1.f - al;
-      const float iom = __builtin_amdgcn_rcpf(om);
-      T = act ? T * iom : T;
-      const float wgt = act ? al * T : 0.f;
-      const float g6 = gC0 * wgt, g7 = gC1 * wgt, g8 = gC2 * wgt, g9 = gD * wgt;
-      const float dal =
-          T * (gC0 * (c.x - BC0) + gC1 * (c.y - BC1) + gC2 * (c.z - BC2) + gD * (r1.z - BD)) + gA * Tfin * iom;
-      BC0 = act ? al * c.x + om * BC0 : BC0;
-      BC1 = act ? al * c.y + om * BC1 : BC1;
-      BC2 = act ? al * c.z + om * BC2 : BC2;
-      BD = act ? al * r1.z + om * BD : BD;
-      const float da = (act && a <= ru.amax) ? dal : 0.f;
-      const float g5 = da * G;
-      const float dpw = da * a;
-      // (A dx + B dy, B dx + C dy) = -ln 2 (2a' dx + b' dy, b' dx + 2c' dy)
-      const float dpl = -0.69314718055994531f * dpw;
-      const float g0 = dpl * (r1.w * dx + r0.w * dy);
-      const float g1 = dpl * (r0.w * dx + c.w * dy);
-      const float g2 = -0.5f * dpw * dx * dx;
-      const float g3 = -dpw * dx * dy;
-      const float g4 = -0.5f * dpw * dy * dy;
-      const float gv[10] = {g0, g1, g2, g3, g4, g5, g6, g7, g8, g9};
-      float w0, w1, w2;
-      wave_sum10(gv, w0, w1, w2);
-      if ((lane & 15) == 0) {  // one lane per row adds its row's totals
-        const int row = lane >> 4;
-        const int k = row == 1 ? 2 : (row == 2 ? 1 : row);
-        if (kBlockSum) {
-          atomicAdd(&s_g[j][k], w0);
-          atomicAdd(&s_g[j][4 + k], w1);
-          if (!(row & 1)) atomicAdd(&s_g[j][8 + (row >> 1)], w2);
-        } else {
-          float* dst = grad2d + int64_t(s_id[j]) * kGrad2D;
-          unsafeAtomicAdd(dst + k, w0);
-          unsafeAtomicAdd(dst + 4 + k, w1);
-          if (!(row & 1)) unsafeAtomicAdd(dst + 8 + (row >> 1), w2);
-        }
-      }
-    }
-    if (kBlockSum) {
-      __syncthreads();
-      // splat-major: the lanes of a wavefront add consecutive sums of a few splats, so
-      // one atomic instruction touches a few gradient rows (cache lines), not 64
-      for (int i = threadIdx.x; i < 10 * nstage; i += NT) {
-        const int j = i / 10, k = i - 10 * j;
-        float* g = &(&s_g[0][0])[i];
-        const float v = *g;
-        if (v != 0.f) {
-          unsafeAtomicAdd(grad2d + int64_t(s_id[j]) * kGrad2D + k, v);
-          *g = 0.f;
-        }
-      }
-    }
-  }
-  }
-}
-
-// K8 with PPL vertically adjacent pixels per lane (tiles of 16 and 32): with two, a
+// K8 with PPL vertically adjacent pixels per lane: with two (tiles of 16 and 32) a
 // wavefront covers 128 pixels, so each splat's ten partials are reduced across the
-// wavefront once for twice the pixels (the pair's partials are added first).  Same
-// per-pixel arithmetic and work items as k_blend_bwd.  Two per lane is the build's
-// choice (kBwdPixelsPerLane); four ran slower on the headline view.
+// wavefront once for twice the pixels (the pair's partials are added first); tiles of 8
+// use one.  Two per lane is the build's choice for the larger tiles (kBwdPixelsPerLane);
+// four ran slower on the headline view.
+//
+// Per pixel, back to front, with g = dL/d(colour, depth) of the pixel and B the blend of
+// g . (colour, depth) of the contributors behind (B = g . (bg, 0) behind the last):
+//   T_i = T_(i+1) / (1 - alpha_i),  dL/dalpha_i = T_i (g . (c_i, z_i) - B) + gA T_final / (1 - alpha_i),
+//   B <- alpha_i g . (c_i, z_i) + (1 - alpha_i) B,
+// which is the per-channel recurrence of the colour behind, dotted with g once (g is fixed
+// per pixel).  The splat's geometric partials are kept as moments of q = a dL/da over the
+// pixel offsets, (sum q dx, sum q dy, sum q dx^2, sum q dx dy, sum q dy^2); the flush turns
+// them into the centre and conic gradients with the splat's conic, once per splat.
 struct BwdPixel {
-  float T, Tfin, gC0, gC1, gC2, gD, gA, BC0, BC1, BC2, BD, fpy;
+  float T, Tfin, gC0, gC1, gC2, gD, gATf, B, fpy;
   int top;
 };
 
-// A pixel's state at the end of work item (tile, bf): as in k_blend_bwd.
+// A pixel's state at the end of work item (tile, bf): its final state when the pixel's
+// list ends inside the item, else the forward's checkpoint at the item's end, with the
+// colour/depth behind = (total - in front + T_final bg) / T.
 template <int TS>
 __device__ __forceinline__ void bwd_pixel_setup(BwdPixel& s, const ViewDev& cam, const Rules& ru, const Ckpt& ck,
                                                 const float* T_final, const uint32_t* n_contrib, int tile, int bf,
@@ -1728,34 +1602,33 @@ __device__ __forceinline__ void bwd_pixel_setup(BwdPixel& s, const ViewDev& cam,
   const int64_t pix = int64_t(py) * cam.W + px;
   s.T = 1.f;
   s.Tfin = 1.f;
-  s.gC0 = s.gC1 = s.gC2 = s.gD = s.gA = 0.f;
-  s.BC0 = ru.bg[0];
-  s.BC1 = ru.bg[1];
-  s.BC2 = ru.bg[2];
-  s.BD = 0.f;
+  s.gC0 = s.gC1 = s.gC2 = s.gD = s.gATf = s.B = 0.f;
   s.top = 0;
   s.fpy = float(py);
   if (!inside) return;
   const int nc = int(n_contrib[cam.pix_off + pix]);
   if (nc <= lo) return;
   s.Tfin = T_final[cam.pix_off + pix];
+  float gA = 0.f;
   if (cam.g_color) {
     s.gC0 = cam.g_color[pix];
     s.gC1 = cam.g_color[P + pix];
     s.gC2 = cam.g_color[2 * P + pix];
   }
   if (cam.g_depth) s.gD = cam.g_depth[pix];
-  if (cam.g_alpha) s.gA = cam.g_alpha[pix];
+  if (cam.g_alpha) gA = cam.g_alpha[pix];
   if (ru.norm_depth) {  // output Dn = D / A, A = 1 - T_final: dL/dD = g / A, dL/dA -= g Dn / A
     const float A = 1.f - s.Tfin;
     if (A > 0.f) {
       const float Dn = ck.acc[cam.pix_off + pix].w / A;
-      s.gA -= s.gD * Dn / A;
+      gA -= s.gD * Dn / A;
       s.gD = s.gD / A;
     } else {
       s.gD = 0.f;
     }
   }
+  s.gATf = gA * s.Tfin;
+  float BC0 = ru.bg[0], BC1 = ru.bg[1], BC2 = ru.bg[2], BD = 0.f;
   if (nc <= hi) {
     s.T = s.Tfin;
     s.top = nc;
@@ -1764,45 +1637,77 @@ __device__ __forceinline__ void bwd_pixel_setup(BwdPixel& s, const ViewDev& cam,
     const float4 acc = ck.acc[cam.pix_off + pix];
     s.T = st[0];
     const float inv = 1.f / s.T;
-    s.BC0 = (acc.x - st[NP] + s.Tfin * ru.bg[0]) * inv;
-    s.BC1 = (acc.y - st[2 * NP] + s.Tfin * ru.bg[1]) * inv;
-    s.BC2 = (acc.z - st[3 * NP] + s.Tfin * ru.bg[2]) * inv;
-    s.BD = (acc.w - st[4 * NP]) * inv;
+    BC0 = (acc.x - st[NP] + s.Tfin * ru.bg[0]) * inv;
+    BC1 = (acc.y - st[2 * NP] + s.Tfin * ru.bg[1]) * inv;
+    BC2 = (acc.z - st[3 * NP] + s.Tfin * ru.bg[2]) * inv;
+    BD = (acc.w - st[4 * NP]) * inv;
     s.top = hi;
   }
+  s.B = s.gC0 * BC0 + s.gC1 * BC1 + s.gC2 * BC2 + s.gD * BD;
 }
 
-// One (pixel, splat) step back to front: updates the pixel's state and adds its ten
-// partials to g (the same arithmetic as k_blend_bwd's loop body).
+// One (pixel, splat) step back to front, adding the pixel's partials to g: the five
+// geometric moments, dL/dopacity's sum of dL/da G, and the colour/depth weights.  A lane
+// that does not take part (past its list, or below the skip threshold) takes alpha = 0,
+// which leaves B unchanged and adds zeros; its T is kept by a select (1 / (1 - 0) is not
+// relied on to be exact).
 __device__ __forceinline__ void bwd_pixel_step(BwdPixel& s, bool act, float a, float G, float dx, float dy,
-                                               const float4& r0, const float4& r1, const float4& c, const Rules& ru,
-                                               float (&g)[10]) {
-  const float al = a < ru.amax ? a : ru.amax;
+                                               const float4& r1, const float4& c, const Rules& ru, float (&g)[10]) {
+  const float al = act ? fminf(a, ru.amax) : 0.f;
   const float om = 1.f - al;
   const float iom = __builtin_amdgcn_rcpf(om);
   s.T = act ? s.T * iom : s.T;
-  const float wgt = act ? al * s.T : 0.f;
+  const float wgt = al * s.T;
   g[6] += s.gC0 * wgt;
   g[7] += s.gC1 * wgt;
   g[8] += s.gC2 * wgt;
   g[9] += s.gD * wgt;
-  const float dal = s.T * (s.gC0 * (c.x - s.BC0) + s.gC1 * (c.y - s.BC1) + s.gC2 * (c.z - s.BC2) +
-                           s.gD * (r1.z - s.BD)) +
-                    s.gA * s.Tfin * iom;
-  s.BC0 = act ? al * c.x + om * s.BC0 : s.BC0;
-  s.BC1 = act ? al * c.y + om * s.BC1 : s.BC1;
-  s.BC2 = act ? al * c.z + om * s.BC2 : s.BC2;
-  s.BD = act ? al * r1.z + om * s.BD : s.BD;
+  const float S = s.gC0 * c.x + s.gC1 * c.y + s.gC2 * c.z + s.gD * r1.z;
+  const float dal = s.T * (S - s.B) + s.gATf * iom;
+  s.B = al * S + om * s.B;
   const float da = (act && a <= ru.amax) ? dal : 0.f;
   g[5] += da * G;
-  const float dpw = da * a;
-  // (A dx + B dy, B dx + C dy) = -ln 2 (2a' dx + b' dy, b' dx + 2c' dy)
-  const float dpl = -0.69314718055994531f * dpw;
-  g[0] += dpl * (r1.w * dx + r0.w * dy);
-  g[1] += dpl * (r0.w * dx + c.w * dy);
-  g[2] += -0.5f * dpw * dx * dx;
-  g[3] += -dpw * dx * dy;
-  g[4] += -0.5f * dpw * dy * dy;
+  const float q = da * a;
+  const float qx = q * dx, qy = q * dy;
+  g[0] += qx;
+  g[1] += qy;
+  g[2] += qx * dx;
+  g[3] += qx * dy;
+  g[4] += qy * dy;
+}
+
+// The splat-major flush of a batch's per-splat sums (s_g, ten per splat, cleared as they
+// are read) into the 2D-gradient rows: the lanes of a wavefront add consecutive sums of a
+// few splats, so one atomic instruction touches a few gradient rows (cache lines), not 64.
+// The moments become gradients here: with the staged conic (a', b', c') = (A, 2B, C) (-log2 e / 2),
+// (A dx + B dy, B dx + C dy) = -ln 2 (2a' dx + b' dy, b' dx + 2c' dy), so
+//   dmu = -ln 2 (2a' Mx + b' My, b' Mx + 2c' My),  d(A, B, C) = -(Mxx / 2, Mxy, Myy / 2).
+template <int NT, int BATCH>
+__device__ __forceinline__ void flush_splat_sums(float (&s_g)[BATCH][10], const uint32_t* s_id, const float4* s_r0,
+                                                 const float4* s_r1, const float4* s_rgb, int nstage,
+                                                 float* grad2d) {
+  constexpr float kNegLn2 = -0.69314718055994531f;
+  for (int i = threadIdx.x; i < 10 * nstage; i += NT) {
+    const int j = i / 10, k = i - 10 * j;
+    if (k == 1) continue;  // the centre's y gradient goes with its x gradient (k == 0)
+    float* dst = grad2d + int64_t(s_id[j]) * kGrad2D;
+    if (k == 0) {
+      const float mx = s_g[j][0], my = s_g[j][1];
+      s_g[j][0] = 0.f;
+      s_g[j][1] = 0.f;
+      if (mx != 0.f || my != 0.f) {
+        const float b = s_r0[j].w;   // b'
+        const float a2 = s_r1[j].w;  // 2 a'
+        const float c2 = s_rgb[j].w; // 2 c'
+        unsafeAtomicAdd(dst, kNegLn2 * (a2 * mx + b * my));
+        unsafeAtomicAdd(dst + 1, kNegLn2 * (b * mx + c2 * my));
+      }
+      continue;
+    }
+    const float v = s_g[j][k];
+    s_g[j][k] = 0.f;
+    if (v != 0.f) unsafeAtomicAdd(dst + k, k == 3 ? -v : ((k == 2 || k == 4) ? -0.5f * v : v));
+  }
 }
 
 template <int TS, int BATCH, int PPL>
@@ -1877,7 +1782,7 @@ __global__ __launch_bounds__(TS* TS / PPL) void k_blend_bwd2(ViewTable vt, Rules
         const float4 c = s_rgb[j];
         float gv[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int i = 0; i < PPL; ++i) bwd_pixel_step(p[i], act[i], a[i], G[i], dx, dy[i], r0, r1, c, ru, gv);
+        for (int i = 0; i < PPL; ++i) bwd_pixel_step(p[i], act[i], a[i], G[i], dx, dy[i], r1, c, ru, gv);
         float w0, w1, w2;
         wave_sum10(gv, w0, w1, w2);
         if ((lane & 15) == 0) {  // one lane per row adds its row's totals
@@ -1889,17 +1794,7 @@ __global__ __launch_bounds__(TS* TS / PPL) void k_blend_bwd2(ViewTable vt, Rules
         }
       }
       __syncthreads();
-      // splat-major: the lanes of a wavefront add consecutive sums of a few splats, so
-      // one atomic instruction touches a few gradient rows (cache lines), not 64
-      for (int i = threadIdx.x; i < 10 * nstage; i += NT) {
-        const int j = i / 10, k = i - 10 * j;
-        float* g = &(&s_g[0][0])[i];
-        const float v = *g;
-        if (v != 0.f) {
-          unsafeAtomicAdd(grad2d + int64_t(s_id[j]) * kGrad2D + k, v);
-          *g = 0.f;
-        }
-      }
+      flush_splat_sums<NT, BATCH>(s_g, s_id, s_r0, s_r1, s_rgb, nstage, grad2d);
     }
   }
 }
@@ -2046,7 +1941,7 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd_geo(GaussDev g, Vi
     const float dmux = ga.x, dmuy = ga.y, dA = ga.z, dB = ga.w, dC = gb.x, dO = gb.y;
     const float dz = gc.y;
     Proj pr;
-    discrete_stage(p, s, q, cam, ru.k, ru.lowpass, ru.guard, pr);
+    discrete_stage(p, s, q, cam, ru.k, ru.lowpass, ru.guard, ru.jclamp, pr);
     float A, B, C;
     conic_of(pr.a, pr.b, pr.c, A, B, C);
     dop += dO;
@@ -2084,9 +1979,12 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd_geo(GaussDev g, Vi
     const float tx = pr.tx, ty = pr.ty, tz = pr.tz;
     const float iz = 1.f / tz, iz2 = iz * iz, iz3 = iz2 * iz;
     const float fx = cam.fx, fy = cam.fy;
-    const float dtx = -fx * iz2 * dJ02 + fx * iz * dmux;
-    const float dty = -fy * iz2 * dJ12 + fy * iz * dmuy;
-    const float dtz = -fx * iz2 * dJ00 + 2.f * fx * tx * iz3 * dJ02 - fy * iz2 * dJ11 + 2.f * fy * ty * iz3 * dJ12 -
+    // J02 = -fx x' / z^2 with x' = tx, or +-limit tz where clamped: d/dtx of a clamped
+    // entry is 0 and its d/dtz is -J02 / tz (2 fx x' / z^3 halved); likewise J12
+    const float kx = pr.clx ? 1.f : 2.f, ky = pr.cly ? 1.f : 2.f;
+    const float dtx = (pr.clx ? 0.f : -fx * iz2 * dJ02) + fx * iz * dmux;
+    const float dty = (pr.cly ? 0.f : -fy * iz2 * dJ12) + fy * iz * dmuy;
+    const float dtz = -fx * iz2 * dJ00 + kx * fx * pr.txj * iz3 * dJ02 - fy * iz2 * dJ11 + ky * fy * pr.tyj * iz3 * dJ12 -
                       fx * tx * iz2 * dmux - fy * ty * iz2 * dmuy + dz;
 #pragma unroll
     for (int j = 0; j < 3; ++j) dp[j] += W[j] * dtx + W[3 + j] * dty + W[6 + j] * dtz;
@@ -2414,17 +2312,12 @@ template <int TS, int BATCH>
 static void blend_bwd_t(const ViewTable& vt, const Rules& ru, const Records& rec, const uint2* ranges,
                         const uint32_t* vals, const float* T_final, const uint32_t* n_contrib, float* grad2d,
                         const TileQueue& q, const Ckpt& ck, hipStream_t s) {
-  if constexpr (TS >= 16) {  // kBwdPixelsPerLane pixels per lane
-    constexpr int PPL = kBwdPixelsPerLane;
-    const int grid = int(std::min<int64_t>(
-        ck.cap_items, resident_blocks<k_blend_bwd2<TS, BATCH, PPL>>(TS * TS / PPL, kBwd2BlocksPerCU)));
-    k_blend_bwd2<TS, BATCH, PPL><<<grid, TS * TS / PPL, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d,
-                                                                q, ck);
-  } else {
-    const int grid =
-        int(std::min<int64_t>(ck.cap_items, resident_blocks<k_blend_bwd<TS, BATCH>>(TS * TS, kBwdBlocksPerCU)));
-    k_blend_bwd<TS, BATCH><<<grid, TS * TS, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck);
-  }
+  constexpr int PPL = TS >= 16 ? kBwdPixelsPerLane : 1;
+  constexpr int cap = TS >= 16 ? kBwd2BlocksPerCU : kBwdBlocksPerCU;
+  const int grid =
+      int(std::min<int64_t>(ck.cap_items, resident_blocks<k_blend_bwd2<TS, BATCH, PPL>>(TS * TS / PPL, cap)));
+  k_blend_bwd2<TS, BATCH, PPL><<<grid, TS * TS / PPL, 0, s>>>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d,
+                                                              q, ck);
 }
 
 hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,

@@ -26,6 +26,7 @@ gsr_status settings(const gsr_settings* s, std::string& err) {
     return bad(err, "rule value out of range");
   if (!std::isfinite(s->extent_k) || !std::isfinite(s->lowpass) || !std::isfinite(s->guard))
     return bad(err, "rule value not finite");
+  if (!(s->jclamp >= 0.f) || !std::isfinite(s->jclamp)) return bad(err, "jclamp must be finite and >= 0");
   if (s->flags & ~(GSR_EXACT_TILES | GSR_NORMALIZED_DEPTH | GSR_CHECK_FINITE)) return bad(err, "unknown settings flag");
   return GSR_OK;
 }

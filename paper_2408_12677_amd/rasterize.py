@@ -38,12 +38,13 @@ class Settings:
     exact_tiles: bool = False   # GSR_EXACT_TILES: per tile row, only the columns the ellipse reaches
     normalized_depth: bool = False   # GSR_NORMALIZED_DEPTH: depth output D / (1 - T_final)
     check_finite: bool = False   # GSR_CHECK_FINITE: eager forwards reject NaN/Inf parameters
+    jclamp: float = 0.0     # > 0: x/z, y/z clamped inside the projection's Jacobian (guard band)
 
     def c(self) -> N.Settings:
         return N.Settings(self.tile, self.batch, self.extent_k, self.lowpass, self.alpha_min, self.alpha_max,
                           self.T_min, self.guard, (ctypes.c_float * 3)(*self.bg),
                           (N.EXACT_TILES if self.exact_tiles else 0) | (N.NORMALIZED_DEPTH if self.normalized_depth else 0)
-                          | (N.CHECK_FINITE if self.check_finite else 0))
+                          | (N.CHECK_FINITE if self.check_finite else 0), self.jclamp)
 
 
 @dataclass
@@ -75,15 +76,31 @@ def _cams(cameras):
 
 
 class Context:
-    """A gsr_ctx bound to one device and one HIP stream."""
+    """A gsr_ctx bound to one device and one HIP stream.
 
-    def __init__(self, device: int, stream: int):
+    allocator (optional): an object with ``alloc(nbytes, stream) -> int`` (a device address,
+    0 when it cannot) and ``free(ptr, stream)``, given to the library as its gsr_alloc; by
+    default the library uses the device's stream-ordered pool."""
+
+    def __init__(self, device: int, stream: int, allocator=None):
         lib = N.load()
         self.lib = lib
         self.device = device
         self.stream = stream
+        self._alloc = None
+        if allocator is not None:
+            def _a(user, nbytes, strm):
+                try:
+                    return int(allocator.alloc(int(nbytes), strm or 0)) or None
+                except Exception:  # noqa: BLE001 -- the library sees an allocation failure
+                    return None
+
+            def _f(user, ptr, strm):
+                allocator.free(int(ptr), strm or 0)
+            self._alloc = N.Alloc(N.ALLOC_FN(_a), N.FREE_FN(_f), None)
         h = ctypes.c_void_p()
-        N.check(lib.gsr_ctx_create(device, ctypes.c_void_p(stream), ctypes.byref(h)))
+        N.check(lib.gsr_ctx_create(device, ctypes.c_void_p(stream),
+                                   ctypes.byref(self._alloc) if self._alloc is not None else None, ctypes.byref(h)))
         self.h = h
 
     def set_timing(self, on: bool):
@@ -103,10 +120,29 @@ class Context:
 
 
 _contexts: dict = {}
+_active: list = []
+
+
+class using:
+    """Inside ``with using(ctx):`` every call of this module runs on ``ctx`` (for example a
+    context with a caller's allocator) instead of the cached per-stream context."""
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+
+    def __enter__(self):
+        _active.append(self.ctx)
+        return self.ctx
+
+    def __exit__(self, *exc):
+        _active.pop()
 
 
 def context(device: torch.device | int | None = None) -> Context:
-    """The cached context of ``device`` bound to torch's current stream there."""
+    """The cached context of ``device`` bound to torch's current stream there (or the one
+    a ``using`` block selects)."""
+    if _active:
+        return _active[-1]
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     idx = dev.index if dev.index is not None else torch.cuda.current_device()
     stream = torch.cuda.current_stream(idx).cuda_stream
@@ -563,6 +599,54 @@ class Schedule:
         if h is not None and h.value:
             self.lib.gsr_schedule_free(h)
             self.h = None
+
+
+class KeyframeSteps:
+    """Time steps of the keyframe-list optimisation (Sec. III-B-3; the m / n settings of
+    Sec. IV-A) run as captured iterations.  ``step(frame, new_gaussians)`` asks the schedule
+    (gsr_schedule) which view each iteration of the time step renders, then replays, per
+    iteration, the captured optimisation iteration of that view: forward, L1 loss and
+    backward with the fused Adam step (gsr_graph_create with an optimiser).  Each view's
+    graph is captured on its first use and replayed afterwards, so a time step is a run of
+    graph launches with no host read-back; ``sync()`` waits for them and reports a capacity
+    overflow (re-create the object then).
+
+    cameras and targets are indexed by frame; the parameters are updated in place."""
+
+    def __init__(self, means, scales, quats, opacities, sh, cameras, targets, optimizer: "Adam",
+                 schedule: Schedule, settings: Settings | None = None, depth_weight: float = 0.1,
+                 headroom: float = 0.25):
+        self.params = (means, scales, quats, opacities, sh)
+        self.cameras, self.targets = cameras, targets
+        self.optimizer, self.schedule = optimizer, schedule
+        self.settings = settings or Settings()
+        self.depth_weight, self.headroom = float(depth_weight), float(headroom)
+        self.graphs: dict = {}
+        self.iterations: list = []   # the frame rendered by every iteration so far
+
+    def graph(self, frame: int) -> Graph:
+        g = self.graphs.get(frame)
+        if g is None:
+            g = self.graphs[frame] = Graph(*self.params, [self.cameras[frame]], [self.targets[frame]], self.settings,
+                                           self.depth_weight, self.headroom, optimizer=self.optimizer)
+        return g
+
+    def step(self, frame: int, new_gaussians: int):
+        """Run one time step; returns (is_keyframe, [frame of each iteration])."""
+        kf, iters = self.schedule.step(frame, new_gaussians)
+        for f in iters:
+            self.graph(f).launch()
+        self.iterations.extend(iters)
+        return kf, iters
+
+    def sync(self):
+        for g in self.graphs.values():
+            g.sync()
+
+    def free(self):
+        for g in self.graphs.values():
+            g.free()
+        self.graphs.clear()
 
 
 class TsdfMap:

@@ -56,7 +56,8 @@ def settings(**kw) -> R.Settings:
 def oracle_for(g, cams, s: R.Settings, threads=8):
     os_ = oracle.Settings(tile=s.tile, extent_k=s.extent_k, lowpass=s.lowpass, alpha_min=s.alpha_min,
                           alpha_max=s.alpha_max, T_min=s.T_min, guard=s.guard, bg=tuple(s.bg), mu_fp32=True,
-                          threads=threads, exact_tiles=s.exact_tiles, normalized_depth=s.normalized_depth)
+                          threads=threads, exact_tiles=s.exact_tiles, normalized_depth=s.normalized_depth,
+                          jclamp=s.jclamp)
     return oracle.Oracle(g.arrays(), g.sh_degree, cams, os_)
 
 

@@ -64,8 +64,14 @@ def test_null_arguments_are_rejected_before_device_work(lib):
     assert lib.gsr_saved_free(None) == N.EINVAL
     assert lib.gsr_saved_info(None, None) == N.EINVAL
     assert lib.gsr_ctx_destroy(None) == N.EINVAL
-    assert lib.gsr_ctx_create(0, None, None) == N.EINVAL
+    assert lib.gsr_ctx_create(0, None, None, None) == N.EINVAL
     assert b"NULL" in lib.gsr_last_error(None)
+    # a caller's allocator needs both functions (checked before any device call)
+    half = N.Alloc(N.ALLOC_FN(lambda user, n, s: None), N.FREE_FN(), None)
+    h = ctypes.c_void_p()
+    assert lib.gsr_ctx_create(0, None, ctypes.byref(half), ctypes.byref(h)) == N.EINVAL
+    assert b"alloc and free" in lib.gsr_last_error(None)
+    assert not h.value
 
 
 def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):

@@ -439,6 +439,41 @@ def test_headline_view_full_size_exact_tiles(R):
 
 
 # ---------------------------------------------------------------------------------------
+# the guard-band clamp of the projection's Jacobian on off-centre cameras
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tile,exact", [(8, False), (16, True)])
+def test_jacobian_clamp_offcentre_crops(R, tile, exact):
+    # crops whose principal points lie far from their centres (one outside the image): the
+    # clamp at 1.3 half fields of view acts on many rendered splats
+    w = scenes.make_cfg1()
+    c = w.cameras[0]
+    cams = [c.crop(0, 0, 40, 30), c.crop(80, 60, 48, 36), c.crop(88, 8, 40, 44)]
+    s = settings(tile=tile, exact_tiles=exact, jclamp=1.3)
+    plain = oracle_for(w.gaussians, cams, settings(tile=tile, exact_tiles=exact)).forward()
+    clamped = oracle_for(w.gaussians, cams, s).forward()
+    moved = max(float(np.abs(a["color"] - b["color"]).max()) for a, b in zip(plain, clamped))
+    say("clamp", tile, exact, "largest image change by the clamp", moved)
+    assert moved > 1e-3
+    rep, grep = fwd_bwd_parity(R, w.gaussians, cams, s)
+    say(rep, grep)
+
+
+def test_jacobian_clamp_cfg3_crop_with_loss(R):
+    w = scenes.make_cfg3()
+    cam = w.cameras[0]
+    crop = cam.crop(1100, 560, 64, 64)   # near the corner: x/z, y/z beyond the crop's limits
+    rec = oracle.Oracle(w.gaussians.arrays(), 3, [crop], oracle.Settings(threads=8, jclamp=1.3)).records()
+    idx = np.nonzero(rec["visible"])[0]
+    pick = np.sort(np.random.default_rng(34).choice(idx, size=min(2000, idx.size), replace=False))
+    g = w.gaussians.subset(pick)
+    rng = np.random.default_rng(35)
+    targets = [(rng.random((3, 64, 64)).astype(np.float32), (1 + 4 * rng.random((64, 64))).astype(np.float32))]
+    rep, grep = fwd_bwd_parity(R, g, [crop], settings(jclamp=1.3), targets=targets)
+    say("cfg3 clamp crop", g.n, rep, grep)
+
+
+# ---------------------------------------------------------------------------------------
 # variants: normalised depth output, a 3-sigma (lossy) splat extent
 # ---------------------------------------------------------------------------------------
 
