@@ -1676,25 +1676,34 @@ __device__ __forceinline__ void bwd_pixel_step(BwdPixel& s, bool act, float a, f
   g[4] += qy * dy;
 }
 
-// The splat-major flush of a batch's per-splat sums (s_g, ten per splat, cleared as they
-// are read) into the 2D-gradient rows: the lanes of a wavefront add consecutive sums of a
+// The splat-major flush of a batch's per-splat sums (s_g: ten per splat and wavefront,
+// each wavefront writing only its own; summed over the wavefronts and cleared as they are
+// read) into the 2D-gradient rows: the lanes of a wavefront add consecutive sums of a
 // few splats, so one atomic instruction touches a few gradient rows (cache lines), not 64.
 // The moments become gradients here: with the staged conic (a', b', c') = (A, 2B, C) (-log2 e / 2),
 // (A dx + B dy, B dx + C dy) = -ln 2 (2a' dx + b' dy, b' dx + 2c' dy), so
 //   dmu = -ln 2 (2a' Mx + b' My, b' Mx + 2c' My),  d(A, B, C) = -(Mxx / 2, Mxy, Myy / 2).
-template <int NT, int BATCH>
-__device__ __forceinline__ void flush_splat_sums(float (&s_g)[BATCH][10], const uint32_t* s_id, const float4* s_r0,
+template <int NT, int NW, int SB>
+__device__ __forceinline__ void flush_splat_sums(float (&s_g)[NW][SB][10], const uint32_t* s_id, const float4* s_r0,
                                                  const float4* s_r1, const float4* s_rgb, int nstage,
                                                  float* grad2d) {
   constexpr float kNegLn2 = -0.69314718055994531f;
+  // the wavefronts' sums of slot (j, k), cleared as they are read
+  auto take = [&](int j, int k) {
+    float v = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      v += s_g[w][j][k];
+      s_g[w][j][k] = 0.f;
+    }
+    return v;
+  };
   for (int i = threadIdx.x; i < 10 * nstage; i += NT) {
     const int j = i / 10, k = i - 10 * j;
     if (k == 1) continue;  // the centre's y gradient goes with its x gradient (k == 0)
     float* dst = grad2d + int64_t(s_id[j]) * kGrad2D;
     if (k == 0) {
-      const float mx = s_g[j][0], my = s_g[j][1];
-      s_g[j][0] = 0.f;
-      s_g[j][1] = 0.f;
+      const float mx = take(j, 0), my = take(j, 1);
       if (mx != 0.f || my != 0.f) {
         const float b = s_r0[j].w;   // b'
         const float a2 = s_r1[j].w;  // 2 a'
@@ -1704,8 +1713,7 @@ __device__ __forceinline__ void flush_splat_sums(float (&s_g)[BATCH][10], const 
       }
       continue;
     }
-    const float v = s_g[j][k];
-    s_g[j][k] = 0.f;
+    const float v = take(j, k);
     if (v != 0.f) unsafeAtomicAdd(dst + k, k == 3 ? -v : ((k == 2 || k == 4) ? -0.5f * v : v));
   }
 }
@@ -1716,14 +1724,17 @@ __global__ __launch_bounds__(TS* TS / PPL) void k_blend_bwd2(ViewTable vt, Rules
                                                             const float* T_final, const uint32_t* n_contrib,
                                                             float* grad2d, TileQueue q, Ckpt ck) {
   constexpr int NT = TS * TS / PPL;  // threads: pixels (PPL r + i, c), i < PPL, for t = r TS + c
-  __shared__ float4 s_r0[BATCH];
-  __shared__ float4 s_r1[BATCH];
-  __shared__ float4 s_rgb[BATCH];
-  __shared__ uint32_t s_id[BATCH];
-  __shared__ float s_g[BATCH][10];  // per staged splat, its ten sums
+  constexpr int NW = NT / 64;        // wavefronts
+  constexpr int SB = BATCH / 2;      // entries staged at a time: one checkpoint stride
+  __shared__ float4 s_r0[SB];
+  __shared__ float4 s_r1[SB];
+  __shared__ float4 s_rgb[SB];
+  __shared__ uint32_t s_id[SB];
+  __shared__ float s_g[NW][SB][10];  // per wavefront and staged splat, its ten sums
   __shared__ uint32_t s_max;
   __shared__ int s_item;
-  for (int i = threadIdx.x; i < 10 * BATCH; i += NT) (&s_g[0][0])[i] = 0.f;
+  for (int i = threadIdx.x; i < NW * 10 * SB; i += NT) (&s_g[0][0][0])[i] = 0.f;
+  const int wv = int(threadIdx.x) >> 6;
   const int total = int(q.ctrl[kItems]);
   const int lane = threadIdx.x & 63;
   const int cx = int(threadIdx.x % TS), ry = PPL * int(threadIdx.x / TS);
@@ -1754,8 +1765,8 @@ __global__ __launch_bounds__(TS* TS / PPL) void k_blend_bwd2(ViewTable vt, Rules
     __syncthreads();
     const int bmax = int(s_max);
     const float fpx = float(px);
-    for (int bend = bmax; bend > lo; bend -= BATCH) {
-      const int bstart = max(lo, bend - BATCH);
+    for (int bend = bmax; bend > lo; bend -= SB) {
+      const int bstart = max(lo, bend - SB);
       const int nstage = bend - bstart;
       __syncthreads();
       for (int j = threadIdx.x; j < nstage; j += NT) {
@@ -1785,16 +1796,16 @@ __global__ __launch_bounds__(TS* TS / PPL) void k_blend_bwd2(ViewTable vt, Rules
         for (int i = 0; i < PPL; ++i) bwd_pixel_step(p[i], act[i], a[i], G[i], dx, dy[i], r1, c, ru, gv);
         float w0, w1, w2;
         wave_sum10(gv, w0, w1, w2);
-        if ((lane & 15) == 0) {  // one lane per row adds its row's totals
+        if ((lane & 15) == 0) {  // one lane per row stores its row's totals
           const int row = lane >> 4;
           const int k = row == 1 ? 2 : (row == 2 ? 1 : row);
-          atomicAdd(&s_g[j][k], w0);
-          atomicAdd(&s_g[j][4 + k], w1);
-          if (!(row & 1)) atomicAdd(&s_g[j][8 + (row >> 1)], w2);
+          s_g[wv][j][k] = w0;  // this wavefront's own slots: plain stores
+          s_g[wv][j][4 + k] = w1;
+          if (!(row & 1)) s_g[wv][j][8 + (row >> 1)] = w2;
         }
       }
       __syncthreads();
-      flush_splat_sums<NT, BATCH>(s_g, s_id, s_r0, s_r1, s_rgb, nstage, grad2d);
+      flush_splat_sums<NT, NW, SB>(s_g, s_id, s_r0, s_r1, s_rgb, nstage, grad2d);
     }
   }
 }
