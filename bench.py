@@ -69,10 +69,8 @@ def kernel_bytes(name, st):
         return Nv * 16
     if name == "bin_count":                      # mean of the row and the tile histogram launches
         return (Nv * 12 + E1 * 8) / 2
-    if name == "bin_scatter":                    # mean of the row and the tile placement launches
-        return (Nv * 12 + E1 * 8 + E1 * 8 + M * 4) / 2
-    if name == "ranges":
-        return st["tiles"] * 32
+    if name == "bin_scatter":                    # mean of the row and the tile placement (+ ranges) launches
+        return (Nv * 12 + E1 * 8 + E1 * 8 + M * 4 + st["tiles"] * 32) / 2
     if name == "blend_fwd":
         return st["loaded_fwd"] * (4 + 48) + P * 28
     if name == "blend_bwd":

@@ -112,7 +112,7 @@ namespace {
 
 const char* const kKernelNames[K_COUNT] = {"project",    "scan",          "compact",       "radix_hist",
                                            "radix_rowscan", "radix_scatter", "bin_count",   "bin_scan",
-                                           "bin_scatter", "ranges",        "tile_order",    "fill",
+                                           "bin_scatter", "tile_order",    "fill",
                                            "blend_fwd",  "loss_l1",       "blend_bwd",     "project_bwd",
                                            "adam",       "tsdf_alloc",    "tsdf_fuse"};
 
@@ -274,6 +274,7 @@ gsr_status make_saved(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_camera* ca
   if ((st = alloc_in(sv, B, &sv->rec.r0, VN)) != GSR_OK || (st = alloc_in(sv, B, &sv->rec.r1, VN)) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->rec.rgb, VN)) != GSR_OK || (st = alloc_in(sv, B, &sv->rec.rect, VN)) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->rec.counts, VN)) != GSR_OK ||
+      ((s->flags & GSR_EXACT_TILES) && (st = alloc_in(sv, B, &sv->rec.runs, size_t(VN) * kRowRuns)) != GSR_OK) ||
       (st = alloc_in(sv, B, &sv->blocksums, size_t(V) * sv->nblk + 1)) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->d_total, 4)) != GSR_OK || (st = alloc_in(sv, B, &sv->ranges, size_t(tiles))) != GSR_OK ||
       (st = alloc_in(sv, B, &sv->order, size_t(tiles))) != GSR_OK ||
@@ -298,7 +299,6 @@ gsr_status alloc_sort(gsr_saved* sv, int64_t cap_vis, int64_t cap_M, bool persis
   sv->cap_vis = cap_vis;
   sv->cap_M = cap_M;
   std::vector<void*>& T = persistent ? sv->blocks : sv->temps;
-  const int64_t nb_sort = (cap_vis + kSortTile - 1) / kSortTile;
   BinPlan& p = sv->plan;
   p = bin_plan(sv->vt, cap_vis, cap_M);
   const int64_t n1 = int64_t(p.rows) * p.nch1;
@@ -306,7 +306,7 @@ gsr_status alloc_sort(gsr_saved* sv, int64_t cap_vis, int64_t cap_M, bool persis
   gsr_status st = GSR_OK;
   if ((st = alloc_in(sv, T, &sv->dk, cap_vis)) != GSR_OK || (st = alloc_in(sv, T, &sv->dv, cap_vis)) != GSR_OK ||
       (st = alloc_in(sv, T, &sv->dk2, cap_vis)) != GSR_OK || (st = alloc_in(sv, T, &sv->dv2, cap_vis)) != GSR_OK ||
-      (st = alloc_in(sv, T, &sv->hist, size_t(nb_sort) * 256)) != GSR_OK ||
+      (st = alloc_in(sv, T, &sv->hist, size_t(radix_hist_words(cap_vis)))) != GSR_OK ||
       (st = alloc_in(sv, T, &sv->dtot, 256)) != GSR_OK ||
       (st = alloc_in(sv, sv->blocks, &sv->vals, cap_M)) != GSR_OK ||
       (st = alloc_in(sv, T, &p.cnt1, size_t(n1))) != GSR_OK || (st = alloc_in(sv, T, &p.rowlist, cap_M)) != GSR_OK ||
@@ -389,7 +389,7 @@ hipError_t enqueue_project(gsr_saved* sv, hipStream_t s, bool timing) {
   hipError_t e = T(K_PROJECT, [&] {
     // a captured step zeroes its 2D-gradient rows here, for the records that are visible
     return launch_project(sv->deg, sv->g, sv->vt, sv->ru, sv->s.tile, sv->rec, sv->blocksums, sv->nblk, sv->grad2d,
-                          sv->ctrl, clear, s);
+                          sv->ctrl, clear, (sv->s.flags & GSR_EXACT_TILES) ? sv->ru.k : 0.f, s);
   });
   if (e == hipSuccess)
     e = T(K_SCAN, [&] { return launch_scan_pairs(sv->blocksums, sv->V * sv->nblk, sv->d_total, s); });
@@ -414,12 +414,14 @@ hipError_t enqueue_sort_blend(gsr_saved* sv, hipStream_t s, bool timing) {
                             sv->cap_vis, ovf, s);
     });
     if (e == hipSuccess)
+      // depth keys are the bits of a positive binary32 depth: bit 31 is zero
       e = launch_radix_sort(sv->dk, sv->dv, sv->dk2, sv->dv2, sv->hist, sv->dtot, sv->d_total + 1, sv->cap_vis, ovf,
-                            32, &alt, &sv->sort_passes, s, tm);
+                            31, &alt, &sv->sort_passes, s, tm);
     if (alt) sorted = sv->dv2;
   }
   if (e == hipSuccess)
-    e = launch_bin(sv->vt, sv->N, sv->rec, sorted, sv->d_total + 1, sv->cap_vis, sv->plan, sv->vals, sv->ranges, ovf,
+    e = launch_bin(sv->vt, sv->N, sv->rec, sorted, sv->d_total + 1, sv->cap_vis, sv->plan, sv->vals, sv->ranges,
+                   sv->ctrl,
                    (sv->s.flags & GSR_EXACT_TILES) ? sv->ru.k : 0.f, sv->s.tile, s, tm);
   if (e == hipSuccess)
     e = T(K_TILE_ORDER, [&] {

@@ -22,7 +22,6 @@ enum KernelId {
   K_BIN_COUNT,
   K_BIN_SCAN,
   K_BIN_SCATTER,
-  K_RANGES,
   K_TILE_ORDER,
   K_FILL,
   K_BLEND_FWD,
@@ -113,7 +112,7 @@ constexpr int kStepWords = 4;  // words 0..3 start at zero in every step (cleare
 // step reads it to leave the parameters alone once one happened
 constexpr int kOverflowSticky = 4;
 constexpr int kCtrlWords = 8;
-constexpr int kScanTile = 4096;            // elements per block of the device-wide scans
+constexpr int kScanTile = 4096;  // elements per block of the device-wide scans
 constexpr int64_t kMaxBinCounts = int64_t(1) << 22;  // entries of each binning count array (soft)
 
 // One camera plus where its tiles and pixels live in the concatenated spaces.
@@ -169,7 +168,14 @@ struct Records {
   float4* rgb;      // (r, g, b, unused)
   uint2* rect;      // (tx0 | tx1 << 16, ty0 | ty1 << 16)
   uint32_t* counts; // tiles touched, 0 when culled
+  uint32_t* runs;   // exact tiles only (else null): [kRowRuns] column runs of the first tile rows
 };
+// Column runs lo | hi << 16 (tile columns, below kRunUncut): the projection keeps the
+// exact runs of a record's first kRowRuns tile rows; an empty run is kRunEmpty (lo > hi);
+// kRunUncut marks a rectangle run that the binning still has to cut.
+constexpr int kRowRuns = 8;
+constexpr uint32_t kRunEmpty = 0x7FFFu;
+constexpr uint32_t kRunUncut = 0x8000u;
 
 // Heaviest-first tile order (k_tile_order) and the control words of the persistent
 // compositing kernels: kHeadFwd / kHeadBwd queue heads, kOverflow the capacity-overflow
@@ -272,9 +278,10 @@ hipError_t launch_scan_small(uint32_t* a, int count, unsigned long long* total, 
 // grid and buffers were sized for.
 // zero_rows (may be null): 2D-gradient rows (kGrad2D floats) zeroed for every visible record;
 // the first block also zeroes the first clear_words control words `ctrl`
+// rec.runs (exact tiles) gets each record's first kRowRuns exact row runs for extent exact_k
 hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru, int tile,
                           const Records& rec, uint2* blocksums, int nblk, float* zero_rows, uint32_t* ctrl,
-                          int clear_words, hipStream_t s);
+                          int clear_words, float exact_k, hipStream_t s);
 hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* totals, hipStream_t s);
 hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
                           const unsigned long long* pairs, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
@@ -288,16 +295,21 @@ hipError_t launch_tile_order(const uint2* ranges, const uint32_t* hint, int tota
 int ckpt_stride(int batch);
 int ckpt_per_tile(int batch);
 int64_t bwd_items_cap(int total_tiles, int batch);
+// Stable LSD radix sort of min(*count, cap) (key, value) pairs by their key_bits low bits
+// (at most 32; 8-bit passes); the result is in the _alt arrays when *result_in_alt.  hist
+// holds radix_hist_words(cap) words, digit_tot 256.
+int radix_hist_words(int64_t cap);
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                              uint32_t* hist, uint32_t* digit_tot, const unsigned long long* count, int64_t cap,
                              const uint32_t* overflow, int key_bits, bool* result_in_alt, int* passes, hipStream_t s,
                              Timer* tm);
 // Sizes of a binning plan for capacities (cap_vis, cap_M); pointers are left null.
 BinPlan bin_plan(const ViewTable& vt, int64_t cap_vis, int64_t cap_M);
-// exact_k > 0: per tile row only the columns the ellipse d^T Q d <= exact_k^2 reaches
+// exact_k > 0: per tile row only the columns the ellipse d^T Q d <= exact_k^2 reaches.
+// Uses the control words' overflow word.
 hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* dvals,
                       const unsigned long long* nvis, int64_t cap_vis, const BinPlan& plan, uint32_t* vals,
-                      uint2* ranges, uint32_t* overflow, float exact_k, int tile, hipStream_t s, Timer* tm);
+                      uint2* ranges, uint32_t* ctrl, float exact_k, int tile, hipStream_t s, Timer* tm);
 hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
                             const TileQueue& q, const Ckpt& ck, hipStream_t s);

@@ -321,26 +321,43 @@ __device__ __forceinline__ void conic_of(float a, float b, float c, float& A, fl
 // kernels compile with contraction off here), so the lists are reproducible bit for bit;
 // a degenerate conic or a NaN keeps the rectangle's columns.  False when the row keeps
 // no tile.
-__device__ __forceinline__ bool row_run(float mux, float muy, float A, float B, float C, float k, int ts, int ty,
-                                        int W, int H, int tx0, int tx1, int& lo, int& hi) {
+// The row-independent part of row_run: det_Q, the boundary's extreme offset B k / sqrt(C
+// det_Q) and A k^2; `whole` when the conic is degenerate (or a NaN): keep the rectangle.
+struct RowCut {
+  float dq, q, ak;
+  bool whole;
+};
+
+__device__ __forceinline__ RowCut row_cut(float A, float B, float C, float k) {
+#pragma clang fp contract(off)
+  RowCut r{};
+  r.dq = A * C - B * B;
+  r.whole = true;
+  if (!(r.dq > 0.f)) return r;
+  const float sq = __builtin_sqrtf(C * r.dq);
+  if (!(sq > 0.f)) return r;
+  r.q = (B * k) / sq;
+  r.ak = A * (k * k);
+  r.whole = false;
+  return r;
+}
+
+// row_run for tile row ty given the record's row_cut; ts = 1 << tshift
+__device__ __forceinline__ bool row_run_at(const RowCut& rc, float mux, float muy, float A, float B, int ts,
+                                           int tshift, int ty, int W, int H, int tx0, int tx1, int& lo, int& hi) {
 #pragma clang fp contract(off)
   lo = tx0;
   hi = tx1;
-  const float dq = A * C - B * B;
-  if (!(dq > 0.f)) return true;
-  const float sq = __builtin_sqrtf(C * dq);
-  if (!(sq > 0.f)) return true;
-  const float q = (B * k) / sq;
-  const float dyr = -q, dyl = q;
+  if (rc.whole) return true;
+  const float dyr = -rc.q, dyl = rc.q;
   const int ylast = min(ty * ts + ts - 1, H - 1);
   const float u0 = float(ty * ts) - muy;
   const float u1 = float(ylast) - muy;
   const float ur = fminf(fmaxf(dyr, u0), u1);
   const float ul = fminf(fmaxf(dyl, u0), u1);
-  const float ak = A * (k * k);
-  const float sr = __builtin_sqrtf(fmaxf(ak - dq * (ur * ur), 0.f));
+  const float sr = __builtin_sqrtf(fmaxf(rc.ak - rc.dq * (ur * ur), 0.f));
   const float xr = (sr - B * ur) / A;
-  const float sl = __builtin_sqrtf(fmaxf(ak - dq * (ul * ul), 0.f));
+  const float sl = __builtin_sqrtf(fmaxf(rc.ak - rc.dq * (ul * ul), 0.f));
   const float xl = ((-sl) - B * ul) / A;
   float pl = ceilf(mux + xl);
   float pr = floorf(mux + xr);
@@ -349,9 +366,15 @@ __device__ __forceinline__ bool row_run(float mux, float muy, float A, float B, 
   if (!(pl >= xa)) pl = xa;  // also a NaN
   if (!(pr <= xb)) pr = xb;
   if (!(pl <= pr)) return false;
-  lo = int(pl) / ts;
-  hi = int(pr) / ts;
+  lo = int(pl) >> tshift;  // pl, pr >= 0 here
+  hi = int(pr) >> tshift;
   return true;
+}
+
+__device__ __forceinline__ bool row_run(float mux, float muy, float A, float B, float C, float k, int ts, int ty,
+                                        int W, int H, int tx0, int tx1, int& lo, int& hi) {
+  return row_run_at(row_cut(A, B, C, k), mux, muy, A, B, ts, __builtin_ctz(unsigned(ts)), ty, W, H, tx0, tx1, lo,
+                    hi);
 }
 
 // Splat value a = o * exp(-q/2), q = A dx^2 + 2 B dx dy + C dy^2.  The compositing kernels
@@ -475,7 +498,8 @@ __device__ __forceinline__ void sh_grad_dot(float x, float y, float z, const flo
 template <int DEG>
 __global__ __launch_bounds__(kProjThreads) void k_project(GaussDev g, ViewTable vt, Rules ru, int tile,
                                                           Records rec, uint2* blocksums, int nblk,
-                                                          float* zero_rows, uint32_t* ctrl, int clear_words) {
+                                                          float* zero_rows, uint32_t* ctrl, int clear_words,
+                                                          float exact_k) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ uint32_t red[kProjThreads / 64];
   // the step's control words start at zero (no kernel before the projection reads them)
@@ -531,6 +555,23 @@ __global__ __launch_bounds__(kProjThreads) void k_project(GaussDev g, ViewTable 
         rec.r1[rid] = make_float4(C, op, pr.tz, 0.f);
         rec.rgb[rid] = make_float4(col[0], col[1], col[2], 0.f);
         rec.rect[rid] = make_uint2(uint32_t(tx0) | (uint32_t(tx1) << 16), uint32_t(ty0) | (uint32_t(ty1) << 16));
+        if (rec.runs) {  // exact tiles: the column runs of the first kRowRuns tile rows, once per record
+          const RowCut rc = row_cut(A, B, C, exact_k);
+          const int tshift = __builtin_ctz(unsigned(tile));
+          uint32_t rr[kRowRuns];
+#pragma unroll
+          for (int k = 0; k < kRowRuns; ++k) {
+            rr[k] = kRunEmpty;
+            if (k <= ty1 - ty0) {
+              int lo, hi;
+              if (row_run_at(rc, pr.mux, pr.muy, A, B, tile, tshift, ty0 + k, cam.W, cam.H, tx0, tx1, lo, hi))
+                rr[k] = uint32_t(lo) | (uint32_t(hi) << 16);
+            }
+          }
+          uint4* dst = reinterpret_cast<uint4*>(rec.runs + rid * kRowRuns);
+#pragma unroll
+          for (int k = 0; k < kRowRuns / 4; ++k) dst[k] = make_uint4(rr[4 * k], rr[4 * k + 1], rr[4 * k + 2], rr[4 * k + 3]);
+        }
         if (zero_rows) {  // the backward's 2D-gradient row of this record starts at zero
           float4* z = reinterpret_cast<float4*>(zero_rows + rid * kGrad2D);
           z[0] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -651,29 +692,47 @@ __global__ __launch_bounds__(kProjThreads) void k_compact(int64_t n, Records rec
 }
 
 // ------------------------------------------------------------------------------------
-// K4: stable LSD radix sort of (u32 key, u32 value), 8-bit digits, count read from the
-// device (clamped to the capacity the grid was sized for).  Per pass:
-//   hist:    per-block digit histograms, stored digit-major [256][nblk]
+// K4: stable LSD radix sort of (u32 key, u32 value) by digits of BITS bits, count read
+// from the device (clamped to the capacity the grid was sized for).  Per pass:
+//   hist:    per-block digit histograms, stored digit-major [2^BITS][nblk]
 //   rowscan: one block per digit scans its row -> start of each block in that digit,
 //            and the digit total
 //   scatter: each block ranks its keys stably (wavefront multisplit by ballots, then
 //            across the four wavefronts through LDS) and writes them to their slots
 // ------------------------------------------------------------------------------------
+// 8-bit digits: wider ones (11 bits, three passes for a depth key) ran slower on MI355X,
+// their digit-major histograms being written and read across many more cache lines
+constexpr int kSortBits = 8;
+
+// Block b of a grid of G blocks (G a multiple of 8) as index (b mod 8) * (G / 8) + b / 8:
+// the hardware hands consecutive blocks to the eight XCDs in turn, so with this index
+// consecutive key tiles and record chunks run on one XCD, and the strided count words
+// they share meet in that XCD's L2.  (Only for even work: the row-list segments stay
+// round-robin, as a contiguous range of rows would load some XCDs far more than others.)
+__device__ __forceinline__ int xcd_block(int b, int G) { return (b & 7) * (G >> 3) + (b >> 3); }
+static int xcd_grid(int64_t blocks) { return int((blocks + 7) / 8 * 8); }
+
+
+template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* keys, const unsigned long long* count,
                                                              int64_t cap, const uint32_t* overflow, int shift,
                                                              uint32_t* hist, int nblk) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  constexpr int D = 1 << BITS;
+  constexpr uint32_t MASK = D - 1;
+  __shared__ uint32_t h[D];
+  const int tb = xcd_block(blockIdx.x, gridDim.x);  // this block's tile of keys
+  if (tb >= nblk) return;                            // block-uniform
+  for (int d = threadIdx.x; d < D; d += kSortThreads) h[d] = 0;
   __syncthreads();
   const int64_t M = clamp_count(count, cap, overflow);
-  const int64_t base = int64_t(blockIdx.x) * kSortTile;
+  const int64_t base = int64_t(tb) * kSortTile;
 #pragma unroll 4
   for (int i = 0; i < kSortItems; ++i) {
     const int64_t idx = base + i * kSortThreads + threadIdx.x;
-    if (idx < M) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+    if (idx < M) atomicAdd(&h[(keys[idx] >> shift) & MASK], 1u);
   }
   __syncthreads();
-  hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < D; d += kSortThreads) hist[int64_t(d) * nblk + tb] = h[d];
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* hist, int nblk, uint32_t* digit_tot) {
@@ -695,27 +754,53 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_rowscan(uint32_t* hist, 
   if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
+template <int BITS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* kin, const uint32_t* vin,
                                                                 uint32_t* kout, uint32_t* vout,
                                                                 const unsigned long long* count, int64_t cap,
                                                                 const uint32_t* overflow, int shift,
                                                                 const uint32_t* hist, const uint32_t* digit_tot,
                                                                 int nblk) {
-  // bases and per-wavefront counters are double buffered so each round needs two barriers
-  __shared__ uint32_t base[2][256];
-  __shared__ uint32_t wcnt[2][kSortThreads / 64][256];
-  __shared__ uint32_t red[kSortThreads / 64];
+  constexpr int D = 1 << BITS;
+  constexpr int DPT = D / kSortThreads;  // digits per thread
+  constexpr int NW = kSortThreads / 64;
+  constexpr uint32_t MASK = D - 1;
+  static_assert(D % kSortThreads == 0, "whole digits per thread");
+  // bases and per-wavefront counters are double buffered so each round needs two barriers;
+  // a round's counts and offsets are below kSortThreads, so 16 bits hold them
+  __shared__ uint32_t base[2][D];
+  __shared__ uint16_t wcnt[2][NW][D];
+  __shared__ uint32_t red[NW];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int tb = xcd_block(blockIdx.x, gridDim.x);  // this block's tile of keys
+  if (tb >= nblk) return;                            // block-uniform
   const int64_t M = clamp_count(count, cap, overflow);
-  const uint32_t ex = block_exclusive_scan_u32(digit_tot[t], red);
-  base[0][t] = ex + hist[int64_t(t) * nblk + blockIdx.x];
+  // first slot of each digit: thread t scans digits t * DPT .. t * DPT + DPT - 1
+  {
+    uint32_t tot[DPT], sum = 0;
 #pragma unroll
-  for (int i = 0; i < kSortThreads / 64; ++i) {
-    wcnt[0][i][t] = 0;
-    wcnt[1][i][t] = 0;
+    for (int j = 0; j < DPT; ++j) {
+      tot[j] = digit_tot[t * DPT + j];
+      sum += tot[j];
+    }
+    uint32_t run = block_exclusive_scan_u32(sum, red);
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      const int d = t * DPT + j;
+      base[0][d] = run + hist[int64_t(d) * nblk + tb];
+      run += tot[j];
+    }
   }
+  // the per-round work below takes digits t + kSortThreads j (consecutive lanes, banks)
+#pragma unroll
+  for (int j = 0; j < DPT; ++j)
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      wcnt[0][i][t + kSortThreads * j] = 0;
+      wcnt[1][i][t + kSortThreads * j] = 0;
+    }
   __syncthreads();
-  const int64_t b0 = int64_t(blockIdx.x) * kSortTile;
+  const int64_t b0 = int64_t(tb) * kSortTile;
   const uint64_t lt_mask = (1ull << lane) - 1ull;
   for (int r = 0; r < kSortItems; ++r) {
     const int b = r & 1;
@@ -725,28 +810,32 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
     if (valid) {
       key = kin[idx];
       val = vin[idx];
-      d = (key >> shift) & 255u;
+      d = (key >> shift) & MASK;
     }
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
+    for (int bit = 0; bit < BITS; ++bit) {
       const bool on = (d >> bit) & 1u;
       const uint64_t m = __ballot(on);
       peers &= on ? m : ~m;
     }
     const uint32_t rank = __popcll(peers & lt_mask);
-    if (valid && rank == 0) wcnt[b][w][d] = __popcll(peers);
+    if (valid && rank == 0) wcnt[b][w][d] = uint16_t(__popcll(peers));
     __syncthreads();
-    // digit t: offsets of the four wavefronts, next round's base, clear next round's counters
-    uint32_t run = 0;
+    // per digit: offsets of the four wavefronts, next round's base, clear next round's counters
 #pragma unroll
-    for (int i = 0; i < kSortThreads / 64; ++i) {
-      const uint32_t c = wcnt[b][i][t];
-      wcnt[b][i][t] = run;
-      run += c;
-      wcnt[b ^ 1][i][t] = 0;
+    for (int j = 0; j < DPT; ++j) {
+      const int dd = t + kSortThreads * j;
+      uint32_t run = 0;
+#pragma unroll
+      for (int i = 0; i < NW; ++i) {
+        const uint32_t c = wcnt[b][i][dd];
+        wcnt[b][i][dd] = uint16_t(run);
+        run += c;
+        wcnt[b ^ 1][i][dd] = 0;
+      }
+      base[b ^ 1][dd] = base[b][dd] + run;
     }
-    base[b ^ 1][t] = base[b][t] + run;
     __syncthreads();
     if (valid) {
       const uint32_t dst = base[b][d] + wcnt[b][w][d] + rank;
@@ -758,9 +847,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
 
 // ------------------------------------------------------------------------------------
 // Device-wide exclusive scan of u32 counts, in place: per-block sums, one block scans the
-// sums (k_scan_u32), then each block scans its 4096 elements from its base.  The element
-// count is read from the device (clamped to the capacity the grid was sized for) when
-// `count` is given.
+// sums (k_scan_u32), then each block scans its kScanTile elements from its base.  The
+// element count is read from the device (clamped to the capacity the grid was sized for)
+// when `count` is given.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ int64_t scan_len(int64_t cap, const unsigned long long* count) {
   if (!count) return cap;
@@ -850,16 +939,47 @@ __device__ __forceinline__ uint32_t view_of_record(const ViewTable& vt, uint32_t
   return vt.nviews == 1 ? 0u : rid / uint32_t(n);
 }
 
+// The column run of a row entry: for (record, rect columns) `entry` in its k-th tile row,
+// with exact tiles the run the projection kept (rr, loaded by load_row_runs before the
+// row walk) for k < kRowRuns and past those rows the rectangle's columns marked kRunUncut,
+// so that stage 2 cuts them; without exact tiles the rectangle's columns.
+__device__ __forceinline__ uint32_t row_entry_run(const Records& rec, uint2 entry, const uint32_t (&rr)[kRowRuns],
+                                                  uint32_t k) {
+  if (!rec.runs) return entry.y;
+  uint32_t r = entry.y | kRunUncut;
+#pragma unroll
+  for (int j = 0; j < kRowRuns; ++j)
+    if (k == uint32_t(j)) r = rr[j];
+  return r;
+}
+
+__device__ __forceinline__ void load_row_runs(const Records& rec, uint2 entry, bool valid, uint32_t (&rr)[kRowRuns]) {
+#pragma unroll
+  for (int j = 0; j < kRowRuns; ++j) rr[j] = 0u;
+  if (!rec.runs || !valid) return;
+  const uint4* src = reinterpret_cast<const uint4*>(rec.runs + int64_t(entry.x) * kRowRuns);
+#pragma unroll
+  for (int j = 0; j < kRowRuns / 4; ++j) {
+    const uint4 q = src[j];
+    rr[4 * j] = q.x;
+    rr[4 * j + 1] = q.y;
+    rr[4 * j + 2] = q.z;
+    rr[4 * j + 3] = q.w;
+  }
+}
+
 // stage 1 counts: tile-row histogram of one chunk of depth-sorted records
 __global__ __launch_bounds__(256) void k_bin_rows_count(ViewTable vt, int64_t n, Records rec, const uint32_t* dvals,
                                                         const unsigned long long* nvis, int64_t cap_vis,
                                                         const uint32_t* overflow, BinPlan plan) {
   extern __shared__ uint32_t hist[];
   const int R = plan.rows;
+  const int chunk = xcd_block(blockIdx.x, gridDim.x);
+  if (chunk >= plan.nch1) return;  // block-uniform
   for (int i = threadIdx.x; i < R; i += 256) hist[i] = 0;
   __syncthreads();
   const int64_t NV = clamp_count(nvis, cap_vis, overflow);
-  const int64_t beg = int64_t(blockIdx.x) * 64 * plan.rounds1;
+  const int64_t beg = int64_t(chunk) * 64 * plan.rounds1;
   const int64_t end = min(NV, beg + int64_t(64) * plan.rounds1);
   for (int64_t i = beg + threadIdx.x; i < end; i += 256) {
     const uint32_t rid = dvals[i];
@@ -869,7 +989,7 @@ __global__ __launch_bounds__(256) void k_bin_rows_count(ViewTable vt, int64_t n,
     for (int y = y0; y <= y1; ++y) atomicAdd(&hist[y], 1u);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < R; i += 256) plan.cnt1[int64_t(i) * plan.nch1 + blockIdx.x] = hist[i];
+  for (int i = threadIdx.x; i < R; i += 256) plan.cnt1[int64_t(i) * plan.nch1 + chunk] = hist[i];
 }
 
 // stage 1 placement: one wavefront per chunk writes (record, column run) entries into the
@@ -900,13 +1020,16 @@ __global__ __launch_bounds__(64) void k_bin_rows_scatter(ViewTable vt, int64_t n
       hi = min(uint32_t(ro) + (rc.y >> 16), uint32_t(R - 1));
       entry = make_uint2(rid, rc.x);
     }
+    const uint32_t first = cur;
+    uint32_t rr[kRowRuns];
+    load_row_runs(rec, entry, cur != 0xFFFFFFFFu, rr);
     for (uint32_t y = wave_min_u32(cur); y != 0xFFFFFFFFu; y = wave_min_u32(cur)) {
       const bool on = cur == y;
       const uint64_t m = __ballot(on);
       const uint32_t base = next[y];
       if (on) {
         const uint32_t dst = base + uint32_t(__popcll(m & lt_mask));
-        if (int64_t(dst) < plan.cap_M) plan.rowlist[dst] = entry;
+        if (int64_t(dst) < plan.cap_M) plan.rowlist[dst] = make_uint2(entry.x, row_entry_run(rec, entry, rr, y - first));
         cur = cur < hi ? cur + 1u : 0xFFFFFFFFu;
       }
       if (lane == 0) next[y] = base + uint32_t(__popcll(m));
@@ -914,23 +1037,50 @@ __global__ __launch_bounds__(64) void k_bin_rows_scatter(ViewTable vt, int64_t n
   }
 }
 
+// Next free slot of bin b when the slots of bins lane + 64 k sit in register k of that
+// lane, and its update by the c entries just placed: readlanes and selects only, so the
+// walks over bins carry no branches.
+template <int NREG>
+__device__ __forceinline__ uint32_t slot_of(const uint32_t (&nx)[NREG], uint32_t b) {
+  const int src = int(b & 63u), kb = int(b >> 6);
+  uint32_t base = uint32_t(__builtin_amdgcn_readlane(int(nx[0]), src));
+#pragma unroll
+  for (int k = 1; k < NREG; ++k) {
+    const uint32_t v = uint32_t(__builtin_amdgcn_readlane(int(nx[k]), src));
+    base = kb == k ? v : base;
+  }
+  return base;
+}
+
+template <int NREG>
+__device__ __forceinline__ void take_slots(uint32_t (&nx)[NREG], uint32_t b, uint32_t c, int lane) {
+  const uint32_t add = lane == int(b & 63u) ? c : 0u;
+  const int kb = int(b >> 6);
+#pragma unroll
+  for (int k = 0; k < NREG; ++k) nx[k] += kb == k ? add : 0u;
+}
+
 // The same placement with the rows' next free slots in registers (row lane + 64 k in
 // register k of that lane, read with readlane) for at most 64 * NREG rows: each round
 // walks the rows from the wavefront's lowest to its highest with one ballot per row.
+// Four wavefronts per block, each with its own chunk (blocks of one wavefront were held
+// back by the per-CU workgroup limit).
 template <int NREG>
-__global__ __launch_bounds__(64) void k_bin_rows_scatter_r(ViewTable vt, int64_t n, Records rec,
-                                                           const uint32_t* dvals, const unsigned long long* nvis,
-                                                           int64_t cap_vis, const uint32_t* overflow, BinPlan plan) {
+__global__ __launch_bounds__(256) void k_bin_rows_scatter_r(ViewTable vt, int64_t n, Records rec,
+                                                            const uint32_t* dvals, const unsigned long long* nvis,
+                                                            int64_t cap_vis, const uint32_t* overflow, BinPlan plan) {
   const int R = plan.rows;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int chunk = int(blockIdx.x) * 4 + int(threadIdx.x >> 6);  // one chunk per wavefront
   const int64_t NV = clamp_count(nvis, cap_vis, overflow);
-  const int64_t beg = int64_t(blockIdx.x) * 64 * plan.rounds1;
-  if (beg >= NV) return;
+  const int64_t beg = int64_t(chunk) * 64 * plan.rounds1;
+  if (chunk >= plan.nch1 || beg >= NV) return;
+  const uint32_t cap = uint32_t(min<int64_t>(plan.cap_M, int64_t(0xFFFFFFFFu)));
   uint32_t nx[NREG];
 #pragma unroll
   for (int k = 0; k < NREG; ++k) {
     const int y = lane + 64 * k;
-    nx[k] = valu_copy(y < R ? plan.cnt1[int64_t(y) * plan.nch1 + blockIdx.x] : 0u);
+    nx[k] = valu_copy(y < R ? plan.cnt1[int64_t(y) * plan.nch1 + chunk] : 0u);
   }
   const uint64_t lt_mask = (1ull << lane) - 1ull;
   for (int r = 0; r < plan.rounds1; ++r) {
@@ -948,26 +1098,18 @@ __global__ __launch_bounds__(64) void k_bin_rows_scatter_r(ViewTable vt, int64_t
       if (lo > hi) lo = 0xFFFFFFFFu;
       entry = make_uint2(rid, rc.x);
     }
+    const uint32_t first = lo;
+    uint32_t rr[kRowRuns];
+    load_row_runs(rec, entry, lo != 0xFFFFFFFFu, rr);
     const uint32_t y0 = wave_min_u32(lo);
     if (y0 == 0xFFFFFFFFu) continue;
     const uint32_t y1 = uint32_t(__builtin_amdgcn_readfirstlane(int(wave_max_u32(lo != 0xFFFFFFFFu ? hi : 0u))));
-    for (uint32_t y = y0; y <= y1; ++y) {
+    for (uint32_t y = y0; y <= y1; ++y) {  // branch-free but for the store
       const bool on = lo <= y && y <= hi;
       const uint64_t m = __ballot(on);
-      if (!m) continue;
-      const int src = int(y & 63u), ky = int(y >> 6);
-      uint32_t base = 0;
-#pragma unroll
-      for (int k = 0; k < NREG; ++k)
-        if (k == ky) base = uint32_t(__builtin_amdgcn_readlane(int(nx[k]), src));
-      if (on) {
-        const uint32_t dst = base + uint32_t(__popcll(m & lt_mask));
-        if (int64_t(dst) < plan.cap_M) plan.rowlist[dst] = entry;
-      }
-      const uint32_t c = uint32_t(__popcll(m));
-#pragma unroll
-      for (int k = 0; k < NREG; ++k)
-        if (k == ky && lane == src) nx[k] += c;
+      const uint32_t dst = slot_of(nx, y) + uint32_t(__popcll(m & lt_mask));
+      if (on && dst < cap) plan.rowlist[dst] = make_uint2(entry.x, row_entry_run(rec, entry, rr, y - first));
+      take_slots(nx, y, uint32_t(__popcll(m)), lane);
     }
   }
 }
@@ -1052,21 +1194,26 @@ __device__ __forceinline__ Segment segment_of(const ViewTable& vt, const BinPlan
   return g;
 }
 
-// stage 2 counts: tile-column histogram of one segment of a row list.  With exact tiles
-// (exact_k > 0) each entry's column run is first cut to the columns its ellipse reaches in
-// this row (row_run) and written back, so the placement below sees the same run; a row
-// the ellipse misses keeps an empty run (lo > hi).
+// stage 2 counts: tile-column histogram of one segment of a row list, one wavefront per
+// segment (its own LDS histogram of hist_stride words).  With exact tiles the runs of a
+// record's first kRowRuns rows arrive cut by the projection; a run marked kRunUncut (a
+// later row of a tall splat) is cut here to the columns its ellipse reaches in this row
+// (row_run) and written back, so the placement below sees the same run; a row the
+// ellipse misses gets the empty run kRunEmpty (lo > hi).
 __global__ __launch_bounds__(256) void k_bin_tiles_count(ViewTable vt, BinPlan plan, Records rec, float exact_k,
-                                                         int tile) {
-  extern __shared__ uint32_t hist[];
+                                                         int tile, int hist_stride) {
+  extern __shared__ uint32_t hist_all[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t* hist = hist_all + wv * hist_stride;
   const unsigned long long S = plan.words[1];
-  for (uint32_t s = blockIdx.x; s < S; s += gridDim.x) {
+  for (uint32_t s = blockIdx.x * 4u + uint32_t(wv); s < S; s += gridDim.x * 4u) {
     const Segment g = segment_of(vt, plan, s);
-    for (int i = threadIdx.x; i < g.tiles_x; i += 256) hist[i] = 0;
-    __syncthreads();
-    for (uint32_t i = g.beg + threadIdx.x; i < g.end; i += 256) {
+    for (int i = lane; i < g.tiles_x; i += 64) hist[i] = 0;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t i = g.beg + lane; i < g.end; i += 64) {
       uint32_t cx = plan.rowlist[i].y;
-      if (exact_k > 0.f) {
+      if (cx & kRunUncut) {
+        cx &= ~kRunUncut;
         const uint32_t rid = plan.rowlist[i].x;
         const ViewDev& cam = vt.v[view_of_row(vt, uint32_t(g.row))];
         const float4 sp = rec.r0[rid];  // centre and conic A, B
@@ -1074,22 +1221,47 @@ __global__ __launch_bounds__(256) void k_bin_tiles_count(ViewTable vt, BinPlan p
         int lo, hi;
         const bool any = row_run(sp.x, sp.y, sp.z, sp.w, cc, exact_k, tile, g.row - cam.row_off, cam.W, cam.H,
                                  int(cx & 0xFFFFu), int(cx >> 16), lo, hi);
-        cx = any ? uint32_t(lo) | (uint32_t(hi) << 16) : 0xFFFFu;
+        cx = any ? uint32_t(lo) | (uint32_t(hi) << 16) : kRunEmpty;
         plan.rowlist[i].y = cx;
       }
       const int x0 = int(cx & 0xFFFFu), x1 = min(int(cx >> 16), g.tiles_x - 1);
       for (int x = x0; x <= x1; ++x) atomicAdd(&hist[x], 1u);
     }
-    __syncthreads();
-    for (int x = threadIdx.x; x < g.tiles_x; x += 256) plan.cntF[g.flat + uint32_t(x) * g.nseg] = hist[x];
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
+    for (int x = lane; x < g.tiles_x; x += 64) plan.cntF[g.flat + uint32_t(x) * g.nseg] = hist[x];
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
-// stage 2 placement: one wavefront per segment writes record ids into the tile lists
-__global__ __launch_bounds__(64) void k_bin_tiles_scatter(ViewTable vt, BinPlan plan, uint32_t* vals) {
+// [start, end) of tile t from the flat scan; empty tiles are [0, 0)
+__device__ __forceinline__ uint2 tile_range(const ViewTable& vt, const BinPlan& plan, const uint32_t* overflow,
+                                            int t) {
+  if (*overflow) return make_uint2(0u, 0u);  // nothing was binned
+  const ViewDev& cam = vt.v[view_of_tile(vt, t)];
+  const int local = t - cam.tile_off;
+  const int r = cam.row_off + local / cam.tiles_x, x = local % cam.tiles_x;
+  const uint4 info = plan.rowinfo[r];
+  const uint32_t S2 = 64u * uint32_t(plan.rounds2);
+  const uint32_t nseg = (info.y + S2 - 1) / S2;
+  uint2 out = make_uint2(0u, 0u);
+  if (nseg) {
+    const unsigned long long F = plan.words[2];
+    const uint32_t idx = info.w + uint32_t(x) * nseg;
+    const uint32_t a = plan.cntF[idx];
+    const uint32_t b = (unsigned long long)(idx + nseg) < F ? plan.cntF[idx + nseg] : uint32_t(plan.words[3]);
+    if (b > a) out = make_uint2(a, b);
+  }
+  return out;
+}
+
+// stage 2 placement: one wavefront per segment writes record ids into the tile lists; the
+// blocks first write the tile ranges (grid-stride over the tiles)
+__global__ __launch_bounds__(64) void k_bin_tiles_scatter(ViewTable vt, BinPlan plan, uint32_t* vals,
+                                                          const uint32_t* overflow, uint2* ranges) {
   extern __shared__ uint32_t next[];  // next free slot of each tile for this segment
   const int lane = threadIdx.x;
+  for (int t = int(blockIdx.x) * 64 + lane; t < vt.total_tiles; t += int(gridDim.x) * 64)
+    ranges[t] = tile_range(vt, plan, overflow, t);
   const uint64_t lt_mask = (1ull << lane) - 1ull;
   const unsigned long long S = plan.words[1];
   for (uint32_t s = blockIdx.x; s < S; s += gridDim.x) {
@@ -1123,13 +1295,19 @@ __global__ __launch_bounds__(64) void k_bin_tiles_scatter(ViewTable vt, BinPlan 
 }
 
 // The same placement with the tiles' next free slots in registers (column lane + 64 k
-// in register k of that lane) for rows of at most 64 * NREG tiles.
+// in register k of that lane) for rows of at most 64 * NREG tiles; four wavefronts per
+// block, each with its own segments.
 template <int NREG>
-__global__ __launch_bounds__(64) void k_bin_tiles_scatter_r(ViewTable vt, BinPlan plan, uint32_t* vals) {
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(256) void k_bin_tiles_scatter_r(ViewTable vt, BinPlan plan, uint32_t* vals,
+                                                             const uint32_t* overflow, uint2* ranges) {
+  const int lane = threadIdx.x & 63;
+  for (int t = int(blockIdx.x) * 256 + int(threadIdx.x); t < vt.total_tiles; t += int(gridDim.x) * 256)
+    ranges[t] = tile_range(vt, plan, overflow, t);
   const uint64_t lt_mask = (1ull << lane) - 1ull;
+  const uint32_t cap = uint32_t(min<int64_t>(plan.cap_M, int64_t(0xFFFFFFFFu)));
   const unsigned long long S = plan.words[1];
-  for (uint32_t s = blockIdx.x; s < S; s += gridDim.x) {
+  // a segment per wavefront
+  for (uint32_t s = blockIdx.x * 4u + (threadIdx.x >> 6); s < S; s += gridDim.x * 4u) {
     const Segment g = segment_of(vt, plan, s);
     uint32_t nx[NREG];
 #pragma unroll
@@ -1150,52 +1328,16 @@ __global__ __launch_bounds__(64) void k_bin_tiles_scatter_r(ViewTable vt, BinPla
       const uint32_t x0 = wave_min_u32(lo);
       if (x0 == 0xFFFFFFFFu) continue;
       const uint32_t x1 = uint32_t(__builtin_amdgcn_readfirstlane(int(wave_max_u32(lo != 0xFFFFFFFFu ? hi : 0u))));
-      for (uint32_t x = x0; x <= x1; ++x) {
+      for (uint32_t x = x0; x <= x1; ++x) {  // branch-free but for the store
         const bool on = lo <= x && x <= hi;
         const uint64_t m = __ballot(on);
-        if (!m) continue;
-        const int src = int(x & 63u), kx = int(x >> 6);
-        uint32_t base = 0;
-#pragma unroll
-        for (int k = 0; k < NREG; ++k)
-          if (k == kx) base = uint32_t(__builtin_amdgcn_readlane(int(nx[k]), src));
-        if (on) {
-          const uint32_t dst = base + uint32_t(__popcll(m & lt_mask));
-          if (int64_t(dst) < plan.cap_M) vals[dst] = rid;
-        }
-        const uint32_t c = uint32_t(__popcll(m));
-#pragma unroll
-        for (int k = 0; k < NREG; ++k)
-          if (k == kx && lane == src) nx[k] += c;
+        const uint32_t base = slot_of(nx, x);
+        const uint32_t dst = base + uint32_t(__popcll(m & lt_mask));
+        if (on && dst < cap) vals[dst] = rid;
+        take_slots(nx, x, uint32_t(__popcll(m)), lane);
       }
     }
   }
-}
-
-// K5: [start, end) of every tile from the flat scan; empty tiles are [0, 0)
-__global__ __launch_bounds__(256) void k_bin_ranges(ViewTable vt, BinPlan plan, const uint32_t* overflow,
-                                                    uint2* ranges) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= vt.total_tiles) return;
-  if (*overflow) {  // nothing was binned
-    ranges[t] = make_uint2(0u, 0u);
-    return;
-  }
-  const ViewDev& cam = vt.v[view_of_tile(vt, t)];
-  const int local = t - cam.tile_off;
-  const int r = cam.row_off + local / cam.tiles_x, x = local % cam.tiles_x;
-  const uint4 info = plan.rowinfo[r];
-  const uint32_t S2 = 64u * uint32_t(plan.rounds2);
-  const uint32_t nseg = (info.y + S2 - 1) / S2;
-  uint2 out = make_uint2(0u, 0u);
-  if (nseg) {
-    const unsigned long long F = plan.words[2];
-    const uint32_t idx = info.w + uint32_t(x) * nseg;
-    const uint32_t a = plan.cntF[idx];
-    const uint32_t b = (unsigned long long)(idx + nseg) < F ? plan.cntF[idx + nseg] : uint32_t(plan.words[3]);
-    if (b > a) out = make_uint2(a, b);
-  }
-  ranges[t] = out;
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
@@ -2059,15 +2201,15 @@ inline unsigned blocks_for(int64_t n, int per) { return unsigned((n + per - 1) /
 // ------------------------------------------------------------------------------------
 hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru, int tile,
                           const Records& rec, uint2* blocksums, int nblk, float* zero_rows, uint32_t* ctrl,
-                          int clear_words, hipStream_t s) {
+                          int clear_words, float exact_k, hipStream_t s) {
   if (nblk == 0) return hipSuccess;
   dim3 grid(nblk), block(kProjThreads);
   const int cw = clear_words;
   switch (deg) {
-    case 0: k_project<0><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl, cw); break;
-    case 1: k_project<1><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl, cw); break;
-    case 2: k_project<2><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl, cw); break;
-    default: k_project<3><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl, cw); break;
+    case 0: k_project<0><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl, cw, exact_k); break;
+    case 1: k_project<1><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl, cw, exact_k); break;
+    case 2: k_project<2><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl, cw, exact_k); break;
+    default: k_project<3><<<grid, block, 0, s>>>(g, vt, ru, tile, rec, blocksums, nblk, zero_rows, ctrl, cw, exact_k); break;
   }
   return hipGetLastError();
 }
@@ -2091,11 +2233,29 @@ hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2*
   return hipGetLastError();
 }
 
+template <int BITS>
+static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, uint32_t* hist,
+                       uint32_t* digit_tot, const unsigned long long* count, int64_t cap, const uint32_t* overflow,
+                       int shift, int nblk, hipStream_t s, Timer* tm) {
+  if (tm) tm->begin(K_RADIX_HIST);
+  k_radix_hist<BITS><<<xcd_grid(nblk), kSortThreads, 0, s>>>(kin, count, cap, overflow, shift, hist, nblk);
+  if (tm) tm->end(K_RADIX_HIST);
+  if (tm) tm->begin(K_RADIX_ROWSCAN);
+  k_radix_rowscan<<<1 << BITS, kSortThreads, 0, s>>>(hist, nblk, digit_tot);
+  if (tm) tm->end(K_RADIX_ROWSCAN);
+  if (tm) tm->begin(K_RADIX_SCATTER);
+  k_radix_scatter<BITS><<<xcd_grid(nblk), kSortThreads, 0, s>>>(kin, vin, kout, vout, count, cap, overflow, shift, hist,
+                                                      digit_tot, nblk);
+  if (tm) tm->end(K_RADIX_SCATTER);
+}
+
+int radix_hist_words(int64_t cap) { return int((cap + kSortTile - 1) / kSortTile) << kSortBits; }
+
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                              uint32_t* hist, uint32_t* digit_tot, const unsigned long long* count, int64_t cap,
                              const uint32_t* overflow, int key_bits, bool* result_in_alt, int* passes, hipStream_t s,
                              Timer* tm) {
-  const int np = (key_bits + 7) / 8;
+  const int np = (key_bits + kSortBits - 1) / kSortBits;
   *passes = 0;
   *result_in_alt = false;
   if (cap <= 1 || np == 0) return hipSuccess;
@@ -2106,17 +2266,7 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
   uint32_t* kout = keys_alt;
   uint32_t* vout = vals_alt;
   for (int p = 0; p < np; ++p) {
-    const int shift = 8 * p;
-    if (tm) tm->begin(K_RADIX_HIST);
-    k_radix_hist<<<nblk, kSortThreads, 0, s>>>(kin, count, cap, overflow, shift, hist, nblk);
-    if (tm) tm->end(K_RADIX_HIST);
-    if (tm) tm->begin(K_RADIX_ROWSCAN);
-    k_radix_rowscan<<<256, kSortThreads, 0, s>>>(hist, nblk, digit_tot);
-    if (tm) tm->end(K_RADIX_ROWSCAN);
-    if (tm) tm->begin(K_RADIX_SCATTER);
-    k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(kin, vin, kout, vout, count, cap, overflow, shift, hist, digit_tot,
-                                                  nblk);
-    if (tm) tm->end(K_RADIX_SCATTER);
+    radix_pass<kSortBits>(kin, vin, kout, vout, hist, digit_tot, count, cap, overflow, kSortBits * p, nblk, s, tm);
     std::swap(kin, kout);
     std::swap(vin, vout);
   }
@@ -2154,7 +2304,7 @@ static void scan_u32(uint32_t* a, int64_t cap, const unsigned long long* count, 
 
 hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* dvals,
                       const unsigned long long* nvis, int64_t cap_vis, const BinPlan& plan, uint32_t* vals,
-                      uint2* ranges, uint32_t* overflow, float exact_k, int tile, hipStream_t s, Timer* tm) {
+                      uint2* ranges, uint32_t* ctrl, float exact_k, int tile, hipStream_t s, Timer* tm) {
   if (vt.total_tiles == 0) return hipSuccess;
   if (cap_vis == 0 || plan.cap_M == 0 || plan.rows == 0) {
     k_fill_u32<<<blocks_for(int64_t(vt.total_tiles) * 2, 256), 256, 0, s>>>(reinterpret_cast<uint32_t*>(ranges), 0u,
@@ -2163,45 +2313,45 @@ hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const 
   }
   auto B = [&](int k) { if (tm) tm->begin(k); };
   auto E = [&](int k) { if (tm) tm->end(k); };
+  uint32_t* overflow = ctrl + kOverflow;
   const size_t lds_rows = size_t(plan.rows) * 4, lds_cols = size_t(vt.max_tiles_x) * 4;
-  const int g_count = int(std::min<int64_t>(plan.cap_seg, 16384));
+  const int64_t n1 = int64_t(plan.rows) * plan.nch1;
+  const int g_count = int(std::min<int64_t>((plan.cap_seg + 3) / 4, 4096));
   const int g_scatter = int(std::min<int64_t>(plan.cap_seg, 16384));
+  const int g_scatter4 = int(std::min<int64_t>((plan.cap_seg + 3) / 4, 4096));
   B(K_BIN_COUNT);
-  k_bin_rows_count<<<plan.nch1, 256, lds_rows, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
+  k_bin_rows_count<<<xcd_grid(plan.nch1), 256, lds_rows, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
   E(K_BIN_COUNT);
   B(K_BIN_SCAN);
-  scan_u32(plan.cnt1, int64_t(plan.rows) * plan.nch1, nullptr, plan.part, plan.words, s);
+  scan_u32(plan.cnt1, n1, nullptr, plan.part, plan.words, s);
   k_bin_rows_meta<<<1, 1024, 0, s>>>(vt, plan, overflow);
   E(K_BIN_SCAN);
   B(K_BIN_SCATTER);
   if (plan.rows <= 64)
-    k_bin_rows_scatter_r<1><<<plan.nch1, 64, 0, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
+    k_bin_rows_scatter_r<1><<<(plan.nch1 + 3) / 4, 256, 0, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
   else if (plan.rows <= 128)
-    k_bin_rows_scatter_r<2><<<plan.nch1, 64, 0, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
+    k_bin_rows_scatter_r<2><<<(plan.nch1 + 3) / 4, 256, 0, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
   else if (plan.rows <= 256)
-    k_bin_rows_scatter_r<4><<<plan.nch1, 64, 0, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
+    k_bin_rows_scatter_r<4><<<(plan.nch1 + 3) / 4, 256, 0, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
   else
     k_bin_rows_scatter<<<plan.nch1, 64, lds_rows, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
   E(K_BIN_SCATTER);
   B(K_BIN_COUNT);
-  k_bin_tiles_count<<<g_count, 256, lds_cols, s>>>(vt, plan, rec, exact_k, tile);
+  k_bin_tiles_count<<<g_count, 256, 4 * lds_cols, s>>>(vt, plan, rec, exact_k, tile, vt.max_tiles_x);
   E(K_BIN_COUNT);
   B(K_BIN_SCAN);
   scan_u32(plan.cntF, plan.cap_flat, plan.words + 2, plan.part, plan.words + 3, s);
   E(K_BIN_SCAN);
   B(K_BIN_SCATTER);
   if (vt.max_tiles_x <= 64)
-    k_bin_tiles_scatter_r<1><<<g_scatter, 64, 0, s>>>(vt, plan, vals);
+    k_bin_tiles_scatter_r<1><<<g_scatter4, 256, 0, s>>>(vt, plan, vals, overflow, ranges);
   else if (vt.max_tiles_x <= 128)
-    k_bin_tiles_scatter_r<2><<<g_scatter, 64, 0, s>>>(vt, plan, vals);
+    k_bin_tiles_scatter_r<2><<<g_scatter4, 256, 0, s>>>(vt, plan, vals, overflow, ranges);
   else if (vt.max_tiles_x <= 256)
-    k_bin_tiles_scatter_r<4><<<g_scatter, 64, 0, s>>>(vt, plan, vals);
+    k_bin_tiles_scatter_r<4><<<g_scatter4, 256, 0, s>>>(vt, plan, vals, overflow, ranges);
   else
-    k_bin_tiles_scatter<<<g_scatter, 64, lds_cols, s>>>(vt, plan, vals);
+    k_bin_tiles_scatter<<<g_scatter, 64, lds_cols, s>>>(vt, plan, vals, overflow, ranges);
   E(K_BIN_SCATTER);
-  B(K_RANGES);
-  k_bin_ranges<<<blocks_for(vt.total_tiles, 256), 256, 0, s>>>(vt, plan, overflow, ranges);
-  E(K_RANGES);
   return hipGetLastError();
 }
 
