@@ -60,8 +60,8 @@ def kernel_bytes(name, st):
     """Algorithmic HBM bytes of one launch of kernel ``name`` given step statistics."""
     N, V, Nv, M, P, K = st["N"], st["V"], st["N_vis"], st["M"], st["P"], st["K"]
     pg = 4 * (3 + 3 + 4 + 1 + 3 * K)            # parameter bytes per Gaussian
-    if name == "project":
-        return N * pg + V * N * 4 + Nv * (16 * 3 + 8)
+    if name == "project":                        # (+ the exact row runs of each visible record)
+        return N * pg + V * N * 4 + Nv * (16 * 3 + 8) + Nv * st.get("row_run_bytes", 0)
     E1 = st["E_rows"]
     if name == "radix_hist":                     # depth digits of the visible records
         return Nv * 4
@@ -249,7 +249,8 @@ def step_stats(R, params, cams, targets, settings):
               M=int(inf["num_keys"]), P=int(inf["num_pixels"]), K=int(params[4].shape[1]),
               tiles=int(inf["num_tiles"]), sort_passes=int(inf["sort_passes"]), loaded_fwd=loaded_fwd,
               loaded_bwd=loaded_bwd, wave_hits=wave_hits, E_rows=e_rows,
-              E_bwd=int(nc_all.sum()), E_fwd=e_fwd, E_used=e_used)
+              E_bwd=int(nc_all.sum()), E_fwd=e_fwd, E_used=e_used,
+              row_run_bytes=32 if settings.exact_tiles else 0)
     n = (dbg["ranges"][:, 1].astype(np.int64) - dbg["ranges"][:, 0].astype(np.int64))
     st["tile_list_length"] = {"p50": float(np.percentile(n, 50)), "p99": float(np.percentile(n, 99)),
                               "max": int(n.max(initial=0))}
@@ -482,6 +483,10 @@ def main():
                     help="1: time the headline at the autotuner's pick instead of the given launch shape "
                          "(the pick is reported either way)")
     ap.add_argument("--no-scale", action="store_true", help="skip the 1M (1200x680) and 3M (16 x 1752x1168) legs")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="profiling runs: the headline launch shape only (no autotuner sweep, no other "
+                         "tile-list kind, no batched, scale or CPU legs), so that per-kernel counters "
+                         "and durations average one shape")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of this many MiB (counter calibration under rocprofv3)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -546,11 +551,15 @@ def main():
     cam = w.cameras[HEADLINE_VIEW]
     px_head = cam.width * cam.height
     os.environ.setdefault("GSR_AUTOTUNE_CACHE", os.path.join("/tmp", "gsr_bench_autotune.txt"))
-    s_tuned, tune_ms = R.autotune(*params, [cam], s, use_cache=False)
-    log(f"autotuner's pick: tile {s_tuned.tile}, batch {s_tuned.batch}, exact tiles {s_tuned.exact_tiles} "
-        f"({tune_ms:.3f} ms/step of kernel time)")
-    if args.autotune:
-        s = s_tuned
+    if args.only_headline:
+        args.no_batched = args.no_scale = args.no_cpu_baseline = True
+        s_tuned, tune_ms = None, None
+    else:
+        s_tuned, tune_ms = R.autotune(*params, [cam], s, use_cache=False)
+        log(f"autotuner's pick: tile {s_tuned.tile}, batch {s_tuned.batch}, exact tiles {s_tuned.exact_tiles} "
+            f"({tune_ms:.3f} ms/step of kernel time)")
+        if args.autotune:
+            s = s_tuned
     stats = step_stats(R, params, [cam], [targets[HEADLINE_VIEW]], s)
     log("headline stats", stats)
 
@@ -573,17 +582,19 @@ def main():
     # lists: the same images, different list lengths)
     import dataclasses
     sx = dataclasses.replace(s, exact_tiles=not s.exact_tiles)
-    gx = R.Graph(*params, [cam], [targets[HEADLINE_VIEW]], sx, depth_weight=DEPTH_W)
-    log(f"timing {args.steps} graph-replayed headline steps with exact tile lists {sx.exact_tiles}")
-    ms_other = timed_steps(gx.launch, args.steps, args.warmup) * 1e3
-    gx.sync()
-    gx.free()
+    kinds = (s,) if args.only_headline else (s, sx)
+    ms_kind = {s.exact_tiles: ms}
+    if not args.only_headline:
+        gx = R.Graph(*params, [cam], [targets[HEADLINE_VIEW]], sx, depth_weight=DEPTH_W)
+        log(f"timing {args.steps} graph-replayed headline steps with exact tile lists {sx.exact_tiles}")
+        ms_kind[sx.exact_tiles] = timed_steps(gx.launch, args.steps, args.warmup) * 1e3
+        gx.sync()
+        gx.free()
     pairs = {}
-    for kind in (s, sx):
+    for kind in kinds:
         _, sv = R.forward(*params, [cam], kind)
         pairs[kind.exact_tiles] = int(sv.debug_export()["ranges"][:, 1].max(initial=0))
         sv.free()
-    ms_kind = {s.exact_tiles: ms, sx.exact_tiles: ms_other}
 
     per_kernel = {k: dict(ms_per_step=t / args.steps, launches_per_step=n / args.steps, avg_launch_us=1e3 * t / n)
                   for k, (t, n) in ktimes.items() if n > 0}
@@ -610,8 +621,9 @@ def main():
                                "forward + L1(colour)+0.1 L1(depth) + backward, captured step replayed",
                    "gaussians": stats["N"], "width": cam.width, "height": cam.height, "sh_degree": 3,
                    "tile": s.tile, "batch": s.batch, "exact_tiles": s.exact_tiles, "path": "hipGraph, one view"},
-        "autotune": {"tile": s_tuned.tile, "batch": s_tuned.batch, "exact_tiles": s_tuned.exact_tiles,
-                     "kernel_ms_per_step": round(tune_ms, 4), "used": bool(args.autotune)},
+        "autotune": None if s_tuned is None else {
+            "tile": s_tuned.tile, "batch": s_tuned.batch, "exact_tiles": s_tuned.exact_tiles,
+            "kernel_ms_per_step": round(tune_ms, 4), "used": bool(args.autotune)},
         "tile_lists": {("exact" if k else "rectangles"): {"ms_per_step": round(v, 4),
                                                          "Mpixel_s": round(px_head / (v * 1e-3) / 1e6, 3),
                                                          "pairs": pairs[k]} for k, v in ms_kind.items()},
