@@ -846,10 +846,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
 }
 
 // ------------------------------------------------------------------------------------
-// Device-wide exclusive scan of u32 counts, in place: per-block sums, one block scans the
-// sums (k_scan_u32), then each block scans its kScanTile elements from its base.  The
-// element count is read from the device (clamped to the capacity the grid was sized for)
-// when `count` is given.
+// Device-wide exclusive scan of u32 counts, in place, in two launches: per-block sums,
+// then each block adds up the sums of the blocks before it (a few hundred words at most
+// for the counts of a step, read once per block) and scans its kScanTile elements from
+// there; the block holding the last element writes the total.  The element count is read
+// from the device (clamped to the capacity the grid was sized for) when `count` is given;
+// blocks past it leave at once.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ int64_t scan_len(int64_t cap, const unsigned long long* count) {
   if (!count) return cap;
@@ -873,10 +875,18 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* a, int64_t 
 }
 
 __global__ __launch_bounds__(256) void k_scan_down(uint32_t* a, int64_t cap, const unsigned long long* count,
-                                                   const uint32_t* part) {
+                                                   const uint32_t* part, unsigned long long* total) {
   __shared__ uint32_t red[4];
   const int64_t n = scan_len(cap, count);
-  const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * 16;
+  const int64_t b0 = int64_t(blockIdx.x) * kScanTile;
+  if (b0 >= n) {  // block-uniform
+    if (blockIdx.x == 0 && threadIdx.x == 0) *total = 0ull;
+    return;
+  }
+  uint32_t before = 0;  // the sums of the blocks in front
+  for (int i = int(threadIdx.x); i < int(blockIdx.x); i += 256) before += part[i];
+  before = block_sum_u32(before, red);
+  const int64_t base = b0 + int64_t(threadIdx.x) * 16;
   uint32_t x[16];
   if (base + 16 <= n) {
     const uint4* src = reinterpret_cast<const uint4*>(a + base);
@@ -895,7 +905,9 @@ __global__ __launch_bounds__(256) void k_scan_down(uint32_t* a, int64_t cap, con
   uint32_t sum = 0;
 #pragma unroll
   for (int j = 0; j < 16; ++j) sum += x[j];
-  uint32_t run = part[blockIdx.x] + block_exclusive_scan_u32(sum, red);
+  const uint32_t ex = block_exclusive_scan_u32(sum, red);
+  if (threadIdx.x == 255 && b0 + kScanTile >= n) *total = (unsigned long long)before + ex + sum;
+  uint32_t run = before + ex;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const uint32_t v = x[j];
@@ -2298,8 +2310,7 @@ static void scan_u32(uint32_t* a, int64_t cap, const unsigned long long* count, 
                      unsigned long long* total, hipStream_t s) {
   const int nb = int((cap + kScanTile - 1) / kScanTile);
   k_scan_reduce<<<nb, 256, 0, s>>>(a, cap, count, part);
-  k_scan_u32<<<1, 1024, 0, s>>>(part, nb, total);
-  k_scan_down<<<nb, 256, 0, s>>>(a, cap, count, part);
+  k_scan_down<<<nb, 256, 0, s>>>(a, cap, count, part, total);
 }
 
 hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* dvals,
