@@ -420,13 +420,10 @@ hipError_t enqueue_sort_blend(gsr_saved* sv, hipStream_t s, bool timing) {
     if (alt) sorted = sv->dv2;
   }
   if (e == hipSuccess)
+    // (the binning also writes the tile queue's order)
     e = launch_bin(sv->vt, sv->N, sv->rec, sorted, sv->d_total + 1, sv->cap_vis, sv->plan, sv->vals, sv->ranges,
-                   sv->ctrl,
-                   (sv->s.flags & GSR_EXACT_TILES) ? sv->ru.k : 0.f, sv->s.tile, s, tm);
-  if (e == hipSuccess)
-    e = T(K_TILE_ORDER, [&] {
-      return launch_tile_order(sv->ranges, sv->order_hint, sv->vt.total_tiles, sv->order, s);
-    });
+                   sv->ctrl, (sv->s.flags & GSR_EXACT_TILES) ? sv->ru.k : 0.f, sv->s.tile, sv->order_hint, sv->order,
+                   s, tm);
   if (e == hipSuccess)
     e = T(K_BLEND_FWD, [&] {
       return launch_blend_fwd(sv->s.tile, sv->s.batch, sv->vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final,

@@ -286,10 +286,6 @@ hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* to
 hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
                           const unsigned long long* pairs, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
                           int64_t cap, uint32_t* overflow, hipStream_t s);
-// Tile queue order by decreasing expected work: hint[t] (a previous forward's longest
-// contributor count of tile t) when given, else the list length.
-hipError_t launch_tile_order(const uint2* ranges, const uint32_t* hint, int total_tiles, uint32_t* order,
-                             hipStream_t s);
 // Checkpoint stride and checkpoints per tile, and the backward work items of all tiles,
 // at a batch size.
 int ckpt_stride(int batch);
@@ -306,10 +302,13 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
 // Sizes of a binning plan for capacities (cap_vis, cap_M); pointers are left null.
 BinPlan bin_plan(const ViewTable& vt, int64_t cap_vis, int64_t cap_M);
 // exact_k > 0: per tile row only the columns the ellipse d^T Q d <= exact_k^2 reaches.
-// Uses the control words' overflow word.
+// Uses the control words' overflow word.  Also writes the tile queue's order by
+// decreasing expected work: hint[t] (a previous forward's longest contributor count of
+// tile t) when given, else the list length.
 hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* dvals,
                       const unsigned long long* nvis, int64_t cap_vis, const BinPlan& plan, uint32_t* vals,
-                      uint2* ranges, uint32_t* ctrl, float exact_k, int tile, hipStream_t s, Timer* tm);
+                      uint2* ranges, uint32_t* ctrl, float exact_k, int tile, const uint32_t* hint,
+                      uint32_t* order, hipStream_t s, Timer* tm);
 hipError_t launch_blend_fwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, float* T_final, uint32_t* n_contrib,
                             const TileQueue& q, const Ckpt& ck, hipStream_t s);

@@ -591,12 +591,12 @@ __global__ __launch_bounds__(kProjThreads) void k_project(GaussDev g, ViewTable 
 // K2: exclusive scans of per-block sums (one block of 1024 threads).  Totals are written
 // as 64-bit values; consumers clamp them to their buffer capacity.
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long block_inclusive_scan_u64_1024(unsigned long long v,
-                                                                           unsigned long long* part) {
+template <int NT>
+__device__ __forceinline__ unsigned long long block_inclusive_scan_u64(unsigned long long v, unsigned long long* part) {
   const int t = threadIdx.x;
   part[t] = v;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
+  for (int off = 1; off < NT; off <<= 1) {
     const unsigned long long add = t >= off ? part[t - off] : 0ull;
     __syncthreads();
     part[t] += add;
@@ -616,9 +616,9 @@ __global__ __launch_bounds__(1024) void k_scan_pairs(uint2* a, int count, unsign
     sx += x.x;
     sy += x.y;
   }
-  const unsigned long long ix = block_inclusive_scan_u64_1024(sx, part);
+  const unsigned long long ix = block_inclusive_scan_u64<1024>(sx, part);
   __syncthreads();
-  const unsigned long long iy = block_inclusive_scan_u64_1024(sy, part);
+  const unsigned long long iy = block_inclusive_scan_u64<1024>(sy, part);
   unsigned long long rx = ix - sx, ry = iy - sy;
   for (int i = beg; i < end; ++i) {
     const uint2 x = a[i];
@@ -639,7 +639,7 @@ __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* a, int count, unsig
   const int beg = min(count, t * per), end = min(count, beg + per);
   unsigned long long sum = 0;
   for (int i = beg; i < end; ++i) sum += a[i];
-  const unsigned long long incl = block_inclusive_scan_u64_1024(sum, part);
+  const unsigned long long incl = block_inclusive_scan_u64<1024>(sum, part);
   unsigned long long run = incl - sum;
   for (int i = beg; i < end; ++i) {
     const uint32_t x = a[i];
@@ -1004,12 +1004,59 @@ __global__ __launch_bounds__(256) void k_bin_rows_count(ViewTable vt, int64_t n,
   for (int i = threadIdx.x; i < R; i += 256) plan.cnt1[int64_t(i) * plan.nch1 + chunk] = hist[i];
 }
 
+// Per row: list start and length, its segments and its first flat (tile, segment) index;
+// totals of segments and of the flat array.  Run by the whole of one block of NT threads
+// (the last block of the row placement, before its own work: no launch of its own).
+template <int NT>
+__device__ void rows_meta(const ViewTable& vt, const BinPlan& plan, uint32_t* overflow, unsigned long long* part) {
+  const int R = plan.rows, t = threadIdx.x;
+  const int per = (R + NT - 1) / NT;
+  const int beg = min(R, t * per), end = min(R, beg + per);
+  const unsigned long long E1 = plan.words[0];
+  const uint32_t S2 = 64u * uint32_t(plan.rounds2);
+  auto row = [&](int r, uint32_t& start, uint32_t& len, uint32_t& nseg, uint32_t& w) {
+    start = plan.cnt1[int64_t(r) * plan.nch1];
+    const unsigned long long next = r + 1 < R ? plan.cnt1[int64_t(r + 1) * plan.nch1] : E1;
+    len = uint32_t(next - start);
+    nseg = (len + S2 - 1) / S2;
+    w = nseg * uint32_t(vt.v[view_of_row(vt, uint32_t(r))].tiles_x);
+  };
+  unsigned long long sseg = 0, sw = 0;
+  for (int r = beg; r < end; ++r) {
+    uint32_t a, l, ns, w;
+    row(r, a, l, ns, w);
+    sseg += ns;
+    sw += w;
+  }
+  const unsigned long long iseg = block_inclusive_scan_u64<NT>(sseg, part);
+  __syncthreads();
+  const unsigned long long iw = block_inclusive_scan_u64<NT>(sw, part);
+  unsigned long long seg = iseg - sseg, flat = iw - sw;
+  for (int r = beg; r < end; ++r) {
+    uint32_t a, l, ns, w;
+    row(r, a, l, ns, w);
+    plan.rowinfo[r] = make_uint4(a, l, uint32_t(seg), uint32_t(flat));
+    plan.seg_start[r] = uint32_t(seg);
+    seg += ns;
+    flat += w;
+  }
+  if (t == NT - 1) {
+    const bool over = iseg > (unsigned long long)plan.cap_seg || iw > (unsigned long long)plan.cap_flat;
+    if (over) raise_overflow(overflow);
+    plan.seg_start[R] = uint32_t(over ? 0ull : iseg);
+    plan.words[1] = over ? 0ull : iseg;
+    plan.words[2] = over ? 0ull : iw;
+  }
+}
+
 // stage 1 placement: one wavefront per chunk writes (record, column run) entries into the
 // row lists
 __global__ __launch_bounds__(64) void k_bin_rows_scatter(ViewTable vt, int64_t n, Records rec, const uint32_t* dvals,
                                                          const unsigned long long* nvis, int64_t cap_vis,
-                                                         const uint32_t* overflow, BinPlan plan) {
+                                                         uint32_t* overflow, BinPlan plan) {
   extern __shared__ uint32_t next[];  // next free slot of each row for this chunk
+  __shared__ unsigned long long s_part[64];
+  if (blockIdx.x == gridDim.x - 1) rows_meta<64>(vt, plan, overflow, s_part);
   const int R = plan.rows;
   const int lane = threadIdx.x;
   const int64_t NV = clamp_count(nvis, cap_vis, overflow);
@@ -1080,7 +1127,9 @@ __device__ __forceinline__ void take_slots(uint32_t (&nx)[NREG], uint32_t b, uin
 template <int NREG>
 __global__ __launch_bounds__(256) void k_bin_rows_scatter_r(ViewTable vt, int64_t n, Records rec,
                                                             const uint32_t* dvals, const unsigned long long* nvis,
-                                                            int64_t cap_vis, const uint32_t* overflow, BinPlan plan) {
+                                                            int64_t cap_vis, uint32_t* overflow, BinPlan plan) {
+  __shared__ unsigned long long s_part[256];
+  if (blockIdx.x == gridDim.x - 1) rows_meta<256>(vt, plan, overflow, s_part);
   const int R = plan.rows;
   const int lane = threadIdx.x & 63;
   const int chunk = int(blockIdx.x) * 4 + int(threadIdx.x >> 6);  // one chunk per wavefront
@@ -1126,50 +1175,6 @@ __global__ __launch_bounds__(256) void k_bin_rows_scatter_r(ViewTable vt, int64_
   }
 }
 
-// Per row: list start and length, its segments and its first flat (tile, segment) index;
-// totals of segments and of the flat array.  One block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_bin_rows_meta(ViewTable vt, BinPlan plan, uint32_t* overflow) {
-  __shared__ unsigned long long part[1024];
-  const int R = plan.rows, t = threadIdx.x;
-  const int per = (R + 1023) / 1024;
-  const int beg = min(R, t * per), end = min(R, beg + per);
-  const unsigned long long E1 = plan.words[0];
-  const uint32_t S2 = 64u * uint32_t(plan.rounds2);
-  auto row = [&](int r, uint32_t& start, uint32_t& len, uint32_t& nseg, uint32_t& w) {
-    start = plan.cnt1[int64_t(r) * plan.nch1];
-    const unsigned long long next = r + 1 < R ? plan.cnt1[int64_t(r + 1) * plan.nch1] : E1;
-    len = uint32_t(next - start);
-    nseg = (len + S2 - 1) / S2;
-    w = nseg * uint32_t(vt.v[view_of_row(vt, uint32_t(r))].tiles_x);
-  };
-  unsigned long long sseg = 0, sw = 0;
-  for (int r = beg; r < end; ++r) {
-    uint32_t a, l, ns, w;
-    row(r, a, l, ns, w);
-    sseg += ns;
-    sw += w;
-  }
-  const unsigned long long iseg = block_inclusive_scan_u64_1024(sseg, part);
-  __syncthreads();
-  const unsigned long long iw = block_inclusive_scan_u64_1024(sw, part);
-  unsigned long long seg = iseg - sseg, flat = iw - sw;
-  for (int r = beg; r < end; ++r) {
-    uint32_t a, l, ns, w;
-    row(r, a, l, ns, w);
-    plan.rowinfo[r] = make_uint4(a, l, uint32_t(seg), uint32_t(flat));
-    plan.seg_start[r] = uint32_t(seg);
-    seg += ns;
-    flat += w;
-  }
-  if (t == 1023) {
-    const bool over = iseg > (unsigned long long)plan.cap_seg || iw > (unsigned long long)plan.cap_flat;
-    if (over) raise_overflow(overflow);
-    plan.seg_start[R] = uint32_t(over ? 0ull : iseg);
-    plan.words[1] = over ? 0ull : iseg;
-    plan.words[2] = over ? 0ull : iw;
-  }
-}
-
 // the row whose segments contain segment s: the last r with seg_start[r] <= s
 __device__ __forceinline__ int row_of_segment(const uint32_t* seg_start, int R, uint32_t s) {
   int lo = 0, hi = R - 1;
@@ -1204,6 +1209,68 @@ __device__ __forceinline__ Segment segment_of(const ViewTable& vt, const BinPlan
   g.tiles_x = vt.v[view_of_row(vt, uint32_t(r))].tiles_x;
   g.row = r;
   return g;
+}
+
+// ------------------------------------------------------------------------------------
+// Tile work queue.  Tiles are ordered by decreasing expected work (a counting sort on
+// buckets of eight steps per octave, in one block: the order inside a bucket is
+// arbitrary) and the compositing kernels run as persistent blocks that take the next tile
+// from a device counter, so the heaviest tiles start first and light ones fill the tail.
+// A tile's work is its longest per-pixel contributor count, which the list length does
+// not predict (a pixel stops once its transmittance is spent); when a previous forward
+// of the same tiles left those counts (`hint`), they are the key, else the list length.
+// ------------------------------------------------------------------------------------
+constexpr int kOrderBuckets = 257;
+
+__device__ __forceinline__ uint32_t work_bucket(uint32_t w) {
+  if (w == 0) return 0;
+  const uint32_t e = 31u - uint32_t(__clz(w));
+  const uint32_t m = e >= 3 ? (w >> (e - 3)) & 7u : (w << (3 - e)) & 7u;
+  return 1u + 8u * e + m;
+}
+
+// The queue order of `total` tiles by one whole block of NT threads (LDS: cnt and start
+// of kOrderBuckets words, red of NT / 64): bucket counts, their scan heaviest bucket first,
+// then each tile's slot (the order inside a bucket is arbitrary).  With a hint the ranges
+// are not read.
+template <int NT>
+__device__ void tile_order_block(const uint2* ranges, const uint32_t* hint, int total, uint32_t* order,
+                                 uint32_t* cnt, uint32_t* start, uint32_t* red) {
+  const int t = threadIdx.x;
+  for (int b = t; b < kOrderBuckets; b += NT) cnt[b] = 0;
+  __syncthreads();
+  auto key = [&](int i) {
+    if (hint) return work_bucket(hint[i]);
+    const uint2 r = ranges[i];
+    return work_bucket(r.y - r.x);
+  };
+  for (int i = t; i < total; i += NT) atomicAdd(&cnt[key(i)], 1u);
+  __syncthreads();
+  // heaviest bucket first: thread t takes positions t P .. t P + P - 1 of the descending order
+  constexpr int P = (kOrderBuckets + NT - 1) / NT;
+  uint32_t c[P], sum = 0;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int bk = kOrderBuckets - 1 - (t * P + j);
+    c[j] = bk >= 0 ? cnt[bk] : 0u;
+    sum += c[j];
+  }
+  uint32_t run = block_exclusive_scan_u32(sum, red);
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int bk = kOrderBuckets - 1 - (t * P + j);
+    if (bk >= 0) start[bk] = run;
+    run += c[j];
+  }
+  __syncthreads();
+  for (int i = t; i < total; i += NT) order[atomicAdd(&start[key(i)], 1u)] = uint32_t(i);
+}
+
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2* ranges, const uint32_t* hint, int total,
+                                                    uint32_t* order) {
+  __shared__ uint32_t cnt[kOrderBuckets], start[kOrderBuckets];
+  __shared__ uint32_t red[16];
+  tile_order_block<1024>(ranges, hint, total, order, cnt, start, red);
 }
 
 // stage 2 counts: tile-column histogram of one segment of a row list, one wavefront per
@@ -1311,7 +1378,12 @@ __global__ __launch_bounds__(64) void k_bin_tiles_scatter(ViewTable vt, BinPlan 
 // block, each with its own segments.
 template <int NREG>
 __global__ __launch_bounds__(256) void k_bin_tiles_scatter_r(ViewTable vt, BinPlan plan, uint32_t* vals,
-                                                             const uint32_t* overflow, uint2* ranges) {
+                                                             const uint32_t* overflow, uint2* ranges,
+                                                             const uint32_t* hint, uint32_t* order) {
+  __shared__ uint32_t s_cnt[kOrderBuckets], s_start[kOrderBuckets], s_red[4];
+  // with a work hint the tile queue's order does not need the ranges: the last block
+  // orders it here (no launch of its own)
+  if (hint && blockIdx.x == gridDim.x - 1) tile_order_block<256>(nullptr, hint, vt.total_tiles, order, s_cnt, s_start, s_red);
   const int lane = threadIdx.x & 63;
   for (int t = int(blockIdx.x) * 256 + int(threadIdx.x); t < vt.total_tiles; t += int(gridDim.x) * 256)
     ranges[t] = tile_range(vt, plan, overflow, t);
@@ -1372,46 +1444,6 @@ __global__ __launch_bounds__(256) void k_first_nonfinite(GaussDev g, int K, uint
     while (j >= sizes[a]) j -= sizes[a++];
     if (!isfinite(arrs[a][j])) atomicMin(first, uint32_t(j / per[a]));
   }
-}
-
-// ------------------------------------------------------------------------------------
-// Tile work queue.  Tiles are ordered by decreasing expected work (a counting sort on
-// buckets of eight steps per octave, in one block: the order inside a bucket is
-// arbitrary) and the compositing kernels run as persistent blocks that take the next tile
-// from a device counter, so the heaviest tiles start first and light ones fill the tail.
-// A tile's work is its longest per-pixel contributor count, which the list length does
-// not predict (a pixel stops once its transmittance is spent); when a previous forward
-// of the same tiles left those counts (`hint`), they are the key, else the list length.
-// ------------------------------------------------------------------------------------
-constexpr int kOrderBuckets = 257;
-
-__device__ __forceinline__ uint32_t work_bucket(uint32_t w) {
-  if (w == 0) return 0;
-  const uint32_t e = 31u - uint32_t(__clz(w));
-  const uint32_t m = e >= 3 ? (w >> (e - 3)) & 7u : (w << (3 - e)) & 7u;
-  return 1u + 8u * e + m;
-}
-
-__global__ __launch_bounds__(1024) void k_tile_order(const uint2* ranges, const uint32_t* hint, int total,
-                                                    uint32_t* order) {
-  __shared__ uint32_t cnt[kOrderBuckets], start[kOrderBuckets];
-  __shared__ uint32_t red[16];
-  const int t = threadIdx.x;
-  if (t < kOrderBuckets) cnt[t] = 0;
-  __syncthreads();
-  auto key = [&](int i) {
-    const uint2 r = ranges[i];
-    return work_bucket(hint ? hint[i] : r.y - r.x);
-  };
-  for (int i = t; i < total; i += 1024) atomicAdd(&cnt[key(i)], 1u);
-  __syncthreads();
-  // heaviest bucket first: thread t takes bucket kOrderBuckets - 1 - t
-  const int bk = kOrderBuckets - 1 - t;
-  const uint32_t c = bk >= 0 ? cnt[bk] : 0u;
-  const uint32_t ex = block_exclusive_scan_u32(c, red);
-  if (bk >= 0) start[bk] = ex;
-  __syncthreads();
-  for (int i = t; i < total; i += 1024) order[atomicAdd(&start[key(i)], 1u)] = uint32_t(i);
 }
 
 // Wave priority 0..3 (s_setprio takes an immediate).
@@ -2315,11 +2347,13 @@ static void scan_u32(uint32_t* a, int64_t cap, const unsigned long long* count, 
 
 hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const uint32_t* dvals,
                       const unsigned long long* nvis, int64_t cap_vis, const BinPlan& plan, uint32_t* vals,
-                      uint2* ranges, uint32_t* ctrl, float exact_k, int tile, hipStream_t s, Timer* tm) {
+                      uint2* ranges, uint32_t* ctrl, float exact_k, int tile, const uint32_t* hint,
+                      uint32_t* order, hipStream_t s, Timer* tm) {
   if (vt.total_tiles == 0) return hipSuccess;
   if (cap_vis == 0 || plan.cap_M == 0 || plan.rows == 0) {
     k_fill_u32<<<blocks_for(int64_t(vt.total_tiles) * 2, 256), 256, 0, s>>>(reinterpret_cast<uint32_t*>(ranges), 0u,
                                                                              int64_t(vt.total_tiles) * 2);
+    k_tile_order<<<1, 1024, 0, s>>>(ranges, hint, vt.total_tiles, order);
     return hipGetLastError();
   }
   auto B = [&](int k) { if (tm) tm->begin(k); };
@@ -2335,7 +2369,6 @@ hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const 
   E(K_BIN_COUNT);
   B(K_BIN_SCAN);
   scan_u32(plan.cnt1, n1, nullptr, plan.part, plan.words, s);
-  k_bin_rows_meta<<<1, 1024, 0, s>>>(vt, plan, overflow);
   E(K_BIN_SCAN);
   B(K_BIN_SCATTER);
   if (plan.rows <= 64)
@@ -2355,14 +2388,19 @@ hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const 
   E(K_BIN_SCAN);
   B(K_BIN_SCATTER);
   if (vt.max_tiles_x <= 64)
-    k_bin_tiles_scatter_r<1><<<g_scatter4, 256, 0, s>>>(vt, plan, vals, overflow, ranges);
+    k_bin_tiles_scatter_r<1><<<g_scatter4, 256, 0, s>>>(vt, plan, vals, overflow, ranges, hint, order);
   else if (vt.max_tiles_x <= 128)
-    k_bin_tiles_scatter_r<2><<<g_scatter4, 256, 0, s>>>(vt, plan, vals, overflow, ranges);
+    k_bin_tiles_scatter_r<2><<<g_scatter4, 256, 0, s>>>(vt, plan, vals, overflow, ranges, hint, order);
   else if (vt.max_tiles_x <= 256)
-    k_bin_tiles_scatter_r<4><<<g_scatter4, 256, 0, s>>>(vt, plan, vals, overflow, ranges);
+    k_bin_tiles_scatter_r<4><<<g_scatter4, 256, 0, s>>>(vt, plan, vals, overflow, ranges, hint, order);
   else
     k_bin_tiles_scatter<<<g_scatter, 64, lds_cols, s>>>(vt, plan, vals, overflow, ranges);
   E(K_BIN_SCATTER);
+  if (!hint || vt.max_tiles_x > 256) {  // the order not taken by the placement above
+    B(K_TILE_ORDER);
+    k_tile_order<<<1, 1024, 0, s>>>(ranges, hint, vt.total_tiles, order);
+    E(K_TILE_ORDER);
+  }
   return hipGetLastError();
 }
 
@@ -2435,13 +2473,6 @@ hipError_t launch_count_used(const ViewTable& vt, const Rules& ru, const Records
   if (total_pix == 0) return hipSuccess;
   k_count_used<<<unsigned((total_pix + 255) / 256), 256, 0, s>>>(vt, ru, rec, ranges, vals, n_contrib, tile, total_pix,
                                                                  n_used);
-  return hipGetLastError();
-}
-
-hipError_t launch_tile_order(const uint2* ranges, const uint32_t* hint, int total_tiles, uint32_t* order,
-                             hipStream_t s) {
-  if (total_tiles == 0) return hipSuccess;
-  k_tile_order<<<1, 1024, 0, s>>>(ranges, hint, total_tiles, order);
   return hipGetLastError();
 }
 
