@@ -378,6 +378,9 @@ void keep_hint(gsr_ctx* ctx, const gsr_saved* sv, hipStream_t s) {
   }
 }
 
+// Whether the compaction scans the projection's block sums itself (see launch_compact).
+bool compact_scans(const gsr_saved* sv) { return sv->graph && int64_t(sv->V) * sv->nblk <= kCompactRawMax; }
+
 // Phase A of a forward: clear the control words, project, scan the block sums.
 hipError_t enqueue_project(gsr_saved* sv, hipStream_t s, bool timing) {
   gsr_ctx* ctx = sv->ctx;
@@ -391,7 +394,9 @@ hipError_t enqueue_project(gsr_saved* sv, hipStream_t s, bool timing) {
     return launch_project(sv->deg, sv->g, sv->vt, sv->ru, sv->s.tile, sv->rec, sv->blocksums, sv->nblk, sv->grad2d,
                           sv->ctrl, clear, (sv->s.flags & GSR_EXACT_TILES) ? sv->ru.k : 0.f, s);
   });
-  if (e == hipSuccess)
+  // a captured step with few block sums leaves their scan to the compaction (the host
+  // does not read the totals); an eager forward reads them to size its buffers
+  if (e == hipSuccess && !compact_scans(sv))
     e = T(K_SCAN, [&] { return launch_scan_pairs(sv->blocksums, sv->V * sv->nblk, sv->d_total, s); });
   return e;
 }
@@ -411,7 +416,7 @@ hipError_t enqueue_sort_blend(gsr_saved* sv, hipStream_t s, bool timing) {
     bool alt = false;
     e = T(K_COMPACT, [&] {
       return launch_compact(sv->N, sv->V, sv->rec, sv->blocksums, sv->nblk, sv->d_total, sv->cap_M, sv->dk, sv->dv,
-                            sv->cap_vis, ovf, s);
+                            sv->cap_vis, ovf, compact_scans(sv), s);
     });
     if (e == hipSuccess)
       // depth keys are the bits of a positive binary32 depth: bit 31 is zero

@@ -283,9 +283,13 @@ hipError_t launch_project(int deg, const GaussDev& g, const ViewTable& vt, const
                           const Records& rec, uint2* blocksums, int nblk, float* zero_rows, uint32_t* ctrl,
                           int clear_words, float exact_k, hipStream_t s);
 hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* totals, hipStream_t s);
+// raw: blocksums as the projection wrote them (not scanned; at most kCompactRawMax of
+// them), and the compaction writes totals[0..1] itself; else scanned by launch_scan_pairs,
+// which wrote the totals.
+constexpr int64_t kCompactRawMax = 4096;
 hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
-                          const unsigned long long* pairs, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
-                          int64_t cap, uint32_t* overflow, hipStream_t s);
+                          unsigned long long* totals, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
+                          int64_t cap, uint32_t* overflow, bool raw, hipStream_t s);
 // Checkpoint stride and checkpoints per tile, and the backward work items of all tiles,
 // at a batch size.
 int ckpt_stride(int batch);

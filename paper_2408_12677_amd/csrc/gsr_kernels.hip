@@ -668,21 +668,50 @@ __device__ __forceinline__ uint32_t clamp_count(const unsigned long long* count,
 // ------------------------------------------------------------------------------------
 // K3a: compaction of the visible records into (depth bits, record id) pairs, record order
 // ------------------------------------------------------------------------------------
+// raw: the block sums are the projection's, not scanned (at most kCompactRawMax of them):
+// each block adds the visible records of the blocks in front of it itself, and the last
+// block writes the totals (pairs, visible records) to totals[0..1].  Otherwise they were
+// scanned (k_scan_pairs, which wrote the totals).
 __global__ __launch_bounds__(kProjThreads) void k_compact(int64_t n, Records rec, const uint2* blocksums, int nblk,
-                                                          const unsigned long long* pairs, int64_t cap_M,
+                                                          unsigned long long* totals, int64_t cap_M,
                                                           uint32_t* dkeys, uint32_t* dvals, int64_t cap,
-                                                          uint32_t* overflow) {
+                                                          uint32_t* overflow, int raw) {
   __shared__ uint32_t red[kProjThreads / 64];
+  __shared__ unsigned long long red64[kProjThreads / 64];
   const int v = blockIdx.y;
-  // more (tile, record) pairs than the binning buffers hold: flag it before anything reads
-  // the flag (every later kernel then sees zero records)
-  if (blockIdx.x == 0 && v == 0 && threadIdx.x == 0 && *pairs > (unsigned long long)cap_M) raise_overflow(overflow);
+  const int64_t me = int64_t(v) * nblk + blockIdx.x;  // this block's sums
+  const int64_t nb = int64_t(gridDim.y) * nblk;
   const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
   const int64_t rid = int64_t(v) * n + gi;
   const uint32_t vis = (gi < n && rec.counts[rid] != 0u) ? 1u : 0u;
+  uint32_t base;
+  if (raw) {
+    uint32_t before = 0;
+    for (int64_t i = threadIdx.x; i < me; i += kProjThreads) before += blocksums[i].y;
+    base = block_sum_u32(before, red);
+    if (me == nb - 1) {  // block-uniform: the last block writes the totals
+      unsigned long long px = 0;
+      for (int64_t i = threadIdx.x; i < nb; i += kProjThreads) px += blocksums[i].x;
+      for (int off = 32; off > 0; off >>= 1) px += __shfl_xor(px, off);
+      if ((threadIdx.x & 63) == 0) red64[threadIdx.x >> 6] = px;
+      const uint32_t mine = block_sum_u32(vis, red);  // (its barrier also publishes red64)
+      if (threadIdx.x == 0) {
+        unsigned long long pairs = 0;
+        for (int i = 0; i < kProjThreads / 64; ++i) pairs += red64[i];
+        totals[0] = pairs;
+        totals[1] = (unsigned long long)base + mine;
+        if (pairs > (unsigned long long)cap_M) raise_overflow(overflow);
+      }
+    }
+  } else {
+    base = blocksums[me].y;
+    // more (tile, record) pairs than the binning buffers hold: flag it before anything
+    // reads the flag (every later kernel then sees zero records)
+    if (me == 0 && threadIdx.x == 0 && totals[0] > (unsigned long long)cap_M) raise_overflow(overflow);
+  }
   const uint32_t excl = block_exclusive_scan_u32(vis, red);
   if (!vis) return;
-  const uint32_t off = blocksums[int64_t(v) * nblk + blockIdx.x].y + excl;
+  const uint32_t off = base + excl;
   if (int64_t(off) >= cap) {
     raise_overflow(overflow);
     return;
@@ -2269,11 +2298,12 @@ hipError_t launch_scan_pairs(uint2* blocksums, int count, unsigned long long* to
 }
 
 hipError_t launch_compact(int64_t n, int views, const Records& rec, const uint2* blocksums, int nblk,
-                          const unsigned long long* pairs, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
-                          int64_t cap, uint32_t* overflow, hipStream_t s) {
+                          unsigned long long* totals, int64_t cap_M, uint32_t* dkeys, uint32_t* dvals,
+                          int64_t cap, uint32_t* overflow, bool raw, hipStream_t s) {
   if (nblk == 0) return hipSuccess;
-  k_compact<<<dim3(nblk, views), kProjThreads, 0, s>>>(n, rec, blocksums, nblk, pairs, cap_M, dkeys, dvals, cap,
-                                                        overflow);
+  if (raw && int64_t(views) * nblk > kCompactRawMax) return hipErrorInvalidValue;
+  k_compact<<<dim3(nblk, views), kProjThreads, 0, s>>>(n, rec, blocksums, nblk, totals, cap_M, dkeys, dvals, cap,
+                                                        overflow, raw ? 1 : 0);
   return hipGetLastError();
 }
 
