@@ -450,14 +450,15 @@ hipError_t enqueue_backward(gsr_saved* sv, const ViewTable& vt, float* grad2d, c
     e = T(K_FILL, [&] { return launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, VN * kGrad2D, s); });
   if (e == hipSuccess)
     e = T(K_BLEND_BWD, [&] {
+      // a captured step (loss non-null) listed the work items in its loss kernel
       return launch_blend_bwd(sv->s.tile, sv->s.batch, vt, sv->ru, sv->rec, sv->ranges, sv->vals, sv->T_final,
-                              sv->n_contrib, grad2d, queue_of(sv), sv->ck, s, sv->loss_part,
-                              loss ? loss_partials(vt) : 0, loss);
+                              sv->n_contrib, grad2d, queue_of(sv), sv->ck, s, loss != nullptr);
     });
   if (e == hipSuccess && adam.on) e = launch_adam_tick(adam_state, adam.b1, adam.b2, adam.skip, s);
   if (e == hipSuccess)
     e = T(K_PROJECT_BWD, [&] {
-      return launch_project_bwd(sv->deg, sv->g, vt, sv->ru, sv->rec, grad2d, grad2d + VN * kGrad2D, go, adam, s);
+      return launch_project_bwd(sv->deg, sv->g, vt, sv->ru, sv->rec, grad2d, grad2d + VN * kGrad2D, go, adam, s,
+                                sv->loss_part, loss ? loss_partials(vt) : 0, loss);
     });
   return e;
 }
@@ -1036,8 +1037,10 @@ gsr_status gsr_graph_create(gsr_ctx* ctx, const gsr_gaussians* g, const gsr_came
   if (e == hipSuccess) {
     hipError_t k = enqueue_project(sv, cs, false);
     if (k == hipSuccess) k = enqueue_sort_blend(sv, cs, false);
-    // the loss total is added up by the backward's first kernel
-    if (k == hipSuccess) k = launch_loss_l1(lvt, depth_weight, sv->loss_part, nullptr, cs);
+    // the loss kernel also lists the backward's work items; the loss total is added up by
+    // the backward projection
+    if (k == hipSuccess)
+      k = launch_loss_l1(lvt, depth_weight, sv->loss_part, nullptr, cs, sv->order, sv->s.batch, &sv->ck, sv->ctrl);
     if (k == hipSuccess)
       k = enqueue_backward(sv, bvt, sv->grad2d, go, cs, false, ad, opt ? opt->state : nullptr, loss_dev);
     if (k == hipSuccess)

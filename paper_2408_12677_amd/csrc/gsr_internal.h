@@ -322,21 +322,27 @@ hipError_t launch_count_used(const ViewTable& vt, const Rules& ru, const Records
                              uint32_t* n_used, hipStream_t s);
 int loss_partials(const ViewTable& vt);  // block partial sums launch_loss_l1 writes
 // Loss partial sums, and their total into *loss unless loss is null (then the caller has
-// launch_blend_bwd add them up).
-hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* part, float* loss, hipStream_t s);
-// Lists the backward's (tile, stride) work items, then runs them; with loss non-null the
-// listing kernel also writes the total of the loss_np partial sums loss_part to *loss.
+// launch_project_bwd add them up).  With order non-null (the forward's tile queue) the
+// loss kernel also lists the backward's work items for a batch size (the state ck, the
+// control words ctrl), so that launch_blend_bwd can skip its own listing.
+hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* part, float* loss, hipStream_t s,
+                          const uint32_t* order = nullptr, int batch = 0, const Ckpt* ck = nullptr,
+                          uint32_t* ctrl = nullptr);
+// Lists the backward's (tile, stride) work items unless items_listed (the loss kernel
+// did), then runs them.
 hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, const float* T_final,
                             const uint32_t* n_contrib, float* grad2d, const TileQueue& q, const Ckpt& ck,
-                            hipStream_t s, const float* loss_part = nullptr, int loss_np = 0,
-                            float* loss = nullptr);
+                            hipStream_t s, bool items_listed = false);
 // grad2d holds V*N rows of kGrad2D floats; dp_sh is scratch for N * 3 floats.  With
 // adam.on the parameter gradients are not written to `out` but applied to the parameters
 // by one Adam step (adam.bc must already hold the step's bias corrections).
+// With loss non-null the first block of the geometric kernel also writes the total of the
+// loss_np loss partial sums loss_part to *loss (in launch_loss_l1's order).
 hipError_t launch_project_bwd(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru,
                               const Records& rec, const float* grad2d, float* dp_sh, const GradOut& out,
-                              const AdamDev& adam, hipStream_t s);
+                              const AdamDev& adam, hipStream_t s, const float* loss_part = nullptr,
+                              int loss_np = 0, float* loss = nullptr);
 
 // ---- TSDF fusion (gsr_tsdf.hip) -----------------------------------------------------
 int tsdf_band_samples(float eps, float step);

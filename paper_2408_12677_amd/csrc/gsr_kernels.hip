@@ -1671,10 +1671,49 @@ __global__ __launch_bounds__(256) void k_count_used(ViewTable vt, Rules ru, Reco
 }
 
 // ------------------------------------------------------------------------------------
+// Backward work items, in the tile queue's longest-first order: (tile, k) for every
+// checkpoint stride k that holds a contributor of some pixel of the tile, up to the
+// tile's last checkpoint; one more item (tile, kmax) covers all later entries.  Listed by
+// one whole block of NT threads (red: NT / 64 words, carry: one): k_bwd_items, or in a
+// captured step the last block of the loss kernel.
+template <int NT>
+__device__ void list_bwd_items(const uint32_t* order, int total, int batch, const Ckpt& ck, uint32_t* ctrl,
+                               uint32_t* red, uint32_t& carry) {
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int i0 = 0; i0 < total; i0 += NT) {
+    const int i = i0 + threadIdx.x;
+    uint32_t t = 0, ni = 0;
+    if (i < total) {
+      t = order[i];
+      const uint32_t nb = (ck.tile_nmax[t] + uint32_t(batch) - 1u) / uint32_t(batch);
+      ni = nb <= uint32_t(ck.kmax) ? nb : uint32_t(ck.kmax) + 1u;
+    }
+    const uint32_t base = carry + block_exclusive_scan_u32(ni, red);
+    for (uint32_t k = 0; k < ni; ++k)
+      if (int64_t(base) + k < ck.cap_items) ck.items[base + k] = make_uint2(t, k);
+    __syncthreads();
+    if (threadIdx.x == NT - 1) carry = base + ni;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ctrl[kItems] = uint32_t(min<int64_t>(carry, ck.cap_items));
+}
+
+__global__ __launch_bounds__(1024) void k_bwd_items(const uint32_t* order, int total, int batch, Ckpt ck,
+                                                   uint32_t* ctrl) {
+  __shared__ uint32_t red[16], carry;
+  list_bwd_items<1024>(order, total, batch, ck, ctrl, red, carry);
+}
+
+// ------------------------------------------------------------------------------------
 // K7: L1 loss and its gradient with respect to the rendered colour and depth
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_loss_l1(ViewTable vt, float depth_w, float* partial) {
+// With order non-null (a captured step) the last block also lists the backward's work
+// items (list_bwd_items) for the tiles the forward just composited.
+__global__ __launch_bounds__(256) void k_loss_l1(ViewTable vt, float depth_w, float* partial, const uint32_t* order,
+                                                int total_tiles, int stride, Ckpt ck, uint32_t* ctrl) {
   __shared__ float red[4];
+  __shared__ uint32_t ired[4], icarry;
   const ViewDev& cam = vt.v[blockIdx.y];
   const int64_t P = int64_t(cam.W) * cam.H;
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
@@ -1702,25 +1741,24 @@ __global__ __launch_bounds__(256) void k_loss_l1(ViewTable vt, float depth_w, fl
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
   __syncthreads();
   if (threadIdx.x == 0) partial[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (order && blockIdx.x == gridDim.x - 1 && blockIdx.y == gridDim.y - 1)
+    list_bwd_items<256>(order, total_tiles, stride, ck, ctrl, ired, icarry);
 }
 
-// the loss: the block partial sums added in a fixed order (deterministic), by a block of
-// 1024 threads
+// the loss: the block partial sums added in a fixed order (deterministic) by one whole
+// block of 256 threads (the eager sum below; in a captured step the first block of the
+// backward projection), so both give the same bits
 __device__ __forceinline__ void sum_loss_partials(const float* part, int count, float* loss, float* red) {
   float v = 0.f;
-  for (int i = threadIdx.x; i < count; i += 1024) v += part[i];
+  for (int i = threadIdx.x; i < count; i += 256) v += part[i];
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    float t = 0.f;
-    for (int i = 0; i < 16; ++i) t += red[i];
-    *loss = t;
-  }
+  if (threadIdx.x == 0) *loss = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ __launch_bounds__(1024) void k_loss_sum(const float* part, int count, float* loss) {
-  __shared__ float red[16];
+__global__ __launch_bounds__(256) void k_loss_sum(const float* part, int count, float* loss) {
+  __shared__ float red[4];
   sum_loss_partials(part, count, loss, red);
 }
 
@@ -1737,36 +1775,6 @@ __global__ __launch_bounds__(1024) void k_loss_sum(const float* part, int count,
 // and DPP (wave_sum10); with more than one wavefront per tile the wavefront sums meet
 // in LDS and the block adds each splat's total to the 2D-gradient buffer once per item,
 // with the atomics spread over all lanes.
-// ------------------------------------------------------------------------------------
-// Backward work items, in the tile queue's longest-first order: (tile, k) for every
-// checkpoint stride k that holds a contributor of some pixel of the tile, up to the
-// tile's last checkpoint; one more item (tile, kmax) covers all later entries.  One block.
-__global__ __launch_bounds__(1024) void k_bwd_items(const uint32_t* order, int total, int batch, Ckpt ck,
-                                                   uint32_t* ctrl, const float* loss_part, int loss_np,
-                                                   float* loss) {
-  __shared__ uint32_t red[16], carry;
-  __shared__ float fred[16];
-  // a captured step also adds up its loss here (one launch fewer)
-  if (loss) sum_loss_partials(loss_part, loss_np, loss, fred);
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int i0 = 0; i0 < total; i0 += 1024) {
-    const int i = i0 + threadIdx.x;
-    uint32_t t = 0, ni = 0;
-    if (i < total) {
-      t = order[i];
-      const uint32_t nb = (ck.tile_nmax[t] + uint32_t(batch) - 1u) / uint32_t(batch);
-      ni = nb <= uint32_t(ck.kmax) ? nb : uint32_t(ck.kmax) + 1u;
-    }
-    const uint32_t base = carry + block_exclusive_scan_u32(ni, red);
-    for (uint32_t k = 0; k < ni; ++k)
-      if (int64_t(base) + k < ck.cap_items) ck.items[base + k] = make_uint2(t, k);
-    __syncthreads();
-    if (threadIdx.x == 1023) carry = base + ni;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) ctrl[kItems] = uint32_t(min<int64_t>(carry, ck.cap_items));
-}
 
 // Block-uniform: the next backward work item, or -1; the first items (the heaviest
 // tiles) take a higher wave priority, as in the forward.
@@ -2141,7 +2149,11 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(GaussDev g, ViewTable vt
 // gradient with respect to the mean (dp_sh, from K9a).
 __global__ __launch_bounds__(kProjThreads) void k_project_bwd_geo(GaussDev g, ViewTable vt, Rules ru, Records rec,
                                                                   const float* grad2d, const float* dp_sh,
-                                                                  GradOut out, AdamDev adam) {
+                                                                  GradOut out, AdamDev adam, const float* loss_part,
+                                                                  int loss_np, float* loss) {
+  __shared__ float lred[4];
+  // a captured step adds up its loss here (block-uniform; no launch of its own)
+  if (loss && blockIdx.x == 0) sum_loss_partials(loss_part, loss_np, loss, lred);
   const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
   if (gi >= g.n) return;
   float p[3], s[3], q[4];
@@ -2534,10 +2546,12 @@ int loss_partials(const ViewTable& vt) {
   return int(blocks_for(maxp, 256)) * vt.nviews;
 }
 
-hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* part, float* loss, hipStream_t s) {
+hipError_t launch_loss_l1(const ViewTable& vt, float depth_w, float* part, float* loss, hipStream_t s,
+                          const uint32_t* order, int batch, const Ckpt* ck, uint32_t* ctrl) {
   const int np = loss_partials(vt);
-  k_loss_l1<<<dim3(np / vt.nviews, vt.nviews), 256, 0, s>>>(vt, depth_w, part);
-  if (loss) k_loss_sum<<<1, 1024, 0, s>>>(part, np, loss);
+  k_loss_l1<<<dim3(np / vt.nviews, vt.nviews), 256, 0, s>>>(vt, depth_w, part, order, vt.total_tiles,
+                                                            ckpt_stride(batch), ck ? *ck : Ckpt{}, ctrl);
+  if (loss) k_loss_sum<<<1, 256, 0, s>>>(part, np, loss);
   return hipGetLastError();
 }
 
@@ -2556,9 +2570,9 @@ static void blend_bwd_t(const ViewTable& vt, const Rules& ru, const Records& rec
 hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rules& ru, const Records& rec,
                             const uint2* ranges, const uint32_t* vals, const float* T_final,
                             const uint32_t* n_contrib, float* grad2d, const TileQueue& q, const Ckpt& ck,
-                            hipStream_t s, const float* loss_part, int loss_np, float* loss) {
+                            hipStream_t s, bool items_listed) {
   if (vt.total_tiles == 0) return hipSuccess;
-  k_bwd_items<<<1, 1024, 0, s>>>(q.order, vt.total_tiles, ckpt_stride(batch), ck, q.ctrl, loss_part, loss_np, loss);
+  if (!items_listed) k_bwd_items<<<1, 1024, 0, s>>>(q.order, vt.total_tiles, ckpt_stride(batch), ck, q.ctrl);
   const bool b256 = batch == 256;
   switch (tile) {
     case 8: b256 ? blend_bwd_t<8, 256>(vt, ru, rec, ranges, vals, T_final, n_contrib, grad2d, q, ck, s)
@@ -2573,7 +2587,8 @@ hipError_t launch_blend_bwd(int tile, int batch, const ViewTable& vt, const Rule
 
 hipError_t launch_project_bwd(int deg, const GaussDev& g, const ViewTable& vt, const Rules& ru,
                               const Records& rec, const float* grad2d, float* dp_sh, const GradOut& out,
-                              const AdamDev& adam, hipStream_t s) {
+                              const AdamDev& adam, hipStream_t s, const float* loss_part, int loss_np,
+                              float* loss) {
   if (g.n == 0) return hipSuccess;
   const dim3 gsh(blocks_for(g.n, kShGaussians));
   switch (deg) {
@@ -2583,7 +2598,7 @@ hipError_t launch_project_bwd(int deg, const GaussDev& g, const ViewTable& vt, c
     default: k_project_bwd_sh<3><<<gsh, 256, 0, s>>>(g, vt, rec, grad2d, out, dp_sh, adam); break;
   }
   k_project_bwd_geo<<<blocks_for(g.n, kProjThreads), kProjThreads, 0, s>>>(g, vt, ru, rec, grad2d, dp_sh, out,
-                                                                           adam);
+                                                                           adam, loss_part, loss_np, loss);
   return hipGetLastError();
 }
 
