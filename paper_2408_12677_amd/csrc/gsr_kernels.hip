@@ -1874,8 +1874,9 @@ __device__ __forceinline__ void bwd_pixel_setup(BwdPixel& s, const ViewDev& cam,
 // that does not take part (past its list, or below the skip threshold) takes alpha = 0,
 // which leaves B unchanged and adds zeros; its T is kept by a select (1 / (1 - 0) is not
 // relied on to be exact).
-__device__ __forceinline__ void bwd_pixel_step(BwdPixel& s, bool act, float a, float G, float dx, float dy,
-                                               const float4& r1, const float4& c, const Rules& ru, float (&g)[10]) {
+// Returns q = dL/da a, whose offset moments the caller forms (the pixels of a lane share dx).
+__device__ __forceinline__ float bwd_pixel_step(BwdPixel& s, bool act, float a, float G, const float4& r1,
+                                                const float4& c, const Rules& ru, float (&g)[10]) {
   const float al = act ? fminf(a, ru.amax) : 0.f;
   const float om = 1.f - al;
   const float iom = __builtin_amdgcn_rcpf(om);
@@ -1890,13 +1891,7 @@ __device__ __forceinline__ void bwd_pixel_step(BwdPixel& s, bool act, float a, f
   s.B = al * S + om * s.B;
   const float da = (act && a <= ru.amax) ? dal : 0.f;
   g[5] += da * G;
-  const float q = da * a;
-  const float qx = q * dx, qy = q * dy;
-  g[0] += qx;
-  g[1] += qy;
-  g[2] += qx * dx;
-  g[3] += qx * dy;
-  g[4] += qy * dy;
+  return da * a;
 }
 
 // The splat-major flush of a batch's per-splat sums (s_g: ten per splat and wavefront,
@@ -2015,8 +2010,23 @@ __global__ __launch_bounds__(TS* TS / PPL) void k_blend_bwd2(ViewTable vt, Rules
         if (__ballot(any) == 0ull) continue;
         const float4 c = s_rgb[j];
         float gv[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        // the offset moments of the lane's pixels (one column: one dx): Σq, Σq dy, Σq dy²,
+        // then Σq dx = dx Σq, Σq dx² = dx² Σq, Σq dx dy = dx Σq dy
+        float Q = 0.f, QY = 0.f, QYY = 0.f;
 #pragma unroll
-        for (int i = 0; i < PPL; ++i) bwd_pixel_step(p[i], act[i], a[i], G[i], dx, dy[i], r1, c, ru, gv);
+        for (int i = 0; i < PPL; ++i) {
+          const float q = bwd_pixel_step(p[i], act[i], a[i], G[i], r1, c, ru, gv);
+          const float qy = q * dy[i];
+          Q = i == 0 ? q : Q + q;
+          QY = i == 0 ? qy : QY + qy;
+          QYY = i == 0 ? qy * dy[i] : QYY + qy * dy[i];
+        }
+        const float Qx = Q * dx;
+        gv[0] = Qx;
+        gv[1] = QY;
+        gv[2] = Qx * dx;
+        gv[3] = QY * dx;
+        gv[4] = QYY;
         float w0, w1, w2;
         wave_sum10(gv, w0, w1, w2);
         if ((lane & 15) == 0) {  // one lane per row stores its row's totals
