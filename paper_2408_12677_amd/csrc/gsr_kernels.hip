@@ -86,6 +86,9 @@ __device__ __forceinline__ void wave_sum10(const float (&v)[10], float& w0, floa
   w0 += dpp_move<0x140, 0xF>(w0);
   w1 += dpp_move<0x140, 0xF>(w1);
   w2 += dpp_move<0x140, 0xF>(w2);
+  // the sums exist in every lane here, so the last adds stay with their DPP moves (fused)
+  // rather than sinking into the callers' one-lane-per-row stores
+  asm volatile("" : "+v"(w0), "+v"(w1), "+v"(w2));
 }
 
 template <int CTRL>
@@ -1877,10 +1880,11 @@ __device__ __forceinline__ void bwd_pixel_setup(BwdPixel& s, const ViewDev& cam,
 // Returns q = dL/da a, whose offset moments the caller forms (the pixels of a lane share dx).
 __device__ __forceinline__ float bwd_pixel_step(BwdPixel& s, bool act, float a, float G, const float4& r1,
                                                 const float4& c, const Rules& ru, float (&g)[10]) {
-  const float al = act ? fminf(a, ru.amax) : 0.f;
+  const bool below = a <= ru.amax;  // not clamped (shared by the clamp and its gradient)
+  const float al = act ? (below ? a : ru.amax) : 0.f;
   const float om = 1.f - al;
   const float iom = __builtin_amdgcn_rcpf(om);
-  s.T = act ? s.T * iom : s.T;
+  s.T = s.T * iom;  // a lane that does not take the entry has om = 1, iom = 1 exactly
   const float wgt = al * s.T;
   g[6] += s.gC0 * wgt;
   g[7] += s.gC1 * wgt;
@@ -1889,7 +1893,7 @@ __device__ __forceinline__ float bwd_pixel_step(BwdPixel& s, bool act, float a, 
   const float S = s.gC0 * c.x + s.gC1 * c.y + s.gC2 * c.z + s.gD * r1.z;
   const float dal = s.T * (S - s.B) + s.gATf * iom;
   s.B = al * S + om * s.B;
-  const float da = (act && a <= ru.amax) ? dal : 0.f;
+  const float da = (act && below) ? dal : 0.f;
   g[5] += da * G;
   return da * a;
 }
