@@ -70,7 +70,7 @@ def kernel_bytes(name, st):
     if name == "bin_count":                      # mean of the row and the tile histogram launches
         return (Nv * 12 + E1 * 8) / 2
     if name == "bin_scatter":                    # mean of the row and the tile placement (+ ranges) launches
-        return (Nv * 12 + E1 * 8 + E1 * 8 + M * 4 + st["tiles"] * 32) / 2
+        return (Nv * 12 + E1 * 8 + E1 * 8 + st.get("M_listed", M) * 4 + st["tiles"] * 32) / 2
     if name == "blend_fwd":
         return st["loaded_fwd"] * (4 + 48) + P * 28
     if name == "blend_bwd":
@@ -252,6 +252,7 @@ def step_stats(R, params, cams, targets, settings):
               E_bwd=int(nc_all.sum()), E_fwd=e_fwd, E_used=e_used,
               row_run_bytes=32 if settings.exact_tiles else 0)
     n = (dbg["ranges"][:, 1].astype(np.int64) - dbg["ranges"][:, 0].astype(np.int64))
+    st["M_listed"] = int(n.sum())  # pairs in the tile lists (fewer than M with exact tiles)
     st["tile_list_length"] = {"p50": float(np.percentile(n, 50)), "p99": float(np.percentile(n, 99)),
                               "max": int(n.max(initial=0))}
     saved.free()
