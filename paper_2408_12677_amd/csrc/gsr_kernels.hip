@@ -125,6 +125,25 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   return v;
 }
 
+// Maximum over the wavefront as a wavefront-uniform value, by the DPP steps of
+// wave_min_u32.  Needs every lane active.
+__device__ __forceinline__ uint32_t wave_max_uniform_u32(uint32_t v) {
+  v = max(v, dpp_u32<0xB1>(v));
+  v = max(v, dpp_u32<0x4E>(v));
+  v = max(v, dpp_u32<0x141>(v));
+  v = max(v, dpp_u32<0x140>(v));
+  const uint32_t a = uint32_t(__builtin_amdgcn_readlane(int(v), 0));
+  const uint32_t b = uint32_t(__builtin_amdgcn_readlane(int(v), 16));
+  const uint32_t c = uint32_t(__builtin_amdgcn_readlane(int(v), 32));
+  const uint32_t d = uint32_t(__builtin_amdgcn_readlane(int(v), 48));
+  return uint32_t(__builtin_amdgcn_readfirstlane(int(max(max(a, b), max(c, d)))));
+}
+
+// base + the number of lanes below this one set in m (v_mbcnt)
+__device__ __forceinline__ uint32_t rank_below(uint64_t m, uint32_t base) {
+  return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), base));
+}
+
 __device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   const int nw = blockDim.x >> 6;
@@ -1129,8 +1148,7 @@ __global__ __launch_bounds__(64) void k_bin_rows_scatter(ViewTable vt, int64_t n
 }
 
 // Next free slot of bin b when the slots of bins lane + 64 k sit in register k of that
-// lane, and its update by the c entries just placed: readlanes and selects only, so the
-// walks over bins carry no branches.
+// lane: readlanes and selects only, so the walks over bins carry no branches.
 template <int NREG>
 __device__ __forceinline__ uint32_t slot_of(const uint32_t (&nx)[NREG], uint32_t b) {
   const int src = int(b & 63u), kb = int(b >> 6);
@@ -1143,12 +1161,35 @@ __device__ __forceinline__ uint32_t slot_of(const uint32_t (&nx)[NREG], uint32_t
   return base;
 }
 
+// Advances every bin's next free slot (bin lane + 64 k in register k) by the number of
+// this round's lanes whose run [lo, hi] covers it (lo = 0xFFFFFFFF: no run), from a
+// difference histogram in the wavefront's LDS words diff[0 .. 64 NREG] (+1 at lo, -1
+// past hi) and its inclusive scan over the bins.
 template <int NREG>
-__device__ __forceinline__ void take_slots(uint32_t (&nx)[NREG], uint32_t b, uint32_t c, int lane) {
-  const uint32_t add = lane == int(b & 63u) ? c : 0u;
-  const int kb = int(b >> 6);
+__device__ __forceinline__ void advance_slots(uint32_t (&nx)[NREG], uint32_t* diff, uint32_t lo, uint32_t hi,
+                                              int lane) {
 #pragma unroll
-  for (int k = 0; k < NREG; ++k) nx[k] += kb == k ? add : 0u;
+  for (int k = 0; k < NREG; ++k) diff[lane + 64 * k] = 0u;
+  if (lane == 0) diff[64 * NREG] = 0u;
+  __builtin_amdgcn_wave_barrier();
+  if (lo != 0xFFFFFFFFu) {
+    atomicAdd(&diff[lo], 1u);
+    atomicAdd(&diff[hi + 1u], 0xFFFFFFFFu);
+  }
+  __builtin_amdgcn_wave_barrier();
+  uint32_t carry = 0;
+#pragma unroll
+  for (int k = 0; k < NREG; ++k) {
+    uint32_t v = diff[lane + 64 * k];
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t t = uint32_t(__shfl_up(int(v), off));
+      if (lane >= off) v += t;
+    }
+    v += carry;
+    carry = uint32_t(__builtin_amdgcn_readlane(int(v), 63));
+    nx[k] += v;
+  }
+  __builtin_amdgcn_wave_barrier();
 }
 
 // The same placement with the rows' next free slots in registers (row lane + 64 k in
@@ -1161,9 +1202,11 @@ __global__ __launch_bounds__(256) void k_bin_rows_scatter_r(ViewTable vt, int64_
                                                             const uint32_t* dvals, const unsigned long long* nvis,
                                                             int64_t cap_vis, uint32_t* overflow, BinPlan plan) {
   __shared__ unsigned long long s_part[256];
+  __shared__ uint32_t s_rr[4][kRowRuns + 1][64];  // per wavefront: the round's row runs
+  __shared__ uint32_t s_diff[4][64 * NREG + 1];     // per wavefront: rows covered (difference form)
   if (blockIdx.x == gridDim.x - 1) rows_meta<256>(vt, plan, overflow, s_part);
   const int R = plan.rows;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wv = int(threadIdx.x >> 6);
   const int chunk = int(blockIdx.x) * 4 + int(threadIdx.x >> 6);  // one chunk per wavefront
   const int64_t NV = clamp_count(nvis, cap_vis, overflow);
   const int64_t beg = int64_t(chunk) * 64 * plan.rounds1;
@@ -1175,7 +1218,6 @@ __global__ __launch_bounds__(256) void k_bin_rows_scatter_r(ViewTable vt, int64_
     const int y = lane + 64 * k;
     nx[k] = valu_copy(y < R ? plan.cnt1[int64_t(y) * plan.nch1 + chunk] : 0u);
   }
-  const uint64_t lt_mask = (1ull << lane) - 1ull;
   for (int r = 0; r < plan.rounds1; ++r) {
     const int64_t r0 = beg + int64_t(r) * 64;
     if (r0 >= NV) break;
@@ -1192,18 +1234,30 @@ __global__ __launch_bounds__(256) void k_bin_rows_scatter_r(ViewTable vt, int64_
       entry = make_uint2(rid, rc.x);
     }
     const uint32_t first = lo;
-    uint32_t rr[kRowRuns];
-    load_row_runs(rec, entry, lo != 0xFFFFFFFFu, rr);
+    // this lane's runs, row k of the splat at s_rr[wv][k][lane] (k = kRowRuns: the later
+    // rows); each lane reads back only its own column
+    if (rec.runs) {
+      uint32_t rr[kRowRuns];
+      load_row_runs(rec, entry, lo != 0xFFFFFFFFu, rr);
+#pragma unroll
+      for (int k = 0; k < kRowRuns; ++k) s_rr[wv][k][lane] = rr[k];
+      s_rr[wv][kRowRuns][lane] = entry.y | kRunUncut;
+    }
     const uint32_t y0 = wave_min_u32(lo);
     if (y0 == 0xFFFFFFFFu) continue;
-    const uint32_t y1 = uint32_t(__builtin_amdgcn_readfirstlane(int(wave_max_u32(lo != 0xFFFFFFFFu ? hi : 0u))));
+    const uint32_t y1 = wave_max_uniform_u32(lo != 0xFFFFFFFFu ? hi : 0u);
     for (uint32_t y = y0; y <= y1; ++y) {  // branch-free but for the store
       const bool on = lo <= y && y <= hi;
-      const uint64_t m = __ballot(on);
-      const uint32_t dst = slot_of(nx, y) + uint32_t(__popcll(m & lt_mask));
-      if (on && dst < cap) plan.rowlist[dst] = make_uint2(entry.x, row_entry_run(rec, entry, rr, y - first));
-      take_slots(nx, y, uint32_t(__popcll(m)), lane);
+      // (two ballots of plain compares: the compiler keeps them in scalar registers)
+      const uint64_t m = __builtin_amdgcn_ballot_w64(lo <= y) & __builtin_amdgcn_ballot_w64(y <= hi);
+      const uint32_t base = slot_of(nx, y);
+      const uint32_t dst = rank_below(m, base);
+      if (on && dst < cap) {
+        const uint32_t run = rec.runs ? s_rr[wv][min(y - first, uint32_t(kRowRuns))][lane] : entry.y;
+        plan.rowlist[dst] = make_uint2(entry.x, run);
+      }
     }
+    advance_slots(nx, s_diff[wv], lo, hi, lane);
   }
 }
 
@@ -1413,13 +1467,13 @@ __global__ __launch_bounds__(256) void k_bin_tiles_scatter_r(ViewTable vt, BinPl
                                                              const uint32_t* overflow, uint2* ranges,
                                                              const uint32_t* hint, uint32_t* order) {
   __shared__ uint32_t s_cnt[kOrderBuckets], s_start[kOrderBuckets], s_red[4];
+  __shared__ uint32_t s_diff[4][64 * NREG + 1];  // per wavefront: tiles covered (difference form)
   // with a work hint the tile queue's order does not need the ranges: the last block
   // orders it here (no launch of its own)
   if (hint && blockIdx.x == gridDim.x - 1) tile_order_block<256>(nullptr, hint, vt.total_tiles, order, s_cnt, s_start, s_red);
   const int lane = threadIdx.x & 63;
   for (int t = int(blockIdx.x) * 256 + int(threadIdx.x); t < vt.total_tiles; t += int(gridDim.x) * 256)
     ranges[t] = tile_range(vt, plan, overflow, t);
-  const uint64_t lt_mask = (1ull << lane) - 1ull;
   const uint32_t cap = uint32_t(min<int64_t>(plan.cap_M, int64_t(0xFFFFFFFFu)));
   const unsigned long long S = plan.words[1];
   // a segment per wavefront
@@ -1443,15 +1497,16 @@ __global__ __launch_bounds__(256) void k_bin_tiles_scatter_r(ViewTable vt, BinPl
       }
       const uint32_t x0 = wave_min_u32(lo);
       if (x0 == 0xFFFFFFFFu) continue;
-      const uint32_t x1 = uint32_t(__builtin_amdgcn_readfirstlane(int(wave_max_u32(lo != 0xFFFFFFFFu ? hi : 0u))));
+      const uint32_t x1 = wave_max_uniform_u32(lo != 0xFFFFFFFFu ? hi : 0u);
       for (uint32_t x = x0; x <= x1; ++x) {  // branch-free but for the store
         const bool on = lo <= x && x <= hi;
-        const uint64_t m = __ballot(on);
+        // (two ballots of plain compares: the compiler keeps them in scalar registers)
+        const uint64_t m = __builtin_amdgcn_ballot_w64(lo <= x) & __builtin_amdgcn_ballot_w64(x <= hi);
         const uint32_t base = slot_of(nx, x);
-        const uint32_t dst = base + uint32_t(__popcll(m & lt_mask));
+        const uint32_t dst = rank_below(m, base);
         if (on && dst < cap) vals[dst] = rid;
-        take_slots(nx, x, uint32_t(__popcll(m)), lane);
       }
+      advance_slots(nx, s_diff[threadIdx.x >> 6], lo, hi, lane);
     }
   }
 }
