@@ -1360,7 +1360,8 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2* ranges, const 
 }
 
 // stage 2 counts: tile-column histogram of one segment of a row list, one wavefront per
-// segment (its own LDS histogram of hist_stride words).  With exact tiles the runs of a
+// segment (its own LDS words, hist_stride >= tiles + 1: each run adds +1 at its first
+// column and -1 past its last, and a scan over the columns gives the counts).  With exact tiles the runs of a
 // record's first kRowRuns rows arrive cut by the projection; a run marked kRunUncut (a
 // later row of a tall splat) is cut here to the columns its ellipse reaches in this row
 // (row_run) and written back, so the placement below sees the same run; a row the
@@ -1373,7 +1374,7 @@ __global__ __launch_bounds__(256) void k_bin_tiles_count(ViewTable vt, BinPlan p
   const unsigned long long S = plan.words[1];
   for (uint32_t s = blockIdx.x * 4u + uint32_t(wv); s < S; s += gridDim.x * 4u) {
     const Segment g = segment_of(vt, plan, s);
-    for (int i = lane; i < g.tiles_x; i += 64) hist[i] = 0;
+    for (int i = lane; i <= g.tiles_x; i += 64) hist[i] = 0;
     __builtin_amdgcn_wave_barrier();
     for (uint32_t i = g.beg + lane; i < g.end; i += 64) {
       uint32_t cx = plan.rowlist[i].y;
@@ -1390,10 +1391,23 @@ __global__ __launch_bounds__(256) void k_bin_tiles_count(ViewTable vt, BinPlan p
         plan.rowlist[i].y = cx;
       }
       const int x0 = int(cx & 0xFFFFu), x1 = min(int(cx >> 16), g.tiles_x - 1);
-      for (int x = x0; x <= x1; ++x) atomicAdd(&hist[x], 1u);
+      if (x0 <= x1) {  // the run in difference form: +1 at its first column, -1 past its last
+        atomicAdd(&hist[x0], 1u);
+        atomicAdd(&hist[x1 + 1], 0xFFFFFFFFu);
+      }
     }
     __builtin_amdgcn_wave_barrier();
-    for (int x = lane; x < g.tiles_x; x += 64) plan.cntF[g.flat + uint32_t(x) * g.nseg] = hist[x];
+    uint32_t carry = 0;  // inclusive scan over the columns, 64 at a time
+    for (int x = lane; x < ((g.tiles_x + 63) & ~63); x += 64) {
+      uint32_t v = x < g.tiles_x ? hist[x] : 0u;
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = uint32_t(__shfl_up(int(v), off));
+        if (lane >= off) v += t;
+      }
+      v += carry;
+      carry = uint32_t(__builtin_amdgcn_readlane(int(v), 63));
+      if (x < g.tiles_x) plan.cntF[g.flat + uint32_t(x) * g.nseg] = v;
+    }
     __builtin_amdgcn_wave_barrier();
   }
 }
@@ -2492,7 +2506,7 @@ hipError_t launch_bin(const ViewTable& vt, int64_t n, const Records& rec, const 
     k_bin_rows_scatter<<<plan.nch1, 64, lds_rows, s>>>(vt, n, rec, dvals, nvis, cap_vis, overflow, plan);
   E(K_BIN_SCATTER);
   B(K_BIN_COUNT);
-  k_bin_tiles_count<<<g_count, 256, 4 * lds_cols, s>>>(vt, plan, rec, exact_k, tile, vt.max_tiles_x);
+  k_bin_tiles_count<<<g_count, 256, 4 * (lds_cols + 4), s>>>(vt, plan, rec, exact_k, tile, vt.max_tiles_x + 1);
   E(K_BIN_COUNT);
   B(K_BIN_SCAN);
   scan_u32(plan.cntF, plan.cap_flat, plan.words + 2, plan.part, plan.words + 3, s);
