@@ -1680,6 +1680,7 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
         float Tn = Tk[kFwdGroup];
 #pragma unroll
         for (int u = kFwdGroup - 1; u >= 0; --u) Tn = (done || Tk[u] < ru.Tmin) ? Tk[u] : Tn;
+        uint32_t lg = 0;  // 1 + the group position of the group's last contributor, 0: none
 #pragma unroll
         for (int u = 0; u < kFwdGroup; ++u) {
           const bool act = !(done || Tk[u] < ru.Tmin) && !(a4[u] < ru.amin);
@@ -1688,8 +1689,9 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
           C1 += c4[u].y * wgt;
           C2 += c4[u].z * wgt;
           D += z4[u] * wgt;
-          last = act ? uint32_t(b0 + j + u + 1) : last;
+          lg = act ? uint32_t(u + 1) : lg;
         }
+        last = lg ? uint32_t(b0 + j) + lg : last;
         T = Tn;
         done = done || Tn < ru.Tmin;
       }
