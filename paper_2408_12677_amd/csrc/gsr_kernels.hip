@@ -542,13 +542,12 @@ __global__ __launch_bounds__(kProjThreads) void k_project(GaussDev g, ViewTable 
     q[2] = q4.z;
     q[3] = q4.w;
     op = g.opac[gi];
-    const float* src = g.sh + gi * (K * 3);
-#pragma unroll
-    for (int i = 0; i < K * 3; ++i) sh[i] = src[i];
-  } else {
-#pragma unroll
-    for (int i = 0; i < K * 3; ++i) sh[i] = 0.f;
   }
+  // the colour coefficients are read at the first view that sees the Gaussian (none for
+  // a Gaussian outside every view)
+  bool have_sh = false;
+#pragma unroll
+  for (int i = 0; i < K * 3; ++i) sh[i] = 0.f;
   for (int v = 0; v < vt.nviews; ++v) {
     const ViewDev& cam = vt.v[v];
     uint32_t cnt = 0;
@@ -557,6 +556,12 @@ __global__ __launch_bounds__(kProjThreads) void k_project(GaussDev g, ViewTable 
       discrete_stage(p, s, q, cam, ru.k, ru.lowpass, ru.guard, ru.jclamp, pr);
       const int64_t rid = int64_t(v) * g.n + gi;
       if (pr.vis) {
+        if (!have_sh) {
+          const float* src = g.sh + gi * (K * 3);
+#pragma unroll
+          for (int i = 0; i < K * 3; ++i) sh[i] = src[i];
+          have_sh = true;
+        }
         const int tx0 = pr.x0 / tile, tx1 = pr.x1 / tile, ty0 = pr.y0 / tile, ty1 = pr.y1 / tile;
         cnt = uint32_t((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
         float A, B, C;
@@ -2148,6 +2153,21 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(GaussDev g, ViewTable vt
   const int t = threadIdx.x;
   const int64_t g0 = int64_t(blockIdx.x) * kShGaussians;
   const int nb = int(min<int64_t>(kShGaussians, g.n - g0));
+  const int gl = t >> 2, ch = t & 3;
+  const int64_t gi = g0 + gl;
+  // this lane's mean and first view's colour gradient, loaded before the block stages the
+  // coefficients (their latency overlaps the staging)
+  float p0 = 0.f, p1 = 0.f, p2 = 0.f, dc0 = 0.f;
+  uint32_t cnt0 = 0;
+  if (gl < nb && ch < 3) {
+    cnt0 = rec.counts[gi];
+    if (cnt0) {
+      p0 = g.means[gi * 3];
+      p1 = g.means[gi * 3 + 1];
+      p2 = g.means[gi * 3 + 2];
+      dc0 = grad2d[gi * kGrad2D + 6 + ch];
+    }
+  }
   if (t < kShGaussians) {
     uint32_t vis = 0;
     if (t < nb)
@@ -2160,8 +2180,6 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(GaussDev g, ViewTable vt
     s_sh[r * STRIDE + (i - r * KK)] = s_vis[r] ? g.sh[g0 * KK + i] : 0.f;
   }
   __syncthreads();
-  const int gl = t >> 2, ch = t & 3;
-  const int64_t gi = g0 + gl;
   const bool mine = gl < nb && s_vis[gl] != 0u;
   float dsh[K], dp[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -2170,10 +2188,14 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(GaussDev g, ViewTable vt
     float shc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) shc[k] = s_sh[gl * STRIDE + k * 3 + ch];
-    const float p0 = g.means[gi * 3], p1 = g.means[gi * 3 + 1], p2 = g.means[gi * 3 + 2];
+    if (!cnt0) {  // visible only in later views: the mean was not loaded above
+      p0 = g.means[gi * 3];
+      p1 = g.means[gi * 3 + 1];
+      p2 = g.means[gi * 3 + 2];
+    }
     for (int v = 0; v < vt.nviews; ++v) {
       const int64_t rid = int64_t(v) * g.n + gi;
-      if (rec.counts[rid] == 0) continue;
+      if ((v == 0 ? cnt0 : rec.counts[rid]) == 0) continue;
       const ViewDev& cam = vt.v[v];
       const float d0 = p0 - cam.cam_pos[0], d1 = p1 - cam.cam_pos[1], d2 = p2 - cam.cam_pos[2];
       const float il = 1.f / __builtin_sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
@@ -2183,7 +2205,7 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(GaussDev g, ViewTable vt
       float raw = 0.5f;
 #pragma unroll
       for (int k = 0; k < K; ++k) raw += shc[k] * Y[k];
-      const float dc = raw > 0.f ? grad2d[rid * kGrad2D + 6 + ch] : 0.f;
+      const float dc = raw > 0.f ? (v == 0 ? dc0 : grad2d[rid * kGrad2D + 6 + ch]) : 0.f;
 #pragma unroll
       for (int k = 0; k < K; ++k) dsh[k] += Y[k] * dc;
       if (DEG > 0) {
