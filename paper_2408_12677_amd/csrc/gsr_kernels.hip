@@ -2147,6 +2147,7 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(GaussDev g, ViewTable vt
                                                         GradOut out, float* dp_sh, AdamDev adam) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   constexpr int KK = K * 3;
+  constexpr bool kVec = KK % 4 == 0;  // degrees 1 and 3: whole float4s per Gaussian
   constexpr int STRIDE = KK | 1;
   __shared__ float s_sh[kShGaussians * STRIDE];
   __shared__ uint32_t s_vis[kShGaussians];
@@ -2175,9 +2176,25 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(GaussDev g, ViewTable vt
     s_vis[t] = vis;
   }
   __syncthreads();
-  for (int i = t; i < nb * KK; i += 256) {
-    const int r = i / KK;
-    s_sh[r * STRIDE + (i - r * KK)] = s_vis[r] ? g.sh[g0 * KK + i] : 0.f;
+  // 16-byte loads where the array allows them (with KK a multiple of 4 a float4 never
+  // straddles two Gaussians)
+  const bool vec_in = kVec && (reinterpret_cast<uintptr_t>(g.sh) & 15u) == 0;
+  if (vec_in) {
+    const float4* src = reinterpret_cast<const float4*>(g.sh + g0 * KK);
+    for (int i = t; i < nb * (KK / 4); i += 256) {
+      const int r = (4 * i) / KK, j = 4 * i - r * KK;
+      const float4 v = s_vis[r] ? src[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      float* d = s_sh + r * STRIDE + j;
+      d[0] = v.x;
+      d[1] = v.y;
+      d[2] = v.z;
+      d[3] = v.w;
+    }
+  } else {
+    for (int i = t; i < nb * KK; i += 256) {
+      const int r = i / KK;
+      s_sh[r * STRIDE + (i - r * KK)] = s_vis[r] ? g.sh[g0 * KK + i] : 0.f;
+    }
   }
   __syncthreads();
   const bool mine = gl < nb && s_vis[gl] != 0u;
@@ -2243,6 +2260,15 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(GaussDev g, ViewTable vt
       const int64_t e = g0 * KK + i;
       adam_apply<G_SH>(adam, e, adam.p[G_SH][e], s_sh[r * STRIDE + j], j < 3 ? adam.lr[G_SH] : adam.lr[G_SH + 1],
                        bc1, bc2);
+    }
+    return;
+  }
+  if (kVec && (reinterpret_cast<uintptr_t>(out.sh) & 15u) == 0 && !out.accumulate) {
+    float4* dst = reinterpret_cast<float4*>(out.sh + g0 * KK);
+    for (int i = t; i < nb * (KK / 4); i += 256) {
+      const int r = (4 * i) / KK, j = 4 * i - r * KK;
+      const float* v = s_sh + r * STRIDE + j;
+      dst[i] = make_float4(v[0], v[1], v[2], v[3]);
     }
     return;
   }
