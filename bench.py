@@ -61,7 +61,10 @@ def kernel_bytes(name, st):
     N, V, Nv, M, P, K = st["N"], st["V"], st["N_vis"], st["M"], st["P"], st["K"]
     pg = 4 * (3 + 3 + 4 + 1 + 3 * K)            # parameter bytes per Gaussian
     if name == "project":                        # (+ the exact row runs of each visible record)
-        return N * pg + V * N * 4 + Nv * (16 * 3 + 8) + Nv * st.get("row_run_bytes", 0)
+        # colour coefficients are read only for Gaussians some view sees
+        sh = 4 * 3 * K
+        return (N * (pg - sh) + st.get("N_any", N) * sh + V * N * 4 + Nv * (16 * 3 + 8)
+                + Nv * st.get("row_run_bytes", 0))
     E1 = st["E_rows"]
     if name == "radix_hist":                     # depth digits of the visible records
         return Nv * 4
@@ -253,6 +256,7 @@ def step_stats(R, params, cams, targets, settings):
               row_run_bytes=32 if settings.exact_tiles else 0)
     n = (dbg["ranges"][:, 1].astype(np.int64) - dbg["ranges"][:, 0].astype(np.int64))
     st["M_listed"] = int(n.sum())  # pairs in the tile lists (fewer than M with exact tiles)
+    st["N_any"] = int((dbg["tiles_touched"].reshape(len(cams), -1) > 0).any(axis=0).sum())  # seen by some view
     st["tile_list_length"] = {"p50": float(np.percentile(n, 50)), "p99": float(np.percentile(n, 99)),
                               "max": int(n.max(initial=0))}
     saved.free()
