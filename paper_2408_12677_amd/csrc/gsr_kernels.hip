@@ -2255,6 +2255,26 @@ __global__ __launch_bounds__(256) void k_project_bwd_sh(GaussDev g, ViewTable vt
   if (adam.on) {  // one Adam step of every coefficient of the block's Gaussians, in place
     if (adam.skip && *adam.skip) return;  // the step overflowed: parameters stay as they are
     const float bc1 = adam.bc[0], bc2 = adam.bc[1];
+    auto al = [](const float* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+    if (kVec && al(adam.p[G_SH]) && al(adam.m[G_SH]) && al(adam.v[G_SH])) {  // 16-byte accesses
+      const int64_t e0 = g0 * (KK / 4);
+      for (int i = t; i < nb * (KK / 4); i += 256) {
+        const int r = (4 * i) / KK, j = 4 * i - r * KK;
+        const float* gs = s_sh + r * STRIDE + j;
+        float4 x = reinterpret_cast<const float4*>(adam.p[G_SH])[e0 + i];
+        float4 m = reinterpret_cast<const float4*>(adam.m[G_SH])[e0 + i];
+        float4 v = reinterpret_cast<const float4*>(adam.v[G_SH])[e0 + i];
+        auto lr = [&](int k) { return j + k < 3 ? adam.lr[G_SH] : adam.lr[G_SH + 1]; };
+        x.x = adam_value<G_SH>(x.x, gs[0], m.x, v.x, lr(0), adam, bc1, bc2);
+        x.y = adam_value<G_SH>(x.y, gs[1], m.y, v.y, lr(1), adam, bc1, bc2);
+        x.z = adam_value<G_SH>(x.z, gs[2], m.z, v.z, lr(2), adam, bc1, bc2);
+        x.w = adam_value<G_SH>(x.w, gs[3], m.w, v.w, lr(3), adam, bc1, bc2);
+        reinterpret_cast<float4*>(adam.p[G_SH])[e0 + i] = x;
+        reinterpret_cast<float4*>(adam.m[G_SH])[e0 + i] = m;
+        reinterpret_cast<float4*>(adam.v[G_SH])[e0 + i] = v;
+      }
+      return;
+    }
     for (int i = t; i < nb * KK; i += 256) {
       const int r = i / KK, j = i - r * KK;
       const int64_t e = g0 * KK + i;
