@@ -2309,17 +2309,23 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd_geo(GaussDev g, Vi
   if (loss && blockIdx.x == 0) sum_loss_partials(loss_part, loss_np, loss, lred);
   const int64_t gi = int64_t(blockIdx.x) * kProjThreads + threadIdx.x;
   if (gi >= g.n) return;
-  float p[3], s[3], q[4];
+  // the geometry is read for a Gaussian some view sees (or for the Adam step, which moves
+  // every element); the others only get zero gradients
+  uint32_t seen = 0;
+  for (int v = 0; v < vt.nviews && !seen; ++v) seen = rec.counts[int64_t(v) * g.n + gi];
+  float p[3] = {0.f, 0.f, 0.f}, s[3] = {0.f, 0.f, 0.f}, q[4] = {0.f, 0.f, 0.f, 0.f};
+  if (seen || adam.on) {
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    p[i] = g.means[gi * 3 + i];
-    s[i] = g.scales[gi * 3 + i];
+    for (int i = 0; i < 3; ++i) {
+      p[i] = g.means[gi * 3 + i];
+      s[i] = g.scales[gi * 3 + i];
+    }
+    const float4 q4 = reinterpret_cast<const float4*>(g.quats)[gi];
+    q[0] = q4.x;
+    q[1] = q4.y;
+    q[2] = q4.z;
+    q[3] = q4.w;
   }
-  const float4 q4 = reinterpret_cast<const float4*>(g.quats)[gi];
-  q[0] = q4.x;
-  q[1] = q4.y;
-  q[2] = q4.z;
-  q[3] = q4.w;
   float dp[3] = {0.f, 0.f, 0.f}, ds[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f}, dop = 0.f;
   bool any = false;
   for (int v = 0; v < vt.nviews; ++v) {
@@ -2425,8 +2431,12 @@ __global__ __launch_bounds__(kProjThreads) void k_project_bwd_geo(GaussDev g, Vi
     for (int i = 0; i < 3; ++i) store_grad(out.means + gi * 3 + i, dp[i], acc);
   if (out.scales)
     for (int i = 0; i < 3; ++i) store_grad(out.scales + gi * 3 + i, ds[i], acc);
-  if (out.quats)
-    for (int i = 0; i < 4; ++i) store_grad(out.quats + gi * 4 + i, dq[i], acc);
+  if (out.quats) {
+    if (!acc && (reinterpret_cast<uintptr_t>(out.quats) & 15u) == 0)
+      reinterpret_cast<float4*>(out.quats)[gi] = make_float4(dq[0], dq[1], dq[2], dq[3]);
+    else
+      for (int i = 0; i < 4; ++i) store_grad(out.quats + gi * 4 + i, dq[i], acc);
+  }
   if (out.opac) store_grad(out.opac + gi, dop, acc);
 }
 
