@@ -858,16 +858,22 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
   __syncthreads();
   const int64_t b0 = int64_t(tb) * kSortTile;
   const uint64_t lt_mask = (1ull << lane) - 1ull;
+  // every round's key and value loaded up front (one memory latency per block, not one
+  // per round)
+  uint32_t kk[kSortItems], vv[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t idx = b0 + r * kSortThreads + t;
+    kk[r] = idx < M ? kin[idx] : 0u;
+    vv[r] = idx < M ? vin[idx] : 0u;
+  }
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int b = r & 1;
     const int64_t idx = b0 + r * kSortThreads + t;
     const bool valid = idx < M;
-    uint32_t key = 0, val = 0, d = 0;
-    if (valid) {
-      key = kin[idx];
-      val = vin[idx];
-      d = (key >> shift) & MASK;
-    }
+    const uint32_t key = kk[r], val = vv[r];
+    const uint32_t d = valid ? (key >> shift) & MASK : 0u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < BITS; ++bit) {
