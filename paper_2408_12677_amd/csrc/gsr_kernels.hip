@@ -1387,11 +1387,15 @@ __global__ __launch_bounds__(256) void k_bin_tiles_count(ViewTable vt, BinPlan p
     const Segment g = segment_of(vt, plan, s);
     for (int i = lane; i <= g.tiles_x; i += 64) hist[i] = 0;
     __builtin_amdgcn_wave_barrier();
+    // each entry is loaded one iteration ahead
+    uint2 e_next = g.beg + uint32_t(lane) < g.end ? plan.rowlist[g.beg + lane] : make_uint2(0u, kRunEmpty);
     for (uint32_t i = g.beg + lane; i < g.end; i += 64) {
-      uint32_t cx = plan.rowlist[i].y;
+      const uint2 e = e_next;
+      e_next = i + 64u < g.end ? plan.rowlist[i + 64u] : make_uint2(0u, kRunEmpty);
+      uint32_t cx = e.y;
       if (cx & kRunUncut) {
         cx &= ~kRunUncut;
-        const uint32_t rid = plan.rowlist[i].x;
+        const uint32_t rid = e.x;
         const ViewDev& cam = vt.v[view_of_row(vt, uint32_t(g.row))];
         const float4 sp = rec.r0[rid];  // centre and conic A, B
         const float cc = rec.r1[rid].x;
@@ -1510,11 +1514,14 @@ __global__ __launch_bounds__(256) void k_bin_tiles_scatter_r(ViewTable vt, BinPl
       const int x = lane + 64 * k;
       nx[k] = valu_copy(x < g.tiles_x ? plan.cntF[g.flat + uint32_t(x) * g.nseg] : 0u);
     }
+    // each round's entry is loaded one round ahead (its latency under the walk before it)
+    uint2 e_next = g.beg + uint32_t(lane) < g.end ? plan.rowlist[g.beg + lane] : make_uint2(0u, kRunEmpty);
     for (uint32_t r0 = g.beg; r0 < g.end; r0 += 64) {
       const uint32_t i = r0 + uint32_t(lane);
+      const uint2 e = e_next;
+      e_next = i + 64u < g.end ? plan.rowlist[i + 64u] : make_uint2(0u, kRunEmpty);
       uint32_t lo = 0xFFFFFFFFu, hi = 0u, rid = 0u;
       if (i < g.end) {
-        const uint2 e = plan.rowlist[i];
         rid = e.x;
         lo = e.y & 0xFFFFu;
         hi = min(e.y >> 16, uint32_t(g.tiles_x - 1));
