@@ -74,6 +74,37 @@ def close(ga, gb, tol=1e-5):
         assert r <= tol, (k, r)
 
 
+def _shifted(t):
+    """A copy of t whose data starts one float past a 16-byte boundary."""
+    buf = torch.empty(t.numel() + 1, dtype=t.dtype, device=t.device)
+    out = buf[1:].view(t.shape)
+    out.copy_(t)
+    return out
+
+
+def test_misaligned_sh_arrays_take_the_scalar_paths(R):
+    """SH coefficients and an SH gradient output one float off a 16-byte boundary go
+    through the kernels' scalar paths (the projection's coefficient loads, the backward's
+    staging and gradient stores): the same images bit for bit and the same gradients up to
+    the backward's atomic summation order as with aligned arrays."""
+    g, cams, targets = small_views()
+    params = to_dev(g)
+    tg = dev_targets(targets)
+    s = settings()
+    a_images, _, a_grads, _ = eager_step(R, params, cams, tg, s)
+    shifted = list(params[:4]) + [_shifted(params[4])]
+    images, saved = R.forward(*shifted, cams, s)
+    _, gc, gd = R.loss_l1(saved, images, tg, 0.1)
+    grads = {k: torch.empty_like(p) for k, p in zip(NAMES, params)}
+    grads["sh"] = _shifted(torch.zeros_like(params[4]))
+    R.backward(saved, gc, gd, grads=grads)
+    torch.cuda.synchronize()
+    for a, b in zip(a_images, images):
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+    close(grads, a_grads)
+
+
 def test_batched_equals_per_view(R):
     g, cams, targets = small_views()
     params = to_dev(g)
