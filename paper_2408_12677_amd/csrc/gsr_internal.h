@@ -187,11 +187,11 @@ struct TileQueue {
 };
 
 // What the forward keeps so that the backward can run a tile's list in independent
-// pieces of half an LDS batch each: at the first `kmax` such boundaries the forward passes,
-// per pixel, the transmittance in front of it and the colour and depth accumulated up
-// to it (a "checkpoint"); per pixel the accumulated totals; per tile its longest
-// contributor list.  The backward's work items are (tile, stride) pairs; entries past
-// the last checkpoint of a tile form one item that walks them all.
+// pieces of one checkpoint stride (64 entries) each: at the first `kmax` such boundaries
+// the forward passes, per pixel, the transmittance in front of it and the colour and
+// depth accumulated up to it (a "checkpoint"); per pixel the accumulated totals; per tile
+// its longest contributor list.  The backward's work items are (tile, stride) pairs;
+// entries past the last checkpoint of a tile form one item that walks them all.
 struct Ckpt {
   float* state;         // [tiles][kmax][5][pixels of a tile]: T, colour (3), depth in front
   float4* acc;          // [pixels] colour (3) and depth accumulated, without background

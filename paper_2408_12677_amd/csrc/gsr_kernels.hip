@@ -1602,14 +1602,20 @@ __device__ __forceinline__ int next_tile(const TileQueue& q, uint32_t* head, int
 // entries evaluated together by the forward compositing (eight ran 5% faster than four:
 // the heaviest tiles' single-wavefront chains wait on one group's LDS reads at a time)
 constexpr int kFwdGroup = 8;
-static_assert(128 % kFwdGroup == 0 && 64 % kFwdGroup == 0, "batches and checkpoint strides hold whole groups");
+// list entries between two checkpoints of the forward, and so the length of a backward
+// work item: 64 rather than half a batch gives the backward about twice as many items,
+// so that fewer long items are left running at the end of its launch (32 was slower:
+// each item has a fixed cost, its setup reads and staging, of some 10 us under load)
+constexpr int kCkptStride = 64;
+static_assert(128 % kFwdGroup == 0 && kCkptStride % kFwdGroup == 0 && 128 % kCkptStride == 0,
+              "batches and checkpoint strides hold whole groups");
 
 template <int TS, int BATCH>
 __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Records rec, const uint2* ranges,
                                                      const uint32_t* vals, float* T_final, uint32_t* n_contrib,
                                                      TileQueue q, Ckpt ck) {
   constexpr int NT = TS * TS;
-  constexpr int CK = BATCH / 2;  // checkpoint stride
+  constexpr int CK = kCkptStride;
   __shared__ float4 s_r0[BATCH];
   __shared__ float4 s_r1[BATCH];
   __shared__ float4 s_rgb[BATCH];
@@ -1669,7 +1675,7 @@ __global__ __launch_bounds__(TS* TS) void k_blend_fwd(ViewTable vt, Rules ru, Re
       // keeps T.  The wavefront leaves the batch once all its lanes have stopped.
       for (int j = 0; j < cnt; j += kFwdGroup) {
         if (__ballot(!done) == 0ull) break;
-        if (j == CK) checkpoint((b0 + CK) / CK, T, C0, C1, C2, D);
+        if (j > 0 && j % CK == 0) checkpoint((b0 + j) / CK, T, C0, C1, C2, D);
         float a4[kFwdGroup], z4[kFwdGroup];
         float4 c4[kFwdGroup];
 #pragma unroll
@@ -1857,10 +1863,10 @@ __global__ __launch_bounds__(256) void k_loss_sum(const float* part, int count, 
 // ------------------------------------------------------------------------------------
 // K8: backward compositing, back to front over each pixel's contributors; the
 // transmittance before contributor i is T_{i+1} / (1 - alpha_i), and the colour/depth
-// behind i is carried as a running blend.  The work is cut into (tile, batch) items that
+// behind i is carried as a running blend.  The work is cut into (tile, stride) items that
 // run independently: an item starts from the pixel's final state when its list ends in
 // the item, else from the forward's checkpoint at the item's end.  So no wavefront walks
-// more than one batch until a tile's checkpoints run out.
+// more than one checkpoint stride until a tile's checkpoints run out.
 //
 // Each wavefront walks the staged batch only down from its own longest contributor list.
 // The ten per-(pixel, splat) partials are summed across the wavefront with lane swaps
@@ -2036,7 +2042,7 @@ __global__ __launch_bounds__(TS* TS / PPL) void k_blend_bwd2(ViewTable vt, Rules
                                                             float* grad2d, TileQueue q, Ckpt ck) {
   constexpr int NT = TS * TS / PPL;  // threads: pixels (PPL r + i, c), i < PPL, for t = r TS + c
   constexpr int NW = NT / 64;        // wavefronts
-  constexpr int SB = BATCH / 2;      // entries staged at a time: one checkpoint stride
+  constexpr int SB = kCkptStride;    // entries staged at a time: one checkpoint stride
   __shared__ float4 s_r0[SB];
   __shared__ float4 s_r1[SB];
   __shared__ float4 s_rgb[SB];
@@ -2059,7 +2065,7 @@ __global__ __launch_bounds__(TS* TS / PPL) void k_blend_bwd2(ViewTable vt, Rules
     const int ty = lt / cam.tiles_x, tx = lt - ty * cam.tiles_x;
     const int px = tx * TS + cx, py = ty * TS + ry;
     const uint2 rg = ranges[tile];
-    constexpr int CK = BATCH / 2;  // checkpoint stride of the forward
+    constexpr int CK = kCkptStride;  // checkpoint stride of the forward
     const int lo = bf * CK;        // the item's list entries: [lo, hi)
     const int hi = bf < ck.kmax ? lo + CK : int(rg.y - rg.x);
     BwdPixel p[PPL];
@@ -2694,8 +2700,8 @@ hipError_t launch_count_used(const ViewTable& vt, const Rules& ru, const Records
   return hipGetLastError();
 }
 
-// checkpoints every half batch over the first 1024 list entries of each tile
-int ckpt_stride(int batch) { return batch / 2; }
+// checkpoints every kCkptStride entries over the first 1024 list entries of each tile
+int ckpt_stride(int) { return kCkptStride; }
 int ckpt_per_tile(int batch) { return std::max(1, 1024 / ckpt_stride(batch)); }
 
 int64_t bwd_items_cap(int total_tiles, int batch) { return int64_t(total_tiles) * (ckpt_per_tile(batch) + 1); }
