@@ -1599,9 +1599,10 @@ __device__ __forceinline__ int next_tile(const TileQueue& q, uint32_t* head, int
 // pixel; the tile's sorted list is staged through LDS BATCH records at a time; a tile is
 // left once every pixel has reached T < T_min.
 // ------------------------------------------------------------------------------------
-// entries evaluated together by the forward compositing (eight ran 5% faster than four:
-// the heaviest tiles' single-wavefront chains wait on one group's LDS reads at a time)
-constexpr int kFwdGroup = 8;
+// entries evaluated together by the forward compositing (eight ran 5% faster than four,
+// sixteen another 5% faster than eight: the heaviest tiles' single-wavefront chains wait
+// on one group's LDS reads and exponentials at a time)
+constexpr int kFwdGroup = 16;
 // list entries between two checkpoints of the forward, and so the length of a backward
 // work item: 64 rather than half a batch gives the backward about twice as many items,
 // so that fewer long items are left running at the end of its launch (32 was slower:
