@@ -315,6 +315,27 @@ def test_single_pixel_and_huge_splat(R):
         fwd_bwd_parity(R, g, [cam], settings())
 
 
+def test_lists_past_the_last_checkpoint(R):
+    # 2,000 faint splats over the whole image: every pixel takes some 1,500 of them before
+    # its transmittance stops, so the backward's items past the forward's last checkpoint
+    # (list entry 1,024 on) walk several staged strides back from the final state
+    rng = np.random.default_rng(11)
+    n = 2000
+    means = np.stack([rng.uniform(-0.2, 0.2, n), rng.uniform(-0.1, 0.1, n), rng.uniform(2.0, 6.0, n)], 1)
+    g = scenes.random_gaussians(rng, means, 1)
+    g.scales[:] = rng.uniform(8.0, 12.0, (n, 3)).astype(np.float32)
+    g.opacities[:] = rng.uniform(0.0055, 0.0065, n).astype(np.float32)
+    cam = scenes.Camera(40, 24, 30.0, 30.0, 20.0, 12.0, np.eye(3, dtype=np.float32), np.zeros(3, np.float32))
+    for exact in (False, True):
+        s = settings(exact_tiles=exact)
+        _, _, saved = run_fwd(R, g, [cam], s)
+        longest = int(np.asarray(saved.debug_export()["n_contrib"]).max())
+        saved.free()
+        say("exact", exact, "longest contributor list", longest)
+        assert longest > 1100
+        fwd_bwd_parity(R, g, [cam], s)
+
+
 def test_invalid_arguments_raise(R):
     w = scenes.make_cfg1()
     params = to_dev(w.gaussians)
