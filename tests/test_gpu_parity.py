@@ -326,12 +326,12 @@ def test_lists_past_the_last_checkpoint(R):
     g.scales[:] = rng.uniform(8.0, 12.0, (n, 3)).astype(np.float32)
     g.opacities[:] = rng.uniform(0.0055, 0.0065, n).astype(np.float32)
     cam = scenes.Camera(40, 24, 30.0, 30.0, 20.0, 12.0, np.eye(3, dtype=np.float32), np.zeros(3, np.float32))
-    for exact in (False, True):
-        s = settings(exact_tiles=exact)
+    for tile, exact in ((16, False), (16, True), (8, False), (32, True)):
+        s = settings(tile=tile, exact_tiles=exact)
         _, _, saved = run_fwd(R, g, [cam], s)
         longest = int(np.asarray(saved.debug_export()["n_contrib"]).max())
         saved.free()
-        say("exact", exact, "longest contributor list", longest)
+        say("tile", tile, "exact", exact, "longest contributor list", longest)
         assert longest > 1100
         fwd_bwd_parity(R, g, [cam], s)
 
